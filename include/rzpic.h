@@ -1,0 +1,205 @@
+/*
+ * rzpic.h -- C ABI of the MI355X (gfx950) library for the hot path of the
+ * implicit electrostatic r-z PIC/MC model of Wang, Jiang & Wang (arXiv
+ * 1001.2969): the direct-implicit particle cycle (Sec. 2.1, 2.3), weighting
+ * with radius-dependent volumes (Sec. 2.4), weight splitting (Sec. 2.2),
+ * null-collision Monte Carlo (Sec. 2.6) and the z-semi-coarsening multigrid
+ * field solve of div((1+chi) grad phi) = -rho/eps0 (Sec. 2.5, Algorithm 1).
+ *
+ * Conventions
+ *   - Every entry point returns an rzpic_status; no exception crosses the ABI.
+ *     On failure rzpic_last_error() returns a message (thread-local).
+ *   - "device" pointers are HIP device allocations on the context's device;
+ *     "host" pointers are ordinary host memory.  The library never frees a
+ *     pointer it did not allocate.
+ *   - Work is enqueued asynchronously on the context's stream unless a call
+ *     says it synchronises.  Device-side failures (capacity overflow,
+ *     fixed-point overflow, non-finite values) set a sticky status word that
+ *     the next synchronising call returns.
+ *   - Mesh: nr nodes in r (r_j = j*hr, hr = R/(nr-1)), nz nodes in z
+ *     (z_i = i*hz, hz = L/(nz-1)), nz-1 a power of two.  Grids are row-major
+ *     [nz][nr] (r contiguous), double precision, index i*nr + j.
+ *   - Species 0 are electrons, species 1 positive ions.  Particle records are
+ *     structures of arrays {r, z, v_r, v_theta, v_z, a_r, a_z, w, id}
+ *     (Sec. 2.3 record plus the weight of Sec. 2.2 and a 64-bit identity).
+ *     Positions in m, velocities in m/s, damped accelerations in m/s^2,
+ *     weights in physical particles.  Real arrays are double in RZPIC_FP64
+ *     and float in RZPIC_MIXED.
+ */
+#ifndef RZPIC_H
+#define RZPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rzpic_status {
+    RZPIC_OK = 0,
+    RZPIC_EINVAL = 1,     /* bad argument or configuration                  */
+    RZPIC_ENOMEM = 2,     /* device allocation failed                       */
+    RZPIC_EHIP = 3,       /* a HIP runtime call failed                      */
+    RZPIC_ECAPACITY = 4,  /* particle capacity exceeded (children dropped)  */
+    RZPIC_ENOTCONV = 5,   /* multigrid did not reach the tolerance          */
+    RZPIC_ENUMERIC = 6,   /* fixed-point overflow or non-finite value       */
+    RZPIC_ESTATE = 7      /* call out of order (e.g. species not bound)     */
+} rzpic_status;
+
+enum { RZPIC_FP64 = 0, RZPIC_MIXED = 1 };          /* precision            */
+enum { RZPIC_W_ZR2 = 0, RZPIC_W_ZR = 1 };          /* weighting, Sec. 2.4  */
+enum { RZPIC_FACE_AVG = 0, RZPIC_FACE_MAX = 1 };   /* half-point chi, Sec. 2.5 */
+enum { RZPIC_MC_NONE = 0, RZPIC_MC_ELECTRON = 1, RZPIC_MC_ION = 2 };
+enum { RZPIC_P_ELASTIC = 0, RZPIC_P_EXCITATION = 1, RZPIC_P_IONIZATION = 2 };
+/* Grid selectors of rzpic_grid_copy.  N0/N1 are the deposited physical
+ * particle counts N_ij of Sec. 2.4 (kept internally in fixed point). */
+enum {
+    RZPIC_G_PHI = 0, RZPIC_G_RHO = 1, RZPIC_G_CHI = 2, RZPIC_G_ER = 3, RZPIC_G_EZ = 4,
+    RZPIC_G_N0 = 5, RZPIC_G_N1 = 6, RZPIC_G_DENS0 = 7, RZPIC_G_DENS1 = 8, RZPIC_G_VOL = 9
+};
+/* Per-particle Monte Carlo event codes written to rzpic_species_view.mc_event:
+ * 0 not a candidate, 1 null collision, 2+k real collision of process k. */
+enum { RZPIC_EV_NONE = 0, RZPIC_EV_NULL = 1, RZPIC_EV_PROC0 = 2 };
+
+typedef struct rzpic_config {
+    int32_t nr, nz;           /* nodes; nr >= 3, nz-1 = 2^k, k >= 1          */
+    double R, L, dt;          /* radius, electrode gap (m), time step (s)    */
+    int32_t precision;        /* RZPIC_FP64 or RZPIC_MIXED                    */
+    int32_t weighting;        /* RZPIC_W_ZR2 (default) or RZPIC_W_ZR          */
+    int32_t chi_face;         /* RZPIC_FACE_AVG or RZPIC_FACE_MAX             */
+    int32_t fixed_point_bits; /* deposit quantum = w_ref * 2^-bits (0 -> 40)  */
+    double V_dc, V_rf, f_rf;  /* z=0 electrode: V_dc + V_rf sin(2 pi f_rf t) */
+    uint64_t seed;            /* Philox key of every random draw             */
+    double mg_tol;            /* relative L-inf residual target (Sec. 2.5)   */
+    int32_t mg_max_cycles;    /* cap on V(0,1) cycles per solve              */
+    int32_t mg_fixed_cycles;  /* > 0: exactly this many cycles, no test      */
+    int32_t resize_every;     /* weight split period in steps, 0 = never     */
+    int32_t reserved0;
+    double resize_wcoef;      /* split weight w_r(r) = resize_wcoef*max(r,hr/2) */
+    double n_gas, T_gas, m_gas; /* neutral density (m^-3), temperature (K), mass (kg) */
+} rzpic_config;
+
+typedef struct rzpic_species_view {
+    /* device arrays of `capacity` elements (double in FP64, float in MIXED) */
+    void *r, *z, *vr, *vt, *vz, *ar, *az, *w;
+    uint64_t *id;             /* device, unique particle identities          */
+    uint8_t *mc_event;        /* optional device array (capacity bytes) of MC
+                                 event codes of the last collision pass, or NULL */
+    int64_t capacity;         /* elements of every array above              */
+    double q, m;              /* charge (C) and mass (kg)                    */
+    double w_ref;             /* reference weight of the fixed-point deposit */
+    int32_t mc_model;         /* RZPIC_MC_*                                  */
+    int32_t reserved0;
+} rzpic_species_view;
+
+typedef struct rzpic_diag {
+    int64_t count[2];          /* live particles per species                */
+    uint64_t next_id[2];       /* next identity to assign per species       */
+    double absorbed[2][3];     /* cumulative weight absorbed at z=0, z=L, r=R */
+    int64_t candidates[2];     /* MC candidates of the last collision pass  */
+    int64_t events[2][4];      /* real collisions per process, last pass    */
+    int32_t last_cycles;       /* V-cycles of the last solve                */
+    int32_t status;            /* sticky device status (rzpic_status)       */
+    double last_relres;        /* ||f - A phi||_inf / ||f_bc||_inf, last solve (tol mode) */
+} rzpic_diag;
+
+typedef struct rzpic_ctx rzpic_ctx;
+
+/* Create a context on the current HIP device.  `stream` is a hipStream_t (NULL
+ * = default stream).  Allocates every internal grid and multigrid level;
+ * particle work buffers are allocated by rzpic_bind_species.  Validates the
+ * configuration (EINVAL with a message). */
+rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out);
+/* Free a context and everything it allocated (synchronises its stream). */
+rzpic_status rzpic_destroy(rzpic_ctx *ctx);
+/* Change the stream later work is enqueued on. */
+rzpic_status rzpic_set_stream(rzpic_ctx *ctx, void *stream);
+
+/* Attach caller-owned particle arrays of species s (0 or 1).  The arrays must
+ * outlive the binding.  Allocates per-species scratch sized by `capacity`
+ * (chunk tables, new-particle staging).  The particle count becomes 0. */
+rzpic_status rzpic_bind_species(rzpic_ctx *ctx, int32_t s, const rzpic_species_view *v);
+/* Set the live count n (<= capacity) and the next identity of species s
+ * (asynchronous host-to-device write). */
+rzpic_status rzpic_set_count(rzpic_ctx *ctx, int32_t s, int64_t n, uint64_t next_id);
+/* Read the live count and next identity (synchronises). */
+rzpic_status rzpic_get_count(rzpic_ctx *ctx, int32_t s, int64_t *n, uint64_t *next_id);
+
+/* Cross sections of species s (Sec. 2.6) on the uniform energy grid
+ * eps_k = k*de eV, k < ne: host arrays kind[nproc] (RZPIC_P_*), thr_eV[nproc]
+ * and sigma[nproc][ne] (m^2, linearly interpolated, 1/E above the table).
+ * ej_B is the ejected-electron energy constant (eV) of ionization.  Computes
+ * the null-collision frequency nu_max (a rigorous bound of n_gas*sigma_T*g
+ * over all energies) and P_null = 1 - exp(-nu_max dt) on the host. */
+rzpic_status rzpic_set_xsec(rzpic_ctx *ctx, int32_t s, int32_t nproc, const int32_t *kind,
+                            const double *thr_eV, double de, int32_t ne, const double *sigma,
+                            double ej_B);
+rzpic_status rzpic_get_mc_consts(rzpic_ctx *ctx, int32_t s, double *nu_max, double *p_null);
+
+/* Sec. 2.3 initialisation of n particles of species s: r = U R, z = U L,
+ * w = 2 pi n0 R L r / n (uniform density n0), Maxwellian velocities at T_eV,
+ * zero damped accelerations, identities id0 .. id0+n-1 (Philox draws keyed by
+ * (seed, s, id, step 0xFFFFFFFF)).  Sets the count to n. */
+rzpic_status rzpic_init_particles(rzpic_ctx *ctx, int32_t s, int64_t n, double n0,
+                                  double T_eV, uint64_t id0);
+
+/* --- the cycle of Sec. 2.1, one operation per call --------------------- */
+/* First push in the local X-Y frame and rotation onto the new radius
+ * (Sec. 2.3); absorbed particles are marked and tallied. */
+rzpic_status rzpic_push_first(rzpic_ctx *ctx, int32_t s);
+/* Deposit N_ij of both species from scratch (Sec. 2.4), then n = N/V,
+ * rho = sum q n and chi = sum q^2 n dt^2 / (2 m eps0) (Sec. 2.1). */
+rzpic_status rzpic_deposit(rzpic_ctx *ctx);
+/* Multigrid solve (Sec. 2.5) of the implicit field equation with phi = V(t)
+ * on z = 0, 0 on z = L and r = R, warm-started from the current phi.
+ * Fixed-cycle mode runs config.mg_fixed_cycles V(0,1) cycles without a
+ * test; otherwise cycles until the relative residual <= mg_tol (this mode
+ * synchronises once per cycle).  cycles / relres (host, may be NULL) receive
+ * the cycles run and the final relative residual (requesting them
+ * synchronises).  ENOTCONV if the tolerance is not met. */
+rzpic_status rzpic_solve(rzpic_ctx *ctx, double t, int32_t *cycles, double *relres);
+/* E = -grad phi on the nodes. */
+rzpic_status rzpic_efield(rzpic_ctx *ctx);
+/* Gather of E at the first-pushed position, final push, damped-acceleration
+ * update, axis rule and absorption (Sec. 2.1, 2.3). */
+rzpic_status rzpic_push_final(rzpic_ctx *ctx, int32_t s);
+/* Null-collision Monte Carlo of species s at step `step` (Sec. 2.6).  New
+ * particles wait in staging until rzpic_compact; rzpic_push_first and
+ * rzpic_deposit include them. */
+rzpic_status rzpic_collide(rzpic_ctx *ctx, int32_t s, int64_t step);
+/* Remove absorbed particles (holes below n-D filled in order by the live
+ * particles of [n-D, n)) and append the staged new particles of species s. */
+rzpic_status rzpic_compact(rzpic_ctx *ctx, int32_t s);
+/* Weight split of Sec. 2.2 (clones appended in parent order). */
+rzpic_status rzpic_resize(rzpic_ctx *ctx, int32_t s);
+/* After initialisation: first push, deposit and compaction of both species. */
+rzpic_status rzpic_prologue(rzpic_ctx *ctx);
+/* One merged step n (Sec. 2.1): finalize rho/chi, solve at t = (n+1) dt,
+ * E, one fused particle pass per species (gather, final push, MC, first
+ * push, deposit), compaction, and the periodic weight split.  Equal, bit for
+ * bit, to the composition of the single operations above. */
+rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
+
+/* Copy grid `which` (RZPIC_G_*) between the context and a caller device
+ * buffer of nz*nr doubles: to_ctx = 0 reads from the context, 1 writes into
+ * it (PHI, RHO, CHI, ER, EZ, N0, N1 writable).  Asynchronous. */
+rzpic_status rzpic_grid_copy(rzpic_ctx *ctx, int32_t which, double *dev, int32_t to_ctx);
+/* Diagnostics (synchronises; returns the sticky device status). */
+rzpic_status rzpic_get_diag(rzpic_ctx *ctx, rzpic_diag *out);
+/* Synchronise the stream and return (and clear) the sticky device status. */
+rzpic_status rzpic_sync(rzpic_ctx *ctx);
+/* Message of the last failure on this thread. */
+const char *rzpic_last_error(void);
+/* Physical constants used inside the library: e, m_e, amu, eps0, k_B, 2 pi. */
+void rzpic_constants(double out[6]);
+/* Kernel time accounting: average device time (ms) of the last `rzpic_step`
+ * phases measured with HIP events when timing is enabled:
+ * out[0] = whole step, out[1] = field solve, out[2] = particle passes,
+ * out[3] = compaction; out[4] = V-cycles in the last solve. */
+rzpic_status rzpic_set_timing(rzpic_ctx *ctx, int32_t enable);
+rzpic_status rzpic_get_timing(rzpic_ctx *ctx, double out[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,371 @@
+// Device helpers: counter-based random numbers, particle/grid weights, the
+// particle push steps and the collision outcomes, shared by the kernels.
+#pragma once
+
+#include "internal.h"
+
+namespace rz {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): per round the words
+// (c0, c2) are multiplied by the published 32-bit multipliers; the high halves
+// are xored with the other two words and the key, which is bumped by the
+// published Weyl constants between rounds.
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Two uniforms in (0,1) from draw block `blk` of (seed, species, id, step):
+// counter (id lo, id hi, step, species<<16 | blk), key = seed; each pair of
+// words gives a 52-bit integer u and U = (u + 1/2) 2^-52, exact in FP64.
+__device__ __forceinline__ void uniform2(uint64_t seed, int s, uint64_t id, uint32_t step,
+                                         uint32_t blk, double &a, double &b)
+{
+    U4 c{(uint32_t)id, (uint32_t)(id >> 32), step, ((uint32_t)s << 16) | (blk & 0xFFFFu)};
+    U4 x = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    uint64_t ua = ((uint64_t)x.x << 20) | (uint64_t)(x.y >> 12);
+    uint64_t ub = ((uint64_t)x.z << 20) | (uint64_t)(x.w >> 12);
+    a = ((double)ua + 0.5) * 0x1p-52;
+    b = ((double)ub + 0.5) * 0x1p-52;
+}
+
+__device__ __forceinline__ void normal2(double ua, double ub, double &n1, double &n2)
+{
+    double rad = sqrt(-2.0 * log(ua));
+    double sn, cs;
+    sincos(kTwoPi * ub, &sn, &cs);
+    n1 = rad * cs;
+    n2 = rad * sn;
+}
+
+// ---------------------------------------------------------------------------
+// Bilinear weights of Sec. 2.4 in (z, r^2) or (z, r).
+
+template <typename T> struct W4 {
+    int g;       // index of node (i, j)
+    T sz0, sz1, sr0, sr1;
+};
+
+template <typename T> __device__ __forceinline__ const T *inv2j1_of(const Mesh &m);
+template <> __device__ __forceinline__ const double *inv2j1_of<double>(const Mesh &m)
+{
+    return m.inv2j1;
+}
+template <> __device__ __forceinline__ const float *inv2j1_of<float>(const Mesh &m)
+{
+    return m.inv2j1f;
+}
+
+template <typename T> __device__ __forceinline__ W4<T> weights(const Mesh &m, T r, T z)
+{
+    W4<T> q;
+    const T ihz = (T)m.inv_hz, ihr = (T)m.inv_hr;
+    T xz = z * ihz, xr = r * ihr;
+    int i = (int)xz, j = (int)xr;
+    i = i < 0 ? 0 : (i > m.nz - 2 ? m.nz - 2 : i);
+    j = j < 0 ? 0 : (j > m.nr - 2 ? m.nr - 2 : j);
+    q.g = i * m.nr + j;
+    T zi = (T)i * (T)m.hz, zi1 = (T)(i + 1) * (T)m.hz;
+    q.sz0 = (zi1 - z) * ihz;
+    q.sz1 = (z - zi) * ihz;
+    if (m.weighting == 1) {
+        T rj = (T)j * (T)m.hr, rj1 = (T)(j + 1) * (T)m.hr;
+        q.sr0 = (rj1 - r) * ihr;
+        q.sr1 = (r - rj) * ihr;
+    } else {
+        // (r_{j+1}^2 - r^2) / (r_{j+1}^2 - r_j^2) with r = x hr: ((j+1)^2 - x^2) / (2j+1)
+        T x2 = xr * xr;
+        T inv = inv2j1_of<T>(m)[j];
+        q.sr0 = ((T)((j + 1) * (j + 1)) - x2) * inv;
+        q.sr1 = (x2 - (T)(j * j)) * inv;
+    }
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// Cross sections (Sec. 2.6): linear interpolation, 1/E law above the table.
+// Evaluated with contraction off so that it rounds exactly like the host
+// reference arithmetic on identical inputs (decisions depend on it).
+
+__device__ __noinline__ double xsec_at(const Xsec &x, int k, double eps)
+{
+#pragma clang fp contract(off)
+    const double *sg = x.sigma + (size_t)k * x.ne;
+    if (eps >= x.emax) return sg[x.ne - 1] * (x.emax / eps);
+    double xx = eps / x.de;
+    int j = (int)xx;
+    if (j > x.ne - 2) j = x.ne - 2;
+    double t = xx - (double)j;
+    return sg[j] + t * (sg[j + 1] - sg[j]);
+}
+
+// Process chosen by a candidate with uniform u1: the first k with
+// u1 * nu_max < sum_{k' <= k} n_gas sigma_k'(eps) g, or -1 (null collision).
+__device__ __noinline__ int choose_process(const Xsec &x, double n_gas, double thr_nu, double eps,
+                                           double g)
+{
+#pragma clang fp contract(off)
+    double cum = 0.0;
+    for (int k = 0; k < x.nproc; ++k) {
+        cum += n_gas * xsec_at(x, k, eps) * g;
+        if (thr_nu < cum) return k;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ double energy_ev(double v0, double v1, double v2, double ekin)
+{
+#pragma clang fp contract(off)
+    double v2s = v0 * v0 + v1 * v1 + v2 * v2;
+    return v2s * ekin;
+}
+
+__device__ __forceinline__ double sumsq3(double a, double b, double c)
+{
+#pragma clang fp contract(off)
+    return a * a + b * b + c * c;
+}
+
+// Turn unit vector u by polar angle chi (cosine cx) and azimuth phi about
+// itself; azimuth measured from p = (a x u)/|a x u|, a = z (or x if u is within
+// ~8 degrees of z), q = u x p.
+__device__ __forceinline__ void turn(double &u0, double &u1, double &u2, double cx, double phi)
+{
+    double px, py, pz;
+    if (fabs(u2) < 0.99) {
+        px = -u1;
+        py = u0;
+        pz = 0.0;
+    } else {
+        px = 0.0;
+        py = -u2;
+        pz = u1;
+    }
+    double pn = sqrt(px * px + py * py + pz * pz);
+    px /= pn;
+    py /= pn;
+    pz /= pn;
+    double qx = u1 * pz - u2 * py;
+    double qy = u2 * px - u0 * pz;
+    double qz = u0 * py - u1 * px;
+    double sx = sqrt(fmax(0.0, 1.0 - cx * cx));
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    double n0 = cx * u0 + sx * (cp * px + sp * qx);
+    double n1 = cx * u1 + sx * (cp * py + sp * qy);
+    double n2 = cx * u2 + sx * (cp * pz + sp * qz);
+    u0 = n0;
+    u1 = n1;
+    u2 = n2;
+}
+
+// Vahedi & Surendra (1995) electron scattering angle, eps in eV.
+__device__ __forceinline__ double cos_chi_e(double eps, double R)
+{
+    if (!(eps > 0.0)) return 1.0 - 2.0 * R;
+    double c = (2.0 + eps - 2.0 * pow(1.0 + eps, R)) / eps;
+    return fmin(1.0, fmax(-1.0, c));
+}
+
+struct Child {
+    double vr, vt, vz;
+};
+
+// Null-collision test and outcome of one particle (Sec. 2.6).  Returns the
+// event code (0 none, 1 null, 2+k process k).  v[] is updated in place; an
+// ionization fills the ejected electron and the new ion velocities and sets
+// *iz.  Draw blocks: 0 = (candidate, process); electrons: 1 = (chi, phi),
+// 2 = (ejected energy, chi_ej), 3 = (phi_ej, -), 4-5 = ion normals;
+// ions: 1-2 = target normals, 3 = (cos chi, phi) in the centre of mass.
+__device__ __noinline__ int collide(const SpeciesK &sp, const Phys &ph, uint64_t id,
+                                    uint32_t step, double &v0, double &v1, double &v2, int &iz,
+                                    Child &ce, Child &ci)
+{
+    iz = 0;
+    double ua, ub;
+    uniform2(ph.seed, sp.s, id, step, 0, ua, ub);
+    if (!(ua < sp.p_null)) return 0;
+    double thr_nu = ub * sp.nu_max;
+    if (sp.mc_model == 1) {
+        double eps = energy_ev(v0, v1, v2, sp.ekin);
+        double vm = sqrt(sumsq3(v0, v1, v2));
+        int k = choose_process(sp.xs, ph.n_gas, thr_nu, eps, vm);
+        if (k < 0) return 1;
+        double u0 = 0.0, u1 = 0.0, u2 = 1.0;
+        if (vm > 0.0) {
+            u0 = v0 / vm;
+            u1 = v1 / vm;
+            u2 = v2 / vm;
+        }
+        double ra, rb;
+        uniform2(ph.seed, sp.s, id, step, 1, ra, rb);
+        int kind = sp.xs.kind[k];
+        const double m = sp.m;
+        if (kind == 0) {
+            double cx = cos_chi_e(eps, ra);
+            double eps1 = eps * (1.0 - (2.0 * m / ph.m_gas) * (1.0 - cx));
+            turn(u0, u1, u2, cx, kTwoPi * rb);
+            double s1 = sqrt(2.0 * eps1 * kE / m);
+            v0 = s1 * u0;
+            v1 = s1 * u1;
+            v2 = s1 * u2;
+            return 2 + k;
+        }
+        double ex;
+        {
+#pragma clang fp contract(off)
+            ex = eps - sp.xs.thr[k];
+        }
+        if (ex < 0.0) return 1;
+        if (kind == 1) {
+            double cx = cos_chi_e(ex, ra);
+            turn(u0, u1, u2, cx, kTwoPi * rb);
+            double s1 = sqrt(2.0 * ex * kE / m);
+            v0 = s1 * u0;
+            v1 = s1 * u1;
+            v2 = s1 * u2;
+            return 2 + k;
+        }
+        double rc, rd, re, rf;
+        uniform2(ph.seed, sp.s, id, step, 2, rc, rd);
+        uniform2(ph.seed, sp.s, id, step, 3, re, rf);
+        const double B = sp.xs.ejB;
+        double eej = B * tan(rc * atan(ex / (2.0 * B)));
+        double esc = ex - eej;
+        double s0 = u0, s1_ = u1, s2 = u2;
+        turn(s0, s1_, s2, cos_chi_e(esc, ra), kTwoPi * rb);
+        double e0 = u0, e1 = u1, e2 = u2;
+        turn(e0, e1, e2, cos_chi_e(eej, rd), kTwoPi * re);
+        double vs = sqrt(2.0 * esc * kE / m);
+        double ve = sqrt(2.0 * eej * kE / m);
+        v0 = vs * s0;
+        v1 = vs * s1_;
+        v2 = vs * s2;
+        ce.vr = ve * e0;
+        ce.vt = ve * e1;
+        ce.vz = ve * e2;
+        double g1a, g1b, g2a, g2b, n1, n2, n3, n4;
+        uniform2(ph.seed, sp.s, id, step, 4, g1a, g1b);
+        uniform2(ph.seed, sp.s, id, step, 5, g2a, g2b);
+        normal2(g1a, g1b, n1, n2);
+        normal2(g2a, g2b, n3, n4);
+        ci.vr = ph.vth_gas * n1;
+        ci.vt = ph.vth_gas * n2;
+        ci.vz = ph.vth_gas * n3;
+        iz = 1;
+        return 2 + k;
+    }
+    if (sp.mc_model == 2) {
+        double g1a, g1b, g2a, g2b, n1, n2, n3, n4;
+        uniform2(ph.seed, sp.s, id, step, 1, g1a, g1b);
+        uniform2(ph.seed, sp.s, id, step, 2, g2a, g2b);
+        normal2(g1a, g1b, n1, n2);
+        normal2(g2a, g2b, n3, n4);
+        double t0 = ph.vth_gas * n1, t1 = ph.vth_gas * n2, t2 = ph.vth_gas * n3;
+        double g0, gg1, gg2;
+        {
+#pragma clang fp contract(off)
+            g0 = v0 - t0;
+            gg1 = v1 - t1;
+            gg2 = v2 - t2;
+        }
+        double g2s = sumsq3(g0, gg1, gg2);
+        double eps;
+        {
+#pragma clang fp contract(off)
+            eps = g2s * sp.ekin;
+        }
+        double gm = sqrt(g2s);
+        int k = choose_process(sp.xs, ph.n_gas, thr_nu, eps, gm);
+        if (k < 0) return 1;
+        double ra, rb;
+        uniform2(ph.seed, sp.s, id, step, 3, ra, rb);
+        double cx = 1.0 - 2.0 * ra;
+        double sx = sqrt(fmax(0.0, 1.0 - cx * cx));
+        double sp_, cp_;
+        sincos(kTwoPi * rb, &sp_, &cp_);
+        const double M = ph.m_gas, m = sp.m;
+        const double fcm = M / (m + M);
+        double d0 = sx * cp_, d1 = sx * sp_, d2 = cx;
+        v0 = (m * v0 + M * t0) / (m + M) + fcm * gm * d0;
+        v1 = (m * v1 + M * t1) / (m + M) + fcm * gm * d1;
+        v2 = (m * v2 + M * t2) / (m + M) + fcm * gm * d2;
+        return 2 + k;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Wave/block scans.  The block is a whole number of 64-lane waves.
+
+__device__ __forceinline__ int lane_rank(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Exclusive ranks of up to 4 flags over the block (in thread order) and their
+// totals.  `sh` needs 4 * (blockDim/64) ints of shared memory.
+__device__ __forceinline__ void block_rank4(const bool f[4], int rank[4], int total[4], int *sh)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int wr[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        unsigned long long m = __ballot(f[k]);
+        wr[k] = lane_rank(m);
+        if (lane == 0) sh[k * 16 + wv] = __popcll(m);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int before = 0, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            int c = sh[k * 16 + w];
+            before += w < wv ? c : 0;
+            tot += c;
+        }
+        rank[k] = before + wr[k];
+        total[k] = tot;
+    }
+    __syncthreads();
+}
+
+// Exclusive prefix of a non-negative int over the block, and its total.
+__device__ __forceinline__ int block_excl_sum(int v, int &total, int *sh)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        int c = sh[w];
+        before += w < wv ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return before + x - v;
+}
+
+}  // namespace rz

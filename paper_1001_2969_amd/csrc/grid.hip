@@ -1,0 +1,143 @@
+// Node-grid kernels: densities, charge and susceptibility from the deposit,
+// E = -grad phi, and fixed-point <-> double conversion of the deposit.
+#include "device.h"
+
+namespace rz {
+
+// n_s = N_s / V, rho = sum q n, chi = sum q^2 n dt^2 / (2 m eps0) (the
+// implicit susceptibility of Sec. 2.1 in SI), eps = 1 + chi, f = rho / eps0.
+// A negative accumulator means the fixed-point range overflowed.
+__global__ void k_finalize(GridArgs g)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.nn; k += gridDim.x * blockDim.x) {
+        long long a0 = (long long)g.acc0[k], a1 = (long long)g.acc1[k];
+        if (a0 < 0 || a1 < 0) atomicOr(g.status, kStNumeric);
+        double n0 = ((double)a0 * g.quantum0) / g.vol[k];
+        double n1 = ((double)a1 * g.quantum1) / g.vol[k];
+        g.dens0[k] = n0;
+        g.dens1[k] = n1;
+        double rho = 0.0, chi = 0.0;
+        rho += g.q0 * n0;
+        chi += g.q0 * g.q0 * n0 * g.dt * g.dt / (2.0 * g.m0 * kEps0);
+        rho += g.q1 * n1;
+        chi += g.q1 * g.q1 * n1 * g.dt * g.dt / (2.0 * g.m1 * kEps0);
+        g.rho[k] = rho;
+        g.chi[k] = chi;
+        g.eps[k] = 1.0 + chi;
+        if (g.eps32) g.eps32[k] = (float)(1.0 + chi);
+        g.f[k] = rho / kEps0;
+        if (g.zero_acc) {
+            g.acc0w[k] = 0;
+            g.acc1w[k] = 0;
+        }
+    }
+}
+
+hipError_t launch_finalize(const GridArgs &g, hipStream_t st)
+{
+    int threads = 256, blocks = (g.nn + threads - 1) / threads;
+    hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(threads), 0, st, g);
+    return hipGetLastError();
+}
+
+// E = -grad phi: centred differences inside, one-sided on z = 0, z = L and
+// r = R, E_r = 0 on the axis.  Also the interleaved (E_r, E_z) copy that the
+// particle gather reads (in the particles' precision).
+template <typename T>
+__global__ void k_efield(int nr, int nz, double hr, double hz, const double *phi, double *er,
+                         double *ez, typename Vec2<T>::type *E2)
+{
+    const int nn = nr * nz;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += gridDim.x * blockDim.x) {
+        int i = g / nr, j = g - i * nr;
+        double vz, vr;
+        if (i == 0) vz = -(phi[g + nr] - phi[g]) / hz;
+        else if (i == nz - 1) vz = -(phi[g] - phi[g - nr]) / hz;
+        else vz = -(phi[g + nr] - phi[g - nr]) / (2.0 * hz);
+        if (j == 0) vr = 0.0;
+        else if (j == nr - 1) vr = -(phi[g] - phi[g - 1]) / hr;
+        else vr = -(phi[g + 1] - phi[g - 1]) / (2.0 * hr);
+        er[g] = vr;
+        ez[g] = vz;
+        typename Vec2<T>::type e;
+        e.x = (T)vr;
+        e.y = (T)vz;
+        E2[g] = e;
+    }
+}
+
+template <typename T>
+hipError_t launch_efield(int nr, int nz, double hr, double hz, const double *phi, double *er,
+                         double *ez, typename Vec2<T>::type *E2, hipStream_t st)
+{
+    int nn = nr * nz, threads = 256, blocks = (nn + threads - 1) / threads;
+    hipLaunchKernelGGL((k_efield<T>), dim3(blocks), dim3(threads), 0, st, nr, nz, hr, hz, phi, er,
+                       ez, E2);
+    return hipGetLastError();
+}
+
+// Interleaved gather copy of caller-written E_r, E_z.
+template <typename T>
+__global__ void k_pack_e2(int nn, const double *er, const double *ez, typename Vec2<T>::type *E2)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += gridDim.x * blockDim.x) {
+        typename Vec2<T>::type e;
+        e.x = (T)er[g];
+        e.y = (T)ez[g];
+        E2[g] = e;
+    }
+}
+
+template <typename T>
+hipError_t launch_pack_e2(int nn, const double *er, const double *ez, typename Vec2<T>::type *E2,
+                          hipStream_t st)
+{
+    int threads = 256, blocks = (nn + threads - 1) / threads;
+    hipLaunchKernelGGL((k_pack_e2<T>), dim3(blocks), dim3(threads), 0, st, nn, er, ez, E2);
+    return hipGetLastError();
+}
+
+__global__ void k_acc_convert(int nn, unsigned long long *acc, double *dev, double quantum,
+                              int to_acc)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += gridDim.x * blockDim.x) {
+        if (to_acc) acc[g] = (unsigned long long)__double2ll_rn(dev[g] / quantum);
+        else dev[g] = (double)(long long)acc[g] * quantum;
+    }
+}
+
+hipError_t launch_acc_convert(int nn, unsigned long long *acc, double *dev, double quantum,
+                              int to_acc, hipStream_t st)
+{
+    int threads = 256, blocks = (nn + threads - 1) / threads;
+    hipLaunchKernelGGL(k_acc_convert, dim3(blocks), dim3(threads), 0, st, nn, acc, dev, quantum,
+                       to_acc);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st)
+{
+    int threads = 256;
+    int64_t b = (n + threads - 1) / threads;
+    int blocks = (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(threads), 0, st, p, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pack_e2<double>(int, const double *, const double *, double2 *,
+                                           hipStream_t);
+template hipError_t launch_pack_e2<float>(int, const double *, const double *, float2 *,
+                                          hipStream_t);
+template hipError_t launch_efield<double>(int, int, double, double, const double *, double *,
+                                          double *, double2 *, hipStream_t);
+template hipError_t launch_efield<float>(int, int, double, double, const double *, double *,
+                                         double *, float2 *, hipStream_t);
+
+}  // namespace rz

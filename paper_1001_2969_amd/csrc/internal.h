@@ -1,0 +1,226 @@
+// Internal definitions shared by the library's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rz {
+
+// Physical constants (CODATA 2018, SI).
+constexpr double kE = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kKb = 1.380649e-23;
+constexpr double kTwoPi = 6.283185307179586;
+
+constexpr int kMaxProc = 4;
+constexpr int kMaxLevels = 16;
+constexpr int kMinChunk = 256;   // smallest particle chunk (= pass block size)
+constexpr int kMaxChunk = 1024;  // largest particle chunk
+constexpr int kMaxLine = 2048;   // longest r-line (nr - 1 unknowns) the smoother takes
+
+// Device status bits (sticky).
+enum : int32_t {
+    kStCapacity = 1,
+    kStNumeric = 2,
+};
+
+// Pass mode bits of the particle kernel.
+enum : int {
+    M_FINAL = 1,   // gather + final push + axis rule + absorption
+    M_MC = 2,      // null-collision Monte Carlo, children staged
+    M_FIRST = 4,   // first push + rotation + absorption
+    M_DEP = 8,     // deposit at the (new) position
+    M_MARK = 16,   // unmerged form: dead particles carry w = -1, skipped on input
+    M_LISTS = 32,  // merged form: per-chunk dead lists built in the pass
+    M_LDS = 64,    // deposit into an LDS copy of the whole grid, flushed to a slice
+};
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename T> struct Parts {
+    T *r, *z, *vr, *vt, *vz, *ar, *az, *w;
+    uint64_t *id;
+};
+
+struct Mesh {
+    int nr, nz, nn, weighting;
+    double R, L, hr, hz, inv_hr, inv_hz;
+    const double *inv2j1;  // 1 / (2j + 1)
+    const float *inv2j1f;
+};
+
+struct Xsec {
+    const double *sigma;   // [nproc][ne]
+    int nproc, ne;
+    double de, emax;
+    int kind[kMaxProc];
+    double thr[kMaxProc];
+    double ejB;
+};
+
+struct SpeciesK {
+    int s, mc_model;
+    double q, m, qm;
+    double k1, k2;          // 0.5 q/m dt^2, 0.5 q/m dt
+    double inv_quantum;     // 2^bits / w_ref
+    double p_null, nu_max;
+    double ekin;            // 0.5 * (pair mass) / e : eV per (m/s)^2
+    double mu;              // pair mass
+    Xsec xs;
+};
+
+struct Phys {
+    double dt, n_gas, T_gas, m_gas, vth_gas;
+    double R, L;
+    uint64_t seed;
+    double ion_acc_ratio;   // q_i m_e / (q_e m_i) for new ions
+    double ion_inv_quantum; // fixed-point scale of the ion deposit
+};
+
+struct Counts {      // per species, device resident
+    int64_t n;       // live particles in the array
+    uint64_t next_id;
+};
+
+struct FixRec {       // per species, written by the dead-list scan
+    int64_t n_old, dead, keep, pad;
+};
+
+struct ChildRec {     // new particles staged by the electron pass
+    int64_t n_parent;                // electron count when they were staged
+    int64_t ev_total;                // ionization events
+    int64_t surv_total[2];           // survivors per child species
+    uint64_t next_id_old[2];         // identities before this batch
+};
+
+struct CloneRec {     // weight split of one species
+    int64_t n_old, total, ok, pad;
+    uint64_t next_id_old;
+};
+
+struct Chunks {       // per parent species; chunk = `chunk` consecutive particles
+    int32_t *dead_cnt, *ev_cnt, *surv_e, *surv_i, *clone_cnt;
+    int32_t *dead_list;                    // [chunk*B + k] local dead indices
+    int64_t *dead_off, *ev_off, *surv_e_off, *surv_i_off, *clone_off;
+    int64_t *dead_glob;                    // sorted global dead list
+    int32_t *pcount;                       // per particle clone count (resize)
+};
+
+template <typename T> struct PassArgs {
+    Parts<T> p;              // particles of species s
+    Parts<T> ce, ci;         // staging of new electrons / ions (electron pass)
+    const Counts *cnt;
+    Chunks ch;
+    Mesh mesh;
+    Phys phys;
+    SpeciesK sp;
+    const typename Vec2<T>::type *E2;
+    unsigned long long *acc;      // deposit of species s (global)
+    unsigned long long *acc_ion;  // deposit of new ions (global)
+    unsigned long long *slices;   // per-block LDS flush [gridDim][nn]
+    unsigned long long *tally;    // [3] absorbed weight of species s, fixed point
+    unsigned long long *tally_ion;
+    unsigned long long *mcstat;   // [1 + kMaxProc] candidates, events per process
+    uint8_t *ev;                  // optional per-particle event codes
+    ChildRec *crec;               // electron pass records n_parent here
+    int32_t *status;
+    uint32_t step;
+    int chunk;                    // particles per chunk (staged kernels)
+};
+
+// Host-side launchers (defined in the .hip files).
+template <typename T>
+hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_staged(int mode, const PassArgs<T> &a, int32_t *surv, hipStream_t st);
+template <typename T>
+hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t id0, int s,
+                       const Phys &phys, double m, hipStream_t st);
+
+// fixup.hip: deterministic removal of absorbed particles and appending of new
+// ones (identities in parent order, independent of the launch shape).
+struct ScanJobs {
+    int chunk;
+    // job 0: children of the electron pass
+    int children;
+    Chunks ech;
+    const Counts *ecnt, *icnt;
+    ChildRec *crec;
+    // jobs 1, 2: dead lists of species 0 and 1
+    int dead[2];
+    Chunks ch[2];
+    const Counts *cnt[2];
+    FixRec *fix[2];
+};
+hipError_t launch_scan(const ScanJobs &j, hipStream_t st);
+template <typename T>
+hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, int chunk, hipStream_t st);
+hipError_t launch_dead_list(Chunks ch, const Counts *cnt, const FixRec *fix, int chunk,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st);
+// Append the staged children of species `cs` (slots of electron chunks) after
+// the kept particles and commit the new count and next identity.
+template <typename T>
+hipError_t launch_append(Parts<T> dst, Parts<T> stage, int cs, Chunks ech, int children,
+                         const ChildRec *crec, const FixRec *fix, Counts *cnt, int64_t cap,
+                         int chunk, int32_t *status, hipStream_t st);
+template <typename T>
+hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, int chunk,
+                         double wcoef, double half_hr, int64_t cap, int32_t *status,
+                         hipStream_t st);
+hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
+                                int nn, hipStream_t st);
+
+// grid.hip
+struct GridArgs {
+    int nr, nz, nn;
+    double hr, hz, dt;
+    const unsigned long long *acc0, *acc1;
+    double quantum0, quantum1;
+    double q0, q1, m0, m1;
+    const double *vol;
+    double *dens0, *dens1, *rho, *chi, *eps, *f;
+    float *eps32;
+    int zero_acc;
+    unsigned long long *acc0w, *acc1w;
+    int32_t *status;
+};
+hipError_t launch_finalize(const GridArgs &g, hipStream_t st);
+template <typename T>
+hipError_t launch_efield(int nr, int nz, double hr, double hz, const double *phi, double *er,
+                         double *ez, typename Vec2<T>::type *E2, hipStream_t st);
+template <typename T>
+hipError_t launch_pack_e2(int nn, const double *er, const double *ez, typename Vec2<T>::type *E2,
+                          hipStream_t st);
+hipError_t launch_acc_convert(int nn, unsigned long long *acc, double *dev, double quantum,
+                              int to_acc, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st);
+
+// mg.hip
+struct MgLevels {
+    int L, nr;
+    double *res;                   // finest-level residual scratch
+    int nzl[kMaxLevels + 1];
+    double hzl[kMaxLevels + 1];
+    double *eps64[kMaxLevels + 1];
+    float *eps32[kMaxLevels + 1];
+    double *u64[kMaxLevels + 1], *f64[kMaxLevels + 1];
+    float *u32[kMaxLevels + 1], *f32[kMaxLevels + 1];
+    int chi_face;
+    double hr;
+};
+hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st);
+hipError_t mg_set_bc(double *phi, int nr, int nz, double V, hipStream_t st);
+hipError_t mg_resid_norm(const MgLevels &m, const double *u, const double *f, int zero_interior,
+                         unsigned long long *norm, hipStream_t st);
+hipError_t mg_vcycle(const MgLevels &m, int mixed, double *phi, const double *f,
+                     unsigned long long *norm, hipStream_t st);
+
+}  // namespace rz

@@ -1,0 +1,399 @@
+// Particle kernels: the fused pass of the D1 cycle (gather, final push,
+// Monte Carlo, first push, deposit), initialisation and the pass over staged
+// new particles.
+#include "device.h"
+
+namespace rz {
+
+// Deposit of one particle (Sec. 2.4): N_ij += w S_z S_r, accumulated in fixed
+// point (quantum = w_ref 2^-bits) so that the sum does not depend on order.
+template <typename T>
+__device__ __forceinline__ void deposit4(unsigned long long *acc, const Mesh &m, const W4<T> &q,
+                                         double w, double inv_quantum)
+{
+    const double ws = w * inv_quantum;
+    const double a = (double)q.sz0 * (double)q.sr0, b = (double)q.sz0 * (double)q.sr1;
+    const double c = (double)q.sz1 * (double)q.sr0, d = (double)q.sz1 * (double)q.sr1;
+    atomicAdd(acc + q.g, (unsigned long long)__double2ll_rn(ws * a));
+    atomicAdd(acc + q.g + 1, (unsigned long long)__double2ll_rn(ws * b));
+    atomicAdd(acc + q.g + m.nr, (unsigned long long)__double2ll_rn(ws * c));
+    atomicAdd(acc + q.g + m.nr + 1, (unsigned long long)__double2ll_rn(ws * d));
+}
+
+__device__ __forceinline__ void tally_add(unsigned long long *t, int b, double w, double inv_q)
+{
+    atomicAdd(t + b, (unsigned long long)__double2ll_rn(w * inv_q));
+}
+
+template <typename T> struct PState {
+    T r, z, vr, vt, vz, ar, az, w;
+};
+
+// Absorption at the electrodes (z <= 0, z >= L) and the wall (r >= R).
+template <typename T> __device__ __forceinline__ int boundary_of(const PState<T> &s, const Phys &ph)
+{
+    if (s.z <= (T)0) return 0;
+    if (s.z >= (T)ph.L) return 1;
+    if (s.r >= (T)ph.R) return 2;
+    return -1;
+}
+
+// First push in the local X-Y frame plus rotation (Sec. 2.3); a_theta = 0.
+template <typename T> __device__ __forceinline__ void first_push(PState<T> &s, T dt)
+{
+    const T half = (T)0.5;
+    T vx = s.vr + half * s.ar * dt;
+    T vy = s.vt;
+    T x = s.r + vx * dt;
+    T y = vy * dt;
+    T vz = s.vz + half * s.az * dt;
+    T z = s.z + vz * dt;
+    T rn = sqrt(x * x + y * y);
+    T c = (T)1, sn = (T)0;
+    if (rn > (T)0) {
+        c = x / rn;
+        sn = y / rn;
+    }
+    s.r = rn;
+    s.z = z;
+    s.vr = vx * c + vy * sn;
+    s.vt = -vx * sn + vy * c;
+    s.vz = vz;
+    s.ar = s.ar * c;
+}
+
+// Gather E at (r, z) with the deposit weights, then the final push, the
+// damped-acceleration update and the axis rule (Sec. 2.1, 2.3).
+template <typename T>
+__device__ __forceinline__ void final_push(PState<T> &s, const Mesh &m,
+                                           const typename Vec2<T>::type *E2, T k1, T k2, T qm)
+{
+    W4<T> q = weights<T>(m, s.r, s.z);
+    auto e00 = E2[q.g], e01 = E2[q.g + 1], e10 = E2[q.g + m.nr], e11 = E2[q.g + m.nr + 1];
+    T w00 = q.sz0 * q.sr0, w01 = q.sz0 * q.sr1, w10 = q.sz1 * q.sr0, w11 = q.sz1 * q.sr1;
+    T Er = w00 * e00.x + w01 * e01.x + w10 * e10.x + w11 * e11.x;
+    T Ez = w00 * e00.y + w01 * e01.y + w10 * e10.y + w11 * e11.y;
+    T r = s.r + k1 * Er;
+    T z = s.z + k1 * Ez;
+    T vr = s.vr + k2 * Er;
+    T vz = s.vz + k2 * Ez;
+    T ar = (T)0.5 * (qm * Er + s.ar);
+    T az = (T)0.5 * (qm * Ez + s.az);
+    if (r < (T)0) {
+        r = -r;
+        vr = fabs(vr);
+        ar = fabs(ar);
+    }
+    s.r = r;
+    s.z = z;
+    s.vr = vr;
+    s.vz = vz;
+    s.ar = ar;
+    s.az = az;
+}
+
+template <typename T> __device__ __forceinline__ PState<T> load(const Parts<T> &p, int64_t i)
+{
+    return PState<T>{p.r[i], p.z[i], p.vr[i], p.vt[i], p.vz[i], p.ar[i], p.az[i], p.w[i]};
+}
+
+template <typename T>
+__device__ __forceinline__ void store(const Parts<T> &p, int64_t i, const PState<T> &s, bool w)
+{
+    p.r[i] = s.r;
+    p.z[i] = s.z;
+    p.vr[i] = s.vr;
+    p.vt[i] = s.vt;
+    p.vz[i] = s.vz;
+    p.ar[i] = s.ar;
+    p.az[i] = s.az;
+    if (w) p.w[i] = s.w;
+}
+
+// One pass over the particles of a species.  The block processes chunks of
+// blockDim consecutive particles (grid-stride over chunks); MODE selects the
+// steps (M_* bits).  New particles of an ionization are staged at slot
+// (chunk*blockDim + event rank) with w = -1 when absorbed at birth; the
+// merged form also records each chunk's dead particles in increasing order.
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
+{
+    extern __shared__ unsigned long long lds_acc[];
+    __shared__ int sh_scan[64];
+    __shared__ unsigned long long sh_stat[1 + kMaxProc];
+
+    const Mesh &m = a.mesh;
+    const int B = blockDim.x;
+    const int64_t n = a.cnt->n;
+    const int64_t nch = (n + B - 1) / B;
+    const T dt = (T)a.phys.dt;
+    const T k1 = (T)a.sp.k1, k2 = (T)a.sp.k2, qm = (T)a.sp.qm;
+    constexpr bool kLds = (MODE & M_LDS) != 0;
+    constexpr bool kDep = (MODE & M_DEP) != 0;
+    unsigned long long *dep = a.acc;
+
+    if (threadIdx.x < 1 + kMaxProc) sh_stat[threadIdx.x] = 0;
+    if ((MODE & M_MC) && a.crec && blockIdx.x == 0 && threadIdx.x == 0) a.crec->n_parent = n;
+    if (kLds) {
+        for (int g = threadIdx.x; g < m.nn; g += B) lds_acc[g] = 0;
+        dep = lds_acc;
+    }
+    __syncthreads();
+
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int64_t pi = c * B + threadIdx.x;
+        const bool valid = pi < n;
+        bool live = valid;
+        PState<T> s{};
+        uint64_t id = 0;
+        if (valid) {
+            s = load(a.p, pi);
+            if (MODE & M_MC) id = a.p.id[pi];
+            if (MODE & M_MARK) live = s.w >= (T)0;
+        }
+        bool died = false;
+        if ((MODE & M_FINAL) && live) {
+            final_push<T>(s, m, a.E2, k1, k2, qm);
+            int b = boundary_of(s, a.phys);
+            if (b >= 0) {
+                tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
+                live = false;
+                died = true;
+            }
+        }
+        int iz = 0;
+        Child che{}, chi{};
+        if (MODE & M_MC) {
+            int ev = 0;
+            if (live) {
+                double v0 = s.vr, v1 = s.vt, v2 = s.vz;
+                ev = collide(a.sp, a.phys, id, a.step, v0, v1, v2, iz, che, chi);
+                if (ev >= 2) {
+                    s.vr = (T)v0;
+                    s.vt = (T)v1;
+                    s.vz = (T)v2;
+                    atomicAdd(&sh_stat[1 + ev - 2], 1ull);
+                }
+                if (ev >= 1) atomicAdd(&sh_stat[0], 1ull);
+            }
+            if (valid && a.ev) a.ev[pi] = (uint8_t)ev;
+        }
+        // New particles of an ionization sit at the parent's (final-pushed)
+        // position with its weight; the ion's damped acceleration is scaled
+        // by the charge-to-mass ratios.
+        PState<T> ne{}, ni{};
+        bool ne_live = false, ni_live = false;
+        if (iz) {
+            ne = PState<T>{s.r, s.z, (T)che.vr, (T)che.vt, (T)che.vz, s.ar, s.az, s.w};
+            ni = PState<T>{s.r,
+                           s.z,
+                           (T)chi.vr,
+                           (T)chi.vt,
+                           (T)chi.vz,
+                           (T)((double)s.ar * a.phys.ion_acc_ratio),
+                           (T)((double)s.az * a.phys.ion_acc_ratio),
+                           s.w};
+            ne_live = ni_live = true;
+        }
+        if (MODE & M_FIRST) {
+            if (live) {
+                first_push<T>(s, dt);
+                int b = boundary_of(s, a.phys);
+                if (b >= 0) {
+                    tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
+                    live = false;
+                    died = true;
+                }
+            }
+            if (iz) {
+                first_push<T>(ne, dt);
+                int b = boundary_of(ne, a.phys);
+                if (b >= 0) {
+                    tally_add(a.tally, b, (double)ne.w, a.sp.inv_quantum);
+                    ne_live = false;
+                }
+                first_push<T>(ni, dt);
+                b = boundary_of(ni, a.phys);
+                if (b >= 0) {
+                    tally_add(a.tally_ion, b, (double)ni.w, a.phys.ion_inv_quantum);
+                    ni_live = false;
+                }
+            }
+        }
+        if (kDep) {
+            if (live) deposit4<T>(dep, m, weights<T>(m, s.r, s.z), (double)s.w, a.sp.inv_quantum);
+            if (ne_live)
+                deposit4<T>(dep, m, weights<T>(m, ne.r, ne.z), (double)ne.w, a.sp.inv_quantum);
+            if (ni_live)
+                deposit4<T>(a.acc_ion, m, weights<T>(m, ni.r, ni.z), (double)ni.w,
+                            a.phys.ion_inv_quantum);
+        }
+        if (valid) {
+            if ((MODE & M_MARK) && died) {
+                a.p.w[pi] = (T)-1;
+            } else if (live && (MODE & (M_FINAL | M_MC | M_FIRST))) {
+                store(a.p, pi, s, false);
+            }
+        }
+        if (MODE & (M_LISTS | M_MC)) {
+            bool f[4] = {(bool)((MODE & M_LISTS) && died), iz != 0, ne_live, ni_live};
+            int rank[4], tot[4];
+            block_rank4(f, rank, tot, sh_scan);
+            if (MODE & M_LISTS) {
+                if (died) a.ch.dead_list[c * B + rank[0]] = threadIdx.x;
+                if (threadIdx.x == 0) a.ch.dead_cnt[c] = tot[0];
+            }
+            if (iz) {
+                int64_t slot = c * B + rank[1];
+                PState<T> e = ne, i = ni;
+                if (!ne_live) e.w = (T)-1;
+                if (!ni_live) i.w = (T)-1;
+                store(a.ce, slot, e, true);
+                store(a.ci, slot, i, true);
+            }
+            if (threadIdx.x == 0) {
+                a.ch.ev_cnt[c] = tot[1];
+                a.ch.surv_e[c] = tot[2];
+                a.ch.surv_i[c] = tot[3];
+            }
+        }
+    }
+    __syncthreads();
+    if (MODE & M_MC) {
+        if (threadIdx.x < 1 + kMaxProc && sh_stat[threadIdx.x])
+            atomicAdd(a.mcstat + threadIdx.x, sh_stat[threadIdx.x]);
+    }
+    if (kLds) {
+        unsigned long long *out = a.slices + (size_t)blockIdx.x * m.nn;
+        for (int g = threadIdx.x; g < m.nn; g += B) out[g] = lds_acc[g];
+    }
+}
+
+// Staged new particles (unmerged form): first push or deposit of the children
+// of ionizations recorded per electron chunk.  `a.p` is the staging buffer of
+// the child species, its counts in a.ch (electron chunks), the deposit goes to
+// a.acc with the child species' quantum in a.sp.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_staged(PassArgs<T> a, int32_t *surv)
+{
+    const Mesh &m = a.mesh;
+    const T dt = (T)a.phys.dt;
+    const int B = a.chunk;
+    const int64_t nch = (a.crec->n_parent + B - 1) / B;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        int ne = a.ch.ev_cnt[c];
+        for (int k = threadIdx.x; k < ne; k += blockDim.x) {
+            int64_t slot = c * B + k;
+            PState<T> s = load(a.p, slot);
+            if (s.w < (T)0) continue;
+            if (MODE & M_FIRST) {
+                first_push<T>(s, dt);
+                int b = boundary_of(s, a.phys);
+                if (b >= 0) {
+                    tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
+                    a.p.w[slot] = (T)-1;
+                    atomicSub(surv + c, 1);
+                    continue;
+                }
+                store(a.p, slot, s, false);
+            }
+            if (MODE & M_DEP)
+                deposit4<T>(a.acc, m, weights<T>(m, s.r, s.z), (double)s.w, a.sp.inv_quantum);
+        }
+    }
+}
+
+// Sec. 2.3 initialisation (C-ABI rzpic_init_particles).
+template <typename T>
+__global__ void k_init(Parts<T> p, int64_t n, double wcoef, double vth, uint64_t id0, int s,
+                       Phys ph)
+{
+    const uint32_t kInit = 0xFFFFFFFFu;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t id = id0 + (uint64_t)i;
+        double u0, u1, a0, a1, b0, b1, n1, n2, n3, n4;
+        uniform2(ph.seed, s, id, kInit, 0, u0, u1);
+        uniform2(ph.seed, s, id, kInit, 1, a0, a1);
+        uniform2(ph.seed, s, id, kInit, 2, b0, b1);
+        normal2(a0, a1, n1, n2);
+        normal2(b0, b1, n3, n4);
+        double r = u0 * ph.R;
+        p.r[i] = (T)r;
+        p.z[i] = (T)(u1 * ph.L);
+        p.vr[i] = (T)(vth * n1);
+        p.vt[i] = (T)(vth * n2);
+        p.vz[i] = (T)(vth * n3);
+        p.ar[i] = (T)0;
+        p.az[i] = (T)0;
+        p.w[i] = (T)(wcoef * r);
+        p.id[i] = id;
+    }
+}
+
+template <typename T>
+hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
+                       hipStream_t st)
+{
+#define RZ_CASE(M)                                                              \
+    case M:                                                                     \
+        hipLaunchKernelGGL((k_pass<T, M>), dim3(blocks), dim3(threads), lds, st, a); \
+        break;
+    switch (mode) {
+        RZ_CASE(M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS)
+        RZ_CASE(M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS)
+        RZ_CASE(M_FIRST | M_DEP | M_LISTS)
+        RZ_CASE(M_FIRST | M_DEP | M_LISTS | M_LDS)
+        RZ_CASE(M_DEP)
+        RZ_CASE(M_DEP | M_LDS)
+        RZ_CASE(M_DEP | M_MARK)
+        RZ_CASE(M_DEP | M_MARK | M_LDS)
+        RZ_CASE(M_FINAL | M_MARK)
+        RZ_CASE(M_FIRST | M_MARK)
+        RZ_CASE(M_MC | M_MARK)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef RZ_CASE
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_staged(int mode, const PassArgs<T> &a, int32_t *surv, hipStream_t st)
+{
+    const int blocks = 1024, threads = 256;
+    if (mode == M_FIRST)
+        hipLaunchKernelGGL((k_staged<T, M_FIRST>), dim3(blocks), dim3(threads), 0, st, a, surv);
+    else if (mode == M_DEP)
+        hipLaunchKernelGGL((k_staged<T, M_DEP>), dim3(blocks), dim3(threads), 0, st, a, surv);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t id0, int s,
+                       const Phys &phys, double m, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    double wcoef = kTwoPi * n0 * phys.R * phys.L / (double)n;
+    double vth = sqrt(T_eV * kE / m);
+    int threads = 256;
+    int64_t blocks64 = (n + threads - 1) / threads;
+    int blocks = (int)(blocks64 < 65536 ? blocks64 : 65536);
+    hipLaunchKernelGGL((k_init<T>), dim3(blocks), dim3(threads), 0, st, p, n, wcoef, vth, id0, s,
+                       phys);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pass<double>(int, const PassArgs<double> &, int, int, size_t,
+                                        hipStream_t);
+template hipError_t launch_pass<float>(int, const PassArgs<float> &, int, int, size_t, hipStream_t);
+template hipError_t launch_staged<double>(int, const PassArgs<double> &, int32_t *, hipStream_t);
+template hipError_t launch_staged<float>(int, const PassArgs<float> &, int32_t *, hipStream_t);
+template hipError_t launch_init<double>(Parts<double>, int64_t, double, double, uint64_t, int,
+                                        const Phys &, double, hipStream_t);
+template hipError_t launch_init<float>(Parts<float>, int64_t, double, double, uint64_t, int,
+                                       const Phys &, double, hipStream_t);
+
+}  // namespace rz

@@ -1,0 +1,1055 @@
+// Host runtime of the C ABI declared in include/rzpic.h: context and
+// configuration checks, device allocations, and the launch sequences of the
+// cycle of Sec. 2.1 on the caller's stream.
+#include "../../include/rzpic.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace rz;
+
+namespace {
+
+thread_local std::string g_err;
+
+rzpic_status fail(rzpic_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(RZPIC_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct SpeciesState {
+    bool bound = false;
+    rzpic_species_view v{};
+    int64_t cap = 0;
+    Chunks ch{};
+    int64_t nchunks_max = 0;
+    // staging of the new particles of ionizations (electron species only):
+    // [0] new electrons, [1] new ions, slots indexed like electron particles
+    void *stage[2][8] = {};
+    bool has_xsec = false;
+    Xsec xs{};
+    double nu_max = 0.0, p_null = 0.0;
+    DevBuf sigma;
+};
+
+}  // namespace
+
+struct rzpic_ctx {
+    rzpic_config c{};
+    hipStream_t st = nullptr;
+    int device = 0, cus = 0;
+    size_t lds_block = 0, lds_cu = 0;
+    int mixed = 0;
+    int chunk = kMinChunk;
+    double hr = 0, hz = 0;
+    int L = 0;
+    int nn = 0;
+    double quantum[2] = {1.0, 1.0};
+    std::vector<void *> allocs;
+
+    // grids
+    double *phi, *rho, *chi, *er, *ez, *dens[2], *vol, *f, *eps;
+    void *E2;
+    unsigned long long *acc[2];
+    unsigned long long *slices = nullptr;
+    int slice_blocks = 0;
+    bool lds_ok = false;
+    double *inv2j1;
+    float *inv2j1f;
+    MgLevels mg{};
+    // device scalars
+    Counts *cnt;
+    FixRec *fix;
+    ChildRec *crec;
+    CloneRec *clrec;
+    unsigned long long *tally;   // [2][3]
+    unsigned long long *mcstat;  // [2][1 + kMaxProc]
+    unsigned long long *norm;    // [2]
+    int32_t *status;
+    // host-side bookkeeping
+    SpeciesState sp[2];
+    bool children_pending[2] = {false, false};  // staged children not yet appended
+    bool children_scanned = false;
+    int last_cycles = 0;
+    double last_relres = 0.0;
+    // timing
+    bool timing = false;
+    hipEvent_t ev[5] = {};
+    double t_ms[5] = {};
+};
+
+namespace {
+
+template <typename T> rzpic_status dalloc(rzpic_ctx *c, T **p, size_t count)
+{
+    void *q = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(RZPIC_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    e = hipMemset(q, 0, bytes);
+    if (e != hipSuccess) return fail(RZPIC_EHIP, "hipMemset failed: %s", hipGetErrorString(e));
+    c->allocs.push_back(q);
+    *p = (T *)q;
+    return RZPIC_OK;
+}
+
+#define TRY(expr)                            \
+    do {                                     \
+        rzpic_status s_ = (expr);            \
+        if (s_ != RZPIC_OK) return s_;       \
+    } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+Mesh mesh_of(const rzpic_ctx *c)
+{
+    Mesh m;
+    m.nr = c->c.nr;
+    m.nz = c->c.nz;
+    m.nn = c->nn;
+    m.weighting = c->c.weighting;
+    m.R = c->c.R;
+    m.L = c->c.L;
+    m.hr = c->hr;
+    m.hz = c->hz;
+    m.inv_hr = 1.0 / c->hr;
+    m.inv_hz = 1.0 / c->hz;
+    m.inv2j1 = c->inv2j1;
+    m.inv2j1f = c->inv2j1f;
+    return m;
+}
+
+Phys phys_of(const rzpic_ctx *c)
+{
+    Phys p;
+    p.dt = c->c.dt;
+    p.n_gas = c->c.n_gas;
+    p.T_gas = c->c.T_gas;
+    p.m_gas = c->c.m_gas;
+    p.vth_gas = c->c.m_gas > 0 ? std::sqrt(kKb * c->c.T_gas / c->c.m_gas) : 0.0;
+    p.R = c->c.R;
+    p.L = c->c.L;
+    p.seed = c->c.seed;
+    const rzpic_species_view &e = c->sp[0].v, &i = c->sp[1].v;
+    p.ion_acc_ratio = (c->sp[0].bound && c->sp[1].bound) ? (i.q * e.m) / (e.q * i.m) : 0.0;
+    p.ion_inv_quantum = 1.0 / c->quantum[1];
+    return p;
+}
+
+double pair_mass(const rzpic_ctx *c, int s)
+{
+    const rzpic_species_view &v = c->sp[s].v;
+    if (v.mc_model == RZPIC_MC_ION) return v.m * c->c.m_gas / (v.m + c->c.m_gas);
+    return v.m;
+}
+
+SpeciesK species_of(const rzpic_ctx *c, int s)
+{
+    SpeciesK k{};
+    const SpeciesState &ss = c->sp[s];
+    const rzpic_species_view &v = ss.v;
+    k.s = s;
+    k.mc_model = ss.has_xsec ? v.mc_model : RZPIC_MC_NONE;
+    k.q = v.q;
+    k.m = v.m;
+    k.qm = v.q / v.m;
+    k.k1 = 0.5 * k.qm * c->c.dt * c->c.dt;
+    k.k2 = 0.5 * k.qm * c->c.dt;
+    k.inv_quantum = 1.0 / c->quantum[s];
+    k.p_null = ss.p_null;
+    k.nu_max = ss.nu_max;
+    k.mu = ss.bound ? pair_mass(c, s) : 1.0;
+    k.ekin = 0.5 * k.mu / kE;
+    k.xs = ss.xs;
+    return k;
+}
+
+template <typename T> Parts<T> parts_of(const rzpic_species_view &v)
+{
+    Parts<T> p;
+    p.r = (T *)v.r;
+    p.z = (T *)v.z;
+    p.vr = (T *)v.vr;
+    p.vt = (T *)v.vt;
+    p.vz = (T *)v.vz;
+    p.ar = (T *)v.ar;
+    p.az = (T *)v.az;
+    p.w = (T *)v.w;
+    p.id = v.id;
+    return p;
+}
+
+template <typename T> Parts<T> stage_of(const rzpic_ctx *c, int cs)
+{
+    Parts<T> p{};
+    void *const *a = c->sp[0].stage[cs];
+    p.r = (T *)a[0];
+    p.z = (T *)a[1];
+    p.vr = (T *)a[2];
+    p.vt = (T *)a[3];
+    p.vz = (T *)a[4];
+    p.ar = (T *)a[5];
+    p.az = (T *)a[6];
+    p.w = (T *)a[7];
+    p.id = nullptr;
+    return p;
+}
+
+template <typename T> PassArgs<T> pass_args(rzpic_ctx *c, int s, uint32_t step)
+{
+    PassArgs<T> a{};
+    a.p = parts_of<T>(c->sp[s].v);
+    if (s == 0 && c->sp[0].stage[0][0]) {
+        a.ce = stage_of<T>(c, 0);
+        a.ci = stage_of<T>(c, 1);
+    }
+    a.cnt = c->cnt + s;
+    a.ch = c->sp[s].ch;
+    a.mesh = mesh_of(c);
+    a.phys = phys_of(c);
+    a.sp = species_of(c, s);
+    a.E2 = (const typename Vec2<T>::type *)c->E2;
+    a.acc = c->acc[s];
+    a.acc_ion = c->acc[1];
+    a.slices = c->slices;
+    a.tally = c->tally + 3 * s;
+    a.tally_ion = c->tally + 3;
+    a.mcstat = c->mcstat + (1 + kMaxProc) * s;
+    a.ev = c->sp[s].v.mc_event;
+    a.crec = s == 0 ? c->crec : nullptr;
+    a.status = c->status;
+    a.step = step;
+    a.chunk = c->chunk;
+    return a;
+}
+
+rzpic_status need_species(rzpic_ctx *c, int s)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (s < 0 || s > 1) return fail(RZPIC_EINVAL, "species %d out of range (0 or 1)", s);
+    if (!c->sp[s].bound) return fail(RZPIC_ESTATE, "species %d is not bound", s);
+    return RZPIC_OK;
+}
+
+rzpic_status need_both(rzpic_ctx *c)
+{
+    TRY(need_species(c, 0));
+    TRY(need_species(c, 1));
+    return RZPIC_OK;
+}
+
+__global__ void k_set_count(Counts *cnt, int64_t n, uint64_t next_id)
+{
+    cnt->n = n;
+    cnt->next_id = next_id;
+}
+
+__global__ void k_prep_solve(int nn, const double *rho, const double *chi, double *eps,
+                             float *eps32, double *f)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += gridDim.x * blockDim.x) {
+        double e = 1.0 + chi[g];
+        eps[g] = e;
+        if (eps32) eps32[g] = (float)e;
+        f[g] = rho[g] / kEps0;
+    }
+}
+
+// Particle pass of species s in `mode` (LDS variant chosen here).
+template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step)
+{
+    PassArgs<T> a = pass_args<T>(c, s, step);
+    int blocks, threads = c->chunk;
+    size_t lds = 0;
+    int64_t cap_chunks = (c->sp[s].cap + threads - 1) / threads;
+    if ((mode & M_DEP) && c->lds_ok) {
+        mode |= M_LDS;
+        lds = (size_t)c->nn * sizeof(unsigned long long);
+        blocks = c->slice_blocks;
+    } else {
+        blocks = c->cus * 8;
+    }
+    if (cap_chunks < blocks && !(mode & M_LDS)) blocks = (int)(cap_chunks > 0 ? cap_chunks : 1);
+    if (mode & M_MC) HIPCHK(launch_fill_u64(a.mcstat, 1 + kMaxProc, c->st));
+    HIPCHK(launch_pass<T>(mode, a, blocks, threads, lds, c->st));
+    if (mode & M_LDS) HIPCHK(launch_reduce_slices(c->acc[s], c->slices, blocks, c->nn, c->st));
+    return RZPIC_OK;
+}
+
+template <typename T> rzpic_status run_staged(rzpic_ctx *c, int cs, int mode)
+{
+    // children of species cs staged by the electron pass
+    PassArgs<T> a = pass_args<T>(c, cs, 0);
+    a.p = stage_of<T>(c, cs);
+    a.ch = c->sp[0].ch;
+    a.crec = c->crec;
+    a.acc = c->acc[cs];
+    a.tally = c->tally + 3 * cs;
+    a.sp = species_of(c, cs);
+    int32_t *surv = cs == 0 ? c->sp[0].ch.surv_e : c->sp[0].ch.surv_i;
+    HIPCHK(launch_staged<T>(mode, a, surv, c->st));
+    return RZPIC_OK;
+}
+
+// Scan + dead list + fill + append for the species in `which` (bit s).
+template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
+{
+    ScanJobs j{};
+    j.chunk = c->chunk;
+    j.children = (c->children_pending[0] || c->children_pending[1]) && !c->children_scanned;
+    j.ech = c->sp[0].ch;
+    j.ecnt = c->cnt;
+    j.icnt = c->cnt + 1;
+    j.crec = c->crec;
+    for (int s = 0; s < 2; ++s) {
+        j.dead[s] = (which >> s) & 1;
+        j.ch[s] = c->sp[s].ch;
+        j.cnt[s] = c->cnt + s;
+        j.fix[s] = c->fix + s;
+    }
+    HIPCHK(launch_scan(j, c->st));
+    if (j.children) c->children_scanned = true;
+    for (int s = 0; s < 2; ++s)
+        if ((which >> s) & 1) HIPCHK(launch_dead_list(c->sp[s].ch, c->cnt + s, c->fix + s, c->chunk, c->st));
+    for (int s = 0; s < 2; ++s)
+        if ((which >> s) & 1) HIPCHK(launch_fill<T>(parts_of<T>(c->sp[s].v), c->sp[s].ch, c->fix + s, c->st));
+    for (int s = 0; s < 2; ++s) {
+        if (!((which >> s) & 1)) continue;
+        int kids = c->children_pending[s] ? 1 : 0;
+        HIPCHK(launch_append<T>(parts_of<T>(c->sp[s].v), stage_of<T>(c, s), s, c->sp[0].ch, kids,
+                                c->crec, c->fix + s, c->cnt + s, c->sp[s].cap, c->chunk,
+                                c->status, c->st));
+        c->children_pending[s] = false;
+    }
+    if (!c->children_pending[0] && !c->children_pending[1]) c->children_scanned = false;
+    return RZPIC_OK;
+}
+
+rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, double *relres)
+{
+    const int nr = c->c.nr, nz = c->c.nz;
+    if (!prepared) {
+        int threads = 256, blocks = (c->nn + threads - 1) / threads;
+        hipLaunchKernelGGL(k_prep_solve, dim3(blocks), dim3(threads), 0, c->st, c->nn,
+                           (const double *)c->rho, (const double *)c->chi, c->eps,
+                           c->mixed ? c->mg.eps32[c->L] : nullptr, c->f);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(mg_restrict_eps(c->mg, c->mixed, c->st));
+    const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
+    HIPCHK(mg_set_bc(c->phi, nr, nz, V, c->st));
+    int k = 0;
+    rzpic_status st = RZPIC_OK;
+    const bool want = cycles || relres;
+    double scale = 0.0;
+    if (c->c.mg_fixed_cycles > 0) {
+        for (; k < c->c.mg_fixed_cycles; ++k)
+            HIPCHK(mg_vcycle(c->mg, c->mixed, c->phi, c->f, nullptr, c->st));
+    } else {
+        unsigned long long h = 0;
+        HIPCHK(launch_fill_u64(c->norm, 2, c->st));
+        HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 1, c->norm + 1, c->st));
+        for (;;) {
+            HIPCHK(launch_fill_u64(c->norm, 1, c->st));
+            HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 0, c->norm, c->st));
+            unsigned long long hv[2];
+            HIPCHK(hipMemcpyAsync(hv, c->norm, sizeof hv, hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            double rn, sc;
+            std::memcpy(&rn, &hv[0], 8);
+            std::memcpy(&sc, &hv[1], 8);
+            scale = sc;
+            if (rn <= c->c.mg_tol * sc) break;
+            if (k >= c->c.mg_max_cycles) {
+                st = fail(RZPIC_ENOTCONV, "multigrid: relative residual %.3e after %d cycles",
+                          sc > 0 ? rn / sc : rn, k);
+                break;
+            }
+            HIPCHK(mg_vcycle(c->mg, c->mixed, c->phi, c->f, nullptr, c->st));
+            ++k;
+        }
+        (void)h;
+    }
+    c->last_cycles = k;
+    if (want || c->c.mg_fixed_cycles <= 0) {
+        unsigned long long hv[2];
+        HIPCHK(launch_fill_u64(c->norm, 2, c->st));
+        HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 1, c->norm + 1, c->st));
+        HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 0, c->norm, c->st));
+        HIPCHK(hipMemcpyAsync(hv, c->norm, sizeof hv, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        double rn, sc;
+        std::memcpy(&rn, &hv[0], 8);
+        std::memcpy(&sc, &hv[1], 8);
+        c->last_relres = sc > 0 ? rn / sc : rn;
+        (void)scale;
+    }
+    if (cycles) *cycles = k;
+    if (relres) *relres = c->last_relres;
+    return st;
+}
+
+rzpic_status efield_impl(rzpic_ctx *c)
+{
+    if (c->mixed)
+        HIPCHK(launch_efield<float>(c->c.nr, c->c.nz, c->hr, c->hz, c->phi, c->er, c->ez,
+                                    (float2 *)c->E2, c->st));
+    else
+        HIPCHK(launch_efield<double>(c->c.nr, c->c.nz, c->hr, c->hz, c->phi, c->er, c->ez,
+                                     (double2 *)c->E2, c->st));
+    return RZPIC_OK;
+}
+
+rzpic_status finalize_impl(rzpic_ctx *c, int zero_acc)
+{
+    GridArgs g{};
+    g.nr = c->c.nr;
+    g.nz = c->c.nz;
+    g.nn = c->nn;
+    g.hr = c->hr;
+    g.hz = c->hz;
+    g.dt = c->c.dt;
+    g.acc0 = c->acc[0];
+    g.acc1 = c->acc[1];
+    g.quantum0 = c->quantum[0];
+    g.quantum1 = c->quantum[1];
+    g.q0 = c->sp[0].v.q;
+    g.q1 = c->sp[1].v.q;
+    g.m0 = c->sp[0].bound ? c->sp[0].v.m : 1.0;
+    g.m1 = c->sp[1].bound ? c->sp[1].v.m : 1.0;
+    g.vol = c->vol;
+    g.dens0 = c->dens[0];
+    g.dens1 = c->dens[1];
+    g.rho = c->rho;
+    g.chi = c->chi;
+    g.eps = c->eps;
+    g.f = c->f;
+    g.eps32 = c->mixed ? c->mg.eps32[c->L] : nullptr;
+    g.zero_acc = zero_acc;
+    g.acc0w = c->acc[0];
+    g.acc1w = c->acc[1];
+    g.status = c->status;
+    HIPCHK(launch_finalize(g, c->st));
+    return RZPIC_OK;
+}
+
+template <typename T> rzpic_status deposit_impl(rzpic_ctx *c)
+{
+    for (int s = 0; s < 2; ++s) HIPCHK(launch_fill_u64(c->acc[s], c->nn, c->st));
+    for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, M_DEP | M_MARK, 0));
+    for (int s = 0; s < 2; ++s)
+        if (c->children_pending[s]) TRY(run_staged<T>(c, s, M_DEP));
+    return RZPIC_OK;
+}
+
+template <typename T> rzpic_status resize_impl(rzpic_ctx *c, int s)
+{
+    HIPCHK(launch_resize<T>(parts_of<T>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->clrec + s,
+                            c->chunk, c->c.resize_wcoef, 0.5 * c->hr, c->sp[s].cap, c->status,
+                            c->st));
+    return RZPIC_OK;
+}
+
+void tic(rzpic_ctx *c, int k)
+{
+    if (c->timing) (void)hipEventRecord(c->ev[k], c->st);
+}
+
+template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
+{
+    TRY(need_both(c));
+    if (c->children_pending[0] || c->children_pending[1])
+        return fail(RZPIC_ESTATE, "new particles are staged: call rzpic_compact first");
+    tic(c, 0);
+    TRY(finalize_impl(c, 1));
+    TRY(solve_impl(c, (double)(n + 1) * c->c.dt, true, nullptr, nullptr));
+    TRY(efield_impl(c));
+    tic(c, 1);
+    const int fused = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS;
+    for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, fused, (uint32_t)n));
+    c->children_pending[0] = c->children_pending[1] = c->sp[0].v.mc_model == RZPIC_MC_ELECTRON;
+    c->children_scanned = false;
+    tic(c, 2);
+    TRY(run_fixup<T>(c, 3));
+    if (c->c.resize_every > 0 && n % c->c.resize_every == c->c.resize_every - 1) {
+        for (int s = 0; s < 2; ++s) TRY(resize_impl<T>(c, s));
+        for (int s = 0; s < 2; ++s) HIPCHK(launch_fill_u64(c->acc[s], c->nn, c->st));
+        for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, M_DEP, 0));
+    }
+    tic(c, 3);
+    if (c->timing) {
+        HIPCHK(hipEventSynchronize(c->ev[3]));
+        float a, b, d, e;
+        (void)hipEventElapsedTime(&a, c->ev[0], c->ev[3]);
+        (void)hipEventElapsedTime(&b, c->ev[0], c->ev[1]);
+        (void)hipEventElapsedTime(&d, c->ev[1], c->ev[2]);
+        (void)hipEventElapsedTime(&e, c->ev[2], c->ev[3]);
+        c->t_ms[0] = a;
+        c->t_ms[1] = b;
+        c->t_ms[2] = d;
+        c->t_ms[3] = e;
+        c->t_ms[4] = c->last_cycles;
+    }
+    return RZPIC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+const char *rzpic_last_error(void) { return g_err.c_str(); }
+
+void rzpic_constants(double out[6])
+{
+    out[0] = kE;
+    out[1] = kMe;
+    out[2] = kAmu;
+    out[3] = kEps0;
+    out[4] = kKb;
+    out[5] = kTwoPi;
+}
+
+rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out)
+{
+    if (!cfg || !out) return fail(RZPIC_EINVAL, "null argument");
+    *out = nullptr;
+    const rzpic_config &k = *cfg;
+    if (k.nr < 3 || k.nr - 1 > kMaxLine)
+        return fail(RZPIC_EINVAL, "nr = %d: need 3 <= nr <= %d", k.nr, kMaxLine + 1);
+    if (k.nz < 3 || !is_pow2(k.nz - 1))
+        return fail(RZPIC_EINVAL, "nz = %d: nz-1 must be a power of two >= 2", k.nz);
+    if (!(k.R > 0) || !(k.L > 0) || !(k.dt > 0))
+        return fail(RZPIC_EINVAL, "R, L and dt must be positive");
+    if (k.precision != RZPIC_FP64 && k.precision != RZPIC_MIXED)
+        return fail(RZPIC_EINVAL, "precision must be RZPIC_FP64 or RZPIC_MIXED");
+    if (k.weighting != RZPIC_W_ZR2 && k.weighting != RZPIC_W_ZR)
+        return fail(RZPIC_EINVAL, "unknown weighting %d", k.weighting);
+    if (k.chi_face != RZPIC_FACE_AVG && k.chi_face != RZPIC_FACE_MAX)
+        return fail(RZPIC_EINVAL, "unknown chi_face %d", k.chi_face);
+    if (k.mg_fixed_cycles < 0 || (k.mg_fixed_cycles == 0 && (k.mg_max_cycles < 1 || !(k.mg_tol > 0))))
+        return fail(RZPIC_EINVAL, "need mg_fixed_cycles > 0, or mg_max_cycles >= 1 and mg_tol > 0");
+    if (k.fixed_point_bits < 0 || k.fixed_point_bits > 52)
+        return fail(RZPIC_EINVAL, "fixed_point_bits = %d out of [0, 52]", k.fixed_point_bits);
+    if (k.resize_every < 0 || (k.resize_every > 0 && !(k.resize_wcoef > 0)))
+        return fail(RZPIC_EINVAL, "resize_every > 0 needs resize_wcoef > 0");
+
+    rzpic_ctx *c = new rzpic_ctx();
+    c->c = k;
+    if (c->c.fixed_point_bits == 0) c->c.fixed_point_bits = 40;
+    c->st = (hipStream_t)stream;
+    c->mixed = k.precision == RZPIC_MIXED;
+    c->hr = k.R / (double)(k.nr - 1);
+    c->hz = k.L / (double)(k.nz - 1);
+    c->nn = k.nr * k.nz;
+    int L = 0;
+    while ((1 << L) < k.nz - 1) ++L;
+    c->L = L;
+    auto bail = [&](rzpic_status s) {
+        std::string keep = g_err;
+        rzpic_destroy(c);
+        g_err = keep;
+        return s;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(RZPIC_EHIP, "no HIP device"));
+    int v = 0;
+    (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c->device);
+    c->cus = v > 0 ? v : 1;
+    (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    c->lds_block = (size_t)v;
+    (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device);
+    c->lds_cu = v > 0 ? (size_t)v : c->lds_block;
+    if (const char *e = std::getenv("RZPIC_CHUNK")) {
+        int ch = std::atoi(e);
+        if (ch == 256 || ch == 512 || ch == 1024) c->chunk = ch;
+    }
+    const size_t nn = (size_t)c->nn;
+    rzpic_status s;
+#define A(p, n)                                  \
+    if ((s = dalloc(c, &(p), (n))) != RZPIC_OK) \
+        return bail(s);
+    A(c->phi, nn) A(c->rho, nn) A(c->chi, nn) A(c->er, nn) A(c->ez, nn) A(c->dens[0], nn)
+    A(c->dens[1], nn) A(c->vol, nn) A(c->f, nn) A(c->eps, nn)
+    {
+        double2 *e2;
+        A(e2, nn) c->E2 = e2;
+    }
+    A(c->acc[0], nn) A(c->acc[1], nn) A(c->inv2j1, (size_t)k.nr) A(c->inv2j1f, (size_t)k.nr)
+    A(c->cnt, 2) A(c->fix, 2) A(c->crec, 1) A(c->clrec, 2) A(c->tally, 6)
+    A(c->mcstat, 2 * (1 + kMaxProc)) A(c->norm, 2) A(c->status, 1)
+    // LDS privatisation of the whole deposit grid when it fits.
+    const size_t lds_need = nn * sizeof(unsigned long long) + 1024;
+    if (lds_need <= c->lds_block && !std::getenv("RZPIC_NO_LDS")) {
+        int per_cu = (int)(c->lds_cu / lds_need);
+        if (per_cu < 1) per_cu = 1;
+        if (per_cu > 4) per_cu = 4;
+        c->slice_blocks = c->cus * per_cu;
+        if (const char *e = std::getenv("RZPIC_SLICE_BLOCKS")) {
+            int b = std::atoi(e);
+            if (b > 0 && b <= 65536) c->slice_blocks = b;
+        }
+        A(c->slices, (size_t)c->slice_blocks * nn)
+        c->lds_ok = true;
+    }
+    // multigrid levels
+    MgLevels &m = c->mg;
+    m.L = L;
+    m.nr = k.nr;
+    m.chi_face = k.chi_face;
+    m.hr = c->hr;
+    A(m.res, nn)
+    for (int l = 1; l <= L; ++l) {
+        m.nzl[l] = (1 << l) + 1;
+        m.hzl[l] = c->hz * (double)(1 << (L - l));
+        size_t sz = (size_t)m.nzl[l] * k.nr;
+        if (l == L) {
+            m.eps64[l] = c->eps;
+        } else {
+            A(m.eps64[l], sz)
+        }
+        if (c->mixed) {
+            A(m.eps32[l], sz) A(m.u32[l], sz) A(m.f32[l], sz)
+        } else if (l < L) {
+            A(m.u64[l], sz) A(m.f64[l], sz)
+        }
+    }
+    if (!c->mixed) {
+        m.u64[L] = c->phi;
+        m.f64[L] = c->f;
+    }
+#undef A
+    // host tables: 1/(2j+1), weighting volumes (Sec. 2.4, radial neighbours
+    // clamped to the axis and the wall, half axial cells on the electrodes)
+    std::vector<double> inv(k.nr), vol(nn);
+    std::vector<float> invf(k.nr);
+    for (int j = 0; j < k.nr; ++j) {
+        inv[j] = 1.0 / (double)(2 * j + 1);
+        invf[j] = (float)inv[j];
+    }
+    const double PI = 3.141592653589793;
+    for (int i = 0; i < k.nz; ++i) {
+        double zf = (i == 0 || i == k.nz - 1) ? 0.5 * c->hz : c->hz;
+        for (int j = 0; j < k.nr; ++j) {
+            int jp = j + 1 < k.nr ? j + 1 : k.nr - 1, jm = j > 0 ? j - 1 : 0;
+            double rj = j * c->hr, rp = jp * c->hr, rm = jm * c->hr, rf;
+            if (k.weighting == RZPIC_W_ZR) rf = (PI / 3.0) * (rp * (rj + rp) - rm * (rj + rm));
+            else rf = 0.5 * PI * (rp * rp - rm * rm);
+            vol[(size_t)i * k.nr + j] = rf * zf;
+        }
+    }
+    if (hipMemcpy(c->inv2j1, inv.data(), k.nr * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->inv2j1f, invf.data(), k.nr * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->vol, vol.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(RZPIC_EHIP, "table upload failed"));
+    for (int e = 0; e < 5; ++e) (void)hipEventCreate(&c->ev[e]);
+    *out = c;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_destroy(rzpic_ctx *c)
+{
+    if (!c) return RZPIC_OK;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    else (void)hipDeviceSynchronize();
+    for (void *p : c->allocs) (void)hipFree(p);
+    for (int s = 0; s < 2; ++s) {
+        for (int a = 0; a < 2; ++a)
+            for (int f = 0; f < 8; ++f)
+                if (c->sp[s].stage[a][f]) (void)hipFree(c->sp[s].stage[a][f]);
+        if (c->sp[s].sigma.p) (void)hipFree(c->sp[s].sigma.p);
+    }
+    for (int e = 0; e < 5; ++e)
+        if (c->ev[e]) (void)hipEventDestroy(c->ev[e]);
+    delete c;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_set_stream(rzpic_ctx *c, void *stream)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    c->st = (hipStream_t)stream;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_view *v)
+{
+    if (!c || !v) return fail(RZPIC_EINVAL, "null argument");
+    if (s < 0 || s > 1) return fail(RZPIC_EINVAL, "species %d out of range", s);
+    if (!v->r || !v->z || !v->vr || !v->vt || !v->vz || !v->ar || !v->az || !v->w || !v->id)
+        return fail(RZPIC_EINVAL, "species %d: null particle array", s);
+    if (v->capacity < 1 || v->capacity > ((int64_t)1 << 31) - kMaxChunk)
+        return fail(RZPIC_EINVAL, "species %d: capacity %lld out of range", s, (long long)v->capacity);
+    if (!(v->m > 0) || !(v->w_ref > 0))
+        return fail(RZPIC_EINVAL, "species %d: need m > 0 and w_ref > 0", s);
+    if (v->mc_model < RZPIC_MC_NONE || v->mc_model > RZPIC_MC_ION)
+        return fail(RZPIC_EINVAL, "species %d: unknown mc_model", s);
+    if (v->mc_model == RZPIC_MC_ELECTRON && s != 0)
+        return fail(RZPIC_EINVAL, "the electron collision model is species 0");
+    HIPCHK(c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize());
+    SpeciesState &ss = c->sp[s];
+    for (int a = 0; a < 2; ++a)
+        for (int f = 0; f < 8; ++f)
+            if (ss.stage[a][f]) {
+                (void)hipFree(ss.stage[a][f]);
+                ss.stage[a][f] = nullptr;
+            }
+    ss.v = *v;
+    ss.cap = v->capacity;
+    ss.bound = true;
+    c->quantum[s] = v->w_ref * std::ldexp(1.0, -c->c.fixed_point_bits);
+    const int64_t nch = (v->capacity + kMinChunk - 1) / kMinChunk + 1;
+    ss.nchunks_max = nch;
+    const size_t cap = (size_t)v->capacity + kMaxChunk;  // slots of the last chunk
+    rzpic_status st;
+#define A(p, n)                                   \
+    if ((st = dalloc(c, &(p), (n))) != RZPIC_OK) \
+        return st;
+    A(ss.ch.dead_cnt, nch) A(ss.ch.ev_cnt, nch) A(ss.ch.surv_e, nch) A(ss.ch.surv_i, nch)
+    A(ss.ch.clone_cnt, nch) A(ss.ch.dead_list, cap) A(ss.ch.dead_off, nch) A(ss.ch.ev_off, nch)
+    A(ss.ch.surv_e_off, nch) A(ss.ch.surv_i_off, nch) A(ss.ch.clone_off, nch)
+    A(ss.ch.dead_glob, cap) A(ss.ch.pcount, cap)
+#undef A
+    if (s == 0 && v->mc_model == RZPIC_MC_ELECTRON) {
+        size_t es = c->mixed ? sizeof(float) : sizeof(double);
+        for (int a = 0; a < 2; ++a)
+            for (int f = 0; f < 8; ++f) HIPCHK(hipMalloc(&ss.stage[a][f], cap * es));
+    }
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, (int64_t)0, (uint64_t)0);
+    HIPCHK(hipGetLastError());
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_set_count(rzpic_ctx *c, int32_t s, int64_t n, uint64_t next_id)
+{
+    TRY(need_species(c, s));
+    if (n < 0 || n > c->sp[s].cap)
+        return fail(RZPIC_EINVAL, "count %lld outside [0, capacity %lld]", (long long)n,
+                    (long long)c->sp[s].cap);
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, n, next_id);
+    HIPCHK(hipGetLastError());
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_get_count(rzpic_ctx *c, int32_t s, int64_t *n, uint64_t *next_id)
+{
+    TRY(need_species(c, s));
+    Counts h;
+    HIPCHK(hipMemcpyAsync(&h, c->cnt + s, sizeof h, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (n) *n = h.n;
+    if (next_id) *next_id = h.next_id;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_set_xsec(rzpic_ctx *c, int32_t s, int32_t nproc, const int32_t *kind,
+                            const double *thr_eV, double de, int32_t ne, const double *sigma,
+                            double ej_B)
+{
+    TRY(need_species(c, s));
+    if (nproc < 1 || nproc > kMaxProc || ne < 2 || !(de > 0) || !kind || !thr_eV || !sigma)
+        return fail(RZPIC_EINVAL, "cross sections: need 1 <= nproc <= %d, ne >= 2, de > 0", kMaxProc);
+    for (int k = 0; k < nproc; ++k)
+        if (kind[k] < RZPIC_P_ELASTIC || kind[k] > RZPIC_P_IONIZATION)
+            return fail(RZPIC_EINVAL, "cross sections: unknown process kind %d", kind[k]);
+    for (int k = 0; k < nproc; ++k)
+        if (kind[k] == RZPIC_P_IONIZATION && (s != 0 || !c->sp[1].bound))
+            return fail(RZPIC_EINVAL, "ionization needs electrons as species 0 and ions bound as species 1");
+    SpeciesState &ss = c->sp[s];
+    HIPCHK(c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize());
+    if (ss.sigma.p) {
+        (void)hipFree(ss.sigma.p);
+        ss.sigma.p = nullptr;
+    }
+    size_t bytes = (size_t)nproc * ne * sizeof(double);
+    HIPCHK(hipMalloc(&ss.sigma.p, bytes));
+    HIPCHK(hipMemcpy(ss.sigma.p, sigma, bytes, hipMemcpyHostToDevice));
+    Xsec &x = ss.xs;
+    x.sigma = (const double *)ss.sigma.p;
+    x.nproc = nproc;
+    x.ne = ne;
+    x.de = de;
+    x.emax = (double)(ne - 1) * de;
+    x.ejB = ej_B;
+    for (int k = 0; k < nproc; ++k) {
+        x.kind[k] = kind[k];
+        x.thr[k] = thr_eV[k];
+    }
+    // nu_max: on [eps_j, eps_j+1] the interpolated sigma_T is at most its
+    // larger end value and the pair speed at most g(eps_j+1); above the table
+    // sigma_T g decreases, so these interval bounds bound every energy.
+    const double mu = pair_mass(c, s);
+    double numax = 0.0;
+    for (int j = 0; j + 1 < ne; ++j) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int k = 0; k < nproc; ++k) {
+            s0 += sigma[(size_t)k * ne + j];
+            s1 += sigma[(size_t)k * ne + j + 1];
+        }
+        double smax = s0 > s1 ? s0 : s1;
+        double e1 = (double)(j + 1) * de;
+        double g = std::sqrt(2.0 * e1 * kE / mu);
+        double nu = c->c.n_gas * smax * g;
+        if (nu > numax) numax = nu;
+    }
+    ss.nu_max = numax;
+    ss.p_null = -std::expm1(-numax * c->c.dt);
+    ss.has_xsec = true;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_get_mc_consts(rzpic_ctx *c, int32_t s, double *nu_max, double *p_null)
+{
+    TRY(need_species(c, s));
+    if (nu_max) *nu_max = c->sp[s].nu_max;
+    if (p_null) *p_null = c->sp[s].p_null;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_init_particles(rzpic_ctx *c, int32_t s, int64_t n, double n0, double T_eV,
+                                  uint64_t id0)
+{
+    TRY(need_species(c, s));
+    if (n < 0 || n > c->sp[s].cap) return fail(RZPIC_EINVAL, "n = %lld exceeds capacity", (long long)n);
+    if (!(T_eV >= 0) || !(n0 >= 0)) return fail(RZPIC_EINVAL, "need n0 >= 0 and T_eV >= 0");
+    Phys ph = phys_of(c);
+    if (c->mixed)
+        HIPCHK(launch_init<float>(parts_of<float>(c->sp[s].v), n, n0, T_eV, id0, s, ph, c->sp[s].v.m, c->st));
+    else
+        HIPCHK(launch_init<double>(parts_of<double>(c->sp[s].v), n, n0, T_eV, id0, s, ph, c->sp[s].v.m, c->st));
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, n, id0 + (uint64_t)n);
+    HIPCHK(hipGetLastError());
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_push_first(rzpic_ctx *c, int32_t s)
+{
+    TRY(need_species(c, s));
+    if (c->mixed) {
+        TRY(run_pass<float>(c, s, M_FIRST | M_MARK, 0));
+        if (c->children_pending[s]) TRY(run_staged<float>(c, s, M_FIRST));
+    } else {
+        TRY(run_pass<double>(c, s, M_FIRST | M_MARK, 0));
+        if (c->children_pending[s]) TRY(run_staged<double>(c, s, M_FIRST));
+    }
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_push_final(rzpic_ctx *c, int32_t s)
+{
+    TRY(need_species(c, s));
+    if (c->mixed) TRY(run_pass<float>(c, s, M_FINAL | M_MARK, 0));
+    else TRY(run_pass<double>(c, s, M_FINAL | M_MARK, 0));
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_collide(rzpic_ctx *c, int32_t s, int64_t step)
+{
+    TRY(need_species(c, s));
+    if (!c->sp[s].has_xsec) return RZPIC_OK;
+    if (s == 0 && (c->children_pending[0] || c->children_pending[1]))
+        return fail(RZPIC_ESTATE, "new particles already staged: call rzpic_compact first");
+    if (c->mixed) TRY(run_pass<float>(c, s, M_MC | M_MARK, (uint32_t)step));
+    else TRY(run_pass<double>(c, s, M_MC | M_MARK, (uint32_t)step));
+    if (s == 0 && c->sp[0].v.mc_model == RZPIC_MC_ELECTRON) {
+        c->children_pending[0] = c->children_pending[1] = true;
+        c->children_scanned = false;
+    }
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_deposit(rzpic_ctx *c)
+{
+    TRY(need_both(c));
+    if (c->mixed) TRY(deposit_impl<float>(c));
+    else TRY(deposit_impl<double>(c));
+    TRY(finalize_impl(c, 0));
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_solve(rzpic_ctx *c, double t, int32_t *cycles, double *relres)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    return solve_impl(c, t, false, cycles, relres);
+}
+
+rzpic_status rzpic_efield(rzpic_ctx *c)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    return efield_impl(c);
+}
+
+rzpic_status rzpic_compact(rzpic_ctx *c, int32_t s)
+{
+    TRY(need_species(c, s));
+    if (s == 1 && c->children_pending[1] && !c->sp[0].bound)
+        return fail(RZPIC_ESTATE, "species 0 must stay bound while new ions are staged");
+    if (c->mixed) {
+        HIPCHK(launch_dead_scan<float>(parts_of<float>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->chunk, c->st));
+        TRY(run_fixup<float>(c, 1 << s));
+    } else {
+        HIPCHK(launch_dead_scan<double>(parts_of<double>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->chunk, c->st));
+        TRY(run_fixup<double>(c, 1 << s));
+    }
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_resize(rzpic_ctx *c, int32_t s)
+{
+    TRY(need_species(c, s));
+    if (!(c->c.resize_wcoef > 0)) return fail(RZPIC_EINVAL, "resize_wcoef must be positive");
+    if (c->children_pending[s]) return fail(RZPIC_ESTATE, "call rzpic_compact before rzpic_resize");
+    if (c->mixed) TRY(resize_impl<float>(c, s));
+    else TRY(resize_impl<double>(c, s));
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_prologue(rzpic_ctx *c)
+{
+    TRY(need_both(c));
+    if (c->children_pending[0] || c->children_pending[1])
+        return fail(RZPIC_ESTATE, "new particles are staged: call rzpic_compact first");
+    for (int s = 0; s < 2; ++s) HIPCHK(launch_fill_u64(c->acc[s], c->nn, c->st));
+    const int mode = M_FIRST | M_DEP | M_LISTS;
+    if (c->mixed) {
+        for (int s = 0; s < 2; ++s) TRY(run_pass<float>(c, s, mode, 0));
+        TRY(run_fixup<float>(c, 3));
+    } else {
+        for (int s = 0; s < 2; ++s) TRY(run_pass<double>(c, s, mode, 0));
+        TRY(run_fixup<double>(c, 3));
+    }
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_step(rzpic_ctx *c, int64_t step)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (step < 0 || step > 0xFFFFFFFELL) return fail(RZPIC_EINVAL, "step out of range");
+    return c->mixed ? step_impl<float>(c, step) : step_impl<double>(c, step);
+}
+
+rzpic_status rzpic_grid_copy(rzpic_ctx *c, int32_t which, double *dev, int32_t to_ctx)
+{
+    if (!c || !dev) return fail(RZPIC_EINVAL, "null argument");
+    double *src = nullptr;
+    switch (which) {
+    case RZPIC_G_PHI: src = c->phi; break;
+    case RZPIC_G_RHO: src = c->rho; break;
+    case RZPIC_G_CHI: src = c->chi; break;
+    case RZPIC_G_ER: src = c->er; break;
+    case RZPIC_G_EZ: src = c->ez; break;
+    case RZPIC_G_DENS0: src = c->dens[0]; break;
+    case RZPIC_G_DENS1: src = c->dens[1]; break;
+    case RZPIC_G_VOL: src = c->vol; break;
+    case RZPIC_G_N0:
+    case RZPIC_G_N1: {
+        int s = which - RZPIC_G_N0;
+        HIPCHK(launch_acc_convert(c->nn, c->acc[s], dev, c->quantum[s], to_ctx ? 1 : 0, c->st));
+        return RZPIC_OK;
+    }
+    default: return fail(RZPIC_EINVAL, "unknown grid %d", which);
+    }
+    size_t bytes = (size_t)c->nn * sizeof(double);
+    if (to_ctx) {
+        if (which == RZPIC_G_VOL || which == RZPIC_G_DENS0 || which == RZPIC_G_DENS1)
+            return fail(RZPIC_EINVAL, "grid %d is read-only", which);
+        HIPCHK(hipMemcpyAsync(src, dev, bytes, hipMemcpyDeviceToDevice, c->st));
+        if (which == RZPIC_G_ER || which == RZPIC_G_EZ) {
+            // the gather reads the interleaved copy: repack it
+            if (c->mixed)
+                HIPCHK(launch_pack_e2<float>(c->nn, c->er, c->ez, (float2 *)c->E2, c->st));
+            else
+                HIPCHK(launch_pack_e2<double>(c->nn, c->er, c->ez, (double2 *)c->E2, c->st));
+        }
+    } else {
+        HIPCHK(hipMemcpyAsync(dev, src, bytes, hipMemcpyDeviceToDevice, c->st));
+    }
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_sync(rzpic_ctx *c)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    int32_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, c->status, sizeof h, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (h) {
+        int32_t zero = 0;
+        HIPCHK(hipMemcpy(c->status, &zero, sizeof zero, hipMemcpyHostToDevice));
+        if (h & kStCapacity) return fail(RZPIC_ECAPACITY, "particle capacity exceeded");
+        return fail(RZPIC_ENUMERIC, "fixed-point deposit overflow or non-finite value");
+    }
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_get_diag(rzpic_ctx *c, rzpic_diag *out)
+{
+    if (!c || !out) return fail(RZPIC_EINVAL, "null argument");
+    std::memset(out, 0, sizeof *out);
+    Counts cn[2];
+    unsigned long long tal[6], ms[2 * (1 + kMaxProc)];
+    int32_t stw = 0;
+    HIPCHK(hipMemcpyAsync(cn, c->cnt, sizeof cn, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(tal, c->tally, sizeof tal, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(ms, c->mcstat, sizeof ms, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(&stw, c->status, sizeof stw, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int s = 0; s < 2; ++s) {
+        out->count[s] = cn[s].n;
+        out->next_id[s] = cn[s].next_id;
+        for (int b = 0; b < 3; ++b)
+            out->absorbed[s][b] = (double)(long long)tal[3 * s + b] * c->quantum[s];
+        out->candidates[s] = (int64_t)ms[(1 + kMaxProc) * s];
+        for (int k = 0; k < kMaxProc; ++k) out->events[s][k] = (int64_t)ms[(1 + kMaxProc) * s + 1 + k];
+    }
+    out->last_cycles = c->last_cycles;
+    out->last_relres = c->last_relres;
+    out->status = stw & kStCapacity ? RZPIC_ECAPACITY : (stw ? RZPIC_ENUMERIC : RZPIC_OK);
+    return (rzpic_status)out->status;
+}
+
+rzpic_status rzpic_set_timing(rzpic_ctx *c, int32_t enable)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    c->timing = enable != 0;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_get_timing(rzpic_ctx *c, double out[5])
+{
+    if (!c || !out) return fail(RZPIC_EINVAL, "null argument");
+    for (int k = 0; k < 5; ++k) out[k] = c->t_ms[k];
+    return RZPIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,312 @@
+"""ctypes binding of librzpic.so (include/rzpic.h).
+
+Argument marshalling only: torch supplies device memory and the stream, every
+step of the method runs in the HIP library.  There is no fallback: without
+the built library or a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librzpic.so")
+
+FP64, MIXED = 0, 1
+G_PHI, G_RHO, G_CHI, G_ER, G_EZ, G_N0, G_N1, G_DENS0, G_DENS1, G_VOL = range(10)
+FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "az", "w")
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ECAPACITY", 5: "ENOTCONV",
+          6: "ENUMERIC", 7: "ESTATE"}
+EXPORTS = (
+    "rzpic_create", "rzpic_destroy", "rzpic_set_stream", "rzpic_bind_species", "rzpic_set_count",
+    "rzpic_get_count", "rzpic_set_xsec", "rzpic_get_mc_consts", "rzpic_init_particles",
+    "rzpic_push_first", "rzpic_deposit", "rzpic_solve", "rzpic_efield", "rzpic_push_final",
+    "rzpic_collide", "rzpic_compact", "rzpic_resize", "rzpic_prologue", "rzpic_step",
+    "rzpic_grid_copy", "rzpic_get_diag", "rzpic_sync", "rzpic_last_error", "rzpic_constants",
+    "rzpic_set_timing", "rzpic_get_timing",
+)
+
+
+class RzpicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rzpic {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("nr", C.c_int32), ("nz", C.c_int32),
+        ("R", C.c_double), ("L", C.c_double), ("dt", C.c_double),
+        ("precision", C.c_int32), ("weighting", C.c_int32), ("chi_face", C.c_int32),
+        ("fixed_point_bits", C.c_int32),
+        ("V_dc", C.c_double), ("V_rf", C.c_double), ("f_rf", C.c_double),
+        ("seed", C.c_uint64),
+        ("mg_tol", C.c_double), ("mg_max_cycles", C.c_int32), ("mg_fixed_cycles", C.c_int32),
+        ("resize_every", C.c_int32), ("reserved0", C.c_int32),
+        ("resize_wcoef", C.c_double),
+        ("n_gas", C.c_double), ("T_gas", C.c_double), ("m_gas", C.c_double),
+    ]
+
+
+class SpeciesView(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in FIELDS] + [
+        ("id", C.c_void_p), ("mc_event", C.c_void_p), ("capacity", C.c_int64),
+        ("q", C.c_double), ("m", C.c_double), ("w_ref", C.c_double),
+        ("mc_model", C.c_int32), ("reserved0", C.c_int32),
+    ]
+
+
+class Diag(C.Structure):
+    _fields_ = [
+        ("count", C.c_int64 * 2), ("next_id", C.c_uint64 * 2),
+        ("absorbed", (C.c_double * 3) * 2), ("candidates", C.c_int64 * 2),
+        ("events", (C.c_int64 * 4) * 2), ("last_cycles", C.c_int32), ("status", C.c_int32),
+        ("last_relres", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1001_2969_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, I, D = C.c_void_p, C.c_int32, C.c_double
+        st = C.c_int
+        sig = {
+            "rzpic_create": [C.POINTER(Config), P, C.POINTER(P)],
+            "rzpic_destroy": [P], "rzpic_set_stream": [P, P],
+            "rzpic_bind_species": [P, I, C.POINTER(SpeciesView)],
+            "rzpic_set_count": [P, I, C.c_int64, C.c_uint64],
+            "rzpic_get_count": [P, I, C.POINTER(C.c_int64), C.POINTER(C.c_uint64)],
+            "rzpic_set_xsec": [P, I, I, P, P, D, I, P, D],
+            "rzpic_get_mc_consts": [P, I, C.POINTER(D), C.POINTER(D)],
+            "rzpic_init_particles": [P, I, C.c_int64, D, D, C.c_uint64],
+            "rzpic_push_first": [P, I], "rzpic_push_final": [P, I], "rzpic_compact": [P, I],
+            "rzpic_resize": [P, I], "rzpic_collide": [P, I, C.c_int64],
+            "rzpic_deposit": [P], "rzpic_efield": [P], "rzpic_prologue": [P],
+            "rzpic_solve": [P, D, C.POINTER(I), C.POINTER(D)],
+            "rzpic_step": [P, C.c_int64], "rzpic_grid_copy": [P, I, P, I],
+            "rzpic_get_diag": [P, C.POINTER(Diag)], "rzpic_sync": [P],
+            "rzpic_set_timing": [P, I], "rzpic_get_timing": [P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = st
+        L.rzpic_last_error.restype = C.c_char_p
+        L.rzpic_last_error.argtypes = []
+        L.rzpic_constants.restype = None
+        L.rzpic_constants.argtypes = [P]
+        _lib = L
+    return _lib
+
+
+def constants():
+    out = (C.c_double * 6)()
+    lib().rzpic_constants(C.cast(out, C.c_void_p))
+    return dict(zip(("e", "m_e", "amu", "eps0", "k_B", "two_pi"), list(out)))
+
+
+def _check(code):
+    if code != 0:
+        raise RzpicError(code, lib().rzpic_last_error().decode())
+
+
+class Context:
+    """One discharge on one GPU: the library context plus torch-owned particle
+    arrays of both species.  `w` is a workloads.Workload."""
+
+    def __init__(self, w, *, precision=None, mg_tol=None, mg_fixed_cycles=None,
+                 mg_max_cycles=None, fixed_point_bits=0, device="cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("rzpic needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.w = w
+        prec = w.precision if precision is None else precision
+        self.precision = MIXED if prec in ("mixed", MIXED) else FP64
+        self.dtype = torch.float32 if self.precision == MIXED else torch.float64
+        cfg = Config(nr=w.nr, nz=w.nz, R=w.R, L=w.L, dt=w.dt, precision=self.precision,
+                     weighting=w.weighting, chi_face=w.chi_face,
+                     fixed_point_bits=fixed_point_bits, V_dc=w.V_dc, V_rf=w.V_rf, f_rf=w.f_rf,
+                     seed=w.seed, mg_tol=w.mg_tol if mg_tol is None else mg_tol,
+                     mg_max_cycles=w.mg_max_cycles if mg_max_cycles is None else mg_max_cycles,
+                     mg_fixed_cycles=(w.mg_fixed_cycles if mg_fixed_cycles is None
+                                      else mg_fixed_cycles),
+                     resize_every=w.resize_every, reserved0=0, resize_wcoef=w.wcoef,
+                     n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas)
+        self._cfg = cfg
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            h = C.c_void_p()
+            _check(lib().rzpic_create(C.byref(cfg), C.c_void_p(self.stream.cuda_stream),
+                                      C.byref(h)))
+        self.h = h
+        self.nn = w.nr * w.nz
+        self.arrays = {}
+        self.events = {}
+        self.capacity = {}
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().rzpic_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- species
+    def bind(self, s, capacity, q, m, w_ref, mc_model, events=False):
+        t = self.torch
+        arr = {f: t.zeros(capacity, dtype=self.dtype, device=self.device) for f in FIELDS}
+        arr["id"] = t.zeros(capacity, dtype=t.int64, device=self.device)
+        ev = t.zeros(capacity, dtype=t.uint8, device=self.device) if events else None
+        v = SpeciesView(**{f: arr[f].data_ptr() for f in FIELDS}, id=arr["id"].data_ptr(),
+                        mc_event=ev.data_ptr() if ev is not None else None,
+                        capacity=capacity, q=q, m=m, w_ref=w_ref, mc_model=mc_model,
+                        reserved0=0)
+        _check(lib().rzpic_bind_species(self.h, s, C.byref(v)))
+        self.arrays[s] = arr
+        self.events[s] = ev
+        self.capacity[s] = capacity
+
+    def set_xsec(self, s, kind, thr, de, sigma, ejb):
+        kind = np.ascontiguousarray(kind, np.int32)
+        thr = np.ascontiguousarray(thr, np.float64)
+        sigma = np.ascontiguousarray(sigma, np.float64)
+        _check(lib().rzpic_set_xsec(self.h, s, sigma.shape[0], kind.ctypes.data,
+                                    thr.ctypes.data, de, sigma.shape[1], sigma.ctypes.data, ejb))
+
+    def mc_consts(self, s):
+        a, b = C.c_double(), C.c_double()
+        _check(lib().rzpic_get_mc_consts(self.h, s, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def set_particles(self, s, parts, next_id):
+        t = self.torch
+        n = len(parts["r"])
+        arr = self.arrays[s]
+        for f in FIELDS:
+            arr[f][:n].copy_(t.as_tensor(np.asarray(parts[f]), dtype=self.dtype))
+        arr["id"][:n].copy_(t.as_tensor(np.asarray(parts["id"]).astype(np.int64)))
+        _check(lib().rzpic_set_count(self.h, s, n, next_id))
+
+    def count(self, s):
+        n, nid = C.c_int64(), C.c_uint64()
+        _check(lib().rzpic_get_count(self.h, s, C.byref(n), C.byref(nid)))
+        return n.value, nid.value
+
+    def particles(self, s):
+        n, _ = self.count(s)
+        arr = self.arrays[s]
+        out = {f: arr[f][:n].double().cpu().numpy() for f in FIELDS}
+        out["id"] = arr["id"][:n].cpu().numpy().astype(np.uint64)
+        return out
+
+    def event_codes(self, s, n):
+        return self.events[s][:n].cpu().numpy()
+
+    def init_particles(self, s, n, n0, T_eV, id0=0):
+        _check(lib().rzpic_init_particles(self.h, s, n, n0, T_eV, id0))
+
+    # ---- operations
+    def push_first(self, s):
+        _check(lib().rzpic_push_first(self.h, s))
+
+    def push_final(self, s):
+        _check(lib().rzpic_push_final(self.h, s))
+
+    def collide(self, s, step):
+        _check(lib().rzpic_collide(self.h, s, step))
+
+    def compact(self, s):
+        _check(lib().rzpic_compact(self.h, s))
+
+    def resize(self, s):
+        _check(lib().rzpic_resize(self.h, s))
+
+    def deposit(self):
+        _check(lib().rzpic_deposit(self.h))
+
+    def efield(self):
+        _check(lib().rzpic_efield(self.h))
+
+    def prologue(self):
+        _check(lib().rzpic_prologue(self.h))
+
+    def solve(self, t, want=True):
+        if not want:
+            _check(lib().rzpic_solve(self.h, t, None, None))
+            return None
+        cyc, rr = C.c_int32(), C.c_double()
+        _check(lib().rzpic_solve(self.h, t, C.byref(cyc), C.byref(rr)))
+        return cyc.value, rr.value
+
+    def step(self, n):
+        _check(lib().rzpic_step(self.h, n))
+
+    def sync(self):
+        _check(lib().rzpic_sync(self.h))
+
+    # ---- grids
+    def grid(self, which):
+        t = self.torch
+        buf = t.empty(self.nn, dtype=t.float64, device=self.device)
+        _check(lib().rzpic_grid_copy(self.h, which, C.c_void_p(buf.data_ptr()), 0))
+        return buf.cpu().numpy().reshape(self.w.nz, self.w.nr)
+
+    def set_grid(self, which, arr):
+        t = self.torch
+        buf = t.as_tensor(np.ascontiguousarray(arr, np.float64).reshape(-1)).to(self.device)
+        _check(lib().rzpic_grid_copy(self.h, which, C.c_void_p(buf.data_ptr()), 1))
+        self.stream.synchronize()
+
+    def diag(self):
+        d = Diag()
+        code = lib().rzpic_get_diag(self.h, C.byref(d))
+        out = {"count": list(d.count), "next_id": list(d.next_id),
+               "absorbed": [list(d.absorbed[s]) for s in range(2)],
+               "candidates": list(d.candidates), "events": [list(d.events[s]) for s in range(2)],
+               "last_cycles": d.last_cycles, "last_relres": d.last_relres, "status": d.status}
+        if code:
+            _check(code)
+        return out
+
+    def set_timing(self, on=True):
+        _check(lib().rzpic_set_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        out = (C.c_double * 5)()
+        _check(lib().rzpic_get_timing(self.h, C.cast(out, C.c_void_p)))
+        return list(out)
+
+
+def make_context(w, *, capacity_factor=1.6, events=False, with_xsec=True, **kw):
+    """Context with both species bound (capacity = factor * initial count) and
+    the workload's synthetic cross sections loaded."""
+    from . import workloads as wl
+    ctx = Context(w, **kw)
+    hr = w.R / (w.nr - 1)
+    for s in (0, 1):
+        cap = max(1024, int(w.n_per_species * capacity_factor))
+        w_ref = w.wcoef * w.R  # heaviest initial weight
+        model = (wl.MC_ELECTRON, wl.MC_ION)[s] if with_xsec else wl.MC_NONE
+        ctx.bind(s, cap, wl.SPECIES_Q[s], wl.SPECIES_M[s], w_ref, model, events=events)
+    if with_xsec:
+        for s, (kind, thr, sig, ejb) in wl.xsec_tables(w).items():
+            ctx.set_xsec(s, kind, thr, wl.XSEC_DE, sig, ejb)
+    del hr
+    return ctx
