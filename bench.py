@@ -1,0 +1,231 @@
+#!/usr/bin/env python
+"""Benchmark of the merged implicit r-z PIC/MC step on one MI355X.
+
+Workload: 129x65 mesh (R = 4 cm, L = 2 cm), 2M electrons + 2M Ar+ ions
+(seeded Maxwellian init, weights proportional to r), 200 V 13.56 MHz drive,
+3 V(0,1) cycles per step; the headline runs the mixed form (FP32 particles and
+smoothing, FP64 residual / defect correction and int64 deposit), and the same
+workload runs in plain FP64 beside it.
+
+Prints one JSON line: particle-steps/s of the mixed form (`value`), the FP64
+rate, V-cycle times and the cycles each form needs for a fixed phi error,
+the roofline of the fused particle pass (HIP events on the library's stream
+over the timed region), and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/sec + multigrid V-cycle ms, mixed vs FP64 GPU at fixed phi err"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of one particle through the fused pass: read the 8 real
+# fields + 8-byte id, write 7 real fields (the weight is only read).
+BYTES_PER_PARTICLE = {"mixed": 8 * 4 + 8 + 7 * 4, "fp64": 8 * 8 + 8 + 7 * 8}
+
+
+def run_gpu(w, precision, steps, warmup, seed_shift=0):
+    import torch
+
+    from paper_1001_2969_amd import rzpic
+
+    ctx = rzpic.make_context(w, precision=precision, capacity_factor=1.25)
+    ctx.init_particles(0, w.n_per_species, w.n0, w.Te_eV, 0)
+    ctx.init_particles(1, w.n_per_species, w.n0, w.Ti_eV, 0)
+    ctx.prologue()
+    n = 0
+    for _ in range(warmup):
+        ctx.step(n)
+        n += 1
+    ctx.sync()
+    ctx.set_timing(True)
+    ctx.timing()  # reset accumulators
+    d0 = ctx.diag()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(n)
+        n += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    tim = ctx.timing()
+    d1 = ctx.diag()
+    ctx.set_timing(False)
+    psteps = sum(d1["particle_steps"]) - sum(d0["particle_steps"])
+    dt = t1 - t0
+    return ctx, {
+        "value": psteps / dt, "ms_per_step": 1e3 * dt / steps, "particle_steps": psteps,
+        "timing": tim, "count": d1["count"], "events_last_step": d1["events"],
+    }
+
+
+def vcycle_study(w, rho, chi, phi0):
+    """Solver level, identical (rho, chi): cycles each form needs to bring the
+    L-inf error of phi below 1e-8 of |phi| (reference: the FP64 solve to a
+    1e-12 residual), and device time per V-cycle on the benchmark mesh."""
+    import numpy as np
+    import torch
+
+    from paper_1001_2969_amd import rzpic
+
+    out = {}
+    ref_ctx = rzpic.Context(w, precision="fp64", mg_fixed_cycles=0, mg_tol=1e-12,
+                            mg_max_cycles=200)
+    for g, a in ((rzpic.G_RHO, rho), (rzpic.G_CHI, chi), (rzpic.G_PHI, phi0)):
+        ref_ctx.set_grid(g, a)
+    t_ref = 1e-9
+    ref_ctx.solve(t_ref)
+    phi_ref = ref_ctx.grid(rzpic.G_PHI)
+    scale = np.abs(phi_ref).max()
+    for prec in ("fp64", "mixed"):
+        ctx = rzpic.Context(w, precision=prec, mg_fixed_cycles=1)
+        errs = []
+        for k in range(1, 41):
+            ctx.set_mg(fixed_cycles=k)
+            for g, a in ((rzpic.G_RHO, rho), (rzpic.G_CHI, chi), (rzpic.G_PHI, phi0)):
+                ctx.set_grid(g, a)
+            ctx.solve(t_ref, want=False)
+            e = float(np.abs(ctx.grid(rzpic.G_PHI) - phi_ref).max() / scale)
+            errs.append(e)
+            if e <= 1e-8:
+                break
+        k_need = len(errs) if errs[-1] <= 1e-8 else None
+        # device time per cycle: (T(1 + m cycles) - T(1 cycle)) / m
+        times = {}
+        for k in (1, 21):
+            ctx.set_mg(fixed_cycles=k)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            best = math.inf
+            for _ in range(5):
+                ctx.stream.synchronize()
+                ev0.record(ctx.stream)
+                ctx.solve(t_ref, want=False)
+                ev1.record(ctx.stream)
+                ev1.synchronize()
+                best = min(best, ev0.elapsed_time(ev1))
+            times[k] = best
+        out[prec] = {"vcycle_ms": (times[21] - times[1]) / 20.0, "cycles_to_1e-8": k_need,
+                     "err_after_3_cycles": errs[2] if len(errs) >= 3 else errs[-1],
+                     "solve_ms_at_1e-8": (times[1] + (times[21] - times[1]) / 20.0 *
+                                          ((k_need or 41) - 1))}
+    return out
+
+
+def cpu_baseline(w, steps):
+    """The FP64 CPU oracle (single thread, as it stands) on the first `steps`
+    steps of the same workload: particle-steps/s."""
+    from oracle import rzo
+
+    o = rzo.Oracle(w.replace(precision="fp64"))
+    o.init_particles(0, w.n_per_species, w.n0, w.Te_eV, 0)
+    o.init_particles(1, w.n_per_species, w.n0, w.Ti_eV, 0)
+    o.prologue()
+    ps = 0
+    t0 = time.perf_counter()
+    for n in range(steps):
+        ps += o.count(0) + o.count(1)
+        o.step(n)
+    dt = time.perf_counter() - t0
+    return ps / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-vcycle-study", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU form is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1001_2969_amd import rzpic, workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = wl.rf_129x65()
+    print(f"# workload {w.name}: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr,
+          flush=True)
+    ctx_m, mixed = run_gpu(w, "mixed", args.steps, args.warmup)
+    print(f"# mixed: {mixed['value']:.4g} particle-steps/s, {mixed['ms_per_step']:.4f} ms/step",
+          file=sys.stderr, flush=True)
+    fp64 = None
+    rho = chi = phi = None
+    if not args.no_fp64:
+        ctx_d, fp64 = run_gpu(w, "fp64", args.steps, args.warmup)
+        print(f"# fp64: {fp64['value']:.4g} particle-steps/s, {fp64['ms_per_step']:.4f} ms/step",
+              file=sys.stderr, flush=True)
+        rho, chi, phi = (ctx_d.grid(g) for g in (rzpic.G_RHO, rzpic.G_CHI, rzpic.G_PHI))
+        ctx_d.close()
+    vstudy = None
+    if not args.no_vcycle_study:
+        if rho is None:
+            rho, chi, phi = (ctx_m.grid(g) for g in (rzpic.G_RHO, rzpic.G_CHI, rzpic.G_PHI))
+        phi0 = np.zeros_like(phi)
+        vstudy = vcycle_study(w, rho, chi, phi0)
+        print(f"# V-cycle study: {json.dumps(vstudy)}", file=sys.stderr, flush=True)
+    ctx_m.close()
+
+    tm = mixed["timing"]
+    n_launch = 0.5 * (tm["n0"] + tm["n1"])
+    t_launch_ms = 0.5 * (tm["pass0_ms"] + tm["pass1_ms"])
+    bpp = BYTES_PER_PARTICLE["mixed"]
+    achieved = bpp * n_launch / (t_launch_ms * 1e-3) / 1e9 if t_launch_ms > 0 else None
+    roofline = {"kernel": "k_pass<float, fused, LDS deposit>", "bound": "hbm",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                "bytes_per_particle": bpp, "particles_per_launch": n_launch,
+                "avg_launch_ms": t_launch_ms}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        v, secs = cpu_baseline(w, args.cpu_steps)
+        cpu = {"value": v, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {args.cpu_steps} steps of the same workload "
+                         f"(2 x {w.n_per_species} particles, FP64, single thread), {secs:.1f} s"}
+
+    line = {
+        "metric": METRIC, "value": mixed["value"], "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 particles / f64 residual / int64 deposit", "data": "synthetic",
+        "config": {"workload": w.name, "mesh": f"{w.nr}x{w.nz}", "R_m": w.R, "L_m": w.L,
+                   "particles_per_species": w.n_per_species, "precision": "mixed",
+                   "v_cycles_per_step": w.mg_fixed_cycles, "V_rf": w.V_rf, "f_rf": w.f_rf},
+        "breakdown_ms_per_step": {k: tm[k] for k in ("step_ms", "solve_ms", "pass0_ms",
+                                                     "pass1_ms", "collide_ms", "grid_ms",
+                                                     "lists_ms")},
+        "vcycle_ms": {"mixed": tm["solve_ms"] / max(tm["vcycles"], 1)},
+        "fp64": None if fp64 is None else {
+            "value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+            "breakdown_ms_per_step": {k: fp64["timing"][k] for k in
+                                      ("step_ms", "solve_ms", "pass0_ms", "pass1_ms")},
+            "pass_GBps": BYTES_PER_PARTICLE["fp64"] * 0.5 * (fp64["timing"]["n0"] +
+                                                            fp64["timing"]["n1"]) /
+            (0.5e-3 * (fp64["timing"]["pass0_ms"] + fp64["timing"]["pass1_ms"])) / 1e9},
+        "mixed_over_fp64": None if fp64 is None else mixed["value"] / fp64["value"],
+        "fixed_phi_err": vstudy,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if fp64 is not None:
+        line["vcycle_ms"]["fp64"] = fp64["timing"]["solve_ms"] / max(fp64["timing"]["vcycles"], 1)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

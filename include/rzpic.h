@@ -101,6 +101,7 @@ typedef struct rzpic_diag {
     int32_t last_cycles;       /* V-cycles of the last solve                */
     int32_t status;            /* sticky device status (rzpic_status)       */
     double last_relres;        /* ||f - A phi||_inf / ||f_bc||_inf, last solve (tol mode) */
+    uint64_t particle_steps[2];/* cumulative live particles entering rzpic_step passes */
 } rzpic_diag;
 
 typedef struct rzpic_ctx rzpic_ctx;
@@ -158,6 +159,9 @@ rzpic_status rzpic_deposit(rzpic_ctx *ctx);
  * the cycles run and the final relative residual (requesting them
  * synchronises).  ENOTCONV if the tolerance is not met. */
 rzpic_status rzpic_solve(rzpic_ctx *ctx, double t, int32_t *cycles, double *relres);
+/* Change the multigrid cycling of later solves (same meaning as the config
+ * fields mg_tol, mg_max_cycles, mg_fixed_cycles). */
+rzpic_status rzpic_set_mg(rzpic_ctx *ctx, double tol, int32_t max_cycles, int32_t fixed_cycles);
 /* E = -grad phi on the nodes. */
 rzpic_status rzpic_efield(rzpic_ctx *ctx);
 /* Gather of E at the first-pushed position, final push, damped-acceleration
@@ -192,12 +196,18 @@ rzpic_status rzpic_sync(rzpic_ctx *ctx);
 const char *rzpic_last_error(void);
 /* Physical constants used inside the library: e, m_e, amu, eps0, k_B, 2 pi. */
 void rzpic_constants(double out[6]);
-/* Kernel time accounting: average device time (ms) of the last `rzpic_step`
- * phases measured with HIP events when timing is enabled:
- * out[0] = whole step, out[1] = field solve, out[2] = particle passes,
- * out[3] = compaction; out[4] = V-cycles in the last solve. */
+/* Device-time accounting of rzpic_step with HIP events on the context's
+ * stream (off by default).  rzpic_get_timing synchronises and returns, averaged
+ * over the steps recorded since the previous call (then resets):
+ *   out[0] steps recorded          out[1] whole step (ms)
+ *   out[2] field solve (ms)        out[3] V-cycles per solve
+ *   out[4] electron pass kernel    out[5] ion pass kernel (ms), without
+ *                                  the collision kernel of their candidates
+ *   out[6] finalize + E field (ms) out[7] list maintenance + split (ms)
+ *   out[8] electrons, out[9] ions entering the passes (per step)
+ *   out[10] collision kernels over the candidates, both species (ms) */
 rzpic_status rzpic_set_timing(rzpic_ctx *ctx, int32_t enable);
-rzpic_status rzpic_get_timing(rzpic_ctx *ctx, double out[5]);
+rzpic_status rzpic_get_timing(rzpic_ctx *ctx, double out[11]);
 
 #ifdef __cplusplus
 }

@@ -101,7 +101,7 @@ template <typename T> __device__ __forceinline__ W4<T> weights(const Mesh &m, T 
 // Evaluated with contraction off so that it rounds exactly like the host
 // reference arithmetic on identical inputs (decisions depend on it).
 
-__device__ __noinline__ double xsec_at(const Xsec &x, int k, double eps)
+__device__ __forceinline__ double xsec_at(const Xsec &x, int k, double eps)
 {
 #pragma clang fp contract(off)
     const double *sg = x.sigma + (size_t)k * x.ne;
@@ -115,7 +115,7 @@ __device__ __noinline__ double xsec_at(const Xsec &x, int k, double eps)
 
 // Process chosen by a candidate with uniform u1: the first k with
 // u1 * nu_max < sum_{k' <= k} n_gas sigma_k'(eps) g, or -1 (null collision).
-__device__ __noinline__ int choose_process(const Xsec &x, double n_gas, double thr_nu, double eps,
+__device__ __forceinline__ int choose_process(const Xsec &x, double n_gas, double thr_nu, double eps,
                                            double g)
 {
 #pragma clang fp contract(off)
@@ -185,21 +185,23 @@ struct Child {
     double vr, vt, vz;
 };
 
-// Null-collision test and outcome of one particle (Sec. 2.6).  Returns the
-// event code (0 none, 1 null, 2+k process k).  v[] is updated in place; an
+// Outcome of a null-collision candidate (Sec. 2.6; the candidate test itself,
+// U0 < P_null with block 0 of the draws, is made by the caller, which passes
+// U1 = ub).  Returns the event code (1 null, 2+k process k).  v[] is updated in place; an
 // ionization fills the ejected electron and the new ion velocities and sets
 // *iz.  Draw blocks: 0 = (candidate, process); electrons: 1 = (chi, phi),
 // 2 = (ejected energy, chi_ej), 3 = (phi_ej, -), 4-5 = ion normals;
 // ions: 1-2 = target normals, 3 = (cos chi, phi) in the centre of mass.
-__device__ __noinline__ int collide(const SpeciesK &sp, const Phys &ph, uint64_t id,
-                                    uint32_t step, double &v0, double &v1, double &v2, int &iz,
-                                    Child &ce, Child &ci)
+__device__ __forceinline__ int collide_candidate(const SpeciesK &sp, const Phys &ph, uint64_t id,
+                                              uint32_t step, double ub, double &v0, double &v1,
+                                              double &v2, int &iz, Child &ce, Child &ci)
 {
     iz = 0;
-    double ua, ub;
-    uniform2(ph.seed, sp.s, id, step, 0, ua, ub);
-    if (!(ua < sp.p_null)) return 0;
-    double thr_nu = ub * sp.nu_max;
+    double thr_nu;
+    {
+#pragma clang fp contract(off)
+        thr_nu = ub * sp.nu_max;
+    }
     if (sp.mc_model == 1) {
         double eps = energy_ev(v0, v1, v2, sp.ekin);
         double vm = sqrt(sumsq3(v0, v1, v2));
@@ -310,7 +312,7 @@ __device__ __noinline__ int collide(const SpeciesK &sp, const Phys &ph, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// Wave/block scans.  The block is a whole number of 64-lane waves.
+// Wavefront scans (a chunk of particles is one 64-lane wavefront).
 
 __device__ __forceinline__ int lane_rank(unsigned long long mask)
 {
@@ -318,44 +320,35 @@ __device__ __forceinline__ int lane_rank(unsigned long long mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Exclusive ranks of up to 4 flags over the block (in thread order) and their
-// totals.  `sh` needs 4 * (blockDim/64) ints of shared memory.
-__device__ __forceinline__ void block_rank4(const bool f[4], int rank[4], int total[4], int *sh)
+// Rank of this lane among the lanes with f set (lane order), and their number.
+__device__ __forceinline__ int wave_rank(bool f, int &total)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int wr[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        unsigned long long m = __ballot(f[k]);
-        wr[k] = lane_rank(m);
-        if (lane == 0) sh[k * 16 + wv] = __popcll(m);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int before = 0, tot = 0;
-        for (int w = 0; w < nw; ++w) {
-            int c = sh[k * 16 + w];
-            before += w < wv ? c : 0;
-            tot += c;
-        }
-        rank[k] = before + wr[k];
-        total[k] = tot;
-    }
-    __syncthreads();
+    unsigned long long m = __ballot(f);
+    total = __popcll(m);
+    return lane_rank(m);
 }
 
-// Exclusive prefix of a non-negative int over the block, and its total.
-__device__ __forceinline__ int block_excl_sum(int v, int &total, int *sh)
+// Exclusive prefix over the wavefront of a non-negative int, and the total.
+__device__ __forceinline__ int wave_excl_sum(int v, int &total)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     int x = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         int y = __shfl_up(x, d, 64);
         if (lane >= d) x += y;
     }
-    if (lane == 63) sh[wv] = x;
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// Exclusive prefix of a non-negative int over the block, and its total.
+__device__ __forceinline__ int block_excl_sum(int v, int &total, int *sh)
+{
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+    int wt;
+    int x = wave_excl_sum(v, wt);
+    if (lane == 0) sh[wv] = wt;
     __syncthreads();
     int before = 0, tot = 0;
     for (int w = 0; w < nw; ++w) {
@@ -365,7 +358,16 @@ __device__ __forceinline__ int block_excl_sum(int v, int &total, int *sh)
     }
     __syncthreads();
     total = tot;
-    return before + x - v;
+    return before + x;
+}
+
+// Round-to-nearest-even of |x| < 2^51 to an integer, exactly: adding 1.5*2^52
+// leaves the integer in the low mantissa bits.
+__device__ __forceinline__ long long round_fixed(double x)
+{
+    const double magic = 6755399441055744.0;
+    double y = x + magic;
+    return (long long)(__double_as_longlong(y) - __double_as_longlong(magic));
 }
 
 }  // namespace rz

@@ -7,16 +7,38 @@
 
 namespace rz {
 
-// Exclusive scan of in[0..n) into out[] by one block; returns the total.
-__device__ int64_t block_scan_tiles(const int32_t *in, int64_t *out, int64_t n, int *sh)
+__device__ __forceinline__ int count_of(const int32_t *in, int64_t i) { return in[i]; }
+__device__ __forceinline__ int count_of(const unsigned long long *in, int64_t i)
 {
+    return __popcll(in[i]);
+}
+
+// Exclusive scan of the counts of in[0..n) (ints, or the set bits of lane
+// masks) into out[] by one block of 1024 threads, 8 consecutive items per
+// thread per tile; returns the total.
+template <typename C>
+__device__ int64_t block_scan_tiles(const C *in, int64_t *out, int64_t n, int *sh)
+{
+    constexpr int kItems = 8;
     int64_t carry = 0;
-    for (int64_t base = 0; base < n; base += blockDim.x) {
-        int64_t i = base + threadIdx.x;
-        int v = i < n ? in[i] : 0;
+    const int64_t tile = (int64_t)blockDim.x * kItems;
+    for (int64_t base = 0; base < n; base += tile) {
+        const int64_t i0 = base + (int64_t)threadIdx.x * kItems;
+        int v[kItems];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            v[k] = i0 + k < n ? count_of(in, i0 + k) : 0;
+            sum += v[k];
+        }
         int tot;
-        int ex = block_excl_sum(v, tot, sh);
-        if (i < n) out[i] = carry + ex;
+        int ex = block_excl_sum(sum, tot, sh);
+        int64_t run = carry + ex;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (i0 + k < n) out[i0 + k] = run;
+            run += v[k];
+        }
         carry += tot;
     }
     return carry;
@@ -25,13 +47,12 @@ __device__ int64_t block_scan_tiles(const int32_t *in, int64_t *out, int64_t n, 
 __global__ __launch_bounds__(1024) void k_scan(ScanJobs j)
 {
     __shared__ int sh[64];
-    const int B = j.chunk;
     if (blockIdx.x == 0) {
         if (!j.children) return;
-        const int64_t nch = (j.crec->n_parent + B - 1) / B;
-        int64_t ev = block_scan_tiles(j.ech.ev_cnt, j.ech.ev_off, nch, sh);
-        int64_t se = block_scan_tiles(j.ech.surv_e, j.ech.surv_e_off, nch, sh);
-        int64_t si = block_scan_tiles(j.ech.surv_i, j.ech.surv_i_off, nch, sh);
+        const int64_t nch = (j.crec->n_parent + kChunk - 1) / kChunk;
+        int64_t ev = block_scan_tiles(j.ech.ev, j.ech.ev_off, nch, sh);
+        int64_t se = block_scan_tiles(j.ech.se, j.ech.se_off, nch, sh);
+        int64_t si = block_scan_tiles(j.ech.si, j.ech.si_off, nch, sh);
         if (threadIdx.x == 0) {
             j.crec->ev_total = ev;
             j.crec->surv_total[0] = se;
@@ -44,8 +65,8 @@ __global__ __launch_bounds__(1024) void k_scan(ScanJobs j)
     const int s = blockIdx.x - 1;
     if (!j.dead[s]) return;
     const int64_t n = j.cnt[s]->n;
-    const int64_t nch = (n + B - 1) / B;
-    int64_t d = block_scan_tiles(j.ch[s].dead_cnt, j.ch[s].dead_off, nch, sh);
+    const int64_t nch = (n + kChunk - 1) / kChunk;
+    int64_t d = block_scan_tiles(j.ch[s].dead, j.ch[s].dead_off, nch, sh);
     if (threadIdx.x == 0) {
         j.fix[s]->n_old = n;
         j.fix[s]->dead = d;
@@ -60,46 +81,45 @@ hipError_t launch_scan(const ScanJobs &j, hipStream_t st)
 }
 
 // Unmerged form: per-chunk lists of the particles marked dead (w < 0).
-template <typename T>
-__global__ __launch_bounds__(256) void k_dead_scan(const T *w, const Counts *cnt, Chunks ch)
+template <typename T> __global__ __launch_bounds__(256) void k_dead_scan(const T *w, const Counts *cnt, Chunks ch)
 {
-    __shared__ int sh[64];
-    const int B = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t n = cnt->n;
-    const int64_t nch = (n + B - 1) / B;
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        int64_t i = c * B + threadIdx.x;
-        bool f[4] = {i < n && w[i] < (T)0, false, false, false};
-        int rank[4], tot[4];
-        block_rank4(f, rank, tot, sh);
-        if (f[0]) ch.dead_list[c * B + rank[0]] = threadIdx.x;
-        if (threadIdx.x == 0) ch.dead_cnt[c] = tot[0];
+    const int64_t nch = (n + kChunk - 1) / kChunk;
+    for (int64_t c = wave; c < nch; c += nwaves) {
+        int64_t i = c * kChunk + lane;
+        unsigned long long dm = __ballot(i < n && w[i] < (T)0);
+        if (lane == 0) ch.dead[c] = dm;
     }
 }
 
 template <typename T>
-hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, int chunk, hipStream_t st)
+hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_dead_scan<T>), dim3(1024), dim3(chunk), 0, st, p.w, cnt, ch);
+    hipLaunchKernelGGL((k_dead_scan<T>), dim3(1024), dim3(256), 0, st, p.w, cnt, ch);
     return hipGetLastError();
 }
 
-__global__ void k_dead_list(Chunks ch, const FixRec *fix, int B)
+__global__ __launch_bounds__(256) void k_dead_list(Chunks ch, const FixRec *fix)
 {
-    const int64_t nch = (fix->n_old + B - 1) / B;
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        int cnt = ch.dead_cnt[c];
-        int64_t off = ch.dead_off[c];
-        for (int k = threadIdx.x; k < cnt; k += blockDim.x)
-            ch.dead_glob[off + k] = c * B + ch.dead_list[c * B + k];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nch = (fix->n_old + kChunk - 1) / kChunk;
+    if (fix->dead == 0) return;
+    const unsigned long long below = (1ull << lane) - 1;
+    for (int64_t c = wave; c < nch; c += nwaves) {
+        unsigned long long dm = ch.dead[c];
+        if ((dm >> lane) & 1)
+            ch.dead_glob[ch.dead_off[c] + __popcll(dm & below)] = c * kChunk + lane;
     }
 }
 
-hipError_t launch_dead_list(Chunks ch, const Counts *cnt, const FixRec *fix, int chunk,
-                            hipStream_t st)
+hipError_t launch_dead_list(Chunks ch, const FixRec *fix, hipStream_t st)
 {
-    (void)cnt;
-    hipLaunchKernelGGL(k_dead_list, dim3(1024), dim3(256), 0, st, ch, fix, chunk);
+    hipLaunchKernelGGL(k_dead_list, dim3(1024), dim3(256), 0, st, ch, fix);
     return hipGetLastError();
 }
 
@@ -146,30 +166,27 @@ hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st)
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_append(Parts<T> dst, Parts<T> stage, int cs, Chunks ech,
-                                                 int children, const ChildRec *crec,
-                                                 const FixRec *fix, Counts *cnt, int64_t cap,
-                                                 int32_t *status)
+__global__ __launch_bounds__(256) void k_append(Parts<T> dst, Parts<T> stage, int cs, Chunks ech,
+                                                int children, const ChildRec *crec,
+                                                const FixRec *fix, Counts *cnt, int64_t cap,
+                                                int32_t *status)
 {
-    __shared__ int sh[64];
-    const int B = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t keep = fix->keep;
     if (children) {
-        const int32_t *surv = cs == 0 ? ech.surv_e : ech.surv_i;
-        const int64_t *surv_off = cs == 0 ? ech.surv_e_off : ech.surv_i_off;
-        (void)surv;
+        const int64_t *surv_off = cs == 0 ? ech.se_off : ech.si_off;
+        const unsigned long long *alive = cs == 0 ? ech.se : ech.si;
         const uint64_t id0 = crec->next_id_old[cs];
-        const int64_t nch = (crec->n_parent + B - 1) / B;
-        for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-            const int ne = ech.ev_cnt[c];
-            if (ne == 0) continue;  // uniform over the block
-            const int k = threadIdx.x;
-            const int64_t slot = c * B + k;
-            bool alive = k < ne && stage.w[slot] >= (T)0;
-            int tot;
-            int rank = block_excl_sum(alive ? 1 : 0, tot, sh);
-            int64_t to = keep + surv_off[c] + rank;
-            if (alive && to < cap) {
+        const int64_t nch = (crec->n_parent + kChunk - 1) / kChunk;
+        const unsigned long long below = (1ull << lane) - 1;
+        for (int64_t c = wave; c < nch; c += nwaves) {
+            const unsigned long long am = alive[c];
+            if (!((am >> lane) & 1)) continue;
+            const int64_t slot = c * kChunk + lane;
+            const int64_t to = keep + surv_off[c] + __popcll(am & below);
+            if (to < cap) {
                 dst.r[to] = stage.r[slot];
                 dst.z[to] = stage.z[slot];
                 dst.vr[to] = stage.vr[slot];
@@ -178,7 +195,7 @@ __global__ __launch_bounds__(1024) void k_append(Parts<T> dst, Parts<T> stage, i
                 dst.ar[to] = stage.ar[slot];
                 dst.az[to] = stage.az[slot];
                 dst.w[to] = stage.w[slot];
-                dst.id[to] = id0 + (uint64_t)(ech.ev_off[c] + k);
+                dst.id[to] = id0 + (uint64_t)(ech.ev_off[c] + __popcll(ech.ev[c] & below));
             }
         }
     }
@@ -201,9 +218,9 @@ __global__ __launch_bounds__(1024) void k_append(Parts<T> dst, Parts<T> stage, i
 template <typename T>
 hipError_t launch_append(Parts<T> dst, Parts<T> stage, int cs, Chunks ech, int children,
                          const ChildRec *crec, const FixRec *fix, Counts *cnt, int64_t cap,
-                         int chunk, int32_t *status, hipStream_t st)
+                         int32_t *status, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_append<T>), dim3(children ? 1024 : 1), dim3(chunk), 0, st, dst, stage, cs,
+    hipLaunchKernelGGL((k_append<T>), dim3(children ? 1024 : 1), dim3(256), 0, st, dst, stage, cs,
                        ech, children, crec, fix, cnt, cap, status);
     return hipGetLastError();
 }
@@ -233,12 +250,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_resize_count(Parts<T> p, const Counts *cnt, Chunks ch,
                                                       double wcoef, double half_hr)
 {
-    __shared__ int sh[64];
-    const int B = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t n = cnt->n;
-    const int64_t nch = (n + B - 1) / B;
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        int64_t i = c * B + threadIdx.x;
+    const int64_t nch = (n + kChunk - 1) / kChunk;
+    for (int64_t c = wave; c < nch; c += nwaves) {
+        int64_t i = c * kChunk + lane;
         int nc = 0;
         if (i < n) {
             double wr;
@@ -246,17 +264,17 @@ __global__ __launch_bounds__(256) void k_resize_count(Parts<T> p, const Counts *
             ch.pcount[i] = nc;
         }
         int tot;
-        block_excl_sum(nc, tot, sh);
-        if (threadIdx.x == 0) ch.clone_cnt[c] = tot;
+        wave_excl_sum(nc, tot);
+        if (lane == 0) ch.clone_cnt[c] = tot;
     }
 }
 
 __global__ __launch_bounds__(1024) void k_resize_scan(const Counts *cnt, Chunks ch, CloneRec *rec,
-                                                      int B, int64_t cap)
+                                                      int64_t cap)
 {
     __shared__ int sh[64];
     const int64_t n = cnt->n;
-    const int64_t nch = (n + B - 1) / B;
+    const int64_t nch = (n + kChunk - 1) / kChunk;
     int64_t tot = block_scan_tiles(ch.clone_cnt, ch.clone_off, nch, sh);
     if (threadIdx.x == 0) {
         rec->n_old = n;
@@ -271,19 +289,20 @@ __global__ __launch_bounds__(256) void k_resize_scatter(Parts<T> p, Counts *cnt,
                                                         const CloneRec *rec, double wcoef,
                                                         double half_hr, int32_t *status)
 {
-    __shared__ int sh[64];
-    const int B = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t n = rec->n_old;
     if (!rec->ok) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(status, kStCapacity);
         return;
     }
-    const int64_t nch = (n + B - 1) / B;
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        int64_t i = c * B + threadIdx.x;
+    const int64_t nch = (n + kChunk - 1) / kChunk;
+    for (int64_t c = wave; c < nch; c += nwaves) {
+        int64_t i = c * kChunk + lane;
         int nc = i < n ? ch.pcount[i] : 0;
         int tot;
-        int ex = block_excl_sum(nc, tot, sh);
+        int ex = wave_excl_sum(nc, tot);
         if (nc > 0) {
             double wr;
             double w = (double)p.w[i];
@@ -313,52 +332,54 @@ __global__ __launch_bounds__(256) void k_resize_scatter(Parts<T> p, Counts *cnt,
 }
 
 template <typename T>
-hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, int chunk,
-                         double wcoef, double half_hr, int64_t cap, int32_t *status,
-                         hipStream_t st)
+hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, double wcoef,
+                         double half_hr, int64_t cap, int32_t *status, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_resize_count<T>), dim3(1024), dim3(chunk), 0, st, p, cnt, ch, wcoef,
+    hipLaunchKernelGGL((k_resize_count<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, wcoef,
                        half_hr);
-    hipLaunchKernelGGL(k_resize_scan, dim3(1), dim3(1024), 0, st, cnt, ch, rec, chunk, cap);
-    hipLaunchKernelGGL((k_resize_scatter<T>), dim3(1024), dim3(chunk), 0, st, p, cnt, ch, rec,
+    hipLaunchKernelGGL(k_resize_scan, dim3(1), dim3(1024), 0, st, cnt, ch, rec, cap);
+    hipLaunchKernelGGL((k_resize_scatter<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, rec,
                        wcoef, half_hr, status);
     return hipGetLastError();
 }
 
-// acc[g] += sum over blocks of the per-block LDS copies.
-__global__ void k_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
-                                int nn)
+// acc[g] += sum over blocks of the per-block LDS copies: block (x, y) sums
+// slices y, y + gridDim.y, ... of nodes [256x, 256x + 256) and adds the
+// (integer) partial sum atomically.
+__global__ __launch_bounds__(256) void k_reduce_slices(unsigned long long *acc,
+                                                       const unsigned long long *slices, int nb,
+                                                       int nn)
 {
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += gridDim.x * blockDim.x) {
-        unsigned long long s = 0;
-        for (int b = 0; b < nb; ++b) s += slices[(size_t)b * nn + g];
-        acc[g] += s;
-    }
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nn) return;
+    unsigned long long s = 0;
+    for (int b = blockIdx.y; b < nb; b += gridDim.y) s += slices[(size_t)b * nn + g];
+    atomicAdd(acc + g, s);
 }
 
 hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
                                 int nn, hipStream_t st)
 {
     int threads = 256;
-    int blocks = (nn + threads - 1) / threads;
-    hipLaunchKernelGGL(k_reduce_slices, dim3(blocks), dim3(threads), 0, st, acc, slices, nb, nn);
+    int bx = (nn + threads - 1) / threads;
+    int by = nb < 32 ? nb : 32;
+    hipLaunchKernelGGL(k_reduce_slices, dim3(bx, by), dim3(threads), 0, st, acc, slices, nb, nn);
     return hipGetLastError();
 }
 
-template hipError_t launch_dead_scan<double>(Parts<double>, const Counts *, Chunks, int,
-                                             hipStream_t);
-template hipError_t launch_dead_scan<float>(Parts<float>, const Counts *, Chunks, int, hipStream_t);
+template hipError_t launch_dead_scan<double>(Parts<double>, const Counts *, Chunks, hipStream_t);
+template hipError_t launch_dead_scan<float>(Parts<float>, const Counts *, Chunks, hipStream_t);
 template hipError_t launch_fill<double>(Parts<double>, Chunks, const FixRec *, hipStream_t);
 template hipError_t launch_fill<float>(Parts<float>, Chunks, const FixRec *, hipStream_t);
 template hipError_t launch_append<double>(Parts<double>, Parts<double>, int, Chunks, int,
                                           const ChildRec *, const FixRec *, Counts *, int64_t,
-                                          int, int32_t *, hipStream_t);
+                                          int32_t *, hipStream_t);
 template hipError_t launch_append<float>(Parts<float>, Parts<float>, int, Chunks, int,
-                                         const ChildRec *, const FixRec *, Counts *, int64_t, int,
+                                         const ChildRec *, const FixRec *, Counts *, int64_t,
                                          int32_t *, hipStream_t);
-template hipError_t launch_resize<double>(Parts<double>, Counts *, Chunks, CloneRec *, int, double,
+template hipError_t launch_resize<double>(Parts<double>, Counts *, Chunks, CloneRec *, double,
                                           double, int64_t, int32_t *, hipStream_t);
-template hipError_t launch_resize<float>(Parts<float>, Counts *, Chunks, CloneRec *, int, double,
+template hipError_t launch_resize<float>(Parts<float>, Counts *, Chunks, CloneRec *, double,
                                          double, int64_t, int32_t *, hipStream_t);
 
 }  // namespace rz

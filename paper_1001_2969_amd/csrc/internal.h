@@ -17,8 +17,8 @@ constexpr double kTwoPi = 6.283185307179586;
 
 constexpr int kMaxProc = 4;
 constexpr int kMaxLevels = 16;
-constexpr int kMinChunk = 256;   // smallest particle chunk (= pass block size)
-constexpr int kMaxChunk = 1024;  // largest particle chunk
+constexpr int kChunk = 64;       // particles per chunk: one wavefront
+constexpr int kMaxWaves = 16384; // wavefronts of a particle pass (candidate buckets)
 constexpr int kMaxLine = 2048;   // longest r-line (nr - 1 unknowns) the smoother takes
 
 // Device status bits (sticky).
@@ -37,6 +37,10 @@ enum : int {
     M_LISTS = 32,  // merged form: per-chunk dead lists built in the pass
     M_LDS = 64,    // deposit into an LDS copy of the whole grid, flushed to a slice
 };
+// The fused pass only tests for Monte Carlo candidates (M_MC): a candidate
+// keeps its final-pushed state and goes to the candidate list, where the
+// collision kernel applies the outcome and, in the merged form, its first
+// push and deposit.
 
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
@@ -103,12 +107,16 @@ struct CloneRec {     // weight split of one species
     uint64_t next_id_old;
 };
 
-struct Chunks {       // per parent species; chunk = `chunk` consecutive particles
-    int32_t *dead_cnt, *ev_cnt, *surv_e, *surv_i, *clone_cnt;
-    int32_t *dead_list;                    // [chunk*B + k] local dead indices
-    int64_t *dead_off, *ev_off, *surv_e_off, *surv_i_off, *clone_off;
-    int64_t *dead_glob;                    // sorted global dead list
-    int32_t *pcount;                       // per particle clone count (resize)
+struct Chunks {       // per parent species; chunk = 64 consecutive particles (lane = bit)
+    unsigned long long *dead;   // absorbed particles
+    unsigned long long *ev;     // ionization events (electron chunks)
+    unsigned long long *se, *si;// new electron / new ion still alive
+    int64_t *dead_off, *ev_off, *se_off, *si_off, *clone_off;
+    int32_t *clone_cnt;         // per chunk (resize)
+    int64_t *dead_glob;         // sorted global dead list
+    int32_t *pcount;            // per particle clone count (resize)
+    int32_t *cand;              // Monte Carlo candidates: per-wavefront buckets
+    int32_t *ncand;             // candidates per bucket
 };
 
 template <typename T> struct PassArgs {
@@ -128,9 +136,10 @@ template <typename T> struct PassArgs {
     unsigned long long *mcstat;   // [1 + kMaxProc] candidates, events per process
     uint8_t *ev;                  // optional per-particle event codes
     ChildRec *crec;               // electron pass records n_parent here
+    unsigned long long *psteps;   // if set: += particles entering the pass
+    int nbuckets;                 // wavefronts of the pass (= candidate buckets)
     int32_t *status;
     uint32_t step;
-    int chunk;                    // particles per chunk (staged kernels)
 };
 
 // Host-side launchers (defined in the .hip files).
@@ -138,7 +147,10 @@ template <typename T>
 hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
                        hipStream_t st);
 template <typename T>
-hipError_t launch_staged(int mode, const PassArgs<T> &a, int32_t *surv, hipStream_t st);
+hipError_t launch_collide(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
+                          hipStream_t st);
+template <typename T>
+hipError_t launch_staged(int mode, const PassArgs<T> &a, int cs, hipStream_t st);
 template <typename T>
 hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t id0, int s,
                        const Phys &phys, double m, hipStream_t st);
@@ -146,7 +158,6 @@ hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t i
 // fixup.hip: deterministic removal of absorbed particles and appending of new
 // ones (identities in parent order, independent of the launch shape).
 struct ScanJobs {
-    int chunk;
     // job 0: children of the electron pass
     int children;
     Chunks ech;
@@ -160,9 +171,8 @@ struct ScanJobs {
 };
 hipError_t launch_scan(const ScanJobs &j, hipStream_t st);
 template <typename T>
-hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, int chunk, hipStream_t st);
-hipError_t launch_dead_list(Chunks ch, const Counts *cnt, const FixRec *fix, int chunk,
-                            hipStream_t st);
+hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_t st);
+hipError_t launch_dead_list(Chunks ch, const FixRec *fix, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st);
 // Append the staged children of species `cs` (slots of electron chunks) after
@@ -170,11 +180,10 @@ hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st)
 template <typename T>
 hipError_t launch_append(Parts<T> dst, Parts<T> stage, int cs, Chunks ech, int children,
                          const ChildRec *crec, const FixRec *fix, Counts *cnt, int64_t cap,
-                         int chunk, int32_t *status, hipStream_t st);
+                         int32_t *status, hipStream_t st);
 template <typename T>
-hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, int chunk,
-                         double wcoef, double half_hr, int64_t cap, int32_t *status,
-                         hipStream_t st);
+hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, double wcoef,
+                         double half_hr, int64_t cap, int32_t *status, hipStream_t st);
 hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
                                 int nn, hipStream_t st);
 

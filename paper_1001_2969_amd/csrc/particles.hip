@@ -7,22 +7,29 @@ namespace rz {
 
 // Deposit of one particle (Sec. 2.4): N_ij += w S_z S_r, accumulated in fixed
 // point (quantum = w_ref 2^-bits) so that the sum does not depend on order.
+// Contributions must stay below 2^51 quanta (a weight below 2^11 w_ref); a
+// larger one is flagged and the step reports RZPIC_ENUMERIC.
 template <typename T>
 __device__ __forceinline__ void deposit4(unsigned long long *acc, const Mesh &m, const W4<T> &q,
-                                         double w, double inv_quantum)
+                                         double w, double inv_quantum, int32_t *status)
 {
     const double ws = w * inv_quantum;
+    if (!(fabs(ws) < 0x1p51)) atomicOr(status, kStNumeric);
     const double a = (double)q.sz0 * (double)q.sr0, b = (double)q.sz0 * (double)q.sr1;
     const double c = (double)q.sz1 * (double)q.sr0, d = (double)q.sz1 * (double)q.sr1;
-    atomicAdd(acc + q.g, (unsigned long long)__double2ll_rn(ws * a));
-    atomicAdd(acc + q.g + 1, (unsigned long long)__double2ll_rn(ws * b));
-    atomicAdd(acc + q.g + m.nr, (unsigned long long)__double2ll_rn(ws * c));
-    atomicAdd(acc + q.g + m.nr + 1, (unsigned long long)__double2ll_rn(ws * d));
+    __hip_atomic_fetch_add(acc + q.g, (unsigned long long)round_fixed(ws * a), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + q.g + 1, (unsigned long long)round_fixed(ws * b),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + q.g + m.nr, (unsigned long long)round_fixed(ws * c),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + q.g + m.nr + 1, (unsigned long long)round_fixed(ws * d),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void tally_add(unsigned long long *t, int b, double w, double inv_q)
 {
-    atomicAdd(t + b, (unsigned long long)__double2ll_rn(w * inv_q));
+    atomicAdd(t + b, (unsigned long long)round_fixed(w * inv_q));
 }
 
 template <typename T> struct PState {
@@ -110,50 +117,58 @@ __device__ __forceinline__ void store(const Parts<T> &p, int64_t i, const PState
     if (w) p.w[i] = s.w;
 }
 
-// One pass over the particles of a species.  The block processes chunks of
-// blockDim consecutive particles (grid-stride over chunks); MODE selects the
-// steps (M_* bits).  New particles of an ionization are staged at slot
-// (chunk*blockDim + event rank) with w = -1 when absorbed at birth; the
-// merged form also records each chunk's dead particles in increasing order.
+// One pass over the particles of a species.  Each wavefront processes chunks
+// of 64 consecutive particles (grid-stride over chunks, no block barrier in
+// the loop); MODE selects the steps (M_* bits).  With M_MC a particle that
+// draws U0 < P_null is a candidate: it keeps its final-pushed state, joins the
+// candidate list and skips the rest of the pass (the collision kernel takes
+// over).  The merged form records each chunk's dead particles as a lane mask.
+// With M_LDS the block deposits into its own LDS copy of the grid, written out
+// once at the end to its slice.
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
 {
     extern __shared__ unsigned long long lds_acc[];
-    __shared__ int sh_scan[64];
-    __shared__ unsigned long long sh_stat[1 + kMaxProc];
 
     const Mesh &m = a.mesh;
-    const int B = blockDim.x;
     const int64_t n = a.cnt->n;
-    const int64_t nch = (n + B - 1) / B;
+    const int64_t nch = (n + kChunk - 1) / kChunk;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const T dt = (T)a.phys.dt;
     const T k1 = (T)a.sp.k1, k2 = (T)a.sp.k2, qm = (T)a.sp.qm;
     constexpr bool kLds = (MODE & M_LDS) != 0;
     constexpr bool kDep = (MODE & M_DEP) != 0;
+    constexpr bool kMc = (MODE & M_MC) != 0;
+    const bool mc_on = kMc && a.sp.mc_model != 0;
     unsigned long long *dep = a.acc;
 
-    if (threadIdx.x < 1 + kMaxProc) sh_stat[threadIdx.x] = 0;
-    if ((MODE & M_MC) && a.crec && blockIdx.x == 0 && threadIdx.x == 0) a.crec->n_parent = n;
+    if (kMc && a.crec && blockIdx.x == 0 && threadIdx.x == 0) a.crec->n_parent = n;
+    if (a.psteps && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.psteps, (unsigned long long)n);
     if (kLds) {
-        for (int g = threadIdx.x; g < m.nn; g += B) lds_acc[g] = 0;
+        for (int g = threadIdx.x; g < m.nn; g += blockDim.x) lds_acc[g] = 0;
         dep = lds_acc;
+        __syncthreads();
     }
-    __syncthreads();
 
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int64_t pi = c * B + threadIdx.x;
+    // candidates of this wavefront go to its own bucket of the candidate list
+    const int64_t bsize = ((nch + nwaves - 1) / nwaves) * kChunk;
+    int32_t *bucket = a.ch.cand + wave * bsize;
+    int ncand = 0;
+    for (int64_t c = wave; c < nch; c += nwaves) {
+        const int64_t pi = c * kChunk + lane;
         const bool valid = pi < n;
         bool live = valid;
         PState<T> s{};
-        uint64_t id = 0;
         if (valid) {
             s = load(a.p, pi);
-            if (MODE & M_MC) id = a.p.id[pi];
             if (MODE & M_MARK) live = s.w >= (T)0;
         }
-        bool died = false;
+        bool died = false, moved = false;
         if ((MODE & M_FINAL) && live) {
             final_push<T>(s, m, a.E2, k1, k2, qm);
+            moved = true;
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
                 tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
@@ -161,29 +176,108 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
                 died = true;
             }
         }
+        bool cand = false;
+        if (kMc) {
+            if (live && mc_on) {
+                double ua, ub;
+                uniform2(a.phys.seed, a.sp.s, a.p.id[pi], a.step, 0, ua, ub);
+                cand = ua < a.sp.p_null;
+            }
+            if (valid && a.ev) a.ev[pi] = 0;
+            int tot;
+            int r = wave_rank(cand, tot);
+            if (cand) bucket[ncand + r] = (int32_t)pi;
+            ncand += tot;
+            if (lane == 0) {
+                a.ch.ev[c] = 0;
+                a.ch.se[c] = 0;
+                a.ch.si[c] = 0;
+            }
+        }
+        if ((MODE & M_FIRST) && live && !cand) {
+            first_push<T>(s, dt);
+            moved = true;
+            int b = boundary_of(s, a.phys);
+            if (b >= 0) {
+                tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
+                live = false;
+                died = true;
+            }
+        }
+        if (kDep && live && !cand)
+            deposit4<T>(dep, m, weights<T>(m, s.r, s.z), (double)s.w, a.sp.inv_quantum, a.status);
+        if (valid) {
+            if ((MODE & M_MARK) && died) a.p.w[pi] = (T)-1;
+            else if (live && moved) store(a.p, pi, s, false);
+        }
+        if (MODE & M_LISTS) {
+            unsigned long long dm = __ballot(died);
+            if (lane == 0) a.ch.dead[c] = dm;
+        }
+    }
+    if (kMc && lane == 0 && wave < a.nbuckets) a.ch.ncand[wave] = ncand;
+    if (kLds) {
+        __syncthreads();
+        unsigned long long *out = a.slices + (size_t)blockIdx.x * m.nn;
+        for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds_acc[g];
+    }
+}
+
+// Collision kernel over the candidate list (any order: every result below is
+// keyed by the particle index, combined with order-free integer atomics).
+// Applies the outcome (Sec. 2.6), records events and new particles in the
+// chunk masks and the staging slot of the parent, and with M_FIRST finishes
+// the cycle of the candidate and its new particles (first push, absorption,
+// deposit).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
+{
+    extern __shared__ unsigned long long lds_acc[];
+    __shared__ unsigned long long sh_stat[1 + kMaxProc];
+    const Mesh &m = a.mesh;
+    constexpr bool kLds = (MODE & M_LDS) != 0;
+    constexpr bool kFirst = (MODE & M_FIRST) != 0;
+    const T dt = (T)a.phys.dt;
+    unsigned long long *dep = a.acc;
+    if (threadIdx.x < 1 + kMaxProc) sh_stat[threadIdx.x] = 0;
+    if (kLds) {
+        for (int g = threadIdx.x; g < m.nn; g += blockDim.x) lds_acc[g] = 0;
+        dep = lds_acc;
+    }
+    __syncthreads();
+    // buckets of the pass that found the candidates, one wavefront per bucket
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nch = (a.cnt->n + kChunk - 1) / kChunk;
+    const int64_t bsize = ((nch + a.nbuckets - 1) / a.nbuckets) * kChunk;
+    for (int64_t b = wave; b < a.nbuckets; b += nwaves) {
+      const int nb = a.ch.ncand[b];
+      for (int j = lane; j < nb; j += kChunk) {
+        const int64_t pi = a.ch.cand[b * bsize + j];
+        const int64_t c = pi >> 6;
+        const unsigned long long bit = 1ull << (pi & 63);
+        PState<T> s = load(a.p, pi);
+        const uint64_t id = a.p.id[pi];
+        double ua, ub;
+        uniform2(a.phys.seed, a.sp.s, id, a.step, 0, ua, ub);
+        double v0 = s.vr, v1 = s.vt, v2 = s.vz;
         int iz = 0;
         Child che{}, chi{};
-        if (MODE & M_MC) {
-            int ev = 0;
-            if (live) {
-                double v0 = s.vr, v1 = s.vt, v2 = s.vz;
-                ev = collide(a.sp, a.phys, id, a.step, v0, v1, v2, iz, che, chi);
-                if (ev >= 2) {
-                    s.vr = (T)v0;
-                    s.vt = (T)v1;
-                    s.vz = (T)v2;
-                    atomicAdd(&sh_stat[1 + ev - 2], 1ull);
-                }
-                if (ev >= 1) atomicAdd(&sh_stat[0], 1ull);
-            }
-            if (valid && a.ev) a.ev[pi] = (uint8_t)ev;
+        int ev = collide_candidate(a.sp, a.phys, id, a.step, ub, v0, v1, v2, iz, che, chi);
+        if (ev >= 2) {
+            s.vr = (T)v0;
+            s.vt = (T)v1;
+            s.vz = (T)v2;
+            atomicAdd(&sh_stat[1 + ev - 2], 1ull);
         }
-        // New particles of an ionization sit at the parent's (final-pushed)
-        // position with its weight; the ion's damped acceleration is scaled
-        // by the charge-to-mass ratios.
+        atomicAdd(&sh_stat[0], 1ull);
+        if (a.ev) a.ev[pi] = (uint8_t)ev;
         PState<T> ne{}, ni{};
         bool ne_live = false, ni_live = false;
         if (iz) {
+            // new electron and ion at the parent's position with its weight;
+            // the ion's damped acceleration scaled by the charge-to-mass ratios
             ne = PState<T>{s.r, s.z, (T)che.vr, (T)che.vt, (T)che.vz, s.ar, s.az, s.w};
             ni = PState<T>{s.r,
                            s.z,
@@ -195,19 +289,18 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
                            s.w};
             ne_live = ni_live = true;
         }
-        if (MODE & M_FIRST) {
-            if (live) {
-                first_push<T>(s, dt);
-                int b = boundary_of(s, a.phys);
-                if (b >= 0) {
-                    tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
-                    live = false;
-                    died = true;
-                }
+        bool live = true;
+        if (kFirst) {
+            first_push<T>(s, dt);
+            int b = boundary_of(s, a.phys);
+            if (b >= 0) {
+                tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
+                live = false;
+                atomicOr(a.ch.dead + c, bit);
             }
             if (iz) {
                 first_push<T>(ne, dt);
-                int b = boundary_of(ne, a.phys);
+                b = boundary_of(ne, a.phys);
                 if (b >= 0) {
                     tally_add(a.tally, b, (double)ne.w, a.sp.inv_quantum);
                     ne_live = false;
@@ -219,87 +312,69 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
                     ni_live = false;
                 }
             }
-        }
-        if (kDep) {
-            if (live) deposit4<T>(dep, m, weights<T>(m, s.r, s.z), (double)s.w, a.sp.inv_quantum);
+            if (live)
+                deposit4<T>(dep, m, weights<T>(m, s.r, s.z), (double)s.w, a.sp.inv_quantum,
+                            a.status);
             if (ne_live)
-                deposit4<T>(dep, m, weights<T>(m, ne.r, ne.z), (double)ne.w, a.sp.inv_quantum);
+                deposit4<T>(dep, m, weights<T>(m, ne.r, ne.z), (double)ne.w, a.sp.inv_quantum,
+                            a.status);
             if (ni_live)
                 deposit4<T>(a.acc_ion, m, weights<T>(m, ni.r, ni.z), (double)ni.w,
-                            a.phys.ion_inv_quantum);
+                            a.phys.ion_inv_quantum, a.status);
         }
-        if (valid) {
-            if ((MODE & M_MARK) && died) {
-                a.p.w[pi] = (T)-1;
-            } else if (live && (MODE & (M_FINAL | M_MC | M_FIRST))) {
-                store(a.p, pi, s, false);
-            }
+        if (live) store(a.p, pi, s, false);
+        if (iz) {
+            PState<T> e = ne, i = ni;
+            if (!ne_live) e.w = (T)-1;
+            if (!ni_live) i.w = (T)-1;
+            store(a.ce, pi, e, true);
+            store(a.ci, pi, i, true);
+            atomicOr(a.ch.ev + c, bit);
+            if (ne_live) atomicOr(a.ch.se + c, bit);
+            if (ni_live) atomicOr(a.ch.si + c, bit);
         }
-        if (MODE & (M_LISTS | M_MC)) {
-            bool f[4] = {(bool)((MODE & M_LISTS) && died), iz != 0, ne_live, ni_live};
-            int rank[4], tot[4];
-            block_rank4(f, rank, tot, sh_scan);
-            if (MODE & M_LISTS) {
-                if (died) a.ch.dead_list[c * B + rank[0]] = threadIdx.x;
-                if (threadIdx.x == 0) a.ch.dead_cnt[c] = tot[0];
-            }
-            if (iz) {
-                int64_t slot = c * B + rank[1];
-                PState<T> e = ne, i = ni;
-                if (!ne_live) e.w = (T)-1;
-                if (!ni_live) i.w = (T)-1;
-                store(a.ce, slot, e, true);
-                store(a.ci, slot, i, true);
-            }
-            if (threadIdx.x == 0) {
-                a.ch.ev_cnt[c] = tot[1];
-                a.ch.surv_e[c] = tot[2];
-                a.ch.surv_i[c] = tot[3];
-            }
-        }
+      }
     }
     __syncthreads();
-    if (MODE & M_MC) {
-        if (threadIdx.x < 1 + kMaxProc && sh_stat[threadIdx.x])
-            atomicAdd(a.mcstat + threadIdx.x, sh_stat[threadIdx.x]);
-    }
+    if (threadIdx.x < 1 + kMaxProc && sh_stat[threadIdx.x])
+        atomicAdd(a.mcstat + threadIdx.x, sh_stat[threadIdx.x]);
     if (kLds) {
         unsigned long long *out = a.slices + (size_t)blockIdx.x * m.nn;
-        for (int g = threadIdx.x; g < m.nn; g += B) out[g] = lds_acc[g];
+        for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds_acc[g];
     }
 }
 
-// Staged new particles (unmerged form): first push or deposit of the children
-// of ionizations recorded per electron chunk.  `a.p` is the staging buffer of
-// the child species, its counts in a.ch (electron chunks), the deposit goes to
-// a.acc with the child species' quantum in a.sp.
+// Staged new particles of species cs (unmerged form): first push or deposit
+// of the children recorded in the electron chunk masks (slot = parent index).
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_staged(PassArgs<T> a, int32_t *surv)
+__global__ __launch_bounds__(256) void k_staged(PassArgs<T> a, int cs)
 {
     const Mesh &m = a.mesh;
     const T dt = (T)a.phys.dt;
-    const int B = a.chunk;
-    const int64_t nch = (a.crec->n_parent + B - 1) / B;
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        int ne = a.ch.ev_cnt[c];
-        for (int k = threadIdx.x; k < ne; k += blockDim.x) {
-            int64_t slot = c * B + k;
-            PState<T> s = load(a.p, slot);
-            if (s.w < (T)0) continue;
-            if (MODE & M_FIRST) {
-                first_push<T>(s, dt);
-                int b = boundary_of(s, a.phys);
-                if (b >= 0) {
-                    tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
-                    a.p.w[slot] = (T)-1;
-                    atomicSub(surv + c, 1);
-                    continue;
-                }
-                store(a.p, slot, s, false);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nch = (a.crec->n_parent + kChunk - 1) / kChunk;
+    unsigned long long *alive = cs == 0 ? a.ch.se : a.ch.si;
+    for (int64_t c = wave; c < nch; c += nwaves) {
+        const unsigned long long bit = 1ull << lane;
+        if (!(alive[c] & bit)) continue;
+        int64_t slot = c * kChunk + lane;
+        PState<T> s = load(a.p, slot);
+        if (MODE & M_FIRST) {
+            first_push<T>(s, dt);
+            int b = boundary_of(s, a.phys);
+            if (b >= 0) {
+                tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
+                a.p.w[slot] = (T)-1;
+                atomicAnd(alive + c, ~bit);
+                continue;
             }
-            if (MODE & M_DEP)
-                deposit4<T>(a.acc, m, weights<T>(m, s.r, s.z), (double)s.w, a.sp.inv_quantum);
+            store(a.p, slot, s, false);
         }
+        if (MODE & M_DEP)
+            deposit4<T>(a.acc, m, weights<T>(m, s.r, s.z), (double)s.w, a.sp.inv_quantum,
+                        a.status);
     }
 }
 
@@ -335,8 +410,8 @@ template <typename T>
 hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
                        hipStream_t st)
 {
-#define RZ_CASE(M)                                                              \
-    case M:                                                                     \
+#define RZ_CASE(M)                                                                     \
+    case M:                                                                            \
         hipLaunchKernelGGL((k_pass<T, M>), dim3(blocks), dim3(threads), lds, st, a); \
         break;
     switch (mode) {
@@ -359,13 +434,28 @@ hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, 
 }
 
 template <typename T>
-hipError_t launch_staged(int mode, const PassArgs<T> &a, int32_t *surv, hipStream_t st)
+hipError_t launch_collide(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
+                          hipStream_t st)
+{
+    if (mode == (M_FIRST | M_LDS))
+        hipLaunchKernelGGL((k_collide<T, M_FIRST | M_LDS>), dim3(blocks), dim3(threads), lds, st, a);
+    else if (mode == M_FIRST)
+        hipLaunchKernelGGL((k_collide<T, M_FIRST>), dim3(blocks), dim3(threads), 0, st, a);
+    else if (mode == 0)
+        hipLaunchKernelGGL((k_collide<T, 0>), dim3(blocks), dim3(threads), 0, st, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_staged(int mode, const PassArgs<T> &a, int cs, hipStream_t st)
 {
     const int blocks = 1024, threads = 256;
     if (mode == M_FIRST)
-        hipLaunchKernelGGL((k_staged<T, M_FIRST>), dim3(blocks), dim3(threads), 0, st, a, surv);
+        hipLaunchKernelGGL((k_staged<T, M_FIRST>), dim3(blocks), dim3(threads), 0, st, a, cs);
     else if (mode == M_DEP)
-        hipLaunchKernelGGL((k_staged<T, M_DEP>), dim3(blocks), dim3(threads), 0, st, a, surv);
+        hipLaunchKernelGGL((k_staged<T, M_DEP>), dim3(blocks), dim3(threads), 0, st, a, cs);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -389,8 +479,12 @@ hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t i
 template hipError_t launch_pass<double>(int, const PassArgs<double> &, int, int, size_t,
                                         hipStream_t);
 template hipError_t launch_pass<float>(int, const PassArgs<float> &, int, int, size_t, hipStream_t);
-template hipError_t launch_staged<double>(int, const PassArgs<double> &, int32_t *, hipStream_t);
-template hipError_t launch_staged<float>(int, const PassArgs<float> &, int32_t *, hipStream_t);
+template hipError_t launch_collide<double>(int, const PassArgs<double> &, int, int, size_t,
+                                           hipStream_t);
+template hipError_t launch_collide<float>(int, const PassArgs<float> &, int, int, size_t,
+                                          hipStream_t);
+template hipError_t launch_staged<double>(int, const PassArgs<double> &, int, hipStream_t);
+template hipError_t launch_staged<float>(int, const PassArgs<float> &, int, hipStream_t);
 template hipError_t launch_init<double>(Parts<double>, int64_t, double, double, uint64_t, int,
                                         const Phys &, double, hipStream_t);
 template hipError_t launch_init<float>(Parts<float>, int64_t, double, double, uint64_t, int,

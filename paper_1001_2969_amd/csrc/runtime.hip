@@ -1,7 +1,7 @@
 // Host runtime of the C ABI declared in include/rzpic.h: context and
 // configuration checks, device allocations, and the launch sequences of the
 // cycle of Sec. 2.1 on the caller's stream.
-#include "../../include/rzpic.h"
+#include "rzpic.h"
 
 #include <hip/hip_runtime.h>
 
@@ -68,7 +68,7 @@ struct rzpic_ctx {
     int device = 0, cus = 0;
     size_t lds_block = 0, lds_cu = 0;
     int mixed = 0;
-    int chunk = kMinChunk;
+    int pass_threads = 512;
     double hr = 0, hz = 0;
     int L = 0;
     int nn = 0;
@@ -100,10 +100,16 @@ struct rzpic_ctx {
     bool children_scanned = false;
     int last_cycles = 0;
     double last_relres = 0.0;
-    // timing
+    unsigned long long *psteps;  // [2]
+    // timing: per recorded step 9 events (see mark())
     bool timing = false;
-    hipEvent_t ev[5] = {};
-    double t_ms[5] = {};
+    static constexpr int kEvPerStep = 11, kPool = 128;
+    std::vector<hipEvent_t> evpool;
+    int ev_used = 0;        // steps recorded in the pool
+    double acc_ms[8] = {};  // accumulated phase times (see flush_timing)
+    double acc_cycles = 0, acc_n[2] = {0, 0};
+    int acc_steps = 0;
+    std::vector<double> step_n0, step_n1;  // per recorded step, from the pass counts
 };
 
 namespace {
@@ -248,7 +254,6 @@ template <typename T> PassArgs<T> pass_args(rzpic_ctx *c, int s, uint32_t step)
     a.crec = s == 0 ? c->crec : nullptr;
     a.status = c->status;
     a.step = step;
-    a.chunk = c->chunk;
     return a;
 }
 
@@ -284,24 +289,51 @@ __global__ void k_prep_solve(int nn, const double *rho, const double *chi, doubl
     }
 }
 
+void mark(rzpic_ctx *c, int k);
+
 // Particle pass of species s in `mode` (LDS variant chosen here).
-template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step)
+template <typename T>
+rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step, int mark_at = -1)
 {
     PassArgs<T> a = pass_args<T>(c, s, step);
-    int blocks, threads = c->chunk;
+    if (mark_at >= 0) a.psteps = c->psteps + s;
+    int blocks, threads = c->pass_threads;
     size_t lds = 0;
-    int64_t cap_chunks = (c->sp[s].cap + threads - 1) / threads;
     if ((mode & M_DEP) && c->lds_ok) {
         mode |= M_LDS;
         lds = (size_t)c->nn * sizeof(unsigned long long);
         blocks = c->slice_blocks;
     } else {
-        blocks = c->cus * 8;
+        int64_t need = (c->sp[s].cap + threads - 1) / threads;
+        blocks = c->cus * (2048 / threads);
+        if (need < blocks) blocks = (int)(need > 0 ? need : 1);
     }
-    if (cap_chunks < blocks && !(mode & M_LDS)) blocks = (int)(cap_chunks > 0 ? cap_chunks : 1);
+    const bool mc = (mode & M_MC) && a.sp.mc_model != RZPIC_MC_NONE;
     if (mode & M_MC) HIPCHK(launch_fill_u64(a.mcstat, 1 + kMaxProc, c->st));
+    a.nbuckets = blocks * (threads / 64);
+    if (a.nbuckets > kMaxWaves) return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", a.nbuckets, kMaxWaves);
+    if (mark_at >= 0) mark(c, mark_at);
     HIPCHK(launch_pass<T>(mode, a, blocks, threads, lds, c->st));
+    if (mark_at >= 0) mark(c, mark_at + 1);
     if (mode & M_LDS) HIPCHK(launch_reduce_slices(c->acc[s], c->slices, blocks, c->nn, c->st));
+    if (mc) {
+        // candidates: outcome, and in the merged form their first push and deposit
+        const bool merged = (mode & M_FIRST) != 0;
+        int cmode = merged ? M_FIRST : 0;
+        const double expect = c->sp[s].p_null * (double)c->sp[s].cap;
+        int cblocks = c->cus * 2, cthreads = 256;
+        size_t clds = 0;
+        if (merged && c->lds_ok && expect > 65536.0) {
+            cmode |= M_LDS;
+            clds = (size_t)c->nn * sizeof(unsigned long long);
+            if (cblocks > c->slice_blocks) cblocks = c->slice_blocks;
+        } else if (expect < 4096.0) {
+            cblocks = c->cus / 4 > 0 ? c->cus / 4 : 1;
+        }
+        HIPCHK(launch_collide<T>(cmode, a, cblocks, cthreads, clds, c->st));
+        if (cmode & M_LDS) HIPCHK(launch_reduce_slices(c->acc[s], c->slices, cblocks, c->nn, c->st));
+    }
+    if (mark_at >= 0) mark(c, mark_at + 2);
     return RZPIC_OK;
 }
 
@@ -315,8 +347,7 @@ template <typename T> rzpic_status run_staged(rzpic_ctx *c, int cs, int mode)
     a.acc = c->acc[cs];
     a.tally = c->tally + 3 * cs;
     a.sp = species_of(c, cs);
-    int32_t *surv = cs == 0 ? c->sp[0].ch.surv_e : c->sp[0].ch.surv_i;
-    HIPCHK(launch_staged<T>(mode, a, surv, c->st));
+    HIPCHK(launch_staged<T>(mode, a, cs, c->st));
     return RZPIC_OK;
 }
 
@@ -324,7 +355,6 @@ template <typename T> rzpic_status run_staged(rzpic_ctx *c, int cs, int mode)
 template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
 {
     ScanJobs j{};
-    j.chunk = c->chunk;
     j.children = (c->children_pending[0] || c->children_pending[1]) && !c->children_scanned;
     j.ech = c->sp[0].ch;
     j.ecnt = c->cnt;
@@ -339,15 +369,15 @@ template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
     HIPCHK(launch_scan(j, c->st));
     if (j.children) c->children_scanned = true;
     for (int s = 0; s < 2; ++s)
-        if ((which >> s) & 1) HIPCHK(launch_dead_list(c->sp[s].ch, c->cnt + s, c->fix + s, c->chunk, c->st));
+        if ((which >> s) & 1) HIPCHK(launch_dead_list(c->sp[s].ch, c->fix + s, c->st));
     for (int s = 0; s < 2; ++s)
         if ((which >> s) & 1) HIPCHK(launch_fill<T>(parts_of<T>(c->sp[s].v), c->sp[s].ch, c->fix + s, c->st));
     for (int s = 0; s < 2; ++s) {
         if (!((which >> s) & 1)) continue;
         int kids = c->children_pending[s] ? 1 : 0;
         HIPCHK(launch_append<T>(parts_of<T>(c->sp[s].v), stage_of<T>(c, s), s, c->sp[0].ch, kids,
-                                c->crec, c->fix + s, c->cnt + s, c->sp[s].cap, c->chunk,
-                                c->status, c->st));
+                                c->crec, c->fix + s, c->cnt + s, c->sp[s].cap, c->status,
+                                c->st));
         c->children_pending[s] = false;
     }
     if (!c->children_pending[0] && !c->children_pending[1]) c->children_scanned = false;
@@ -474,14 +504,44 @@ template <typename T> rzpic_status deposit_impl(rzpic_ctx *c)
 template <typename T> rzpic_status resize_impl(rzpic_ctx *c, int s)
 {
     HIPCHK(launch_resize<T>(parts_of<T>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->clrec + s,
-                            c->chunk, c->c.resize_wcoef, 0.5 * c->hr, c->sp[s].cap, c->status,
-                            c->st));
+                            c->c.resize_wcoef, 0.5 * c->hr, c->sp[s].cap, c->status, c->st));
     return RZPIC_OK;
 }
 
-void tic(rzpic_ctx *c, int k)
+// Timing marks of one step: 0 start, 1 after finalize, 2 after solve,
+// 3 after E, 4/5 around the electron pass kernel, 6 after its collisions,
+// 7/8 around the ion pass kernel, 9 after its collisions, 10 end.
+rzpic_status flush_timing(rzpic_ctx *c);
+
+void mark(rzpic_ctx *c, int k)
 {
-    if (c->timing) (void)hipEventRecord(c->ev[k], c->st);
+    if (!c->timing || c->ev_used >= rzpic_ctx::kPool) return;
+    (void)hipEventRecord(c->evpool[(size_t)c->ev_used * rzpic_ctx::kEvPerStep + k], c->st);
+}
+
+rzpic_status flush_timing(rzpic_ctx *c)
+{
+    if (c->ev_used == 0) return RZPIC_OK;
+    const int E = rzpic_ctx::kEvPerStep;
+    HIPCHK(hipEventSynchronize(c->evpool[(size_t)(c->ev_used - 1) * E + E - 1]));
+    auto el = [&](hipEvent_t a, hipEvent_t b) {
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, a, b);
+        return (double)t;
+    };
+    for (int st = 0; st < c->ev_used; ++st) {
+        hipEvent_t *e = &c->evpool[(size_t)st * E];
+        c->acc_ms[0] += el(e[0], e[10]);
+        c->acc_ms[1] += el(e[1], e[2]);
+        c->acc_ms[2] += el(e[4], e[5]);
+        c->acc_ms[3] += el(e[7], e[8]);
+        c->acc_ms[4] += el(e[0], e[1]) + el(e[2], e[3]);
+        c->acc_ms[5] += el(e[6], e[7]) + el(e[9], e[10]);
+        c->acc_ms[6] += el(e[5], e[6]) + el(e[8], e[9]);
+    }
+    c->acc_steps += c->ev_used;
+    c->ev_used = 0;
+    return RZPIC_OK;
 }
 
 template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
@@ -489,36 +549,27 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
     TRY(need_both(c));
     if (c->children_pending[0] || c->children_pending[1])
         return fail(RZPIC_ESTATE, "new particles are staged: call rzpic_compact first");
-    tic(c, 0);
+    if (c->timing && c->ev_used >= rzpic_ctx::kPool) TRY(flush_timing(c));
+    mark(c, 0);
     TRY(finalize_impl(c, 1));
+    mark(c, 1);
     TRY(solve_impl(c, (double)(n + 1) * c->c.dt, true, nullptr, nullptr));
+    c->acc_cycles += c->last_cycles;
+    mark(c, 2);
     TRY(efield_impl(c));
-    tic(c, 1);
+    mark(c, 3);
     const int fused = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS;
-    for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, fused, (uint32_t)n));
+    for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, fused, (uint32_t)n, 4 + 3 * s));
     c->children_pending[0] = c->children_pending[1] = c->sp[0].v.mc_model == RZPIC_MC_ELECTRON;
     c->children_scanned = false;
-    tic(c, 2);
     TRY(run_fixup<T>(c, 3));
     if (c->c.resize_every > 0 && n % c->c.resize_every == c->c.resize_every - 1) {
         for (int s = 0; s < 2; ++s) TRY(resize_impl<T>(c, s));
         for (int s = 0; s < 2; ++s) HIPCHK(launch_fill_u64(c->acc[s], c->nn, c->st));
         for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, M_DEP, 0));
     }
-    tic(c, 3);
-    if (c->timing) {
-        HIPCHK(hipEventSynchronize(c->ev[3]));
-        float a, b, d, e;
-        (void)hipEventElapsedTime(&a, c->ev[0], c->ev[3]);
-        (void)hipEventElapsedTime(&b, c->ev[0], c->ev[1]);
-        (void)hipEventElapsedTime(&d, c->ev[1], c->ev[2]);
-        (void)hipEventElapsedTime(&e, c->ev[2], c->ev[3]);
-        c->t_ms[0] = a;
-        c->t_ms[1] = b;
-        c->t_ms[2] = d;
-        c->t_ms[3] = e;
-        c->t_ms[4] = c->last_cycles;
-    }
+    mark(c, 10);
+    if (c->timing) c->ev_used++;
     return RZPIC_OK;
 }
 
@@ -590,9 +641,9 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     c->lds_block = (size_t)v;
     (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device);
     c->lds_cu = v > 0 ? (size_t)v : c->lds_block;
-    if (const char *e = std::getenv("RZPIC_CHUNK")) {
-        int ch = std::atoi(e);
-        if (ch == 256 || ch == 512 || ch == 1024) c->chunk = ch;
+    if (const char *e = std::getenv("RZPIC_PASS_THREADS")) {
+        int t = std::atoi(e);
+        if (t == 256 || t == 512 || t == 1024) c->pass_threads = t;
     }
     const size_t nn = (size_t)c->nn;
     rzpic_status s;
@@ -607,13 +658,15 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     }
     A(c->acc[0], nn) A(c->acc[1], nn) A(c->inv2j1, (size_t)k.nr) A(c->inv2j1f, (size_t)k.nr)
     A(c->cnt, 2) A(c->fix, 2) A(c->crec, 1) A(c->clrec, 2) A(c->tally, 6)
-    A(c->mcstat, 2 * (1 + kMaxProc)) A(c->norm, 2) A(c->status, 1)
+    A(c->mcstat, 2 * (1 + kMaxProc)) A(c->norm, 2) A(c->status, 1) A(c->psteps, 2)
     // LDS privatisation of the whole deposit grid when it fits.
     const size_t lds_need = nn * sizeof(unsigned long long) + 1024;
     if (lds_need <= c->lds_block && !std::getenv("RZPIC_NO_LDS")) {
+        // blocks per CU: as many as LDS allows up to the 32-wave limit
         int per_cu = (int)(c->lds_cu / lds_need);
+        int wave_cap = 2048 / c->pass_threads;
         if (per_cu < 1) per_cu = 1;
-        if (per_cu > 4) per_cu = 4;
+        if (per_cu > wave_cap) per_cu = wave_cap;
         c->slice_blocks = c->cus * per_cu;
         if (const char *e = std::getenv("RZPIC_SLICE_BLOCKS")) {
             int b = std::atoi(e);
@@ -672,7 +725,6 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         hipMemcpy(c->inv2j1f, invf.data(), k.nr * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->vol, vol.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(RZPIC_EHIP, "table upload failed"));
-    for (int e = 0; e < 5; ++e) (void)hipEventCreate(&c->ev[e]);
     *out = c;
     return RZPIC_OK;
 }
@@ -689,8 +741,7 @@ rzpic_status rzpic_destroy(rzpic_ctx *c)
                 if (c->sp[s].stage[a][f]) (void)hipFree(c->sp[s].stage[a][f]);
         if (c->sp[s].sigma.p) (void)hipFree(c->sp[s].sigma.p);
     }
-    for (int e = 0; e < 5; ++e)
-        if (c->ev[e]) (void)hipEventDestroy(c->ev[e]);
+    for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     delete c;
     return RZPIC_OK;
 }
@@ -708,7 +759,7 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
     if (s < 0 || s > 1) return fail(RZPIC_EINVAL, "species %d out of range", s);
     if (!v->r || !v->z || !v->vr || !v->vt || !v->vz || !v->ar || !v->az || !v->w || !v->id)
         return fail(RZPIC_EINVAL, "species %d: null particle array", s);
-    if (v->capacity < 1 || v->capacity > ((int64_t)1 << 31) - kMaxChunk)
+    if (v->capacity < 1 || v->capacity > ((int64_t)1 << 31) - kChunk)
         return fail(RZPIC_EINVAL, "species %d: capacity %lld out of range", s, (long long)v->capacity);
     if (!(v->m > 0) || !(v->w_ref > 0))
         return fail(RZPIC_EINVAL, "species %d: need m > 0 and w_ref > 0", s);
@@ -728,17 +779,17 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
     ss.cap = v->capacity;
     ss.bound = true;
     c->quantum[s] = v->w_ref * std::ldexp(1.0, -c->c.fixed_point_bits);
-    const int64_t nch = (v->capacity + kMinChunk - 1) / kMinChunk + 1;
+    const int64_t nch = (v->capacity + kChunk - 1) / kChunk + 1;
     ss.nchunks_max = nch;
-    const size_t cap = (size_t)v->capacity + kMaxChunk;  // slots of the last chunk
+    const size_t cap = (size_t)v->capacity + kChunk;  // slots of the last chunk
     rzpic_status st;
 #define A(p, n)                                   \
     if ((st = dalloc(c, &(p), (n))) != RZPIC_OK) \
         return st;
-    A(ss.ch.dead_cnt, nch) A(ss.ch.ev_cnt, nch) A(ss.ch.surv_e, nch) A(ss.ch.surv_i, nch)
-    A(ss.ch.clone_cnt, nch) A(ss.ch.dead_list, cap) A(ss.ch.dead_off, nch) A(ss.ch.ev_off, nch)
-    A(ss.ch.surv_e_off, nch) A(ss.ch.surv_i_off, nch) A(ss.ch.clone_off, nch)
-    A(ss.ch.dead_glob, cap) A(ss.ch.pcount, cap)
+    A(ss.ch.dead, nch) A(ss.ch.ev, nch) A(ss.ch.se, nch) A(ss.ch.si, nch)
+    A(ss.ch.clone_cnt, nch) A(ss.ch.dead_off, nch) A(ss.ch.ev_off, nch)
+    A(ss.ch.se_off, nch) A(ss.ch.si_off, nch) A(ss.ch.clone_off, nch)
+    A(ss.ch.dead_glob, cap) A(ss.ch.pcount, cap) A(ss.ch.cand, cap + (size_t)kChunk * (kMaxWaves + 1)) A(ss.ch.ncand, kMaxWaves)
 #undef A
     if (s == 0 && v->mc_model == RZPIC_MC_ELECTRON) {
         size_t es = c->mixed ? sizeof(float) : sizeof(double);
@@ -903,6 +954,17 @@ rzpic_status rzpic_solve(rzpic_ctx *c, double t, int32_t *cycles, double *relres
     return solve_impl(c, t, false, cycles, relres);
 }
 
+rzpic_status rzpic_set_mg(rzpic_ctx *c, double tol, int32_t max_cycles, int32_t fixed_cycles)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (fixed_cycles < 0 || (fixed_cycles == 0 && (max_cycles < 1 || !(tol > 0))))
+        return fail(RZPIC_EINVAL, "need fixed_cycles > 0, or max_cycles >= 1 and tol > 0");
+    c->c.mg_tol = tol;
+    c->c.mg_max_cycles = max_cycles;
+    c->c.mg_fixed_cycles = fixed_cycles;
+    return RZPIC_OK;
+}
+
 rzpic_status rzpic_efield(rzpic_ctx *c)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
@@ -915,10 +977,10 @@ rzpic_status rzpic_compact(rzpic_ctx *c, int32_t s)
     if (s == 1 && c->children_pending[1] && !c->sp[0].bound)
         return fail(RZPIC_ESTATE, "species 0 must stay bound while new ions are staged");
     if (c->mixed) {
-        HIPCHK(launch_dead_scan<float>(parts_of<float>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->chunk, c->st));
+        HIPCHK(launch_dead_scan<float>(parts_of<float>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->st));
         TRY(run_fixup<float>(c, 1 << s));
     } else {
-        HIPCHK(launch_dead_scan<double>(parts_of<double>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->chunk, c->st));
+        HIPCHK(launch_dead_scan<double>(parts_of<double>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->st));
         TRY(run_fixup<double>(c, 1 << s));
     }
     return RZPIC_OK;
@@ -1032,6 +1094,10 @@ rzpic_status rzpic_get_diag(rzpic_ctx *c, rzpic_diag *out)
         out->candidates[s] = (int64_t)ms[(1 + kMaxProc) * s];
         for (int k = 0; k < kMaxProc; ++k) out->events[s][k] = (int64_t)ms[(1 + kMaxProc) * s + 1 + k];
     }
+    unsigned long long ps[2];
+    HIPCHK(hipMemcpy(ps, c->psteps, sizeof ps, hipMemcpyDeviceToHost));
+    out->particle_steps[0] = ps[0];
+    out->particle_steps[1] = ps[1];
     out->last_cycles = c->last_cycles;
     out->last_relres = c->last_relres;
     out->status = stw & kStCapacity ? RZPIC_ECAPACITY : (stw ? RZPIC_ENUMERIC : RZPIC_OK);
@@ -1041,14 +1107,39 @@ rzpic_status rzpic_get_diag(rzpic_ctx *c, rzpic_diag *out)
 rzpic_status rzpic_set_timing(rzpic_ctx *c, int32_t enable)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (enable && c->evpool.empty()) {
+        c->evpool.resize((size_t)rzpic_ctx::kPool * rzpic_ctx::kEvPerStep);
+        for (auto &e : c->evpool) HIPCHK(hipEventCreate(&e));
+    }
+    if (!enable) TRY(flush_timing(c));
     c->timing = enable != 0;
     return RZPIC_OK;
 }
 
-rzpic_status rzpic_get_timing(rzpic_ctx *c, double out[5])
+rzpic_status rzpic_get_timing(rzpic_ctx *c, double out[11])
 {
     if (!c || !out) return fail(RZPIC_EINVAL, "null argument");
-    for (int k = 0; k < 5; ++k) out[k] = c->t_ms[k];
+    TRY(flush_timing(c));
+    unsigned long long ps[2];
+    HIPCHK(hipMemcpyAsync(ps, c->psteps, sizeof ps, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    const double k = c->acc_steps > 0 ? (double)c->acc_steps : 1.0;
+    out[0] = c->acc_steps;
+    out[1] = c->acc_ms[0] / k;
+    out[2] = c->acc_ms[1] / k;
+    out[3] = c->acc_cycles / k;
+    out[4] = c->acc_ms[2] / k;
+    out[5] = c->acc_ms[3] / k;
+    out[6] = c->acc_ms[4] / k;
+    out[7] = c->acc_ms[5] / k;
+    out[8] = ((double)ps[0] - c->acc_n[0]) / k;
+    out[9] = ((double)ps[1] - c->acc_n[1]) / k;
+    out[10] = c->acc_ms[6] / k;
+    c->acc_n[0] = (double)ps[0];
+    c->acc_n[1] = (double)ps[1];
+    for (double &v : c->acc_ms) v = 0.0;
+    c->acc_cycles = 0;
+    c->acc_steps = 0;
     return RZPIC_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = (
     "rzpic_push_first", "rzpic_deposit", "rzpic_solve", "rzpic_efield", "rzpic_push_final",
     "rzpic_collide", "rzpic_compact", "rzpic_resize", "rzpic_prologue", "rzpic_step",
     "rzpic_grid_copy", "rzpic_get_diag", "rzpic_sync", "rzpic_last_error", "rzpic_constants",
-    "rzpic_set_timing", "rzpic_get_timing",
+    "rzpic_set_timing", "rzpic_get_timing", "rzpic_set_mg",
 )
 
 
@@ -63,7 +63,7 @@ class Diag(C.Structure):
         ("count", C.c_int64 * 2), ("next_id", C.c_uint64 * 2),
         ("absorbed", (C.c_double * 3) * 2), ("candidates", C.c_int64 * 2),
         ("events", (C.c_int64 * 4) * 2), ("last_cycles", C.c_int32), ("status", C.c_int32),
-        ("last_relres", C.c_double),
+        ("last_relres", C.c_double), ("particle_steps", C.c_uint64 * 2),
     ]
 
 
@@ -96,6 +96,7 @@ def lib():
             "rzpic_step": [P, C.c_int64], "rzpic_grid_copy": [P, I, P, I],
             "rzpic_get_diag": [P, C.POINTER(Diag)], "rzpic_sync": [P],
             "rzpic_set_timing": [P, I], "rzpic_get_timing": [P, P],
+            "rzpic_set_mg": [P, D, I, I],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -255,6 +256,9 @@ class Context:
         _check(lib().rzpic_solve(self.h, t, C.byref(cyc), C.byref(rr)))
         return cyc.value, rr.value
 
+    def set_mg(self, tol=1e-10, max_cycles=100, fixed_cycles=0):
+        _check(lib().rzpic_set_mg(self.h, tol, max_cycles, fixed_cycles))
+
     def step(self, n):
         _check(lib().rzpic_step(self.h, n))
 
@@ -280,7 +284,8 @@ class Context:
         out = {"count": list(d.count), "next_id": list(d.next_id),
                "absorbed": [list(d.absorbed[s]) for s in range(2)],
                "candidates": list(d.candidates), "events": [list(d.events[s]) for s in range(2)],
-               "last_cycles": d.last_cycles, "last_relres": d.last_relres, "status": d.status}
+               "last_cycles": d.last_cycles, "last_relres": d.last_relres, "status": d.status,
+               "particle_steps": list(d.particle_steps)}
         if code:
             _check(code)
         return out
@@ -289,9 +294,12 @@ class Context:
         _check(lib().rzpic_set_timing(self.h, 1 if on else 0))
 
     def timing(self):
-        out = (C.c_double * 5)()
+        """Averages per recorded step (see rzpic_get_timing)."""
+        out = (C.c_double * 11)()
         _check(lib().rzpic_get_timing(self.h, C.cast(out, C.c_void_p)))
-        return list(out)
+        keys = ("steps", "step_ms", "solve_ms", "vcycles", "pass0_ms", "pass1_ms",
+                "grid_ms", "lists_ms", "n0", "n1", "collide_ms")
+        return dict(zip(keys, list(out)))
 
 
 def make_context(w, *, capacity_factor=1.6, events=False, with_xsec=True, **kw):

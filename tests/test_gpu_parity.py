@@ -308,3 +308,30 @@ def test_capacity_overflow_is_reported_and_state_stays_consistent():
         assert n <= g.capacity[s]
         p = g.particles(s)
         assert len(np.unique(p["id"])) == n and np.all(p["w"] > 0)
+
+
+def test_results_do_not_depend_on_the_launch_shape(monkeypatch):
+    """Block size of the particle pass and the number of LDS slices change the
+    order in which atomics land, never the particles or the grids."""
+    w = _small(n_per_species=9000)
+    st = random_state(w, 18)
+    outs = []
+    for threads, slices in (("1024", None), ("256", "37"), ("512", "300")):
+        monkeypatch.setenv("RZPIC_PASS_THREADS", threads)
+        if slices:
+            monkeypatch.setenv("RZPIC_SLICE_BLOCKS", slices)
+        else:
+            monkeypatch.delenv("RZPIC_SLICE_BLOCKS", raising=False)
+        g = rzpic.make_context(w)
+        for s, (p, nid) in st.items():
+            g.set_particles(s, p, nid)
+        g.prologue()
+        for n in range(3):
+            g.step(n)
+        outs.append([g.particles(s) for s in (0, 1)] + [g.grid(rzpic.G_PHI), g.grid(rzpic.G_N0)])
+    for o in outs[1:]:
+        for s in (0, 1):
+            for f in rzo.FIELDS + ("id",):
+                np.testing.assert_array_equal(outs[0][s][f], o[s][f])
+        np.testing.assert_array_equal(outs[0][2], o[2])
+        np.testing.assert_array_equal(outs[0][3], o[3])
