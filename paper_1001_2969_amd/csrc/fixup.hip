@@ -7,17 +7,9 @@
 
 namespace rz {
 
-__device__ __forceinline__ int count_of(const int32_t *in, int64_t i) { return in[i]; }
-__device__ __forceinline__ int count_of(const unsigned long long *in, int64_t i)
-{
-    return __popcll(in[i]);
-}
-
-// Exclusive scan of the counts of in[0..n) (ints, or the set bits of lane
-// masks) into out[] by one block of 1024 threads, 8 consecutive items per
-// thread per tile; returns the total.
-template <typename C>
-__device__ int64_t block_scan_tiles(const C *in, int64_t *out, int64_t n, int *sh)
+// Exclusive scan of in[0..n) into out[] by one block of 1024 threads, 8
+// consecutive items per thread per tile; returns the total (weight split).
+__device__ int64_t block_scan_tiles(const int32_t *in, int64_t *out, int64_t n, int *sh)
 {
     constexpr int kItems = 8;
     int64_t carry = 0;
@@ -28,7 +20,7 @@ __device__ int64_t block_scan_tiles(const C *in, int64_t *out, int64_t n, int *s
         int sum = 0;
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
-            v[k] = i0 + k < n ? count_of(in, i0 + k) : 0;
+            v[k] = i0 + k < n ? in[i0 + k] : 0;
             sum += v[k];
         }
         int tot;
@@ -44,39 +36,110 @@ __device__ int64_t block_scan_tiles(const C *in, int64_t *out, int64_t n, int *s
     return carry;
 }
 
-__global__ __launch_bounds__(1024) void k_scan(ScanJobs j)
+// Sum over the block of one value per thread (all threads must call).
+__device__ __forceinline__ int64_t block_sum64(int64_t v, int64_t *sh)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    int64_t t = 0;
+    for (int w = 0; w < nw; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// Sum of sc[0..upto) by the whole block.
+__device__ __forceinline__ int64_t prefix_of(const int32_t *sc, int64_t upto, int64_t *sh)
+{
+    int64_t v = 0;
+    for (int64_t k = threadIdx.x; k < upto; k += blockDim.x) v += sc[k];
+    return block_sum64(v, sh);
+}
+
+// Superchunk totals: block (sc, 0) sums the children masks of its 512
+// electron chunks, blocks (sc, 1 + s) the dead masks of species s.
+__global__ __launch_bounds__(kSuper) void k_scan(ScanJobs j)
 {
     __shared__ int sh[64];
-    if (blockIdx.x == 0) {
+    const int job = blockIdx.y;
+    const int64_t sc = blockIdx.x;
+    const int64_t c = sc * kSuper + threadIdx.x;
+    int tot;
+    if (job == 0) {
         if (!j.children) return;
-        const int64_t nch = (j.crec->n_parent + kChunk - 1) / kChunk;
-        int64_t ev = block_scan_tiles(j.ech.ev, j.ech.ev_off, nch, sh);
-        int64_t se = block_scan_tiles(j.ech.se, j.ech.se_off, nch, sh);
-        int64_t si = block_scan_tiles(j.ech.si, j.ech.si_off, nch, sh);
-        if (threadIdx.x == 0) {
-            j.crec->ev_total = ev;
-            j.crec->surv_total[0] = se;
-            j.crec->surv_total[1] = si;
+        if (sc == 0 && threadIdx.x == 0) {
             j.crec->next_id_old[0] = j.ecnt->next_id;
             j.crec->next_id_old[1] = j.icnt->next_id;
         }
+        const int64_t nch = (j.crec->n_parent + kChunk - 1) / kChunk;
+        if (sc * kSuper >= nch) return;
+        const bool in = c < nch;
+        block_excl_sum(in ? __popcll(j.ech.ev[c]) : 0, tot, sh);
+        if (threadIdx.x == 0) j.ech.sc_ev[sc] = tot;
+        block_excl_sum(in ? __popcll(j.ech.se[c]) : 0, tot, sh);
+        if (threadIdx.x == 0) j.ech.sc_se[sc] = tot;
+        block_excl_sum(in ? __popcll(j.ech.si[c]) : 0, tot, sh);
+        if (threadIdx.x == 0) j.ech.sc_si[sc] = tot;
         return;
     }
-    const int s = blockIdx.x - 1;
+    const int s = job - 1;
     if (!j.dead[s]) return;
+    const int64_t nch = (j.cnt[s]->n + kChunk - 1) / kChunk;
+    if (sc * kSuper >= nch && sc > 0) return;
+    block_excl_sum(c < nch ? __popcll(j.ch[s].dead[c]) : 0, tot, sh);
+    if (threadIdx.x == 0) j.ch[s].sc_dead[sc] = tot;
+}
+
+hipError_t launch_scan(const ScanJobs &j, int64_t max_chunks, hipStream_t st)
+{
+    int64_t nsc = (max_chunks + kSuper - 1) / kSuper;
+    if (nsc < 1) nsc = 1;
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)nsc, 3), dim3(kSuper), 0, st, j);
+    return hipGetLastError();
+}
+
+// Sorted dead list of species blockIdx.y: superchunk prefix + the in-block
+// scan of the chunk counts give each chunk's offset; its set lanes follow in
+// increasing order.  Block (0, s) records n, the dead total and the kept count.
+__global__ __launch_bounds__(kSuper) void k_dead_list(ScanJobs j)
+{
+    __shared__ int sh[64];
+    __shared__ int64_t sh64[16];
+    const int s = blockIdx.y;
+    if (!j.dead[s]) return;
+    const int64_t sc = blockIdx.x;
     const int64_t n = j.cnt[s]->n;
     const int64_t nch = (n + kChunk - 1) / kChunk;
-    int64_t d = block_scan_tiles(j.ch[s].dead, j.ch[s].dead_off, nch, sh);
-    if (threadIdx.x == 0) {
-        j.fix[s]->n_old = n;
-        j.fix[s]->dead = d;
-        j.fix[s]->keep = n - d;
+    const int64_t nsc = (nch + kSuper - 1) / kSuper;
+    const Chunks &ch = j.ch[s];
+    if (sc == 0) {
+        int64_t D = prefix_of(ch.sc_dead, nsc, sh64);
+        if (threadIdx.x == 0) {
+            j.fix[s]->n_old = n;
+            j.fix[s]->dead = D;
+            j.fix[s]->keep = n - D;
+        }
+    }
+    if (sc >= nsc) return;
+    const int64_t base = prefix_of(ch.sc_dead, sc, sh64);
+    const int64_t c = sc * kSuper + threadIdx.x;
+    unsigned long long m = c < nch ? ch.dead[c] : 0ull;
+    int tot;
+    int64_t off = base + block_excl_sum(__popcll(m), tot, sh);
+    while (m) {
+        int lane = __ffsll((long long)m) - 1;
+        ch.dead_glob[off++] = c * kChunk + lane;
+        m &= m - 1;
     }
 }
 
-hipError_t launch_scan(const ScanJobs &j, hipStream_t st)
+hipError_t launch_dead_list(const ScanJobs &j, int64_t max_chunks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, st, j);
+    int64_t nsc = (max_chunks + kSuper - 1) / kSuper;
+    if (nsc < 1) nsc = 1;
+    hipLaunchKernelGGL(k_dead_list, dim3((unsigned)nsc, 2), dim3(kSuper), 0, st, j);
     return hipGetLastError();
 }
 
@@ -99,27 +162,6 @@ template <typename T>
 hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_t st)
 {
     hipLaunchKernelGGL((k_dead_scan<T>), dim3(1024), dim3(256), 0, st, p.w, cnt, ch);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_dead_list(Chunks ch, const FixRec *fix)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t nch = (fix->n_old + kChunk - 1) / kChunk;
-    if (fix->dead == 0) return;
-    const unsigned long long below = (1ull << lane) - 1;
-    for (int64_t c = wave; c < nch; c += nwaves) {
-        unsigned long long dm = ch.dead[c];
-        if ((dm >> lane) & 1)
-            ch.dead_glob[ch.dead_off[c] + __popcll(dm & below)] = c * kChunk + lane;
-    }
-}
-
-hipError_t launch_dead_list(Chunks ch, const FixRec *fix, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_dead_list, dim3(1024), dim3(256), 0, st, ch, fix);
     return hipGetLastError();
 }
 
@@ -165,63 +207,92 @@ hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st)
     return hipGetLastError();
 }
 
+// Append of the staged children of species blockIdx.y after its kept
+// particles: the survivor and event offsets of each electron chunk come from
+// the superchunk prefix and an in-block scan; slot = parent index, identity =
+// next identity + event rank.  Block (0, cs) commits the count and identity.
+template <typename T> struct AppendArgs {
+    Parts<T> dst[2], stage[2];
+    Counts *cnt[2];
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_append(Parts<T> dst, Parts<T> stage, int cs, Chunks ech,
-                                                int children, const ChildRec *crec,
-                                                const FixRec *fix, Counts *cnt, int64_t cap,
-                                                int32_t *status)
+__global__ __launch_bounds__(kSuper) void k_append(ScanJobs j, AppendArgs<T> g)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t keep = fix->keep;
-    if (children) {
-        const int64_t *surv_off = cs == 0 ? ech.se_off : ech.si_off;
-        const unsigned long long *alive = cs == 0 ? ech.se : ech.si;
-        const uint64_t id0 = crec->next_id_old[cs];
-        const int64_t nch = (crec->n_parent + kChunk - 1) / kChunk;
-        const unsigned long long below = (1ull << lane) - 1;
-        for (int64_t c = wave; c < nch; c += nwaves) {
-            const unsigned long long am = alive[c];
-            if (!((am >> lane) & 1)) continue;
-            const int64_t slot = c * kChunk + lane;
-            const int64_t to = keep + surv_off[c] + __popcll(am & below);
-            if (to < cap) {
-                dst.r[to] = stage.r[slot];
-                dst.z[to] = stage.z[slot];
-                dst.vr[to] = stage.vr[slot];
-                dst.vt[to] = stage.vt[slot];
-                dst.vz[to] = stage.vz[slot];
-                dst.ar[to] = stage.ar[slot];
-                dst.az[to] = stage.az[slot];
-                dst.w[to] = stage.w[slot];
-                dst.id[to] = id0 + (uint64_t)(ech.ev_off[c] + __popcll(ech.ev[c] & below));
-            }
-        }
+    __shared__ int sh[64];
+    __shared__ int64_t sh64[16];
+    const int cs = blockIdx.y;
+    if (!j.dead[cs]) return;
+    const int64_t sc = blockIdx.x;
+    const int64_t keep = j.fix[cs]->keep;
+    const int64_t cap = j.cap[cs];
+    const bool kids = j.kids[cs] != 0;
+    int64_t nch = 0, nsc = 0;
+    const int32_t *sc_alive = cs == 0 ? j.ech.sc_se : j.ech.sc_si;
+    if (kids) {
+        nch = (j.crec->n_parent + kChunk - 1) / kChunk;
+        nsc = (nch + kSuper - 1) / kSuper;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        int64_t n_new = keep;
-        if (children) {
-            int64_t surv = crec->surv_total[cs];
-            int64_t room = cap - keep;
+    if (sc == 0) {
+        int64_t surv = kids ? prefix_of(sc_alive, nsc, sh64) : 0;
+        int64_t evs = kids ? prefix_of(j.ech.sc_ev, nsc, sh64) : 0;
+        if (threadIdx.x == 0) {
+            const int64_t room = cap - keep;
             if (surv > room) {
-                atomicOr(status, kStCapacity);
+                atomicOr(j.status, kStCapacity);
                 surv = room;
             }
-            n_new += surv;
-            cnt->next_id = crec->next_id_old[cs] + (uint64_t)crec->ev_total;
+            g.cnt[cs]->n = keep + surv;
+            if (kids) g.cnt[cs]->next_id = j.crec->next_id_old[cs] + (uint64_t)evs;
         }
-        cnt->n = n_new;
+    }
+    if (!kids || sc >= nsc) return;
+    const unsigned long long *alive = cs == 0 ? j.ech.se : j.ech.si;
+    const int64_t sbase = prefix_of(sc_alive, sc, sh64);
+    const int64_t ebase = prefix_of(j.ech.sc_ev, sc, sh64);
+    const int64_t c = sc * kSuper + threadIdx.x;
+    const unsigned long long am = c < nch ? alive[c] : 0ull;
+    const unsigned long long em = c < nch ? j.ech.ev[c] : 0ull;
+    int tot;
+    const int64_t soff = sbase + block_excl_sum(__popcll(am), tot, sh);
+    const int64_t eoff = ebase + block_excl_sum(__popcll(em), tot, sh);
+    const uint64_t id0 = j.crec->next_id_old[cs];
+    const Parts<T> &dst = g.dst[cs], &stage = g.stage[cs];
+    unsigned long long m = am;
+    int64_t k = 0;
+    while (m) {
+        const int lane = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const int64_t slot = c * kChunk + lane;
+        const int64_t to = keep + soff + k++;
+        if (to >= cap) continue;
+        dst.r[to] = stage.r[slot];
+        dst.z[to] = stage.z[slot];
+        dst.vr[to] = stage.vr[slot];
+        dst.vt[to] = stage.vt[slot];
+        dst.vz[to] = stage.vz[slot];
+        dst.ar[to] = stage.ar[slot];
+        dst.az[to] = stage.az[slot];
+        dst.w[to] = stage.w[slot];
+        dst.id[to] = id0 + (uint64_t)(eoff + __popcll(em & ((1ull << lane) - 1)));
     }
 }
 
 template <typename T>
-hipError_t launch_append(Parts<T> dst, Parts<T> stage, int cs, Chunks ech, int children,
-                         const ChildRec *crec, const FixRec *fix, Counts *cnt, int64_t cap,
-                         int32_t *status, hipStream_t st)
+hipError_t launch_append(const ScanJobs &j, Parts<T> dst0, Parts<T> dst1, Parts<T> stage0,
+                         Parts<T> stage1, Counts *cnt0, Counts *cnt1, int64_t max_chunks,
+                         hipStream_t st)
 {
-    hipLaunchKernelGGL((k_append<T>), dim3(children ? 1024 : 1), dim3(256), 0, st, dst, stage, cs,
-                       ech, children, crec, fix, cnt, cap, status);
+    AppendArgs<T> g;
+    g.dst[0] = dst0;
+    g.dst[1] = dst1;
+    g.stage[0] = stage0;
+    g.stage[1] = stage1;
+    g.cnt[0] = cnt0;
+    g.cnt[1] = cnt1;
+    int64_t nsc = (max_chunks + kSuper - 1) / kSuper;
+    if (nsc < 1) nsc = 1;
+    hipLaunchKernelGGL((k_append<T>), dim3((unsigned)nsc, 2), dim3(kSuper), 0, st, j, g);
     return hipGetLastError();
 }
 
@@ -371,12 +442,12 @@ template hipError_t launch_dead_scan<double>(Parts<double>, const Counts *, Chun
 template hipError_t launch_dead_scan<float>(Parts<float>, const Counts *, Chunks, hipStream_t);
 template hipError_t launch_fill<double>(Parts<double>, Chunks, const FixRec *, hipStream_t);
 template hipError_t launch_fill<float>(Parts<float>, Chunks, const FixRec *, hipStream_t);
-template hipError_t launch_append<double>(Parts<double>, Parts<double>, int, Chunks, int,
-                                          const ChildRec *, const FixRec *, Counts *, int64_t,
-                                          int32_t *, hipStream_t);
-template hipError_t launch_append<float>(Parts<float>, Parts<float>, int, Chunks, int,
-                                         const ChildRec *, const FixRec *, Counts *, int64_t,
-                                         int32_t *, hipStream_t);
+template hipError_t launch_append<double>(const ScanJobs &, Parts<double>, Parts<double>,
+                                          Parts<double>, Parts<double>, Counts *, Counts *, int64_t,
+                                          hipStream_t);
+template hipError_t launch_append<float>(const ScanJobs &, Parts<float>, Parts<float>,
+                                         Parts<float>, Parts<float>, Counts *, Counts *, int64_t,
+                                         hipStream_t);
 template hipError_t launch_resize<double>(Parts<double>, Counts *, Chunks, CloneRec *, double,
                                           double, int64_t, int32_t *, hipStream_t);
 template hipError_t launch_resize<float>(Parts<float>, Counts *, Chunks, CloneRec *, double,

@@ -18,7 +18,7 @@ constexpr double kTwoPi = 6.283185307179586;
 constexpr int kMaxProc = 4;
 constexpr int kMaxLevels = 16;
 constexpr int kChunk = 64;       // particles per chunk: one wavefront
-constexpr int kMaxWaves = 16384; // wavefronts of a particle pass (candidate buckets)
+constexpr int kMaxWaves = 16384; // wavefronts of a particle pass (bounds the bucket padding)
 constexpr int kMaxLine = 2048;   // longest r-line (nr - 1 unknowns) the smoother takes
 
 // Device status bits (sticky).
@@ -107,11 +107,14 @@ struct CloneRec {     // weight split of one species
     uint64_t next_id_old;
 };
 
+constexpr int kSuper = 512;      // chunks per superchunk (two-level offsets)
+
 struct Chunks {       // per parent species; chunk = 64 consecutive particles (lane = bit)
     unsigned long long *dead;   // absorbed particles
     unsigned long long *ev;     // ionization events (electron chunks)
     unsigned long long *se, *si;// new electron / new ion still alive
-    int64_t *dead_off, *ev_off, *se_off, *si_off, *clone_off;
+    int32_t *sc_dead, *sc_ev, *sc_se, *sc_si;  // set bits per superchunk
+    int64_t *clone_off;
     int32_t *clone_cnt;         // per chunk (resize)
     int64_t *dead_glob;         // sorted global dead list
     int32_t *pcount;            // per particle clone count (resize)
@@ -137,7 +140,8 @@ template <typename T> struct PassArgs {
     uint8_t *ev;                  // optional per-particle event codes
     ChildRec *crec;               // electron pass records n_parent here
     unsigned long long *psteps;   // if set: += particles entering the pass
-    int nbuckets;                 // wavefronts of the pass (= candidate buckets)
+    int nbuckets;                 // blocks of the pass (= candidate buckets)
+    int bucket_waves;             // wavefronts per pass block
     int32_t *status;
     uint32_t step;
 };
@@ -158,29 +162,34 @@ hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t i
 // fixup.hip: deterministic removal of absorbed particles and appending of new
 // ones (identities in parent order, independent of the launch shape).
 struct ScanJobs {
-    // job 0: children of the electron pass
+    // children staged by the electron pass (electron chunks)
     int children;
     Chunks ech;
     const Counts *ecnt, *icnt;
     ChildRec *crec;
-    // jobs 1, 2: dead lists of species 0 and 1
+    int kids[2];   // append the staged children of species 0 / 1
+    // dead lists of species 0 and 1
     int dead[2];
     Chunks ch[2];
     const Counts *cnt[2];
     FixRec *fix[2];
+    int64_t cap[2];
+    int32_t *status;
 };
-hipError_t launch_scan(const ScanJobs &j, hipStream_t st);
+// Superchunk totals of the masks (children and/or dead particles).
+hipError_t launch_scan(const ScanJobs &j, int64_t max_chunks, hipStream_t st);
+// Sorted global dead lists and the kept counts, both species in one launch.
+hipError_t launch_dead_list(const ScanJobs &j, int64_t max_chunks, hipStream_t st);
 template <typename T>
 hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_t st);
-hipError_t launch_dead_list(Chunks ch, const FixRec *fix, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st);
-// Append the staged children of species `cs` (slots of electron chunks) after
-// the kept particles and commit the new count and next identity.
+// Append the staged children after the kept particles of each species (slot
+// = parent index, identities in parent order) and commit the counts.
 template <typename T>
-hipError_t launch_append(Parts<T> dst, Parts<T> stage, int cs, Chunks ech, int children,
-                         const ChildRec *crec, const FixRec *fix, Counts *cnt, int64_t cap,
-                         int32_t *status, hipStream_t st);
+hipError_t launch_append(const ScanJobs &j, Parts<T> dst0, Parts<T> dst1, Parts<T> stage0,
+                         Parts<T> stage1, Counts *cnt0, Counts *cnt1, int64_t max_chunks,
+                         hipStream_t st);
 template <typename T>
 hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, double wcoef,
                          double half_hr, int64_t cap, int32_t *status, hipStream_t st);

@@ -129,6 +129,8 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
 {
     extern __shared__ unsigned long long lds_acc[];
+    __shared__ unsigned long long sh_cand;
+    __shared__ int sh_bucket;
 
     const Mesh &m = a.mesh;
     const int64_t n = a.cnt->n;
@@ -145,17 +147,20 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
     unsigned long long *dep = a.acc;
 
     if (kMc && a.crec && blockIdx.x == 0 && threadIdx.x == 0) a.crec->n_parent = n;
+    if (kMc && threadIdx.x == 0) {
+        sh_cand = 0;
+        sh_bucket = 0;
+    }
     if (a.psteps && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.psteps, (unsigned long long)n);
     if (kLds) {
         for (int g = threadIdx.x; g < m.nn; g += blockDim.x) lds_acc[g] = 0;
         dep = lds_acc;
-        __syncthreads();
     }
+    if (kLds || kMc) __syncthreads();
 
-    // candidates of this wavefront go to its own bucket of the candidate list
-    const int64_t bsize = ((nch + nwaves - 1) / nwaves) * kChunk;
-    int32_t *bucket = a.ch.cand + wave * bsize;
-    int ncand = 0;
+    // candidates of this block go to its own bucket of the candidate list
+    const int64_t bsize = ((nch + nwaves - 1) / nwaves) * kChunk * (blockDim.x >> 6);
+    int32_t *bucket = a.ch.cand + (int64_t)blockIdx.x * bsize;
     for (int64_t c = wave; c < nch; c += nwaves) {
         const int64_t pi = c * kChunk + lane;
         const bool valid = pi < n;
@@ -176,18 +181,47 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
                 died = true;
             }
         }
+        // Null-collision candidate test; for electrons (target at rest) the
+        // process choice is cheap and a null event is settled here, so only
+        // real collisions (and every ion candidate) go to the bucket.
         bool cand = false;
         if (kMc) {
+            int code = 0;
+            bool tested = false;
             if (live && mc_on) {
                 double ua, ub;
                 uniform2(a.phys.seed, a.sp.s, a.p.id[pi], a.step, 0, ua, ub);
-                cand = ua < a.sp.p_null;
+                if (ua < a.sp.p_null) {
+                    tested = true;
+                    cand = true;
+                    if (a.sp.mc_model == 1) {
+                        double v0 = s.vr, v1 = s.vt, v2 = s.vz;
+                        double thr_nu;
+                        {
+#pragma clang fp contract(off)
+                            thr_nu = ub * a.sp.nu_max;
+                        }
+                        double eps = energy_ev(v0, v1, v2, a.sp.ekin);
+                        double vm = sqrt(sumsq3(v0, v1, v2));
+                        if (choose_process(a.sp.xs, a.phys.n_gas, thr_nu, eps, vm) < 0) {
+                            cand = false;
+                            code = 1;
+                        }
+                    }
+                }
             }
-            if (valid && a.ev) a.ev[pi] = 0;
+            if (valid && a.ev) a.ev[pi] = (uint8_t)code;
+            int ntested;
+            wave_rank(tested, ntested);
+            if (lane == 0 && ntested) atomicAdd(&sh_cand, (unsigned long long)ntested);
             int tot;
             int r = wave_rank(cand, tot);
-            if (cand) bucket[ncand + r] = (int32_t)pi;
-            ncand += tot;
+            int base = 0;
+            if (tot > 0) {
+                if (lane == 0) base = atomicAdd(&sh_bucket, tot);
+                base = __shfl(base, 0, 64);
+            }
+            if (cand) bucket[base + r] = (int32_t)pi;
             if (lane == 0) {
                 a.ch.ev[c] = 0;
                 a.ch.se[c] = 0;
@@ -215,7 +249,13 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
             if (lane == 0) a.ch.dead[c] = dm;
         }
     }
-    if (kMc && lane == 0 && wave < a.nbuckets) a.ch.ncand[wave] = ncand;
+    if (kMc) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (blockIdx.x < a.nbuckets) a.ch.ncand[blockIdx.x] = sh_bucket;
+            if (sh_cand) atomicAdd(a.mcstat, sh_cand);
+        }
+    }
     if (kLds) {
         __syncthreads();
         unsigned long long *out = a.slices + (size_t)blockIdx.x * m.nn;
@@ -245,15 +285,19 @@ __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
         dep = lds_acc;
     }
     __syncthreads();
-    // buckets of the pass that found the candidates, one wavefront per bucket
+    // buckets of the pass blocks; R wavefronts share a bucket (segments of 64)
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t nch = (a.cnt->n + kChunk - 1) / kChunk;
-    const int64_t bsize = ((nch + a.nbuckets - 1) / a.nbuckets) * kChunk;
-    for (int64_t b = wave; b < a.nbuckets; b += nwaves) {
+    const int64_t NB = a.nbuckets;
+    const int64_t pass_waves = NB * a.bucket_waves;
+    const int64_t bsize = ((nch + pass_waves - 1) / pass_waves) * kChunk * a.bucket_waves;
+    const int64_t R = nwaves >= NB ? nwaves / NB : 1;
+    for (int64_t t = wave; t < NB * R; t += nwaves) {
+      const int64_t b = t % NB, seg = t / NB;
       const int nb = a.ch.ncand[b];
-      for (int j = lane; j < nb; j += kChunk) {
+      for (int64_t j = seg * kChunk + lane; j < nb; j += R * kChunk) {
         const int64_t pi = a.ch.cand[b * bsize + j];
         const int64_t c = pi >> 6;
         const unsigned long long bit = 1ull << (pi & 63);
@@ -271,7 +315,6 @@ __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
             s.vz = (T)v2;
             atomicAdd(&sh_stat[1 + ev - 2], 1ull);
         }
-        atomicAdd(&sh_stat[0], 1ull);
         if (a.ev) a.ev[pi] = (uint8_t)ev;
         PState<T> ne{}, ni{};
         bool ne_live = false, ni_live = false;
@@ -336,7 +379,7 @@ __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
       }
     }
     __syncthreads();
-    if (threadIdx.x < 1 + kMaxProc && sh_stat[threadIdx.x])
+    if (threadIdx.x >= 1 && threadIdx.x < 1 + kMaxProc && sh_stat[threadIdx.x])
         atomicAdd(a.mcstat + threadIdx.x, sh_stat[threadIdx.x]);
     if (kLds) {
         unsigned long long *out = a.slices + (size_t)blockIdx.x * m.nn;

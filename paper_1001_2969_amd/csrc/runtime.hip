@@ -310,8 +310,10 @@ rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step, int mark_at 
     }
     const bool mc = (mode & M_MC) && a.sp.mc_model != RZPIC_MC_NONE;
     if (mode & M_MC) HIPCHK(launch_fill_u64(a.mcstat, 1 + kMaxProc, c->st));
-    a.nbuckets = blocks * (threads / 64);
-    if (a.nbuckets > kMaxWaves) return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", a.nbuckets, kMaxWaves);
+    a.nbuckets = blocks;
+    a.bucket_waves = threads / 64;
+    if (blocks * (threads / 64) > kMaxWaves)
+        return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", blocks * threads / 64, kMaxWaves);
     if (mark_at >= 0) mark(c, mark_at);
     HIPCHK(launch_pass<T>(mode, a, blocks, threads, lds, c->st));
     if (mark_at >= 0) mark(c, mark_at + 1);
@@ -324,8 +326,14 @@ rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step, int mark_at 
         int cblocks = c->cus * 2, cthreads = 256;
         size_t clds = 0;
         if (merged && c->lds_ok && expect > 65536.0) {
+            // few blocks: each flushes a whole grid copy
             cmode |= M_LDS;
             clds = (size_t)c->nn * sizeof(unsigned long long);
+            cblocks = c->cus / 2 > 0 ? c->cus / 2 : 1;
+            if (const char *e = std::getenv("RZPIC_COLLIDE_BLOCKS")) {
+                int b = std::atoi(e);
+                if (b > 0) cblocks = b;
+            }
             if (cblocks > c->slice_blocks) cblocks = c->slice_blocks;
         } else if (expect < 4096.0) {
             cblocks = c->cus / 4 > 0 ? c->cus / 4 : 1;
@@ -351,7 +359,8 @@ template <typename T> rzpic_status run_staged(rzpic_ctx *c, int cs, int mode)
     return RZPIC_OK;
 }
 
-// Scan + dead list + fill + append for the species in `which` (bit s).
+// List maintenance of the species in `which` (bit s): superchunk totals,
+// sorted dead lists, hole filling, appending of staged children.
 template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
 {
     ScanJobs j{};
@@ -360,26 +369,29 @@ template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
     j.ecnt = c->cnt;
     j.icnt = c->cnt + 1;
     j.crec = c->crec;
+    j.status = c->status;
+    int64_t max_chunks = 1;
     for (int s = 0; s < 2; ++s) {
         j.dead[s] = (which >> s) & 1;
+        j.kids[s] = j.dead[s] && c->children_pending[s];
         j.ch[s] = c->sp[s].ch;
         j.cnt[s] = c->cnt + s;
         j.fix[s] = c->fix + s;
+        j.cap[s] = c->sp[s].cap;
+        int64_t nch = (c->sp[s].cap + kChunk - 1) / kChunk;
+        if (c->sp[s].bound && nch > max_chunks) max_chunks = nch;
     }
-    HIPCHK(launch_scan(j, c->st));
+    HIPCHK(launch_scan(j, max_chunks, c->st));
     if (j.children) c->children_scanned = true;
+    HIPCHK(launch_dead_list(j, max_chunks, c->st));
     for (int s = 0; s < 2; ++s)
-        if ((which >> s) & 1) HIPCHK(launch_dead_list(c->sp[s].ch, c->fix + s, c->st));
+        if (j.dead[s]) HIPCHK(launch_fill<T>(parts_of<T>(c->sp[s].v), c->sp[s].ch, c->fix + s, c->st));
+    Parts<T> none{};
+    HIPCHK(launch_append<T>(j, c->sp[0].bound ? parts_of<T>(c->sp[0].v) : none,
+                            c->sp[1].bound ? parts_of<T>(c->sp[1].v) : none, stage_of<T>(c, 0),
+                            stage_of<T>(c, 1), c->cnt, c->cnt + 1, max_chunks, c->st));
     for (int s = 0; s < 2; ++s)
-        if ((which >> s) & 1) HIPCHK(launch_fill<T>(parts_of<T>(c->sp[s].v), c->sp[s].ch, c->fix + s, c->st));
-    for (int s = 0; s < 2; ++s) {
-        if (!((which >> s) & 1)) continue;
-        int kids = c->children_pending[s] ? 1 : 0;
-        HIPCHK(launch_append<T>(parts_of<T>(c->sp[s].v), stage_of<T>(c, s), s, c->sp[0].ch, kids,
-                                c->crec, c->fix + s, c->cnt + s, c->sp[s].cap, c->status,
-                                c->st));
-        c->children_pending[s] = false;
-    }
+        if (j.kids[s]) c->children_pending[s] = false;
     if (!c->children_pending[0] && !c->children_pending[1]) c->children_scanned = false;
     return RZPIC_OK;
 }
@@ -786,9 +798,10 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
 #define A(p, n)                                   \
     if ((st = dalloc(c, &(p), (n))) != RZPIC_OK) \
         return st;
+    const int64_t nsc = nch / kSuper + 2;
     A(ss.ch.dead, nch) A(ss.ch.ev, nch) A(ss.ch.se, nch) A(ss.ch.si, nch)
-    A(ss.ch.clone_cnt, nch) A(ss.ch.dead_off, nch) A(ss.ch.ev_off, nch)
-    A(ss.ch.se_off, nch) A(ss.ch.si_off, nch) A(ss.ch.clone_off, nch)
+    A(ss.ch.clone_cnt, nch) A(ss.ch.clone_off, nch)
+    A(ss.ch.sc_dead, nsc) A(ss.ch.sc_ev, nsc) A(ss.ch.sc_se, nsc) A(ss.ch.sc_si, nsc)
     A(ss.ch.dead_glob, cap) A(ss.ch.pcount, cap) A(ss.ch.cand, cap + (size_t)kChunk * (kMaxWaves + 1)) A(ss.ch.ncand, kMaxWaves)
 #undef A
     if (s == 0 && v->mc_model == RZPIC_MC_ELECTRON) {
