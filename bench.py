@@ -30,7 +30,11 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE = {"mixed": 8 * 4 + 8 + 7 * 4, "fp64": 8 * 8 + 8 + 7 * 8}
 
 
-def run_gpu(w, precision, steps, warmup, seed_shift=0):
+def run_gpu(w, precision, steps, warmup, timing_steps=50):
+    """Throughput over `steps` merged steps with nothing else on the stream,
+    then `timing_steps` more with the library's HIP events around each phase
+    (per-phase device times; every event costs the stream a few microseconds,
+    which is why the throughput run records none)."""
     import torch
 
     from paper_1001_2969_amd import rzpic
@@ -44,8 +48,6 @@ def run_gpu(w, precision, steps, warmup, seed_shift=0):
         ctx.step(n)
         n += 1
     ctx.sync()
-    ctx.set_timing(True)
-    ctx.timing()  # reset accumulators
     d0 = ctx.diag()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -54,9 +56,14 @@ def run_gpu(w, precision, steps, warmup, seed_shift=0):
         n += 1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    d1 = ctx.diag()
+    ctx.set_timing(True)
+    ctx.timing()  # reset accumulators
+    for _ in range(timing_steps):
+        ctx.step(n)
+        n += 1
     ctx.sync()
     tim = ctx.timing()
-    d1 = ctx.diag()
     ctx.set_timing(False)
     psteps = sum(d1["particle_steps"]) - sum(d0["particle_steps"])
     dt = t1 - t0
@@ -136,6 +143,30 @@ def cpu_baseline(w, steps):
     return ps / dt, dt
 
 
+def pmc_run(steps):
+    """Short run for hardware-counter passes: a few merged steps of the mixed
+    workload, then a plain device copy of known size (the calibration of the
+    byte counters: its algorithmic traffic is exactly the bytes read and
+    written)."""
+    import torch
+
+    from paper_1001_2969_amd import workloads as wl
+
+    w = wl.rf_129x65()
+    ctx, res = run_gpu(w, "mixed", steps, 3, timing_steps=steps)
+    ctx.close()
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_run": True, "steps": steps, "particles_per_pass":
+                      [res["timing"]["n0"], res["timing"]["n1"]],
+                      "bytes_per_particle": BYTES_PER_PARTICLE["mixed"],
+                      "copy_bytes_each_way": nbytes}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-vcycle-study", action="store_true")
+    ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
+                    help="only a short mixed run plus a copy calibration (for counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the "
@@ -157,6 +190,9 @@ def main():
     from paper_1001_2969_amd import rzpic, workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.pmc_run:
+        pmc_run(args.pmc_run)
+        return
     w = wl.rf_129x65()
     print(f"# workload {w.name}: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr,
           flush=True)

@@ -123,7 +123,9 @@ rzpic_status rzpic_bind_species(rzpic_ctx *ctx, int32_t s, const rzpic_species_v
 /* Set the live count n (<= capacity) and the next identity of species s
  * (asynchronous host-to-device write). */
 rzpic_status rzpic_set_count(rzpic_ctx *ctx, int32_t s, int64_t n, uint64_t next_id);
-/* Read the live count and next identity (synchronises). */
+/* Read the live count and next identity.  Synchronises the stream, and like
+ * rzpic_sync returns (and clears) a pending device-side failure such as
+ * RZPIC_ECAPACITY; the counts are written either way. */
 rzpic_status rzpic_get_count(rzpic_ctx *ctx, int32_t s, int64_t *n, uint64_t *next_id);
 
 /* Cross sections of species s (Sec. 2.6) on the uniform energy grid

@@ -224,7 +224,6 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st);
 // mg.hip
 struct MgLevels {
     int L, nr;
-    double *res;                   // finest-level residual scratch
     int nzl[kMaxLevels + 1];
     double hzl[kMaxLevels + 1];
     double *eps64[kMaxLevels + 1];
@@ -233,12 +232,38 @@ struct MgLevels {
     float *u32[kMaxLevels + 1], *f32[kMaxLevels + 1];
     int chi_face;
     double hr;
+    int K;                 // coarse levels 1..K solved by the single-block bottom kernel
+    size_t bottom_lds;     // its LDS bytes
+    // Single-block cycles: every level's right-hand side and correction held
+    // in LDS (FP64: the finest level is phi itself, in global memory), the
+    // line matrices factored beforehand into per-line tables.
+    int one_block;         // 1: this path is used
+    int S;                 // reduction steps of an r-line (ceil(log2(nr - 1)))
+    int line_off[kMaxLevels + 2];  // first table line of each level; line_off[L+1] = total
+    size_t tab_stride;     // elements per line table: (3 + 2 S) (nr - 1)
+    void *tab;             // line tables, float (mixed) or double
+    double *res;           // finest-level residual scratch
+    size_t solve_lds;      // LDS bytes of the single-block kernel
 };
 hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st);
-hipError_t mg_set_bc(double *phi, int nr, int nz, double V, hipStream_t st);
 hipError_t mg_resid_norm(const MgLevels &m, const double *u, const double *f, int zero_interior,
                          unsigned long long *norm, hipStream_t st);
-hipError_t mg_vcycle(const MgLevels &m, int mixed, double *phi, const double *f,
-                     unsigned long long *norm, hipStream_t st);
+hipError_t mg_set_bc(double *phi, int nr, int nz, double V, hipStream_t st);
+// Chooses the cycle path for `lds_budget` bytes of LDS per block: the
+// single-block path when every level fits (sets one_block, S, line_off,
+// tab_stride, solve_lds; the caller allocates tab and res), else the levels of
+// the bottom kernel (K, bottom_lds).
+void mg_plan(MgLevels &m, int mixed, size_t lds_budget, bool allow_one_block);
+// Single-block path: factor every line matrix of every level (once per solve,
+// after mg_restrict_eps), then run `cycles` V(0,1) cycles on phi in one
+// launch, the Dirichlet values of phi set first.
+hipError_t mg_factor(const MgLevels &m, int mixed, hipStream_t st);
+hipError_t mg_solve_block(const MgLevels &m, int mixed, double *phi, const double *f, double V,
+                          int cycles, hipStream_t st);
+// One V(0,1) cycle of the multi-launch path.  FP64: the finest level
+// alternates between phi and phi_alt (both carry the boundary values); the
+// pointers are swapped.
+hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_alt,
+                     const double *f, hipStream_t st);
 
 }  // namespace rz

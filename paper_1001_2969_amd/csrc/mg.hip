@@ -62,19 +62,16 @@ __device__ __forceinline__ void atomic_max_abs(unsigned long long *norm, double 
     atomicMax(norm, (unsigned long long)__double_as_longlong(fabs(v)));
 }
 
-// res = f - A u on the interior unknowns of the finest level (0 elsewhere),
-// optionally its max-norm.  zero_interior: u taken as its boundary values only.
+// Max-norm of f - A u over the interior unknowns of the finest level.
+// zero_interior: u taken as its boundary values only.
 __global__ void k_resid(const double *u, const double *f, const double *eps, int nr, int nz,
-                        double inv_hz2, double inv_hr2, int rule, double *res,
-                        unsigned long long *norm, int zero_interior)
+                        double inv_hz2, double inv_hr2, int rule, unsigned long long *norm,
+                        int zero_interior)
 {
     const int nn = nr * nz;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += gridDim.x * blockDim.x) {
         int i = g / nr, j = g - i * nr;
-        if (i == 0 || i == nz - 1 || j == nr - 1) {
-            if (res) res[g] = 0.0;
-            continue;
-        }
+        if (i == 0 || i == nz - 1 || j == nr - 1) continue;
         Coef<double> k = coef<double>(eps, nr, i, j, inv_hz2, inv_hr2, rule);
         auto U = [&](int gg) {
             int ii = gg / nr, jj = gg - ii * nr;
@@ -83,9 +80,7 @@ __global__ void k_resid(const double *u, const double *f, const double *eps, int
         };
         double Au = k.b * U(g) - k.a * U(g - nr) - k.c * U(g + nr) - k.e * U(g + 1);
         if (j > 0) Au -= k.d * U(g - 1);
-        double r = f[g] - Au;
-        if (res) res[g] = r;
-        if (norm) atomic_max_abs(norm, r);
+        atomic_max_abs(norm, f[g] - Au);
     }
 }
 
@@ -96,49 +91,8 @@ hipError_t mg_resid_norm(const MgLevels &m, const double *u, const double *f, in
     const double hz = m.hzl[L];
     int nn = nr * nz, threads = 256, blocks = (nn + threads - 1) / threads;
     hipLaunchKernelGGL(k_resid, dim3(blocks), dim3(threads), 0, st, u, f, m.eps64[L], nr, nz,
-                       1.0 / (hz * hz), 1.0 / (m.hr * m.hr), m.chi_face, (double *)nullptr, norm,
-                       zero_interior);
+                       1.0 / (hz * hz), 1.0 / (m.hr * m.hr), m.chi_face, norm, zero_interior);
     return hipGetLastError();
-}
-
-// Restriction of the fine residual down every level, f^{l-1} = FW_z(f^l)
-// (u^l = 0 on the coarse levels, so their residual is f^l itself).  Columns
-// are independent: each block stages `cpb` columns of all rows in LDS.
-template <typename T>
-__global__ void k_restrict_down(const double *res, MgLevels m, int mixed, int cpb)
-{
-    extern __shared__ double sbuf[];
-    const int L = m.L, nr = m.nr, nz = m.nzl[L];
-    double *cur = sbuf, *nxt = sbuf + (size_t)cpb * nz;
-    const int j0 = blockIdx.x * cpb;
-    for (int t = threadIdx.x; t < cpb * nz; t += blockDim.x) {
-        int cj = t / nz, i = t - cj * nz, j = j0 + cj;
-        double v = (j < nr - 1) ? res[(size_t)i * nr + j] : 0.0;
-        cur[t] = v;
-        if (mixed && j < nr - 1 && i > 0 && i < nz - 1) m.f32[L][(size_t)i * nr + j] = (float)v;
-    }
-    __syncthreads();
-    int nzf = nz;
-    for (int l = L - 1; l >= 1; --l) {
-        const int nzc = m.nzl[l];
-        T *fo = mixed ? (T *)m.f32[l] : (T *)m.f64[l];
-        for (int t = threadIdx.x; t < cpb * nzc; t += blockDim.x) {
-            int cj = t / nzc, I = t - cj * nzc, j = j0 + cj;
-            double v = 0.0;
-            if (I > 0 && I < nzc - 1) {
-                const double *col = cur + (size_t)cj * nzf;
-                v = 0.25 * col[2 * I - 1] + 0.5 * col[2 * I] + 0.25 * col[2 * I + 1];
-                if (mixed) v = (double)(float)v;  // coarse right-hand sides in FP32
-            }
-            nxt[(size_t)cj * nzc + I] = v;
-            if (j < nr - 1 && I > 0 && I < nzc - 1) fo[(size_t)I * nr + j] = (T)v;
-        }
-        __syncthreads();
-        double *tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-        nzf = nzc;
-    }
 }
 
 // epsilon on every level: full weighting along z, electrode rows injected.
@@ -298,57 +252,700 @@ __global__ void k_add_corr(double *phi, const float *u, int nr, int nz)
     }
 }
 
-// One V(0,1) cycle on phi.  FP64: every level in double with phi itself on
-// the finest level.  Mixed: the finest residual in double, the correction
-// cycle in float on every level, phi += correction in double.
-hipError_t mg_vcycle(const MgLevels &m, int mixed, double *phi, const double *f,
-                     unsigned long long *norm, hipStream_t st)
+// Down-leg of the V(0,1) cycle: the block takes `cpb` unknown columns of the
+// finest level, forms the residual f - A u there (u, eps staged in LDS with a
+// one-column halo) and restricts it along z down every level,
+// f^{l-1} = FW_z(f^l) (the coarse u^l are zero, so their residual is f^l).
+// Mixed: the finest residual is also stored in FP32 as the right-hand side of
+// the correction.
+template <typename T>
+__global__ void k_down(const double *u, const double *f, MgLevels m, int mixed, int cpb)
+{
+    extern __shared__ double sbuf[];
+    const int L = m.L, nr = m.nr, nz = m.nzl[L];
+    const int w = cpb + 2;  // staged columns j0-1 .. j0+cpb
+    double *us = sbuf, *es = sbuf + (size_t)w * nz;
+    double *cur = es + (size_t)w * nz, *nxt = cur + (size_t)cpb * nz;
+    const int j0 = blockIdx.x * cpb;
+    for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
+        int cj = t / nz, i = t - cj * nz, j = j0 - 1 + cj;
+        bool in = j >= 0 && j < nr;
+        us[t] = in ? u[(size_t)i * nr + j] : 0.0;
+        es[t] = in ? m.eps64[L][(size_t)i * nr + j] : 1.0;
+    }
+    __syncthreads();
+    const double hz = m.hzl[L];
+    const double iz2 = 1.0 / (hz * hz), ir2 = 1.0 / (m.hr * m.hr);
+    for (int t = threadIdx.x; t < cpb * nz; t += blockDim.x) {
+        int cj = t / nz, i = t - cj * nz, j = j0 + cj;
+        double r = 0.0;
+        if (j < nr - 1 && i > 0 && i < nz - 1) {
+            const int k = (cj + 1) * nz + i;  // staged index of (i, j)
+            auto E = [&](int di, int dj) { return es[k + dj * nz + di]; };
+            auto U = [&](int di, int dj) { return us[k + dj * nz + di]; };
+            double a = face<double>(E(-1, 0), E(0, 0), m.chi_face) * iz2;
+            double c = face<double>(E(0, 0), E(1, 0), m.chi_face) * iz2;
+            double d, e;
+            if (j == 0) {
+                d = 0.0;
+                e = 4.0 * face<double>(E(0, 0), E(0, 1), m.chi_face) * ir2;
+            } else {
+                double jj = (double)j;
+                d = face<double>(E(0, -1), E(0, 0), m.chi_face) * ((jj - 0.5) / jj) * ir2;
+                e = face<double>(E(0, 0), E(0, 1), m.chi_face) * ((jj + 0.5) / jj) * ir2;
+            }
+            double b = a + c + d + e;
+            double Au = b * U(0, 0) - a * U(-1, 0) - c * U(1, 0) - e * U(0, 1);
+            if (j > 0) Au -= d * U(0, -1);
+            r = f[(size_t)i * nr + j] - Au;
+            if (mixed) m.f32[L][(size_t)i * nr + j] = (float)r;
+        }
+        cur[t] = r;
+    }
+    __syncthreads();
+    int nzf = nz;
+    for (int l = L - 1; l >= 1; --l) {
+        const int nzc = m.nzl[l];
+        T *fo = mixed ? (T *)m.f32[l] : (T *)m.f64[l];
+        for (int t = threadIdx.x; t < cpb * nzc; t += blockDim.x) {
+            int cj = t / nzc, I = t - cj * nzc, j = j0 + cj;
+            double v = 0.0;
+            if (I > 0 && I < nzc - 1) {
+                const double *col = cur + (size_t)cj * nzf;
+                v = 0.25 * col[2 * I - 1] + 0.5 * col[2 * I] + 0.25 * col[2 * I + 1];
+                if (mixed) v = (double)(float)v;  // coarse right-hand sides in FP32
+            }
+            nxt[(size_t)cj * nzc + I] = v;
+            if (j < nr - 1 && I > 0 && I < nzc - 1) fo[(size_t)I * nr + j] = (T)v;
+        }
+        __syncthreads();
+        double *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        nzf = nzc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Parallel cyclic reduction of `ne` tridiagonal equations held in LDS
+// (A x_{j-1} + B x_j + C x_{j+1} = R), grouped in systems of n consecutive
+// equations.  Each thread keeps its equations' new coefficients in registers
+// between the two barriers of a step.  On return R/B is the solution.
+template <typename T, int EPT>
+__device__ __forceinline__ void pcr(T *A, T *Bd, T *C, T *Rr, int n, int ne)
+{
+    for (int s = 1; s < n; s <<= 1) {
+        T na[EPT], nb[EPT], ncc[EPT], nr[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            if (e >= ne) continue;
+            const int j = e % n;
+            T a = A[e], b = Bd[e], c = C[e], r = Rr[e], a2 = (T)0, c2 = (T)0;
+            if (j >= s) {
+                T k1 = a / Bd[e - s];
+                a2 = -A[e - s] * k1;
+                b -= C[e - s] * k1;
+                r -= Rr[e - s] * k1;
+            }
+            if (j + s < n) {
+                T k2 = c / Bd[e + s];
+                c2 = -C[e + s] * k2;
+                b -= A[e + s] * k2;
+                r -= Rr[e + s] * k2;
+            }
+            na[q] = a2;
+            nb[q] = b;
+            ncc[q] = c2;
+            nr[q] = r;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            if (e >= ne) continue;
+            A[e] = na[q];
+            Bd[e] = nb[q];
+            C[e] = ncc[q];
+            Rr[e] = nr[q];
+        }
+        __syncthreads();
+    }
+}
+
+// The coarse levels 1..K in one block, entirely in LDS: the exact solve of the
+// single line of level 1, then for l = 2..K the prolonged correction (injected
+// into the even lines the odd lines read) and one zebra sweep.  The coarse u^l
+// start from zero; u^K is written out for the next level's prolongation.
+template <typename T, int EPT> __global__ __launch_bounds__(1024) void k_bottom(MgLevels m, int mixed)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = (T *)smem_raw;
+    const int K = m.K, nr = m.nr, n = nr - 1;
+    // level l occupies [eps | f | u] rows of nzl[l] x nr from lev(l)
+    auto lev = [&](int l) {
+        size_t o = 0;
+        for (int q = 1; q < l; ++q) o += 3 * (size_t)m.nzl[q] * nr;
+        return sm + o;
+    };
+    T *A = lev(K + 1);
+    const int emax = ((m.nzl[K] - 1) / 2) * n;
+    T *Bd = A + emax, *C = Bd + emax, *Rr = C + emax;
+    for (int l = 1; l <= K; ++l) {
+        const size_t sz = (size_t)m.nzl[l] * nr;
+        T *le = lev(l);
+        const T *ge = mixed ? (const T *)m.eps32[l] : (const T *)m.eps64[l];
+        const T *gf = mixed ? (const T *)m.f32[l] : (const T *)m.f64[l];
+        for (size_t t = threadIdx.x; t < sz; t += blockDim.x) {
+            le[t] = ge[t];
+            le[sz + t] = gf[t];
+            le[2 * sz + t] = (T)0;
+        }
+    }
+    __syncthreads();
+    const T ir2 = (T)(1.0 / (m.hr * m.hr));
+    for (int l = 1; l <= K; ++l) {
+        const int nzl = m.nzl[l];
+        const T iz2 = (T)(1.0 / (m.hzl[l] * m.hzl[l]));
+        const size_t sz = (size_t)nzl * nr;
+        const T *le = lev(l), *lf = le + sz;
+        T *u = lev(l) + 2 * sz;
+        const T *uc = l > 1 ? lev(l - 1) + 2 * (size_t)m.nzl[l - 1] * nr : nullptr;
+        for (int parity = 1; parity >= 0; --parity) {
+            const int lines = parity ? (nzl - 1) / 2 : (nzl - 3) / 2;
+            if (lines <= 0) continue;
+            const int ne = lines * n;
+            for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+                const int t = e / n, j = e - t * n;
+                const int i = parity ? 2 * t + 1 : 2 * t + 2;
+                Coef<T> k = coef<T>(le, nr, i, j, iz2, ir2, m.chi_face);
+                auto nb = [&](int row) -> T {
+                    if (row == 0 || row == nzl - 1) return (T)0;
+                    T v = u[(size_t)row * nr + j];
+                    if (parity && uc) v += uc[(size_t)(row >> 1) * nr + j];
+                    return v;
+                };
+                A[e] = j == 0 ? (T)0 : -k.d;
+                Bd[e] = k.b;
+                C[e] = j == n - 1 ? (T)0 : -k.e;
+                Rr[e] = lf[(size_t)i * nr + j] + k.a * nb(i - 1) + k.c * nb(i + 1);
+            }
+            __syncthreads();
+            pcr<T, EPT>(A, Bd, C, Rr, n, ne);
+            for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+                const int t = e / n, j = e - t * n;
+                const int i = parity ? 2 * t + 1 : 2 * t + 2;
+                u[(size_t)i * nr + j] = Rr[e] / Bd[e];
+            }
+            __syncthreads();
+        }
+    }
+    T *gu = mixed ? (T *)m.u32[K] : (T *)m.u64[K];
+    const size_t szK = (size_t)m.nzl[K] * nr;
+    const T *uK = lev(K) + 2 * szK;
+    for (size_t t = threadIdx.x; t < szK; t += blockDim.x) gu[t] = uK[t];
+}
+
+template <typename T> struct LevelArgs {
+    int nr, nzl, rule, zero_old;
+    T iz2, ir2;
+    const T *eps, *f;
+    const T *u_in;   // old values (finest FP64 level), else null
+    const T *uc;     // coarse correction injected into the even neighbours
+    T *u_out;        // new values of the level, or null
+    double *add_to;  // mixed finest level: phi += correction of the owned lines
+};
+
+// One zebra sweep of a level in one launch.  Block b owns even line i = 2b+2:
+// it solves the odd lines i-1 and i+1 (neighbours: even lines with their old
+// value plus the injected coarse correction) -- the odd lines next to two even
+// lines are solved, identically, by both blocks -- then line i from them.
+// Odd line i-1 is owned by block i, and the last odd line by the last block.
+template <typename T, int EPT> __global__ __launch_bounds__(1024) void k_level(LevelArgs<T> p)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = (T *)smem_raw;
+    const int nr = p.nr, n = nr - 1, nzl = p.nzl;
+    const int i = 2 * blockIdx.x + 2;
+    const bool last = i + 1 == nzl - 2;
+    T *A = sm, *Bd = A + 2 * n, *C = Bd + 2 * n, *Rr = C + 2 * n;
+    auto old = [&](int row, int j) -> T {
+        return p.zero_old ? (T)0 : p.u_in[(size_t)row * nr + j];
+    };
+    auto nb = [&](int row, int j) -> T {
+        T v = old(row, j);
+        if (row != 0 && row != nzl - 1 && p.uc) v += p.uc[(size_t)(row >> 1) * nr + j];
+        return v;
+    };
+    // odd lines i-1 (t = 0) and i+1 (t = 1)
+    for (int e = threadIdx.x; e < 2 * n; e += blockDim.x) {
+        const int t = e / n, j = e - t * n;
+        const int io = i - 1 + 2 * t;
+        Coef<T> k = coef<T>(p.eps, nr, io, j, p.iz2, p.ir2, p.rule);
+        T g = p.f[(size_t)io * nr + j] + k.a * nb(io - 1, j) + k.c * nb(io + 1, j);
+        T ce = k.e;
+        if (j == n - 1) {
+            g += ce * old(io, nr - 1);
+            ce = (T)0;
+        }
+        A[e] = j == 0 ? (T)0 : -k.d;
+        Bd[e] = k.b;
+        C[e] = -ce;
+        Rr[e] = g;
+    }
+    __syncthreads();
+    pcr<T, EPT>(A, Bd, C, Rr, n, 2 * n);
+    // solutions of the odd lines stay in Rr (as x = R/B), then the even line
+    for (int e = threadIdx.x; e < 2 * n; e += blockDim.x) {
+        const int t = e / n, j = e - t * n;
+        const int io = i - 1 + 2 * t;
+        const T x = Rr[e] / Bd[e];
+        Rr[e] = x;
+        if (p.u_out) p.u_out[(size_t)io * nr + j] = x;
+        if (p.add_to && (t == 0 || last)) p.add_to[(size_t)io * nr + j] += (double)x;
+    }
+    __syncthreads();
+    T *A2 = Rr + 2 * n, *B2 = A2 + n, *C2 = B2 + n, *R2 = C2 + n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        Coef<T> k = coef<T>(p.eps, nr, i, j, p.iz2, p.ir2, p.rule);
+        T g = p.f[(size_t)i * nr + j] + k.a * Rr[j] + k.c * Rr[n + j];
+        T ce = k.e;
+        if (j == n - 1) {
+            g += ce * old(i, nr - 1);
+            ce = (T)0;
+        }
+        A2[j] = j == 0 ? (T)0 : -k.d;
+        B2[j] = k.b;
+        C2[j] = -ce;
+        R2[j] = g;
+    }
+    __syncthreads();
+    pcr<T, EPT>(A2, B2, C2, R2, n, n);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const T x = R2[j] / B2[j];
+        if (p.u_out) p.u_out[(size_t)i * nr + j] = x;
+        if (p.add_to) p.add_to[(size_t)i * nr + j] += (double)x;
+    }
+}
+
+template <typename T>
+static hipError_t level_sweep(const MgLevels &m, int l, int zero_old, const T *u_in,
+                              const T *uc, T *u_out, const T *f, const T *eps, double *add_to,
+                              hipStream_t st)
+{
+    LevelArgs<T> p;
+    p.nr = m.nr;
+    p.nzl = m.nzl[l];
+    p.rule = m.chi_face;
+    p.zero_old = zero_old;
+    p.iz2 = (T)(1.0 / (m.hzl[l] * m.hzl[l]));
+    p.ir2 = (T)(1.0 / (m.hr * m.hr));
+    p.eps = eps;
+    p.f = f;
+    p.u_in = u_in;
+    p.uc = uc;
+    p.u_out = u_out;
+    p.add_to = add_to;
+    const int blocks = (p.nzl - 3) / 2;
+    if (blocks <= 0) return hipSuccess;
+    const int n = m.nr - 1;
+    int threads = ((2 * n + 63) / 64) * 64;
+    if (threads > 1024) threads = 1024;
+    const int ept = (2 * n + threads - 1) / threads;  // n <= kMaxLine: at most 4
+    size_t lds = 12 * (size_t)n * sizeof(T);
+    if (ept <= 1)
+        hipLaunchKernelGGL((k_level<T, 1>), dim3(blocks), dim3(threads), lds, st, p);
+    else if (ept <= 2)
+        hipLaunchKernelGGL((k_level<T, 2>), dim3(blocks), dim3(threads), lds, st, p);
+    else
+        hipLaunchKernelGGL((k_level<T, 4>), dim3(blocks), dim3(threads), lds, st, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Single-block path.
+//
+// Line tables.  Every interior line (level l, row i) is the tridiagonal system
+// -d x_{j-1} + b x_j - e x_{j+1} = g of its r-line; the matrix does not change
+// during a solve, so the multipliers of the parallel cyclic reduction are
+// formed once here and a sweep only carries right-hand sides.  The table of
+// one line holds rows of n = nr - 1 values:
+//   a | c | b after the last step | k1, k2 of step 0 | k1, k2 of step 1 | ...
+// with k1 = A_j / B_{j-s} (0 for j < s) and k2 = C_j / B_{j+s} (0 for
+// j + s >= n), s = 2^step, exactly the products the reduction forms.
+template <typename T> __global__ __launch_bounds__(256) void k_factor(MgLevels m, int mixed)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = (T *)smem_raw;
+    const int line = blockIdx.x;
+    int l = 1;
+    while (line >= m.line_off[l + 1]) ++l;
+    const int i = line - m.line_off[l] + 1;
+    const int nr = m.nr, n = nr - 1;
+    T *tab = (T *)m.tab + (size_t)line * m.tab_stride;
+    const T *eps = mixed ? (const T *)m.eps32[l] : (const T *)m.eps64[l];
+    const T iz2 = (T)(1.0 / (m.hzl[l] * m.hzl[l])), ir2 = (T)(1.0 / (m.hr * m.hr));
+    T *A = sm, *Bd = A + n, *C = Bd + n;
+    const int j = threadIdx.x;  // blockDim.x >= n
+    if (j < n) {
+        Coef<T> k = coef<T>(eps, nr, i, j, iz2, ir2, m.chi_face);
+        tab[j] = k.a;
+        tab[n + j] = k.c;
+        A[j] = j == 0 ? (T)0 : -k.d;
+        Bd[j] = k.b;
+        C[j] = j == n - 1 ? (T)0 : -k.e;
+    }
+    __syncthreads();
+    int q = 0;
+    for (int s = 1; s < n; s <<= 1, ++q) {
+        T a2 = (T)0, b = (T)0, c2 = (T)0;
+        if (j < n) {
+            T a = A[j], c = C[j], k1 = (T)0, k2 = (T)0;
+            b = Bd[j];
+            if (j >= s) {
+                k1 = a / Bd[j - s];
+                a2 = -A[j - s] * k1;
+                b -= C[j - s] * k1;
+            }
+            if (j + s < n) {
+                k2 = c / Bd[j + s];
+                c2 = -C[j + s] * k2;
+                b -= A[j + s] * k2;
+            }
+            tab[(size_t)(3 + 2 * q) * n + j] = k1;
+            tab[(size_t)(4 + 2 * q) * n + j] = k2;
+        }
+        __syncthreads();
+        if (j < n) {
+            A[j] = a2;
+            Bd[j] = b;
+            C[j] = c2;
+        }
+        __syncthreads();
+    }
+    if (j < n) tab[2 * n + j] = Bd[j];
+}
+
+hipError_t mg_factor(const MgLevels &m, int mixed, hipStream_t st)
+{
+    const int lines = m.line_off[m.L + 1], n = m.nr - 1;
+    const int threads = ((n + 63) / 64) * 64;  // n <= 256 on this path
+    if (mixed)
+        hipLaunchKernelGGL((k_factor<float>), dim3(lines), dim3(threads), 3 * n * sizeof(float),
+                           st, m, mixed);
+    else
+        hipLaunchKernelGGL((k_factor<double>), dim3(lines), dim3(threads), 3 * n * sizeof(double),
+                           st, m, mixed);
+    return hipGetLastError();
+}
+
+// V(0,1) cycles in one block of 16 wavefronts.  Level l keeps [u | f] rows in
+// LDS (FP64: levels below the finest; the finest level is phi and the global
+// right-hand side).  Down: the finest residual in FP64 (to a global scratch),
+// restricted along z level by level.  Up: one wavefront per r-line, Q
+// unknowns per lane (j = q*64 + lane); the reduction steps exchange
+// right-hand sides across lanes with shuffles, so a line needs no block
+// barrier, and the block synchronises once per half-sweep.
+template <typename T, int Q>
+__global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *phi,
+                                                const double *f, double V, int cycles)
+{
+    constexpr int SMAX = Q == 1 ? 6 : Q == 2 ? 7 : 8;
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = (T *)smem_raw;
+    const int L = m.L, nr = m.nr, n = nr - 1, nz = m.nzl[L], S = m.S;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    auto lev = [&](int l) {  // u of level l; its f follows at + nzl * nr
+        size_t o = 0;
+        for (int q = 1; q < l; ++q) o += 2 * (size_t)m.nzl[q] * nr;
+        return sm + o;
+    };
+    for (int t = threadIdx.x; t < nr + nz; t += blockDim.x) {
+        if (t < nr) {
+            phi[t] = t < nr - 1 ? V : 0.0;
+            phi[(size_t)(nz - 1) * nr + t] = 0.0;
+        } else {
+            phi[(size_t)(t - nr) * nr + nr - 1] = 0.0;
+        }
+    }
+    __syncthreads();
+    const double iz2 = 1.0 / (m.hzl[L] * m.hzl[L]), ir2 = 1.0 / (m.hr * m.hr);
+    for (int cyc = 0; cyc < cycles; ++cyc) {
+        // ---- down
+        if (mixed || L > 1) {
+            T *fL = lev(mixed ? L : 1) + (size_t)(mixed ? nz : 0) * nr;  // used when mixed
+            for (int g = threadIdx.x; g < (nz - 2) * n; g += blockDim.x) {
+                const int i = 1 + g / n, j = g - (i - 1) * n;
+                Coef<double> k = coef<double>(m.eps64[L], nr, i, j, iz2, ir2, m.chi_face);
+                const double *u = phi + (size_t)i * nr + j;
+                double Au = k.b * u[0] - k.a * u[-nr] - k.c * u[nr] - k.e * u[1];
+                if (j > 0) Au -= k.d * u[-1];
+                const double r = f[(size_t)i * nr + j] - Au;
+                if (L > 1) m.res[(size_t)i * nr + j] = r;
+                if (mixed) fL[(size_t)i * nr + j] = (T)r;
+            }
+            __syncthreads();
+            if (L > 1) {
+                const int nzc = m.nzl[L - 1];
+                T *fc = lev(L - 1) + (size_t)nzc * nr;
+                for (int g = threadIdx.x; g < (nzc - 2) * n; g += blockDim.x) {
+                    const int I = 1 + g / n, j = g - (I - 1) * n;
+                    const double *col = m.res + j;
+                    double v = 0.25 * col[(size_t)(2 * I - 1) * nr] + 0.5 * col[(size_t)(2 * I) * nr] +
+                               0.25 * col[(size_t)(2 * I + 1) * nr];
+                    fc[(size_t)I * nr + j] = (T)v;
+                }
+                __syncthreads();
+                for (int l = L - 2; l >= 1; --l) {
+                    const int nzl = m.nzl[l], nzf = m.nzl[l + 1];
+                    T *fo = lev(l) + (size_t)nzl * nr;
+                    const T *fi = lev(l + 1) + (size_t)nzf * nr;
+                    for (int g = threadIdx.x; g < (nzl - 2) * n; g += blockDim.x) {
+                        const int I = 1 + g / n, j = g - (I - 1) * n;
+                        const T *col = fi + j;
+                        double v = 0.25 * (double)col[(size_t)(2 * I - 1) * nr] +
+                                   0.5 * (double)col[(size_t)(2 * I) * nr] +
+                                   0.25 * (double)col[(size_t)(2 * I + 1) * nr];
+                        fo[(size_t)I * nr + j] = (T)v;
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        // ---- up: exact coarsest line, then prolongation + zebra sweep per level
+        for (int l = 1; l <= L; ++l) {
+            const int nzl = m.nzl[l];
+            const bool fine = l == L, direct = fine && !mixed;
+            // LDS rows of this level (not used when direct) and of the level below
+            T *ul = lev(direct ? 1 : l);
+            const T *fl = ul + (size_t)(direct ? 0 : nzl) * nr;
+            const T *uc = lev(l > 1 ? l - 1 : 1);
+            for (int parity = 1; parity >= 0; --parity) {
+                const int lines = parity ? (nzl - 1) / 2 : (nzl - 3) / 2;
+                for (int t = wave; t < lines; t += nwaves) {
+                    const int i = parity ? 2 * t + 1 : 2 * t + 2;
+                    const T *tb = (const T *)m.tab + (size_t)(m.line_off[l] + i - 1) * m.tab_stride;
+                    T R[Q], bf[Q], k1[SMAX][Q], k2[SMAX][Q];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int j = q * 64 + lane;
+                        const bool ok = j < n;
+                        const int jj = ok ? j : 0;
+                        const T ta = tb[jj], tc = tb[n + jj];
+                        bf[q] = ok ? tb[2 * n + jj] : (T)1;
+#pragma unroll
+                        for (int st = 0; st < SMAX; ++st) {
+                            const bool have = ok && st < S;
+                            k1[st][q] = have ? tb[(size_t)(3 + 2 * st) * n + jj] : (T)0;
+                            k2[st][q] = have ? tb[(size_t)(4 + 2 * st) * n + jj] : (T)0;
+                        }
+                        T lo, hi, g;
+                        if (direct) {
+                            double vlo = phi[(size_t)(i - 1) * nr + jj];
+                            double vhi = phi[(size_t)(i + 1) * nr + jj];
+                            if (parity && l > 1) {
+                                if (i - 1 > 0) vlo += uc[(size_t)((i - 1) >> 1) * nr + jj];
+                                if (i + 1 < nzl - 1) vhi += uc[(size_t)((i + 1) >> 1) * nr + jj];
+                            }
+                            lo = (T)vlo;
+                            hi = (T)vhi;
+                            g = (T)f[(size_t)i * nr + jj];
+                        } else {
+                            if (parity) {
+                                lo = (l > 1 && i - 1 > 0) ? uc[(size_t)((i - 1) >> 1) * nr + jj] : (T)0;
+                                hi = (l > 1 && i + 1 < nzl - 1) ? uc[(size_t)((i + 1) >> 1) * nr + jj]
+                                                                : (T)0;
+                            } else {
+                                lo = ul[(size_t)(i - 1) * nr + jj];
+                                hi = ul[(size_t)(i + 1) * nr + jj];
+                            }
+                            g = fl[(size_t)i * nr + jj];
+                        }
+                        R[q] = ok ? g + ta * lo + tc * hi : (T)0;
+                    }
+#pragma unroll
+                    for (int st = 0; st < SMAX; ++st) {
+                        if (st >= S) break;
+                        const int s = 1 << st;
+                        T nR[Q];
+                        if (s < 64) {
+                            T dn[Q], up[Q];
+#pragma unroll
+                            for (int q = 0; q < Q; ++q) {
+                                dn[q] = __shfl(R[q], (lane - s) & 63, 64);
+                                up[q] = __shfl(R[q], (lane + s) & 63, 64);
+                            }
+#pragma unroll
+                            for (int q = 0; q < Q; ++q) {
+                                const T left = lane >= s ? dn[q] : (q > 0 ? dn[q > 0 ? q - 1 : 0] : (T)0);
+                                const T right = lane + s < 64 ? up[q]
+                                                              : (q + 1 < Q ? up[q + 1 < Q ? q + 1 : q] : (T)0);
+                                nR[q] = R[q] - left * k1[st][q] - right * k2[st][q];
+                            }
+                        } else {
+                            const int kq = s >> 6;
+#pragma unroll
+                            for (int q = 0; q < Q; ++q) {
+                                const T left = q >= kq ? R[q >= kq ? q - kq : 0] : (T)0;
+                                const T right = q + kq < Q ? R[q + kq < Q ? q + kq : q] : (T)0;
+                                nR[q] = R[q] - left * k1[st][q] - right * k2[st][q];
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) R[q] = nR[q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int j = q * 64 + lane;
+                        if (j >= n) continue;
+                        const T x = R[q] / bf[q];
+                        const size_t at = (size_t)i * nr + j;
+                        if (direct) {
+                            phi[at] = (double)x;
+                        } else {
+                            ul[at] = x;
+                            if (fine) phi[at] += (double)x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+hipError_t mg_solve_block(const MgLevels &m, int mixed, double *phi, const double *f, double V,
+                          int cycles, hipStream_t st)
+{
+    const int n = m.nr - 1;
+    const size_t lds = m.solve_lds;
+    if (mixed) {
+        if (n <= 64)
+            hipLaunchKernelGGL((k_solve<float, 1>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
+                               cycles);
+        else if (n <= 128)
+            hipLaunchKernelGGL((k_solve<float, 2>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
+                               cycles);
+        else
+            hipLaunchKernelGGL((k_solve<float, 4>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
+                               cycles);
+    } else {
+        if (n <= 64)
+            hipLaunchKernelGGL((k_solve<double, 1>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f,
+                               V, cycles);
+        else
+            hipLaunchKernelGGL((k_solve<double, 2>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f,
+                               V, cycles);
+    }
+    return hipGetLastError();
+}
+
+void mg_plan(MgLevels &m, int mixed, size_t lds_budget, bool allow_one_block)
+{
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    const int n = m.nr - 1;
+    // single-block path
+    int S = 0;
+    while ((1 << S) < n) ++S;
+    m.S = S;
+    int off = 0;
+    for (int l = 1; l <= m.L; ++l) {
+        m.line_off[l] = off;
+        off += m.nzl[l] - 2;
+    }
+    m.line_off[m.L + 1] = off;
+    m.tab_stride = (size_t)(3 + 2 * S) * n;
+    size_t lds = 0;
+    for (int l = 1; l <= (mixed ? m.L : m.L - 1); ++l) lds += 2 * (size_t)m.nzl[l] * m.nr * es;
+    m.solve_lds = lds;
+    m.one_block = allow_one_block && n <= (mixed ? 256 : 128) && lds <= lds_budget;
+    // multi-launch path: levels of the bottom kernel
+    m.K = 0;
+    m.bottom_lds = 0;
+    size_t lev = 0;
+    for (int K = 1; K <= m.L - 1; ++K) {
+        lev += 3 * (size_t)m.nzl[K] * m.nr * es;
+        const size_t emax = (size_t)((m.nzl[K] - 1) / 2) * n;
+        const size_t bytes = lev + 4 * emax * es;
+        if (bytes > lds_budget || emax > 4 * 1024) break;
+        m.K = K;
+        m.bottom_lds = bytes;
+    }
+}
+
+template <typename T>
+static hipError_t bottom(const MgLevels &m, int mixed, hipStream_t st)
+{
+    const int n = m.nr - 1;
+    const int emax = ((m.nzl[m.K] - 1) / 2) * n;
+    const int ept = (emax + 1023) / 1024;
+    if (ept <= 1)
+        hipLaunchKernelGGL((k_bottom<T, 1>), dim3(1), dim3(1024), m.bottom_lds, st, m, mixed);
+    else if (ept <= 2)
+        hipLaunchKernelGGL((k_bottom<T, 2>), dim3(1), dim3(1024), m.bottom_lds, st, m, mixed);
+    else
+        hipLaunchKernelGGL((k_bottom<T, 4>), dim3(1), dim3(1024), m.bottom_lds, st, m, mixed);
+    return hipGetLastError();
+}
+
+// One V(0,1) cycle on phi.  FP64: every level in double, the finest level on
+// phi itself.  Mixed: the finest residual in double, the correction cycle in
+// float on every level, phi += correction in double.
+hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_alt,
+                     const double *f, hipStream_t st)
 {
     const int L = m.L, nr = m.nr, nz = m.nzl[L];
-    const double hz = m.hzl[L];
-    const int nn = nr * nz;
     hipError_t e;
-    if (!mixed && L == 1) return line<double>(m, 1, 1, 0, phi, f, m.eps64[1], nullptr, st);
-    {
-        int threads = 256, blocks = (nn + threads - 1) / threads;
-        hipLaunchKernelGGL(k_resid, dim3(blocks), dim3(threads), 0, st, (const double *)phi, f,
-                           (const double *)m.eps64[L], nr, nz, 1.0 / (hz * hz),
-                           1.0 / (m.hr * m.hr), m.chi_face, m.res, norm, 0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (L == 1) {
+        // a single interior line: the cycle is its exact solve
+        if (!mixed) return line<double>(m, 1, 1, 0, phi, f, m.eps64[1], nullptr, st);
+        int cpb = cols_per_block(nz);
+        size_t lds = (2 * (size_t)(cpb + 2) + 2 * (size_t)cpb) * nz * sizeof(double);
+        hipLaunchKernelGGL((k_down<float>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256), lds, st,
+                           (const double *)phi, f, m, mixed, cpb);
+        if ((e = line<float>(m, 1, 1, 1, m.u32[1], m.f32[1], m.eps32[1], nullptr, st))) return e;
+        const int nn = nr * nz, threads = 256, blocks = (nn + threads - 1) / threads;
+        hipLaunchKernelGGL(k_add_corr, dim3(blocks), dim3(threads), 0, st, phi,
+                           (const float *)m.u32[1], nr, nz);
+        return hipGetLastError();
     }
     {
         int cpb = cols_per_block(nz);
-        int blocks = (nr - 1 + cpb - 1) / cpb;
-        size_t lds = 2 * (size_t)cpb * nz * sizeof(double);
+        size_t lds = (2 * (size_t)(cpb + 2) + 2 * (size_t)cpb) * nz * sizeof(double);
         if (mixed)
-            hipLaunchKernelGGL((k_restrict_down<float>), dim3(blocks), dim3(256), lds, st,
-                               (const double *)m.res, m, mixed, cpb);
+            hipLaunchKernelGGL((k_down<float>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256), lds,
+                               st, (const double *)phi, f, m, mixed, cpb);
         else
-            hipLaunchKernelGGL((k_restrict_down<double>), dim3(blocks), dim3(256), lds, st,
-                               (const double *)m.res, m, mixed, cpb);
+            hipLaunchKernelGGL((k_down<double>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256), lds,
+                               st, (const double *)phi, f, m, mixed, cpb);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (mixed) {
-        if ((e = line<float>(m, 1, 1, 1, m.u32[1], m.f32[1], m.eps32[1], nullptr, st))) return e;
-        for (int l = 2; l <= L; ++l) {
-            if ((e = line<float>(m, l, 1, 1, m.u32[l], m.f32[l], m.eps32[l], m.u32[l - 1], st)))
-                return e;
-            if ((e = line<float>(m, l, 0, 0, m.u32[l], m.f32[l], m.eps32[l], nullptr, st)))
-                return e;
-        }
-        int threads = 256, blocks = (nn + threads - 1) / threads;
-        hipLaunchKernelGGL(k_add_corr, dim3(blocks), dim3(threads), 0, st, phi,
-                           (const float *)m.u32[L], nr, nz);
-        return hipGetLastError();
+    int done = m.K;
+    if (m.K >= 1) {
+        e = mixed ? bottom<float>(m, mixed, st) : bottom<double>(m, mixed, st);
+        if (e != hipSuccess) return e;
+    } else {
+        e = mixed ? line<float>(m, 1, 1, 1, m.u32[1], m.f32[1], m.eps32[1], nullptr, st)
+                  : line<double>(m, 1, 1, 1, m.u64[1], m.f64[1], m.eps64[1], nullptr, st);
+        if (e != hipSuccess) return e;
+        done = 1;
     }
-    if ((e = line<double>(m, 1, 1, 1, m.u64[1], m.f64[1], m.eps64[1], nullptr, st))) return e;
-    for (int l = 2; l <= L; ++l) {
+    for (int l = done + 1; l <= L; ++l) {
         const bool fine = l == L;
-        double *u = fine ? phi : m.u64[l];
-        const double *ff = fine ? f : m.f64[l];
-        if ((e = line<double>(m, l, 1, fine ? 0 : 1, u, ff, m.eps64[l], m.u64[l - 1], st)))
-            return e;
-        if ((e = line<double>(m, l, 0, 0, u, ff, m.eps64[l], nullptr, st))) return e;
+        if (mixed) {
+            e = level_sweep<float>(m, l, 1, nullptr, m.u32[l - 1], fine ? nullptr : m.u32[l],
+                                   m.f32[l], m.eps32[l], fine ? phi : nullptr, st);
+        } else if (fine) {
+            e = level_sweep<double>(m, l, 0, phi, m.u64[l - 1], phi_alt, f, m.eps64[l], nullptr,
+                                    st);
+            double *t = phi;
+            phi = phi_alt;
+            phi_alt = t;
+        } else {
+            e = level_sweep<double>(m, l, 1, nullptr, m.u64[l - 1], m.u64[l], m.f64[l],
+                                    m.eps64[l], nullptr, st);
+        }
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

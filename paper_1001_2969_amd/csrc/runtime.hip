@@ -77,6 +77,7 @@ struct rzpic_ctx {
 
     // grids
     double *phi, *rho, *chi, *er, *ez, *dens[2], *vol, *f, *eps;
+    double *phi_alt;  // FP64 cycles sweep the finest level from one phi buffer into the other
     void *E2;
     unsigned long long *acc[2];
     unsigned long long *slices = nullptr;
@@ -408,16 +409,27 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
     }
     HIPCHK(mg_restrict_eps(c->mg, c->mixed, c->st));
     const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
-    HIPCHK(mg_set_bc(c->phi, nr, nz, V, c->st));
+    const bool ob = c->mg.one_block != 0;
+    if (ob) HIPCHK(mg_factor(c->mg, c->mixed, c->st));
+    auto cycles_run = [&](int kk) -> hipError_t {
+        if (ob) return mg_solve_block(c->mg, c->mixed, c->phi, c->f, V, kk, c->st);
+        for (int q = 0; q < kk; ++q) {
+            hipError_t e = mg_vcycle(c->mg, c->mixed, c->phi, c->phi_alt, c->f, c->st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (!ob || c->c.mg_fixed_cycles <= 0) {
+        HIPCHK(mg_set_bc(c->phi, nr, nz, V, c->st));
+        if (!ob) HIPCHK(mg_set_bc(c->phi_alt, nr, nz, V, c->st));
+    }
     int k = 0;
     rzpic_status st = RZPIC_OK;
     const bool want = cycles || relres;
-    double scale = 0.0;
     if (c->c.mg_fixed_cycles > 0) {
-        for (; k < c->c.mg_fixed_cycles; ++k)
-            HIPCHK(mg_vcycle(c->mg, c->mixed, c->phi, c->f, nullptr, c->st));
+        HIPCHK(cycles_run(c->c.mg_fixed_cycles));
+        k = c->c.mg_fixed_cycles;
     } else {
-        unsigned long long h = 0;
         HIPCHK(launch_fill_u64(c->norm, 2, c->st));
         HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 1, c->norm + 1, c->st));
         for (;;) {
@@ -429,17 +441,15 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
             double rn, sc;
             std::memcpy(&rn, &hv[0], 8);
             std::memcpy(&sc, &hv[1], 8);
-            scale = sc;
             if (rn <= c->c.mg_tol * sc) break;
             if (k >= c->c.mg_max_cycles) {
                 st = fail(RZPIC_ENOTCONV, "multigrid: relative residual %.3e after %d cycles",
                           sc > 0 ? rn / sc : rn, k);
                 break;
             }
-            HIPCHK(mg_vcycle(c->mg, c->mixed, c->phi, c->f, nullptr, c->st));
+            HIPCHK(cycles_run(1));
             ++k;
         }
-        (void)h;
     }
     c->last_cycles = k;
     if (want || c->c.mg_fixed_cycles <= 0) {
@@ -453,7 +463,6 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
         std::memcpy(&rn, &hv[0], 8);
         std::memcpy(&sc, &hv[1], 8);
         c->last_relres = sc > 0 ? rn / sc : rn;
-        (void)scale;
     }
     if (cycles) *cycles = k;
     if (relres) *relres = c->last_relres;
@@ -662,7 +671,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
 #define A(p, n)                                  \
     if ((s = dalloc(c, &(p), (n))) != RZPIC_OK) \
         return bail(s);
-    A(c->phi, nn) A(c->rho, nn) A(c->chi, nn) A(c->er, nn) A(c->ez, nn) A(c->dens[0], nn)
+    A(c->phi, nn) A(c->phi_alt, nn) A(c->rho, nn) A(c->chi, nn) A(c->er, nn) A(c->ez, nn) A(c->dens[0], nn)
     A(c->dens[1], nn) A(c->vol, nn) A(c->f, nn) A(c->eps, nn)
     {
         double2 *e2;
@@ -693,7 +702,6 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     m.nr = k.nr;
     m.chi_face = k.chi_face;
     m.hr = c->hr;
-    A(m.res, nn)
     for (int l = 1; l <= L; ++l) {
         m.nzl[l] = (1 << l) + 1;
         m.hzl[l] = c->hz * (double)(1 << (L - l));
@@ -709,9 +717,17 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
             A(m.u64[l], sz) A(m.f64[l], sz)
         }
     }
-    if (!c->mixed) {
-        m.u64[L] = c->phi;
-        m.f64[L] = c->f;
+    mg_plan(m, c->mixed, c->lds_block, !std::getenv("RZPIC_MG_MULTI"));
+    if (m.one_block) {
+        const size_t tab = (size_t)m.line_off[L + 1] * m.tab_stride;
+        if (c->mixed) {
+            float *t;
+            A(t, tab) m.tab = t;
+        } else {
+            double *t;
+            A(t, tab) m.tab = t;
+        }
+        A(m.res, nn)
     }
 #undef A
     // host tables: 1/(2j+1), weighting volumes (Sec. 2.4, radial neighbours
@@ -830,10 +846,12 @@ rzpic_status rzpic_get_count(rzpic_ctx *c, int32_t s, int64_t *n, uint64_t *next
     TRY(need_species(c, s));
     Counts h;
     HIPCHK(hipMemcpyAsync(&h, c->cnt + s, sizeof h, hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    // synchronises, then returns (and clears) a pending device-side failure;
+    // the counts are valid either way
+    rzpic_status st = rzpic_sync(c);
     if (n) *n = h.n;
     if (next_id) *next_id = h.next_id;
-    return RZPIC_OK;
+    return st;
 }
 
 rzpic_status rzpic_set_xsec(rzpic_ctx *c, int32_t s, int32_t nproc, const int32_t *kind,

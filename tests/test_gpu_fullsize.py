@@ -1,0 +1,65 @@
+"""The benchmark workload at full size, in the benchmark's launch
+configuration (default block shapes, capacity 1.25 x the initial count):
+129x65 mesh, R = 4 cm, L = 2 cm, 2M electrons + 2M ions from the seeded
+init, 200 V 13.56 MHz drive, 3 V-cycles per step.
+
+FP64: every particle and grid against the oracle at the 1e-10 bar with
+identical collision decisions.  Mixed (the benchmarked form): the tolerances
+of the mixed-form tests."""
+import numpy as np
+import pytest
+
+from gpu_helpers import compare_grid, compare_particles, pair
+from oracle import rzo
+from paper_1001_2969_amd import rzpic
+from paper_1001_2969_amd import workloads as wl
+from test_gpu_mixed import TOL_GRID, check_counts, compare_mixed
+
+pytestmark = pytest.mark.gpu
+STEPS = 2
+
+
+def _pair_init(w, precision):
+    o, g = pair(w, precision=precision, capacity_factor=1.25)
+    for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
+        o.init_particles(s, w.n_per_species, w.n0, T, 0)
+        g.init_particles(s, w.n_per_species, w.n0, T, 0)
+    o.prologue()
+    g.prologue()
+    return o, g
+
+
+def test_fullsize_fp64_two_steps():
+    w = wl.rf_129x65().replace(precision="fp64")
+    o, g = _pair_init(w, "fp64")
+    for n in range(STEPS):
+        assert o.step(n) == 0
+        g.step(n)
+    for s in (0, 1):
+        assert g.count(s) == (o.count(s), o.next_id(s))
+        e = compare_particles(g.particles(s), o.particles(s), w, 1e-10, label=f"s={s}")
+        print(f"species {s}: worst field errors {e}")
+    compare_grid(g.grid(rzpic.G_PHI), o.grid(rzo.G_PHI), 1e-10, "phi")
+    for go, oo in ((rzpic.G_N0, rzo.G_N0), (rzpic.G_N1, rzo.G_N1)):
+        compare_grid(g.grid(go), o.grid(oo), 1e-10, "N")
+    d = g.diag()
+    for s in (0, 1):
+        np.testing.assert_allclose(d["absorbed"][s], o.absorbed(s), rtol=1e-9, atol=1e-30)
+
+
+def test_fullsize_mixed_two_steps():
+    w = wl.rf_129x65()
+    assert w.precision == "mixed"
+    o, g = _pair_init(w, "mixed")
+    for n in range(STEPS):
+        assert o.step(n) == 0
+        g.step(n)
+    w_un = {}
+    for s in (0, 1):
+        e, frac, w_un[s] = compare_mixed(g.particles(s), o.particles(s), w, f"s={s}")
+        print(f"species {s}: worst field errors {e}, unmatched fraction {frac:.2e}")
+    e = np.abs(g.grid(rzpic.G_PHI) - o.grid(rzo.G_PHI)).max() / np.abs(o.grid(rzo.G_PHI)).max()
+    print(f"phi error {e:.3e}")
+    assert e <= TOL_GRID
+    for s, (go, oo) in enumerate(((rzpic.G_N0, rzo.G_N0), (rzpic.G_N1, rzo.G_N1))):
+        print(f"N{s} error {check_counts(g.grid(go), o.grid(oo), w_un[s], f'N{s}'):.3e}")

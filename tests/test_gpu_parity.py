@@ -101,9 +101,16 @@ def test_deposit_and_finalize(weighting):
         np.testing.assert_allclose(g.grid(G).sum(), g.particles(s)["w"].sum(), rtol=1e-11)
 
 
+@pytest.mark.parametrize("path", ["one_block", "multi_launch"])
 @pytest.mark.parametrize("mesh", [(33, 33), (129, 65), (65, 3), (40, 17)])
 @pytest.mark.parametrize("face", [wl.FACE_AVG, wl.FACE_MAX])
-def test_solve_cycles_and_convergence(mesh, face):
+def test_solve_cycles_and_convergence(mesh, face, path, monkeypatch):
+    """Both cycle paths of the library: one launch for all cycles (levels in
+    LDS, pre-factored lines) and one launch per level (any mesh size)."""
+    if path == "multi_launch":
+        monkeypatch.setenv("RZPIC_MG_MULTI", "1")
+    else:
+        monkeypatch.delenv("RZPIC_MG_MULTI", raising=False)
     nr, nz = mesh
     w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
                     n_per_species=1, steps=1, V_dc=35.0, chi_face=face)
@@ -184,8 +191,8 @@ def test_weight_split():
 
 
 def _run_steps(w, nsteps, *, state=None, own_init=False, precision="fp64", check=True,
-               tol=TOL, ordered=True):
-    o, g = pair(w, precision=precision, capacity_factor=2.0)
+               tol=TOL, ordered=True, capacity_factor=2.0):
+    o, g = pair(w, precision=precision, capacity_factor=capacity_factor)
     if own_init:
         for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
             o.init_particles(s, w.n_per_species, w.n0, T, 0)
@@ -221,6 +228,17 @@ def test_small_workload_ten_steps_fp64():
         np.testing.assert_allclose(d["absorbed"][s], o.absorbed(s), rtol=1e-9, atol=1e-30)
         assert d["next_id"][s] == o.next_id(s)
     print("worst per-step errors", errs[-1])
+
+
+def test_weight_split_inside_steps_fp64():
+    """Splitting every other step with collisions (power-law tables) and
+    particles near the axis and the wall: ids of clones and children follow
+    the same order as the oracle's."""
+    w = _small(n_per_species=6000, resize_every=2, xsec="powerlaw")
+    st = random_state(w, 32, near_axis_frac=0.05, near_wall_frac=0.05)
+    for s in (0, 1):
+        st[s][0]["w"] = 2.5 * st[s][0]["w"]
+    _run_steps(w, 5, state=st, capacity_factor=8.0)
 
 
 def test_ragged_counts_and_empty_species():
