@@ -217,11 +217,12 @@ def main():
     ctx_m.close()
 
     tm = mixed["timing"]
-    n_launch = 0.5 * (tm["n0"] + tm["n1"])
-    t_launch_ms = 0.5 * (tm["pass0_ms"] + tm["pass1_ms"])
+    # one launch of the fused pass moves both species
+    n_launch = tm["n0"] + tm["n1"]
+    t_launch_ms = tm["pass_ms"]
     bpp = BYTES_PER_PARTICLE["mixed"]
     achieved = bpp * n_launch / (t_launch_ms * 1e-3) / 1e9 if t_launch_ms > 0 else None
-    roofline = {"kernel": "k_pass<float, fused, LDS deposit>", "bound": "hbm",
+    roofline = {"kernel": "k_pass2<float, fused, LDS deposit>", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
                 "bytes_per_particle": bpp, "particles_per_launch": n_launch,
@@ -242,17 +243,17 @@ def main():
         "config": {"workload": w.name, "mesh": f"{w.nr}x{w.nz}", "R_m": w.R, "L_m": w.L,
                    "particles_per_species": w.n_per_species, "precision": "mixed",
                    "v_cycles_per_step": w.mg_fixed_cycles, "V_rf": w.V_rf, "f_rf": w.f_rf},
-        "breakdown_ms_per_step": {k: tm[k] for k in ("step_ms", "solve_ms", "pass0_ms",
-                                                     "pass1_ms", "collide_ms", "grid_ms",
-                                                     "lists_ms")},
+        "breakdown_ms_per_step": {k: tm[k] for k in ("step_ms", "solve_ms", "pass_ms",
+                                                     "collide_ms", "grid_ms", "lists_ms",
+                                                     "resize_ms")},
         "vcycle_ms": {"mixed": tm["solve_ms"] / max(tm["vcycles"], 1)},
         "fp64": None if fp64 is None else {
             "value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
             "breakdown_ms_per_step": {k: fp64["timing"][k] for k in
-                                      ("step_ms", "solve_ms", "pass0_ms", "pass1_ms")},
-            "pass_GBps": BYTES_PER_PARTICLE["fp64"] * 0.5 * (fp64["timing"]["n0"] +
-                                                            fp64["timing"]["n1"]) /
-            (0.5e-3 * (fp64["timing"]["pass0_ms"] + fp64["timing"]["pass1_ms"])) / 1e9},
+                                      ("step_ms", "solve_ms", "pass_ms", "collide_ms")},
+            "pass_GBps": BYTES_PER_PARTICLE["fp64"] * (fp64["timing"]["n0"] +
+                                                      fp64["timing"]["n1"]) /
+            (1e-3 * fp64["timing"]["pass_ms"]) / 1e9},
         "mixed_over_fp64": None if fp64 is None else mixed["value"] / fp64["value"],
         "fixed_phi_err": vstudy,
         "roofline": roofline,

@@ -199,15 +199,16 @@ const char *rzpic_last_error(void);
 /* Physical constants used inside the library: e, m_e, amu, eps0, k_B, 2 pi. */
 void rzpic_constants(double out[6]);
 /* Device-time accounting of rzpic_step with HIP events on the context's
- * stream (off by default).  rzpic_get_timing synchronises and returns, averaged
- * over the steps recorded since the previous call (then resets):
- *   out[0] steps recorded          out[1] whole step (ms)
- *   out[2] field solve (ms)        out[3] V-cycles per solve
- *   out[4] electron pass kernel    out[5] ion pass kernel (ms), without
- *                                  the collision kernel of their candidates
- *   out[6] finalize + E field (ms) out[7] list maintenance + split (ms)
- *   out[8] electrons, out[9] ions entering the passes (per step)
- *   out[10] collision kernels over the candidates, both species (ms) */
+ * stream (off by default; each event costs the stream a few microseconds).
+ * rzpic_get_timing synchronises and returns, averaged over the steps recorded
+ * since the previous call (then resets):
+ *   out[0] steps recorded            out[1] whole step (ms)
+ *   out[2] field solve (ms)          out[3] V-cycles per solve
+ *   out[4] fused particle pass of both species, the kernel alone (ms)
+ *   out[5] collision kernels of both species + deposit slice sum (ms)
+ *   out[6] finalize + E field (ms)   out[7] list maintenance (ms)
+ *   out[8] electrons, out[9] ions entering the pass (per step)
+ *   out[10] weight split and its re-deposit (ms, 0 on other steps) */
 rzpic_status rzpic_set_timing(rzpic_ctx *ctx, int32_t enable);
 rzpic_status rzpic_get_timing(rzpic_ctx *ctx, double out[11]);
 

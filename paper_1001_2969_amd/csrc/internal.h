@@ -151,6 +151,12 @@ template <typename T>
 hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
                        hipStream_t st);
 template <typename T>
+hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, int b0, int b1,
+                        int threads, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
+                           int threads, hipStream_t st);
+template <typename T>
 hipError_t launch_collide(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
                           hipStream_t st);
 template <typename T>
@@ -195,6 +201,11 @@ hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, doub
                          double half_hr, int64_t cap, int32_t *status, hipStream_t st);
 hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
                                 int nn, hipStream_t st);
+// Both species: slices0[nb0][nn] into acc0 and slices1[nb1][nn] into acc1.
+hipError_t launch_reduce_slices2(unsigned long long *acc0, const unsigned long long *slices0,
+                                 int nb0, unsigned long long *acc1,
+                                 const unsigned long long *slices1, int nb1, int nn,
+                                 hipStream_t st);
 
 // grid.hip
 struct GridArgs {
@@ -249,10 +260,11 @@ hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st);
 hipError_t mg_resid_norm(const MgLevels &m, const double *u, const double *f, int zero_interior,
                          unsigned long long *norm, hipStream_t st);
 hipError_t mg_set_bc(double *phi, int nr, int nz, double V, hipStream_t st);
-// Chooses the cycle path for `lds_budget` bytes of LDS per block: the
-// single-block path when every level fits (sets one_block, S, line_off,
-// tab_stride, solve_lds; the caller allocates tab and res), else the levels of
-// the bottom kernel (K, bottom_lds).
+// Plans both cycle paths for `lds_budget` bytes of LDS per block: the
+// single-block path when every level fits (one_block, S, line_off,
+// tab_stride, solve_lds; the caller allocates tab with line_off[L+1] *
+// tab_stride elements and res), and the levels of the bottom kernel of the
+// multi-launch path (K, bottom_lds).
 void mg_plan(MgLevels &m, int mixed, size_t lds_budget, bool allow_one_block);
 // Single-block path: factor every line matrix of every level (once per solve,
 // after mg_restrict_eps), then run `cycles` V(0,1) cycles on phi in one

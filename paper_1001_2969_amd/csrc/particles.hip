@@ -125,8 +125,11 @@ __device__ __forceinline__ void store(const Parts<T> &p, int64_t i, const PState
 // over).  The merged form records each chunk's dead particles as a lane mask.
 // With M_LDS the block deposits into its own LDS copy of the grid, written out
 // once at the end to its slice.
+//
+// The body takes the block's index lb among the gb blocks of its species, so
+// that one launch can run the passes of both species side by side.
 template <typename T, int MODE>
-__global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
+__device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
 {
     extern __shared__ unsigned long long lds_acc[];
     __shared__ unsigned long long sh_cand;
@@ -136,8 +139,8 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
     const int64_t n = a.cnt->n;
     const int64_t nch = (n + kChunk - 1) / kChunk;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t wave = ((int64_t)lb * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gb * blockDim.x) >> 6;
     const T dt = (T)a.phys.dt;
     const T k1 = (T)a.sp.k1, k2 = (T)a.sp.k2, qm = (T)a.sp.qm;
     constexpr bool kLds = (MODE & M_LDS) != 0;
@@ -146,12 +149,12 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
     const bool mc_on = kMc && a.sp.mc_model != 0;
     unsigned long long *dep = a.acc;
 
-    if (kMc && a.crec && blockIdx.x == 0 && threadIdx.x == 0) a.crec->n_parent = n;
+    if (kMc && a.crec && lb == 0 && threadIdx.x == 0) a.crec->n_parent = n;
     if (kMc && threadIdx.x == 0) {
         sh_cand = 0;
         sh_bucket = 0;
     }
-    if (a.psteps && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.psteps, (unsigned long long)n);
+    if (a.psteps && lb == 0 && threadIdx.x == 0) atomicAdd(a.psteps, (unsigned long long)n);
     if (kLds) {
         for (int g = threadIdx.x; g < m.nn; g += blockDim.x) lds_acc[g] = 0;
         dep = lds_acc;
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
 
     // candidates of this block go to its own bucket of the candidate list
     const int64_t bsize = ((nch + nwaves - 1) / nwaves) * kChunk * (blockDim.x >> 6);
-    int32_t *bucket = a.ch.cand + (int64_t)blockIdx.x * bsize;
+    int32_t *bucket = a.ch.cand + (int64_t)lb * bsize;
     for (int64_t c = wave; c < nch; c += nwaves) {
         const int64_t pi = c * kChunk + lane;
         const bool valid = pi < n;
@@ -252,15 +255,28 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
     if (kMc) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            if (blockIdx.x < a.nbuckets) a.ch.ncand[blockIdx.x] = sh_bucket;
+            if (lb < a.nbuckets) a.ch.ncand[lb] = sh_bucket;
             if (sh_cand) atomicAdd(a.mcstat, sh_cand);
         }
     }
     if (kLds) {
         __syncthreads();
-        unsigned long long *out = a.slices + (size_t)blockIdx.x * m.nn;
+        unsigned long long *out = a.slices + (size_t)lb * m.nn;
         for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds_acc[g];
     }
+}
+
+template <typename T, int MODE> __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
+{
+    pass_body<T, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+// Both species in one launch: blocks [0, b0) take species 0, the rest species 1.
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_pass2(PassArgs<T> a0, PassArgs<T> a1, int b0)
+{
+    if ((int)blockIdx.x < b0) pass_body<T, MODE>(a0, blockIdx.x, b0);
+    else pass_body<T, MODE>(a1, blockIdx.x - b0, gridDim.x - b0);
 }
 
 // Collision kernel over the candidate list (any order: every result below is
@@ -270,7 +286,7 @@ __global__ __launch_bounds__(1024) void k_pass(PassArgs<T> a)
 // the cycle of the candidate and its new particles (first push, absorption,
 // deposit).
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
+__device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int gb)
 {
     extern __shared__ unsigned long long lds_acc[];
     __shared__ unsigned long long sh_stat[1 + kMaxProc];
@@ -287,8 +303,8 @@ __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
     __syncthreads();
     // buckets of the pass blocks; R wavefronts share a bucket (segments of 64)
     const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t wave = ((int64_t)lb * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gb * blockDim.x) >> 6;
     const int64_t nch = (a.cnt->n + kChunk - 1) / kChunk;
     const int64_t NB = a.nbuckets;
     const int64_t pass_waves = NB * a.bucket_waves;
@@ -382,9 +398,21 @@ __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
     if (threadIdx.x >= 1 && threadIdx.x < 1 + kMaxProc && sh_stat[threadIdx.x])
         atomicAdd(a.mcstat + threadIdx.x, sh_stat[threadIdx.x]);
     if (kLds) {
-        unsigned long long *out = a.slices + (size_t)blockIdx.x * m.nn;
+        unsigned long long *out = a.slices + (size_t)lb * m.nn;
         for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds_acc[g];
     }
+}
+
+template <typename T, int MODE> __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
+{
+    collide_body<T, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_collide2(PassArgs<T> a0, PassArgs<T> a1, int b0)
+{
+    if ((int)blockIdx.x < b0) collide_body<T, MODE>(a0, blockIdx.x, b0);
+    else collide_body<T, MODE>(a1, blockIdx.x - b0, gridDim.x - b0);
 }
 
 // Staged new particles of species cs (unmerged form): first push or deposit
@@ -519,6 +547,39 @@ hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t i
     return hipGetLastError();
 }
 
+// Fused merged pass of both species (blocks [0, b0) species 0, [b0, b0+b1)
+// species 1), then their collision kernels in one launch (c0 + c1 blocks).
+template <typename T>
+hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, int b0, int b1,
+                        int threads, size_t lds, hipStream_t st)
+{
+    if (mode == (M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS))
+        hipLaunchKernelGGL((k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS>),
+                           dim3(b0 + b1), dim3(threads), lds, st, a0, a1, b0);
+    else if (mode == (M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS))
+        hipLaunchKernelGGL((k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS>),
+                           dim3(b0 + b1), dim3(threads), 0, st, a0, a1, b0);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
+                           int threads, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_collide2<T, M_FIRST>), dim3(c0 + c1), dim3(threads), 0, st, a0, a1, c0);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pass2<double>(int, const PassArgs<double> &, const PassArgs<double> &,
+                                         int, int, int, size_t, hipStream_t);
+template hipError_t launch_pass2<float>(int, const PassArgs<float> &, const PassArgs<float> &, int,
+                                        int, int, size_t, hipStream_t);
+template hipError_t launch_collide2<double>(const PassArgs<double> &, const PassArgs<double> &,
+                                            int, int, int, hipStream_t);
+template hipError_t launch_collide2<float>(const PassArgs<float> &, const PassArgs<float> &, int,
+                                           int, int, hipStream_t);
 template hipError_t launch_pass<double>(int, const PassArgs<double> &, int, int, size_t,
                                         hipStream_t);
 template hipError_t launch_pass<float>(int, const PassArgs<float> &, int, int, size_t, hipStream_t);

@@ -104,7 +104,7 @@ struct rzpic_ctx {
     unsigned long long *psteps;  // [2]
     // timing: per recorded step 9 events (see mark())
     bool timing = false;
-    static constexpr int kEvPerStep = 11, kPool = 128;
+    static constexpr int kEvPerStep = 9, kPool = 128;
     std::vector<hipEvent_t> evpool;
     int ev_used = 0;        // steps recorded in the pool
     double acc_ms[8] = {};  // accumulated phase times (see flush_timing)
@@ -293,11 +293,9 @@ __global__ void k_prep_solve(int nn, const double *rho, const double *chi, doubl
 void mark(rzpic_ctx *c, int k);
 
 // Particle pass of species s in `mode` (LDS variant chosen here).
-template <typename T>
-rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step, int mark_at = -1)
+template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step)
 {
     PassArgs<T> a = pass_args<T>(c, s, step);
-    if (mark_at >= 0) a.psteps = c->psteps + s;
     int blocks, threads = c->pass_threads;
     size_t lds = 0;
     if ((mode & M_DEP) && c->lds_ok) {
@@ -315,9 +313,7 @@ rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step, int mark_at 
     a.bucket_waves = threads / 64;
     if (blocks * (threads / 64) > kMaxWaves)
         return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", blocks * threads / 64, kMaxWaves);
-    if (mark_at >= 0) mark(c, mark_at);
     HIPCHK(launch_pass<T>(mode, a, blocks, threads, lds, c->st));
-    if (mark_at >= 0) mark(c, mark_at + 1);
     if (mode & M_LDS) HIPCHK(launch_reduce_slices(c->acc[s], c->slices, blocks, c->nn, c->st));
     if (mc) {
         // candidates: outcome, and in the merged form their first push and deposit
@@ -342,7 +338,60 @@ rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint32_t step, int mark_at 
         HIPCHK(launch_collide<T>(cmode, a, cblocks, cthreads, clds, c->st));
         if (cmode & M_LDS) HIPCHK(launch_reduce_slices(c->acc[s], c->slices, cblocks, c->nn, c->st));
     }
-    if (mark_at >= 0) mark(c, mark_at + 2);
+    return RZPIC_OK;
+}
+
+// The merged step's particle work for both species in three launches: the
+// fused pass of both species side by side (each block privatises the grid of
+// its species in LDS), the collision kernels of both species, then the sum of
+// the LDS slices into the two deposit grids.
+template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
+{
+    PassArgs<T> a[2] = {pass_args<T>(c, 0, step), pass_args<T>(c, 1, step)};
+    const int threads = c->pass_threads;
+    int mode = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS;
+    int b[2];
+    size_t lds = 0;
+    if (c->lds_ok) {
+        mode |= M_LDS;
+        lds = (size_t)c->nn * sizeof(unsigned long long);
+        b[0] = c->slice_blocks / 2;
+        b[1] = c->slice_blocks - b[0];
+    } else {
+        for (int s = 0; s < 2; ++s) {
+            int64_t need = (c->sp[s].cap + threads - 1) / threads;
+            int bl = c->cus * (2048 / threads) / 2;
+            b[s] = (int)(need < bl ? (need > 0 ? need : 1) : bl);
+        }
+    }
+    for (int s = 0; s < 2; ++s) {
+        a[s].psteps = c->psteps + s;
+        a[s].nbuckets = b[s];
+        a[s].bucket_waves = threads / 64;
+    }
+    a[1].slices = c->slices + (size_t)b[0] * c->nn;
+    if ((b[0] + b[1]) * (threads / 64) > kMaxWaves)
+        return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", (b[0] + b[1]) * threads / 64,
+                    kMaxWaves);
+    HIPCHK(launch_fill_u64(c->mcstat, 2 * (1 + kMaxProc), c->st));
+    mark(c, 4);
+    HIPCHK(launch_pass2<T>(mode, a[0], a[1], b[0], b[1], threads, lds, c->st));
+    mark(c, 5);
+    // collision kernels: about two wavefronts per electron bucket, one per
+    // ion bucket (ion candidates are rare), deposits by global atomics
+    const int cthreads = 256, wpb = cthreads / 64;
+    int cb[2];
+    for (int s = 0; s < 2; ++s) {
+        const double expect = c->sp[s].p_null * (double)c->sp[s].cap;
+        const int want = expect > 16.0 * b[s] ? 2 * b[s] : b[s];
+        cb[s] = (want + wpb - 1) / wpb;
+        if (a[s].sp.mc_model == RZPIC_MC_NONE) cb[s] = 1;
+    }
+    HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, c->st));
+    if (mode & M_LDS)
+        HIPCHK(launch_reduce_slices2(c->acc[0], a[0].slices, b[0], c->acc[1], a[1].slices, b[1],
+                                     c->nn, c->st));
+    mark(c, 6);
     return RZPIC_OK;
 }
 
@@ -530,8 +579,9 @@ template <typename T> rzpic_status resize_impl(rzpic_ctx *c, int s)
 }
 
 // Timing marks of one step: 0 start, 1 after finalize, 2 after solve,
-// 3 after E, 4/5 around the electron pass kernel, 6 after its collisions,
-// 7/8 around the ion pass kernel, 9 after its collisions, 10 end.
+// 3 after E, 4/5 around the fused pass kernel, 6 after the collision kernels
+// and the slice reduction, 7 after list maintenance, 8 end (after a weight
+// split, if any).
 rzpic_status flush_timing(rzpic_ctx *c);
 
 void mark(rzpic_ctx *c, int k)
@@ -552,13 +602,13 @@ rzpic_status flush_timing(rzpic_ctx *c)
     };
     for (int st = 0; st < c->ev_used; ++st) {
         hipEvent_t *e = &c->evpool[(size_t)st * E];
-        c->acc_ms[0] += el(e[0], e[10]);
+        c->acc_ms[0] += el(e[0], e[8]);
         c->acc_ms[1] += el(e[1], e[2]);
         c->acc_ms[2] += el(e[4], e[5]);
-        c->acc_ms[3] += el(e[7], e[8]);
-        c->acc_ms[4] += el(e[0], e[1]) + el(e[2], e[3]);
-        c->acc_ms[5] += el(e[6], e[7]) + el(e[9], e[10]);
-        c->acc_ms[6] += el(e[5], e[6]) + el(e[8], e[9]);
+        c->acc_ms[3] += el(e[5], e[6]);
+        c->acc_ms[4] += el(e[0], e[1]) + el(e[2], e[4]);
+        c->acc_ms[5] += el(e[6], e[7]);
+        c->acc_ms[6] += el(e[7], e[8]);
     }
     c->acc_steps += c->ev_used;
     c->ev_used = 0;
@@ -579,17 +629,17 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
     mark(c, 2);
     TRY(efield_impl(c));
     mark(c, 3);
-    const int fused = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS;
-    for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, fused, (uint32_t)n, 4 + 3 * s));
+    TRY(run_pass_both<T>(c, (uint32_t)n));
     c->children_pending[0] = c->children_pending[1] = c->sp[0].v.mc_model == RZPIC_MC_ELECTRON;
     c->children_scanned = false;
     TRY(run_fixup<T>(c, 3));
+    mark(c, 7);
     if (c->c.resize_every > 0 && n % c->c.resize_every == c->c.resize_every - 1) {
         for (int s = 0; s < 2; ++s) TRY(resize_impl<T>(c, s));
         for (int s = 0; s < 2; ++s) HIPCHK(launch_fill_u64(c->acc[s], c->nn, c->st));
         for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, M_DEP, 0));
     }
-    mark(c, 10);
+    mark(c, 8);
     if (c->timing) c->ev_used++;
     return RZPIC_OK;
 }

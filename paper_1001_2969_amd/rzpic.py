@@ -297,8 +297,8 @@ class Context:
         """Averages per recorded step (see rzpic_get_timing)."""
         out = (C.c_double * 11)()
         _check(lib().rzpic_get_timing(self.h, C.cast(out, C.c_void_p)))
-        keys = ("steps", "step_ms", "solve_ms", "vcycles", "pass0_ms", "pass1_ms",
-                "grid_ms", "lists_ms", "n0", "n1", "collide_ms")
+        keys = ("steps", "step_ms", "solve_ms", "vcycles", "pass_ms", "collide_ms",
+                "grid_ms", "lists_ms", "n0", "n1", "resize_ms")
         return dict(zip(keys, list(out)))
 
 
