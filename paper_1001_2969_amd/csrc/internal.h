@@ -254,6 +254,7 @@ struct MgLevels {
     size_t tab_stride;     // elements per line table: (3 + 2 S) (nr - 1)
     void *tab;             // line tables, float (mixed) or double
     double *res;           // finest-level residual scratch
+    double *cf64;          // FP64 operator of the finest level: a, b, c, d, e arrays [nz][nr]
     size_t solve_lds;      // LDS bytes of the single-block kernel
 };
 hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st);

@@ -575,6 +575,22 @@ static hipError_t level_sweep(const MgLevels &m, int l, int zero_old, const T *u
 // j + s >= n), s = 2^step, exactly the products the reduction forms.
 template <typename T> __global__ __launch_bounds__(256) void k_factor(MgLevels m, int mixed)
 {
+    if (blockIdx.x >= m.line_off[m.L + 1]) {
+        // the FP64 operator of the finest level, row by row: a, b, c, d, e
+        const int L = m.L, nr = m.nr, n = nr - 1, nn = m.nzl[L] * nr;
+        const int i = blockIdx.x - m.line_off[L + 1] + 1;
+        const double iz2 = 1.0 / (m.hzl[L] * m.hzl[L]), ir2 = 1.0 / (m.hr * m.hr);
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            Coef<double> k = coef<double>(m.eps64[L], nr, i, j, iz2, ir2, m.chi_face);
+            const size_t g = (size_t)i * nr + j;
+            m.cf64[g] = k.a;
+            m.cf64[nn + g] = k.b;
+            m.cf64[2 * (size_t)nn + g] = k.c;
+            m.cf64[3 * (size_t)nn + g] = k.d;
+            m.cf64[4 * (size_t)nn + g] = k.e;
+        }
+        return;
+    }
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     const int line = blockIdx.x;
@@ -628,13 +644,15 @@ template <typename T> __global__ __launch_bounds__(256) void k_factor(MgLevels m
 
 hipError_t mg_factor(const MgLevels &m, int mixed, hipStream_t st)
 {
-    const int lines = m.line_off[m.L + 1], n = m.nr - 1;
+    // one block per line of every level, then one per interior row of the
+    // finest level for its FP64 operator
+    const int blocks = m.line_off[m.L + 1] + (m.nzl[m.L] - 2), n = m.nr - 1;
     const int threads = ((n + 63) / 64) * 64;  // n <= 256 on this path
     if (mixed)
-        hipLaunchKernelGGL((k_factor<float>), dim3(lines), dim3(threads), 3 * n * sizeof(float),
+        hipLaunchKernelGGL((k_factor<float>), dim3(blocks), dim3(threads), 3 * n * sizeof(float),
                            st, m, mixed);
     else
-        hipLaunchKernelGGL((k_factor<double>), dim3(lines), dim3(threads), 3 * n * sizeof(double),
+        hipLaunchKernelGGL((k_factor<double>), dim3(blocks), dim3(threads), 3 * n * sizeof(double),
                            st, m, mixed);
     return hipGetLastError();
 }
@@ -651,6 +669,7 @@ __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *p
                                                 const double *f, double V, int cycles)
 {
     constexpr int SMAX = Q == 1 ? 6 : Q == 2 ? 7 : 8;
+    constexpr int RU = 4;  // residuals per thread computed before any is stored
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     const int L = m.L, nr = m.nr, n = nr - 1, nz = m.nzl[L], S = m.S;
@@ -671,29 +690,79 @@ __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *p
     __syncthreads();
     const double iz2 = 1.0 / (m.hzl[L] * m.hzl[L]), ir2 = 1.0 / (m.hr * m.hr);
     for (int cyc = 0; cyc < cycles; ++cyc) {
-        // ---- down
+        // ---- down.  Memory accesses carry no lane-dependent branch (indices
+        // are clamped instead), so the loads of four unknowns per thread are in
+        // flight together.
         if (mixed || L > 1) {
             T *fL = lev(mixed ? L : 1) + (size_t)(mixed ? nz : 0) * nr;  // used when mixed
-            for (int g = threadIdx.x; g < (nz - 2) * n; g += blockDim.x) {
-                const int i = 1 + g / n, j = g - (i - 1) * n;
-                Coef<double> k = coef<double>(m.eps64[L], nr, i, j, iz2, ir2, m.chi_face);
-                const double *u = phi + (size_t)i * nr + j;
-                double Au = k.b * u[0] - k.a * u[-nr] - k.c * u[nr] - k.e * u[1];
-                if (j > 0) Au -= k.d * u[-1];
-                const double r = f[(size_t)i * nr + j] - Au;
-                if (L > 1) m.res[(size_t)i * nr + j] = r;
-                if (mixed) fL[(size_t)i * nr + j] = (T)r;
+            const int nn = nz * nr, NI = (nz - 2) * n;
+            // all residuals of a chunk first (loads only), then their stores:
+            // a store before a load would make every later load wait for it.
+            // Unknown g = (i-1) n + j walks with the block stride, (i, j)
+            // carried along without a division.
+            const double *ca = m.cf64, *cb = ca + nn, *cc = cb + nn, *cd = cc + nn, *ce = cd + nn;
+            const int si = (int)blockDim.x / n, sj = (int)blockDim.x - si * n;
+            int i0 = 1 + (int)threadIdx.x / n, j0 = (int)threadIdx.x - (i0 - 1) * n;
+            for (int g0 = threadIdx.x; g0 < NI; g0 += RU * blockDim.x) {
+                double r[RU];
+                int ii = i0, jj = j0;
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    // clamp past the end to the last unknown (loads stay in bounds)
+                    const bool in = g0 + u * (int)blockDim.x < NI;
+                    const int i = in ? ii : nz - 2, j = in ? jj : n - 1;
+                    const int o = i * nr + j, w = j > 0 ? o - 1 : o;
+                    const double Au = cb[o] * phi[o] - ca[o] * phi[o - nr] - cc[o] * phi[o + nr] -
+                                      ce[o] * phi[o + 1] - cd[o] * phi[w];  // d = 0 on the axis
+                    r[u] = f[o] - Au;
+                    ii += si;
+                    jj += sj;
+                    if (jj >= n) {
+                        jj -= n;
+                        ++ii;
+                    }
+                }
+                ii = i0;
+                jj = j0;
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    if (g0 + u * (int)blockDim.x < NI) {
+                        const size_t k = (size_t)ii * nr + jj;
+                        if (L > 1) m.res[k] = r[u];
+                        if (mixed) fL[k] = (T)r[u];
+                    }
+                    ii += si;
+                    jj += sj;
+                    if (jj >= n) {
+                        jj -= n;
+                        ++ii;
+                    }
+                }
+                i0 = ii;
+                j0 = jj;
             }
             __syncthreads();
             if (L > 1) {
-                const int nzc = m.nzl[L - 1];
+                const int nzc = m.nzl[L - 1], NC = (nzc - 2) * n;
                 T *fc = lev(L - 1) + (size_t)nzc * nr;
-                for (int g = threadIdx.x; g < (nzc - 2) * n; g += blockDim.x) {
-                    const int I = 1 + g / n, j = g - (I - 1) * n;
-                    const double *col = m.res + j;
-                    double v = 0.25 * col[(size_t)(2 * I - 1) * nr] + 0.5 * col[(size_t)(2 * I) * nr] +
+                for (int g0 = threadIdx.x; g0 < NC; g0 += 4 * blockDim.x) {
+                    double v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int g = min(g0 + u * (int)blockDim.x, NC - 1);
+                        const int I = 1 + g / n, j = g - (I - 1) * n;
+                        const double *col = m.res + j;
+                        v[u] = 0.25 * col[(size_t)(2 * I - 1) * nr] + 0.5 * col[(size_t)(2 * I) * nr] +
                                0.25 * col[(size_t)(2 * I + 1) * nr];
-                    fc[(size_t)I * nr + j] = (T)v;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int g = g0 + u * (int)blockDim.x;
+                        if (g < NC) {
+                            const int I = 1 + g / n, j = g - (I - 1) * n;
+                            fc[(size_t)I * nr + j] = (T)v[u];
+                        }
+                    }
                 }
                 __syncthreads();
                 for (int l = L - 2; l >= 1; --l) {
@@ -726,40 +795,46 @@ __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *p
                     const int i = parity ? 2 * t + 1 : 2 * t + 2;
                     const T *tb = (const T *)m.tab + (size_t)(m.line_off[l] + i - 1) * m.tab_stride;
                     T R[Q], bf[Q], k1[SMAX][Q], k2[SMAX][Q];
+                    double ph[Q];  // phi of the line (mixed finest level: phi += x)
+                    // every load below is unconditional (clamped index), the
+                    // lane and level conditions select afterwards
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
                         const int j = q * 64 + lane;
                         const bool ok = j < n;
-                        const int jj = ok ? j : 0;
-                        const T ta = tb[jj], tc = tb[n + jj];
-                        bf[q] = ok ? tb[2 * n + jj] : (T)1;
+                        const int jj = ok ? j : n - 1;
+                        const T ta = tb[jj], tc = tb[n + jj], tbf = tb[2 * n + jj];
+                        bf[q] = ok ? tbf : (T)1;
 #pragma unroll
                         for (int st = 0; st < SMAX; ++st) {
+                            const int sc = st < S ? st : S - 1;
+                            const T v1 = tb[(size_t)(3 + 2 * sc) * n + jj];
+                            const T v2 = tb[(size_t)(4 + 2 * sc) * n + jj];
                             const bool have = ok && st < S;
-                            k1[st][q] = have ? tb[(size_t)(3 + 2 * st) * n + jj] : (T)0;
-                            k2[st][q] = have ? tb[(size_t)(4 + 2 * st) * n + jj] : (T)0;
+                            k1[st][q] = have ? v1 : (T)0;
+                            k2[st][q] = have ? v2 : (T)0;
                         }
+                        // neighbour rows: coarse correction injected into the even
+                        // rows i-1, i+1 (their index halves), or the level's own rows
+                        const T cl = uc[(size_t)((i - 1) >> 1) * nr + jj];
+                        const T ch = uc[(size_t)((i + 1) >> 1) * nr + jj];
+                        const bool inj = parity && l > 1;
+                        const T cl_ = (inj && i - 1 > 0) ? cl : (T)0;
+                        const T ch_ = (inj && i + 1 < nzl - 1) ? ch : (T)0;
                         T lo, hi, g;
+                        ph[q] = 0.0;
                         if (direct) {
-                            double vlo = phi[(size_t)(i - 1) * nr + jj];
-                            double vhi = phi[(size_t)(i + 1) * nr + jj];
-                            if (parity && l > 1) {
-                                if (i - 1 > 0) vlo += uc[(size_t)((i - 1) >> 1) * nr + jj];
-                                if (i + 1 < nzl - 1) vhi += uc[(size_t)((i + 1) >> 1) * nr + jj];
-                            }
-                            lo = (T)vlo;
-                            hi = (T)vhi;
+                            const double vlo = phi[(size_t)(i - 1) * nr + jj];
+                            const double vhi = phi[(size_t)(i + 1) * nr + jj];
+                            lo = (T)(vlo + (double)cl_);
+                            hi = (T)(vhi + (double)ch_);
                             g = (T)f[(size_t)i * nr + jj];
                         } else {
-                            if (parity) {
-                                lo = (l > 1 && i - 1 > 0) ? uc[(size_t)((i - 1) >> 1) * nr + jj] : (T)0;
-                                hi = (l > 1 && i + 1 < nzl - 1) ? uc[(size_t)((i + 1) >> 1) * nr + jj]
-                                                                : (T)0;
-                            } else {
-                                lo = ul[(size_t)(i - 1) * nr + jj];
-                                hi = ul[(size_t)(i + 1) * nr + jj];
-                            }
+                            const T ol = ul[(size_t)(i - 1) * nr + jj], oh = ul[(size_t)(i + 1) * nr + jj];
+                            lo = parity ? cl_ : ol;
+                            hi = parity ? ch_ : oh;
                             g = fl[(size_t)i * nr + jj];
+                            if (fine) ph[q] = phi[(size_t)i * nr + jj];
                         }
                         R[q] = ok ? g + ta * lo + tc * hi : (T)0;
                     }
@@ -804,7 +879,7 @@ __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *p
                             phi[at] = (double)x;
                         } else {
                             ul[at] = x;
-                            if (fine) phi[at] += (double)x;
+                            if (fine) phi[at] = ph[q] + (double)x;
                         }
                     }
                 }

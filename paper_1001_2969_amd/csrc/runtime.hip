@@ -778,6 +778,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
             A(t, tab) m.tab = t;
         }
         A(m.res, nn)
+        A(m.cf64, 5 * nn)
     }
 #undef A
     // host tables: 1/(2j+1), weighting volumes (Sec. 2.4, radial neighbours
