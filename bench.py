@@ -30,6 +30,28 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE = {"mixed": 8 * 4 + 8 + 7 * 4, "fp64": 8 * 8 + 8 + 7 * 8}
 
 
+def measured_traffic():
+    """HBM bytes per launch of the fused pass from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
+    the kernel sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_pass2_hbm_traffic_rf129x65.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    t = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    hs = re.search(r"^kernel_sources_sha256: ([0-9a-f]{64})$", text, re.M)
+    if not t or not hs:
+        return None
+    h = hashlib.sha256()
+    for f in ("particles.hip", "device.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1001_2969_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return float(t.group(1)) if h.hexdigest() == hs.group(1) else None
+
+
 def run_gpu(w, precision, steps, warmup, timing_steps=50):
     """Throughput over `steps` merged steps with nothing else on the stream,
     then `timing_steps` more with the library's HIP events around each phase
@@ -224,7 +246,8 @@ def main():
     achieved = bpp * n_launch / (t_launch_ms * 1e-3) / 1e9 if t_launch_ms > 0 else None
     roofline = {"kernel": "k_pass2<float, fused, LDS deposit>", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                "traffic": measured_traffic(),
                 "bytes_per_particle": bpp, "particles_per_launch": n_launch,
                 "avg_launch_ms": t_launch_ms}
 
