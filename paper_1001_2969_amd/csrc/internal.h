@@ -248,7 +248,9 @@ struct MgLevels {
     // Single-block cycles: every level's right-hand side and correction held
     // in LDS (FP64: the finest level is phi itself, in global memory), the
     // line matrices factored beforehand into per-line tables.
-    int one_block;         // 1: this path is used
+    int one_block;         // 1: every cycle in one single-workgroup launch
+    int split;             // 1: per cycle a residual/restriction launch, the coarse
+                           //    levels in one workgroup, the finest level's sweep
     int S;                 // reduction steps of an r-line (ceil(log2(nr - 1)))
     int line_off[kMaxLevels + 2];  // first table line of each level; line_off[L+1] = total
     size_t tab_stride;     // elements per line table: (3 + 2 S) (nr - 1)
@@ -266,7 +268,9 @@ hipError_t mg_set_bc(double *phi, int nr, int nz, double V, hipStream_t st);
 // tab_stride, solve_lds; the caller allocates tab with line_off[L+1] *
 // tab_stride elements and res), and the levels of the bottom kernel of the
 // multi-launch path (K, bottom_lds).
-void mg_plan(MgLevels &m, int mixed, size_t lds_budget, bool allow_one_block);
+// path: 0 split where it fits (single block for one-line meshes), 1 single
+// block where it fits, 2 multi-launch.
+void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path);
 // Single-block path: factor every line matrix of every level (once per solve,
 // after mg_restrict_eps), then run `cycles` V(0,1) cycles on phi in one
 // launch, the Dirichlet values of phi set first.

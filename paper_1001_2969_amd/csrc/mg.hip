@@ -664,9 +664,83 @@ hipError_t mg_factor(const MgLevels &m, int mixed, hipStream_t st)
 // unknowns per lane (j = q*64 + lane); the reduction steps exchange
 // right-hand sides across lanes with shuffles, so a line needs no block
 // barrier, and the block synchronises once per half-sweep.
+// One r-line per wavefront: Q unknowns per lane (j = q*64 + lane).  The
+// line's table (coefficients a, c of the neighbouring lines, the final
+// diagonal and the reduction multipliers of every step) is loaded with
+// clamped indices, so that no load sits behind a lane-dependent branch.
+template <typename T, int Q, int SMAX> struct LineTab {
+    T ta[Q], tc[Q], bf[Q], k1[SMAX][Q], k2[SMAX][Q];
+};
+
+template <typename T, int Q, int SMAX>
+__device__ __forceinline__ void line_tab_load(const T *tb, int n, int S, int lane,
+                                              LineTab<T, Q, SMAX> &t)
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = q * 64 + lane;
+        const bool ok = j < n;
+        const int jj = ok ? j : n - 1;
+        t.ta[q] = tb[jj];
+        t.tc[q] = tb[n + jj];
+        const T b = tb[2 * n + jj];
+        t.bf[q] = ok ? b : (T)1;
+#pragma unroll
+        for (int st = 0; st < SMAX; ++st) {
+            const int sc = st < S ? st : S - 1;
+            const T v1 = tb[(size_t)(3 + 2 * sc) * n + jj];
+            const T v2 = tb[(size_t)(4 + 2 * sc) * n + jj];
+            const bool have = ok && st < S;
+            t.k1[st][q] = have ? v1 : (T)0;
+            t.k2[st][q] = have ? v2 : (T)0;
+        }
+    }
+}
+
+// The reduction steps on the right-hand sides R (zero for j >= n), then the
+// solution x = R / b_final in R.  Neighbours at distance s come through lane
+// shuffles (s < 64) or other registers of the same lane (s >= 64).
+template <typename T, int Q, int SMAX>
+__device__ __forceinline__ void line_pcr(T (&R)[Q], const LineTab<T, Q, SMAX> &t, int S, int lane)
+{
+#pragma unroll
+    for (int st = 0; st < SMAX; ++st) {
+        if (st >= S) break;
+        const int s = 1 << st;
+        T nR[Q];
+        if (s < 64) {
+            T dn[Q], up[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                dn[q] = __shfl(R[q], (lane - s) & 63, 64);
+                up[q] = __shfl(R[q], (lane + s) & 63, 64);
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const T left = lane >= s ? dn[q] : (q > 0 ? dn[q > 0 ? q - 1 : 0] : (T)0);
+                const T right = lane + s < 64 ? up[q] : (q + 1 < Q ? up[q + 1 < Q ? q + 1 : q] : (T)0);
+                nR[q] = R[q] - left * t.k1[st][q] - right * t.k2[st][q];
+            }
+        } else {
+            const int kq = s >> 6;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const T left = q >= kq ? R[q >= kq ? q - kq : 0] : (T)0;
+                const T right = q + kq < Q ? R[q + kq < Q ? q + kq : q] : (T)0;
+                nR[q] = R[q] - left * t.k1[st][q] - right * t.k2[st][q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) R[q] = nR[q];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) R[q] = R[q] / t.bf[q];
+}
+
 template <typename T, int Q>
 __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *phi,
-                                                const double *f, double V, int cycles)
+                                                const double *f, double V, int cycles,
+                                                int coarse)
 {
     constexpr int SMAX = Q == 1 ? 6 : Q == 2 ? 7 : 8;
     constexpr int RU = 4;  // residuals per thread computed before any is stored
@@ -679,6 +753,90 @@ __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *p
         for (int q = 1; q < l; ++q) o += 2 * (size_t)m.nzl[q] * nr;
         return sm + o;
     };
+    // ---- up: exact coarsest line, then prolongation + zebra sweep per level
+    auto up = [&](int top) {
+    for (int l = 1; l <= top; ++l) {
+        const int nzl = m.nzl[l];
+        const bool fine = l == L, direct = fine && !mixed;
+        // LDS rows of this level (not used when direct) and of the level below
+        T *ul = lev(direct ? 1 : l);
+        const T *fl = ul + (size_t)(direct ? 0 : nzl) * nr;
+        const T *uc = lev(l > 1 ? l - 1 : 1);
+        for (int parity = 1; parity >= 0; --parity) {
+            const int lines = parity ? (nzl - 1) / 2 : (nzl - 3) / 2;
+            for (int t = wave; t < lines; t += nwaves) {
+                const int i = parity ? 2 * t + 1 : 2 * t + 2;
+                const T *tb = (const T *)m.tab + (size_t)(m.line_off[l] + i - 1) * m.tab_stride;
+                LineTab<T, Q, SMAX> tab;
+                line_tab_load<T, Q, SMAX>(tb, n, S, lane, tab);
+                T R[Q];
+                double ph[Q];  // phi of the line (mixed finest level: phi += x)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int j = q * 64 + lane;
+                    const bool ok = j < n;
+                    const int jj = ok ? j : n - 1;
+                    // neighbour rows: coarse correction injected into the even
+                    // rows i-1, i+1 (their index halves), or the level's own rows
+                    const T cl = uc[(size_t)((i - 1) >> 1) * nr + jj];
+                    const T ch = uc[(size_t)((i + 1) >> 1) * nr + jj];
+                    const bool inj = parity && l > 1;
+                    const T cl_ = (inj && i - 1 > 0) ? cl : (T)0;
+                    const T ch_ = (inj && i + 1 < nzl - 1) ? ch : (T)0;
+                    T lo, hi, g;
+                    ph[q] = 0.0;
+                    if (direct) {
+                        const double vlo = phi[(size_t)(i - 1) * nr + jj];
+                        const double vhi = phi[(size_t)(i + 1) * nr + jj];
+                        lo = (T)(vlo + (double)cl_);
+                        hi = (T)(vhi + (double)ch_);
+                        g = (T)f[(size_t)i * nr + jj];
+                    } else {
+                        const T ol = ul[(size_t)(i - 1) * nr + jj], oh = ul[(size_t)(i + 1) * nr + jj];
+                        lo = parity ? cl_ : ol;
+                        hi = parity ? ch_ : oh;
+                        g = fl[(size_t)i * nr + jj];
+                        if (fine) ph[q] = phi[(size_t)i * nr + jj];
+                    }
+                    R[q] = ok ? g + tab.ta[q] * lo + tab.tc[q] * hi : (T)0;
+                }
+                line_pcr<T, Q, SMAX>(R, tab, S, lane);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int j = q * 64 + lane;
+                    if (j >= n) continue;
+                    const T x = R[q];
+                    const size_t at = (size_t)i * nr + j;
+                    if (direct) {
+                        phi[at] = (double)x;
+                    } else {
+                        ul[at] = x;
+                        if (fine) phi[at] = ph[q] + (double)x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    };
+    if (coarse) {
+        // levels 1..L-1 only: their right-hand sides come from a multi-block
+        // residual and restriction launch, the correction u^{L-1} goes back to
+        // global memory for the finest level's launch
+        for (int l = 1; l <= L - 1; ++l) {
+            const size_t sz = (size_t)m.nzl[l] * nr;
+            T *fl = lev(l) + sz;
+            const T *gf = mixed ? (const T *)m.f32[l] : (const T *)m.f64[l];
+            for (size_t t = threadIdx.x; t < sz; t += blockDim.x) fl[t] = gf[t];
+        }
+        __syncthreads();
+        up(L - 1);
+        const size_t szc = (size_t)m.nzl[L - 1] * nr;
+        const T *uc = lev(L - 1);
+        T *gu = mixed ? (T *)m.u32[L - 1] : (T *)m.u64[L - 1];
+        for (size_t t = threadIdx.x; t < szc; t += blockDim.x) gu[t] = uc[t];
+        return;
+    }
     for (int t = threadIdx.x; t < nr + nz; t += blockDim.x) {
         if (t < nr) {
             phi[t] = t < nr - 1 ? V : 0.0;
@@ -688,7 +846,6 @@ __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *p
         }
     }
     __syncthreads();
-    const double iz2 = 1.0 / (m.hzl[L] * m.hzl[L]), ir2 = 1.0 / (m.hr * m.hr);
     for (int cyc = 0; cyc < cycles; ++cyc) {
         // ---- down.  Memory accesses carry no lane-dependent branch (indices
         // are clamped instead), so the loads of four unknowns per thread are in
@@ -781,141 +938,143 @@ __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *p
                 }
             }
         }
-        // ---- up: exact coarsest line, then prolongation + zebra sweep per level
-        for (int l = 1; l <= L; ++l) {
-            const int nzl = m.nzl[l];
-            const bool fine = l == L, direct = fine && !mixed;
-            // LDS rows of this level (not used when direct) and of the level below
-            T *ul = lev(direct ? 1 : l);
-            const T *fl = ul + (size_t)(direct ? 0 : nzl) * nr;
-            const T *uc = lev(l > 1 ? l - 1 : 1);
-            for (int parity = 1; parity >= 0; --parity) {
-                const int lines = parity ? (nzl - 1) / 2 : (nzl - 3) / 2;
-                for (int t = wave; t < lines; t += nwaves) {
-                    const int i = parity ? 2 * t + 1 : 2 * t + 2;
-                    const T *tb = (const T *)m.tab + (size_t)(m.line_off[l] + i - 1) * m.tab_stride;
-                    T R[Q], bf[Q], k1[SMAX][Q], k2[SMAX][Q];
-                    double ph[Q];  // phi of the line (mixed finest level: phi += x)
-                    // every load below is unconditional (clamped index), the
-                    // lane and level conditions select afterwards
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        const int j = q * 64 + lane;
-                        const bool ok = j < n;
-                        const int jj = ok ? j : n - 1;
-                        const T ta = tb[jj], tc = tb[n + jj], tbf = tb[2 * n + jj];
-                        bf[q] = ok ? tbf : (T)1;
-#pragma unroll
-                        for (int st = 0; st < SMAX; ++st) {
-                            const int sc = st < S ? st : S - 1;
-                            const T v1 = tb[(size_t)(3 + 2 * sc) * n + jj];
-                            const T v2 = tb[(size_t)(4 + 2 * sc) * n + jj];
-                            const bool have = ok && st < S;
-                            k1[st][q] = have ? v1 : (T)0;
-                            k2[st][q] = have ? v2 : (T)0;
-                        }
-                        // neighbour rows: coarse correction injected into the even
-                        // rows i-1, i+1 (their index halves), or the level's own rows
-                        const T cl = uc[(size_t)((i - 1) >> 1) * nr + jj];
-                        const T ch = uc[(size_t)((i + 1) >> 1) * nr + jj];
-                        const bool inj = parity && l > 1;
-                        const T cl_ = (inj && i - 1 > 0) ? cl : (T)0;
-                        const T ch_ = (inj && i + 1 < nzl - 1) ? ch : (T)0;
-                        T lo, hi, g;
-                        ph[q] = 0.0;
-                        if (direct) {
-                            const double vlo = phi[(size_t)(i - 1) * nr + jj];
-                            const double vhi = phi[(size_t)(i + 1) * nr + jj];
-                            lo = (T)(vlo + (double)cl_);
-                            hi = (T)(vhi + (double)ch_);
-                            g = (T)f[(size_t)i * nr + jj];
-                        } else {
-                            const T ol = ul[(size_t)(i - 1) * nr + jj], oh = ul[(size_t)(i + 1) * nr + jj];
-                            lo = parity ? cl_ : ol;
-                            hi = parity ? ch_ : oh;
-                            g = fl[(size_t)i * nr + jj];
-                            if (fine) ph[q] = phi[(size_t)i * nr + jj];
-                        }
-                        R[q] = ok ? g + ta * lo + tc * hi : (T)0;
-                    }
-#pragma unroll
-                    for (int st = 0; st < SMAX; ++st) {
-                        if (st >= S) break;
-                        const int s = 1 << st;
-                        T nR[Q];
-                        if (s < 64) {
-                            T dn[Q], up[Q];
-#pragma unroll
-                            for (int q = 0; q < Q; ++q) {
-                                dn[q] = __shfl(R[q], (lane - s) & 63, 64);
-                                up[q] = __shfl(R[q], (lane + s) & 63, 64);
-                            }
-#pragma unroll
-                            for (int q = 0; q < Q; ++q) {
-                                const T left = lane >= s ? dn[q] : (q > 0 ? dn[q > 0 ? q - 1 : 0] : (T)0);
-                                const T right = lane + s < 64 ? up[q]
-                                                              : (q + 1 < Q ? up[q + 1 < Q ? q + 1 : q] : (T)0);
-                                nR[q] = R[q] - left * k1[st][q] - right * k2[st][q];
-                            }
-                        } else {
-                            const int kq = s >> 6;
-#pragma unroll
-                            for (int q = 0; q < Q; ++q) {
-                                const T left = q >= kq ? R[q >= kq ? q - kq : 0] : (T)0;
-                                const T right = q + kq < Q ? R[q + kq < Q ? q + kq : q] : (T)0;
-                                nR[q] = R[q] - left * k1[st][q] - right * k2[st][q];
-                            }
-                        }
-#pragma unroll
-                        for (int q = 0; q < Q; ++q) R[q] = nR[q];
-                    }
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        const int j = q * 64 + lane;
-                        if (j >= n) continue;
-                        const T x = R[q] / bf[q];
-                        const size_t at = (size_t)i * nr + j;
-                        if (direct) {
-                            phi[at] = (double)x;
-                        } else {
-                            ul[at] = x;
-                            if (fine) phi[at] = ph[q] + (double)x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        up(L);
     }
 }
 
-hipError_t mg_solve_block(const MgLevels &m, int mixed, double *phi, const double *f, double V,
-                          int cycles, hipStream_t st)
+static hipError_t solve_block(const MgLevels &m, int mixed, double *phi, const double *f, double V,
+                              int cycles, int coarse, hipStream_t st)
 {
     const int n = m.nr - 1;
     const size_t lds = m.solve_lds;
     if (mixed) {
         if (n <= 64)
             hipLaunchKernelGGL((k_solve<float, 1>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
-                               cycles);
+                               cycles, coarse);
         else if (n <= 128)
             hipLaunchKernelGGL((k_solve<float, 2>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
-                               cycles);
+                               cycles, coarse);
         else
             hipLaunchKernelGGL((k_solve<float, 4>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
-                               cycles);
+                               cycles, coarse);
     } else {
         if (n <= 64)
             hipLaunchKernelGGL((k_solve<double, 1>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f,
-                               V, cycles);
+                               V, cycles, coarse);
         else
             hipLaunchKernelGGL((k_solve<double, 2>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f,
-                               V, cycles);
+                               V, cycles, coarse);
     }
     return hipGetLastError();
 }
 
-void mg_plan(MgLevels &m, int mixed, size_t lds_budget, bool allow_one_block)
+// Finest level of the split cycle, one block of two wavefronts per even line
+// i = 2b+2.  Wavefronts 0 and 1 solve the odd lines i-1 and i+1 (line i+1 is
+// solved again, identically, by block b+1), then wavefront 0 solves line i
+// from them.  Block b owns lines i-1 and i, the last block also line nz-2.
+// FP64: phi_in (old values, plus the injected coarse correction on the even
+// rows) to phi_out.  Mixed: the correction from zero with the FP32 residual as
+// right-hand side, added to phi in place (phi_in == phi_out).
+template <typename T, int Q>
+__global__ __launch_bounds__(128) void k_fine(MgLevels m, int mixed, const double *phi_in,
+                                              double *phi_out, const double *f)
+{
+    constexpr int SMAX = Q == 1 ? 6 : Q == 2 ? 7 : 8;
+    __shared__ T xs[2][Q * 64];
+    const int L = m.L, nr = m.nr, n = nr - 1, nz = m.nzl[L], S = m.S;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = 2 * blockIdx.x + 2;
+    const bool last = i + 1 == nz - 2;
+    const T *uc = mixed ? (const T *)m.u32[L - 1] : (const T *)m.u64[L - 1];
+    const T *fr = (const T *)m.f32[L];  // mixed: FP32 residual
+    const T *tab0 = (const T *)m.tab + (size_t)(m.line_off[L] - 1) * m.tab_stride;
+    {
+        const int io = i - 1 + 2 * w;
+        LineTab<T, Q, SMAX> tb;
+        line_tab_load<T, Q, SMAX>(tab0 + (size_t)io * m.tab_stride, n, S, lane, tb);
+        T R[Q];
+        double ph[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = q * 64 + lane;
+            const bool ok = j < n;
+            const int jj = ok ? j : n - 1;
+            const T cl = uc[(size_t)((io - 1) >> 1) * nr + jj];
+            const T ch = uc[(size_t)((io + 1) >> 1) * nr + jj];
+            const T cl_ = io - 1 > 0 ? cl : (T)0;
+            const T ch_ = io + 1 < nz - 1 ? ch : (T)0;
+            const double pl = phi_in[(size_t)(io - 1) * nr + jj];
+            const double phh = phi_in[(size_t)(io + 1) * nr + jj];
+            ph[q] = phi_in[(size_t)io * nr + jj];
+            T lo, hi, g;
+            if (mixed) {
+                lo = cl_;
+                hi = ch_;
+                g = fr[(size_t)io * nr + jj];
+            } else {
+                lo = (T)(pl + (double)cl_);
+                hi = (T)(phh + (double)ch_);
+                g = (T)f[(size_t)io * nr + jj];
+            }
+            R[q] = ok ? g + tb.ta[q] * lo + tb.tc[q] * hi : (T)0;
+        }
+        line_pcr<T, Q, SMAX>(R, tb, S, lane);
+        const bool own = w == 0 || last;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = q * 64 + lane;
+            if (j >= n) continue;
+            xs[w][j] = R[q];
+            if (own) phi_out[(size_t)io * nr + j] = mixed ? ph[q] + (double)R[q] : (double)R[q];
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+        LineTab<T, Q, SMAX> tb;
+        line_tab_load<T, Q, SMAX>(tab0 + (size_t)i * m.tab_stride, n, S, lane, tb);
+        T R[Q];
+        double ph[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = q * 64 + lane;
+            const bool ok = j < n;
+            const int jj = ok ? j : n - 1;
+            ph[q] = phi_in[(size_t)i * nr + jj];
+            const T g = mixed ? fr[(size_t)i * nr + jj] : (T)f[(size_t)i * nr + jj];
+            R[q] = ok ? g + tb.ta[q] * xs[0][jj] + tb.tc[q] * xs[1][jj] : (T)0;
+        }
+        line_pcr<T, Q, SMAX>(R, tb, S, lane);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = q * 64 + lane;
+            if (j >= n) continue;
+            phi_out[(size_t)i * nr + j] = mixed ? ph[q] + (double)R[q] : (double)R[q];
+        }
+    }
+}
+
+template <typename T>
+static hipError_t fine_sweep(const MgLevels &m, int mixed, const double *phi_in, double *phi_out,
+                             const double *f, hipStream_t st)
+{
+    const int n = m.nr - 1, blocks = (m.nzl[m.L] - 3) / 2;
+    if (blocks <= 0) return hipSuccess;
+    if (n <= 64)
+        hipLaunchKernelGGL((k_fine<T, 1>), dim3(blocks), dim3(128), 0, st, m, mixed, phi_in, phi_out, f);
+    else if (n <= 128)
+        hipLaunchKernelGGL((k_fine<T, 2>), dim3(blocks), dim3(128), 0, st, m, mixed, phi_in, phi_out, f);
+    else
+        hipLaunchKernelGGL((k_fine<T, 4>), dim3(blocks), dim3(128), 0, st, m, mixed, phi_in, phi_out, f);
+    return hipGetLastError();
+}
+
+hipError_t mg_solve_block(const MgLevels &m, int mixed, double *phi, const double *f, double V,
+                          int cycles, hipStream_t st)
+{
+    return solve_block(m, mixed, phi, f, V, cycles, 0, st);
+}
+
+void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path)
 {
     const size_t es = mixed ? sizeof(float) : sizeof(double);
     const int n = m.nr - 1;
@@ -933,7 +1092,9 @@ void mg_plan(MgLevels &m, int mixed, size_t lds_budget, bool allow_one_block)
     size_t lds = 0;
     for (int l = 1; l <= (mixed ? m.L : m.L - 1); ++l) lds += 2 * (size_t)m.nzl[l] * m.nr * es;
     m.solve_lds = lds;
-    m.one_block = allow_one_block && n <= (mixed ? 256 : 128) && lds <= lds_budget;
+    const bool fits = n <= (mixed ? 256 : 128) && lds <= lds_budget;
+    m.split = fits && path == 0 && m.L > 1;
+    m.one_block = fits && (path == 1 || (path == 0 && m.L == 1));
     // multi-launch path: levels of the bottom kernel
     m.K = 0;
     m.bottom_lds = 0;
@@ -994,6 +1155,17 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
             hipLaunchKernelGGL((k_down<double>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256), lds,
                                st, (const double *)phi, f, m, mixed, cpb);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (m.split) {
+        // coarse levels in one workgroup from the restricted residuals, then
+        // the finest level's zebra sweep with pre-factored lines
+        if ((e = solve_block(m, mixed, phi, f, 0.0, 1, 1, st)) != hipSuccess) return e;
+        if (mixed) return fine_sweep<float>(m, mixed, phi, phi, f, st);
+        e = fine_sweep<double>(m, mixed, phi, phi_alt, f, st);
+        double *t = phi;
+        phi = phi_alt;
+        phi_alt = t;
+        return e;
     }
     int done = m.K;
     if (m.K >= 1) {

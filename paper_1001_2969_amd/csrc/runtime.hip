@@ -459,7 +459,7 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
     HIPCHK(mg_restrict_eps(c->mg, c->mixed, c->st));
     const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
     const bool ob = c->mg.one_block != 0;
-    if (ob) HIPCHK(mg_factor(c->mg, c->mixed, c->st));
+    if (ob || c->mg.split) HIPCHK(mg_factor(c->mg, c->mixed, c->st));
     auto cycles_run = [&](int kk) -> hipError_t {
         if (ob) return mg_solve_block(c->mg, c->mixed, c->phi, c->f, V, kk, c->st);
         for (int q = 0; q < kk; ++q) {
@@ -767,8 +767,17 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
             A(m.u64[l], sz) A(m.f64[l], sz)
         }
     }
-    mg_plan(m, c->mixed, c->lds_block, !std::getenv("RZPIC_MG_MULTI"));
-    if (m.one_block) {
+    {
+        // cycle path: the split form unless RZPIC_MG_PATH names another
+        // ("block" or "multi"; for tests and measurements)
+        int path = 0;
+        if (const char *e = std::getenv("RZPIC_MG_PATH")) {
+            if (!std::strcmp(e, "block")) path = 1;
+            else if (!std::strcmp(e, "multi")) path = 2;
+        }
+        mg_plan(m, c->mixed, c->lds_block, path);
+    }
+    if (m.one_block || m.split) {
         const size_t tab = (size_t)m.line_off[L + 1] * m.tab_stride;
         if (c->mixed) {
             float *t;

@@ -101,13 +101,10 @@ def run_mixed(w, nsteps, *, state=None, own_init=False, capacity_factor=2.0, che
     return o, g, report
 
 
-@pytest.mark.parametrize("path", ["one_block", "multi_launch"])
+@pytest.mark.parametrize("path", ["block", "split", "multi"])
 @pytest.mark.parametrize("mesh", [(33, 33), (129, 65), (65, 3)])
 def test_mixed_solve(mesh, path, monkeypatch):
-    if path == "multi_launch":
-        monkeypatch.setenv("RZPIC_MG_MULTI", "1")
-    else:
-        monkeypatch.delenv("RZPIC_MG_MULTI", raising=False)
+    monkeypatch.setenv("RZPIC_MG_PATH", path)
     nr, nz = mesh
     w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
                     n_per_species=1, steps=1, V_dc=35.0)

@@ -101,16 +101,15 @@ def test_deposit_and_finalize(weighting):
         np.testing.assert_allclose(g.grid(G).sum(), g.particles(s)["w"].sum(), rtol=1e-11)
 
 
-@pytest.mark.parametrize("path", ["one_block", "multi_launch"])
+@pytest.mark.parametrize("path", ["block", "split", "multi"])
 @pytest.mark.parametrize("mesh", [(33, 33), (129, 65), (65, 3), (40, 17)])
 @pytest.mark.parametrize("face", [wl.FACE_AVG, wl.FACE_MAX])
 def test_solve_cycles_and_convergence(mesh, face, path, monkeypatch):
-    """Both cycle paths of the library: one launch for all cycles (levels in
-    LDS, pre-factored lines) and one launch per level (any mesh size)."""
-    if path == "multi_launch":
-        monkeypatch.setenv("RZPIC_MG_MULTI", "1")
-    else:
-        monkeypatch.delenv("RZPIC_MG_MULTI", raising=False)
+    """The three cycle paths of the library: one launch for all cycles
+    (levels in LDS, pre-factored lines); per cycle a residual launch, the
+    coarse levels in one workgroup and the finest sweep; one launch per level
+    (any mesh size)."""
+    monkeypatch.setenv("RZPIC_MG_PATH", path)
     nr, nz = mesh
     w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
                     n_per_species=1, steps=1, V_dc=35.0, chi_face=face)
