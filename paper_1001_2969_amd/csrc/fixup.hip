@@ -168,7 +168,8 @@ hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_
 // Hole m (the m-th dead index below keep) receives the m-th live particle of
 // [keep, n).  With T_k the dead indices >= keep (sorted), that particle is
 // keep + m + k for the smallest k whose T_k lies beyond it.
-template <typename T> __global__ void k_fill(Parts<T> p, const int64_t *dead, const FixRec *fix)
+template <typename T>
+__device__ __forceinline__ void fill_body(const Parts<T> &p, const int64_t *dead, const FixRec *fix)
 {
     const int64_t D = fix->dead, keep = fix->keep;
     if (D == 0) return;
@@ -200,10 +201,33 @@ template <typename T> __global__ void k_fill(Parts<T> p, const int64_t *dead, co
     }
 }
 
+template <typename T> __global__ void k_fill(Parts<T> p, const int64_t *dead, const FixRec *fix)
+{
+    fill_body<T>(p, dead, fix);
+}
+
 template <typename T>
 hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st)
 {
     hipLaunchKernelGGL((k_fill<T>), dim3(256), dim3(256), 0, st, p, ch.dead_glob, fix);
+    return hipGetLastError();
+}
+
+// Both species in one launch (blockIdx.y selects the species).
+template <typename T>
+__global__ void k_fill2(Parts<T> p0, Parts<T> p1, const int64_t *dead0, const int64_t *dead1,
+                        const FixRec *fix0, const FixRec *fix1)
+{
+    if (blockIdx.y == 0) fill_body<T>(p0, dead0, fix0);
+    else fill_body<T>(p1, dead1, fix1);
+}
+
+template <typename T>
+hipError_t launch_fill2(Parts<T> p0, Parts<T> p1, Chunks ch0, Chunks ch1, const FixRec *fix0,
+                        const FixRec *fix1, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_fill2<T>), dim3(256, 2), dim3(256), 0, st, p0, p1, ch0.dead_glob,
+                       ch1.dead_glob, fix0, fix1);
     return hipGetLastError();
 }
 
@@ -472,6 +496,10 @@ template hipError_t launch_dead_scan<double>(Parts<double>, const Counts *, Chun
 template hipError_t launch_dead_scan<float>(Parts<float>, const Counts *, Chunks, hipStream_t);
 template hipError_t launch_fill<double>(Parts<double>, Chunks, const FixRec *, hipStream_t);
 template hipError_t launch_fill<float>(Parts<float>, Chunks, const FixRec *, hipStream_t);
+template hipError_t launch_fill2<double>(Parts<double>, Parts<double>, Chunks, Chunks,
+                                         const FixRec *, const FixRec *, hipStream_t);
+template hipError_t launch_fill2<float>(Parts<float>, Parts<float>, Chunks, Chunks, const FixRec *,
+                                        const FixRec *, hipStream_t);
 template hipError_t launch_append<double>(const ScanJobs &, Parts<double>, Parts<double>,
                                           Parts<double>, Parts<double>, Counts *, Counts *, int64_t,
                                           hipStream_t);

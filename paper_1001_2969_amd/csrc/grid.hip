@@ -4,33 +4,11 @@
 
 namespace rz {
 
-// n_s = N_s / V, rho = sum q n, chi = sum q^2 n dt^2 / (2 m eps0) (the
-// implicit susceptibility of Sec. 2.1 in SI), eps = 1 + chi, f = rho / eps0.
-// A negative accumulator means the fixed-point range overflowed.
+// Every node of the deposit (finalize_node).
 __global__ void k_finalize(GridArgs g)
 {
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.nn; k += gridDim.x * blockDim.x) {
-        long long a0 = (long long)g.acc0[k], a1 = (long long)g.acc1[k];
-        if (a0 < 0 || a1 < 0) atomicOr(g.status, kStNumeric);
-        double n0 = ((double)a0 * g.quantum0) / g.vol[k];
-        double n1 = ((double)a1 * g.quantum1) / g.vol[k];
-        g.dens0[k] = n0;
-        g.dens1[k] = n1;
-        double rho = 0.0, chi = 0.0;
-        rho += g.q0 * n0;
-        chi += g.q0 * g.q0 * n0 * g.dt * g.dt / (2.0 * g.m0 * kEps0);
-        rho += g.q1 * n1;
-        chi += g.q1 * g.q1 * n1 * g.dt * g.dt / (2.0 * g.m1 * kEps0);
-        g.rho[k] = rho;
-        g.chi[k] = chi;
-        g.eps[k] = 1.0 + chi;
-        if (g.eps32) g.eps32[k] = (float)(1.0 + chi);
-        g.f[k] = rho / kEps0;
-        if (g.zero_acc) {
-            g.acc0w[k] = 0;
-            g.acc1w[k] = 0;
-        }
-    }
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.nn; k += gridDim.x * blockDim.x)
+        finalize_node(g, k);
 }
 
 hipError_t launch_finalize(const GridArgs &g, hipStream_t st)

@@ -146,6 +146,17 @@ template <typename T> struct PassArgs {
     uint32_t step;
 };
 
+// Sum of per-block LDS deposit slices into the deposit grids of both
+// species, run by extra blocks of the collision launch: block b of those
+// 2 * bx * by blocks takes species b / (bx by), nodes of column block b % bx
+// (256 per block) and every by-th slice.
+struct SliceSum {
+    unsigned long long *acc[2];
+    const unsigned long long *slices[2];
+    int nb[2];
+    int nn, bx, by;
+};
+
 // Host-side launchers (defined in the .hip files).
 template <typename T>
 hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
@@ -155,7 +166,7 @@ hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, 
                         int threads, size_t lds, hipStream_t st);
 template <typename T>
 hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
-                           int threads, hipStream_t st);
+                           int threads, const SliceSum &r, hipStream_t st);
 template <typename T>
 hipError_t launch_collide(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
                           hipStream_t st);
@@ -190,6 +201,9 @@ template <typename T>
 hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st);
+template <typename T>
+hipError_t launch_fill2(Parts<T> p0, Parts<T> p1, Chunks ch0, Chunks ch1, const FixRec *fix0,
+                        const FixRec *fix1, hipStream_t st);
 // Append the staged children after the kept particles of each species (slot
 // = parent index, identities in parent order) and commit the counts.
 template <typename T>
@@ -260,6 +274,11 @@ struct MgLevels {
     size_t solve_lds;      // LDS bytes of the single-block kernel
 };
 hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st);
+// The merged step's grid preparation in one launch: finalize every node,
+// restrict epsilon down the levels, set the Dirichlet values of phi0 (and of
+// phi1 if non-null) for the electrode voltage V, clear `nclear` counters.
+hipError_t mg_finalize(const GridArgs &g, const MgLevels &m, int mixed, double *phi0, double *phi1,
+                       double V, unsigned long long *clear, int nclear, hipStream_t st);
 hipError_t mg_resid_norm(const MgLevels &m, const double *u, const double *f, int zero_interior,
                          unsigned long long *norm, hipStream_t st);
 hipError_t mg_set_bc(double *phi, int nr, int nz, double V, hipStream_t st);
@@ -281,6 +300,11 @@ hipError_t mg_solve_block(const MgLevels &m, int mixed, double *phi, const doubl
 // alternates between phi and phi_alt (both carry the boundary values); the
 // pointers are swapped.
 hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_alt,
-                     const double *f, hipStream_t st);
+                     const double *f, int skip_down, hipStream_t st);
+// Split path, first launch of a solve (after the Dirichlet values are set):
+// the line tables and the first cycle's residual restriction; that cycle then
+// runs mg_vcycle with skip_down = 1.
+hipError_t mg_prep(const MgLevels &m, int mixed, const double *phi, const double *f,
+                   hipStream_t st);
 
 }  // namespace rz

@@ -145,6 +145,72 @@ hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st)
     return hipGetLastError();
 }
 
+// The step's grid preparation in one launch, a block per group of cpb
+// columns: the deposit finalized on every node of its columns
+// (finalize_node), epsilon restricted down every level as k_restrict_eps
+// does, the Dirichlet values of phi0 and phi1 (V on z = 0 for r < R, 0 on
+// z = L and r = R) and, by block 0, `nclear` counters cleared.
+__global__ void k_finalize_mg(GridArgs g, MgLevels m, int mixed, int cpb, double *phi0,
+                              double *phi1, double V, unsigned long long *clear, int nclear)
+{
+    extern __shared__ double sbuf[];
+    const int L = m.L, nr = m.nr, nz = m.nzl[L];
+    double *cur = sbuf, *nxt = sbuf + (size_t)cpb * nz;
+    const int j0 = blockIdx.x * cpb;
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < nclear; t += blockDim.x) clear[t] = 0;
+    for (int t = threadIdx.x; t < cpb * nz; t += blockDim.x) {
+        const int cj = t / nz, i = t - cj * nz, j = j0 + cj;
+        double e = 1.0;
+        if (j < nr) {
+            const int k = i * nr + j;
+            e = finalize_node(g, k);
+            if (i == 0 || i == nz - 1 || j == nr - 1) {
+                const double b = (i == 0 && j < nr - 1) ? V : 0.0;
+                phi0[k] = b;
+                if (phi1) phi1[k] = b;
+            }
+        }
+        cur[t] = e;
+    }
+    __syncthreads();
+    int nzf = nz;
+    for (int l = L - 1; l >= 1; --l) {
+        const int nzc = m.nzl[l];
+        for (int t = threadIdx.x; t < cpb * nzc; t += blockDim.x) {
+            int cj = t / nzc, I = t - cj * nzc, j = j0 + cj;
+            const double *col = cur + (size_t)cj * nzf;
+            double v;
+            if (I == 0) v = col[0];
+            else if (I == nzc - 1) v = col[nzf - 1];
+            else v = 0.25 * col[2 * I - 1] + 0.5 * col[2 * I] + 0.25 * col[2 * I + 1];
+            nxt[(size_t)cj * nzc + I] = v;
+            if (j < nr) {
+                m.eps64[l][(size_t)I * nr + j] = v;
+                if (mixed) m.eps32[l][(size_t)I * nr + j] = (float)v;
+            }
+        }
+        __syncthreads();
+        double *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        nzf = nzc;
+    }
+}
+
+hipError_t mg_finalize(const GridArgs &g, const MgLevels &m, int mixed, double *phi0, double *phi1,
+                       double V, unsigned long long *clear, int nclear, hipStream_t st)
+{
+    const int nz = m.nzl[m.L];
+    int cpb = cols_per_block(nz);
+    if (cpb < 1) cpb = 1;
+    const int blocks = (m.nr + cpb - 1) / cpb;
+    const size_t lds = 2 * (size_t)cpb * nz * sizeof(double);
+    hipLaunchKernelGGL(k_finalize_mg, dim3(blocks), dim3(256), lds, st, g, m, mixed, cpb, phi0, phi1,
+                       V, clear, nclear);
+    return hipGetLastError();
+}
+
 template <typename T> struct LineArgs {
     int nr, nzl, rule, parity, zero_old;
     T inv_hz2, inv_hr2;
@@ -259,14 +325,15 @@ __global__ void k_add_corr(double *phi, const float *u, int nr, int nz)
 // Mixed: the finest residual is also stored in FP32 as the right-hand side of
 // the correction.
 template <typename T>
-__global__ void k_down(const double *u, const double *f, MgLevels m, int mixed, int cpb)
+__device__ __forceinline__ void down_body(const double *u, const double *f, const MgLevels &m,
+                                          int mixed, int cpb, int blk)
 {
     extern __shared__ double sbuf[];
     const int L = m.L, nr = m.nr, nz = m.nzl[L];
     const int w = cpb + 2;  // staged columns j0-1 .. j0+cpb
     double *us = sbuf, *es = sbuf + (size_t)w * nz;
     double *cur = es + (size_t)w * nz, *nxt = cur + (size_t)cpb * nz;
-    const int j0 = blockIdx.x * cpb;
+    const int j0 = blk * cpb;
     for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
         int cj = t / nz, i = t - cj * nz, j = j0 - 1 + cj;
         bool in = j >= 0 && j < nr;
@@ -324,6 +391,12 @@ __global__ void k_down(const double *u, const double *f, MgLevels m, int mixed, 
         nxt = tmp;
         nzf = nzc;
     }
+}
+
+template <typename T>
+__global__ void k_down(const double *u, const double *f, MgLevels m, int mixed, int cpb)
+{
+    down_body<T>(u, f, m, mixed, cpb, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,12 +646,12 @@ static hipError_t level_sweep(const MgLevels &m, int l, int zero_old, const T *u
 //   a | c | b after the last step | k1, k2 of step 0 | k1, k2 of step 1 | ...
 // with k1 = A_j / B_{j-s} (0 for j < s) and k2 = C_j / B_{j+s} (0 for
 // j + s >= n), s = 2^step, exactly the products the reduction forms.
-template <typename T> __global__ __launch_bounds__(256) void k_factor(MgLevels m, int mixed)
+template <typename T> __device__ __forceinline__ void factor_body(const MgLevels &m, int mixed, int blk)
 {
-    if (blockIdx.x >= m.line_off[m.L + 1]) {
+    if (blk >= m.line_off[m.L + 1]) {
         // the FP64 operator of the finest level, row by row: a, b, c, d, e
         const int L = m.L, nr = m.nr, n = nr - 1, nn = m.nzl[L] * nr;
-        const int i = blockIdx.x - m.line_off[L + 1] + 1;
+        const int i = blk - m.line_off[L + 1] + 1;
         const double iz2 = 1.0 / (m.hzl[L] * m.hzl[L]), ir2 = 1.0 / (m.hr * m.hr);
         for (int j = threadIdx.x; j < n; j += blockDim.x) {
             Coef<double> k = coef<double>(m.eps64[L], nr, i, j, iz2, ir2, m.chi_face);
@@ -593,7 +666,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_factor(MgLevels m
     }
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
-    const int line = blockIdx.x;
+    const int line = blk;
     int l = 1;
     while (line >= m.line_off[l + 1]) ++l;
     const int i = line - m.line_off[l] + 1;
@@ -640,6 +713,45 @@ template <typename T> __global__ __launch_bounds__(256) void k_factor(MgLevels m
         __syncthreads();
     }
     if (j < n) tab[2 * n + j] = Bd[j];
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_factor(MgLevels m, int mixed)
+{
+    factor_body<T>(m, mixed, blockIdx.x);
+}
+
+// Split path, first launch of a solve: the line tables of every level
+// (blocks [0, nfb)) and, beside them, the first cycle's finest residual
+// restricted to every level (the remaining blocks, cpb columns each).
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep(const double *u, const double *f, MgLevels m,
+                                              int mixed, int cpb, int nfb)
+{
+    if ((int)blockIdx.x < nfb) factor_body<T>(m, mixed, blockIdx.x);
+    else down_body<T>(u, f, m, mixed, cpb, blockIdx.x - nfb);
+}
+
+static size_t down_lds(int nz, int cpb)
+{
+    return (2 * (size_t)(cpb + 2) + 2 * (size_t)cpb) * nz * sizeof(double);
+}
+
+hipError_t mg_prep(const MgLevels &m, int mixed, const double *phi, const double *f,
+                   hipStream_t st)
+{
+    const int nz = m.nzl[m.L], n = m.nr - 1;
+    const int cpb = cols_per_block(nz);
+    const int nfb = m.line_off[m.L + 1], nd = (n + cpb - 1) / cpb;
+    size_t lds = down_lds(nz, cpb);
+    const size_t lf = 3 * (size_t)n * (mixed ? sizeof(float) : sizeof(double));
+    if (lf > lds) lds = lf;
+    if (mixed)
+        hipLaunchKernelGGL((k_prep<float>), dim3(nfb + nd), dim3(256), lds, st, phi, f, m, mixed, cpb,
+                           nfb);
+    else
+        hipLaunchKernelGGL((k_prep<double>), dim3(nfb + nd), dim3(256), lds, st, phi, f, m, mixed,
+                           cpb, nfb);
+    return hipGetLastError();
 }
 
 hipError_t mg_factor(const MgLevels &m, int mixed, hipStream_t st)
@@ -1127,8 +1239,22 @@ static hipError_t bottom(const MgLevels &m, int mixed, hipStream_t st)
 // One V(0,1) cycle on phi.  FP64: every level in double, the finest level on
 // phi itself.  Mixed: the finest residual in double, the correction cycle in
 // float on every level, phi += correction in double.
+static hipError_t down(const MgLevels &m, int mixed, const double *phi, const double *f,
+                       hipStream_t st)
+{
+    const int nr = m.nr, nz = m.nzl[m.L];
+    const int cpb = cols_per_block(nz);
+    if (mixed)
+        hipLaunchKernelGGL((k_down<float>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256),
+                           down_lds(nz, cpb), st, phi, f, m, mixed, cpb);
+    else
+        hipLaunchKernelGGL((k_down<double>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256),
+                           down_lds(nz, cpb), st, phi, f, m, mixed, cpb);
+    return hipGetLastError();
+}
+
 hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_alt,
-                     const double *f, hipStream_t st)
+                     const double *f, int skip_down, hipStream_t st)
 {
     const int L = m.L, nr = m.nr, nz = m.nzl[L];
     hipError_t e;
@@ -1145,17 +1271,9 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
                            (const float *)m.u32[1], nr, nz);
         return hipGetLastError();
     }
-    {
-        int cpb = cols_per_block(nz);
-        size_t lds = (2 * (size_t)(cpb + 2) + 2 * (size_t)cpb) * nz * sizeof(double);
-        if (mixed)
-            hipLaunchKernelGGL((k_down<float>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256), lds,
-                               st, (const double *)phi, f, m, mixed, cpb);
-        else
-            hipLaunchKernelGGL((k_down<double>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256), lds,
-                               st, (const double *)phi, f, m, mixed, cpb);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    // the residual of the finest level restricted to every level (unless the
+    // solve's first launch has done it for this cycle)
+    if (!skip_down && (e = down(m, mixed, phi, f, st)) != hipSuccess) return e;
     if (m.split) {
         // coarse levels in one workgroup from the restricted residuals, then
         // the finest level's zebra sweep with pre-factored lines

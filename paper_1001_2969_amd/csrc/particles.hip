@@ -408,11 +408,30 @@ template <typename T, int MODE> __global__ __launch_bounds__(256) void k_collide
     collide_body<T, MODE>(a, blockIdx.x, gridDim.x);
 }
 
+// Collisions of both species (blocks [0, c0) species 0, [c0, c0 + c1)
+// species 1) and, in the remaining blocks, the sum of the pass's LDS slices:
+// both only add into the deposit grids, so they run side by side.
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_collide2(PassArgs<T> a0, PassArgs<T> a1, int b0)
+__global__ __launch_bounds__(256) void k_collide2(PassArgs<T> a0, PassArgs<T> a1, int c0, int c1,
+                                                  SliceSum r)
 {
-    if ((int)blockIdx.x < b0) collide_body<T, MODE>(a0, blockIdx.x, b0);
-    else collide_body<T, MODE>(a1, blockIdx.x - b0, gridDim.x - b0);
+    const int b = blockIdx.x;
+    if (b < c0) {
+        collide_body<T, MODE>(a0, b, c0);
+        return;
+    }
+    if (b < c0 + c1) {
+        collide_body<T, MODE>(a1, b - c0, c1);
+        return;
+    }
+    const int rb = b - c0 - c1, per = r.bx * r.by;
+    const int s = rb / per, x = rb % r.bx, y = (rb % per) / r.bx;
+    const int g = x * blockDim.x + threadIdx.x;
+    if (g >= r.nn) return;
+    const unsigned long long *sl = r.slices[s];
+    unsigned long long sum = 0;
+    for (int k = y; k < r.nb[s]; k += r.by) sum += sl[(size_t)k * r.nn + g];
+    atomicAdd(r.acc[s] + g, sum);
 }
 
 // Staged new particles of species cs (unmerged form): first push or deposit
@@ -566,9 +585,11 @@ hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, 
 
 template <typename T>
 hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
-                           int threads, hipStream_t st)
+                           int threads, const SliceSum &r, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_collide2<T, M_FIRST>), dim3(c0 + c1), dim3(threads), 0, st, a0, a1, c0);
+    const int nred = r.nb[0] + r.nb[1] > 0 ? 2 * r.bx * r.by : 0;
+    hipLaunchKernelGGL((k_collide2<T, M_FIRST>), dim3(c0 + c1 + nred), dim3(threads), 0, st, a0, a1,
+                       c0, c1, r);
     return hipGetLastError();
 }
 
@@ -577,9 +598,9 @@ template hipError_t launch_pass2<double>(int, const PassArgs<double> &, const Pa
 template hipError_t launch_pass2<float>(int, const PassArgs<float> &, const PassArgs<float> &, int,
                                         int, int, size_t, hipStream_t);
 template hipError_t launch_collide2<double>(const PassArgs<double> &, const PassArgs<double> &,
-                                            int, int, int, hipStream_t);
+                                            int, int, int, const SliceSum &, hipStream_t);
 template hipError_t launch_collide2<float>(const PassArgs<float> &, const PassArgs<float> &, int,
-                                           int, int, hipStream_t);
+                                           int, int, const SliceSum &, hipStream_t);
 template hipError_t launch_pass<double>(int, const PassArgs<double> &, int, int, size_t,
                                         hipStream_t);
 template hipError_t launch_pass<float>(int, const PassArgs<float> &, int, int, size_t, hipStream_t);

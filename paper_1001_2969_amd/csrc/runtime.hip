@@ -341,10 +341,10 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
     return RZPIC_OK;
 }
 
-// The merged step's particle work for both species in three launches: the
+// The merged step's particle work for both species in two launches: the
 // fused pass of both species side by side (each block privatises the grid of
-// its species in LDS), the collision kernels of both species, then the sum of
-// the LDS slices into the two deposit grids.
+// its species in LDS), then the collision kernels of both species with the
+// sum of the LDS slices into the two deposit grids beside them.
 template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
 {
     PassArgs<T> a[2] = {pass_args<T>(c, 0, step), pass_args<T>(c, 1, step)};
@@ -373,7 +373,6 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
     if ((b[0] + b[1]) * (threads / 64) > kMaxWaves)
         return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", (b[0] + b[1]) * threads / 64,
                     kMaxWaves);
-    HIPCHK(launch_fill_u64(c->mcstat, 2 * (1 + kMaxProc), c->st));
     mark(c, 4);
     HIPCHK(launch_pass2<T>(mode, a[0], a[1], b[0], b[1], threads, lds, c->st));
     mark(c, 5);
@@ -387,10 +386,19 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
         cb[s] = (want + wpb - 1) / wpb;
         if (a[s].sp.mc_model == RZPIC_MC_NONE) cb[s] = 1;
     }
-    HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, c->st));
-    if (mode & M_LDS)
-        HIPCHK(launch_reduce_slices2(c->acc[0], a[0].slices, b[0], c->acc[1], a[1].slices, b[1],
-                                     c->nn, c->st));
+    SliceSum r{};
+    if (mode & M_LDS) {
+        for (int s = 0; s < 2; ++s) {
+            r.acc[s] = c->acc[s];
+            r.slices[s] = a[s].slices;
+            r.nb[s] = b[s];
+        }
+        r.nn = c->nn;
+        r.bx = (c->nn + cthreads - 1) / cthreads;
+        const int nb = b[0] > b[1] ? b[0] : b[1];
+        r.by = nb < 32 ? nb : 32;
+    }
+    HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, r, c->st));
     mark(c, 6);
     return RZPIC_OK;
 }
@@ -434,8 +442,14 @@ template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
     HIPCHK(launch_scan(j, max_chunks, c->st));
     if (j.children) c->children_scanned = true;
     HIPCHK(launch_dead_list(j, max_chunks, c->st));
-    for (int s = 0; s < 2; ++s)
-        if (j.dead[s]) HIPCHK(launch_fill<T>(parts_of<T>(c->sp[s].v), c->sp[s].ch, c->fix + s, c->st));
+    if (j.dead[0] && j.dead[1]) {
+        HIPCHK(launch_fill2<T>(parts_of<T>(c->sp[0].v), parts_of<T>(c->sp[1].v), c->sp[0].ch,
+                               c->sp[1].ch, c->fix, c->fix + 1, c->st));
+    } else {
+        for (int s = 0; s < 2; ++s)
+            if (j.dead[s])
+                HIPCHK(launch_fill<T>(parts_of<T>(c->sp[s].v), c->sp[s].ch, c->fix + s, c->st));
+    }
     Parts<T> none{};
     HIPCHK(launch_append<T>(j, c->sp[0].bound ? parts_of<T>(c->sp[0].v) : none,
                             c->sp[1].bound ? parts_of<T>(c->sp[1].v) : none, stage_of<T>(c, 0),
@@ -446,32 +460,40 @@ template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
     return RZPIC_OK;
 }
 
+// prepared: the step's grid launch (mg_finalize) has formed eps and f,
+// restricted eps and set the Dirichlet values of both phi buffers.
 rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, double *relres)
 {
     const int nr = c->c.nr, nz = c->c.nz;
+    const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
     if (!prepared) {
         int threads = 256, blocks = (c->nn + threads - 1) / threads;
         hipLaunchKernelGGL(k_prep_solve, dim3(blocks), dim3(threads), 0, c->st, c->nn,
                            (const double *)c->rho, (const double *)c->chi, c->eps,
                            c->mixed ? c->mg.eps32[c->L] : nullptr, c->f);
         HIPCHK(hipGetLastError());
+        HIPCHK(mg_restrict_eps(c->mg, c->mixed, c->st));
+        HIPCHK(mg_set_bc(c->phi, nr, nz, V, c->st));
+        HIPCHK(mg_set_bc(c->phi_alt, nr, nz, V, c->st));
     }
-    HIPCHK(mg_restrict_eps(c->mg, c->mixed, c->st));
-    const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
     const bool ob = c->mg.one_block != 0;
-    if (ob || c->mg.split) HIPCHK(mg_factor(c->mg, c->mixed, c->st));
+    bool down_done = false;  // the first cycle's restriction came with the tables
+    if (c->mg.split) {
+        HIPCHK(mg_prep(c->mg, c->mixed, c->phi, c->f, c->st));
+        down_done = true;
+    } else if (ob) {
+        HIPCHK(mg_factor(c->mg, c->mixed, c->st));
+    }
     auto cycles_run = [&](int kk) -> hipError_t {
         if (ob) return mg_solve_block(c->mg, c->mixed, c->phi, c->f, V, kk, c->st);
         for (int q = 0; q < kk; ++q) {
-            hipError_t e = mg_vcycle(c->mg, c->mixed, c->phi, c->phi_alt, c->f, c->st);
+            hipError_t e =
+                mg_vcycle(c->mg, c->mixed, c->phi, c->phi_alt, c->f, down_done ? 1 : 0, c->st);
+            down_done = false;
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     };
-    if (!ob || c->c.mg_fixed_cycles <= 0) {
-        HIPCHK(mg_set_bc(c->phi, nr, nz, V, c->st));
-        if (!ob) HIPCHK(mg_set_bc(c->phi_alt, nr, nz, V, c->st));
-    }
     int k = 0;
     rzpic_status st = RZPIC_OK;
     const bool want = cycles || relres;
@@ -529,7 +551,7 @@ rzpic_status efield_impl(rzpic_ctx *c)
     return RZPIC_OK;
 }
 
-rzpic_status finalize_impl(rzpic_ctx *c, int zero_acc)
+GridArgs grid_args(rzpic_ctx *c, int zero_acc)
 {
     GridArgs g{};
     g.nr = c->c.nr;
@@ -558,7 +580,12 @@ rzpic_status finalize_impl(rzpic_ctx *c, int zero_acc)
     g.acc0w = c->acc[0];
     g.acc1w = c->acc[1];
     g.status = c->status;
-    HIPCHK(launch_finalize(g, c->st));
+    return g;
+}
+
+rzpic_status finalize_impl(rzpic_ctx *c, int zero_acc)
+{
+    HIPCHK(launch_finalize(grid_args(c, zero_acc), c->st));
     return RZPIC_OK;
 }
 
@@ -622,7 +649,14 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
         return fail(RZPIC_ESTATE, "new particles are staged: call rzpic_compact first");
     if (c->timing && c->ev_used >= rzpic_ctx::kPool) TRY(flush_timing(c));
     mark(c, 0);
-    TRY(finalize_impl(c, 1));
+    {
+        // finalize, eps restriction, Dirichlet values of both phi buffers and
+        // the Monte Carlo counters cleared, in one launch
+        const double t = (double)(n + 1) * c->c.dt;
+        const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
+        HIPCHK(mg_finalize(grid_args(c, 1), c->mg, c->mixed, c->phi, c->phi_alt, V, c->mcstat,
+                           2 * (1 + kMaxProc), c->st));
+    }
     mark(c, 1);
     TRY(solve_impl(c, (double)(n + 1) * c->c.dt, true, nullptr, nullptr));
     c->acc_cycles += c->last_cycles;
