@@ -67,7 +67,11 @@ typedef struct rzpic_config {
     int32_t precision;        /* RZPIC_FP64 or RZPIC_MIXED                    */
     int32_t weighting;        /* RZPIC_W_ZR2 (default) or RZPIC_W_ZR          */
     int32_t chi_face;         /* RZPIC_FACE_AVG or RZPIC_FACE_MAX             */
-    int32_t fixed_point_bits; /* deposit quantum = w_ref * 2^-bits (0 -> 40)  */
+    int32_t fixed_point_bits; /* deposit quantum = w_ref * 2^-bits (0 -> 46):
+                               * one contribution must stay below 2^51 quanta
+                               * (weights below 2^(51-bits) w_ref) and a node's
+                               * total below 2^63; 46 bits keep the rounding of
+                               * the deposit near 1e-14 of a node's count */
     double V_dc, V_rf, f_rf;  /* z=0 electrode: V_dc + V_rf sin(2 pi f_rf t) */
     uint64_t seed;            /* Philox key of every random draw             */
     double mg_tol;            /* relative L-inf residual target (Sec. 2.5)   */

@@ -7,8 +7,8 @@ namespace rz {
 
 // Deposit of one particle (Sec. 2.4): N_ij += w S_z S_r, accumulated in fixed
 // point (quantum = w_ref 2^-bits) so that the sum does not depend on order.
-// Contributions must stay below 2^51 quanta (a weight below 2^11 w_ref); a
-// larger one is flagged and the step reports RZPIC_ENUMERIC.
+// Contributions must stay below 2^51 quanta (a weight below 2^(51-bits)
+// w_ref); a larger one is flagged and the step reports RZPIC_ENUMERIC.
 template <typename T>
 __device__ __forceinline__ void deposit4(unsigned long long *acc, const Mesh &m, const W4<T> &q,
                                          double w, double inv_quantum, int32_t *status)

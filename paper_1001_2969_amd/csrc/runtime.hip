@@ -723,7 +723,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
 
     rzpic_ctx *c = new rzpic_ctx();
     c->c = k;
-    if (c->c.fixed_point_bits == 0) c->c.fixed_point_bits = 40;
+    if (c->c.fixed_point_bits == 0) c->c.fixed_point_bits = 46;
     c->st = (hipStream_t)stream;
     c->mixed = k.precision == RZPIC_MIXED;
     c->hr = k.R / (double)(k.nr - 1);

@@ -19,8 +19,8 @@ pytestmark = pytest.mark.gpu
 STEPS = 2
 
 
-def _pair_init(w, precision):
-    o, g = pair(w, precision=precision, capacity_factor=1.25)
+def _pair_init(w, precision, capacity_factor=1.25):
+    o, g = pair(w, precision=precision, capacity_factor=capacity_factor)
     for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
         o.init_particles(s, w.n_per_species, w.n0, T, 0)
         g.init_particles(s, w.n_per_species, w.n0, T, 0)
@@ -61,5 +61,47 @@ def test_fullsize_mixed_two_steps():
     e = np.abs(g.grid(rzpic.G_PHI) - o.grid(rzo.G_PHI)).max() / np.abs(o.grid(rzo.G_PHI)).max()
     print(f"phi error {e:.3e}")
     assert e <= TOL_GRID
+    for s, (go, oo) in enumerate(((rzpic.G_N0, rzo.G_N0), (rzpic.G_N1, rzo.G_N1))):
+        print(f"N{s} error {check_counts(g.grid(go), o.grid(oo), w_un[s], f'N{s}'):.3e}")
+
+
+def test_large_mesh_fp64_with_weight_split():
+    """513x129 mesh, R = 15 cm, L = 2.5 cm, 16M + 16M particles, power-law
+    cross sections, argon at 20 mTorr.  The grid is larger than one
+    workgroup's LDS (deposit by global atomics) and the r-lines have 512
+    unknowns (one-launch-per-level multigrid); the weight split runs after
+    the second step, every particle having moved off the radius its weight
+    was set for."""
+    w = wl.large_513x129().replace(precision="fp64", resize_every=2)
+    o, g = _pair_init(w, "fp64", capacity_factor=2.0)
+    for n in range(STEPS):
+        assert o.step(n) == 0
+        g.step(n)
+    for s in (0, 1):
+        assert g.count(s) == (o.count(s), o.next_id(s))
+        e = compare_particles(g.particles(s), o.particles(s), w, 1e-10, label=f"s={s}")
+        print(f"species {s}: {o.count(s)} particles, worst field errors {e}")
+    compare_grid(g.grid(rzpic.G_PHI), o.grid(rzo.G_PHI), 1e-10, "phi")
+    for go, oo in ((rzpic.G_N0, rzo.G_N0), (rzpic.G_N1, rzo.G_N1)):
+        compare_grid(g.grid(go), o.grid(oo), 1e-10, "N")
+
+
+def test_large_mesh_mixed():
+    """The mixed form on the 513x129 mesh.  FP32 positions resolve about
+    5e-5 of a cell at r = R = 15 cm, and the charge density is a nearly
+    cancelling difference of the two species, so phi is held to 1e-4 here
+    (1e-5 on the 129x65 mesh, where a cell is 3x larger relative to R)."""
+    w = wl.large_513x129()
+    o, g = _pair_init(w, "mixed")
+    for n in range(STEPS):
+        assert o.step(n) == 0
+        g.step(n)
+    w_un = {}
+    for s in (0, 1):
+        e, frac, w_un[s] = compare_mixed(g.particles(s), o.particles(s), w, f"s={s}")
+        print(f"species {s}: worst field errors {e}, unmatched fraction {frac:.2e}")
+    e = np.abs(g.grid(rzpic.G_PHI) - o.grid(rzo.G_PHI)).max() / np.abs(o.grid(rzo.G_PHI)).max()
+    print(f"phi error {e:.3e}")
+    assert e <= 1e-4
     for s, (go, oo) in enumerate(((rzpic.G_N0, rzo.G_N0), (rzpic.G_N1, rzo.G_N1))):
         print(f"N{s} error {check_counts(g.grid(go), o.grid(oo), w_un[s], f'N{s}'):.3e}")

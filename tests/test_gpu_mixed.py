@@ -6,7 +6,8 @@ only at the end: every particle field is rounded to FP32 at every step, so it
 is held to stated tolerances instead of the 1e-10 FP64 bar:
 
 - phi: max |mixed - oracle| <= 1e-5 max |oracle| within two steps of a
-  shared state, 1e-4 after ten;
+  shared state, 1e-4 after ten (and on the 513x129 mesh, whose cells are
+  smaller relative to the radius FP32 positions resolve);
 - deposited counts N: max |mixed - oracle| <= 1e-5 max |oracle| plus the
   summed weight of the particles present on one side only (a particle
   contributes at most its weight to any node);
