@@ -59,9 +59,10 @@ typedef struct {
     int32_t mg_max_cycles;   /* cap on V-cycles per solve                   */
     int32_t mg_fixed_cycles; /* >0: exactly this many cycles, no test       */
     int32_t resize_every;    /* weight split period in steps (0 = never)    */
-    int32_t pad0;
+    int32_t sort_every;      /* tile sort period in steps (0 = never)       */
     double resize_wcoef;     /* w_r(r) = resize_wcoef * max(r, hr/2)        */
     double n_gas, T_gas, m_gas; /* background neutral density, K, kg        */
+    int32_t tile_z, tile_r;  /* tile of the sort key, in cells              */
 } rzo_config;
 
 rzo *rzo_create(const rzo_config *cfg);
@@ -105,6 +106,11 @@ int rzo_push_final(rzo *o, int s);          /* gather + final push + axis + abso
 int rzo_collide(rzo *o, int s, int64_t step);
 int rzo_compact(rzo *o, int s);
 int rzo_resize(rzo *o, int s);
+/* Stable counting sort of species s by the tile (tile_z x tile_r cells) of
+ * each particle's cell; returns the number of tiles. */
+int rzo_sort(rzo *o, int s);
+/* Tile key of a position (the key rzo_sort orders by). */
+int32_t rzo_tile_key(const rzo *o, double r, double z);
 /* Whole step n (finalize, solve at t=(n+1)dt, E, particles, compact, resize).
  * merged!=0: one pass per species; merged==0: one pass per operation. */
 int rzo_step(rzo *o, int64_t n, int merged);

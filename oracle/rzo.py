@@ -27,9 +27,10 @@ class Config(C.Structure):
         ("seed", C.c_uint64),
         ("mg_tol", C.c_double),
         ("mg_max_cycles", C.c_int32), ("mg_fixed_cycles", C.c_int32),
-        ("resize_every", C.c_int32), ("pad0", C.c_int32),
+        ("resize_every", C.c_int32), ("sort_every", C.c_int32),
         ("resize_wcoef", C.c_double),
         ("n_gas", C.c_double), ("T_gas", C.c_double), ("m_gas", C.c_double),
+        ("tile_z", C.c_int32), ("tile_r", C.c_int32),
     ]
 
 
@@ -61,8 +62,10 @@ def lib():
         L.rzo_mc_consts.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.rzo_init_particles.argtypes = [P, C.c_int, C.c_int64, C.c_double, C.c_double,
                                          C.c_uint64]
-        for name in ("rzo_push_first", "rzo_push_final", "rzo_compact", "rzo_resize"):
+        for name in ("rzo_push_first", "rzo_push_final", "rzo_compact", "rzo_resize", "rzo_sort"):
             getattr(L, name).argtypes = [P, C.c_int]
+        L.rzo_tile_key.restype = C.c_int32
+        L.rzo_tile_key.argtypes = [P, C.c_double, C.c_double]
         L.rzo_collide.argtypes = [P, C.c_int, C.c_int64]
         L.rzo_deposit.argtypes = [P]
         L.rzo_efield.argtypes = [P]
@@ -129,8 +132,9 @@ class Oracle:
                      mg_max_cycles=w.mg_max_cycles if mg_max_cycles is None else mg_max_cycles,
                      mg_fixed_cycles=(w.mg_fixed_cycles if mg_fixed_cycles is None
                                       else mg_fixed_cycles),
-                     resize_every=w.resize_every, pad0=0, resize_wcoef=w.wcoef,
-                     n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas)
+                     resize_every=w.resize_every, sort_every=w.sort_every,
+                     resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
+                     tile_z=w.tile_z, tile_r=w.tile_r)
         self._cfg = cfg
         self.h = lib().rzo_create(C.byref(cfg))
         if not self.h:
@@ -206,6 +210,15 @@ class Oracle:
 
     def resize(self, s):
         assert lib().rzo_resize(self.h, s) == 0
+
+    def sort(self, s):
+        """Stable counting sort by tile; returns the number of tiles."""
+        nt = lib().rzo_sort(self.h, s)
+        assert nt > 0
+        return nt
+
+    def tile_key(self, r, z):
+        return lib().rzo_tile_key(self.h, r, z)
 
     def deposit(self):
         lib().rzo_deposit(self.h)

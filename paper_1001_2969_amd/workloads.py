@@ -59,6 +59,9 @@ class Workload:
     mg_max_cycles: int = 100
     mg_fixed_cycles: int = 0
     resize_every: int = 0
+    sort_every: int = 0
+    tile_z: int = 16
+    tile_r: int = 32
     n0: float = 5e15
     Te_eV: float = 2.0
     Ti_eV: float = 0.026
@@ -98,10 +101,11 @@ def rf_129x65() -> Workload:
 
 
 def large_513x129() -> Workload:
-    """513x129 mesh, R = 15 cm, L = 2.5 cm, 16M per species, resize active."""
+    """513x129 mesh, R = 15 cm, L = 2.5 cm, 16M per species, resize active,
+    particles sorted by 16 x 32-cell tile every 20 steps."""
     return Workload(name="513x129_16M_resize", nr=513, nz=129, R=0.15, L=0.025,
                     n_per_species=16_000_000, steps=1000, V_rf=200.0,
-                    mg_fixed_cycles=3, resize_every=100, pressure_mTorr=20.0,
+                    mg_fixed_cycles=3, resize_every=100, sort_every=20, pressure_mTorr=20.0,
                     xsec="powerlaw")
 
 

@@ -21,11 +21,12 @@ def _state(o):
     return out
 
 
-@pytest.mark.parametrize("resize_every", [0, 3])
-def test_merged_cycle_equals_unmerged_bitwise(resize_every):
+@pytest.mark.parametrize("resize_every,sort_every", [(0, 0), (3, 0), (3, 2)])
+def test_merged_cycle_equals_unmerged_bitwise(resize_every, sort_every):
     """The paper reports that merging the final push of cycle n with the first
     push of cycle n+1 into one particle pass gives identical results."""
-    w = wl.small_fp64().replace(n_per_species=4000, resize_every=resize_every)
+    w = wl.small_fp64().replace(n_per_species=4000, resize_every=resize_every,
+                                sort_every=sort_every, tile_z=4, tile_r=8)
     states = []
     for merged in (True, False):
         o = rzo.Oracle(w)
@@ -119,3 +120,59 @@ def test_small_workload_runs_and_conserves_particles():
         assert created >= 0
         assert o.count(s) <= w.n_per_species + created
         assert lost >= 0 and np.all(p["w"] > 0)
+
+
+def _tile_keys(w, r, z):
+    """Tile of each particle's cell, written independently of the oracle."""
+    hr, hz = w.R / (w.nr - 1), w.L / (w.nz - 1)
+    i = np.clip(np.floor(z / hz).astype(np.int64), 0, w.nz - 2)
+    j = np.clip(np.floor(r / hr).astype(np.int64), 0, w.nr - 2)
+    ntr = (w.nr - 2) // w.tile_r + 1
+    return (i // w.tile_z) * ntr + j // w.tile_r
+
+
+@pytest.mark.parametrize("tiles", [(4, 8), (16, 32), (1, 1), (32, 32)])
+def test_tile_sort_is_the_stable_sort_by_tile(tiles):
+    """rzo_sort equals numpy's stable argsort of the tile keys: a permutation,
+    keys non-decreasing, the array order kept within a tile."""
+    w = wl.small_fp64().replace(n_per_species=3000, tile_z=tiles[0], tile_r=tiles[1])
+    o = rzo.Oracle(w, mc=False)
+    st, nid = wl.random_particles(7, 3000, w, 0, near_axis_frac=0.1, near_wall_frac=0.1)
+    st["z"][:5] = [0.0, w.L, 0.5 * w.L, w.L * (1 - 1e-12), 1e-12]
+    st["r"][5:8] = [0.0, w.R * (1 - 1e-12), w.R / (w.nr - 1)]
+    o.set_particles(0, st, nid)
+    before = o.particles(0)
+    keys = _tile_keys(w, before["r"], before["z"])
+    for p in range(0, 3000, 97):
+        assert o.tile_key(before["r"][p], before["z"][p]) == keys[p]
+    nt = o.sort(0)
+    assert nt == ((w.nz - 2) // w.tile_z + 1) * ((w.nr - 2) // w.tile_r + 1)
+    after = o.particles(0)
+    order = np.argsort(keys, kind="stable")
+    for f in rzo.FIELDS + ("id",):
+        np.testing.assert_array_equal(after[f], before[f][order])
+    assert np.all(np.diff(_tile_keys(w, after["r"], after["z"])) >= 0)
+
+
+def test_sorting_changes_order_not_physics():
+    """Without collisions (identities then never enter a random draw), runs
+    with and without sorting carry the same particles to rounding: sorting
+    only reorders the array and the order of the deposit sums."""
+    w = wl.small_fp64().replace(n_per_species=6000, tile_z=4, tile_r=8)
+    res = []
+    for sort_every in (0, 1):
+        o = rzo.Oracle(w.replace(sort_every=sort_every), mc=False)
+        for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
+            o.init_particles(s, w.n_per_species, w.n0, T, 0)
+        o.prologue()
+        for n in range(4):
+            assert o.step(n) == 0
+        res.append(_state(o))
+    a, b = res
+    for s in (0, 1):
+        np.testing.assert_array_equal(a[s]["id"], b[s]["id"])
+        for f in ("r", "z", "vr", "vt", "vz", "ar", "az", "w"):
+            np.testing.assert_allclose(a[s][f], b[s][f], rtol=1e-9, atol=1e-9 * np.abs(a[s][f]).max())
+    for g in a["grids"]:
+        sc = np.abs(a["grids"][g]).max()
+        np.testing.assert_allclose(a["grids"][g], b["grids"][g], rtol=0, atol=1e-10 * sc)
