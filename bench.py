@@ -268,7 +268,7 @@ def main():
                    "v_cycles_per_step": w.mg_fixed_cycles, "V_rf": w.V_rf, "f_rf": w.f_rf},
         "breakdown_ms_per_step": {k: tm[k] for k in ("step_ms", "solve_ms", "pass_ms",
                                                      "collide_ms", "grid_ms", "lists_ms",
-                                                     "resize_ms")},
+                                                     "resize_ms", "sort_ms")},
         "vcycle_ms": {"mixed": tm["solve_ms"] / max(tm["vcycles"], 1)},
         "fp64": None if fp64 is None else {
             "value": fp64["value"], "ms_per_step": fp64["ms_per_step"],

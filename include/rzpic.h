@@ -78,9 +78,13 @@ typedef struct rzpic_config {
     int32_t mg_max_cycles;    /* cap on V(0,1) cycles per solve              */
     int32_t mg_fixed_cycles;  /* > 0: exactly this many cycles, no test      */
     int32_t resize_every;     /* weight split period in steps, 0 = never     */
-    int32_t reserved0;
+    int32_t sort_every;       /* tile sort period in steps (rzpic_sort of both
+                               * species at the end of every sort_every-th
+                               * step), 0 = never                            */
     double resize_wcoef;      /* split weight w_r(r) = resize_wcoef*max(r,hr/2) */
     double n_gas, T_gas, m_gas; /* neutral density (m^-3), temperature (K), mass (kg) */
+    int32_t tile_z, tile_r;   /* cells per sort tile in z and r (0 -> 16, 32);
+                               * at most 2048 tiles                          */
 } rzpic_config;
 
 typedef struct rzpic_species_view {
@@ -182,12 +186,24 @@ rzpic_status rzpic_collide(rzpic_ctx *ctx, int32_t s, int64_t step);
 rzpic_status rzpic_compact(rzpic_ctx *ctx, int32_t s);
 /* Weight split of Sec. 2.2 (clones appended in parent order). */
 rzpic_status rzpic_resize(rzpic_ctx *ctx, int32_t s);
+/* Stable sort of the particles of species s by tile (Sec. 2.7 orders
+ * particles by cell for the weighting): key = tile of the cell
+ * (floor(z/hz), floor(r/hr)), clamped to the mesh, tiles of tile_z x tile_r
+ * cells numbered r fastest; particles of one tile keep their order.  Moves
+ * every particle array (mc_event is not reordered).  When the deposit grid
+ * does not fit in LDS, later particle passes give each block a contiguous
+ * range of the sorted array and deposit into an LDS window of its tiles; the
+ * results do not depend on it.  ESTATE while new particles are staged.
+ * Allocates the sort's scratch on first use unless config.sort_every > 0
+ * (then rzpic_bind_species does). */
+rzpic_status rzpic_sort(rzpic_ctx *ctx, int32_t s);
 /* After initialisation: first push, deposit and compaction of both species. */
 rzpic_status rzpic_prologue(rzpic_ctx *ctx);
 /* One merged step n (Sec. 2.1): finalize rho/chi, solve at t = (n+1) dt,
  * E, one fused particle pass per species (gather, final push, MC, first
- * push, deposit), compaction, and the periodic weight split.  Equal, bit for
- * bit, to the composition of the single operations above. */
+ * push, deposit), compaction, the periodic weight split (with the deposit
+ * redone) and the periodic tile sort.  Equal, bit for bit, to the
+ * composition of the single operations above. */
 rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
 
 /* Copy grid `which` (RZPIC_G_*) between the context and a caller device
@@ -212,9 +228,10 @@ void rzpic_constants(double out[6]);
  *   out[5] collision kernels of both species + deposit slice sum (ms)
  *   out[6] finalize + E field (ms)   out[7] list maintenance (ms)
  *   out[8] electrons, out[9] ions entering the pass (per step)
- *   out[10] weight split and its re-deposit (ms, 0 on other steps) */
+ *   out[10] weight split (ms, 0 on other steps)
+ *   out[11] tile sort and the deposit redone after a weight split (ms) */
 rzpic_status rzpic_set_timing(rzpic_ctx *ctx, int32_t enable);
-rzpic_status rzpic_get_timing(rzpic_ctx *ctx, double out[11]);
+rzpic_status rzpic_get_timing(rzpic_ctx *ctx, double out[12]);
 
 #ifdef __cplusplus
 }

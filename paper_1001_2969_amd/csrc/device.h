@@ -57,6 +57,7 @@ __device__ __forceinline__ void normal2(double ua, double ub, double &n1, double
 
 template <typename T> struct W4 {
     int g;       // index of node (i, j)
+    int i, j;    // cell
     T sz0, sz1, sr0, sr1;
 };
 
@@ -79,6 +80,8 @@ template <typename T> __device__ __forceinline__ W4<T> weights(const Mesh &m, T 
     i = i < 0 ? 0 : (i > m.nz - 2 ? m.nz - 2 : i);
     j = j < 0 ? 0 : (j > m.nr - 2 ? m.nr - 2 : j);
     q.g = i * m.nr + j;
+    q.i = i;
+    q.j = j;
     T zi = (T)i * (T)m.hz, zi1 = (T)(i + 1) * (T)m.hz;
     q.sz0 = (zi1 - z) * ihz;
     q.sz1 = (z - zi) * ihz;

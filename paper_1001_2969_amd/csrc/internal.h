@@ -20,6 +20,9 @@ constexpr int kMaxLevels = 16;
 constexpr int kChunk = 64;       // particles per chunk: one wavefront
 constexpr int kMaxWaves = 16384; // wavefronts of a particle pass (bounds the bucket padding)
 constexpr int kMaxLine = 2048;   // longest r-line (nr - 1 unknowns) the smoother takes
+constexpr int kMaxTiles = 2048;  // tiles of the particle sort
+constexpr int kWinNodes = 4096;  // LDS deposit window of a tiled pass block (nodes)
+constexpr int kWinHalo = 8;      // cells of drift margin around a block's tiles
 
 // Device status bits (sticky).
 enum : int32_t {
@@ -36,6 +39,8 @@ enum : int {
     M_MARK = 16,   // unmerged form: dead particles carry w = -1, skipped on input
     M_LISTS = 32,  // merged form: per-chunk dead lists built in the pass
     M_LDS = 64,    // deposit into an LDS copy of the whole grid, flushed to a slice
+    M_TILE = 128,  // blocks take contiguous particle ranges and deposit into an
+                   // LDS window of the tiles their (sorted) particles occupy
 };
 // The fused pass only tests for Monte Carlo candidates (M_MC): a candidate
 // keeps its final-pushed state and goes to the candidate list, where the
@@ -144,7 +149,23 @@ template <typename T> struct PassArgs {
     int bucket_waves;             // wavefronts per pass block
     int32_t *status;
     uint32_t step;
+    // M_TILE: block ranges and deposit windows planned at the last sort
+    // (per_block = 0 or a plan made for another block count: no windows)
+    int tiled;                    // the pass ran with M_TILE (bucket layout)
+    int tile_nb;                  // pass blocks the plan was made for
+    const int64_t *tile_pb;       // particles per block, multiple of kChunk
+    const int4 *tile_win;         // [tile_nb] window {i0, j0, ni, nj} in nodes
 };
+
+// Candidate bucket of each pass block: chunks it may process.  Grid-stride
+// form: ceil(nch / waves) per wavefront; tiled form: its planned range plus
+// its share of the chunks beyond the planned ones.
+__host__ __device__ inline int64_t tiled_q(int64_t pb) { return pb / kChunk; }
+__host__ __device__ inline int64_t tiled_q2(int64_t nch, int nb, int64_t q)
+{
+    const int64_t rem = nch - (int64_t)nb * q;
+    return rem > 0 ? (rem + nb - 1) / nb : 0;
+}
 
 // Sum of per-block LDS deposit slices into the deposit grids of both
 // species, run by extra blocks of the collision launch: block b of those
@@ -220,6 +241,22 @@ hipError_t launch_reduce_slices2(unsigned long long *acc0, const unsigned long l
                                  int nb0, unsigned long long *acc1,
                                  const unsigned long long *slices1, int nb1, int nn,
                                  hipStream_t st);
+
+// sort.hip: stable counting sort of a species by tile of the cell of each
+// particle, and the window plan of the tiled pass.
+template <typename T> struct SortArgs {
+    Parts<T> p, tmp;         // particles; staging of the sorted copy
+    const Counts *cnt;
+    double hr, hz;           // the key divides positions by the spacings
+    int nr, nz, tile_z, tile_r, ntr, nt, kbits;
+    int64_t seg, nseg;       // particles per segment (one wavefront), segments
+    int64_t *off;            // [nt * nseg + 1]: counts, then exclusive offsets
+    int64_t *part;           // scan partial sums
+    int64_t *tile_pb;        // plan: particles per pass block
+    int4 *tile_win;          // plan: [nb] deposit windows
+    int nb;                  // pass blocks of the plan
+};
+template <typename T> hipError_t launch_sort(const SortArgs<T> &a, hipStream_t st);
 
 // grid.hip
 struct GridArgs {

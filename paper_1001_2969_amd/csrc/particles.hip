@@ -9,22 +9,32 @@ namespace rz {
 // point (quantum = w_ref 2^-bits) so that the sum does not depend on order.
 // Contributions must stay below 2^51 quanta (a weight below 2^(51-bits)
 // w_ref); a larger one is flagged and the step reports RZPIC_ENUMERIC.
+// The four nodes of the cell sit at acc[g], acc[g + 1], acc[g + stride] and
+// acc[g + stride + 1] (stride nr for a whole grid, the row length of a window).
 template <typename T>
-__device__ __forceinline__ void deposit4(unsigned long long *acc, const Mesh &m, const W4<T> &q,
-                                         double w, double inv_quantum, int32_t *status)
+__device__ __forceinline__ void deposit4_at(unsigned long long *acc, int g, int stride,
+                                            const W4<T> &q, double w, double inv_quantum,
+                                            int32_t *status)
 {
     const double ws = w * inv_quantum;
     if (!(fabs(ws) < 0x1p51)) atomicOr(status, kStNumeric);
     const double a = (double)q.sz0 * (double)q.sr0, b = (double)q.sz0 * (double)q.sr1;
     const double c = (double)q.sz1 * (double)q.sr0, d = (double)q.sz1 * (double)q.sr1;
-    __hip_atomic_fetch_add(acc + q.g, (unsigned long long)round_fixed(ws * a), __ATOMIC_RELAXED,
+    __hip_atomic_fetch_add(acc + g, (unsigned long long)round_fixed(ws * a), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(acc + q.g + 1, (unsigned long long)round_fixed(ws * b),
+    __hip_atomic_fetch_add(acc + g + 1, (unsigned long long)round_fixed(ws * b),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(acc + q.g + m.nr, (unsigned long long)round_fixed(ws * c),
+    __hip_atomic_fetch_add(acc + g + stride, (unsigned long long)round_fixed(ws * c),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(acc + q.g + m.nr + 1, (unsigned long long)round_fixed(ws * d),
+    __hip_atomic_fetch_add(acc + g + stride + 1, (unsigned long long)round_fixed(ws * d),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void deposit4(unsigned long long *acc, const Mesh &m, const W4<T> &q,
+                                         double w, double inv_quantum, int32_t *status)
+{
+    deposit4_at<T>(acc, q.g, m.nr, q, w, inv_quantum, status);
 }
 
 __device__ __forceinline__ void tally_add(unsigned long long *t, int b, double w, double inv_q)
@@ -118,13 +128,20 @@ __device__ __forceinline__ void store(const Parts<T> &p, int64_t i, const PState
 }
 
 // One pass over the particles of a species.  Each wavefront processes chunks
-// of 64 consecutive particles (grid-stride over chunks, no block barrier in
-// the loop); MODE selects the steps (M_* bits).  With M_MC a particle that
-// draws U0 < P_null is a candidate: it keeps its final-pushed state, joins the
-// candidate list and skips the rest of the pass (the collision kernel takes
-// over).  The merged form records each chunk's dead particles as a lane mask.
-// With M_LDS the block deposits into its own LDS copy of the grid, written out
-// once at the end to its slice.
+// of 64 consecutive particles (no block barrier in the loop); MODE selects the
+// steps (M_* bits).  With M_MC a particle that draws U0 < P_null is a
+// candidate: it keeps its final-pushed state, joins the candidate list and
+// skips the rest of the pass (the collision kernel takes over).  The merged
+// form records each chunk's dead particles as a lane mask.
+//
+// Deposit targets: by default global atomics on the grid of the species
+// (chunks grid-strided over the wavefronts).  M_LDS: the block deposits into
+// its own LDS copy of the whole grid, written out once at the end to its
+// slice.  M_TILE: the block takes a contiguous range of particles (planned at
+// the last tile sort, so they sit in one or two tiles) and deposits into an
+// LDS window of those tiles plus a drift margin; a particle outside the
+// window, and the chunks beyond the planned ranges, go to global atomics.  The
+// window is added to the grid once at the end.
 //
 // The body takes the block's index lb among the gb blocks of its species, so
 // that one launch can run the passes of both species side by side.
@@ -139,11 +156,13 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
     const int64_t n = a.cnt->n;
     const int64_t nch = (n + kChunk - 1) / kChunk;
     const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
     const int64_t wave = ((int64_t)lb * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gb * blockDim.x) >> 6;
     const T dt = (T)a.phys.dt;
     const T k1 = (T)a.sp.k1, k2 = (T)a.sp.k2, qm = (T)a.sp.qm;
     constexpr bool kLds = (MODE & M_LDS) != 0;
+    constexpr bool kTile = (MODE & M_TILE) != 0;
     constexpr bool kDep = (MODE & M_DEP) != 0;
     constexpr bool kMc = (MODE & M_MC) != 0;
     const bool mc_on = kMc && a.sp.mc_model != 0;
@@ -159,12 +178,28 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         for (int g = threadIdx.x; g < m.nn; g += blockDim.x) lds_acc[g] = 0;
         dep = lds_acc;
     }
-    if (kLds || kMc) __syncthreads();
+    // tiled form: planned chunks per block and this block's window
+    int64_t q = 0;
+    int4 win = make_int4(0, 0, 0, 0);
+    if (kTile) {
+        if (a.tile_pb && a.tile_nb == gb) {
+            q = tiled_q(*a.tile_pb);
+            win = a.tile_win[lb];
+        }
+        if (win.z < 2 || win.w < 2 || win.z * win.w > kWinNodes) win = make_int4(0, 0, 0, 0);
+        for (int g = threadIdx.x; g < win.z * win.w; g += blockDim.x) lds_acc[g] = 0;
+    }
+    // cells inside the window: 0 <= i - i0 < ci, 0 <= j - j0 < cj (none if empty)
+    const unsigned ci = win.z > 1 ? (unsigned)(win.z - 1) : 0u;
+    const unsigned cj = win.w > 1 ? (unsigned)(win.w - 1) : 0u;
+    if (kLds || kTile || kMc) __syncthreads();
 
     // candidates of this block go to its own bucket of the candidate list
-    const int64_t bsize = ((nch + nwaves - 1) / nwaves) * kChunk * (blockDim.x >> 6);
-    int32_t *bucket = a.ch.cand + (int64_t)lb * bsize;
-    for (int64_t c = wave; c < nch; c += nwaves) {
+    const int64_t bchunks =
+        kTile ? q + tiled_q2(nch, gb, q) : ((nch + nwaves - 1) / nwaves) * wpb;
+    int32_t *bucket = a.ch.cand + (int64_t)lb * bchunks * kChunk;
+
+    auto chunk = [&](int64_t c) {
         const int64_t pi = c * kChunk + lane;
         const bool valid = pi < n;
         bool live = valid;
@@ -241,8 +276,19 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
                 died = true;
             }
         }
-        if (kDep && live && !cand)
-            deposit4<T>(dep, m, weights<T>(m, s.r, s.z), (double)s.w, a.sp.inv_quantum, a.status);
+        if (kDep && live && !cand) {
+            const W4<T> w4 = weights<T>(m, s.r, s.z);
+            if (kTile) {
+                const int li = w4.i - win.x, lj = w4.j - win.y;
+                if ((unsigned)li < ci && (unsigned)lj < cj)
+                    deposit4_at<T>(lds_acc, li * win.w + lj, win.w, w4, (double)s.w,
+                                   a.sp.inv_quantum, a.status);
+                else
+                    deposit4<T>(a.acc, m, w4, (double)s.w, a.sp.inv_quantum, a.status);
+            } else {
+                deposit4<T>(dep, m, w4, (double)s.w, a.sp.inv_quantum, a.status);
+            }
+        }
         if (valid) {
             if ((MODE & M_MARK) && died) a.p.w[pi] = (T)-1;
             else if (live && moved) store(a.p, pi, s, false);
@@ -251,6 +297,20 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
             unsigned long long dm = __ballot(died);
             if (lane == 0) a.ch.dead[c] = dm;
         }
+    };
+
+    if (kTile) {
+        // the planned range, then this block's share of the chunks beyond
+        const int wib = threadIdx.x >> 6;
+        const int64_t c0 = (int64_t)lb * q;
+        const int64_t c1 = c0 + q < nch ? c0 + q : nch;
+        for (int64_t c = c0 + wib; c < c1; c += wpb) chunk(c);
+        const int64_t q2 = tiled_q2(nch, gb, q);
+        const int64_t d0 = (int64_t)gb * q + (int64_t)lb * q2;
+        const int64_t d1 = d0 + q2 < nch ? d0 + q2 : nch;
+        for (int64_t c = d0 + wib; c < d1; c += wpb) chunk(c);
+    } else {
+        for (int64_t c = wave; c < nch; c += nwaves) chunk(c);
     }
     if (kMc) {
         __syncthreads();
@@ -263,6 +323,16 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         __syncthreads();
         unsigned long long *out = a.slices + (size_t)lb * m.nn;
         for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds_acc[g];
+    }
+    if (kTile) {
+        __syncthreads();
+        for (int g = threadIdx.x; g < win.z * win.w; g += blockDim.x) {
+            const unsigned long long v = lds_acc[g];
+            if (v) {
+                const int i = g / win.w, j = g - i * win.w;
+                atomicAdd(a.acc + (size_t)(win.x + i) * m.nr + win.y + j, v);
+            }
+        }
     }
 }
 
@@ -308,7 +378,14 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
     const int64_t nch = (a.cnt->n + kChunk - 1) / kChunk;
     const int64_t NB = a.nbuckets;
     const int64_t pass_waves = NB * a.bucket_waves;
-    const int64_t bsize = ((nch + pass_waves - 1) / pass_waves) * kChunk * a.bucket_waves;
+    int64_t bchunks;
+    if (a.tiled) {
+        const int64_t q = a.tile_pb && a.tile_nb == NB ? tiled_q(*a.tile_pb) : 0;
+        bchunks = q + tiled_q2(nch, (int)NB, q);
+    } else {
+        bchunks = ((nch + pass_waves - 1) / pass_waves) * a.bucket_waves;
+    }
+    const int64_t bsize = bchunks * kChunk;
     const int64_t R = nwaves >= NB ? nwaves / NB : 1;
     for (int64_t t = wave; t < NB * R; t += nwaves) {
       const int64_t b = t % NB, seg = t / NB;
@@ -513,6 +590,9 @@ hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, 
         RZ_CASE(M_DEP | M_LDS)
         RZ_CASE(M_DEP | M_MARK)
         RZ_CASE(M_DEP | M_MARK | M_LDS)
+        RZ_CASE(M_DEP | M_TILE)
+        RZ_CASE(M_DEP | M_MARK | M_TILE)
+        RZ_CASE(M_FIRST | M_DEP | M_LISTS | M_TILE)
         RZ_CASE(M_FINAL | M_MARK)
         RZ_CASE(M_FIRST | M_MARK)
         RZ_CASE(M_MC | M_MARK)
@@ -574,6 +654,9 @@ hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, 
 {
     if (mode == (M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS))
         hipLaunchKernelGGL((k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS>),
+                           dim3(b0 + b1), dim3(threads), lds, st, a0, a1, b0);
+    else if (mode == (M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_TILE))
+        hipLaunchKernelGGL((k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_TILE>),
                            dim3(b0 + b1), dim3(threads), lds, st, a0, a1, b0);
     else if (mode == (M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS))
         hipLaunchKernelGGL((k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS>),

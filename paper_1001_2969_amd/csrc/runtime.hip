@@ -58,7 +58,30 @@ struct SpeciesState {
     Xsec xs{};
     double nu_max = 0.0, p_null = 0.0;
     DevBuf sigma;
+    // tile sort: sorted-copy staging (8 real arrays + identities), per-segment
+    // tile counts/offsets, scan partials, and the window plan of the pass
+    void *sort_buf[9] = {};
+    int64_t *sort_off = nullptr, *sort_part = nullptr, *tile_pb = nullptr;
+    int4 *tile_win = nullptr;
+    int64_t sort_seg = 0, sort_nseg = 0;
+    int tile_nb = 0;  // pass blocks the plan is made for
 };
+
+void free_sort(SpeciesState &ss)
+{
+    for (void *&p : ss.sort_buf)
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+    for (void *p : {(void *)ss.sort_off, (void *)ss.sort_part, (void *)ss.tile_pb,
+                    (void *)ss.tile_win})
+        if (p) (void)hipFree(p);
+    ss.sort_off = ss.sort_part = ss.tile_pb = nullptr;
+    ss.tile_win = nullptr;
+    ss.sort_seg = ss.sort_nseg = 0;
+    ss.tile_nb = 0;
+}
 
 }  // namespace
 
@@ -74,6 +97,7 @@ struct rzpic_ctx {
     int nn = 0;
     double quantum[2] = {1.0, 1.0};
     std::vector<void *> allocs;
+    int ntr = 1, nt = 1, kbits = 0;  // tiles in r, tiles, bits of a tile key
 
     // grids
     double *phi, *rho, *chi, *er, *ez, *dens[2], *vol, *f, *eps;
@@ -102,9 +126,9 @@ struct rzpic_ctx {
     int last_cycles = 0;
     double last_relres = 0.0;
     unsigned long long *psteps;  // [2]
-    // timing: per recorded step 9 events (see mark())
+    // timing: per recorded step 10 events (see mark())
     bool timing = false;
-    static constexpr int kEvPerStep = 9, kPool = 128;
+    static constexpr int kEvPerStep = 10, kPool = 128;
     std::vector<hipEvent_t> evpool;
     int ev_used = 0;        // steps recorded in the pool
     double acc_ms[8] = {};  // accumulated phase times (see flush_timing)
@@ -255,7 +279,21 @@ template <typename T> PassArgs<T> pass_args(rzpic_ctx *c, int s, uint32_t step)
     a.crec = s == 0 ? c->crec : nullptr;
     a.status = c->status;
     a.step = step;
+    a.tile_pb = c->sp[s].tile_pb;
+    a.tile_win = c->sp[s].tile_win;
+    a.tile_nb = c->sp[s].tile_nb;
     return a;
+}
+
+// Blocks of the tiled pass of species s: two 2048-thread CU slots shared by
+// the two species, fewer for small capacities.  The window plan of the sort
+// is made for this count.
+int tiled_blocks(const rzpic_ctx *c, int s)
+{
+    const int threads = c->pass_threads;
+    const int64_t need = (c->sp[s].cap + threads - 1) / threads;
+    const int bl = c->cus * (2048 / threads) / 2;
+    return (int)(need < bl ? (need > 0 ? need : 1) : bl);
 }
 
 rzpic_status need_species(rzpic_ctx *c, int s)
@@ -302,6 +340,11 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
         mode |= M_LDS;
         lds = (size_t)c->nn * sizeof(unsigned long long);
         blocks = c->slice_blocks;
+    } else if ((mode & M_DEP) && !(mode & M_MC)) {
+        mode |= M_TILE;
+        lds = (size_t)kWinNodes * sizeof(unsigned long long);
+        blocks = tiled_blocks(c, s);
+        a.tiled = 1;
     } else {
         int64_t need = (c->sp[s].cap + threads - 1) / threads;
         blocks = c->cus * (2048 / threads);
@@ -358,16 +401,17 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
         b[0] = c->slice_blocks / 2;
         b[1] = c->slice_blocks - b[0];
     } else {
-        for (int s = 0; s < 2; ++s) {
-            int64_t need = (c->sp[s].cap + threads - 1) / threads;
-            int bl = c->cus * (2048 / threads) / 2;
-            b[s] = (int)(need < bl ? (need > 0 ? need : 1) : bl);
-        }
+        // grid larger than LDS: contiguous block ranges with LDS windows of
+        // the tiles planned at the last sort (global atomics without a plan)
+        mode |= M_TILE;
+        lds = (size_t)kWinNodes * sizeof(unsigned long long);
+        for (int s = 0; s < 2; ++s) b[s] = tiled_blocks(c, s);
     }
     for (int s = 0; s < 2; ++s) {
         a[s].psteps = c->psteps + s;
         a[s].nbuckets = b[s];
         a[s].bucket_waves = threads / 64;
+        a[s].tiled = (mode & M_TILE) ? 1 : 0;
     }
     a[1].slices = c->slices + (size_t)b[0] * c->nn;
     if ((b[0] + b[1]) * (threads / 64) > kMaxWaves)
@@ -605,10 +649,79 @@ template <typename T> rzpic_status resize_impl(rzpic_ctx *c, int s)
     return RZPIC_OK;
 }
 
+// Scratch of the tile sort of species s (sized by its capacity).
+rzpic_status sort_alloc(rzpic_ctx *c, int s)
+{
+    SpeciesState &ss = c->sp[s];
+    if (ss.sort_off) return RZPIC_OK;
+    const size_t cap = (size_t)ss.cap + kChunk;
+    const size_t es = c->mixed ? sizeof(float) : sizeof(double);
+    // segments of at least 4096 particles, at most 2^22 (tile, segment) counts
+    int64_t seg = 4096;
+    while (((int64_t)cap + seg - 1) / seg * c->nt > ((int64_t)1 << 22)) seg *= 2;
+    ss.sort_seg = seg;
+    ss.sort_nseg = ((int64_t)cap + seg - 1) / seg;
+    const size_t M = (size_t)ss.sort_nseg * c->nt + 1;
+    auto get = [&](void **p, size_t bytes) -> rzpic_status {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            free_sort(ss);
+            return fail(RZPIC_ENOMEM, "hipMalloc(%zu) for the tile sort failed", bytes);
+        }
+        return RZPIC_OK;
+    };
+    for (int f = 0; f < 8; ++f) TRY(get(&ss.sort_buf[f], cap * es));
+    TRY(get(&ss.sort_buf[8], cap * sizeof(uint64_t)));
+    TRY(get((void **)&ss.sort_off, M * sizeof(int64_t)));
+    TRY(get((void **)&ss.sort_part, 4096 * sizeof(int64_t)));
+    TRY(get((void **)&ss.tile_pb, sizeof(int64_t)));
+    TRY(get((void **)&ss.tile_win, (size_t)kMaxWaves * sizeof(int4)));
+    HIPCHK(launch_fill_u64((unsigned long long *)ss.tile_pb, 1, c->st));
+    return RZPIC_OK;
+}
+
+// Stable counting sort of species s by tile, then the window plan of its
+// tiled pass.  Positions are unchanged, so the deposit grids stay valid.
+template <typename T> rzpic_status sort_impl(rzpic_ctx *c, int s)
+{
+    if (c->nt > kMaxTiles)
+        return fail(RZPIC_EINVAL, "%d tiles exceed %d: enlarge tile_z / tile_r", c->nt, kMaxTiles);
+    TRY(sort_alloc(c, s));
+    SpeciesState &ss = c->sp[s];
+    SortArgs<T> a{};
+    a.p = parts_of<T>(ss.v);
+    Parts<T> t{};
+    T **tf[8] = {&t.r, &t.z, &t.vr, &t.vt, &t.vz, &t.ar, &t.az, &t.w};
+    for (int f = 0; f < 8; ++f) *tf[f] = (T *)ss.sort_buf[f];
+    t.id = (uint64_t *)ss.sort_buf[8];
+    a.tmp = t;
+    a.cnt = c->cnt + s;
+    a.hr = c->hr;
+    a.hz = c->hz;
+    a.nr = c->c.nr;
+    a.nz = c->c.nz;
+    a.tile_z = c->c.tile_z;
+    a.tile_r = c->c.tile_r;
+    a.ntr = c->ntr;
+    a.nt = c->nt;
+    a.kbits = c->kbits;
+    a.seg = ss.sort_seg;
+    a.nseg = ss.sort_nseg;
+    a.off = ss.sort_off;
+    a.part = ss.sort_part;
+    a.tile_pb = ss.tile_pb;
+    a.tile_win = ss.tile_win;
+    a.nb = tiled_blocks(c, s);
+    HIPCHK(launch_sort<T>(a, c->st));
+    ss.tile_nb = a.nb;
+    return RZPIC_OK;
+}
+
 // Timing marks of one step: 0 start, 1 after finalize, 2 after solve,
 // 3 after E, 4/5 around the fused pass kernel, 6 after the collision kernels
-// and the slice reduction, 7 after list maintenance, 8 end (after a weight
-// split, if any).
+// and the slice reduction, 7 after list maintenance, 8 after a weight split
+// (if any), 9 end (after a tile sort, if any).
 rzpic_status flush_timing(rzpic_ctx *c);
 
 void mark(rzpic_ctx *c, int k)
@@ -629,13 +742,14 @@ rzpic_status flush_timing(rzpic_ctx *c)
     };
     for (int st = 0; st < c->ev_used; ++st) {
         hipEvent_t *e = &c->evpool[(size_t)st * E];
-        c->acc_ms[0] += el(e[0], e[8]);
+        c->acc_ms[0] += el(e[0], e[9]);
         c->acc_ms[1] += el(e[1], e[2]);
         c->acc_ms[2] += el(e[4], e[5]);
         c->acc_ms[3] += el(e[5], e[6]);
         c->acc_ms[4] += el(e[0], e[1]) + el(e[2], e[4]);
         c->acc_ms[5] += el(e[6], e[7]);
         c->acc_ms[6] += el(e[7], e[8]);
+        c->acc_ms[7] += el(e[8], e[9]);
     }
     c->acc_steps += c->ev_used;
     c->ev_used = 0;
@@ -668,12 +782,21 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
     c->children_scanned = false;
     TRY(run_fixup<T>(c, 3));
     mark(c, 7);
-    if (c->c.resize_every > 0 && n % c->c.resize_every == c->c.resize_every - 1) {
+    // Weight split, then the deposit from scratch; a tile sort due at this
+    // step runs in between (the fixed-point deposit does not depend on the
+    // particle order, and the sorted order gives the deposit its windows).
+    const bool resize = c->c.resize_every > 0 && n % c->c.resize_every == c->c.resize_every - 1;
+    const bool sort = c->c.sort_every > 0 && n % c->c.sort_every == c->c.sort_every - 1;
+    if (resize)
         for (int s = 0; s < 2; ++s) TRY(resize_impl<T>(c, s));
+    mark(c, 8);
+    if (sort)
+        for (int s = 0; s < 2; ++s) TRY(sort_impl<T>(c, s));
+    if (resize) {
         for (int s = 0; s < 2; ++s) HIPCHK(launch_fill_u64(c->acc[s], c->nn, c->st));
         for (int s = 0; s < 2; ++s) TRY(run_pass<T>(c, s, M_DEP, 0));
     }
-    mark(c, 8);
+    mark(c, 9);
     if (c->timing) c->ev_used++;
     return RZPIC_OK;
 }
@@ -720,6 +843,8 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         return fail(RZPIC_EINVAL, "fixed_point_bits = %d out of [0, 52]", k.fixed_point_bits);
     if (k.resize_every < 0 || (k.resize_every > 0 && !(k.resize_wcoef > 0)))
         return fail(RZPIC_EINVAL, "resize_every > 0 needs resize_wcoef > 0");
+    if (k.sort_every < 0 || k.tile_z < 0 || k.tile_r < 0)
+        return fail(RZPIC_EINVAL, "sort_every, tile_z and tile_r must be >= 0");
 
     rzpic_ctx *c = new rzpic_ctx();
     c->c = k;
@@ -729,6 +854,16 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     c->hr = k.R / (double)(k.nr - 1);
     c->hz = k.L / (double)(k.nz - 1);
     c->nn = k.nr * k.nz;
+    if (c->c.tile_z == 0) c->c.tile_z = 16;
+    if (c->c.tile_r == 0) c->c.tile_r = 32;
+    c->ntr = (k.nr - 2) / c->c.tile_r + 1;
+    c->nt = ((k.nz - 2) / c->c.tile_z + 1) * c->ntr;
+    while ((1 << c->kbits) < c->nt) ++c->kbits;
+    if (k.sort_every > 0 && c->nt > kMaxTiles) {
+        const int nt = c->nt;
+        delete c;
+        return fail(RZPIC_EINVAL, "%d tiles exceed %d: enlarge tile_z / tile_r", nt, kMaxTiles);
+    }
     int L = 0;
     while ((1 << L) < k.nz - 1) ++L;
     c->L = L;
@@ -862,6 +997,7 @@ rzpic_status rzpic_destroy(rzpic_ctx *c)
             for (int f = 0; f < 8; ++f)
                 if (c->sp[s].stage[a][f]) (void)hipFree(c->sp[s].stage[a][f]);
         if (c->sp[s].sigma.p) (void)hipFree(c->sp[s].sigma.p);
+        free_sort(c->sp[s]);
     }
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     delete c;
@@ -897,6 +1033,7 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
                 (void)hipFree(ss.stage[a][f]);
                 ss.stage[a][f] = nullptr;
             }
+    free_sort(ss);
     ss.v = *v;
     ss.cap = v->capacity;
     ss.bound = true;
@@ -919,6 +1056,7 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
         for (int a = 0; a < 2; ++a)
             for (int f = 0; f < 8; ++f) HIPCHK(hipMalloc(&ss.stage[a][f], cap * es));
     }
+    if (c->c.sort_every > 0) TRY(sort_alloc(c, s));
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, (int64_t)0, (uint64_t)0);
     HIPCHK(hipGetLastError());
     return RZPIC_OK;
@@ -1121,6 +1259,15 @@ rzpic_status rzpic_resize(rzpic_ctx *c, int32_t s)
     return RZPIC_OK;
 }
 
+rzpic_status rzpic_sort(rzpic_ctx *c, int32_t s)
+{
+    TRY(need_species(c, s));
+    if (c->children_pending[s]) return fail(RZPIC_ESTATE, "call rzpic_compact before rzpic_sort");
+    if (c->mixed) TRY(sort_impl<float>(c, s));
+    else TRY(sort_impl<double>(c, s));
+    return RZPIC_OK;
+}
+
 rzpic_status rzpic_prologue(rzpic_ctx *c)
 {
     TRY(need_both(c));
@@ -1241,7 +1388,7 @@ rzpic_status rzpic_set_timing(rzpic_ctx *c, int32_t enable)
     return RZPIC_OK;
 }
 
-rzpic_status rzpic_get_timing(rzpic_ctx *c, double out[11])
+rzpic_status rzpic_get_timing(rzpic_ctx *c, double out[12])
 {
     if (!c || !out) return fail(RZPIC_EINVAL, "null argument");
     TRY(flush_timing(c));
@@ -1260,6 +1407,7 @@ rzpic_status rzpic_get_timing(rzpic_ctx *c, double out[11])
     out[8] = ((double)ps[0] - c->acc_n[0]) / k;
     out[9] = ((double)ps[1] - c->acc_n[1]) / k;
     out[10] = c->acc_ms[6] / k;
+    out[11] = c->acc_ms[7] / k;
     c->acc_n[0] = (double)ps[0];
     c->acc_n[1] = (double)ps[1];
     for (double &v : c->acc_ms) v = 0.0;

@@ -25,7 +25,7 @@ EXPORTS = (
     "rzpic_push_first", "rzpic_deposit", "rzpic_solve", "rzpic_efield", "rzpic_push_final",
     "rzpic_collide", "rzpic_compact", "rzpic_resize", "rzpic_prologue", "rzpic_step",
     "rzpic_grid_copy", "rzpic_get_diag", "rzpic_sync", "rzpic_last_error", "rzpic_constants",
-    "rzpic_set_timing", "rzpic_get_timing", "rzpic_set_mg",
+    "rzpic_set_timing", "rzpic_get_timing", "rzpic_set_mg", "rzpic_sort",
 )
 
 
@@ -44,9 +44,10 @@ class Config(C.Structure):
         ("V_dc", C.c_double), ("V_rf", C.c_double), ("f_rf", C.c_double),
         ("seed", C.c_uint64),
         ("mg_tol", C.c_double), ("mg_max_cycles", C.c_int32), ("mg_fixed_cycles", C.c_int32),
-        ("resize_every", C.c_int32), ("reserved0", C.c_int32),
+        ("resize_every", C.c_int32), ("sort_every", C.c_int32),
         ("resize_wcoef", C.c_double),
         ("n_gas", C.c_double), ("T_gas", C.c_double), ("m_gas", C.c_double),
+        ("tile_z", C.c_int32), ("tile_r", C.c_int32),
     ]
 
 
@@ -90,7 +91,7 @@ def lib():
             "rzpic_get_mc_consts": [P, I, C.POINTER(D), C.POINTER(D)],
             "rzpic_init_particles": [P, I, C.c_int64, D, D, C.c_uint64],
             "rzpic_push_first": [P, I], "rzpic_push_final": [P, I], "rzpic_compact": [P, I],
-            "rzpic_resize": [P, I], "rzpic_collide": [P, I, C.c_int64],
+            "rzpic_resize": [P, I], "rzpic_sort": [P, I], "rzpic_collide": [P, I, C.c_int64],
             "rzpic_deposit": [P], "rzpic_efield": [P], "rzpic_prologue": [P],
             "rzpic_solve": [P, D, C.POINTER(I), C.POINTER(D)],
             "rzpic_step": [P, C.c_int64], "rzpic_grid_copy": [P, I, P, I],
@@ -143,8 +144,9 @@ class Context:
                      mg_max_cycles=w.mg_max_cycles if mg_max_cycles is None else mg_max_cycles,
                      mg_fixed_cycles=(w.mg_fixed_cycles if mg_fixed_cycles is None
                                       else mg_fixed_cycles),
-                     resize_every=w.resize_every, reserved0=0, resize_wcoef=w.wcoef,
-                     n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas)
+                     resize_every=w.resize_every, sort_every=w.sort_every,
+                     resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
+                     tile_z=w.tile_z, tile_r=w.tile_r)
         self._cfg = cfg
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
@@ -239,6 +241,9 @@ class Context:
     def resize(self, s):
         _check(lib().rzpic_resize(self.h, s))
 
+    def sort(self, s):
+        _check(lib().rzpic_sort(self.h, s))
+
     def deposit(self):
         _check(lib().rzpic_deposit(self.h))
 
@@ -295,10 +300,10 @@ class Context:
 
     def timing(self):
         """Averages per recorded step (see rzpic_get_timing)."""
-        out = (C.c_double * 11)()
+        out = (C.c_double * 12)()
         _check(lib().rzpic_get_timing(self.h, C.cast(out, C.c_void_p)))
         keys = ("steps", "step_ms", "solve_ms", "vcycles", "pass_ms", "collide_ms",
-                "grid_ms", "lists_ms", "n0", "n1", "resize_ms")
+                "grid_ms", "lists_ms", "n0", "n1", "resize_ms", "sort_ms")
         return dict(zip(keys, list(out)))
 
 

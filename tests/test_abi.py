@@ -43,10 +43,12 @@ def test_create_rejects_bad_configs_without_touching_the_gpu(lib):
     import ctypes as C
     base = dict(nr=33, nz=33, R=0.02, L=0.02, dt=5e-11, precision=0, weighting=0, chi_face=0,
                 fixed_point_bits=0, V_dc=0, V_rf=0, f_rf=0, seed=0, mg_tol=1e-10,
-                mg_max_cycles=50, mg_fixed_cycles=0, resize_every=0, reserved0=0,
-                resize_wcoef=0, n_gas=1e21, T_gas=300, m_gas=6.6e-26)
+                mg_max_cycles=50, mg_fixed_cycles=0, resize_every=0, sort_every=0,
+                resize_wcoef=0, n_gas=1e21, T_gas=300, m_gas=6.6e-26, tile_z=0, tile_r=0)
     for bad in ({"nz": 34}, {"nr": 2}, {"R": 0.0}, {"precision": 7}, {"weighting": 3},
-                {"mg_tol": 0.0}, {"fixed_point_bits": 60}, {"resize_every": 5}):
+                {"mg_tol": 0.0}, {"fixed_point_bits": 60}, {"resize_every": 5},
+                {"sort_every": -1}, {"tile_z": -2},
+                {"nr": 2049, "nz": 2049, "tile_z": 1, "tile_r": 1, "sort_every": 1}):
         cfg = rzpic.Config(**{**base, **bad})
         h = C.c_void_p()
         code = lib.rzpic_create(C.byref(cfg), None, C.byref(h))

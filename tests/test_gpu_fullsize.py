@@ -19,13 +19,17 @@ pytestmark = pytest.mark.gpu
 STEPS = 2
 
 
-def _pair_init(w, precision, capacity_factor=1.25):
+def _pair_init(w, precision, capacity_factor=1.25, sort=False):
     o, g = pair(w, precision=precision, capacity_factor=capacity_factor)
     for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
         o.init_particles(s, w.n_per_species, w.n0, T, 0)
         g.init_particles(s, w.n_per_species, w.n0, T, 0)
     o.prologue()
     g.prologue()
+    if sort:
+        for s in (0, 1):
+            o.sort(s)
+            g.sort(s)
     return o, g
 
 
@@ -68,12 +72,14 @@ def test_fullsize_mixed_two_steps():
 def test_large_mesh_fp64_with_weight_split():
     """513x129 mesh, R = 15 cm, L = 2.5 cm, 16M + 16M particles, power-law
     cross sections, argon at 20 mTorr.  The grid is larger than one
-    workgroup's LDS (deposit by global atomics) and the r-lines have 512
-    unknowns (one-launch-per-level multigrid); the weight split runs after
-    the second step, every particle having moved off the radius its weight
-    was set for."""
-    w = wl.large_513x129().replace(precision="fp64", resize_every=2)
-    o, g = _pair_init(w, "fp64", capacity_factor=2.0)
+    workgroup's LDS: the particles are tile-sorted after the prologue and
+    after every step, and the passes deposit into LDS windows of their
+    tiles.  The r-lines have 512 unknowns.  The weight split runs after the
+    second step (every particle having moved off the radius its weight was
+    set for), followed by the sort and the deposit redone.  Compared in
+    array order, so the sorted orders agree too."""
+    w = wl.large_513x129().replace(precision="fp64", resize_every=2, sort_every=1)
+    o, g = _pair_init(w, "fp64", capacity_factor=2.0, sort=True)
     for n in range(STEPS):
         assert o.step(n) == 0
         g.step(n)
@@ -90,9 +96,11 @@ def test_large_mesh_mixed():
     """The mixed form on the 513x129 mesh.  FP32 positions resolve about
     5e-5 of a cell at r = R = 15 cm, and the charge density is a nearly
     cancelling difference of the two species, so phi is held to 1e-4 here
-    (1e-5 on the 129x65 mesh, where a cell is 3x larger relative to R)."""
-    w = wl.large_513x129()
-    o, g = _pair_init(w, "mixed")
+    (1e-5 on the 129x65 mesh, where a cell is 3x larger relative to R).
+    Tile-sorted after the prologue and after every step as in the FP64
+    test; particles are matched by identity."""
+    w = wl.large_513x129().replace(sort_every=1)
+    o, g = _pair_init(w, "mixed", sort=True)
     for n in range(STEPS):
         assert o.step(n) == 0
         g.step(n)
