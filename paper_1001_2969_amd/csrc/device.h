@@ -61,14 +61,12 @@ template <typename T> struct W4 {
     T sz0, sz1, sr0, sr1;
 };
 
-template <typename T> __device__ __forceinline__ const T *inv2j1_of(const Mesh &m);
-template <> __device__ __forceinline__ const double *inv2j1_of<double>(const Mesh &m)
+// 1 / (2j + 1), correctly rounded in double (then rounded to T): computed in
+// registers rather than looked up, which would put a dependent memory round
+// trip in front of every weighting.
+template <typename T> __device__ __forceinline__ T inv2j1(int j)
 {
-    return m.inv2j1;
-}
-template <> __device__ __forceinline__ const float *inv2j1_of<float>(const Mesh &m)
-{
-    return m.inv2j1f;
+    return (T)(1.0 / (double)(2 * j + 1));
 }
 
 template <typename T> __device__ __forceinline__ W4<T> weights(const Mesh &m, T r, T z)
@@ -92,7 +90,7 @@ template <typename T> __device__ __forceinline__ W4<T> weights(const Mesh &m, T 
     } else {
         // (r_{j+1}^2 - r^2) / (r_{j+1}^2 - r_j^2) with r = x hr: ((j+1)^2 - x^2) / (2j+1)
         T x2 = xr * xr;
-        T inv = inv2j1_of<T>(m)[j];
+        T inv = inv2j1<T>(j);
         q.sr0 = ((T)((j + 1) * (j + 1)) - x2) * inv;
         q.sr1 = (x2 - (T)(j * j)) * inv;
     }

@@ -59,8 +59,6 @@ template <typename T> struct Parts {
 struct Mesh {
     int nr, nz, nn, weighting;
     double R, L, hr, hz, inv_hr, inv_hz;
-    const double *inv2j1;  // 1 / (2j + 1)
-    const float *inv2j1f;
 };
 
 struct Xsec {
@@ -185,6 +183,8 @@ hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, 
 template <typename T>
 hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, int b0, int b1,
                         int threads, size_t lds, hipStream_t st);
+// Resident blocks per CU of the tiled merged pass (register and LDS limits).
+template <typename T> int pass2_tiled_blocks_per_cu(int threads);
 template <typename T>
 hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
                            int threads, const SliceSum &r, hipStream_t st);

@@ -79,17 +79,24 @@ template <typename T> __device__ __forceinline__ void first_push(PState<T> &s, T
     s.ar = s.ar * c;
 }
 
-// Gather E at (r, z) with the deposit weights, then the final push, the
-// damped-acceleration update and the axis rule (Sec. 2.1, 2.3).
+// Gather of E at (r, z) with the deposit weights (any position: the cell is
+// clamped to the mesh).
 template <typename T>
-__device__ __forceinline__ void final_push(PState<T> &s, const Mesh &m,
-                                           const typename Vec2<T>::type *E2, T k1, T k2, T qm)
+__device__ __forceinline__ void gather_E(const Mesh &m, const typename Vec2<T>::type *E2, T r, T z,
+                                         T &Er, T &Ez)
 {
-    W4<T> q = weights<T>(m, s.r, s.z);
+    W4<T> q = weights<T>(m, r, z);
     auto e00 = E2[q.g], e01 = E2[q.g + 1], e10 = E2[q.g + m.nr], e11 = E2[q.g + m.nr + 1];
     T w00 = q.sz0 * q.sr0, w01 = q.sz0 * q.sr1, w10 = q.sz1 * q.sr0, w11 = q.sz1 * q.sr1;
-    T Er = w00 * e00.x + w01 * e01.x + w10 * e10.x + w11 * e11.x;
-    T Ez = w00 * e00.y + w01 * e01.y + w10 * e10.y + w11 * e11.y;
+    Er = w00 * e00.x + w01 * e01.x + w10 * e10.x + w11 * e11.x;
+    Ez = w00 * e00.y + w01 * e01.y + w10 * e10.y + w11 * e11.y;
+}
+
+// Final push with the gathered field, the damped-acceleration update and the
+// axis rule (Sec. 2.1, 2.3).
+template <typename T>
+__device__ __forceinline__ void final_push(PState<T> &s, T Er, T Ez, T k1, T k2, T qm)
+{
     T r = s.r + k1 * Er;
     T z = s.z + k1 * Ez;
     T vr = s.vr + k2 * Er;
@@ -199,18 +206,16 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         kTile ? q + tiled_q2(nch, gb, q) : ((nch + nwaves - 1) / nwaves) * wpb;
     int32_t *bucket = a.ch.cand + (int64_t)lb * bchunks * kChunk;
 
-    auto chunk = [&](int64_t c) {
+    // The rest of the cycle of chunk c from its loaded state s, identity pid
+    // and gathered field (Er, Ez).
+    auto chunk = [&](int64_t c, PState<T> s, uint64_t pid, T Er, T Ez) {
         const int64_t pi = c * kChunk + lane;
         const bool valid = pi < n;
         bool live = valid;
-        PState<T> s{};
-        if (valid) {
-            s = load(a.p, pi);
-            if (MODE & M_MARK) live = s.w >= (T)0;
-        }
+        if ((MODE & M_MARK) && valid) live = s.w >= (T)0;
         bool died = false, moved = false;
         if ((MODE & M_FINAL) && live) {
-            final_push<T>(s, m, a.E2, k1, k2, qm);
+            final_push<T>(s, Er, Ez, k1, k2, qm);
             moved = true;
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
@@ -228,7 +233,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
             bool tested = false;
             if (live && mc_on) {
                 double ua, ub;
-                uniform2(a.phys.seed, a.sp.s, a.p.id[pi], a.step, 0, ua, ub);
+                uniform2(a.phys.seed, a.sp.s, pid, a.step, 0, ua, ub);
                 if (ua < a.sp.p_null) {
                     tested = true;
                     cand = true;
@@ -299,18 +304,49 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         }
     };
 
+    // kUnroll chunks per iteration, c, c + step, ... (those below end): the
+    // loads and field gathers of all of them are in flight together before
+    // any is pushed.  Loads are unconditional (an index past n reads particle
+    // 0 and is discarded), so no branch separates them.  Two chunks pay off
+    // where the memory system has the most requests to hide (the tiled and
+    // global forms, at full occupancy); the whole-grid LDS form, whose
+    // resident wavefronts its LDS limits, measured best with one.
+    constexpr int kUnroll = kLds ? 1 : 2;
+    auto group = [&](int64_t c, int64_t step, int64_t end) {
+        int64_t cc[kUnroll];
+        PState<T> s[kUnroll];
+        uint64_t pid[kUnroll];
+        T Er[kUnroll], Ez[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            cc[u] = c + u * step < end ? c + u * step : -1;
+            const int64_t pi = cc[u] * kChunk + lane;
+            const int64_t pl = cc[u] >= 0 && pi < n ? pi : 0;
+            s[u] = load(a.p, pl);
+            pid[u] = kMc ? a.p.id[pl] : 0;
+            Er[u] = Ez[u] = (T)0;
+        }
+        if (MODE & M_FINAL) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                gather_E<T>(m, a.E2, s[u].r, s[u].z, Er[u], Ez[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (cc[u] >= 0) chunk(cc[u], s[u], pid[u], Er[u], Ez[u]);
+    };
     if (kTile) {
         // the planned range, then this block's share of the chunks beyond
         const int wib = threadIdx.x >> 6;
         const int64_t c0 = (int64_t)lb * q;
         const int64_t c1 = c0 + q < nch ? c0 + q : nch;
-        for (int64_t c = c0 + wib; c < c1; c += wpb) chunk(c);
+        for (int64_t c = c0 + wib; c < c1; c += kUnroll * wpb) group(c, wpb, c1);
         const int64_t q2 = tiled_q2(nch, gb, q);
         const int64_t d0 = (int64_t)gb * q + (int64_t)lb * q2;
         const int64_t d1 = d0 + q2 < nch ? d0 + q2 : nch;
-        for (int64_t c = d0 + wib; c < d1; c += wpb) chunk(c);
+        for (int64_t c = d0 + wib; c < d1; c += kUnroll * wpb) group(c, wpb, d1);
     } else {
-        for (int64_t c = wave; c < nch; c += nwaves) chunk(c);
+        for (int64_t c = wave; c < nch; c += kUnroll * nwaves) group(c, nwaves, nch);
     }
     if (kMc) {
         __syncthreads();
@@ -666,6 +702,15 @@ hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, 
     return hipGetLastError();
 }
 
+template <typename T> int pass2_tiled_blocks_per_cu(int threads)
+{
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_TILE>, threads,
+        (size_t)kWinNodes * sizeof(unsigned long long));
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
 template <typename T>
 hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
                            int threads, const SliceSum &r, hipStream_t st)
@@ -676,6 +721,8 @@ hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0,
     return hipGetLastError();
 }
 
+template int pass2_tiled_blocks_per_cu<double>(int);
+template int pass2_tiled_blocks_per_cu<float>(int);
 template hipError_t launch_pass2<double>(int, const PassArgs<double> &, const PassArgs<double> &,
                                          int, int, int, size_t, hipStream_t);
 template hipError_t launch_pass2<float>(int, const PassArgs<float> &, const PassArgs<float> &, int,

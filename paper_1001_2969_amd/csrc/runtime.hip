@@ -92,6 +92,7 @@ struct rzpic_ctx {
     size_t lds_block = 0, lds_cu = 0;
     int mixed = 0;
     int pass_threads = 512;
+    int tile_per_cu = 1;  // resident blocks per CU of the tiled merged pass
     double hr = 0, hz = 0;
     int L = 0;
     int nn = 0;
@@ -107,8 +108,6 @@ struct rzpic_ctx {
     unsigned long long *slices = nullptr;
     int slice_blocks = 0;
     bool lds_ok = false;
-    double *inv2j1;
-    float *inv2j1f;
     MgLevels mg{};
     // device scalars
     Counts *cnt;
@@ -174,8 +173,6 @@ Mesh mesh_of(const rzpic_ctx *c)
     m.hz = c->hz;
     m.inv_hr = 1.0 / c->hr;
     m.inv_hz = 1.0 / c->hz;
-    m.inv2j1 = c->inv2j1;
-    m.inv2j1f = c->inv2j1f;
     return m;
 }
 
@@ -285,14 +282,15 @@ template <typename T> PassArgs<T> pass_args(rzpic_ctx *c, int s, uint32_t step)
     return a;
 }
 
-// Blocks of the tiled pass of species s: two 2048-thread CU slots shared by
-// the two species, fewer for small capacities.  The window plan of the sort
-// is made for this count.
+// Blocks of the tiled pass of species s: the blocks the merged pass keeps
+// resident at once, shared by the two species (one round, no tail), fewer
+// for small capacities.  The window plan of the sort is made for this count.
 int tiled_blocks(const rzpic_ctx *c, int s)
 {
     const int threads = c->pass_threads;
     const int64_t need = (c->sp[s].cap + threads - 1) / threads;
-    const int bl = c->cus * (2048 / threads) / 2;
+    int bl = c->cus * c->tile_per_cu / 2;
+    if (bl < 1) bl = 1;
     return (int)(need < bl ? (need > 0 ? need : 1) : bl);
 }
 
@@ -656,9 +654,13 @@ rzpic_status sort_alloc(rzpic_ctx *c, int s)
     if (ss.sort_off) return RZPIC_OK;
     const size_t cap = (size_t)ss.cap + kChunk;
     const size_t es = c->mixed ? sizeof(float) : sizeof(double);
-    // segments of at least 4096 particles, at most 2^22 (tile, segment) counts
-    int64_t seg = 4096;
-    while (((int64_t)cap + seg - 1) / seg * c->nt > ((int64_t)1 << 22)) seg *= 2;
+    // Segments (one wavefront each walks its segment serially): at most 8192
+    // of them, which keeps every CU busy, and at most 2^22 (tile, segment)
+    // counts for the scan; at least 256 particles.
+    int64_t seg = 256;
+    while (((int64_t)cap + seg - 1) / seg > 8192 ||
+           ((int64_t)cap + seg - 1) / seg * c->nt > ((int64_t)1 << 22))
+        seg *= 2;
     ss.sort_seg = seg;
     ss.sort_nseg = ((int64_t)cap + seg - 1) / seg;
     const size_t M = (size_t)ss.sort_nseg * c->nt + 1;
@@ -896,7 +898,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         double2 *e2;
         A(e2, nn) c->E2 = e2;
     }
-    A(c->acc[0], nn) A(c->acc[1], nn) A(c->inv2j1, (size_t)k.nr) A(c->inv2j1f, (size_t)k.nr)
+    A(c->acc[0], nn) A(c->acc[1], nn)
     A(c->cnt, 2) A(c->fix, 2) A(c->crec, 1) A(c->clrec, 2) A(c->tally, 6)
     A(c->mcstat, 2 * (1 + kMaxProc)) A(c->norm, 2) A(c->status, 1) A(c->psteps, 2)
     // LDS privatisation of the whole deposit grid when it fits.
@@ -914,6 +916,9 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         }
         A(c->slices, (size_t)c->slice_blocks * nn)
         c->lds_ok = true;
+    } else {
+        c->tile_per_cu = c->mixed ? pass2_tiled_blocks_per_cu<float>(c->pass_threads)
+                                  : pass2_tiled_blocks_per_cu<double>(c->pass_threads);
     }
     // multigrid levels
     MgLevels &m = c->mg;
@@ -959,14 +964,9 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         A(m.cf64, 5 * nn)
     }
 #undef A
-    // host tables: 1/(2j+1), weighting volumes (Sec. 2.4, radial neighbours
-    // clamped to the axis and the wall, half axial cells on the electrodes)
-    std::vector<double> inv(k.nr), vol(nn);
-    std::vector<float> invf(k.nr);
-    for (int j = 0; j < k.nr; ++j) {
-        inv[j] = 1.0 / (double)(2 * j + 1);
-        invf[j] = (float)inv[j];
-    }
+    // weighting volumes (Sec. 2.4, radial neighbours clamped to the axis and
+    // the wall, half axial cells on the electrodes)
+    std::vector<double> vol(nn);
     const double PI = 3.141592653589793;
     for (int i = 0; i < k.nz; ++i) {
         double zf = (i == 0 || i == k.nz - 1) ? 0.5 * c->hz : c->hz;
@@ -978,9 +978,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
             vol[(size_t)i * k.nr + j] = rf * zf;
         }
     }
-    if (hipMemcpy(c->inv2j1, inv.data(), k.nr * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->inv2j1f, invf.data(), k.nr * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->vol, vol.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(c->vol, vol.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(RZPIC_EHIP, "table upload failed"));
     *out = c;
     return RZPIC_OK;
