@@ -30,18 +30,18 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE = {"mixed": 8 * 4 + 8 + 7 * 4, "fp64": 8 * 8 + 8 + 7 * 8}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused pass from the committed counter
+def measured_traffic(name):
+    """HBM bytes per particle of the fused pass from a committed counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
     the kernel sources have changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_pass2_hbm_traffic_rf129x65.md")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         text = open(path).read()
     except OSError:
         return None
-    t = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    t = re.search(r"^traffic_bytes_per_particle: ([0-9.]+)$", text, re.M)
     hs = re.search(r"^kernel_sources_sha256: ([0-9a-f]{64})$", text, re.M)
     if not t or not hs:
         return None
@@ -52,7 +52,7 @@ def measured_traffic():
     return float(t.group(1)) if h.hexdigest() == hs.group(1) else None
 
 
-def run_gpu(w, precision, steps, warmup, timing_steps=50):
+def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25):
     """Throughput over `steps` merged steps with nothing else on the stream,
     then `timing_steps` more with the library's HIP events around each phase
     (per-phase device times; every event costs the stream a few microseconds,
@@ -61,10 +61,14 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50):
 
     from paper_1001_2969_amd import rzpic
 
-    ctx = rzpic.make_context(w, precision=precision, capacity_factor=1.25)
+    ctx = rzpic.make_context(w, precision=precision, capacity_factor=capacity_factor)
     ctx.init_particles(0, w.n_per_species, w.n0, w.Te_eV, 0)
     ctx.init_particles(1, w.n_per_species, w.n0, w.Ti_eV, 0)
     ctx.prologue()
+    if w.sort_every:
+        # tile-sorted from the start (the steps then re-sort every sort_every)
+        for s in (0, 1):
+            ctx.sort(s)
     n = 0
     for _ in range(warmup):
         ctx.step(n)
@@ -165,7 +169,34 @@ def cpu_baseline(w, steps):
     return ps / dt, dt
 
 
-def pmc_run(steps):
+def large_mesh(steps, warmup):
+    """The 513x129 / 16M-per-species workload (R >> L, weight split every 100
+    steps, tile sort every 20), mixed and FP64: throughput and per-phase
+    device times, for context beside the headline workload.  Capacity 2x:
+    the split at step 99 clones every particle that drifted inward of the
+    radius its weight was set for (about half of them)."""
+    from paper_1001_2969_amd import workloads as wl
+
+    w = wl.large_513x129()
+    out = {"workload": w.name, "mesh": f"{w.nr}x{w.nz}", "particles_per_species": w.n_per_species,
+           "sort_every": w.sort_every, "resize_every": w.resize_every}
+    for prec in ("mixed", "fp64"):
+        ctx, r = run_gpu(w, prec, steps, warmup, timing_steps=min(steps, 40), capacity_factor=2.0)
+        ctx.close()
+        tm = r["timing"]
+        out[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                     "breakdown_ms_per_step": {k: tm[k] for k in
+                                               ("step_ms", "solve_ms", "pass_ms", "collide_ms",
+                                                "grid_ms", "lists_ms", "resize_ms", "sort_ms")},
+                     "pass_GBps": BYTES_PER_PARTICLE[prec] * (tm["n0"] + tm["n1"]) /
+                     (1e-3 * tm["pass_ms"]) / 1e9}
+    tpp = measured_traffic("k_pass2_hbm_traffic_513x129.md")
+    if tpp is not None:
+        out["mixed"]["pass_traffic_over_algorithmic"] = tpp / BYTES_PER_PARTICLE["mixed"]
+    return out
+
+
+def pmc_run(steps, workload):
     """Short run for hardware-counter passes: a few merged steps of the mixed
     workload, then a plain device copy of known size (the calibration of the
     byte counters: its algorithmic traffic is exactly the bytes read and
@@ -174,8 +205,8 @@ def pmc_run(steps):
 
     from paper_1001_2969_amd import workloads as wl
 
-    w = wl.rf_129x65()
-    ctx, res = run_gpu(w, "mixed", steps, 3, timing_steps=steps)
+    w = {"rf_129x65": wl.rf_129x65, "large_513x129": wl.large_513x129}[workload]()
+    ctx, res = run_gpu(w, "mixed", steps, 3, timing_steps=steps, capacity_factor=2.0)
     ctx.close()
     nbytes = 256 << 20
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -183,7 +214,7 @@ def pmc_run(steps):
     for _ in range(2):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_run": True, "steps": steps, "particles_per_pass":
+    print(json.dumps({"pmc_run": True, "workload": w.name, "steps": steps, "particles_per_pass":
                       [res["timing"]["n0"], res["timing"]["n1"]],
                       "bytes_per_particle": BYTES_PER_PARTICLE["mixed"],
                       "copy_bytes_each_way": nbytes}), flush=True)
@@ -198,8 +229,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-vcycle-study", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 513x129 / 16M-per-species context measurement")
+    ap.add_argument("--large-steps", type=int, default=60)
     ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
                     help="only a short mixed run plus a copy calibration (for counter passes)")
+    ap.add_argument("--pmc-workload", default="rf_129x65", choices=["rf_129x65", "large_513x129"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the "
@@ -213,7 +248,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.pmc_run:
-        pmc_run(args.pmc_run)
+        pmc_run(args.pmc_run, args.pmc_workload)
         return
     w = wl.rf_129x65()
     print(f"# workload {w.name}: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr,
@@ -237,6 +272,10 @@ def main():
         vstudy = vcycle_study(w, rho, chi, phi0)
         print(f"# V-cycle study: {json.dumps(vstudy)}", file=sys.stderr, flush=True)
     ctx_m.close()
+    large = None
+    if not args.no_large:
+        large = large_mesh(args.large_steps, 5)
+        print(f"# large mesh: {json.dumps(large)}", file=sys.stderr, flush=True)
 
     tm = mixed["timing"]
     # one launch of the fused pass moves both species
@@ -247,9 +286,14 @@ def main():
     roofline = {"kernel": "k_pass2<float, fused, LDS deposit>", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                "traffic": measured_traffic(),
+                "traffic": None,
                 "bytes_per_particle": bpp, "particles_per_launch": n_launch,
                 "avg_launch_ms": t_launch_ms}
+    tpp = measured_traffic("k_pass2_hbm_traffic_rf129x65.md")
+    if tpp is not None:
+        # counter bytes per particle (profile run) times this launch's particles
+        roofline["traffic"] = tpp * n_launch
+        roofline["traffic_over_algorithmic"] = tpp / bpp
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -279,6 +323,7 @@ def main():
             (1e-3 * fp64["timing"]["pass_ms"]) / 1e9},
         "mixed_over_fp64": None if fp64 is None else mixed["value"] / fp64["value"],
         "fixed_phi_err": vstudy,
+        "large_mesh": large,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
