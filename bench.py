@@ -151,6 +151,70 @@ def vcycle_study(w, rho, chi, phi0):
     return out
 
 
+# Algorithmic bytes per fine node of one V(0,1) cycle on the long-line path
+# (two half-sweeps per level): the down leg reads phi, f, eps (FP64) and
+# writes the restricted right-hand sides of the coarser levels; each level's
+# up leg reads eps, f, the neighbour lines and the coarse correction and
+# writes its unknowns (coarser levels add half, a quarter, ... of the
+# finest); the mixed form adds phi += correction.
+VCYCLE_BYTES_PER_NODE = {"fp64": 32 + 2 * 44, "mixed": 32 + 2 * 22 + 20}
+
+
+def vcycle_time(w, precision):
+    """Device time of one V(0,1) cycle on w's mesh: (T(6) - T(1)) / 5 for
+    fixed-cycle solves of a smooth rho, chi ~ 1 (best of 3), and the path."""
+    import numpy as np
+    import torch
+
+    from paper_1001_2969_amd import rzpic, workloads as wl
+
+    ctx = rzpic.Context(w, precision=precision, mg_fixed_cycles=1)
+    rho, chi = wl.smooth_rho(w, 5, 2e-4), wl.smooth_chi(w, 1.0)
+    ctx.set_grid(rzpic.G_RHO, rho)
+    ctx.set_grid(rzpic.G_CHI, chi)
+    ctx.set_grid(rzpic.G_PHI, np.zeros((w.nz, w.nr)))
+    del rho, chi
+    times = {}
+    for k in (1, 6):
+        ctx.set_mg(fixed_cycles=k)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = math.inf
+        for _ in range(3):
+            ctx.stream.synchronize()
+            ev0.record(ctx.stream)
+            ctx.solve(1e-9, want=False)
+            ev1.record(ctx.stream)
+            ev1.synchronize()
+            best = min(best, ev0.elapsed_time(ev1))
+        times[k] = best
+    ctx.close()
+    return (times[6] - times[1]) / 5.0
+
+
+def vcycle_by_mesh():
+    """V-cycle device time on every workload mesh, and on a synthetic
+    8193 x 2049 grid (square cells, 16.8M nodes: a working set far above the
+    256 MB last-level cache) where the smoother's bandwidth means something."""
+    from paper_1001_2969_amd import workloads as wl
+
+    meshes = [wl.small_fp64(), wl.rf_129x65(), wl.large_513x129(),
+              wl.Workload(name="synthetic_8193x2049_vcycle", nr=8193, nz=2049, R=0.16, L=0.04,
+                          n_per_species=1, steps=1, V_dc=35.0)]
+    out = {}
+    for w in meshes:
+        row = {}
+        for prec in ("mixed", "fp64"):
+            ms = vcycle_time(w, prec)
+            row[prec] = {"vcycle_ms": ms}
+            if w.nr * w.nz > 1 << 24:
+                b = VCYCLE_BYTES_PER_NODE[prec] * w.nr * w.nz
+                row[prec]["algorithmic_GBps"] = b / (ms * 1e-3) / 1e9
+                row[prec]["bytes_per_node"] = VCYCLE_BYTES_PER_NODE[prec]
+        out[f"{w.nr}x{w.nz}"] = row
+        print(f"# V-cycle {w.nr}x{w.nz}: {json.dumps(row)}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(w, steps):
     """The FP64 CPU oracle (single thread, as it stands) on the first `steps`
     steps of the same workload: particle-steps/s."""
@@ -232,6 +296,8 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 513x129 / 16M-per-species context measurement")
     ap.add_argument("--large-steps", type=int, default=60)
+    ap.add_argument("--no-vcycle-meshes", action="store_true",
+                    help="skip the V-cycle timing on every mesh and the synthetic grid")
     ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
                     help="only a short mixed run plus a copy calibration (for counter passes)")
     ap.add_argument("--pmc-workload", default="rf_129x65", choices=["rf_129x65", "large_513x129"])
@@ -272,6 +338,7 @@ def main():
         vstudy = vcycle_study(w, rho, chi, phi0)
         print(f"# V-cycle study: {json.dumps(vstudy)}", file=sys.stderr, flush=True)
     ctx_m.close()
+    vmesh = None if args.no_vcycle_meshes else vcycle_by_mesh()
     large = None
     if not args.no_large:
         large = large_mesh(args.large_steps, 5)
@@ -324,6 +391,7 @@ def main():
         "mixed_over_fp64": None if fp64 is None else mixed["value"] / fp64["value"],
         "fixed_phi_err": vstudy,
         "large_mesh": large,
+        "vcycle_by_mesh": vmesh,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

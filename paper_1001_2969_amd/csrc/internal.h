@@ -19,7 +19,8 @@ constexpr int kMaxProc = 4;
 constexpr int kMaxLevels = 16;
 constexpr int kChunk = 64;       // particles per chunk: one wavefront
 constexpr int kMaxWaves = 16384; // wavefronts of a particle pass (bounds the bucket padding)
-constexpr int kMaxLine = 2048;   // longest r-line (nr - 1 unknowns) the smoother takes
+constexpr int kLongThreads = 1024;            // threads of a long-line solve
+constexpr int kMaxLine = 8 * kLongThreads;    // longest r-line (nr - 1 unknowns) the smoother takes
 constexpr int kMaxTiles = 2048;  // tiles of the particle sort
 constexpr int kWinNodes = 4096;  // LDS deposit window of a tiled pass block (nodes)
 constexpr int kWinHalo = 8;      // cells of drift margin around a block's tiles
@@ -309,6 +310,8 @@ struct MgLevels {
     double *res;           // finest-level residual scratch
     double *cf64;          // FP64 operator of the finest level: a, b, c, d, e arrays [nz][nr]
     size_t solve_lds;      // LDS bytes of the single-block kernel
+    size_t lds_budget;     // LDS bytes of one workgroup
+    int long_lines;        // r-lines solved by the partition method, two half-sweeps per level
 };
 hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st);
 // The merged step's grid preparation in one launch: finalize every node,
@@ -325,7 +328,7 @@ hipError_t mg_set_bc(double *phi, int nr, int nz, double V, hipStream_t st);
 // tab_stride elements and res), and the levels of the bottom kernel of the
 // multi-launch path (K, bottom_lds).
 // path: 0 split where it fits (single block for one-line meshes), 1 single
-// block where it fits, 2 multi-launch.
+// block where it fits, 2 multi-launch, 3 long-line half-sweeps.
 void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path);
 // Single-block path: factor every line matrix of every level (once per solve,
 // after mg_restrict_eps), then run `cycles` V(0,1) cycles on phi in one

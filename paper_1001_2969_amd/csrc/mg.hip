@@ -282,6 +282,107 @@ template <typename T> __global__ __launch_bounds__(1024) void k_line(LineArgs<T>
     for (int j = threadIdx.x; j < n; j += blockDim.x) p.u[(size_t)i * nr + j] = Rr[j] / Bd[j];
 }
 
+// The same half-sweep for lines too long for k_line's LDS (8 (nr-1) values):
+// the partition method.  Thread t owns Q consecutive unknowns (a segment,
+// padded past nr-2 with decoupled identity rows) and eliminates inside it in
+// registers: a forward sweep leaves every row coupled only to the last
+// unknown of the previous segment, y_{t-1}, and to its successor; a backward
+// sweep expresses the segment's first unknown through y_{t-1} and its own last
+// unknown y_t.  The T last unknowns then satisfy a tridiagonal system, solved
+// by cyclic reduction in LDS, and each thread substitutes back.  The line
+// matrices are strictly diagonally dominant, so no pivoting is needed.
+template <typename T, int EPT>
+__device__ __forceinline__ void pcr(T *A, T *Bd, T *C, T *Rr, int n, int ne);
+
+template <typename T, int Q>
+__global__ __launch_bounds__(kLongThreads) void k_line_part(LineArgs<T> p)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = (T *)smem_raw;
+    const int NT = blockDim.x;
+    T *RA = sm, *RB = sm + NT, *RC = sm + 2 * NT, *RR = sm + 3 * NT;
+    T *X0 = sm + 4 * NT, *X1 = sm + 5 * NT, *X2 = sm + 6 * NT;
+    const int nr = p.nr, n = nr - 1, nzl = p.nzl;
+    const int i = p.parity ? 2 * blockIdx.x + 1 : 2 * blockIdx.x + 2;
+    const int t = threadIdx.x, j0 = t * Q;
+    auto nb = [&](int row, int j) -> T {
+        bool bnd = row == 0 || row == nzl - 1;
+        T v = p.zero_old ? (T)0 : p.u[(size_t)row * nr + j];
+        if (!bnd && p.uc) v += p.uc[(size_t)(row >> 1) * nr + j];
+        return v;
+    };
+    // rows of the segment: a x_{j-1} + b x_j + c x_{j+1} = r
+    T ap[Q], bp[Q], c[Q], rp[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = j0 + q;
+        T a = (T)0, b = (T)1, cc = (T)0, r = (T)0;
+        if (j < n) {
+            Coef<T> k = coef<T>(p.eps, nr, i, j, p.inv_hz2, p.inv_hr2, p.rule);
+            T g = p.f[(size_t)i * nr + j] + k.a * nb(i - 1, j) + k.c * nb(i + 1, j);
+            T e = k.e;
+            if (j == n - 1) {
+                g += e * (p.zero_old ? (T)0 : p.u[(size_t)i * nr + nr - 1]);
+                e = (T)0;
+            }
+            a = j == 0 ? (T)0 : -k.d;
+            b = k.b;
+            cc = -e;
+            r = g;
+        }
+        // forward elimination inside the segment; ap couples to y_{t-1}
+        if (q == 0) {
+            ap[0] = a;
+            bp[0] = b;
+            rp[0] = r;
+        } else {
+            const T mq = a / bp[q - 1];
+            ap[q] = -mq * ap[q - 1];
+            bp[q] = b - mq * c[q - 1];
+            rp[q] = r - mq * rp[q - 1];
+        }
+        c[q] = cc;
+    }
+    // first unknown of the segment = al y_{t-1} + be y_t + ga
+    T al = (T)0, be = (T)1, ga = (T)0;
+#pragma unroll
+    for (int q = Q - 2; q >= 0; --q) {
+        const T ib = (T)1 / bp[q];
+        const T nal = -(ap[q] + c[q] * al) * ib;
+        const T nbe = -c[q] * be * ib;
+        const T nga = (rp[q] - c[q] * ga) * ib;
+        al = nal;
+        be = nbe;
+        ga = nga;
+    }
+    X0[t] = al;
+    X1[t] = be;
+    X2[t] = ga;
+    __syncthreads();
+    // reduced row of y_t: the segment's last row with its successor (the next
+    // segment's first unknown) expressed through y_t and y_{t+1}
+    {
+        const T cl = c[Q - 1];
+        const T nal = t + 1 < NT ? X0[t + 1] : (T)0, nbe = t + 1 < NT ? X1[t + 1] : (T)0;
+        const T nga = t + 1 < NT ? X2[t + 1] : (T)0;
+        RA[t] = ap[Q - 1];
+        RB[t] = bp[Q - 1] + cl * nal;
+        RC[t] = cl * nbe;
+        RR[t] = rp[Q - 1] - cl * nga;
+    }
+    __syncthreads();
+    pcr<T, 1>(RA, RB, RC, RR, NT, NT);
+    const T yt = RR[t] / RB[t];
+    const T yp = t > 0 ? RR[t - 1] / RB[t - 1] : (T)0;
+    T x = yt;
+    if (j0 + Q - 1 < n) p.u[(size_t)i * nr + j0 + Q - 1] = x;
+#pragma unroll
+    for (int q = Q - 2; q >= 0; --q) {
+        x = (rp[q] - ap[q] * yp - c[q] * x) / bp[q];
+        if (j0 + q < n) p.u[(size_t)i * nr + j0 + q] = x;
+    }
+}
+
 template <typename T>
 static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u, const T *f,
                        const T *eps, const T *uc, hipStream_t st)
@@ -302,10 +403,24 @@ static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u,
     const int rows = parity ? (p.nzl - 1) / 2 : (p.nzl - 3) / 2;
     if (rows <= 0) return hipSuccess;
     const int n = m.nr - 1;
-    int threads = ((n + 63) / 64) * 64;
-    if (threads > 1024) threads = 1024;
     size_t lds = 8 * (size_t)n * sizeof(T);
-    hipLaunchKernelGGL((k_line<T>), dim3(rows), dim3(threads), lds, st, p);
+    if (lds <= m.lds_budget && n <= 1024 * 4) {
+        int threads = ((n + 63) / 64) * 64;
+        if (threads > 1024) threads = 1024;
+        hipLaunchKernelGGL((k_line<T>), dim3(rows), dim3(threads), lds, st, p);
+        return hipGetLastError();
+    }
+    // long lines: segments of Q unknowns per thread
+    const int q = (n + kLongThreads - 1) / kLongThreads;
+    lds = 7 * (size_t)kLongThreads * sizeof(T);
+    if (q <= 2)
+        hipLaunchKernelGGL((k_line_part<T, 2>), dim3(rows), dim3(kLongThreads), lds, st, p);
+    else if (q <= 4)
+        hipLaunchKernelGGL((k_line_part<T, 4>), dim3(rows), dim3(kLongThreads), lds, st, p);
+    else if (q <= 8)
+        hipLaunchKernelGGL((k_line_part<T, 8>), dim3(rows), dim3(kLongThreads), lds, st, p);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -397,6 +512,91 @@ template <typename T>
 __global__ void k_down(const double *u, const double *f, MgLevels m, int mixed, int cpb)
 {
     down_body<T>(u, f, m, mixed, cpb, blockIdx.x);
+}
+
+// The same down leg row by row, for large meshes (coalesced along r; the
+// column form above reads a z-column per block): the finest residual into
+// m.res (and f32 of the finest level in the mixed form), then one launch per
+// coarser level, f^{l-1} = FW_z(f^l), with the arithmetic of down_body.
+__global__ void k_resid_rows(const double *u, const double *f, MgLevels m, int mixed)
+{
+    const int L = m.L, nr = m.nr, nz = m.nzl[L];
+    const double *ep = m.eps64[L];
+    const double hz = m.hzl[L];
+    const double iz2 = 1.0 / (hz * hz), ir2 = 1.0 / (m.hr * m.hr);
+    const int64_t nn = (int64_t)nr * nz;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nn;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g / nr), j = (int)(g - (int64_t)i * nr);
+        if (i == 0 || i == nz - 1 || j == nr - 1) continue;
+        auto E = [&](int di, int dj) { return ep[g + (int64_t)di * nr + dj]; };
+        auto U = [&](int di, int dj) { return u[g + (int64_t)di * nr + dj]; };
+        double a = face<double>(E(-1, 0), E(0, 0), m.chi_face) * iz2;
+        double c = face<double>(E(0, 0), E(1, 0), m.chi_face) * iz2;
+        double d, e;
+        if (j == 0) {
+            d = 0.0;
+            e = 4.0 * face<double>(E(0, 0), E(0, 1), m.chi_face) * ir2;
+        } else {
+            double jj = (double)j;
+            d = face<double>(E(0, -1), E(0, 0), m.chi_face) * ((jj - 0.5) / jj) * ir2;
+            e = face<double>(E(0, 0), E(0, 1), m.chi_face) * ((jj + 0.5) / jj) * ir2;
+        }
+        double b = a + c + d + e;
+        double Au = b * U(0, 0) - a * U(-1, 0) - c * U(1, 0) - e * U(0, 1);
+        if (j > 0) Au -= d * U(0, -1);
+        const double r = f[g] - Au;
+        m.res[g] = r;
+        if (mixed) m.f32[L][g] = (float)r;
+    }
+}
+
+// f^{l-1} from the level above (src: the finest residual, or f^l as stored).
+template <typename S, typename T>
+__global__ void k_restrict_rows(const S *src, T *dst, int nr, int nzc, int mixed)
+{
+    const int64_t ncell = (int64_t)(nzc - 2) * (nr - 1);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int I = 1 + (int)(t / (nr - 1)), j = (int)(t % (nr - 1));
+        const int64_t r0 = (int64_t)(2 * I - 1) * nr + j;
+        double v = 0.25 * (double)src[r0] + 0.5 * (double)src[r0 + nr] +
+                   0.25 * (double)src[r0 + 2 * nr];
+        if (mixed) v = (double)(float)v;  // coarse right-hand sides in FP32
+        dst[(int64_t)I * nr + j] = (T)v;
+    }
+}
+
+static int grid_blocks(int64_t n, int threads)
+{
+    const int64_t b = (n + threads - 1) / threads;
+    return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+static hipError_t down_rows(const MgLevels &m, int mixed, const double *phi, const double *f,
+                            hipStream_t st)
+{
+    const int L = m.L, nr = m.nr;
+    const int threads = 256;
+    hipLaunchKernelGGL(k_resid_rows, dim3(grid_blocks((int64_t)nr * m.nzl[L], threads)),
+                       dim3(threads), 0, st, phi, f, m, mixed);
+    for (int l = L - 1; l >= 1; --l) {
+        const int nzc = m.nzl[l];
+        const int blocks = grid_blocks((int64_t)(nzc - 2) * (nr - 1), threads);
+        if (mixed) {
+            if (l == L - 1)
+                hipLaunchKernelGGL((k_restrict_rows<double, float>), dim3(blocks), dim3(threads), 0,
+                                   st, (const double *)m.res, m.f32[l], nr, nzc, mixed);
+            else
+                hipLaunchKernelGGL((k_restrict_rows<float, float>), dim3(blocks), dim3(threads), 0,
+                                   st, (const float *)m.f32[l + 1], m.f32[l], nr, nzc, mixed);
+        } else {
+            const double *src = l == L - 1 ? (const double *)m.res : (const double *)m.f64[l + 1];
+            hipLaunchKernelGGL((k_restrict_rows<double, double>), dim3(blocks), dim3(threads), 0, st,
+                               src, m.f64[l], nr, nzc, mixed);
+        }
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -624,7 +824,7 @@ static hipError_t level_sweep(const MgLevels &m, int l, int zero_old, const T *u
     const int n = m.nr - 1;
     int threads = ((2 * n + 63) / 64) * 64;
     if (threads > 1024) threads = 1024;
-    const int ept = (2 * n + threads - 1) / threads;  // n <= kMaxLine: at most 4
+    const int ept = (2 * n + threads - 1) / threads;  // 2 n <= 4096 here: at most 4
     size_t lds = 12 * (size_t)n * sizeof(T);
     if (ept <= 1)
         hipLaunchKernelGGL((k_level<T, 1>), dim3(blocks), dim3(threads), lds, st, p);
@@ -1190,6 +1390,10 @@ void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path)
 {
     const size_t es = mixed ? sizeof(float) : sizeof(double);
     const int n = m.nr - 1;
+    m.lds_budget = lds_budget;
+    // the level kernel holds three lines of four arrays (12 n values) in LDS
+    // and reduces 2 n values with at most four per thread
+    m.long_lines = path == 3 || 12 * (size_t)n * es > lds_budget || 2 * n > 4 * 1024;
     // single-block path
     int S = 0;
     while ((1 << S) < n) ++S;
@@ -1204,7 +1408,7 @@ void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path)
     size_t lds = 0;
     for (int l = 1; l <= (mixed ? m.L : m.L - 1); ++l) lds += 2 * (size_t)m.nzl[l] * m.nr * es;
     m.solve_lds = lds;
-    const bool fits = n <= (mixed ? 256 : 128) && lds <= lds_budget;
+    const bool fits = n <= (mixed ? 256 : 128) && lds <= lds_budget && !m.long_lines;
     m.split = fits && path == 0 && m.L > 1;
     m.one_block = fits && (path == 1 || (path == 0 && m.L == 1));
     // multi-launch path: levels of the bottom kernel
@@ -1242,6 +1446,7 @@ static hipError_t bottom(const MgLevels &m, int mixed, hipStream_t st)
 static hipError_t down(const MgLevels &m, int mixed, const double *phi, const double *f,
                        hipStream_t st)
 {
+    if (m.long_lines) return down_rows(m, mixed, phi, f, st);
     const int nr = m.nr, nz = m.nzl[m.L];
     const int cpb = cols_per_block(nz);
     if (mixed)
@@ -1284,6 +1489,35 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
         phi = phi_alt;
         phi_alt = t;
         return e;
+    }
+    if (m.long_lines) {
+        // r-lines longer than the level kernel's LDS: every level as two
+        // half-sweeps of line solves (odd lines with the injected coarse
+        // correction, then even lines), in place
+        for (int l = 1; l <= L; ++l) {
+            const bool fine = l == L;
+            if (mixed) {
+                float *u = m.u32[l];
+                const float *uc = l > 1 ? m.u32[l - 1] : nullptr;
+                if ((e = line<float>(m, l, 1, 1, u, m.f32[l], m.eps32[l], uc, st))) return e;
+                if ((e = line<float>(m, l, 0, 0, u, m.f32[l], m.eps32[l], nullptr, st))) return e;
+                if (fine) {
+                    const int nn = nr * nz, threads = 256;
+                    const int blocks = (nn + threads - 1) / threads < 65536 ? (nn + threads - 1) / threads
+                                                                          : 65536;
+                    hipLaunchKernelGGL(k_add_corr, dim3(blocks), dim3(threads), 0, st, phi,
+                                       (const float *)u, nr, nz);
+                    if ((e = hipGetLastError())) return e;
+                }
+            } else {
+                double *u = fine ? phi : m.u64[l];
+                const double *fl = fine ? f : m.f64[l];
+                const double *uc = l > 1 ? m.u64[l - 1] : nullptr;
+                if ((e = line<double>(m, l, 1, fine ? 0 : 1, u, fl, m.eps64[l], uc, st))) return e;
+                if ((e = line<double>(m, l, 0, 0, u, fl, m.eps64[l], nullptr, st))) return e;
+            }
+        }
+        return hipSuccess;
     }
     int done = m.K;
     if (m.K >= 1) {

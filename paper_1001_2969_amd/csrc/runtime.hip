@@ -883,6 +883,11 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     c->lds_block = (size_t)v;
     (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device);
     c->lds_cu = v > 0 ? (size_t)v : c->lds_block;
+    // the multigrid's down leg holds a whole z-column (8 values per node) in LDS
+    if ((size_t)64 * k.nz > c->lds_block)
+        return bail(fail(RZPIC_EINVAL, "nz = %d: a z-column of the multigrid does not fit in "
+                                       "one workgroup's LDS (%zu bytes)",
+                         k.nz, c->lds_block));
     if (const char *e = std::getenv("RZPIC_PASS_THREADS")) {
         int t = std::atoi(e);
         if (t == 256 || t == 512 || t == 1024) c->pass_threads = t;
@@ -943,11 +948,12 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     }
     {
         // cycle path: the split form unless RZPIC_MG_PATH names another
-        // ("block" or "multi"; for tests and measurements)
+        // ("block", "multi" or "long"; for tests and measurements)
         int path = 0;
         if (const char *e = std::getenv("RZPIC_MG_PATH")) {
             if (!std::strcmp(e, "block")) path = 1;
             else if (!std::strcmp(e, "multi")) path = 2;
+            else if (!std::strcmp(e, "long")) path = 3;
         }
         mg_plan(m, c->mixed, c->lds_block, path);
     }
@@ -962,6 +968,8 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         }
         A(m.res, nn)
         A(m.cf64, 5 * nn)
+    } else if (m.long_lines) {
+        A(m.res, nn)  // finest residual of the row-wise down leg
     }
 #undef A
     // weighting volumes (Sec. 2.4, radial neighbours clamped to the axis and

@@ -102,7 +102,7 @@ def run_mixed(w, nsteps, *, state=None, own_init=False, capacity_factor=2.0, che
     return o, g, report
 
 
-@pytest.mark.parametrize("path", ["block", "split", "multi"])
+@pytest.mark.parametrize("path", ["block", "split", "multi", "long"])
 @pytest.mark.parametrize("mesh", [(33, 33), (129, 65), (65, 3)])
 def test_mixed_solve(mesh, path, monkeypatch):
     monkeypatch.setenv("RZPIC_MG_PATH", path)

@@ -101,14 +101,14 @@ def test_deposit_and_finalize(weighting):
         np.testing.assert_allclose(g.grid(G).sum(), g.particles(s)["w"].sum(), rtol=1e-11)
 
 
-@pytest.mark.parametrize("path", ["block", "split", "multi"])
+@pytest.mark.parametrize("path", ["block", "split", "multi", "long"])
 @pytest.mark.parametrize("mesh", [(33, 33), (129, 65), (65, 3), (40, 17)])
 @pytest.mark.parametrize("face", [wl.FACE_AVG, wl.FACE_MAX])
 def test_solve_cycles_and_convergence(mesh, face, path, monkeypatch):
-    """The three cycle paths of the library: one launch for all cycles
-    (levels in LDS, pre-factored lines); per cycle a residual launch, the
-    coarse levels in one workgroup and the finest sweep; one launch per level
-    (any mesh size)."""
+    """The cycle paths of the library: one launch for all cycles (levels in
+    LDS, pre-factored lines); per cycle a residual launch, the coarse levels
+    in one workgroup and the finest sweep; one launch per level; two
+    half-sweeps per level with partition-method line solves (long lines)."""
     monkeypatch.setenv("RZPIC_MG_PATH", path)
     nr, nz = mesh
     w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
@@ -135,6 +135,29 @@ def test_solve_cycles_and_convergence(mesh, face, path, monkeypatch):
     assert st == 0 and orr <= 1e-11 and grr <= 1e-11
     assert abs(gc - oc) <= 1
     compare_grid(g.grid(rzpic.G_PHI), o.grid(rzo.G_PHI), 1e-10, "phi converged")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("mesh", [(4097, 9), (8193, 5), (2049, 17)])
+def test_solve_long_lines(mesh, precision):
+    """Meshes whose r-lines exceed the level kernel's LDS (4096 and 8192
+    unknowns, or 2048 in FP64): the partition-method half-sweeps, selected by
+    the library itself, against the oracle's Thomas solves."""
+    nr, nz = mesh
+    w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
+                    n_per_species=1, steps=1, V_dc=35.0)
+    chi = wl.smooth_chi(w, 1.0)
+    rho = wl.smooth_rho(w, 5, 2e-4)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for k in (1, 3):
+        o, g = pair(w, precision=precision, mc=False, mg_fixed_cycles=k)
+        for ctx, G in ((o, rzo), (g, rzpic)):
+            ctx.set_grid(G.G_CHI, chi)
+            ctx.set_grid(G.G_RHO, rho)
+            ctx.set_grid(G.G_PHI, _random_phi(w, 9, 10.0))
+        o.solve(1e-9)
+        g.solve(1e-9)
+        compare_grid(g.grid(rzpic.G_PHI), o.grid(rzo.G_PHI), tol, f"phi after {k} cycles")
 
 
 @pytest.mark.parametrize("eps_eV", [4.0, 40.0])
