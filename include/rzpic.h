@@ -233,6 +233,31 @@ void rzpic_constants(double out[6]);
 rzpic_status rzpic_set_timing(rzpic_ctx *ctx, int32_t enable);
 rzpic_status rzpic_get_timing(rzpic_ctx *ctx, double out[12]);
 
+/* --- batched steps of independent discharges ---------------------------- */
+/* Many independent discharges (contexts of any mesh, particle count and
+ * precision) stepped together.  Each rzpic_batch_step performs rzpic_step on
+ * every context, equal to it bit for bit, but groups the discharges whose
+ * launch sequences are identical (same mesh, precision and options) and runs
+ * each group position by position: kernels written for it cover the whole
+ * group in one launch (a device job table gives each discharge its arguments
+ * and blocks), the others are launched per discharge; the groups run on up to
+ * four streams of their own.  Requirements, checked at create and at every
+ * step (EINVAL): both species bound, mg_fixed_cycles > 0 (no solve
+ * synchronises), step timing off, no staged new particles.  A step that fails
+ * while recording leaves the contexts recorded before it advanced on the
+ * host: destroy them.  The batch orders itself after the contexts' streams
+ * and the streams after the batch; the contexts must not be stepped
+ * elsewhere meanwhile.  ctxs is a host array of n handles (copied).  The
+ * batch allocates a device job table and two pinned staging buffers, grown
+ * as needed. */
+typedef struct rzpic_batch rzpic_batch;
+rzpic_status rzpic_batch_create(rzpic_ctx *const *ctxs, int32_t n, void *stream,
+                                rzpic_batch **out);
+rzpic_status rzpic_batch_step(rzpic_batch *batch, int64_t step);
+/* out[0] groups, out[1] launches and out[2] of them batched, last step. */
+rzpic_status rzpic_batch_stats(rzpic_batch *batch, int32_t out[3]);
+rzpic_status rzpic_batch_destroy(rzpic_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,315 @@
+// Batched steps of independent discharges.
+//
+// A batched step records the launches of every discharge's merged step
+// (rzpic_step in record mode: the host-side bookkeeping runs, no kernel is
+// launched), groups the discharges whose launch sequences are identical
+// (same kernels and block shapes: the same mesh, precision and options), and
+// replays each group position by position on a stream of its own.  At a
+// position whose kernel is written as a body over a virtual block index, one
+// launch covers the whole group: a job table gives each discharge its
+// arguments and its range of blocks.  Other kernels are launched once per
+// discharge.  Every block runs exactly what it runs in the discharge's own
+// step, so a batched step equals the separate steps bit for bit.
+#include <algorithm>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rzpic.h"
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace rz {
+thread_local Recorder *g_recorder = nullptr;
+}
+
+using namespace rz;
+
+// Defined in runtime.hip (C ABI helpers shared with the batch).
+extern "C" rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
+rzpic_status rz_fail(rzpic_status s, const char *msg);
+hipStream_t rz_stream(const rzpic_ctx *c);
+int rz_batchable(const rzpic_ctx *c, std::string &why);
+
+namespace {
+
+constexpr int kStreams = 4;  // the device's hardware queues
+
+struct Staging {
+    void *host = nullptr;  // pinned
+    size_t cap = 0;
+    hipEvent_t done = nullptr;  // the upload that last read it
+    bool used = false;
+};
+
+}  // namespace
+
+struct rzpic_batch {
+    std::vector<rzpic_ctx *> ctx;
+    hipStream_t st = nullptr;
+    hipStream_t streams[kStreams] = {};
+    hipEvent_t fork = nullptr, join[kStreams] = {}, ctx_ev = nullptr;
+    Staging stage[2];
+    int which = 0;
+    void *dev = nullptr;
+    size_t dev_cap = 0;
+    std::vector<Recorder> rec;
+    int32_t classes = 0, launches = 0, batched = 0;
+};
+
+namespace {
+
+rzpic_status hipfail(hipError_t e, const char *what)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    return rz_fail(RZPIC_EHIP, buf);
+}
+
+#define BCHK(expr, what)                         \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hipfail(e_, what); \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+extern "C" {
+
+rzpic_status rzpic_batch_create(rzpic_ctx *const *ctxs, int32_t n, void *stream, rzpic_batch **out)
+{
+    if (!ctxs || !out || n < 1) return rz_fail(RZPIC_EINVAL, "batch: need contexts and n >= 1");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return rz_fail(RZPIC_EINVAL, "batch: null context");
+        std::string why;
+        if (!rz_batchable(ctxs[i], why)) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf, "batch: context %d: %s", i, why.c_str());
+            return rz_fail(RZPIC_EINVAL, buf);
+        }
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return rz_fail(RZPIC_EINVAL, "batch: a context appears twice");
+    }
+    rzpic_batch *b = new rzpic_batch();
+    b->ctx.assign(ctxs, ctxs + n);
+    b->st = (hipStream_t)stream;
+    b->rec.resize(n);
+    auto bail = [&](rzpic_status s) {
+        rzpic_batch_destroy(b);
+        return s;
+    };
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kStreams && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ctx_ev, hipEventDisableTiming);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&b->stage[k].done, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(hipfail(e, "batch: stream/event creation"));
+    *out = b;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_batch_destroy(rzpic_batch *b)
+{
+    if (!b) return RZPIC_OK;
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    for (int k = 0; k < kStreams; ++k) {
+        if (b->streams[k]) {
+            (void)hipStreamSynchronize(b->streams[k]);
+            (void)hipStreamDestroy(b->streams[k]);
+        }
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->ctx_ev) (void)hipEventDestroy(b->ctx_ev);
+    for (auto &s : b->stage) {
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.host) (void)hipHostFree(s.host);
+    }
+    if (b->dev) (void)hipFree(b->dev);
+    delete b;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_batch_step(rzpic_batch *b, int64_t step)
+{
+    if (!b) return rz_fail(RZPIC_EINVAL, "null batch");
+    const int n = (int)b->ctx.size();
+    for (int i = 0; i < n; ++i) {
+        std::string why;
+        if (!rz_batchable(b->ctx[i], why)) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf, "batch: context %d: %s", i, why.c_str());
+            return rz_fail(RZPIC_EINVAL, buf);
+        }
+    }
+    // record every discharge's step (host bookkeeping only)
+    for (int i = 0; i < n; ++i) {
+        b->rec[i].recs.clear();
+        g_recorder = &b->rec[i];
+        const rzpic_status s = rzpic_step(b->ctx[i], step);
+        g_recorder = nullptr;
+        if (s != RZPIC_OK) return s;
+    }
+    // groups of identical launch sequences, in order of first appearance
+    std::vector<std::vector<int>> groups;
+    {
+        std::map<std::vector<std::pair<const void *, unsigned>>, int> sig_group;
+        for (int i = 0; i < n; ++i) {
+            std::vector<std::pair<const void *, unsigned>> sig;
+            sig.reserve(b->rec[i].recs.size());
+            for (const LaunchRec &L : b->rec[i].recs) sig.emplace_back(L.key, L.threads);
+            auto it = sig_group.find(sig);
+            if (it == sig_group.end()) {
+                sig_group.emplace(std::move(sig), (int)groups.size());
+                groups.push_back({i});
+            } else {
+                groups[it->second].push_back(i);
+            }
+        }
+    }
+    // job tables of the batched positions: layout, then contents
+    struct Table {
+        size_t off;
+        int blocks;
+    };
+    std::vector<std::vector<Table>> tables(groups.size());
+    size_t total = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const int i0 = groups[g][0];
+        const size_t npos = b->rec[i0].recs.size();
+        tables[g].assign(npos, Table{0, 0});
+        for (size_t p = 0; p < npos; ++p) {
+            const LaunchRec &L = b->rec[i0].recs[p];
+            if (!L.many) continue;
+            total = align_up(total, 256);
+            tables[g][p].off = total;
+            total += L.job_size * groups[g].size();
+        }
+    }
+    Staging &S = b->stage[b->which];
+    if (total > 0) {
+        if (S.used) BCHK(hipEventSynchronize(S.done), "batch: staging reuse");
+        if (total > S.cap) {
+            if (S.host) BCHK(hipHostFree(S.host), "batch: staging free");
+            S.host = nullptr;
+            S.cap = 0;
+            BCHK(hipHostMalloc(&S.host, total * 2), "batch: staging allocation");
+            S.cap = total * 2;
+        }
+        if (total > b->dev_cap) {
+            // earlier steps may still read the old table
+            BCHK(hipStreamSynchronize(b->st), "batch: table reallocation");
+            if (b->dev) BCHK(hipFree(b->dev), "batch: table free");
+            b->dev = nullptr;
+            b->dev_cap = 0;
+            BCHK(hipMalloc(&b->dev, total * 2), "batch: table allocation");
+            b->dev_cap = total * 2;
+        }
+        unsigned char *h = (unsigned char *)S.host;
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const int i0 = groups[g][0];
+            for (size_t p = 0; p < tables[g].size(); ++p) {
+                const LaunchRec &L0 = b->rec[i0].recs[p];
+                if (!L0.many) continue;
+                int first = 0;
+                for (size_t k = 0; k < groups[g].size(); ++k) {
+                    const LaunchRec &L = b->rec[groups[g][k]].recs[p];
+                    unsigned char *job = h + tables[g][p].off + k * L0.job_size;
+                    std::memset(job, 0, L0.job_size);
+                    std::memcpy(job, L.args.data(), L.args.size());
+                    const int nx = (int)L.gx, ny = (int)L.gy;
+                    int *f = (int *)(job + L0.first_off);
+                    f[0] = first;
+                    f[1] = nx;
+                    f[2] = ny;
+                    first += nx * ny;
+                }
+                tables[g][p].blocks = first;
+            }
+        }
+    }
+    // order after the contexts' own streams, upload, fork
+    {
+        std::vector<hipStream_t> seen;
+        for (rzpic_ctx *c : b->ctx) {
+            hipStream_t cs = rz_stream(c);
+            if (cs == b->st || std::find(seen.begin(), seen.end(), cs) != seen.end()) continue;
+            seen.push_back(cs);
+            BCHK(hipEventRecord(b->ctx_ev, cs), "batch: event");
+            BCHK(hipStreamWaitEvent(b->st, b->ctx_ev, 0), "batch: wait");
+        }
+    }
+    if (total > 0) {
+        BCHK(hipMemcpyAsync(b->dev, S.host, total, hipMemcpyHostToDevice, b->st), "batch: upload");
+        BCHK(hipEventRecord(S.done, b->st), "batch: event");
+        S.used = true;
+        b->which ^= 1;
+    }
+    BCHK(hipEventRecord(b->fork, b->st), "batch: event");
+    const int nst = (int)std::min<size_t>(groups.size(), kStreams);
+    for (int k = 0; k < nst; ++k) BCHK(hipStreamWaitEvent(b->streams[k], b->fork, 0), "batch: wait");
+    int launches = 0, batched = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        hipStream_t gs = b->streams[g % kStreams];
+        const std::vector<int> &mem = groups[g];
+        const Recorder &R0 = b->rec[mem[0]];
+        for (size_t p = 0; p < R0.recs.size(); ++p) {
+            const LaunchRec &L0 = R0.recs[p];
+            if (L0.many) {
+                size_t lds = 0;
+                for (int i : mem) lds = std::max(lds, b->rec[i].recs[p].lds);
+                BCHK(L0.many((const unsigned char *)b->dev + tables[g][p].off, (int)mem.size(),
+                             tables[g][p].blocks, L0.threads, lds, gs),
+                     "batch: launch");
+                ++launches;
+                ++batched;
+            } else {
+                for (int i : mem) {
+                    b->rec[i].recs[p].raw(gs);
+                    BCHK(hipGetLastError(), "batch: launch");
+                    ++launches;
+                }
+            }
+        }
+    }
+    for (int k = 0; k < nst; ++k) {
+        BCHK(hipEventRecord(b->join[k], b->streams[k]), "batch: event");
+        BCHK(hipStreamWaitEvent(b->st, b->join[k], 0), "batch: wait");
+    }
+    // the contexts' streams continue after the batch
+    BCHK(hipEventRecord(b->ctx_ev, b->st), "batch: event");
+    {
+        std::vector<hipStream_t> seen;
+        for (rzpic_ctx *c : b->ctx) {
+            hipStream_t cs = rz_stream(c);
+            if (cs == b->st || std::find(seen.begin(), seen.end(), cs) != seen.end()) continue;
+            seen.push_back(cs);
+            BCHK(hipStreamWaitEvent(cs, b->ctx_ev, 0), "batch: wait");
+        }
+    }
+    b->classes = (int32_t)groups.size();
+    b->launches = launches;
+    b->batched = batched;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_batch_stats(rzpic_batch *b, int32_t out[3])
+{
+    if (!b || !out) return rz_fail(RZPIC_EINVAL, "null argument");
+    out[0] = b->classes;
+    out[1] = b->launches;
+    out[2] = b->batched;
+    return RZPIC_OK;
+}
+
+}  // extern "C"

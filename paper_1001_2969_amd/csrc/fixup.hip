@@ -60,11 +60,11 @@ __device__ __forceinline__ int64_t prefix_of(const int32_t *sc, int64_t upto, in
 
 // Superchunk totals: block (sc, 0) sums the children masks of its 512
 // electron chunks, blocks (sc, 1 + s) the dead masks of species s.
-__global__ __launch_bounds__(kSuper) void k_scan(ScanJobs j)
+__device__ void scan_body(const Blk &k, const ScanJobs &j)
 {
     __shared__ int sh[64];
-    const int job = blockIdx.y;
-    const int64_t sc = blockIdx.x;
+    const int job = k.y;
+    const int64_t sc = k.x;
     const int64_t c = sc * kSuper + threadIdx.x;
     int tot;
     if (job == 0) {
@@ -96,20 +96,19 @@ hipError_t launch_scan(const ScanJobs &j, int64_t max_chunks, hipStream_t st)
 {
     int64_t nsc = (max_chunks + kSuper - 1) / kSuper;
     if (nsc < 1) nsc = 1;
-    hipLaunchKernelGGL(k_scan, dim3((unsigned)nsc, 3), dim3(kSuper), 0, st, j);
-    return hipGetLastError();
+    return launch<ScanJobs, scan_body, kSuper>(dim3((unsigned)nsc, 3), dim3(kSuper), 0, st, j);
 }
 
 // Sorted dead list of species blockIdx.y: superchunk prefix + the in-block
 // scan of the chunk counts give each chunk's offset; its set lanes follow in
 // increasing order.  Block (0, s) records n, the dead total and the kept count.
-__global__ __launch_bounds__(kSuper) void k_dead_list(ScanJobs j)
+__device__ void dead_list_body(const Blk &k, const ScanJobs &j)
 {
     __shared__ int sh[64];
     __shared__ int64_t sh64[16];
-    const int s = blockIdx.y;
+    const int s = k.y;
     if (!j.dead[s]) return;
-    const int64_t sc = blockIdx.x;
+    const int64_t sc = k.x;
     const int64_t n = j.cnt[s]->n;
     const int64_t nch = (n + kChunk - 1) / kChunk;
     const int64_t nsc = (nch + kSuper - 1) / kSuper;
@@ -139,8 +138,7 @@ hipError_t launch_dead_list(const ScanJobs &j, int64_t max_chunks, hipStream_t s
 {
     int64_t nsc = (max_chunks + kSuper - 1) / kSuper;
     if (nsc < 1) nsc = 1;
-    hipLaunchKernelGGL(k_dead_list, dim3((unsigned)nsc, 2), dim3(kSuper), 0, st, j);
-    return hipGetLastError();
+    return launch<ScanJobs, dead_list_body, kSuper>(dim3((unsigned)nsc, 2), dim3(kSuper), 0, st, j);
 }
 
 // Unmerged form: per-chunk lists of the particles marked dead (w < 0).
@@ -161,7 +159,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_dead_scan(const T
 template <typename T>
 hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_dead_scan<T>), dim3(1024), dim3(256), 0, st, p.w, cnt, ch);
+    RZ_LAUNCH((k_dead_scan<T>), dim3(1024), dim3(256), 0, st, p.w, cnt, ch);
     return hipGetLastError();
 }
 
@@ -169,7 +167,8 @@ hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_
 // [keep, n).  With T_k the dead indices >= keep (sorted), that particle is
 // keep + m + k for the smallest k whose T_k lies beyond it.
 template <typename T>
-__device__ __forceinline__ void fill_body(const Parts<T> &p, const int64_t *dead, const FixRec *fix)
+__device__ __forceinline__ void fill_body(const Blk &kb, const Parts<T> &p, const int64_t *dead,
+                                          const FixRec *fix)
 {
     const int64_t D = fix->dead, keep = fix->keep;
     if (D == 0) return;
@@ -180,8 +179,8 @@ __device__ __forceinline__ void fill_body(const Parts<T> &p, const int64_t *dead
         else hi = mid;
     }
     const int64_t H = lo;
-    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < H;
-         m += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t m = kb.x * (int64_t)blockDim.x + threadIdx.x; m < H;
+         m += (int64_t)kb.nx * blockDim.x) {
         int64_t a = 0, b = D - H;
         while (a < b) {
             int64_t k = (a + b) >> 1;
@@ -203,32 +202,40 @@ __device__ __forceinline__ void fill_body(const Parts<T> &p, const int64_t *dead
 
 template <typename T> __global__ void k_fill(Parts<T> p, const int64_t *dead, const FixRec *fix)
 {
-    fill_body<T>(p, dead, fix);
+    fill_body<T>(Blk{(int)blockIdx.x, 0, (int)gridDim.x, 1}, p, dead, fix);
 }
 
 template <typename T>
 hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fill<T>), dim3(256), dim3(256), 0, st, p, ch.dead_glob, fix);
+    RZ_LAUNCH((k_fill<T>), dim3(256), dim3(256), 0, st, p, ch.dead_glob, fix);
     return hipGetLastError();
 }
 
-// Both species in one launch (blockIdx.y selects the species).
-template <typename T>
-__global__ void k_fill2(Parts<T> p0, Parts<T> p1, const int64_t *dead0, const int64_t *dead1,
-                        const FixRec *fix0, const FixRec *fix1)
+// Both species in one launch (the block row selects the species).
+template <typename T> struct Fill2Args {
+    Parts<T> p[2];
+    const int64_t *dead[2];
+    const FixRec *fix[2];
+};
+
+template <typename T> __device__ void fill2_body(const Blk &k, const Fill2Args<T> &a)
 {
-    if (blockIdx.y == 0) fill_body<T>(p0, dead0, fix0);
-    else fill_body<T>(p1, dead1, fix1);
+    fill_body<T>(k, a.p[k.y], a.dead[k.y], a.fix[k.y]);
 }
 
 template <typename T>
 hipError_t launch_fill2(Parts<T> p0, Parts<T> p1, Chunks ch0, Chunks ch1, const FixRec *fix0,
                         const FixRec *fix1, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fill2<T>), dim3(256, 2), dim3(256), 0, st, p0, p1, ch0.dead_glob,
-                       ch1.dead_glob, fix0, fix1);
-    return hipGetLastError();
+    Fill2Args<T> a;
+    a.p[0] = p0;
+    a.p[1] = p1;
+    a.dead[0] = ch0.dead_glob;
+    a.dead[1] = ch1.dead_glob;
+    a.fix[0] = fix0;
+    a.fix[1] = fix1;
+    return launch<Fill2Args<T>, fill2_body<T>, 256>(dim3(256, 2), dim3(256), 0, st, a);
 }
 
 // Append of the staged children of species blockIdx.y after its kept
@@ -240,14 +247,20 @@ template <typename T> struct AppendArgs {
     Counts *cnt[2];
 };
 
-template <typename T>
-__global__ __launch_bounds__(kSuper) void k_append(ScanJobs j, AppendArgs<T> g)
+template <typename T> struct AppendJob {
+    ScanJobs j;
+    AppendArgs<T> g;
+};
+
+template <typename T> __device__ void append_body(const Blk &kb, const AppendJob<T> &aj)
 {
     __shared__ int sh[64];
     __shared__ int64_t sh64[16];
-    const int cs = blockIdx.y;
+    const ScanJobs &j = aj.j;
+    const AppendArgs<T> &g = aj.g;
+    const int cs = kb.y;
     if (!j.dead[cs]) return;
-    const int64_t sc = blockIdx.x;
+    const int64_t sc = kb.x;
     const int64_t keep = j.fix[cs]->keep;
     const int64_t cap = j.cap[cs];
     const bool kids = j.kids[cs] != 0;
@@ -316,8 +329,8 @@ hipError_t launch_append(const ScanJobs &j, Parts<T> dst0, Parts<T> dst1, Parts<
     g.cnt[1] = cnt1;
     int64_t nsc = (max_chunks + kSuper - 1) / kSuper;
     if (nsc < 1) nsc = 1;
-    hipLaunchKernelGGL((k_append<T>), dim3((unsigned)nsc, 2), dim3(kSuper), 0, st, j, g);
-    return hipGetLastError();
+    return launch<AppendJob<T>, append_body<T>, kSuper>(dim3((unsigned)nsc, 2), dim3(kSuper), 0, st,
+                                                        AppendJob<T>{j, g});
 }
 
 // Weight split (Sec. 2.2): clone count of each particle.  Contraction is off
@@ -430,10 +443,10 @@ template <typename T>
 hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, double wcoef,
                          double half_hr, int64_t cap, int32_t *status, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_resize_count<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, wcoef,
+    RZ_LAUNCH((k_resize_count<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, wcoef,
                        half_hr);
-    hipLaunchKernelGGL(k_resize_scan, dim3(1), dim3(1024), 0, st, cnt, ch, rec, cap);
-    hipLaunchKernelGGL((k_resize_scatter<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, rec,
+    RZ_LAUNCH(k_resize_scan, dim3(1), dim3(1024), 0, st, cnt, ch, rec, cap);
+    RZ_LAUNCH((k_resize_scatter<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, rec,
                        wcoef, half_hr, status);
     return hipGetLastError();
 }
@@ -458,7 +471,7 @@ hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long lon
     int threads = 256;
     int bx = (nn + threads - 1) / threads;
     int by = nb < 32 ? nb : 32;
-    hipLaunchKernelGGL(k_reduce_slices, dim3(bx, by), dim3(threads), 0, st, acc, slices, nb, nn);
+    RZ_LAUNCH(k_reduce_slices, dim3(bx, by), dim3(threads), 0, st, acc, slices, nb, nn);
     return hipGetLastError();
 }
 
@@ -487,7 +500,7 @@ hipError_t launch_reduce_slices2(unsigned long long *acc0, const unsigned long l
     int bx = (nn + threads - 1) / threads;
     int nb = nb0 > nb1 ? nb0 : nb1;
     int by = nb < 32 ? nb : 32;
-    hipLaunchKernelGGL(k_reduce_slices2, dim3(bx, by, 2), dim3(threads), 0, st, acc0, slices0, nb0,
+    RZ_LAUNCH(k_reduce_slices2, dim3(bx, by, 2), dim3(threads), 0, st, acc0, slices0, nb0,
                        acc1, slices1, nb1, nn);
     return hipGetLastError();
 }

@@ -14,7 +14,7 @@ __global__ void k_finalize(GridArgs g)
 hipError_t launch_finalize(const GridArgs &g, hipStream_t st)
 {
     int threads = 256, blocks = (g.nn + threads - 1) / threads;
-    hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(threads), 0, st, g);
+    RZ_LAUNCH(k_finalize, dim3(blocks), dim3(threads), 0, st, g);
     return hipGetLastError();
 }
 
@@ -22,11 +22,31 @@ hipError_t launch_finalize(const GridArgs &g, hipStream_t st)
 // r = R, E_r = 0 on the axis.  Also the interleaved (E_r, E_z) copy that the
 // particle gather reads (in the particles' precision).
 template <typename T>
-__global__ void k_efield(int nr, int nz, double hr, double hz, const double *phi, double *er,
-                         double *ez, typename Vec2<T>::type *E2)
+struct k_efield_A {
+    int nr;
+    int nz;
+    double hr;
+    double hz;
+    const double *phi;
+    double *er;
+    double *ez;
+    typename Vec2<T>::type *E2;
+};
+
+template <typename T>
+__device__ void k_efield_body(const Blk &kb_, const k_efield_A<T> &A_)
 {
+    auto nr = A_.nr;
+    auto nz = A_.nz;
+    auto hr = A_.hr;
+    auto hz = A_.hz;
+    auto phi = A_.phi;
+    auto er = A_.er;
+    auto ez = A_.ez;
+    auto E2 = A_.E2;
+
     const int nn = nr * nz;
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += gridDim.x * blockDim.x) {
+    for (int g = kb_.x * blockDim.x + threadIdx.x; g < nn; g += kb_.nx * blockDim.x) {
         int i = g / nr, j = g - i * nr;
         double vz, vr;
         if (i == 0) vz = -(phi[g + nr] - phi[g]) / hz;
@@ -44,13 +64,13 @@ __global__ void k_efield(int nr, int nz, double hr, double hz, const double *phi
     }
 }
 
+
 template <typename T>
 hipError_t launch_efield(int nr, int nz, double hr, double hz, const double *phi, double *er,
                          double *ez, typename Vec2<T>::type *E2, hipStream_t st)
 {
     int nn = nr * nz, threads = 256, blocks = (nn + threads - 1) / threads;
-    hipLaunchKernelGGL((k_efield<T>), dim3(blocks), dim3(threads), 0, st, nr, nz, hr, hz, phi, er,
-                       ez, E2);
+    (void)launch<k_efield_A<T>, k_efield_body<T>, 256>(dim3(blocks), dim3(threads), 0, st, k_efield_A<T>{nr, nz, hr, hz, phi, er, ez, E2});
     return hipGetLastError();
 }
 
@@ -71,7 +91,7 @@ hipError_t launch_pack_e2(int nn, const double *er, const double *ez, typename V
                           hipStream_t st)
 {
     int threads = 256, blocks = (nn + threads - 1) / threads;
-    hipLaunchKernelGGL((k_pack_e2<T>), dim3(blocks), dim3(threads), 0, st, nn, er, ez, E2);
+    RZ_LAUNCH((k_pack_e2<T>), dim3(blocks), dim3(threads), 0, st, nn, er, ez, E2);
     return hipGetLastError();
 }
 
@@ -88,7 +108,7 @@ hipError_t launch_acc_convert(int nn, unsigned long long *acc, double *dev, doub
                               int to_acc, hipStream_t st)
 {
     int threads = 256, blocks = (nn + threads - 1) / threads;
-    hipLaunchKernelGGL(k_acc_convert, dim3(blocks), dim3(threads), 0, st, nn, acc, dev, quantum,
+    RZ_LAUNCH(k_acc_convert, dim3(blocks), dim3(threads), 0, st, nn, acc, dev, quantum,
                        to_acc);
     return hipGetLastError();
 }
@@ -105,7 +125,7 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st)
     int threads = 256;
     int64_t b = (n + threads - 1) / threads;
     int blocks = (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
-    hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(threads), 0, st, p, n);
+    RZ_LAUNCH(k_fill_u64, dim3(blocks), dim3(threads), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "launch.h"
+
 namespace rz {
 
 // Physical constants (CODATA 2018, SI).

@@ -52,7 +52,7 @@ __global__ void k_set_bc(double *phi, int nr, int nz, double V)
 
 hipError_t mg_set_bc(double *phi, int nr, int nz, double V, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_set_bc, dim3(1), dim3(256), 0, st, phi, nr, nz, V);
+    RZ_LAUNCH(k_set_bc, dim3(1), dim3(256), 0, st, phi, nr, nz, V);
     return hipGetLastError();
 }
 
@@ -90,7 +90,7 @@ hipError_t mg_resid_norm(const MgLevels &m, const double *u, const double *f, in
     const int L = m.L, nr = m.nr, nz = m.nzl[L];
     const double hz = m.hzl[L];
     int nn = nr * nz, threads = 256, blocks = (nn + threads - 1) / threads;
-    hipLaunchKernelGGL(k_resid, dim3(blocks), dim3(threads), 0, st, u, f, m.eps64[L], nr, nz,
+    RZ_LAUNCH(k_resid, dim3(blocks), dim3(threads), 0, st, u, f, m.eps64[L], nr, nz,
                        1.0 / (hz * hz), 1.0 / (m.hr * m.hr), m.chi_face, norm, zero_interior);
     return hipGetLastError();
 }
@@ -141,7 +141,7 @@ hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st)
     int blocks = (m.nr + cpb - 1) / cpb;
     size_t lds = 2 * (size_t)cpb * nz * sizeof(double);
     if (m.L > 1)
-        hipLaunchKernelGGL(k_restrict_eps, dim3(blocks), dim3(256), lds, st, m, mixed, cpb);
+        RZ_LAUNCH(k_restrict_eps, dim3(blocks), dim3(256), lds, st, m, mixed, cpb);
     return hipGetLastError();
 }
 
@@ -150,14 +150,35 @@ hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st)
 // (finalize_node), epsilon restricted down every level as k_restrict_eps
 // does, the Dirichlet values of phi0 and phi1 (V on z = 0 for r < R, 0 on
 // z = L and r = R) and, by block 0, `nclear` counters cleared.
-__global__ void k_finalize_mg(GridArgs g, MgLevels m, int mixed, int cpb, double *phi0,
-                              double *phi1, double V, unsigned long long *clear, int nclear)
+struct k_finalize_mg_A {
+    GridArgs g;
+    MgLevels m;
+    int mixed;
+    int cpb;
+    double *phi0;
+    double *phi1;
+    double V;
+    unsigned long long *clear;
+    int nclear;
+};
+
+__device__ void k_finalize_mg_body(const Blk &kb_, const k_finalize_mg_A &A_)
 {
+    const auto &g = A_.g;
+    const auto &m = A_.m;
+    auto mixed = A_.mixed;
+    auto cpb = A_.cpb;
+    auto phi0 = A_.phi0;
+    auto phi1 = A_.phi1;
+    auto V = A_.V;
+    auto clear = A_.clear;
+    auto nclear = A_.nclear;
+
     extern __shared__ double sbuf[];
     const int L = m.L, nr = m.nr, nz = m.nzl[L];
     double *cur = sbuf, *nxt = sbuf + (size_t)cpb * nz;
-    const int j0 = blockIdx.x * cpb;
-    if (blockIdx.x == 0)
+    const int j0 = kb_.x * cpb;
+    if (kb_.x == 0)
         for (int t = threadIdx.x; t < nclear; t += blockDim.x) clear[t] = 0;
     for (int t = threadIdx.x; t < cpb * nz; t += blockDim.x) {
         const int cj = t / nz, i = t - cj * nz, j = j0 + cj;
@@ -198,6 +219,7 @@ __global__ void k_finalize_mg(GridArgs g, MgLevels m, int mixed, int cpb, double
     }
 }
 
+
 hipError_t mg_finalize(const GridArgs &g, const MgLevels &m, int mixed, double *phi0, double *phi1,
                        double V, unsigned long long *clear, int nclear, hipStream_t st)
 {
@@ -206,8 +228,7 @@ hipError_t mg_finalize(const GridArgs &g, const MgLevels &m, int mixed, double *
     if (cpb < 1) cpb = 1;
     const int blocks = (m.nr + cpb - 1) / cpb;
     const size_t lds = 2 * (size_t)cpb * nz * sizeof(double);
-    hipLaunchKernelGGL(k_finalize_mg, dim3(blocks), dim3(256), lds, st, g, m, mixed, cpb, phi0, phi1,
-                       V, clear, nclear);
+    (void)launch<k_finalize_mg_A, k_finalize_mg_body, 256>(dim3(blocks), dim3(256), lds, st, k_finalize_mg_A{g, m, mixed, cpb, phi0, phi1, V, clear, nclear});
     return hipGetLastError();
 }
 
@@ -224,12 +245,20 @@ template <typename T> struct LineArgs {
 // even rows 2b+2) exactly for j = 0..nr-2,
 //   -d x_{j-1} + b x_j - e x_{j+1} = f + a u_{i-1} + c u_{i+1} (+ e u_wall),
 // by parallel cyclic reduction in LDS.
-template <typename T> __global__ __launch_bounds__(1024) void k_line(LineArgs<T> p)
+template <typename T>
+struct k_line_A {
+    LineArgs<T> p;
+};
+
+template <typename T>
+__device__ void k_line_body(const Blk &kb_, const k_line_A<T> &A_)
 {
+    const auto &p = A_.p;
+
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     const int nr = p.nr, n = nr - 1, nzl = p.nzl;
-    const int i = p.parity ? 2 * blockIdx.x + 1 : 2 * blockIdx.x + 2;
+    const int i = p.parity ? 2 * kb_.x + 1 : 2 * kb_.x + 2;
     T *A = sm, *Bd = sm + n, *C = sm + 2 * n, *Rr = sm + 3 * n;
     T *A2 = sm + 4 * n, *B2 = sm + 5 * n, *C2 = sm + 6 * n, *R2 = sm + 7 * n;
     auto nb = [&](int row, int j) -> T {
@@ -281,6 +310,7 @@ template <typename T> __global__ __launch_bounds__(1024) void k_line(LineArgs<T>
     }
     for (int j = threadIdx.x; j < n; j += blockDim.x) p.u[(size_t)i * nr + j] = Rr[j] / Bd[j];
 }
+
 
 // The same half-sweep for lines too long for k_line's LDS (8 (nr-1) values):
 // the partition method.  Thread t owns Q consecutive unknowns (a segment,
@@ -407,31 +437,44 @@ static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u,
     if (lds <= m.lds_budget && n <= 1024 * 4) {
         int threads = ((n + 63) / 64) * 64;
         if (threads > 1024) threads = 1024;
-        hipLaunchKernelGGL((k_line<T>), dim3(rows), dim3(threads), lds, st, p);
+        (void)launch<k_line_A<T>, k_line_body<T>, 1024>(dim3(rows), dim3(threads), lds, st, k_line_A<T>{p});
         return hipGetLastError();
     }
     // long lines: segments of Q unknowns per thread
     const int q = (n + kLongThreads - 1) / kLongThreads;
     lds = 7 * (size_t)kLongThreads * sizeof(T);
     if (q <= 2)
-        hipLaunchKernelGGL((k_line_part<T, 2>), dim3(rows), dim3(kLongThreads), lds, st, p);
+        RZ_LAUNCH((k_line_part<T, 2>), dim3(rows), dim3(kLongThreads), lds, st, p);
     else if (q <= 4)
-        hipLaunchKernelGGL((k_line_part<T, 4>), dim3(rows), dim3(kLongThreads), lds, st, p);
+        RZ_LAUNCH((k_line_part<T, 4>), dim3(rows), dim3(kLongThreads), lds, st, p);
     else if (q <= 8)
-        hipLaunchKernelGGL((k_line_part<T, 8>), dim3(rows), dim3(kLongThreads), lds, st, p);
+        RZ_LAUNCH((k_line_part<T, 8>), dim3(rows), dim3(kLongThreads), lds, st, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-__global__ void k_add_corr(double *phi, const float *u, int nr, int nz)
+struct k_add_corr_A {
+    double *phi;
+    const float *u;
+    int nr;
+    int nz;
+};
+
+__device__ void k_add_corr_body(const Blk &kb_, const k_add_corr_A &A_)
 {
+    auto phi = A_.phi;
+    auto u = A_.u;
+    auto nr = A_.nr;
+    auto nz = A_.nz;
+
     const int nn = nr * nz;
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += gridDim.x * blockDim.x) {
+    for (int g = kb_.x * blockDim.x + threadIdx.x; g < nn; g += kb_.nx * blockDim.x) {
         int i = g / nr, j = g - i * nr;
         if (i > 0 && i < nz - 1 && j < nr - 1) phi[g] += (double)u[g];
     }
 }
+
 
 // Down-leg of the V(0,1) cycle: the block takes `cpb` unknown columns of the
 // finest level, forms the residual f - A u there (u, eps staged in LDS with a
@@ -509,10 +552,26 @@ __device__ __forceinline__ void down_body(const double *u, const double *f, cons
 }
 
 template <typename T>
-__global__ void k_down(const double *u, const double *f, MgLevels m, int mixed, int cpb)
+struct k_down_A {
+    const double *u;
+    const double *f;
+    MgLevels m;
+    int mixed;
+    int cpb;
+};
+
+template <typename T>
+__device__ void k_down_body(const Blk &kb_, const k_down_A<T> &A_)
 {
-    down_body<T>(u, f, m, mixed, cpb, blockIdx.x);
+    auto u = A_.u;
+    auto f = A_.f;
+    const auto &m = A_.m;
+    auto mixed = A_.mixed;
+    auto cpb = A_.cpb;
+
+    down_body<T>(u, f, m, mixed, cpb, kb_.x);
 }
+
 
 // The same down leg row by row, for large meshes (coalesced along r; the
 // column form above reads a z-column per block): the finest residual into
@@ -578,21 +637,21 @@ static hipError_t down_rows(const MgLevels &m, int mixed, const double *phi, con
 {
     const int L = m.L, nr = m.nr;
     const int threads = 256;
-    hipLaunchKernelGGL(k_resid_rows, dim3(grid_blocks((int64_t)nr * m.nzl[L], threads)),
+    RZ_LAUNCH(k_resid_rows, dim3(grid_blocks((int64_t)nr * m.nzl[L], threads)),
                        dim3(threads), 0, st, phi, f, m, mixed);
     for (int l = L - 1; l >= 1; --l) {
         const int nzc = m.nzl[l];
         const int blocks = grid_blocks((int64_t)(nzc - 2) * (nr - 1), threads);
         if (mixed) {
             if (l == L - 1)
-                hipLaunchKernelGGL((k_restrict_rows<double, float>), dim3(blocks), dim3(threads), 0,
+                RZ_LAUNCH((k_restrict_rows<double, float>), dim3(blocks), dim3(threads), 0,
                                    st, (const double *)m.res, m.f32[l], nr, nzc, mixed);
             else
-                hipLaunchKernelGGL((k_restrict_rows<float, float>), dim3(blocks), dim3(threads), 0,
+                RZ_LAUNCH((k_restrict_rows<float, float>), dim3(blocks), dim3(threads), 0,
                                    st, (const float *)m.f32[l + 1], m.f32[l], nr, nzc, mixed);
         } else {
             const double *src = l == L - 1 ? (const double *)m.res : (const double *)m.f64[l + 1];
-            hipLaunchKernelGGL((k_restrict_rows<double, double>), dim3(blocks), dim3(threads), 0, st,
+            RZ_LAUNCH((k_restrict_rows<double, double>), dim3(blocks), dim3(threads), 0, st,
                                src, m.f64[l], nr, nzc, mixed);
         }
     }
@@ -650,8 +709,18 @@ __device__ __forceinline__ void pcr(T *A, T *Bd, T *C, T *Rr, int n, int ne)
 // single line of level 1, then for l = 2..K the prolonged correction (injected
 // into the even lines the odd lines read) and one zebra sweep.  The coarse u^l
 // start from zero; u^K is written out for the next level's prolongation.
-template <typename T, int EPT> __global__ __launch_bounds__(1024) void k_bottom(MgLevels m, int mixed)
+template <typename T, int EPT>
+struct k_bottom_A {
+    MgLevels m;
+    int mixed;
+};
+
+template <typename T, int EPT>
+__device__ void k_bottom_body(const Blk &kb_, const k_bottom_A<T, EPT> &A_)
 {
+    const auto &m = A_.m;
+    auto mixed = A_.mixed;
+
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     const int K = m.K, nr = m.nr, n = nr - 1;
@@ -719,6 +788,7 @@ template <typename T, int EPT> __global__ __launch_bounds__(1024) void k_bottom(
     for (size_t t = threadIdx.x; t < szK; t += blockDim.x) gu[t] = uK[t];
 }
 
+
 template <typename T> struct LevelArgs {
     int nr, nzl, rule, zero_old;
     T iz2, ir2;
@@ -734,12 +804,20 @@ template <typename T> struct LevelArgs {
 // value plus the injected coarse correction) -- the odd lines next to two even
 // lines are solved, identically, by both blocks -- then line i from them.
 // Odd line i-1 is owned by block i, and the last odd line by the last block.
-template <typename T, int EPT> __global__ __launch_bounds__(1024) void k_level(LevelArgs<T> p)
+template <typename T, int EPT>
+struct k_level_A {
+    LevelArgs<T> p;
+};
+
+template <typename T, int EPT>
+__device__ void k_level_body(const Blk &kb_, const k_level_A<T, EPT> &A_)
 {
+    const auto &p = A_.p;
+
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     const int nr = p.nr, n = nr - 1, nzl = p.nzl;
-    const int i = 2 * blockIdx.x + 2;
+    const int i = 2 * kb_.x + 2;
     const bool last = i + 1 == nzl - 2;
     T *A = sm, *Bd = A + 2 * n, *C = Bd + 2 * n, *Rr = C + 2 * n;
     auto old = [&](int row, int j) -> T {
@@ -801,6 +879,7 @@ template <typename T, int EPT> __global__ __launch_bounds__(1024) void k_level(L
     }
 }
 
+
 template <typename T>
 static hipError_t level_sweep(const MgLevels &m, int l, int zero_old, const T *u_in,
                               const T *uc, T *u_out, const T *f, const T *eps, double *add_to,
@@ -827,11 +906,11 @@ static hipError_t level_sweep(const MgLevels &m, int l, int zero_old, const T *u
     const int ept = (2 * n + threads - 1) / threads;  // 2 n <= 4096 here: at most 4
     size_t lds = 12 * (size_t)n * sizeof(T);
     if (ept <= 1)
-        hipLaunchKernelGGL((k_level<T, 1>), dim3(blocks), dim3(threads), lds, st, p);
+        (void)launch<k_level_A<T, 1>, k_level_body<T, 1>, 1024>(dim3(blocks), dim3(threads), lds, st, k_level_A<T, 1>{p});
     else if (ept <= 2)
-        hipLaunchKernelGGL((k_level<T, 2>), dim3(blocks), dim3(threads), lds, st, p);
+        (void)launch<k_level_A<T, 2>, k_level_body<T, 2>, 1024>(dim3(blocks), dim3(threads), lds, st, k_level_A<T, 2>{p});
     else
-        hipLaunchKernelGGL((k_level<T, 4>), dim3(blocks), dim3(threads), lds, st, p);
+        (void)launch<k_level_A<T, 4>, k_level_body<T, 4>, 1024>(dim3(blocks), dim3(threads), lds, st, k_level_A<T, 4>{p});
     return hipGetLastError();
 }
 
@@ -915,21 +994,49 @@ template <typename T> __device__ __forceinline__ void factor_body(const MgLevels
     if (j < n) tab[2 * n + j] = Bd[j];
 }
 
-template <typename T> __global__ __launch_bounds__(256) void k_factor(MgLevels m, int mixed)
+template <typename T>
+struct k_factor_A {
+    MgLevels m;
+    int mixed;
+};
+
+template <typename T>
+__device__ void k_factor_body(const Blk &kb_, const k_factor_A<T> &A_)
 {
-    factor_body<T>(m, mixed, blockIdx.x);
+    const auto &m = A_.m;
+    auto mixed = A_.mixed;
+
+    factor_body<T>(m, mixed, kb_.x);
 }
+
 
 // Split path, first launch of a solve: the line tables of every level
 // (blocks [0, nfb)) and, beside them, the first cycle's finest residual
 // restricted to every level (the remaining blocks, cpb columns each).
 template <typename T>
-__global__ __launch_bounds__(256) void k_prep(const double *u, const double *f, MgLevels m,
-                                              int mixed, int cpb, int nfb)
+struct k_prep_A {
+    const double *u;
+    const double *f;
+    MgLevels m;
+    int mixed;
+    int cpb;
+    int nfb;
+};
+
+template <typename T>
+__device__ void k_prep_body(const Blk &kb_, const k_prep_A<T> &A_)
 {
-    if ((int)blockIdx.x < nfb) factor_body<T>(m, mixed, blockIdx.x);
-    else down_body<T>(u, f, m, mixed, cpb, blockIdx.x - nfb);
+    auto u = A_.u;
+    auto f = A_.f;
+    const auto &m = A_.m;
+    auto mixed = A_.mixed;
+    auto cpb = A_.cpb;
+    auto nfb = A_.nfb;
+
+    if ((int)kb_.x < nfb) factor_body<T>(m, mixed, kb_.x);
+    else down_body<T>(u, f, m, mixed, cpb, kb_.x - nfb);
 }
+
 
 static size_t down_lds(int nz, int cpb)
 {
@@ -946,11 +1053,9 @@ hipError_t mg_prep(const MgLevels &m, int mixed, const double *phi, const double
     const size_t lf = 3 * (size_t)n * (mixed ? sizeof(float) : sizeof(double));
     if (lf > lds) lds = lf;
     if (mixed)
-        hipLaunchKernelGGL((k_prep<float>), dim3(nfb + nd), dim3(256), lds, st, phi, f, m, mixed, cpb,
-                           nfb);
+        (void)launch<k_prep_A<float>, k_prep_body<float>, 256>(dim3(nfb + nd), dim3(256), lds, st, k_prep_A<float>{phi, f, m, mixed, cpb, nfb});
     else
-        hipLaunchKernelGGL((k_prep<double>), dim3(nfb + nd), dim3(256), lds, st, phi, f, m, mixed,
-                           cpb, nfb);
+        (void)launch<k_prep_A<double>, k_prep_body<double>, 256>(dim3(nfb + nd), dim3(256), lds, st, k_prep_A<double>{phi, f, m, mixed, cpb, nfb});
     return hipGetLastError();
 }
 
@@ -961,11 +1066,9 @@ hipError_t mg_factor(const MgLevels &m, int mixed, hipStream_t st)
     const int blocks = m.line_off[m.L + 1] + (m.nzl[m.L] - 2), n = m.nr - 1;
     const int threads = ((n + 63) / 64) * 64;  // n <= 256 on this path
     if (mixed)
-        hipLaunchKernelGGL((k_factor<float>), dim3(blocks), dim3(threads), 3 * n * sizeof(float),
-                           st, m, mixed);
+        (void)launch<k_factor_A<float>, k_factor_body<float>, 256>(dim3(blocks), dim3(threads), 3 * n * sizeof(float), st, k_factor_A<float>{m, mixed});
     else
-        hipLaunchKernelGGL((k_factor<double>), dim3(blocks), dim3(threads), 3 * n * sizeof(double),
-                           st, m, mixed);
+        (void)launch<k_factor_A<double>, k_factor_body<double>, 256>(dim3(blocks), dim3(threads), 3 * n * sizeof(double), st, k_factor_A<double>{m, mixed});
     return hipGetLastError();
 }
 
@@ -1050,10 +1153,27 @@ __device__ __forceinline__ void line_pcr(T (&R)[Q], const LineTab<T, Q, SMAX> &t
 }
 
 template <typename T, int Q>
-__global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *phi,
-                                                const double *f, double V, int cycles,
-                                                int coarse)
+struct k_solve_A {
+    MgLevels m;
+    int mixed;
+    double *phi;
+    const double *f;
+    double V;
+    int cycles;
+    int coarse;
+};
+
+template <typename T, int Q>
+__device__ void k_solve_body(const Blk &kb_, const k_solve_A<T, Q> &A_)
 {
+    const auto &m = A_.m;
+    auto mixed = A_.mixed;
+    auto phi = A_.phi;
+    auto f = A_.f;
+    auto V = A_.V;
+    auto cycles = A_.cycles;
+    auto coarse = A_.coarse;
+
     constexpr int SMAX = Q == 1 ? 6 : Q == 2 ? 7 : 8;
     constexpr int RU = 4;  // residuals per thread computed before any is stored
     extern __shared__ unsigned char smem_raw[];
@@ -1254,6 +1374,7 @@ __global__ __launch_bounds__(1024) void k_solve(MgLevels m, int mixed, double *p
     }
 }
 
+
 static hipError_t solve_block(const MgLevels &m, int mixed, double *phi, const double *f, double V,
                               int cycles, int coarse, hipStream_t st)
 {
@@ -1261,21 +1382,16 @@ static hipError_t solve_block(const MgLevels &m, int mixed, double *phi, const d
     const size_t lds = m.solve_lds;
     if (mixed) {
         if (n <= 64)
-            hipLaunchKernelGGL((k_solve<float, 1>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
-                               cycles, coarse);
+            (void)launch<k_solve_A<float, 1>, k_solve_body<float, 1>, 1024>(dim3(1), dim3(1024), lds, st, k_solve_A<float, 1>{m, mixed, phi, f, V, cycles, coarse});
         else if (n <= 128)
-            hipLaunchKernelGGL((k_solve<float, 2>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
-                               cycles, coarse);
+            (void)launch<k_solve_A<float, 2>, k_solve_body<float, 2>, 1024>(dim3(1), dim3(1024), lds, st, k_solve_A<float, 2>{m, mixed, phi, f, V, cycles, coarse});
         else
-            hipLaunchKernelGGL((k_solve<float, 4>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f, V,
-                               cycles, coarse);
+            (void)launch<k_solve_A<float, 4>, k_solve_body<float, 4>, 1024>(dim3(1), dim3(1024), lds, st, k_solve_A<float, 4>{m, mixed, phi, f, V, cycles, coarse});
     } else {
         if (n <= 64)
-            hipLaunchKernelGGL((k_solve<double, 1>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f,
-                               V, cycles, coarse);
+            (void)launch<k_solve_A<double, 1>, k_solve_body<double, 1>, 1024>(dim3(1), dim3(1024), lds, st, k_solve_A<double, 1>{m, mixed, phi, f, V, cycles, coarse});
         else
-            hipLaunchKernelGGL((k_solve<double, 2>), dim3(1), dim3(1024), lds, st, m, mixed, phi, f,
-                               V, cycles, coarse);
+            (void)launch<k_solve_A<double, 2>, k_solve_body<double, 2>, 1024>(dim3(1), dim3(1024), lds, st, k_solve_A<double, 2>{m, mixed, phi, f, V, cycles, coarse});
     }
     return hipGetLastError();
 }
@@ -1288,14 +1404,28 @@ static hipError_t solve_block(const MgLevels &m, int mixed, double *phi, const d
 // rows) to phi_out.  Mixed: the correction from zero with the FP32 residual as
 // right-hand side, added to phi in place (phi_in == phi_out).
 template <typename T, int Q>
-__global__ __launch_bounds__(128) void k_fine(MgLevels m, int mixed, const double *phi_in,
-                                              double *phi_out, const double *f)
+struct k_fine_A {
+    MgLevels m;
+    int mixed;
+    const double *phi_in;
+    double *phi_out;
+    const double *f;
+};
+
+template <typename T, int Q>
+__device__ void k_fine_body(const Blk &kb_, const k_fine_A<T, Q> &A_)
 {
+    const auto &m = A_.m;
+    auto mixed = A_.mixed;
+    auto phi_in = A_.phi_in;
+    auto phi_out = A_.phi_out;
+    auto f = A_.f;
+
     constexpr int SMAX = Q == 1 ? 6 : Q == 2 ? 7 : 8;
     __shared__ T xs[2][Q * 64];
     const int L = m.L, nr = m.nr, n = nr - 1, nz = m.nzl[L], S = m.S;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = 2 * blockIdx.x + 2;
+    const int i = 2 * kb_.x + 2;
     const bool last = i + 1 == nz - 2;
     const T *uc = mixed ? (const T *)m.u32[L - 1] : (const T *)m.u64[L - 1];
     const T *fr = (const T *)m.f32[L];  // mixed: FP32 residual
@@ -1365,6 +1495,7 @@ __global__ __launch_bounds__(128) void k_fine(MgLevels m, int mixed, const doubl
     }
 }
 
+
 template <typename T>
 static hipError_t fine_sweep(const MgLevels &m, int mixed, const double *phi_in, double *phi_out,
                              const double *f, hipStream_t st)
@@ -1372,11 +1503,11 @@ static hipError_t fine_sweep(const MgLevels &m, int mixed, const double *phi_in,
     const int n = m.nr - 1, blocks = (m.nzl[m.L] - 3) / 2;
     if (blocks <= 0) return hipSuccess;
     if (n <= 64)
-        hipLaunchKernelGGL((k_fine<T, 1>), dim3(blocks), dim3(128), 0, st, m, mixed, phi_in, phi_out, f);
+        (void)launch<k_fine_A<T, 1>, k_fine_body<T, 1>, 128>(dim3(blocks), dim3(128), 0, st, k_fine_A<T, 1>{m, mixed, phi_in, phi_out, f});
     else if (n <= 128)
-        hipLaunchKernelGGL((k_fine<T, 2>), dim3(blocks), dim3(128), 0, st, m, mixed, phi_in, phi_out, f);
+        (void)launch<k_fine_A<T, 2>, k_fine_body<T, 2>, 128>(dim3(blocks), dim3(128), 0, st, k_fine_A<T, 2>{m, mixed, phi_in, phi_out, f});
     else
-        hipLaunchKernelGGL((k_fine<T, 4>), dim3(blocks), dim3(128), 0, st, m, mixed, phi_in, phi_out, f);
+        (void)launch<k_fine_A<T, 4>, k_fine_body<T, 4>, 128>(dim3(blocks), dim3(128), 0, st, k_fine_A<T, 4>{m, mixed, phi_in, phi_out, f});
     return hipGetLastError();
 }
 
@@ -1432,11 +1563,11 @@ static hipError_t bottom(const MgLevels &m, int mixed, hipStream_t st)
     const int emax = ((m.nzl[m.K] - 1) / 2) * n;
     const int ept = (emax + 1023) / 1024;
     if (ept <= 1)
-        hipLaunchKernelGGL((k_bottom<T, 1>), dim3(1), dim3(1024), m.bottom_lds, st, m, mixed);
+        (void)launch<k_bottom_A<T, 1>, k_bottom_body<T, 1>, 1024>(dim3(1), dim3(1024), m.bottom_lds, st, k_bottom_A<T, 1>{m, mixed});
     else if (ept <= 2)
-        hipLaunchKernelGGL((k_bottom<T, 2>), dim3(1), dim3(1024), m.bottom_lds, st, m, mixed);
+        (void)launch<k_bottom_A<T, 2>, k_bottom_body<T, 2>, 1024>(dim3(1), dim3(1024), m.bottom_lds, st, k_bottom_A<T, 2>{m, mixed});
     else
-        hipLaunchKernelGGL((k_bottom<T, 4>), dim3(1), dim3(1024), m.bottom_lds, st, m, mixed);
+        (void)launch<k_bottom_A<T, 4>, k_bottom_body<T, 4>, 1024>(dim3(1), dim3(1024), m.bottom_lds, st, k_bottom_A<T, 4>{m, mixed});
     return hipGetLastError();
 }
 
@@ -1450,11 +1581,9 @@ static hipError_t down(const MgLevels &m, int mixed, const double *phi, const do
     const int nr = m.nr, nz = m.nzl[m.L];
     const int cpb = cols_per_block(nz);
     if (mixed)
-        hipLaunchKernelGGL((k_down<float>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256),
-                           down_lds(nz, cpb), st, phi, f, m, mixed, cpb);
+        (void)launch<k_down_A<float>, k_down_body<float>, 256>(dim3((nr - 1 + cpb - 1) / cpb), dim3(256), down_lds(nz, cpb), st, k_down_A<float>{phi, f, m, mixed, cpb});
     else
-        hipLaunchKernelGGL((k_down<double>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256),
-                           down_lds(nz, cpb), st, phi, f, m, mixed, cpb);
+        (void)launch<k_down_A<double>, k_down_body<double>, 256>(dim3((nr - 1 + cpb - 1) / cpb), dim3(256), down_lds(nz, cpb), st, k_down_A<double>{phi, f, m, mixed, cpb});
     return hipGetLastError();
 }
 
@@ -1468,12 +1597,10 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
         if (!mixed) return line<double>(m, 1, 1, 0, phi, f, m.eps64[1], nullptr, st);
         int cpb = cols_per_block(nz);
         size_t lds = (2 * (size_t)(cpb + 2) + 2 * (size_t)cpb) * nz * sizeof(double);
-        hipLaunchKernelGGL((k_down<float>), dim3((nr - 1 + cpb - 1) / cpb), dim3(256), lds, st,
-                           (const double *)phi, f, m, mixed, cpb);
+        (void)launch<k_down_A<float>, k_down_body<float>, 256>(dim3((nr - 1 + cpb - 1) / cpb), dim3(256), lds, st, k_down_A<float>{(const double *)phi, f, m, mixed, cpb});
         if ((e = line<float>(m, 1, 1, 1, m.u32[1], m.f32[1], m.eps32[1], nullptr, st))) return e;
         const int nn = nr * nz, threads = 256, blocks = (nn + threads - 1) / threads;
-        hipLaunchKernelGGL(k_add_corr, dim3(blocks), dim3(threads), 0, st, phi,
-                           (const float *)m.u32[1], nr, nz);
+        (void)launch<k_add_corr_A, k_add_corr_body, 256>(dim3(blocks), dim3(threads), 0, st, k_add_corr_A{phi, (const float *)m.u32[1], nr, nz});
         return hipGetLastError();
     }
     // the residual of the finest level restricted to every level (unless the
@@ -1505,8 +1632,7 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
                     const int nn = nr * nz, threads = 256;
                     const int blocks = (nn + threads - 1) / threads < 65536 ? (nn + threads - 1) / threads
                                                                           : 65536;
-                    hipLaunchKernelGGL(k_add_corr, dim3(blocks), dim3(threads), 0, st, phi,
-                                       (const float *)u, nr, nz);
+                    (void)launch<k_add_corr_A, k_add_corr_body, 256>(dim3(blocks), dim3(threads), 0, st, k_add_corr_A{phi, (const float *)u, nr, nz});
                     if ((e = hipGetLastError())) return e;
                 }
             } else {

@@ -378,11 +378,15 @@ template <typename T, int MODE> __global__ __launch_bounds__(1024) void k_pass(P
 }
 
 // Both species in one launch: blocks [0, b0) take species 0, the rest species 1.
-template <typename T, int MODE>
-__global__ __launch_bounds__(1024) void k_pass2(PassArgs<T> a0, PassArgs<T> a1, int b0)
+template <typename T> struct Pass2Args {
+    PassArgs<T> a0, a1;
+    int b0;
+};
+
+template <typename T, int MODE> __device__ void pass2_body(const Blk &k, const Pass2Args<T> &a)
 {
-    if ((int)blockIdx.x < b0) pass_body<T, MODE>(a0, blockIdx.x, b0);
-    else pass_body<T, MODE>(a1, blockIdx.x - b0, gridDim.x - b0);
+    if (k.x < a.b0) pass_body<T, MODE>(a.a0, k.x, a.b0);
+    else pass_body<T, MODE>(a.a1, k.x - a.b0, k.nx - a.b0);
 }
 
 // Collision kernel over the candidate list (any order: every result below is
@@ -524,19 +528,24 @@ template <typename T, int MODE> __global__ __launch_bounds__(256) void k_collide
 // Collisions of both species (blocks [0, c0) species 0, [c0, c0 + c1)
 // species 1) and, in the remaining blocks, the sum of the pass's LDS slices:
 // both only add into the deposit grids, so they run side by side.
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_collide2(PassArgs<T> a0, PassArgs<T> a1, int c0, int c1,
-                                                  SliceSum r)
+template <typename T> struct Collide2Args {
+    PassArgs<T> a0, a1;
+    int c0, c1;
+    SliceSum r;
+};
+
+template <typename T, int MODE> __device__ void collide2_body(const Blk &k, const Collide2Args<T> &a)
 {
-    const int b = blockIdx.x;
+    const int b = k.x, c0 = a.c0, c1 = a.c1;
     if (b < c0) {
-        collide_body<T, MODE>(a0, b, c0);
+        collide_body<T, MODE>(a.a0, b, c0);
         return;
     }
     if (b < c0 + c1) {
-        collide_body<T, MODE>(a1, b - c0, c1);
+        collide_body<T, MODE>(a.a1, b - c0, c1);
         return;
     }
+    const SliceSum &r = a.r;
     const int rb = b - c0 - c1, per = r.bx * r.by;
     const int s = rb / per, x = rb % r.bx, y = (rb % per) / r.bx;
     const int g = x * blockDim.x + threadIdx.x;
@@ -615,7 +624,7 @@ hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, 
 {
 #define RZ_CASE(M)                                                                     \
     case M:                                                                            \
-        hipLaunchKernelGGL((k_pass<T, M>), dim3(blocks), dim3(threads), lds, st, a); \
+        RZ_LAUNCH((k_pass<T, M>), dim3(blocks), dim3(threads), lds, st, a); \
         break;
     switch (mode) {
         RZ_CASE(M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS)
@@ -644,11 +653,11 @@ hipError_t launch_collide(int mode, const PassArgs<T> &a, int blocks, int thread
                           hipStream_t st)
 {
     if (mode == (M_FIRST | M_LDS))
-        hipLaunchKernelGGL((k_collide<T, M_FIRST | M_LDS>), dim3(blocks), dim3(threads), lds, st, a);
+        RZ_LAUNCH((k_collide<T, M_FIRST | M_LDS>), dim3(blocks), dim3(threads), lds, st, a);
     else if (mode == M_FIRST)
-        hipLaunchKernelGGL((k_collide<T, M_FIRST>), dim3(blocks), dim3(threads), 0, st, a);
+        RZ_LAUNCH((k_collide<T, M_FIRST>), dim3(blocks), dim3(threads), 0, st, a);
     else if (mode == 0)
-        hipLaunchKernelGGL((k_collide<T, 0>), dim3(blocks), dim3(threads), 0, st, a);
+        RZ_LAUNCH((k_collide<T, 0>), dim3(blocks), dim3(threads), 0, st, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -659,9 +668,9 @@ hipError_t launch_staged(int mode, const PassArgs<T> &a, int cs, hipStream_t st)
 {
     const int blocks = 1024, threads = 256;
     if (mode == M_FIRST)
-        hipLaunchKernelGGL((k_staged<T, M_FIRST>), dim3(blocks), dim3(threads), 0, st, a, cs);
+        RZ_LAUNCH((k_staged<T, M_FIRST>), dim3(blocks), dim3(threads), 0, st, a, cs);
     else if (mode == M_DEP)
-        hipLaunchKernelGGL((k_staged<T, M_DEP>), dim3(blocks), dim3(threads), 0, st, a, cs);
+        RZ_LAUNCH((k_staged<T, M_DEP>), dim3(blocks), dim3(threads), 0, st, a, cs);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -677,7 +686,7 @@ hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t i
     int threads = 256;
     int64_t blocks64 = (n + threads - 1) / threads;
     int blocks = (int)(blocks64 < 65536 ? blocks64 : 65536);
-    hipLaunchKernelGGL((k_init<T>), dim3(blocks), dim3(threads), 0, st, p, n, wcoef, vth, id0, s,
+    RZ_LAUNCH((k_init<T>), dim3(blocks), dim3(threads), 0, st, p, n, wcoef, vth, id0, s,
                        phys);
     return hipGetLastError();
 }
@@ -688,25 +697,23 @@ template <typename T>
 hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, int b0, int b1,
                         int threads, size_t lds, hipStream_t st)
 {
-    if (mode == (M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS))
-        hipLaunchKernelGGL((k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS>),
-                           dim3(b0 + b1), dim3(threads), lds, st, a0, a1, b0);
-    else if (mode == (M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_TILE))
-        hipLaunchKernelGGL((k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_TILE>),
-                           dim3(b0 + b1), dim3(threads), lds, st, a0, a1, b0);
-    else if (mode == (M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS))
-        hipLaunchKernelGGL((k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS>),
-                           dim3(b0 + b1), dim3(threads), 0, st, a0, a1, b0);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    constexpr int kBase = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS;
+    const Pass2Args<T> a{a0, a1, b0};
+    const dim3 grid(b0 + b1), block(threads);
+    if (mode == (kBase | M_LDS))
+        return launch<Pass2Args<T>, pass2_body<T, kBase | M_LDS>, 1024>(grid, block, lds, st, a);
+    if (mode == (kBase | M_TILE))
+        return launch<Pass2Args<T>, pass2_body<T, kBase | M_TILE>, 1024>(grid, block, lds, st, a);
+    if (mode == kBase) return launch<Pass2Args<T>, pass2_body<T, kBase>, 1024>(grid, block, 0, st, a);
+    return hipErrorInvalidValue;
 }
 
 template <typename T> int pass2_tiled_blocks_per_cu(int threads)
 {
+    constexpr int kMode = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_TILE;
     int nb = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, k_pass2<T, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_TILE>, threads,
+        &nb, k_one<Pass2Args<T>, pass2_body<T, kMode>, 1024>, threads,
         (size_t)kWinNodes * sizeof(unsigned long long));
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
@@ -716,9 +723,8 @@ hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0,
                            int threads, const SliceSum &r, hipStream_t st)
 {
     const int nred = r.nb[0] + r.nb[1] > 0 ? 2 * r.bx * r.by : 0;
-    hipLaunchKernelGGL((k_collide2<T, M_FIRST>), dim3(c0 + c1 + nred), dim3(threads), 0, st, a0, a1,
-                       c0, c1, r);
-    return hipGetLastError();
+    return launch<Collide2Args<T>, collide2_body<T, M_FIRST>, 256>(
+        dim3(c0 + c1 + nred), dim3(threads), 0, st, Collide2Args<T>{a0, a1, c0, c1, r});
 }
 
 template int pass2_tiled_blocks_per_cu<double>(int);

@@ -510,7 +510,7 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
     const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
     if (!prepared) {
         int threads = 256, blocks = (c->nn + threads - 1) / threads;
-        hipLaunchKernelGGL(k_prep_solve, dim3(blocks), dim3(threads), 0, c->st, c->nn,
+        RZ_LAUNCH(k_prep_solve, dim3(blocks), dim3(threads), 0, c->st, c->nn,
                            (const double *)c->rho, (const double *)c->chi, c->eps,
                            c->mixed ? c->mg.eps32[c->L] : nullptr, c->f);
         HIPCHK(hipGetLastError());
@@ -806,6 +806,36 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
 }  // namespace
 
 // ===========================================================================
+// Helpers of the batched step (batch.hip).
+
+rzpic_status rz_fail(rzpic_status s, const char *msg) { return fail(s, "%s", msg); }
+
+hipStream_t rz_stream(const rzpic_ctx *c) { return c->st; }
+
+// Whether a context can join a batch: its step must launch kernels only (no
+// synchronisation, no timing events) and both species must be bound.
+int rz_batchable(const rzpic_ctx *c, std::string &why)
+{
+    if (!c->sp[0].bound || !c->sp[1].bound) {
+        why = "both species must be bound";
+        return 0;
+    }
+    if (c->c.mg_fixed_cycles <= 0) {
+        why = "the multigrid must run a fixed number of cycles (mg_fixed_cycles > 0)";
+        return 0;
+    }
+    if (c->timing) {
+        why = "step timing must be off";
+        return 0;
+    }
+    if (c->children_pending[0] || c->children_pending[1]) {
+        why = "new particles are staged: call rzpic_compact first";
+        return 0;
+    }
+    return 1;
+}
+
+// ===========================================================================
 // C ABI
 
 extern "C" {
@@ -1063,7 +1093,7 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
             for (int f = 0; f < 8; ++f) HIPCHK(hipMalloc(&ss.stage[a][f], cap * es));
     }
     if (c->c.sort_every > 0) TRY(sort_alloc(c, s));
-    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, (int64_t)0, (uint64_t)0);
+    RZ_LAUNCH(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, (int64_t)0, (uint64_t)0);
     HIPCHK(hipGetLastError());
     return RZPIC_OK;
 }
@@ -1074,7 +1104,7 @@ rzpic_status rzpic_set_count(rzpic_ctx *c, int32_t s, int64_t n, uint64_t next_i
     if (n < 0 || n > c->sp[s].cap)
         return fail(RZPIC_EINVAL, "count %lld outside [0, capacity %lld]", (long long)n,
                     (long long)c->sp[s].cap);
-    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, n, next_id);
+    RZ_LAUNCH(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, n, next_id);
     HIPCHK(hipGetLastError());
     return RZPIC_OK;
 }
@@ -1167,7 +1197,7 @@ rzpic_status rzpic_init_particles(rzpic_ctx *c, int32_t s, int64_t n, double n0,
         HIPCHK(launch_init<float>(parts_of<float>(c->sp[s].v), n, n0, T_eV, id0, s, ph, c->sp[s].v.m, c->st));
     else
         HIPCHK(launch_init<double>(parts_of<double>(c->sp[s].v), n, n0, T_eV, id0, s, ph, c->sp[s].v.m, c->st));
-    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, n, id0 + (uint64_t)n);
+    RZ_LAUNCH(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, n, id0 + (uint64_t)n);
     HIPCHK(hipGetLastError());
     return RZPIC_OK;
 }

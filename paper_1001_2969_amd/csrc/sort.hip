@@ -289,19 +289,19 @@ template <typename T> hipError_t launch_sort(const SortArgs<T> &a, hipStream_t s
     const int64_t nbk = (M + kScanBlock - 1) / kScanBlock;
     if (nbk > kScanBlock || nbk > 4096) return hipErrorInvalidValue;
     const int blocks = (int)((a.nseg + kSortThreads / 64 - 1) / (kSortThreads / 64));
-    hipLaunchKernelGGL(k_sort_count<T>, dim3(blocks), dim3(kSortThreads),
+    RZ_LAUNCH(k_sort_count<T>, dim3(blocks), dim3(kSortThreads),
                        (size_t)(kSortThreads / 64) * a.nt * sizeof(int32_t), st, a);
-    hipLaunchKernelGGL(k_scan_sum, dim3((unsigned)nbk), dim3(kScanThreads), 0, st, a.off, M,
+    RZ_LAUNCH(k_scan_sum, dim3((unsigned)nbk), dim3(kScanThreads), 0, st, a.off, M,
                        a.part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, a.part, (int)nbk);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nbk), dim3(kScanThreads), 0, st, a.off, M,
+    RZ_LAUNCH(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, a.part, (int)nbk);
+    RZ_LAUNCH(k_scan_apply, dim3((unsigned)nbk), dim3(kScanThreads), 0, st, a.off, M,
                        a.part);
-    hipLaunchKernelGGL(k_sort_scatter<T>, dim3(blocks), dim3(kSortThreads),
+    RZ_LAUNCH(k_sort_scatter<T>, dim3(blocks), dim3(kSortThreads),
                        (size_t)(kSortThreads / 64) * a.nt * sizeof(int64_t), st, a);
     const int64_t span = a.nseg * a.seg;
     const int cblocks = (int)((span + 255) / 256 < 8192 ? (span + 255) / 256 : 8192);
-    hipLaunchKernelGGL(k_sort_copy<T>, dim3(cblocks), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_tile_plan<T>, dim3((a.nb + 255) / 256), dim3(256), 0, st, a);
+    RZ_LAUNCH(k_sort_copy<T>, dim3(cblocks), dim3(256), 0, st, a);
+    RZ_LAUNCH(k_tile_plan<T>, dim3((a.nb + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

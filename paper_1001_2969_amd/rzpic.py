@@ -26,6 +26,7 @@ EXPORTS = (
     "rzpic_collide", "rzpic_compact", "rzpic_resize", "rzpic_prologue", "rzpic_step",
     "rzpic_grid_copy", "rzpic_get_diag", "rzpic_sync", "rzpic_last_error", "rzpic_constants",
     "rzpic_set_timing", "rzpic_get_timing", "rzpic_set_mg", "rzpic_sort",
+    "rzpic_batch_create", "rzpic_batch_step", "rzpic_batch_stats", "rzpic_batch_destroy",
 )
 
 
@@ -98,6 +99,9 @@ def lib():
             "rzpic_get_diag": [P, C.POINTER(Diag)], "rzpic_sync": [P],
             "rzpic_set_timing": [P, I], "rzpic_get_timing": [P, P],
             "rzpic_set_mg": [P, D, I, I],
+            "rzpic_batch_create": [P, I, P, C.POINTER(P)],
+            "rzpic_batch_step": [P, C.c_int64], "rzpic_batch_stats": [P, P],
+            "rzpic_batch_destroy": [P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -305,6 +309,42 @@ class Context:
         keys = ("steps", "step_ms", "solve_ms", "vcycles", "pass_ms", "collide_ms",
                 "grid_ms", "lists_ms", "n0", "n1", "resize_ms", "sort_ms")
         return dict(zip(keys, list(out)))
+
+
+class Batch:
+    """Contexts stepped together (rzpic_batch_*): bitwise the same as stepping
+    each alone, with one launch per kernel for each group of same-shaped
+    discharges."""
+
+    def __init__(self, contexts, stream=None):
+        import torch
+        self.contexts = list(contexts)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = C.c_void_p()
+        _check(lib().rzpic_batch_create(C.cast(arr, C.c_void_p), len(self.contexts),
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def step(self, n):
+        _check(lib().rzpic_batch_step(self.h, n))
+
+    def stats(self):
+        out = (C.c_int32 * 3)()
+        _check(lib().rzpic_batch_stats(self.h, C.cast(out, C.c_void_p)))
+        return {"groups": out[0], "launches": out[1], "batched": out[2]}
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().rzpic_batch_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def make_context(w, *, capacity_factor=1.6, events=False, with_xsec=True, **kw):
