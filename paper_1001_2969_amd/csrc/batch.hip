@@ -12,6 +12,7 @@
 // step, so a batched step equals the separate steps bit for bit.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <string>
 #include <vector>
@@ -57,6 +58,7 @@ struct rzpic_batch {
     void *dev = nullptr;
     size_t dev_cap = 0;
     std::vector<Recorder> rec;
+    int nstreams = kStreams;  // streams the groups are spread over
     int32_t classes = 0, launches = 0, batched = 0;
 };
 
@@ -100,6 +102,10 @@ rzpic_status rzpic_batch_create(rzpic_ctx *const *ctxs, int32_t n, void *stream,
     b->ctx.assign(ctxs, ctxs + n);
     b->st = (hipStream_t)stream;
     b->rec.resize(n);
+    if (const char *e = std::getenv("RZPIC_BATCH_STREAMS")) {
+        const int k = std::atoi(e);
+        if (k >= 1 && k <= kStreams) b->nstreams = k;
+    }
     auto bail = [&](rzpic_status s) {
         rzpic_batch_destroy(b);
         return s;
@@ -256,11 +262,11 @@ rzpic_status rzpic_batch_step(rzpic_batch *b, int64_t step)
         b->which ^= 1;
     }
     BCHK(hipEventRecord(b->fork, b->st), "batch: event");
-    const int nst = (int)std::min<size_t>(groups.size(), kStreams);
+    const int nst = (int)std::min<size_t>(groups.size(), (size_t)b->nstreams);
     for (int k = 0; k < nst; ++k) BCHK(hipStreamWaitEvent(b->streams[k], b->fork, 0), "batch: wait");
     int launches = 0, batched = 0;
     for (size_t g = 0; g < groups.size(); ++g) {
-        hipStream_t gs = b->streams[g % kStreams];
+        hipStream_t gs = b->streams[g % b->nstreams];
         const std::vector<int> &mem = groups[g];
         const Recorder &R0 = b->rec[mem[0]];
         for (size_t p = 0; p < R0.recs.size(); ++p) {

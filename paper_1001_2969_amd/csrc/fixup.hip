@@ -60,7 +60,7 @@ __device__ __forceinline__ int64_t prefix_of(const int32_t *sc, int64_t upto, in
 
 // Superchunk totals: block (sc, 0) sums the children masks of its 512
 // electron chunks, blocks (sc, 1 + s) the dead masks of species s.
-__device__ void scan_body(const Blk &k, const ScanJobs &j)
+__device__ __forceinline__ void scan_body(const Blk &k, const ScanJobs &j)
 {
     __shared__ int sh[64];
     const int job = k.y;
@@ -102,7 +102,7 @@ hipError_t launch_scan(const ScanJobs &j, int64_t max_chunks, hipStream_t st)
 // Sorted dead list of species blockIdx.y: superchunk prefix + the in-block
 // scan of the chunk counts give each chunk's offset; its set lanes follow in
 // increasing order.  Block (0, s) records n, the dead total and the kept count.
-__device__ void dead_list_body(const Blk &k, const ScanJobs &j)
+__device__ __forceinline__ void dead_list_body(const Blk &k, const ScanJobs &j)
 {
     __shared__ int sh[64];
     __shared__ int64_t sh64[16];
@@ -219,7 +219,7 @@ template <typename T> struct Fill2Args {
     const FixRec *fix[2];
 };
 
-template <typename T> __device__ void fill2_body(const Blk &k, const Fill2Args<T> &a)
+template <typename T> __device__ __forceinline__ void fill2_body(const Blk &k, const Fill2Args<T> &a)
 {
     fill_body<T>(k, a.p[k.y], a.dead[k.y], a.fix[k.y]);
 }
@@ -252,7 +252,7 @@ template <typename T> struct AppendJob {
     AppendArgs<T> g;
 };
 
-template <typename T> __device__ void append_body(const Blk &kb, const AppendJob<T> &aj)
+template <typename T> __device__ __forceinline__ void append_body(const Blk &kb, const AppendJob<T> &aj)
 {
     __shared__ int sh[64];
     __shared__ int64_t sh64[16];

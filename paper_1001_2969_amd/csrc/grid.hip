@@ -34,7 +34,7 @@ struct k_efield_A {
 };
 
 template <typename T>
-__device__ void k_efield_body(const Blk &kb_, const k_efield_A<T> &A_)
+__device__ __forceinline__ void k_efield_body(const Blk &kb_, const k_efield_A<T> &A_)
 {
     auto nr = A_.nr;
     auto nz = A_.nz;

@@ -35,8 +35,10 @@ __global__ __launch_bounds__(MT) void k_one(A a)
     Body(Blk{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y}, a);
 }
 
+// The job table is read-only for the whole launch (__restrict__): the body's
+// argument fields are loaded once and kept, as kernel arguments would be.
 template <typename A, void (*Body)(const Blk &, const A &), int MT>
-__global__ __launch_bounds__(MT) void k_many(const Job<A> *jobs, int nj)
+__global__ __launch_bounds__(MT) void k_many(const Job<A> *__restrict__ jobs, int nj)
 {
     // the job holding this block: the last one starting at or before it
     int lo = 0, hi = nj - 1;

@@ -162,7 +162,7 @@ struct k_finalize_mg_A {
     int nclear;
 };
 
-__device__ void k_finalize_mg_body(const Blk &kb_, const k_finalize_mg_A &A_)
+__device__ __forceinline__ void k_finalize_mg_body(const Blk &kb_, const k_finalize_mg_A &A_)
 {
     const auto &g = A_.g;
     const auto &m = A_.m;
@@ -251,7 +251,7 @@ struct k_line_A {
 };
 
 template <typename T>
-__device__ void k_line_body(const Blk &kb_, const k_line_A<T> &A_)
+__device__ __forceinline__ void k_line_body(const Blk &kb_, const k_line_A<T> &A_)
 {
     const auto &p = A_.p;
 
@@ -461,7 +461,7 @@ struct k_add_corr_A {
     int nz;
 };
 
-__device__ void k_add_corr_body(const Blk &kb_, const k_add_corr_A &A_)
+__device__ __forceinline__ void k_add_corr_body(const Blk &kb_, const k_add_corr_A &A_)
 {
     auto phi = A_.phi;
     auto u = A_.u;
@@ -561,7 +561,7 @@ struct k_down_A {
 };
 
 template <typename T>
-__device__ void k_down_body(const Blk &kb_, const k_down_A<T> &A_)
+__device__ __forceinline__ void k_down_body(const Blk &kb_, const k_down_A<T> &A_)
 {
     auto u = A_.u;
     auto f = A_.f;
@@ -716,7 +716,7 @@ struct k_bottom_A {
 };
 
 template <typename T, int EPT>
-__device__ void k_bottom_body(const Blk &kb_, const k_bottom_A<T, EPT> &A_)
+__device__ __forceinline__ void k_bottom_body(const Blk &kb_, const k_bottom_A<T, EPT> &A_)
 {
     const auto &m = A_.m;
     auto mixed = A_.mixed;
@@ -810,7 +810,7 @@ struct k_level_A {
 };
 
 template <typename T, int EPT>
-__device__ void k_level_body(const Blk &kb_, const k_level_A<T, EPT> &A_)
+__device__ __forceinline__ void k_level_body(const Blk &kb_, const k_level_A<T, EPT> &A_)
 {
     const auto &p = A_.p;
 
@@ -1001,7 +1001,7 @@ struct k_factor_A {
 };
 
 template <typename T>
-__device__ void k_factor_body(const Blk &kb_, const k_factor_A<T> &A_)
+__device__ __forceinline__ void k_factor_body(const Blk &kb_, const k_factor_A<T> &A_)
 {
     const auto &m = A_.m;
     auto mixed = A_.mixed;
@@ -1024,7 +1024,7 @@ struct k_prep_A {
 };
 
 template <typename T>
-__device__ void k_prep_body(const Blk &kb_, const k_prep_A<T> &A_)
+__device__ __forceinline__ void k_prep_body(const Blk &kb_, const k_prep_A<T> &A_)
 {
     auto u = A_.u;
     auto f = A_.f;
@@ -1164,7 +1164,7 @@ struct k_solve_A {
 };
 
 template <typename T, int Q>
-__device__ void k_solve_body(const Blk &kb_, const k_solve_A<T, Q> &A_)
+__device__ __forceinline__ void k_solve_body(const Blk &kb_, const k_solve_A<T, Q> &A_)
 {
     const auto &m = A_.m;
     auto mixed = A_.mixed;
@@ -1413,7 +1413,7 @@ struct k_fine_A {
 };
 
 template <typename T, int Q>
-__device__ void k_fine_body(const Blk &kb_, const k_fine_A<T, Q> &A_)
+__device__ __forceinline__ void k_fine_body(const Blk &kb_, const k_fine_A<T, Q> &A_)
 {
     const auto &m = A_.m;
     auto mixed = A_.mixed;

@@ -383,7 +383,7 @@ template <typename T> struct Pass2Args {
     int b0;
 };
 
-template <typename T, int MODE> __device__ void pass2_body(const Blk &k, const Pass2Args<T> &a)
+template <typename T, int MODE> __device__ __forceinline__ void pass2_body(const Blk &k, const Pass2Args<T> &a)
 {
     if (k.x < a.b0) pass_body<T, MODE>(a.a0, k.x, a.b0);
     else pass_body<T, MODE>(a.a1, k.x - a.b0, k.nx - a.b0);
@@ -534,7 +534,7 @@ template <typename T> struct Collide2Args {
     SliceSum r;
 };
 
-template <typename T, int MODE> __device__ void collide2_body(const Blk &k, const Collide2Args<T> &a)
+template <typename T, int MODE> __device__ __forceinline__ void collide2_body(const Blk &k, const Collide2Args<T> &a)
 {
     const int b = k.x, c0 = a.c0, c1 = a.c1;
     if (b < c0) {

@@ -282,16 +282,24 @@ template <typename T> PassArgs<T> pass_args(rzpic_ctx *c, int s, uint32_t step)
     return a;
 }
 
-// Blocks of the tiled pass of species s: the blocks the merged pass keeps
-// resident at once, shared by the two species (one round, no tail), fewer
-// for small capacities.  The window plan of the sort is made for this count.
+// Pass blocks of species s, at most `most`: about one per kPartsPerBlock
+// particles of capacity, since every block of a deposit form pays a fixed
+// cost (zeroing and writing out its LDS grid or window) that only pays off
+// over enough particles.
+constexpr int64_t kPartsPerBlock = 8192;
+int pass_blocks(const rzpic_ctx *c, int s, int most)
+{
+    const int64_t want = (c->sp[s].cap + kPartsPerBlock - 1) / kPartsPerBlock;
+    if (most < 1) most = 1;
+    return (int)(want < 1 ? 1 : (want < most ? want : most));
+}
+
+// Blocks of the tiled pass of species s: at most the blocks the merged pass
+// keeps resident at once, shared by the two species (one round, no tail).
+// The window plan of the sort is made for this count.
 int tiled_blocks(const rzpic_ctx *c, int s)
 {
-    const int threads = c->pass_threads;
-    const int64_t need = (c->sp[s].cap + threads - 1) / threads;
-    int bl = c->cus * c->tile_per_cu / 2;
-    if (bl < 1) bl = 1;
-    return (int)(need < bl ? (need > 0 ? need : 1) : bl);
+    return pass_blocks(c, s, c->cus * c->tile_per_cu / 2);
 }
 
 rzpic_status need_species(rzpic_ctx *c, int s)
@@ -337,7 +345,7 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
     if ((mode & M_DEP) && c->lds_ok) {
         mode |= M_LDS;
         lds = (size_t)c->nn * sizeof(unsigned long long);
-        blocks = c->slice_blocks;
+        blocks = pass_blocks(c, s, c->slice_blocks);
     } else if ((mode & M_DEP) && !(mode & M_MC)) {
         mode |= M_TILE;
         lds = (size_t)kWinNodes * sizeof(unsigned long long);
@@ -396,8 +404,8 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
     if (c->lds_ok) {
         mode |= M_LDS;
         lds = (size_t)c->nn * sizeof(unsigned long long);
-        b[0] = c->slice_blocks / 2;
-        b[1] = c->slice_blocks - b[0];
+        b[0] = pass_blocks(c, 0, c->slice_blocks / 2);
+        b[1] = pass_blocks(c, 1, c->slice_blocks - c->slice_blocks / 2);
     } else {
         // grid larger than LDS: contiguous block ranges with LDS windows of
         // the tiles planned at the last sort (global atomics without a plan)

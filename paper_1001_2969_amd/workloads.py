@@ -109,6 +109,23 @@ def large_513x129() -> Workload:
                     xsec="powerlaw")
 
 
+def batch_64(seed: int = 0, n: int = 64):
+    """n independent discharges of uneven size: meshes drawn from 65x33,
+    129x65 and 257x129 (square 0.3125 mm cells: R x L = 2 x 1, 4 x 2, 8 x 4
+    cm), particles per species log-uniform in [1e5, 2e6], 200 V rf drive, 3
+    V-cycles per step, mixed precision, tile sort every 20 steps; seeded."""
+    rng = np.random.default_rng(seed)
+    shapes = ((65, 33, 0.02, 0.01), (129, 65, 0.04, 0.02), (257, 129, 0.08, 0.04))
+    out = []
+    for k in range(n):
+        nr, nz, R, L = shapes[int(rng.integers(0, len(shapes)))]
+        npart = int(round(math.exp(rng.uniform(math.log(1e5), math.log(2e6)))))
+        out.append(Workload(name=f"batch{k}_{nr}x{nz}_{npart}", nr=nr, nz=nz, R=R, L=L,
+                            n_per_species=npart, steps=100, V_rf=200.0, mg_fixed_cycles=3,
+                            sort_every=20, seed=seed * 1000 + k, precision="mixed"))
+    return out
+
+
 def xsec_tables(w: Workload):
     """Synthetic tables on eps_k = k * XSEC_DE.
 
