@@ -260,6 +260,71 @@ def large_mesh(steps, warmup):
     return out
 
 
+def batch_run(steps, warmup):
+    """64 independent discharges (meshes 65x33 / 129x65 / 257x129, 1e5-2e6
+    particles per species, log-uniform, seeded; 94M particles in all), mixed
+    and FP64: the same contexts stepped one by one on the stream and then as
+    one batch (rzpic_batch_step, graph replay on); particle-steps/s of both.
+    The timed steps include the tile sorts (every 20 steps)."""
+    import torch
+
+    from paper_1001_2969_amd import rzpic, workloads as wl
+
+    ws = wl.batch_64()
+    out = {"discharges": len(ws), "particles": 2 * sum(w.n_per_species for w in ws),
+           "meshes": sorted({f"{w.nr}x{w.nz}" for w in ws})}
+    for prec in ("mixed", "fp64"):
+        ctxs = []
+        for w in ws:
+            c = rzpic.make_context(w, precision=prec, capacity_factor=1.3)
+            c.init_particles(0, w.n_per_species, w.n0, w.Te_eV, 0)
+            c.init_particles(1, w.n_per_species, w.n0, w.Ti_eV, 0)
+            c.prologue()
+            for s in (0, 1):
+                c.sort(s)
+            ctxs.append(c)
+
+        def psteps():
+            return sum(sum(c.diag()["particle_steps"]) for c in ctxs)
+
+        n = 0
+        for _ in range(warmup):
+            for c in ctxs:
+                c.step(n)
+            n += 1
+        torch.cuda.synchronize()
+        p0, t0 = psteps(), time.perf_counter()
+        for _ in range(steps):
+            for c in ctxs:
+                c.step(n)
+            n += 1
+        torch.cuda.synchronize()
+        t_seq, p_seq = time.perf_counter() - t0, psteps() - p0
+        b = rzpic.Batch(ctxs, stream=torch.cuda.Stream())
+        b.set_graph(True)  # steps replayed from captured graphs
+        for _ in range(warmup):
+            b.step(n)
+            n += 1
+        torch.cuda.synchronize()
+        p0, t0 = psteps(), time.perf_counter()
+        for _ in range(steps):
+            b.step(n)
+            n += 1
+        torch.cuda.synchronize()
+        t_b, p_b = time.perf_counter() - t0, psteps() - p0
+        out[prec] = {"batched_value": p_b / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
+                     "one_by_one_value": p_seq / t_seq,
+                     "one_by_one_ms_per_step": 1e3 * t_seq / steps,
+                     "speedup": (p_b / t_b) / (p_seq / t_seq), "launches": b.stats()}
+        b.close()
+        for c in ctxs:
+            c.close()
+        del ctxs
+        torch.cuda.empty_cache()
+    out["mixed_over_fp64_batched"] = out["mixed"]["batched_value"] / out["fp64"]["batched_value"]
+    return out
+
+
 def pmc_run(steps, workload):
     """Short run for hardware-counter passes: a few merged steps of the mixed
     workload, then a plain device copy of known size (the calibration of the
@@ -298,6 +363,9 @@ def main():
     ap.add_argument("--large-steps", type=int, default=60)
     ap.add_argument("--no-vcycle-meshes", action="store_true",
                     help="skip the V-cycle timing on every mesh and the synthetic grid")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-discharge batch measurement")
+    ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
                     help="only a short mixed run plus a copy calibration (for counter passes)")
     ap.add_argument("--pmc-workload", default="rf_129x65", choices=["rf_129x65", "large_513x129"])
@@ -339,6 +407,10 @@ def main():
         print(f"# V-cycle study: {json.dumps(vstudy)}", file=sys.stderr, flush=True)
     ctx_m.close()
     vmesh = None if args.no_vcycle_meshes else vcycle_by_mesh()
+    batch = None
+    if not args.no_batch:
+        batch = batch_run(args.batch_steps, 3)
+        print(f"# batch: {json.dumps(batch)}", file=sys.stderr, flush=True)
     large = None
     if not args.no_large:
         large = large_mesh(args.large_steps, 5)
@@ -392,6 +464,7 @@ def main():
         "fixed_phi_err": vstudy,
         "large_mesh": large,
         "vcycle_by_mesh": vmesh,
+        "batch_64": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -254,6 +254,13 @@ typedef struct rzpic_batch rzpic_batch;
 rzpic_status rzpic_batch_create(rzpic_ctx *const *ctxs, int32_t n, void *stream,
                                 rzpic_batch **out);
 rzpic_status rzpic_batch_step(rzpic_batch *batch, int64_t step);
+/* Replay steps from a captured HIP graph (off by default): a step whose
+ * launches are all batched is captured (job-table upload, fork, launches,
+ * join) the first time its layout occurs for each of the two staging
+ * buffers, and later such steps relaunch that graph after writing their job
+ * tables; other steps (tile sort, weight split) launch directly.  Needs a
+ * non-null batch stream (EINVAL). */
+rzpic_status rzpic_batch_set_graph(rzpic_batch *batch, int32_t on);
 /* out[0] groups, out[1] launches and out[2] of them batched, last step. */
 rzpic_status rzpic_batch_stats(rzpic_batch *batch, int32_t out[3]);
 rzpic_status rzpic_batch_destroy(rzpic_batch *batch);

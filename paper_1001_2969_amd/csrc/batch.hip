@@ -44,6 +44,9 @@ struct Staging {
     size_t cap = 0;
     hipEvent_t done = nullptr;  // the upload that last read it
     bool used = false;
+    // captured step reading this buffer, and the layout it was captured for
+    hipGraphExec_t exec = nullptr;
+    std::vector<size_t> layout;
 };
 
 }  // namespace
@@ -59,6 +62,7 @@ struct rzpic_batch {
     size_t dev_cap = 0;
     std::vector<Recorder> rec;
     int nstreams = kStreams;  // streams the groups are spread over
+    bool graph = false;       // replay captured steps
     int32_t classes = 0, launches = 0, batched = 0;
 };
 
@@ -138,6 +142,7 @@ rzpic_status rzpic_batch_destroy(rzpic_batch *b)
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->ctx_ev) (void)hipEventDestroy(b->ctx_ev);
     for (auto &s : b->stage) {
+        if (s.exec) (void)hipGraphExecDestroy(s.exec);
         if (s.done) (void)hipEventDestroy(s.done);
         if (s.host) (void)hipHostFree(s.host);
     }
@@ -206,6 +211,8 @@ rzpic_status rzpic_batch_step(rzpic_batch *b, int64_t step)
     if (total > 0) {
         if (S.used) BCHK(hipEventSynchronize(S.done), "batch: staging reuse");
         if (total > S.cap) {
+            if (S.exec) BCHK(hipGraphExecDestroy(S.exec), "batch: graph free");
+            S.exec = nullptr;
             if (S.host) BCHK(hipHostFree(S.host), "batch: staging free");
             S.host = nullptr;
             S.cap = 0;
@@ -215,6 +222,10 @@ rzpic_status rzpic_batch_step(rzpic_batch *b, int64_t step)
         if (total > b->dev_cap) {
             // earlier steps may still read the old table
             BCHK(hipStreamSynchronize(b->st), "batch: table reallocation");
+            for (auto &t : b->stage) {
+                if (t.exec) BCHK(hipGraphExecDestroy(t.exec), "batch: graph free");
+                t.exec = nullptr;
+            }
             if (b->dev) BCHK(hipFree(b->dev), "batch: table free");
             b->dev = nullptr;
             b->dev_cap = 0;
@@ -255,42 +266,101 @@ rzpic_status rzpic_batch_step(rzpic_batch *b, int64_t step)
             BCHK(hipStreamWaitEvent(b->st, b->ctx_ev, 0), "batch: wait");
         }
     }
-    if (total > 0) {
-        BCHK(hipMemcpyAsync(b->dev, S.host, total, hipMemcpyHostToDevice, b->st), "batch: upload");
-        BCHK(hipEventRecord(S.done, b->st), "batch: event");
-        S.used = true;
-        b->which ^= 1;
-    }
-    BCHK(hipEventRecord(b->fork, b->st), "batch: event");
-    const int nst = (int)std::min<size_t>(groups.size(), (size_t)b->nstreams);
-    for (int k = 0; k < nst; ++k) BCHK(hipStreamWaitEvent(b->streams[k], b->fork, 0), "batch: wait");
+    // the step's device work: upload, fork, every group's launches, join
     int launches = 0, batched = 0;
-    for (size_t g = 0; g < groups.size(); ++g) {
-        hipStream_t gs = b->streams[g % b->nstreams];
-        const std::vector<int> &mem = groups[g];
-        const Recorder &R0 = b->rec[mem[0]];
-        for (size_t p = 0; p < R0.recs.size(); ++p) {
-            const LaunchRec &L0 = R0.recs[p];
-            if (L0.many) {
-                size_t lds = 0;
-                for (int i : mem) lds = std::max(lds, b->rec[i].recs[p].lds);
-                BCHK(L0.many((const unsigned char *)b->dev + tables[g][p].off, (int)mem.size(),
-                             tables[g][p].blocks, L0.threads, lds, gs),
-                     "batch: launch");
-                ++launches;
-                ++batched;
-            } else {
-                for (int i : mem) {
-                    b->rec[i].recs[p].raw(gs);
-                    BCHK(hipGetLastError(), "batch: launch");
+    const int nst = (int)std::min<size_t>(groups.size(), (size_t)b->nstreams);
+    auto enqueue = [&]() -> rzpic_status {
+        launches = batched = 0;
+        if (total > 0)
+            BCHK(hipMemcpyAsync(b->dev, S.host, total, hipMemcpyHostToDevice, b->st),
+                 "batch: upload");
+        BCHK(hipEventRecord(b->fork, b->st), "batch: event");
+        for (int k = 0; k < nst; ++k)
+            BCHK(hipStreamWaitEvent(b->streams[k], b->fork, 0), "batch: wait");
+        for (size_t g = 0; g < groups.size(); ++g) {
+            hipStream_t gs = b->streams[g % b->nstreams];
+            const std::vector<int> &mem = groups[g];
+            const Recorder &R0 = b->rec[mem[0]];
+            for (size_t p = 0; p < R0.recs.size(); ++p) {
+                const LaunchRec &L0 = R0.recs[p];
+                if (L0.many) {
+                    size_t lds = 0;
+                    for (int i : mem) lds = std::max(lds, b->rec[i].recs[p].lds);
+                    BCHK(L0.many((const unsigned char *)b->dev + tables[g][p].off, (int)mem.size(),
+                                 tables[g][p].blocks, L0.threads, lds, gs),
+                         "batch: launch");
                     ++launches;
+                    ++batched;
+                } else {
+                    for (int i : mem) {
+                        b->rec[i].recs[p].raw(gs);
+                        BCHK(hipGetLastError(), "batch: launch");
+                        ++launches;
+                    }
                 }
             }
         }
+        for (int k = 0; k < nst; ++k) {
+            BCHK(hipEventRecord(b->join[k], b->streams[k]), "batch: event");
+            BCHK(hipStreamWaitEvent(b->st, b->join[k], 0), "batch: wait");
+        }
+        return RZPIC_OK;
+    };
+    // A step whose launches are all batched can be replayed from a capture:
+    // only the job tables (uploaded from the staging buffer) change between
+    // such steps, as long as the groups, kernels, shapes and table layout do.
+    bool all_batched = true;
+    std::vector<size_t> layout;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        layout.push_back(groups[g].size());
+        for (int i : groups[g]) layout.push_back((size_t)i);
+        const Recorder &R0 = b->rec[groups[g][0]];
+        for (size_t p = 0; p < R0.recs.size(); ++p) {
+            const LaunchRec &L0 = R0.recs[p];
+            all_batched = all_batched && L0.many != nullptr;
+            size_t lds = 0;
+            for (int i : groups[g]) lds = std::max(lds, b->rec[i].recs[p].lds);
+            layout.insert(layout.end(), {(size_t)L0.key, L0.threads, lds, tables[g][p].off,
+                                         (size_t)tables[g][p].blocks});
+        }
     }
-    for (int k = 0; k < nst; ++k) {
-        BCHK(hipEventRecord(b->join[k], b->streams[k]), "batch: event");
-        BCHK(hipStreamWaitEvent(b->st, b->join[k], 0), "batch: wait");
+    layout.push_back(total);
+    int nl = 0, nb = 0;  // launches of the step, batched ones
+    for (size_t g = 0; g < groups.size(); ++g)
+        for (const LaunchRec &L0 : b->rec[groups[g][0]].recs) {
+            nl += L0.many ? 1 : (int)groups[g].size();
+            nb += L0.many ? 1 : 0;
+        }
+    if (b->graph && all_batched && b->st) {
+        if (!S.exec || S.layout != layout) {
+            if (S.exec) BCHK(hipGraphExecDestroy(S.exec), "batch: graph free");
+            S.exec = nullptr;
+            hipGraph_t gr = nullptr;
+            BCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal), "batch: capture");
+            const rzpic_status es = enqueue();
+            const hipError_t ce = hipStreamEndCapture(b->st, &gr);
+            if (es != RZPIC_OK) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return es;
+            }
+            if (ce != hipSuccess) return hipfail(ce, "batch: capture");
+            const hipError_t ie = hipGraphInstantiate(&S.exec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (ie != hipSuccess) {
+                S.exec = nullptr;
+                return hipfail(ie, "batch: graph instantiation");
+            }
+            S.layout = layout;
+        }
+        BCHK(hipGraphLaunch(S.exec, b->st), "batch: graph launch");
+    } else {
+        const rzpic_status es = enqueue();
+        if (es != RZPIC_OK) return es;
+    }
+    if (total > 0) {
+        BCHK(hipEventRecord(S.done, b->st), "batch: event");
+        S.used = true;
+        b->which ^= 1;
     }
     // the contexts' streams continue after the batch
     BCHK(hipEventRecord(b->ctx_ev, b->st), "batch: event");
@@ -304,8 +374,19 @@ rzpic_status rzpic_batch_step(rzpic_batch *b, int64_t step)
         }
     }
     b->classes = (int32_t)groups.size();
-    b->launches = launches;
-    b->batched = batched;
+    b->launches = nl;
+    b->batched = nb;
+    (void)launches;
+    (void)batched;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_batch_set_graph(rzpic_batch *b, int32_t on)
+{
+    if (!b) return rz_fail(RZPIC_EINVAL, "null batch");
+    if (on && !b->st)
+        return rz_fail(RZPIC_EINVAL, "batch: graph replay needs a stream other than the null stream");
+    b->graph = on != 0;
     return RZPIC_OK;
 }
 

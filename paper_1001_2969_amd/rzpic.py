@@ -27,6 +27,7 @@ EXPORTS = (
     "rzpic_grid_copy", "rzpic_get_diag", "rzpic_sync", "rzpic_last_error", "rzpic_constants",
     "rzpic_set_timing", "rzpic_get_timing", "rzpic_set_mg", "rzpic_sort",
     "rzpic_batch_create", "rzpic_batch_step", "rzpic_batch_stats", "rzpic_batch_destroy",
+    "rzpic_batch_set_graph",
 )
 
 
@@ -101,7 +102,7 @@ def lib():
             "rzpic_set_mg": [P, D, I, I],
             "rzpic_batch_create": [P, I, P, C.POINTER(P)],
             "rzpic_batch_step": [P, C.c_int64], "rzpic_batch_stats": [P, P],
-            "rzpic_batch_destroy": [P],
+            "rzpic_batch_destroy": [P], "rzpic_batch_set_graph": [P, I],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -328,6 +329,9 @@ class Batch:
 
     def step(self, n):
         _check(lib().rzpic_batch_step(self.h, n))
+
+    def set_graph(self, on=True):
+        _check(lib().rzpic_batch_set_graph(self.h, 1 if on else 0))
 
     def stats(self):
         out = (C.c_int32 * 3)()
