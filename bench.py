@@ -422,7 +422,8 @@ def main():
     t_launch_ms = tm["pass_ms"]
     bpp = BYTES_PER_PARTICLE["mixed"]
     achieved = bpp * n_launch / (t_launch_ms * 1e-3) / 1e9 if t_launch_ms > 0 else None
-    roofline = {"kernel": "k_pass2<float, fused, LDS deposit>", "bound": "hbm",
+    roofline = {"kernel": "k_one<pass2_body<float, 111>> (fused pass, whole-grid LDS deposit)",
+                "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None,
                 "traffic": None,
