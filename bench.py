@@ -372,7 +372,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU form is not part of this build.", file=sys.stderr)
+              "multi-GPU form is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
