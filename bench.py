@@ -325,6 +325,48 @@ def batch_run(steps, warmup):
     return out
 
 
+def adjoint_run(reps=2):
+    """The gradient window: 257x129 mesh, 4M particles per species, 50
+    collision-free FP64 steps with converged solves, checkpointed every 10.
+    Wall time of the forward window (the steps plus the objective) and of the
+    backward pass (segment recompute, reverse particle passes, adjoint
+    solves), the last of `reps` repetitions; the context steps on from each
+    window's end."""
+    import torch
+
+    from paper_1001_2969_amd import rzpic, workloads as wl
+
+    w = wl.adjoint_257x129()
+    ctx = rzpic.make_context(w, precision="fp64", with_xsec=False, capacity_factor=1.25)
+    for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
+        ctx.init_particles(s, w.n_per_species, w.n0, T, 0)
+    ctx.prologue()
+    adj = rzpic.Adjoint(ctx, w.steps, checkpoint_every=10, delta=2 * w.L / (w.nz - 1))
+    out = {"workload": w.name, "mesh": f"{w.nr}x{w.nz}", "particles_per_species": w.n_per_species,
+           "window_steps": w.steps, "checkpoint_every": 10, "mg_tol": w.mg_tol}
+    step0 = 0
+    for _ in range(reps):
+        p0 = sum(ctx.diag()["particle_steps"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = adj.forward(step0)
+        t1 = time.perf_counter()
+        p1 = sum(ctx.diag()["particle_steps"])
+        dvdc, dvrf, _, _ = adj.backward(density=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        step0 += w.steps
+        out.update({"J": J, "dJ_dV_rf": dvrf, "dJ_dV_dc": dvdc,
+                    "forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1),
+                    "gradient_ms": 1e3 * (t2 - t0),
+                    "backward_over_forward": (t2 - t1) / (t1 - t0),
+                    "forward_particle_steps_per_s": (p1 - p0) / (t1 - t0)})
+    adj.close()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def pmc_run(steps, workload):
     """Short run for hardware-counter passes: a few merged steps of the mixed
     workload, then a plain device copy of known size (the calibration of the
@@ -366,6 +408,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-discharge batch measurement")
     ap.add_argument("--batch-steps", type=int, default=40)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the 257x129 / 4M-per-species gradient window")
     ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
                     help="only a short mixed run plus a copy calibration (for counter passes)")
     ap.add_argument("--pmc-workload", default="rf_129x65", choices=["rf_129x65", "large_513x129"])
@@ -411,6 +455,10 @@ def main():
     if not args.no_batch:
         batch = batch_run(args.batch_steps, 3)
         print(f"# batch: {json.dumps(batch)}", file=sys.stderr, flush=True)
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_run()
+        print(f"# adjoint: {json.dumps(adjoint)}", file=sys.stderr, flush=True)
     large = None
     if not args.no_large:
         large = large_mesh(args.large_steps, 5)
@@ -466,6 +514,7 @@ def main():
         "large_mesh": large,
         "vcycle_by_mesh": vmesh,
         "batch_64": batch,
+        "adjoint_window": adjoint,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -265,6 +265,56 @@ rzpic_status rzpic_batch_set_graph(rzpic_batch *batch, int32_t on);
 rzpic_status rzpic_batch_stats(rzpic_batch *batch, int32_t out[3]);
 rzpic_status rzpic_batch_destroy(rzpic_batch *batch);
 
+/* Change the z = 0 electrode voltage V_dc + V_rf sin(2 pi f_rf t) of later
+ * solves (config fields of the same names; finite values, else EINVAL). */
+rzpic_status rzpic_set_voltage(rzpic_ctx *ctx, double V_dc, double V_rf, double f_rf);
+
+/* --- adjoint of a collision-free window ---------------------------------- */
+/* Reverse-mode gradient, over a window of N merged steps (Sec. 2.1) without
+ * collisions or weight splits, of the smooth ion-flux objective
+ *   J = sum_{n < N} sum_{live ions p after step n} (q_i dt / delta) w_p (-v_z,p) exp(-z_p / delta),
+ * with respect to the electrode voltage parameters V_dc and V_rf and to the
+ * weights the particles have when the window starts.  The gradient is that of
+ * the exactly solved field equation: the context must run converged solves
+ * (mg_fixed_cycles = 0; the adjoint solves use the same multigrid to `tol`),
+ * FP64, averaged face permittivities (chi_face = RZPIC_FACE_AVG),
+ * resize_every = 0, and both species bound with mc_model = RZPIC_MC_NONE.
+ * Particles absorbed in the window contribute up to their absorption; the
+ * set of absorbed particles is held fixed (the objective is not
+ * differentiable where a particle meets a wall).  Memory: ceil(N/K) + 1
+ * checkpoints and K per-step copies of both species' arrays (sized by their
+ * capacities), 8 doubles per identity of each species, and grids. */
+typedef struct rzpic_adjoint_config {
+    int32_t n_steps;          /* N >= 1                                        */
+    int32_t checkpoint_every; /* K: state kept every K steps (0 -> 10)         */
+    int64_t id_capacity[2];   /* identities of species s lie in [0, id_capacity[s]) */
+    double delta;             /* objective layer thickness, m (0 -> 2 hz)      */
+    double tol;               /* adjoint solves' relative residual (0 -> mg_tol) */
+    int32_t max_cycles;       /* cap on their V-cycles (0 -> mg_max_cycles)    */
+    int32_t reserved;
+} rzpic_adjoint_config;
+typedef struct rzpic_adjoint rzpic_adjoint;
+/* Allocate the window's workspace for `ctx` (which must outlive it). */
+rzpic_status rzpic_adjoint_create(rzpic_ctx *ctx, const rzpic_adjoint_config *cfg,
+                                  rzpic_adjoint **out);
+/* Run steps step0 .. step0+N-1 on the context (as rzpic_step), keeping the
+ * checkpoints; *J (host) receives the objective.  Synchronises. */
+rzpic_status rzpic_adjoint_forward(rzpic_adjoint *adj, int64_t step0, double *J);
+/* Gradient of the last forward window: grad_V (host) = {dJ/dV_dc, dJ/dV_rf};
+ * grad_w0 / grad_w1 (device, id_capacity[s] doubles, may be NULL) receive
+ * dJ/dw by particle identity (0 for identities not present); grad_density
+ * (device, nz*nr doubles, may be NULL) the gradient with respect to a
+ * relative perturbation psi of the initial density field on the nodes, the
+ * weights of both species at the window start becoming
+ * w_p (1 + sum_k S_k(x_p) psi_k) with the Sec. 2.4 weights S_k at the
+ * particle's position: sum_p (dJ/dw_p) w_p S_k(x_p).  Recomputes the
+ * window segment by segment and leaves the context in its state at the end
+ * of the window.  EINVAL if a particle identity is >= id_capacity.
+ * Synchronises. */
+rzpic_status rzpic_adjoint_backward(rzpic_adjoint *adj, double grad_V[2], double *grad_w0,
+                                    double *grad_w1, double *grad_density);
+rzpic_status rzpic_adjoint_destroy(rzpic_adjoint *adj);
+
 #ifdef __cplusplus
 }
 #endif

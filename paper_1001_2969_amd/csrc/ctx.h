@@ -1,0 +1,93 @@
+// Context state shared by the host sources of the library (the C ABI in
+// runtime.hip, the batched step, the adjoint window).
+#pragma once
+
+#include "rzpic.h"
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace rz {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct SpeciesState {
+    bool bound = false;
+    rzpic_species_view v{};
+    int64_t cap = 0;
+    Chunks ch{};
+    int64_t nchunks_max = 0;
+    // staging of the new particles of ionizations (electron species only):
+    // [0] new electrons, [1] new ions, slots indexed like electron particles
+    void *stage[2][8] = {};
+    bool has_xsec = false;
+    Xsec xs{};
+    double nu_max = 0.0, p_null = 0.0;
+    DevBuf sigma;
+    // tile sort: sorted-copy staging (8 real arrays + identities), per-segment
+    // tile counts/offsets, scan partials, and the window plan of the pass
+    void *sort_buf[9] = {};
+    int64_t *sort_off = nullptr, *sort_part = nullptr, *tile_pb = nullptr;
+    int4 *tile_win = nullptr;
+    int64_t sort_seg = 0, sort_nseg = 0;
+    int tile_nb = 0;  // pass blocks the plan is made for
+};
+
+}  // namespace rz
+
+struct rzpic_ctx {
+    rzpic_config c{};
+    hipStream_t st = nullptr;
+    int device = 0, cus = 0;
+    size_t lds_block = 0, lds_cu = 0;
+    int mixed = 0;
+    int pass_threads = 512;
+    int tile_per_cu = 1;  // resident blocks per CU of the tiled merged pass
+    double hr = 0, hz = 0;
+    int L = 0;
+    int nn = 0;
+    double quantum[2] = {1.0, 1.0};
+    std::vector<void *> allocs;
+    int ntr = 1, nt = 1, kbits = 0;  // tiles in r, tiles, bits of a tile key
+
+    // grids
+    double *phi, *rho, *chi, *er, *ez, *dens[2], *vol, *f, *eps;
+    double *phi_alt;  // FP64 cycles sweep the finest level from one phi buffer into the other
+    void *E2;
+    unsigned long long *acc[2];
+    unsigned long long *slices = nullptr;
+    int slice_blocks = 0;
+    bool lds_ok = false;
+    rz::MgLevels mg{};
+    // device scalars
+    rz::Counts *cnt;
+    rz::FixRec *fix;
+    rz::ChildRec *crec;
+    rz::CloneRec *clrec;
+    unsigned long long *tally;   // [2][3]
+    unsigned long long *mcstat;  // [2][1 + kMaxProc]
+    unsigned long long *norm;    // [2]
+    int32_t *status;
+    // host-side bookkeeping
+    rz::SpeciesState sp[2];
+    bool children_pending[2] = {false, false};  // staged children not yet appended
+    bool children_scanned = false;
+    int last_cycles = 0;
+    double last_relres = 0.0;
+    unsigned long long *psteps;  // [2]
+    // timing: per recorded step 10 events (see mark())
+    bool timing = false;
+    static constexpr int kEvPerStep = 10, kPool = 128;
+    std::vector<hipEvent_t> evpool;
+    int ev_used = 0;        // steps recorded in the pool
+    double acc_ms[8] = {};  // accumulated phase times (see flush_timing)
+    double acc_cycles = 0, acc_n[2] = {0, 0};
+    int acc_steps = 0;
+    std::vector<double> step_n0, step_n1;  // per recorded step, from the pass counts
+};

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "ctx.h"
 #include "internal.h"
 
 using namespace rz;
@@ -40,33 +41,6 @@ rzpic_status fail(rzpic_status st, const char *fmt, ...)
                         __FILE__, __LINE__);                                                \
     } while (0)
 
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-struct SpeciesState {
-    bool bound = false;
-    rzpic_species_view v{};
-    int64_t cap = 0;
-    Chunks ch{};
-    int64_t nchunks_max = 0;
-    // staging of the new particles of ionizations (electron species only):
-    // [0] new electrons, [1] new ions, slots indexed like electron particles
-    void *stage[2][8] = {};
-    bool has_xsec = false;
-    Xsec xs{};
-    double nu_max = 0.0, p_null = 0.0;
-    DevBuf sigma;
-    // tile sort: sorted-copy staging (8 real arrays + identities), per-segment
-    // tile counts/offsets, scan partials, and the window plan of the pass
-    void *sort_buf[9] = {};
-    int64_t *sort_off = nullptr, *sort_part = nullptr, *tile_pb = nullptr;
-    int4 *tile_win = nullptr;
-    int64_t sort_seg = 0, sort_nseg = 0;
-    int tile_nb = 0;  // pass blocks the plan is made for
-};
-
 void free_sort(SpeciesState &ss)
 {
     for (void *&p : ss.sort_buf)
@@ -85,56 +59,6 @@ void free_sort(SpeciesState &ss)
 
 }  // namespace
 
-struct rzpic_ctx {
-    rzpic_config c{};
-    hipStream_t st = nullptr;
-    int device = 0, cus = 0;
-    size_t lds_block = 0, lds_cu = 0;
-    int mixed = 0;
-    int pass_threads = 512;
-    int tile_per_cu = 1;  // resident blocks per CU of the tiled merged pass
-    double hr = 0, hz = 0;
-    int L = 0;
-    int nn = 0;
-    double quantum[2] = {1.0, 1.0};
-    std::vector<void *> allocs;
-    int ntr = 1, nt = 1, kbits = 0;  // tiles in r, tiles, bits of a tile key
-
-    // grids
-    double *phi, *rho, *chi, *er, *ez, *dens[2], *vol, *f, *eps;
-    double *phi_alt;  // FP64 cycles sweep the finest level from one phi buffer into the other
-    void *E2;
-    unsigned long long *acc[2];
-    unsigned long long *slices = nullptr;
-    int slice_blocks = 0;
-    bool lds_ok = false;
-    MgLevels mg{};
-    // device scalars
-    Counts *cnt;
-    FixRec *fix;
-    ChildRec *crec;
-    CloneRec *clrec;
-    unsigned long long *tally;   // [2][3]
-    unsigned long long *mcstat;  // [2][1 + kMaxProc]
-    unsigned long long *norm;    // [2]
-    int32_t *status;
-    // host-side bookkeeping
-    SpeciesState sp[2];
-    bool children_pending[2] = {false, false};  // staged children not yet appended
-    bool children_scanned = false;
-    int last_cycles = 0;
-    double last_relres = 0.0;
-    unsigned long long *psteps;  // [2]
-    // timing: per recorded step 10 events (see mark())
-    bool timing = false;
-    static constexpr int kEvPerStep = 10, kPool = 128;
-    std::vector<hipEvent_t> evpool;
-    int ev_used = 0;        // steps recorded in the pool
-    double acc_ms[8] = {};  // accumulated phase times (see flush_timing)
-    double acc_cycles = 0, acc_n[2] = {0, 0};
-    int acc_steps = 0;
-    std::vector<double> step_n0, step_n1;  // per recorded step, from the pass counts
-};
 
 namespace {
 
@@ -510,6 +434,80 @@ template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
     return RZPIC_OK;
 }
 
+// Cycles on a prepared system (eps formed and restricted, f set, the
+// Dirichlet values of u and u_alt set): `fixed` > 0 cycles without a test,
+// else cycles until ||f - A u||_inf <= tol ||f_bc||_inf (at most max_cycles;
+// one synchronisation per cycle).  *k receives the cycles run; with want_res
+// (always in tolerance mode) *relres the final relative residual.  The
+// V-cycle may exchange u and u_alt.
+rzpic_status run_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, const double *f,
+                        int fixed, double tol, int max_cycles, bool want_res, int *k_out,
+                        double *relres)
+{
+    const bool ob = c->mg.one_block != 0;
+    bool down_done = false;  // the first cycle's restriction came with the tables
+    if (c->mg.split) {
+        HIPCHK(mg_prep(c->mg, c->mixed, u, f, c->st));
+        down_done = true;
+    } else if (ob) {
+        HIPCHK(mg_factor(c->mg, c->mixed, c->st));
+    }
+    auto cycles_run = [&](int kk) -> hipError_t {
+        if (ob) return mg_solve_block(c->mg, c->mixed, u, f, V, kk, c->st);
+        for (int q = 0; q < kk; ++q) {
+            hipError_t e = mg_vcycle(c->mg, c->mixed, u, u_alt, f, down_done ? 1 : 0, c->st);
+            down_done = false;
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    auto resid = [&](double &rn, double &sc) -> rzpic_status {
+        unsigned long long hv[2];
+        HIPCHK(launch_fill_u64(c->norm, 2, c->st));
+        HIPCHK(mg_resid_norm(c->mg, u, f, 1, c->norm + 1, c->st));
+        HIPCHK(mg_resid_norm(c->mg, u, f, 0, c->norm, c->st));
+        HIPCHK(hipMemcpyAsync(hv, c->norm, sizeof hv, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        std::memcpy(&rn, &hv[0], 8);
+        std::memcpy(&sc, &hv[1], 8);
+        return RZPIC_OK;
+    };
+    int k = 0;
+    rzpic_status st = RZPIC_OK;
+    if (fixed > 0) {
+        HIPCHK(cycles_run(fixed));
+        k = fixed;
+    } else {
+        HIPCHK(launch_fill_u64(c->norm, 2, c->st));
+        HIPCHK(mg_resid_norm(c->mg, u, f, 1, c->norm + 1, c->st));
+        for (;;) {
+            HIPCHK(launch_fill_u64(c->norm, 1, c->st));
+            HIPCHK(mg_resid_norm(c->mg, u, f, 0, c->norm, c->st));
+            unsigned long long hv[2];
+            HIPCHK(hipMemcpyAsync(hv, c->norm, sizeof hv, hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            double rn, sc;
+            std::memcpy(&rn, &hv[0], 8);
+            std::memcpy(&sc, &hv[1], 8);
+            if (rn <= tol * sc) break;
+            if (k >= max_cycles) {
+                st = fail(RZPIC_ENOTCONV, "multigrid: relative residual %.3e after %d cycles",
+                          sc > 0 ? rn / sc : rn, k);
+                break;
+            }
+            HIPCHK(cycles_run(1));
+            ++k;
+        }
+    }
+    *k_out = k;
+    if (want_res || fixed <= 0) {
+        double rn, sc;
+        TRY(resid(rn, sc));
+        *relres = sc > 0 ? rn / sc : rn;
+    }
+    return st;
+}
+
 // prepared: the step's grid launch (mg_finalize) has formed eps and f,
 // restricted eps and set the Dirichlet values of both phi buffers.
 rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, double *relres)
@@ -526,65 +524,12 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
         HIPCHK(mg_set_bc(c->phi, nr, nz, V, c->st));
         HIPCHK(mg_set_bc(c->phi_alt, nr, nz, V, c->st));
     }
-    const bool ob = c->mg.one_block != 0;
-    bool down_done = false;  // the first cycle's restriction came with the tables
-    if (c->mg.split) {
-        HIPCHK(mg_prep(c->mg, c->mixed, c->phi, c->f, c->st));
-        down_done = true;
-    } else if (ob) {
-        HIPCHK(mg_factor(c->mg, c->mixed, c->st));
-    }
-    auto cycles_run = [&](int kk) -> hipError_t {
-        if (ob) return mg_solve_block(c->mg, c->mixed, c->phi, c->f, V, kk, c->st);
-        for (int q = 0; q < kk; ++q) {
-            hipError_t e =
-                mg_vcycle(c->mg, c->mixed, c->phi, c->phi_alt, c->f, down_done ? 1 : 0, c->st);
-            down_done = false;
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
     int k = 0;
-    rzpic_status st = RZPIC_OK;
-    const bool want = cycles || relres;
-    if (c->c.mg_fixed_cycles > 0) {
-        HIPCHK(cycles_run(c->c.mg_fixed_cycles));
-        k = c->c.mg_fixed_cycles;
-    } else {
-        HIPCHK(launch_fill_u64(c->norm, 2, c->st));
-        HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 1, c->norm + 1, c->st));
-        for (;;) {
-            HIPCHK(launch_fill_u64(c->norm, 1, c->st));
-            HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 0, c->norm, c->st));
-            unsigned long long hv[2];
-            HIPCHK(hipMemcpyAsync(hv, c->norm, sizeof hv, hipMemcpyDeviceToHost, c->st));
-            HIPCHK(hipStreamSynchronize(c->st));
-            double rn, sc;
-            std::memcpy(&rn, &hv[0], 8);
-            std::memcpy(&sc, &hv[1], 8);
-            if (rn <= c->c.mg_tol * sc) break;
-            if (k >= c->c.mg_max_cycles) {
-                st = fail(RZPIC_ENOTCONV, "multigrid: relative residual %.3e after %d cycles",
-                          sc > 0 ? rn / sc : rn, k);
-                break;
-            }
-            HIPCHK(cycles_run(1));
-            ++k;
-        }
-    }
+    double rr = c->last_relres;
+    rzpic_status st = run_cycles(c, V, c->phi, c->phi_alt, c->f, c->c.mg_fixed_cycles,
+                                 c->c.mg_tol, c->c.mg_max_cycles, cycles || relres, &k, &rr);
     c->last_cycles = k;
-    if (want || c->c.mg_fixed_cycles <= 0) {
-        unsigned long long hv[2];
-        HIPCHK(launch_fill_u64(c->norm, 2, c->st));
-        HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 1, c->norm + 1, c->st));
-        HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 0, c->norm, c->st));
-        HIPCHK(hipMemcpyAsync(hv, c->norm, sizeof hv, hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
-        double rn, sc;
-        std::memcpy(&rn, &hv[0], 8);
-        std::memcpy(&sc, &hv[1], 8);
-        c->last_relres = sc > 0 ? rn / sc : rn;
-    }
+    c->last_relres = rr;
     if (cycles) *cycles = k;
     if (relres) *relres = c->last_relres;
     return st;
@@ -841,6 +786,21 @@ int rz_batchable(const rzpic_ctx *c, std::string &why)
         return 0;
     }
     return 1;
+}
+
+// ===========================================================================
+// Helpers of the adjoint window (adjoint.hip).
+
+Mesh rz_mesh(const rzpic_ctx *c) { return mesh_of(c); }
+
+SpeciesK rz_species(const rzpic_ctx *c, int s) { return species_of(c, s); }
+
+// Tolerance-mode cycles on u (u_alt its partner buffer) for the system the
+// caller prepared in the context (eps restricted, f, Dirichlet values).
+rzpic_status rz_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, double tol,
+                       int max_cycles, int *cycles, double *relres)
+{
+    return run_cycles(c, V, u, u_alt, c->f, 0, tol, max_cycles, true, cycles, relres);
 }
 
 // ===========================================================================
@@ -1269,6 +1229,17 @@ rzpic_status rzpic_set_mg(rzpic_ctx *c, double tol, int32_t max_cycles, int32_t 
     c->c.mg_tol = tol;
     c->c.mg_max_cycles = max_cycles;
     c->c.mg_fixed_cycles = fixed_cycles;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_set_voltage(rzpic_ctx *c, double V_dc, double V_rf, double f_rf)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (!std::isfinite(V_dc) || !std::isfinite(V_rf) || !std::isfinite(f_rf))
+        return fail(RZPIC_EINVAL, "voltage parameters must be finite");
+    c->c.V_dc = V_dc;
+    c->c.V_rf = V_rf;
+    c->c.f_rf = f_rf;
     return RZPIC_OK;
 }
 

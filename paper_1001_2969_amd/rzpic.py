@@ -27,7 +27,8 @@ EXPORTS = (
     "rzpic_grid_copy", "rzpic_get_diag", "rzpic_sync", "rzpic_last_error", "rzpic_constants",
     "rzpic_set_timing", "rzpic_get_timing", "rzpic_set_mg", "rzpic_sort",
     "rzpic_batch_create", "rzpic_batch_step", "rzpic_batch_stats", "rzpic_batch_destroy",
-    "rzpic_batch_set_graph",
+    "rzpic_batch_set_graph", "rzpic_set_voltage", "rzpic_adjoint_create",
+    "rzpic_adjoint_forward", "rzpic_adjoint_backward", "rzpic_adjoint_destroy",
 )
 
 
@@ -70,6 +71,14 @@ class Diag(C.Structure):
     ]
 
 
+class AdjointConfig(C.Structure):
+    _fields_ = [
+        ("n_steps", C.c_int32), ("checkpoint_every", C.c_int32),
+        ("id_capacity", C.c_int64 * 2), ("delta", C.c_double), ("tol", C.c_double),
+        ("max_cycles", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -103,6 +112,10 @@ def lib():
             "rzpic_batch_create": [P, I, P, C.POINTER(P)],
             "rzpic_batch_step": [P, C.c_int64], "rzpic_batch_stats": [P, P],
             "rzpic_batch_destroy": [P], "rzpic_batch_set_graph": [P, I],
+            "rzpic_set_voltage": [P, D, D, D],
+            "rzpic_adjoint_create": [P, C.POINTER(AdjointConfig), C.POINTER(P)],
+            "rzpic_adjoint_forward": [P, C.c_int64, C.POINTER(D)],
+            "rzpic_adjoint_backward": [P, P, P, P, P], "rzpic_adjoint_destroy": [P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -272,6 +285,10 @@ class Context:
     def step(self, n):
         _check(lib().rzpic_step(self.h, n))
 
+    def set_voltage(self, V_dc, V_rf, f_rf=None):
+        f = self.w.f_rf if f_rf is None else f_rf
+        _check(lib().rzpic_set_voltage(self.h, V_dc, V_rf, f))
+
     def sync(self):
         _check(lib().rzpic_sync(self.h))
 
@@ -367,3 +384,86 @@ def make_context(w, *, capacity_factor=1.6, events=False, with_xsec=True, **kw):
             ctx.set_xsec(s, kind, thr, wl.XSEC_DE, sig, ejb)
     del hr
     return ctx
+
+
+class Adjoint:
+    """Gradient of the smooth ion-flux objective of an N-step collision-free
+    window (rzpic_adjoint_*) with respect to V_dc, V_rf and the particle
+    weights at the start of the window (by identity)."""
+
+    def __init__(self, ctx, n_steps, *, checkpoint_every=0, id_capacity=None, delta=0.0,
+                 tol=0.0, max_cycles=0):
+        self.ctx = ctx
+        caps = id_capacity or (ctx.capacity[0], ctx.capacity[1])
+        self.cfg = AdjointConfig(n_steps=n_steps, checkpoint_every=checkpoint_every,
+                                 id_capacity=(C.c_int64 * 2)(*caps), delta=delta, tol=tol,
+                                 max_cycles=max_cycles, reserved=0)
+        self.id_capacity = tuple(caps)
+        h = C.c_void_p()
+        _check(lib().rzpic_adjoint_create(ctx.h, C.byref(self.cfg), C.byref(h)))
+        self.h = h
+
+    def forward(self, step0=0):
+        J = C.c_double()
+        _check(lib().rzpic_adjoint_forward(self.h, step0, C.byref(J)))
+        return J.value
+
+    def backward(self, density=False):
+        """Returns (dJ/dV_dc, dJ/dV_rf, [dJ/dw by identity, per species]) and,
+        with density=True, also dJ/dpsi on the nodes ([nz, nr] tensor) for a
+        relative perturbation psi of the initial density."""
+        t = self.ctx.torch
+        gw = [t.zeros(self.id_capacity[s], dtype=t.float64, device=self.ctx.device)
+              for s in (0, 1)]
+        gd = t.zeros(self.ctx.nn, dtype=t.float64, device=self.ctx.device) if density else None
+        gv = (C.c_double * 2)()
+        _check(lib().rzpic_adjoint_backward(self.h, C.cast(gv, C.c_void_p),
+                                            C.c_void_p(gw[0].data_ptr()),
+                                            C.c_void_p(gw[1].data_ptr()),
+                                            C.c_void_p(gd.data_ptr()) if density else None))
+        if density:
+            return gv[0], gv[1], gw, gd.view(self.ctx.w.nz, self.ctx.w.nr)
+        return gv[0], gv[1], gw
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().rzpic_adjoint_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def window_objective(adj, step0, v_dc, v_rf, w_by_id):
+    """J of the window as a differentiable torch function of the electrode
+    voltage (0-d tensors v_dc, v_rf) and of the species weights at the start
+    of the window, given by identity (w_by_id: two float64 device tensors of
+    id_capacity[s] entries).  The context's particles take these weights and
+    voltages before the forward window runs."""
+    import torch
+
+    class _Window(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, vdc, vrf, w0, w1):
+            ctx = adj.ctx
+            ctx.set_voltage(float(vdc), float(vrf))
+            for s, wid in ((0, w0), (1, w1)):
+                n, _ = ctx.count(s)
+                arr = ctx.arrays[s]
+                arr["w"][:n].copy_(wid[arr["id"][:n]])
+            ctx.deposit()  # the window's first deposit, with these weights
+            J = adj.forward(step0)
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, gJ):
+            dvdc, dvrf, gw = adj.backward()
+            g = float(gJ)
+            return (torch.tensor(g * dvdc, dtype=torch.float64),
+                    torch.tensor(g * dvrf, dtype=torch.float64), gw[0] * g, gw[1] * g)
+
+    return _Window.apply(v_dc, v_rf, w_by_id[0], w_by_id[1])

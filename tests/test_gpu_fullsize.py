@@ -113,3 +113,46 @@ def test_large_mesh_mixed():
     assert e <= 1e-4
     for s, (go, oo) in enumerate(((rzpic.G_N0, rzo.G_N0), (rzpic.G_N1, rzo.G_N1))):
         print(f"N{s} error {check_counts(g.grid(go), o.grid(oo), w_un[s], f'N{s}'):.3e}")
+
+
+def test_adjoint_window_fullsize():
+    """The gradient window at full size (257x129, 4M particles per species,
+    50 steps checkpointed every 10): dJ/dV_rf against the central difference
+    of the HIP forward window with a relative step of 1e-6 (a smaller one if
+    that step changes which particles are absorbed), and dJ/dV_dc, dJ/dV_rf
+    and the density gradient finite."""
+    w = wl.adjoint_257x129()
+    delta = 2 * w.L / (w.nz - 1)
+
+    def start(V_rf):
+        g = rzpic.make_context(w.replace(V_rf=V_rf), precision="fp64", with_xsec=False,
+                               capacity_factor=1.25)
+        for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
+            g.init_particles(s, w.n_per_species, w.n0, T, 0)
+        g.prologue()
+        return g
+
+    g = start(w.V_rf)
+    adj = rzpic.Adjoint(g, w.steps, checkpoint_every=10, delta=delta)
+    J = adj.forward(0)
+    dvdc, dvrf, gw, gd = adj.backward(density=True)
+    adj.close()
+    del adj, g
+    assert np.isfinite([J, dvdc, dvrf]).all() and np.isfinite(gd.cpu().numpy()).all()
+    fd = None
+    for rel in (1e-6, 1e-7):
+        h = rel * w.V_rf
+        Js, counts = [], []
+        for v in (w.V_rf + h, w.V_rf - h):
+            gg = start(v)
+            a = rzpic.Adjoint(gg, w.steps, checkpoint_every=10, delta=delta)
+            Js.append(a.forward(0))
+            counts.append((gg.count(0)[0], gg.count(1)[0]))
+            a.close()
+            del a, gg
+        if counts[0] == counts[1]:
+            fd = (Js[0] - Js[1]) / (2 * h)
+            break
+    assert fd is not None, "every step changed the absorbed set"
+    print("257x129 J", J, "dJ/dV_rf", dvrf, "differences", fd, "dJ/dV_dc", dvdc)
+    assert abs(dvrf - fd) <= 1e-5 * abs(fd), (dvrf, fd)
