@@ -327,7 +327,8 @@ def batch_run(steps, warmup):
 
 def adjoint_run(reps=2):
     """The gradient window: 257x129 mesh, 4M particles per species, 50
-    collision-free FP64 steps with converged solves, checkpointed every 10.
+    collision-free FP64 steps with converged solves, checkpointed every 10,
+    particles sorted by tile after the prologue and every 10 steps.
     Wall time of the forward window (the steps plus the objective) and of the
     backward pass (segment recompute, reverse particle passes, adjoint
     solves), the last of `reps` repetitions; the context steps on from each
@@ -341,6 +342,8 @@ def adjoint_run(reps=2):
     for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
         ctx.init_particles(s, w.n_per_species, w.n0, T, 0)
     ctx.prologue()
+    for s in (0, 1):
+        ctx.sort(s)
     adj = rzpic.Adjoint(ctx, w.steps, checkpoint_every=10, delta=2 * w.L / (w.nz - 1))
     out = {"workload": w.name, "mesh": f"{w.nr}x{w.nz}", "particles_per_species": w.n_per_species,
            "window_steps": w.steps, "checkpoint_every": 10, "mg_tol": w.mg_tol}

@@ -42,12 +42,16 @@ using namespace rz;
 namespace rz {
 namespace {
 
-// Adjoint state of one species, indexed by particle identity.
+// Adjoint state of one species, indexed by particle identity: per identity
+// 8 doubles (64 bytes, one aligned segment) holding the adjoint of the entry
+// state r, z, v_r, v_theta, v_z, a_r, a_z and dJ/dw accumulated over the
+// window.  Identity order is not particle order once particles are sorted;
+// one contiguous record per identity keeps each access a single segment.
 struct AdjLam {
-    double *r, *z, *vr, *vt, *vz, *ar, *az;  // adjoint of the entry state
-    double *wbar;                            // dJ/dw accumulated over the window
-    int64_t cap;                             // identities are < cap
+    double *rec;  // [cap][8]
+    int64_t cap;  // identities are < cap
 };
+constexpr int kLamW = 7;  // index of dJ/dw in a record
 
 __device__ __forceinline__ double block_sum(double v, double *sh)
 {
@@ -124,25 +128,64 @@ struct AdjPassArgs {
     int objective;  // species carries the objective
     double cJ, inv_delta;
     unsigned long long *err;
+    // LDS window of dJ/dE (particles sorted by tile): the tile of the block's
+    // first particle plus kAdjHalo cells; 0 = every contribution to global atomics
+    int win, tile_z, tile_r;
 };
+
+constexpr int kAdjHalo = 4;
+
+// LDS bytes of the dJ/dE window of a tile_z x tile_r tile.
+__host__ __device__ constexpr size_t adj_window_bytes(int tile_z, int tile_r)
+{
+    return 2 * sizeof(double) * (size_t)(tile_z + 2 * kAdjHalo + 1) *
+           (size_t)(tile_r + 2 * kAdjHalo + 1);
+}
 
 // Reverse of one step of one species (see the file comment).  The forward
 // arithmetic is that of the fused pass: gather, final push with the axis
-// rule, absorption, first push with rotation, absorption.
+// rule, absorption, first push with rotation, absorption.  Each block takes
+// a contiguous range of the particles.
 __global__ __launch_bounds__(256) void k_adj_particles(AdjPassArgs a)
 {
+    extern __shared__ double lwin[];
     const int64_t n = a.cnt->n;
     const Mesh &m = a.m;
     const double dt = a.dt, half = 0.5;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per;
+    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    // window nodes [wi0, wi0 + wni) x [wj0, wj0 + wnj); none when wni = 0
+    int wi0 = 0, wj0 = 0, wni = 0, wnj = 0;
+    if (a.win && b0 < b1) {
+        const W4<double> q0 = weights<double>(m, a.p.r[b0], a.p.z[b0]);
+        const int ti = q0.i / a.tile_z, tj = q0.j / a.tile_r;
+        const int ci0 = ti * a.tile_z - kAdjHalo > 0 ? ti * a.tile_z - kAdjHalo : 0;
+        const int cj0 = tj * a.tile_r - kAdjHalo > 0 ? tj * a.tile_r - kAdjHalo : 0;
+        int ci1 = (ti + 1) * a.tile_z + kAdjHalo, cj1 = (tj + 1) * a.tile_r + kAdjHalo;
+        ci1 = ci1 < m.nz - 1 ? ci1 : m.nz - 1;  // cells [ci0, ci1), nodes [ci0, ci1]
+        cj1 = cj1 < m.nr - 1 ? cj1 : m.nr - 1;
+        wi0 = ci0;
+        wj0 = cj0;
+        wni = ci1 - ci0 + 1;
+        wnj = cj1 - cj0 + 1;
+    }
+    const int wn = wni * wnj;
+    double *lr_win = lwin, *lz_win = lwin + wn;
+    for (int g = threadIdx.x; g < 2 * wn; g += blockDim.x) lwin[g] = 0.0;
+    if (a.win) __syncthreads();
+    const unsigned wci = wni > 1 ? (unsigned)(wni - 1) : 0u, wcj = wnj > 1 ? (unsigned)(wnj - 1) : 0u;
+
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
         const uint64_t id = a.p.id[i];
         if (id >= (uint64_t)a.lam.cap) {
             atomicOr(a.err, 1ull);
             continue;
         }
+        double2 *rec = (double2 *)(a.lam.rec + 8 * id);
         const double r0 = a.p.r[i], z0 = a.p.z[i], vr0 = a.p.vr[i], vt0 = a.p.vt[i];
         const double vz0 = a.p.vz[i], ar0 = a.p.ar[i], az0 = a.p.az[i], w = a.p.w[i];
+        const double2 l01 = rec[0], l23 = rec[1], l45 = rec[2], l67 = rec[3];
         // gather
         const W4<double> q = weights<double>(m, r0, z0);
         const double2 e00 = a.E2[q.g], e01 = a.E2[q.g + 1], e10 = a.E2[q.g + m.nr],
@@ -184,14 +227,16 @@ __global__ __launch_bounds__(256) void k_adj_particles(AdjPassArgs a)
         const double r2 = rn;
         dead = dead || z2 <= 0.0 || z2 >= m.L || r2 >= m.R;
         if (dead) {  // nothing after this step depends on the particle
-            a.lam.r[id] = a.lam.z[id] = a.lam.vr[id] = a.lam.vt[id] = 0.0;
-            a.lam.vz[id] = a.lam.ar[id] = a.lam.az[id] = 0.0;
+            rec[0] = make_double2(0.0, 0.0);
+            rec[1] = make_double2(0.0, 0.0);
+            rec[2] = make_double2(0.0, 0.0);
+            rec[3] = make_double2(0.0, l67.y);
             continue;
         }
         // adjoint of the exit state: later steps, this step's deposit, the objective
-        double lr = a.lam.r[id], lz = a.lam.z[id], lvr = a.lam.vr[id], lvt = a.lam.vt[id];
-        double lvz = a.lam.vz[id], lar = a.lam.ar[id], laz = a.lam.az[id];
-        double wb = 0.0;
+        double lr = l01.x, lz = l01.y, lvr = l23.x, lvt = l23.y;
+        double lvz = l45.x, lar = l45.y, laz = l67.x;
+        double wb = l67.y;
         if (a.nbar) {
             const W4<double> q2 = weights<double>(m, r2, z2);
             const double n00 = a.nbar[q2.g], n01 = a.nbar[q2.g + 1], n10 = a.nbar[q2.g + m.nr],
@@ -236,22 +281,39 @@ __global__ __launch_bounds__(256) void k_adj_particles(AdjPassArgs a)
         const double dEz_dr = ds0 * ((q.sz0 * e01.y + q.sz1 * e11.y) - (q.sz0 * e00.y + q.sz1 * e10.y));
         const double dEr_dz = m.inv_hz * ((q.sr0 * e10.x + q.sr1 * e11.x) - (q.sr0 * e00.x + q.sr1 * e01.x));
         const double dEz_dz = m.inv_hz * ((q.sr0 * e10.y + q.sr1 * e11.y) - (q.sr0 * e00.y + q.sr1 * e01.y));
-        a.lam.r[id] = r1pb + Erb * dEr_dr + Ezb * dEz_dr;
-        a.lam.z[id] = lz + Erb * dEr_dz + Ezb * dEz_dz;
-        a.lam.vr[id] = vr1pb;
-        a.lam.vt[id] = vyb;
-        a.lam.vz[id] = vz2b;
-        a.lam.ar[id] = half * ar1pb;
-        a.lam.az[id] = half * az1b;
-        if (wb != 0.0) a.lam.wbar[id] += wb;
-        unsafeAtomicAdd(a.ebar_r + q.g, w00 * Erb);
-        unsafeAtomicAdd(a.ebar_r + q.g + 1, w01 * Erb);
-        unsafeAtomicAdd(a.ebar_r + q.g + m.nr, w10 * Erb);
-        unsafeAtomicAdd(a.ebar_r + q.g + m.nr + 1, w11 * Erb);
-        unsafeAtomicAdd(a.ebar_z + q.g, w00 * Ezb);
-        unsafeAtomicAdd(a.ebar_z + q.g + 1, w01 * Ezb);
-        unsafeAtomicAdd(a.ebar_z + q.g + m.nr, w10 * Ezb);
-        unsafeAtomicAdd(a.ebar_z + q.g + m.nr + 1, w11 * Ezb);
+        rec[0] = make_double2(r1pb + Erb * dEr_dr + Ezb * dEz_dr, lz + Erb * dEr_dz + Ezb * dEz_dz);
+        rec[1] = make_double2(vr1pb, vyb);
+        rec[2] = make_double2(vz2b, half * ar1pb);
+        rec[3] = make_double2(half * az1b, wb);
+        const int li = q.i - wi0, lj = q.j - wj0;
+        if ((unsigned)li < wci && (unsigned)lj < wcj) {
+            const int l = li * wnj + lj;
+            atomicAdd(lr_win + l, w00 * Erb);
+            atomicAdd(lr_win + l + 1, w01 * Erb);
+            atomicAdd(lr_win + l + wnj, w10 * Erb);
+            atomicAdd(lr_win + l + wnj + 1, w11 * Erb);
+            atomicAdd(lz_win + l, w00 * Ezb);
+            atomicAdd(lz_win + l + 1, w01 * Ezb);
+            atomicAdd(lz_win + l + wnj, w10 * Ezb);
+            atomicAdd(lz_win + l + wnj + 1, w11 * Ezb);
+        } else {
+            unsafeAtomicAdd(a.ebar_r + q.g, w00 * Erb);
+            unsafeAtomicAdd(a.ebar_r + q.g + 1, w01 * Erb);
+            unsafeAtomicAdd(a.ebar_r + q.g + m.nr, w10 * Erb);
+            unsafeAtomicAdd(a.ebar_r + q.g + m.nr + 1, w11 * Erb);
+            unsafeAtomicAdd(a.ebar_z + q.g, w00 * Ezb);
+            unsafeAtomicAdd(a.ebar_z + q.g + 1, w01 * Ezb);
+            unsafeAtomicAdd(a.ebar_z + q.g + m.nr, w10 * Ezb);
+            unsafeAtomicAdd(a.ebar_z + q.g + m.nr + 1, w11 * Ezb);
+        }
+    }
+    if (!a.win) return;
+    __syncthreads();
+    for (int g = threadIdx.x; g < wn; g += blockDim.x) {
+        const int k = (wi0 + g / wnj) * m.nr + wj0 + g % wnj;
+        const double vr = lr_win[g], vz = lz_win[g];
+        if (vr != 0.0) unsafeAtomicAdd(a.ebar_r + k, vr);
+        if (vz != 0.0) unsafeAtomicAdd(a.ebar_z + k, vz);
     }
 }
 
@@ -269,7 +331,7 @@ __global__ __launch_bounds__(256) void k_adj_wdep(Parts<double> p, const Counts 
             continue;
         }
         const W4<double> q = weights<double>(m, p.r[i], p.z[i]);
-        lam.wbar[id] += q.sz0 * q.sr0 * nbar[q.g] + q.sz0 * q.sr1 * nbar[q.g + 1] +
+        lam.rec[8 * id + kLamW] += q.sz0 * q.sr0 * nbar[q.g] + q.sz0 * q.sr1 * nbar[q.g + 1] +
                         q.sz1 * q.sr0 * nbar[q.g + m.nr] + q.sz1 * q.sr1 * nbar[q.g + m.nr + 1];
     }
 }
@@ -285,7 +347,7 @@ __global__ __launch_bounds__(256) void k_adj_density(Parts<double> p, const Coun
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t id = p.id[i];
         if (id >= (uint64_t)lam.cap) continue;  // reported by the reverse pass
-        const double g = lam.wbar[id] * p.w[i];
+        const double g = lam.rec[8 * id + kLamW] * p.w[i];
         if (g == 0.0) continue;
         const W4<double> q = weights<double>(m, p.r[i], p.z[i]);
         unsafeAtomicAdd(gpsi + q.g, q.sz0 * q.sr0 * g);
@@ -293,6 +355,14 @@ __global__ __launch_bounds__(256) void k_adj_density(Parts<double> p, const Coun
         unsafeAtomicAdd(gpsi + q.g + m.nr, q.sz1 * q.sr0 * g);
         unsafeAtomicAdd(gpsi + q.g + m.nr + 1, q.sz1 * q.sr1 * g);
     }
+}
+
+// dJ/dw by identity out of the records.
+__global__ void k_adj_wbar_out(AdjLam lam, double *out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < lam.cap;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = lam.rec[8 * i + kLamW];
 }
 
 // Control-volume weight of column j relative to pi hr^2 hz (the factor that
@@ -408,7 +478,7 @@ struct rzpic_adjoint {
     double *er = nullptr, *ez = nullptr, *E2 = nullptr;
     double *ebar = nullptr;  // [2][nn]
     double *phibar = nullptr, *mu = nullptr, *mu_alt = nullptr, *nbar = nullptr;  // nbar [2][nn]
-    double *lam[2] = {nullptr, nullptr};  // [8][cap_s]
+    double *lam[2] = {nullptr, nullptr};  // [cap_s][8]
     double *partial = nullptr, *J = nullptr, *gv = nullptr;
     unsigned long long *err = nullptr;
     int64_t step0 = -1;
@@ -498,12 +568,14 @@ Parts<double> ctx_parts(const rzpic_ctx *c, int s)
     return p;
 }
 
-AdjLam lam_of(const rzpic_adjoint *a, int s)
+AdjLam lam_of(const rzpic_adjoint *a, int s) { return AdjLam{a->lam[s], a->cfg.id_capacity[s]}; }
+
+// Blocks of the reverse particle pass: contiguous ranges of about 4096
+// particles of the capacity each.
+int pass_blocks(int64_t cap)
 {
-    const int64_t cap = a->cfg.id_capacity[s];
-    double *b = a->lam[s];
-    return AdjLam{b, b + cap, b + 2 * cap, b + 3 * cap, b + 4 * cap,
-                  b + 5 * cap, b + 6 * cap, b + 7 * cap, cap};
+    int64_t b = (cap + 4095) / 4096;
+    return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
 int copy_blocks(int64_t cap)
@@ -696,6 +768,9 @@ rzpic_status rzpic_adjoint_backward(rzpic_adjoint *a, double grad_V[2], double *
     AHIP(launch_fill_u64((unsigned long long *)a->mu, nn, st));
     AHIP(launch_fill_u64((unsigned long long *)a->mu_alt, nn, st));
     bool have_nbar = false;  // the last step's exit deposit feeds no solve of the window
+    // dJ/dE in LDS windows when the particles are kept sorted by tile
+    const size_t wlds = adj_window_bytes(c->c.tile_z, c->c.tile_r);
+    const bool win = c->c.sort_every > 0 && wlds <= 64 * 1024;
 
     GridAdjArgs g{};
     g.nr = nr;
@@ -759,8 +834,11 @@ rzpic_status rzpic_adjoint_backward(rzpic_adjoint *a, double grad_V[2], double *
                 p.cJ = c->sp[1].v.q * c->c.dt / a->delta;
                 p.inv_delta = 1.0 / a->delta;
                 p.err = a->err;
-                hipLaunchKernelGGL(k_adj_particles, dim3(copy_blocks(c->sp[s].cap)), dim3(256), 0,
-                                   st, p);
+                p.win = win ? 1 : 0;
+                p.tile_z = c->c.tile_z;
+                p.tile_r = c->c.tile_r;
+                hipLaunchKernelGGL(k_adj_particles, dim3(pass_blocks(c->sp[s].cap)), dim3(256),
+                                   win ? wlds : 0, st, p);
                 AHIP(hipGetLastError());
             }
             g.chi = chi;
@@ -802,9 +880,11 @@ rzpic_status rzpic_adjoint_backward(rzpic_adjoint *a, double grad_V[2], double *
     ATRY(checkpoint(a, a->nck - 1, false));
     double *gw[2] = {grad_w0, grad_w1};
     for (int s = 0; s < 2; ++s)
-        if (gw[s])
-            AHIP(hipMemcpyAsync(gw[s], lam_of(a, s).wbar, 8 * (size_t)a->cfg.id_capacity[s],
-                                hipMemcpyDeviceToDevice, st));
+        if (gw[s]) {
+            hipLaunchKernelGGL(k_adj_wbar_out, dim3(copy_blocks(a->cfg.id_capacity[s])), dim3(256),
+                               0, st, lam_of(a, s), gw[s]);
+            AHIP(hipGetLastError());
+        }
     unsigned long long herr = 0;
     AHIP(hipMemcpyAsync(grad_V, a->gv, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     AHIP(hipMemcpyAsync(&herr, a->err, sizeof herr, hipMemcpyDeviceToHost, st));

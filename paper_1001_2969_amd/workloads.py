@@ -112,10 +112,11 @@ def large_513x129() -> Workload:
 def adjoint_257x129() -> Workload:
     """Gradient window: 257x129 mesh (R = 8 cm, L = 4 cm, square 0.3125 mm
     cells), 4M particles per species, FP64, 200 V 13.56 MHz drive, converged
-    solves, no collisions; 50 steps, checkpointed every 10."""
+    solves, no collisions, particles sorted by 16 x 32-cell tile after the
+    prologue and every 10 steps; 50 steps, checkpointed every 10."""
     return Workload(name="257x129_4M_adjoint", nr=257, nz=129, R=0.08, L=0.04,
                     n_per_species=4_000_000, steps=50, V_rf=200.0, mg_tol=1e-12,
-                    mg_max_cycles=200)
+                    mg_max_cycles=200, sort_every=10)
 
 
 def batch_64(seed: int = 0, n: int = 64):

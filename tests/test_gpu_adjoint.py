@@ -155,6 +155,30 @@ def test_checkpoint_spacing_does_not_change_the_gradient():
             assert np.abs(gw[s] - res[0][3][s]).max() <= 1e-12 * sc
 
 
+def test_sorted_particles_give_the_same_gradient():
+    """Tile-sorted particles (sort after the prologue and every 3 steps; the
+    reverse pass then sums dJ/dE in LDS windows) against the unsorted run."""
+    states = _states(W, 67)
+    res = []
+    for sort_every in (0, 3):
+        w = W.replace(sort_every=sort_every, tile_z=8, tile_r=8)
+        g = _context(w, states)
+        if sort_every:
+            for s in (0, 1):
+                g.sort(s)
+        adj = rzpic.Adjoint(g, N, checkpoint_every=K, delta=DELTA)
+        J = adj.forward(STEP0)
+        dvdc, dvrf, gw, gd = adj.backward(density=True)
+        res.append((J, dvdc, dvrf, [x.cpu().numpy() for x in gw], gd.cpu().numpy()))
+        adj.close()
+    (J0, dc0, rf0, gw0, gd0), (J1, dc1, rf1, gw1, gd1) = res
+    assert abs(J1 - J0) <= 1e-13 * abs(J0)
+    assert abs(rf1 - rf0) <= 1e-11 * abs(rf0) and abs(dc1 - dc0) <= 1e-11 * abs(dc0)
+    for s in (0, 1):
+        assert np.abs(gw1[s] - gw0[s]).max() <= 1e-11 * np.abs(gw0[s]).max()
+    assert np.abs(gd1 - gd0).max() <= 1e-11 * np.abs(gd0).max()
+
+
 def test_context_is_left_at_the_end_of_the_window():
     states = _states(W, 64)
     g = _context(W, states)
@@ -226,11 +250,12 @@ def test_rejected_configurations():
 
 
 def test_larger_window_against_differences_of_the_hip_forward():
-    """129x65, 200k particles per species, 10 steps in segments of 4: the
-    adjoint's dJ/dV_rf against the central difference of the HIP forward
-    window (fresh contexts from the same seeded start)."""
+    """129x65, 200k particles per species, 10 steps in segments of 4, tile
+    sort after the prologue and every 4 steps: the adjoint's dJ/dV_rf against
+    the central difference of the HIP forward window (fresh contexts from the
+    same seeded start)."""
     w = wl.rf_129x65().replace(n_per_species=200_000, mg_fixed_cycles=0, mg_tol=1e-13,
-                               mg_max_cycles=400, precision="fp64", V_dc=20.0)
+                               mg_max_cycles=400, precision="fp64", V_dc=20.0, sort_every=4)
     delta = 2 * w.L / (w.nz - 1)
 
     def start():
@@ -238,6 +263,8 @@ def test_larger_window_against_differences_of_the_hip_forward():
         for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
             g.init_particles(s, w.n_per_species, w.n0, T, 0)
         g.prologue()
+        for s in (0, 1):
+            g.sort(s)
         return g
 
     g = start()

@@ -117,7 +117,7 @@ def test_large_mesh_mixed():
 
 def test_adjoint_window_fullsize():
     """The gradient window at full size (257x129, 4M particles per species,
-    50 steps checkpointed every 10): dJ/dV_rf against the central difference
+    50 steps checkpointed every 10, tile sort every 10 steps): dJ/dV_rf against the central difference
     of the HIP forward window with a relative step of 1e-6 (a smaller one if
     that step changes which particles are absorbed), and dJ/dV_dc, dJ/dV_rf
     and the density gradient finite."""
@@ -130,6 +130,8 @@ def test_adjoint_window_fullsize():
         for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
             g.init_particles(s, w.n_per_species, w.n0, T, 0)
         g.prologue()
+        for s in (0, 1):
+            g.sort(s)
         return g
 
     g = start(w.V_rf)
