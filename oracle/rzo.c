@@ -67,6 +67,11 @@ struct rzo {
     double *N[2], *dens[2];
     double *ld, *lb, *le, *lg, *lx, *lcp, *lgp; /* line-solve scratch          */
     species sp[2];
+    /* external circuit: the charge solution with the electrode at 0 V, the
+     * Laplace solution with it at 1 V, a zero right-hand side, and the state */
+    double *phiP, *phiL, *zero;
+    double cV, cQ, cQc, cQconv, cQp, cQl;
+    double absorbed_prev[2];     /* weight absorbed at z=0 by the last solve   */
 };
 
 void rzo_constants(double out[6])
@@ -147,6 +152,7 @@ rzo *rzo_create(const rzo_config *cfg)
         return NULL;
     if (cfg->sort_every < 0 || (cfg->sort_every > 0 && (cfg->tile_z < 1 || cfg->tile_r < 1)))
         return NULL;
+    if (!(cfg->circuit_C >= 0.0)) return NULL;
     rzo *o = (rzo *)calloc(1, sizeof(rzo));
     if (!o) return NULL;
     o->c = *cfg;
@@ -185,6 +191,11 @@ rzo *rzo_create(const rzo_config *cfg)
     o->lx = (double *)calloc(nr, sizeof(double));
     o->lcp = (double *)calloc(nr, sizeof(double));
     o->lgp = (double *)calloc(nr, sizeof(double));
+    if (cfg->circuit_C > 0.0) {
+        o->phiP = (double *)calloc(nn, sizeof(double));
+        o->phiL = (double *)calloc(nn, sizeof(double));
+        o->zero = (double *)calloc(nn, sizeof(double));
+    }
 
     /* Weighting volumes of Sec. 2.4.  Radial factor: the paper's V_j with the
      * outer neighbour clamped to the wall node at j = nr-1 (only the inner
@@ -227,6 +238,7 @@ void rzo_destroy(rzo *o)
     for (int s = 0; s < 2; ++s) { free(o->N[s]); free(o->dens[s]); free_species(&o->sp[s]); }
     free(o->ld); free(o->lb); free(o->le); free(o->lg); free(o->lx); free(o->lcp);
     free(o->lgp);
+    free(o->phiP); free(o->phiL); free(o->zero);
     free(o);
 }
 
@@ -1109,12 +1121,11 @@ static void build_levels(rzo *o)
     }
 }
 
-/* Dirichlet data: V(t) on the powered electrode z = 0 (r < R), 0 V on the
+/* Dirichlet data of u: V on the powered electrode z = 0 (r < R), 0 V on the
  * grounded electrode z = L and on the wall r = R including both corners. */
-static void set_bc(rzo *o, double V)
+static void set_bc(rzo *o, double *u, double V)
 {
     int nr = o->c.nr, nz = o->c.nz;
-    double *u = o->phi;
     for (int j = 0; j < nr; ++j) {
         u[j] = j < nr - 1 ? V : 0.0;
         u[(size_t)(nz - 1) * nr + j] = 0.0;
@@ -1122,20 +1133,24 @@ static void set_bc(rzo *o, double V)
     for (int i = 0; i < nz; ++i) u[(size_t)i * nr + nr - 1] = 0.0;
 }
 
-int rzo_solve(rzo *o, double t, int32_t *cycles, double *relres)
+/* Algorithm 1 on u (warm start: its interior) for the right-hand side fr and
+ * the electrode value V, with the levels' epsilon already built: cycles until
+ * the relative residual test of Sec. 2.5 holds, or the fixed count. */
+static int solve_on(rzo *o, double *u, const double *fr, double V, int32_t *cycles,
+                    double *relres)
 {
     int L = o->L, nr = o->c.nr, nz = o->c.nz;
-    double V = o->c.V_dc + o->c.V_rf * sin(TWO_PI * o->c.f_rf * t);
     double *f = o->f_l[L];
-    for (int g = 0; g < o->nn; ++g) f[g] = o->rho[g] / EPS0;
-    build_levels(o);
-    set_bc(o, V);
+    if (f != fr) memcpy(f, fr, (size_t)o->nn * sizeof(double));
+    set_bc(o, u, V);
+    double *keep = o->u_l[L];
+    o->u_l[L] = u;
     /* Scale of the relative residual: the residual of the boundary data with
      * a zero interior, i.e. the right-hand side of the interior system. */
     double *ubc = (double *)calloc((size_t)o->nn, sizeof(double));
     for (int j = 0; j < nr; ++j) {
-        ubc[j] = o->phi[j];
-        ubc[(size_t)(nz - 1) * nr + j] = o->phi[(size_t)(nz - 1) * nr + j];
+        ubc[j] = u[j];
+        ubc[(size_t)(nz - 1) * nr + j] = u[(size_t)(nz - 1) * nr + j];
     }
     residual(o, L, ubc, f, o->res);
     double scale = maxabs_interior(o, L, o->res);
@@ -1146,7 +1161,7 @@ int rzo_solve(rzo *o, double t, int32_t *cycles, double *relres)
         if (o->c.mg_fixed_cycles > 0) {
             if (k >= o->c.mg_fixed_cycles) break;
         } else {
-            residual(o, L, o->phi, f, o->res);
+            residual(o, L, u, f, o->res);
             double rn = maxabs_interior(o, L, o->res);
             if (rn <= o->c.mg_tol * scale) break;
             if (k >= o->c.mg_max_cycles) {
@@ -1157,11 +1172,101 @@ int rzo_solve(rzo *o, double t, int32_t *cycles, double *relres)
         vcycle(o);
         ++k;
     }
-    residual(o, L, o->phi, f, o->res);
+    residual(o, L, u, f, o->res);
     double rn = maxabs_interior(o, L, o->res);
+    o->u_l[L] = keep;
     if (cycles) *cycles = k;
     if (relres) *relres = scale > 0.0 ? rn / scale : rn;
     return status;
+}
+
+/* Charge on the z = 0 electrode (r < R) of the potential u with the charge
+ * density rho (NULL: none), by Gauss's law on the union of the electrode
+ * nodes' half cells (0 <= z <= hz/2): the displacement eps0 (1+chi) E flowing
+ * out through their upper faces (area 2 pi r_j hr, pi hr^2/4 on the axis, at
+ * distance hz from row 1) and through the side face of the last one towards
+ * the wall node (area pi r_{nr-3/2} hz at distance hr), less the charge the
+ * deposit assigns to the half cells, rho V on row 0. */
+static double electrode_charge(const rzo *o, const double *u, const double *rho)
+{
+    int nr = o->c.nr;
+    double hr = o->hr, hz = o->hz;
+    const double *eps = o->eps_l[o->L];
+    double q = 0.0;
+    for (int j = 0; j < nr - 1; ++j) {
+        double area = j == 0 ? PI_ * 0.25 * hr * hr : 2.0 * PI_ * (double)j * hr * hr;
+        q += EPS0 * face(o, eps[j], eps[nr + j]) * area * (u[j] - u[nr + j]) / hz;
+        if (rho) q -= rho[j] * o->vol[j];
+    }
+    int jw = nr - 2;
+    double rface = ((double)jw + 0.5) * hr;
+    q += EPS0 * face(o, eps[jw], eps[jw + 1]) * PI_ * rface * hz / hr * (u[jw] - u[jw + 1]);
+    return q;
+}
+
+/* External circuit (Sec. 2.5, the superposition of Vahedi): phi_P solves the
+ * field equation with the charge and the electrode at 0 V, phi_L the same
+ * operator without charge and the electrode at 1 V; the electrode charge of
+ * phi = phi_P + V phi_L is Q_P + V Q_L.  The blocking-capacitor equation
+ *   Q^t = Q^{t-1} + C (V_s^t - V^t) - Q_c^{t-1} + Q_conv^t,  Q_c^t = C (V_s^t - V^t),
+ * with Q_conv the charge absorbed at the electrode since the previous solve
+ * (this step's first push and the previous step's final push), gives V^t. */
+static int circuit_solve(rzo *o, double Vs, const double *f, int32_t *cycles, double *relres)
+{
+    int32_t c1 = 0, c2 = 0;
+    double r1 = 0.0, r2 = 0.0;
+    int st = solve_on(o, o->phiP, f, 0.0, &c1, &r1);
+    int st2 = solve_on(o, o->phiL, o->zero, 1.0, &c2, &r2);
+    double C = o->c.circuit_C;
+    double Qp = electrode_charge(o, o->phiP, o->rho);
+    double Ql = electrode_charge(o, o->phiL, NULL);
+    double Qconv = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        Qconv += o->sp[s].q * (o->sp[s].absorbed[0] - o->absorbed_prev[s]);
+        o->absorbed_prev[s] = o->sp[s].absorbed[0];
+    }
+    double V = (o->cQ - o->cQc + Qconv + C * Vs - Qp) / (Ql + C);
+    o->cV = V;
+    o->cQ = Qp + V * Ql;
+    o->cQc = C * (Vs - V);
+    o->cQconv = Qconv;
+    o->cQp = Qp;
+    o->cQl = Ql;
+    for (int g = 0; g < o->nn; ++g) o->phi[g] = o->phiP[g] + V * o->phiL[g];
+    if (cycles) *cycles = c1 > c2 ? c1 : c2;
+    if (relres) *relres = r1 > r2 ? r1 : r2;
+    return st ? st : st2;
+}
+
+int rzo_set_circuit(rzo *o, double V, double Q, double Qc)
+{
+    if (!o || !(o->c.circuit_C > 0.0)) return -1;
+    o->cV = V;
+    o->cQ = Q;
+    o->cQc = Qc;
+    return 0;
+}
+
+int rzo_circuit(const rzo *o, double out[6])
+{
+    out[0] = o->cV;
+    out[1] = o->cQ;
+    out[2] = o->cQc;
+    out[3] = o->cQconv;
+    out[4] = o->cQp;
+    out[5] = o->cQl;
+    return o->c.circuit_C > 0.0 ? 0 : -1;
+}
+
+int rzo_solve(rzo *o, double t, int32_t *cycles, double *relres)
+{
+    int L = o->L;
+    double V = o->c.V_dc + o->c.V_rf * sin(TWO_PI * o->c.f_rf * t);
+    double *f = o->f_l[L];
+    for (int g = 0; g < o->nn; ++g) f[g] = o->rho[g] / EPS0;
+    build_levels(o);
+    if (o->c.circuit_C > 0.0) return circuit_solve(o, V, f, cycles, relres);
+    return solve_on(o, o->phi, f, V, cycles, relres);
 }
 
 /* E = -grad phi: centred differences inside, one-sided on the electrodes and
@@ -1308,6 +1413,8 @@ static double *grid_ptr(const rzo *o, int which)
     case RZO_G_DENS0: return o->dens[0];
     case RZO_G_DENS1: return o->dens[1];
     case RZO_G_VOL: return o->vol;
+    case RZO_G_PHI_P: return o->phiP;
+    case RZO_G_PHI_L: return o->phiL;
     default: return NULL;
     }
 }
@@ -1323,7 +1430,7 @@ int rzo_get_grid(const rzo *o, int which, double *out)
 int rzo_set_grid(rzo *o, int which, const double *in)
 {
     double *p = grid_ptr(o, which);
-    if (!p || which == RZO_G_VOL) return -1;
+    if (!p || which == RZO_G_VOL || which == RZO_G_PHI_P || which == RZO_G_PHI_L) return -1;
     memcpy(p, in, (size_t)o->nn * sizeof(double));
     return 0;
 }

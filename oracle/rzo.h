@@ -43,7 +43,8 @@ enum {
     RZO_G_PHI = 0, RZO_G_RHO = 1, RZO_G_CHI = 2, RZO_G_ER = 3, RZO_G_EZ = 4,
     RZO_G_N0 = 5, RZO_G_N1 = 6,      /* deposited physical-particle counts N_ij */
     RZO_G_DENS0 = 7, RZO_G_DENS1 = 8,/* number densities n_ij = N_ij / V_ij   */
-    RZO_G_VOL = 9                    /* weighting volumes V_ij                 */
+    RZO_G_VOL = 9,                   /* weighting volumes V_ij                 */
+    RZO_G_PHI_P = 10, RZO_G_PHI_L = 11 /* external circuit: the two superposed solutions */
 };
 /* Per-particle Monte Carlo event codes (rzo_get_events). */
 enum { RZO_EV_NONE = 0, RZO_EV_NULL = 1, RZO_EV_PROC0 = 2 };
@@ -63,6 +64,8 @@ typedef struct {
     double resize_wcoef;     /* w_r(r) = resize_wcoef * max(r, hr/2)        */
     double n_gas, T_gas, m_gas; /* background neutral density, K, kg        */
     int32_t tile_z, tile_r;  /* tile of the sort key, in cells              */
+    double circuit_C;        /* >0: blocking capacitor (F) between the source
+                              * V_dc+V_rf sin(2 pi f t) and the z=0 electrode  */
 } rzo_config;
 
 rzo *rzo_create(const rzo_config *cfg);
@@ -122,6 +125,10 @@ int rzo_get_grid(const rzo *o, int which, double *out);
 int rzo_set_grid(rzo *o, int which, const double *in);
 /* Absorbed physical-particle weight of species s at z=0, z=L, r=R. */
 int rzo_absorbed(const rzo *o, int s, double out[3]);
+/* External circuit state (circuit_C > 0): set {V, Q, Q_c}; read
+ * {V, Q, Q_c, Q_conv, Q_P, Q_L} of the last solve. */
+int rzo_set_circuit(rzo *o, double V, double Q, double Qc);
+int rzo_circuit(const rzo *o, double out[6]);
 
 /* Pieces exposed for pinning. */
 /* y = A u on the finest level (interior nodes; boundary entries of y = 0). */

@@ -15,6 +15,7 @@ from . import build as _build
 _LIB = None
 
 G_PHI, G_RHO, G_CHI, G_ER, G_EZ, G_N0, G_N1, G_DENS0, G_DENS1, G_VOL = range(10)
+G_PHI_P, G_PHI_L = 10, 11
 FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "az", "w")
 
 
@@ -31,6 +32,7 @@ class Config(C.Structure):
         ("resize_wcoef", C.c_double),
         ("n_gas", C.c_double), ("T_gas", C.c_double), ("m_gas", C.c_double),
         ("tile_z", C.c_int32), ("tile_r", C.c_int32),
+        ("circuit_C", C.c_double),
     ]
 
 
@@ -75,6 +77,8 @@ def lib():
         L.rzo_get_grid.argtypes = [P, C.c_int, dp]
         L.rzo_set_grid.argtypes = [P, C.c_int, dp]
         L.rzo_absorbed.argtypes = [P, C.c_int, dp]
+        L.rzo_set_circuit.argtypes = [P, C.c_double, C.c_double, C.c_double]
+        L.rzo_circuit.argtypes = [P, dp]
         L.rzo_apply_op.argtypes = [P, dp, dp]
         L.rzo_thomas.argtypes = [C.c_int32, dp, dp, dp, dp, dp]
         u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
@@ -134,7 +138,7 @@ class Oracle:
                                       else mg_fixed_cycles),
                      resize_every=w.resize_every, sort_every=w.sort_every,
                      resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
-                     tile_z=w.tile_z, tile_r=w.tile_r)
+                     tile_z=w.tile_z, tile_r=w.tile_r, circuit_C=w.circuit_C)
         self._cfg = cfg
         self.h = lib().rzo_create(C.byref(cfg))
         if not self.h:
@@ -245,6 +249,15 @@ class Oracle:
 
     def set_grid(self, which, arr):
         assert lib().rzo_set_grid(self.h, which, _f64(np.asarray(arr).reshape(-1))) == 0
+
+    def set_circuit(self, V, Q, Qc):
+        assert lib().rzo_set_circuit(self.h, V, Q, Qc) == 0
+
+    def circuit(self):
+        """{V, Q, Q_c, Q_conv, Q_P, Q_L} of the last solve (external circuit)."""
+        out = np.zeros(6)
+        assert lib().rzo_circuit(self.h, out) == 0
+        return dict(zip(("V", "Q", "Qc", "Qconv", "Qp", "Ql"), out))
 
     def absorbed(self, s):
         out = np.zeros(3)

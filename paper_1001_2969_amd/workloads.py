@@ -69,6 +69,7 @@ class Workload:
     T_gas: float = 300.0
     xsec: str = "constant"
     precision: str = "fp64"
+    circuit_C: float = 0.0  # > 0: blocking capacitor (F) in series with the rf source
 
     @property
     def n_gas(self) -> float:
