@@ -55,7 +55,8 @@ enum { RZPIC_P_ELASTIC = 0, RZPIC_P_EXCITATION = 1, RZPIC_P_IONIZATION = 2 };
  * particle counts N_ij of Sec. 2.4 (kept internally in fixed point). */
 enum {
     RZPIC_G_PHI = 0, RZPIC_G_RHO = 1, RZPIC_G_CHI = 2, RZPIC_G_ER = 3, RZPIC_G_EZ = 4,
-    RZPIC_G_N0 = 5, RZPIC_G_N1 = 6, RZPIC_G_DENS0 = 7, RZPIC_G_DENS1 = 8, RZPIC_G_VOL = 9
+    RZPIC_G_N0 = 5, RZPIC_G_N1 = 6, RZPIC_G_DENS0 = 7, RZPIC_G_DENS1 = 8, RZPIC_G_VOL = 9,
+    RZPIC_G_PHI_P = 10, RZPIC_G_PHI_L = 11  /* external circuit: charge and unit Laplace solutions */
 };
 /* Per-particle Monte Carlo event codes written to rzpic_species_view.mc_event:
  * 0 not a candidate, 1 null collision, 2+k real collision of process k. */
@@ -85,6 +86,11 @@ typedef struct rzpic_config {
     double n_gas, T_gas, m_gas; /* neutral density (m^-3), temperature (K), mass (kg) */
     int32_t tile_z, tile_r;   /* cells per sort tile in z and r (0 -> 16, 32);
                                * at most 2048 tiles                          */
+    double circuit_C;         /* > 0: a blocking capacitor of this capacitance
+                               * (F) between the source V_dc + V_rf sin(2 pi
+                               * f_rf t) and the z=0 electrode, whose potential
+                               * then follows the circuit (Sec. 2.5, see
+                               * rzpic_set_circuit); 0: driven directly      */
 } rzpic_config;
 
 typedef struct rzpic_species_view {
@@ -268,6 +274,23 @@ rzpic_status rzpic_batch_destroy(rzpic_batch *batch);
 /* Change the z = 0 electrode voltage V_dc + V_rf sin(2 pi f_rf t) of later
  * solves (config fields of the same names; finite values, else EINVAL). */
 rzpic_status rzpic_set_voltage(rzpic_ctx *ctx, double V_dc, double V_rf, double f_rf);
+
+/* --- external circuit (config.circuit_C > 0) ----------------------------- */
+/* Sec. 2.5, the superposition of Vahedi: each solve computes phi_P (the
+ * charge with the electrode at 0 V) and phi_L (no charge, electrode at 1 V)
+ * with the same operator and cycling (two solves, warm-started from their
+ * previous solutions), the electrode charges Q_P of phi_P and Q_L of phi_L
+ * (Gauss's law on the electrode nodes' half cells: the displacement
+ * eps0 (1+chi) E through their upper faces and the side face towards the
+ * wall node, less the deposited charge of row 0), the charge Q_conv that
+ * reached the electrode since the previous solve (z = 0 tallies), then
+ *   V = (Q - Q_c + Q_conv + C V_s(t) - Q_P) / (Q_L + C),
+ *   Q <- Q_P + V Q_L,  Q_c <- C (V_s(t) - V),  phi = phi_P + V phi_L.
+ * The state starts at V = Q = Q_c = 0; rzpic_set_circuit sets it
+ * (asynchronous), rzpic_get_circuit reads {V, Q, Q_c, Q_conv, Q_P, Q_L} of
+ * the last solve (synchronises).  EINVAL without a circuit. */
+rzpic_status rzpic_set_circuit(rzpic_ctx *ctx, double V, double Q, double Qc);
+rzpic_status rzpic_get_circuit(rzpic_ctx *ctx, double out[6]);
 
 /* --- adjoint of a collision-free window ---------------------------------- */
 /* Reverse-mode gradient, over a window of N merged steps (Sec. 2.1) without

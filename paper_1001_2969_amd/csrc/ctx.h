@@ -12,6 +12,32 @@
 
 namespace rz {
 
+constexpr double kPi = 3.141592653589793;
+
+// External circuit of the powered electrode (device resident): electrode
+// potential V, electrode charge Q, capacitor charge Q_c, and of the last
+// solve the charge arrived Q_conv and the electrode charges Q_P of the
+// charge solution and Q_L of the unit Laplace solution; the z = 0 tallies
+// (fixed point) the last solve counted up to.
+struct CircuitState {
+    double V, Q, Qc, Qconv, Qp, Ql;
+    unsigned long long prev[2];
+};
+
+struct CircuitArgs {
+    int nr, rule;
+    double hr, hz, C, Vs;
+    const double *eps, *rho, *vol, *phiP, *phiL;
+    const unsigned long long *tally;  // [2][3], z = 0 first
+    double q[2], quantum[2];
+    CircuitState *st;
+};
+
+hipError_t launch_circuit(const CircuitArgs &a, hipStream_t st);
+hipError_t launch_combine(int nn, const double *phiP, const double *phiL, const CircuitState *cs,
+                          double *phi, hipStream_t st);
+hipError_t launch_circuit_set(CircuitState *cs, double V, double Q, double Qc, hipStream_t st);
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -59,6 +85,11 @@ struct rzpic_ctx {
     // grids
     double *phi, *rho, *chi, *er, *ez, *dens[2], *vol, *f, *eps;
     double *phi_alt;  // FP64 cycles sweep the finest level from one phi buffer into the other
+    // external circuit (config.circuit_C > 0): the charge and unit Laplace
+    // solutions with their partner buffers, a zero right-hand side, the state
+    double *phiP = nullptr, *phiP_alt = nullptr, *phiL = nullptr, *phiL_alt = nullptr;
+    double *fzero = nullptr;
+    rz::CircuitState *circ = nullptr;
     void *E2;
     unsigned long long *acc[2];
     unsigned long long *slices = nullptr;

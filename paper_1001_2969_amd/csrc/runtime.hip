@@ -521,11 +521,57 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
                            c->mixed ? c->mg.eps32[c->L] : nullptr, c->f);
         HIPCHK(hipGetLastError());
         HIPCHK(mg_restrict_eps(c->mg, c->mixed, c->st));
-        HIPCHK(mg_set_bc(c->phi, nr, nz, V, c->st));
-        HIPCHK(mg_set_bc(c->phi_alt, nr, nz, V, c->st));
+        if (c->c.circuit_C > 0.0) {
+            HIPCHK(mg_set_bc(c->phiP, nr, nz, 0.0, c->st));
+            HIPCHK(mg_set_bc(c->phiP_alt, nr, nz, 0.0, c->st));
+        } else {
+            HIPCHK(mg_set_bc(c->phi, nr, nz, V, c->st));
+            HIPCHK(mg_set_bc(c->phi_alt, nr, nz, V, c->st));
+        }
     }
     int k = 0;
     double rr = c->last_relres;
+    if (c->c.circuit_C > 0.0) {
+        // external circuit: the charge solution (electrode at 0 V) and the
+        // unit Laplace solution (electrode at 1 V) with the same operator,
+        // then the circuit update and phi = phi_P + V phi_L
+        HIPCHK(mg_set_bc(c->phiL, nr, nz, 1.0, c->st));
+        HIPCHK(mg_set_bc(c->phiL_alt, nr, nz, 1.0, c->st));
+        int k2 = 0;
+        double rr2 = rr;
+        rzpic_status s1 = run_cycles(c, 0.0, c->phiP, c->phiP_alt, c->f, c->c.mg_fixed_cycles,
+                                     c->c.mg_tol, c->c.mg_max_cycles, cycles || relres, &k, &rr);
+        if (s1 != RZPIC_OK && s1 != RZPIC_ENOTCONV) return s1;
+        rzpic_status s2 = run_cycles(c, 1.0, c->phiL, c->phiL_alt, c->fzero,
+                                     c->c.mg_fixed_cycles, c->c.mg_tol, c->c.mg_max_cycles,
+                                     cycles || relres, &k2, &rr2);
+        if (s2 != RZPIC_OK && s2 != RZPIC_ENOTCONV) return s2;
+        CircuitArgs a{};
+        a.nr = nr;
+        a.rule = c->c.chi_face;
+        a.hr = c->hr;
+        a.hz = c->hz;
+        a.C = c->c.circuit_C;
+        a.Vs = V;
+        a.eps = c->eps;
+        a.rho = c->rho;
+        a.vol = c->vol;
+        a.phiP = c->phiP;
+        a.phiL = c->phiL;
+        a.tally = c->tally;
+        for (int s = 0; s < 2; ++s) {
+            a.q[s] = c->sp[s].bound ? c->sp[s].v.q : 0.0;
+            a.quantum[s] = c->quantum[s];
+        }
+        a.st = c->circ;
+        HIPCHK(launch_circuit(a, c->st));
+        HIPCHK(launch_combine(c->nn, c->phiP, c->phiL, c->circ, c->phi, c->st));
+        c->last_cycles = k > k2 ? k : k2;
+        c->last_relres = rr > rr2 ? rr : rr2;
+        if (cycles) *cycles = c->last_cycles;
+        if (relres) *relres = c->last_relres;
+        return s1 != RZPIC_OK ? s1 : s2;
+    }
     rzpic_status st = run_cycles(c, V, c->phi, c->phi_alt, c->f, c->c.mg_fixed_cycles,
                                  c->c.mg_tol, c->c.mg_max_cycles, cycles || relres, &k, &rr);
     c->last_cycles = k;
@@ -723,7 +769,9 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
         // the Monte Carlo counters cleared, in one launch
         const double t = (double)(n + 1) * c->c.dt;
         const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
-        HIPCHK(mg_finalize(grid_args(c, 1), c->mg, c->mixed, c->phi, c->phi_alt, V, c->mcstat,
+        const bool circ = c->c.circuit_C > 0.0;  // then phi_P takes the electrode at 0 V
+        HIPCHK(mg_finalize(grid_args(c, 1), c->mg, c->mixed, circ ? c->phiP : c->phi,
+                           circ ? c->phiP_alt : c->phi_alt, circ ? 0.0 : V, c->mcstat,
                            2 * (1 + kMaxProc), c->st));
     }
     mark(c, 1);
@@ -845,6 +893,8 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         return fail(RZPIC_EINVAL, "resize_every > 0 needs resize_wcoef > 0");
     if (k.sort_every < 0 || k.tile_z < 0 || k.tile_r < 0)
         return fail(RZPIC_EINVAL, "sort_every, tile_z and tile_r must be >= 0");
+    if (!(k.circuit_C >= 0.0) || !std::isfinite(k.circuit_C))
+        return fail(RZPIC_EINVAL, "circuit_C must be finite and >= 0");
 
     rzpic_ctx *c = new rzpic_ctx();
     c->c = k;
@@ -904,6 +954,10 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     A(c->acc[0], nn) A(c->acc[1], nn)
     A(c->cnt, 2) A(c->fix, 2) A(c->crec, 1) A(c->clrec, 2) A(c->tally, 6)
     A(c->mcstat, 2 * (1 + kMaxProc)) A(c->norm, 2) A(c->status, 1) A(c->psteps, 2)
+    if (k.circuit_C > 0.0) {
+        A(c->phiP, nn) A(c->phiP_alt, nn) A(c->phiL, nn) A(c->phiL_alt, nn) A(c->fzero, nn)
+        A(c->circ, 1)
+    }
     // LDS privatisation of the whole deposit grid when it fits.
     const size_t lds_need = nn * sizeof(unsigned long long) + 1024;
     if (lds_need <= c->lds_block && !std::getenv("RZPIC_NO_LDS")) {
@@ -1243,6 +1297,32 @@ rzpic_status rzpic_set_voltage(rzpic_ctx *c, double V_dc, double V_rf, double f_
     return RZPIC_OK;
 }
 
+rzpic_status rzpic_set_circuit(rzpic_ctx *c, double V, double Q, double Qc)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (!c->circ) return fail(RZPIC_EINVAL, "the context has no external circuit (circuit_C = 0)");
+    if (!std::isfinite(V) || !std::isfinite(Q) || !std::isfinite(Qc))
+        return fail(RZPIC_EINVAL, "circuit state must be finite");
+    HIPCHK(launch_circuit_set(c->circ, V, Q, Qc, c->st));
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_get_circuit(rzpic_ctx *c, double out[6])
+{
+    if (!c || !out) return fail(RZPIC_EINVAL, "null argument");
+    if (!c->circ) return fail(RZPIC_EINVAL, "the context has no external circuit (circuit_C = 0)");
+    CircuitState h{};
+    HIPCHK(hipMemcpyAsync(&h, c->circ, sizeof h, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    out[0] = h.V;
+    out[1] = h.Q;
+    out[2] = h.Qc;
+    out[3] = h.Qconv;
+    out[4] = h.Qp;
+    out[5] = h.Ql;
+    return RZPIC_OK;
+}
+
 rzpic_status rzpic_efield(rzpic_ctx *c)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
@@ -1320,6 +1400,12 @@ rzpic_status rzpic_grid_copy(rzpic_ctx *c, int32_t which, double *dev, int32_t t
     case RZPIC_G_DENS0: src = c->dens[0]; break;
     case RZPIC_G_DENS1: src = c->dens[1]; break;
     case RZPIC_G_VOL: src = c->vol; break;
+    case RZPIC_G_PHI_P:
+    case RZPIC_G_PHI_L:
+        if (!c->circ) return fail(RZPIC_EINVAL, "grid %d needs the external circuit", which);
+        if (to_ctx) return fail(RZPIC_EINVAL, "grid %d is read-only", which);
+        src = which == RZPIC_G_PHI_P ? c->phiP : c->phiL;
+        break;
     case RZPIC_G_N0:
     case RZPIC_G_N1: {
         int s = which - RZPIC_G_N0;

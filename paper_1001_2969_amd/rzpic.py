@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "librzpic.so")
 
 FP64, MIXED = 0, 1
 G_PHI, G_RHO, G_CHI, G_ER, G_EZ, G_N0, G_N1, G_DENS0, G_DENS1, G_VOL = range(10)
+G_PHI_P, G_PHI_L = 10, 11
 FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "az", "w")
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ECAPACITY", 5: "ENOTCONV",
           6: "ENUMERIC", 7: "ESTATE"}
@@ -29,6 +30,7 @@ EXPORTS = (
     "rzpic_batch_create", "rzpic_batch_step", "rzpic_batch_stats", "rzpic_batch_destroy",
     "rzpic_batch_set_graph", "rzpic_set_voltage", "rzpic_adjoint_create",
     "rzpic_adjoint_forward", "rzpic_adjoint_backward", "rzpic_adjoint_destroy",
+    "rzpic_set_circuit", "rzpic_get_circuit",
 )
 
 
@@ -51,6 +53,7 @@ class Config(C.Structure):
         ("resize_wcoef", C.c_double),
         ("n_gas", C.c_double), ("T_gas", C.c_double), ("m_gas", C.c_double),
         ("tile_z", C.c_int32), ("tile_r", C.c_int32),
+        ("circuit_C", C.c_double),
     ]
 
 
@@ -113,6 +116,7 @@ def lib():
             "rzpic_batch_step": [P, C.c_int64], "rzpic_batch_stats": [P, P],
             "rzpic_batch_destroy": [P], "rzpic_batch_set_graph": [P, I],
             "rzpic_set_voltage": [P, D, D, D],
+            "rzpic_set_circuit": [P, D, D, D], "rzpic_get_circuit": [P, P],
             "rzpic_adjoint_create": [P, C.POINTER(AdjointConfig), C.POINTER(P)],
             "rzpic_adjoint_forward": [P, C.c_int64, C.POINTER(D)],
             "rzpic_adjoint_backward": [P, P, P, P, P], "rzpic_adjoint_destroy": [P],
@@ -164,7 +168,7 @@ class Context:
                                       else mg_fixed_cycles),
                      resize_every=w.resize_every, sort_every=w.sort_every,
                      resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
-                     tile_z=w.tile_z, tile_r=w.tile_r)
+                     tile_z=w.tile_z, tile_r=w.tile_r, circuit_C=w.circuit_C)
         self._cfg = cfg
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
@@ -288,6 +292,15 @@ class Context:
     def set_voltage(self, V_dc, V_rf, f_rf=None):
         f = self.w.f_rf if f_rf is None else f_rf
         _check(lib().rzpic_set_voltage(self.h, V_dc, V_rf, f))
+
+    def set_circuit(self, V, Q, Qc):
+        _check(lib().rzpic_set_circuit(self.h, V, Q, Qc))
+
+    def circuit(self):
+        """{V, Q, Q_c, Q_conv, Q_P, Q_L} of the last solve (external circuit)."""
+        out = (C.c_double * 6)()
+        _check(lib().rzpic_get_circuit(self.h, C.cast(out, C.c_void_p)))
+        return dict(zip(("V", "Q", "Qc", "Qconv", "Qp", "Ql"), list(out)))
 
     def sync(self):
         _check(lib().rzpic_sync(self.h))
