@@ -145,6 +145,19 @@ static void normal_pair(const double u[2], double out[2])
 
 static int ispow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
+/* Time step of a species: ions take K dt when they are subcycled every K
+ * steps (Sec. 2.7, the subcycling of Vahedi et al.), electrons dt. */
+static int ion_K(const rzo *o) { return o->c.ion_subcycle > 1 ? o->c.ion_subcycle : 1; }
+
+static double dt_of(const rzo *o, const species *sp)
+{
+    return sp == &o->sp[1] ? (double)ion_K(o) * o->c.dt : o->c.dt;
+}
+
+/* Whether the ions move in step n: every K-th step, n = K-1, 2K-1, ... */
+static int ion_step(const rzo *o, int64_t n) { return n % ion_K(o) == ion_K(o) - 1; }
+
+
 rzo *rzo_create(const rzo_config *cfg)
 {
     if (!cfg || cfg->nr < 3 || cfg->nz < 3 || !ispow2(cfg->nz - 1) || !(cfg->R > 0) ||
@@ -378,7 +391,7 @@ int rzo_set_xsec(rzo *o, int s, int nproc, const int32_t *kind, const double *th
         if (nu > numax) numax = nu;
     }
     sp->nu_max = numax;
-    sp->p_null = -expm1(-numax * o->c.dt);
+    sp->p_null = -expm1(-numax * dt_of(o, sp));
     return 0;
 }
 
@@ -459,24 +472,28 @@ static void deposit_all(rzo *o)
     }
 }
 
-/* n = N/V, rho = sum q n, chi = sum q^2 n dt^2 / (2 m eps0): the susceptibility
- * of Sec. 2.1 written in SI units (one half of (omega_p dt)^2 per species). */
-static void finalize(rzo *o)
+/* n = N/V, rho = sum q n, chi = sum q^2 n dt_s^2 / (2 m eps0): the
+ * susceptibility of Sec. 2.1 written in SI units (one half of (omega_p dt_s)^2
+ * per species, dt_s its time step).  `ions` = 0: the ions do not move in the
+ * coming step, so they add charge but no susceptibility. */
+static void finalize_ions(rzo *o, int ions)
 {
-    double dt = o->c.dt;
     for (int g = 0; g < o->nn; ++g) {
         double rho = 0.0, chi = 0.0;
         for (int s = 0; s < 2; ++s) {
             double n = o->N[s][g] / o->vol[g];
             o->dens[s][g] = n;
             double q = o->sp[s].q, m = o->sp[s].m;
+            double dt = dt_of(o, &o->sp[s]);
             rho += q * n;
-            chi += q * q * n * dt * dt / (2.0 * m * EPS0);
+            if (s == 0 || ions) chi += q * q * n * dt * dt / (2.0 * m * EPS0);
         }
         o->rho[g] = rho;
         o->chi[g] = chi;
     }
 }
+
+static void finalize(rzo *o) { finalize_ions(o, 1); }
 
 int rzo_deposit(rzo *o)
 {
@@ -508,7 +525,7 @@ static int absorb(rzo *o, species *sp, int64_t p)
  * the rotated a_theta is dropped. */
 static int first_push_one(rzo *o, species *sp, int64_t p)
 {
-    double dt = o->c.dt;
+    double dt = dt_of(o, sp);
     double vx = sp->vr[p] + 0.5 * sp->ar[p] * dt;
     double vy = sp->vt[p];
     double x = sp->r[p] + vx * dt;
@@ -535,7 +552,7 @@ static int first_push_one(rzo *o, species *sp, int64_t p)
  * (radial position, velocity and acceleration made positive) and absorption. */
 static int final_push_one(rzo *o, species *sp, int64_t p)
 {
-    double dt = o->c.dt;
+    double dt = dt_of(o, sp);
     double qm = sp->q / sp->m;
     double Er, Ez;
     gather(o, sp->r[p], sp->z[p], &Er, &Ez);
@@ -1356,15 +1373,20 @@ int rzo_prologue(rzo *o)
 
 int rzo_step(rzo *o, int64_t n, int merged)
 {
-    finalize(o);
+    /* subcycled ions (Sec. 2.7): they move only in every K-th step; in the
+     * others their deposit is kept and they add no susceptibility */
+    const int ions = ion_step(o, n);
+    finalize_ions(o, ions);
     int32_t cyc;
     double rr;
     int st = rzo_solve(o, (double)(n + 1) * o->c.dt, &cyc, &rr);
     rzo_efield(o);
     uint32_t step = (uint32_t)n;
     if (merged) {
-        for (int s = 0; s < 2; ++s) memset(o->N[s], 0, (size_t)o->nn * sizeof(double));
+        for (int s = 0; s < 2; ++s)
+            if (s == 0 || ions) memset(o->N[s], 0, (size_t)o->nn * sizeof(double));
         for (int s = 0; s < 2; ++s) {
+            if (s == 1 && !ions) continue;
             species *sp = &o->sp[s];
             int do_mc = sp->mc_model != RZO_MC_NONE && sp->nproc > 0;
             if (do_mc && ensure_ev(sp) != 0) return -2;
@@ -1384,9 +1406,18 @@ int rzo_step(rzo *o, int64_t n, int merged)
             }
         }
     } else {
-        for (int s = 0; s < 2; ++s) rzo_push_final(o, s);
-        for (int s = 0; s < 2; ++s) rzo_collide(o, s, n);
-        for (int s = 0; s < 2; ++s) rzo_push_first(o, s);
+        for (int s = 0; s < 2; ++s)
+            if (s == 0 || ions) rzo_push_final(o, s);
+        for (int s = 0; s < 2; ++s)
+            if (s == 0 || ions) rzo_collide(o, s, n);
+        for (int s = 0; s < 2; ++s) {
+            if (s == 0 || ions) {
+                rzo_push_first(o, s);
+            } else {
+                species *sp = &o->sp[s]; /* children of this step's ionizations */
+                for (int64_t c = sp->n; c < sp->n + sp->npend; ++c) first_push_one(o, sp, c);
+            }
+        }
         deposit_all(o);
     }
     for (int s = 0; s < 2; ++s) rzo_compact(o, s);

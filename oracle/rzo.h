@@ -66,6 +66,9 @@ typedef struct {
     int32_t tile_z, tile_r;  /* tile of the sort key, in cells              */
     double circuit_C;        /* >0: blocking capacitor (F) between the source
                               * V_dc+V_rf sin(2 pi f t) and the z=0 electrode  */
+    int32_t ion_subcycle;    /* K >= 2: ions (species 1) move every K-th step
+                              * with dt_i = K dt; 0 or 1: every step         */
+    int32_t reserved;
 } rzo_config;
 
 rzo *rzo_create(const rzo_config *cfg);

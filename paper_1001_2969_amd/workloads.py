@@ -70,6 +70,7 @@ class Workload:
     xsec: str = "constant"
     precision: str = "fp64"
     circuit_C: float = 0.0  # > 0: blocking capacitor (F) in series with the rf source
+    ion_subcycle: int = 0  # K >= 2: ions move every K-th step with K dt
 
     @property
     def n_gas(self) -> float:
