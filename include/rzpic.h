@@ -91,6 +91,16 @@ typedef struct rzpic_config {
                                * f_rf t) and the z=0 electrode, whose potential
                                * then follows the circuit (Sec. 2.5, see
                                * rzpic_set_circuit); 0: driven directly      */
+    int32_t ion_subcycle;     /* K >= 2: the ions (species 1) move only in every
+                               * K-th step (steps K-1, 2K-1, ...) with time step
+                               * K dt (pushes, P_null, chi), the subcycling of
+                               * Sec. 2.7; in the other steps their deposit is
+                               * kept and they add charge but no chi, and ions
+                               * born from ionizations are first-pushed with
+                               * K dt.  0 or 1: every step.  rzpic_step only:
+                               * the single operations act as in a step where
+                               * the ions move. */
+    int32_t reserved1;
 } rzpic_config;
 
 typedef struct rzpic_species_view {

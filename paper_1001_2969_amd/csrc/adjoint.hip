@@ -643,6 +643,8 @@ rzpic_status check_ctx(const rzpic_ctx *c)
         return rz_fail(RZPIC_EINVAL, "adjoint: needs the averaged face permittivity");
     if (c->c.circuit_C > 0.0)
         return rz_fail(RZPIC_EINVAL, "adjoint: the electrode must be driven directly (circuit_C = 0)");
+    if (c->c.ion_subcycle > 1)
+        return rz_fail(RZPIC_EINVAL, "adjoint: ions must move every step (ion_subcycle <= 1)");
     if (c->children_pending[0] || c->children_pending[1])
         return rz_fail(RZPIC_ESTATE, "adjoint: new particles are staged");
     return RZPIC_OK;

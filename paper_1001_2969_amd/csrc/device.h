@@ -312,9 +312,10 @@ __device__ __forceinline__ int collide_candidate(const SpeciesK &sp, const Phys 
     return 0;
 }
 
-// Node k of the deposit: n_s = N_s / V, rho = sum q n, chi = sum q^2 n dt^2 /
-// (2 m eps0) (the implicit susceptibility of Sec. 2.1 in SI), eps = 1 + chi,
-// f = rho / eps0; returns eps.  A negative accumulator means the fixed-point
+// Node k of the deposit: n_s = N_s / V, rho = sum q n, chi = sum q^2 n dt_s^2 /
+// (2 m eps0) (the implicit susceptibility of Sec. 2.1 in SI, dt_s the
+// species' time step; the ion term only when the ions move in the coming
+// step), eps = 1 + chi, f = rho / eps0; returns eps.  A negative accumulator means the fixed-point
 // range overflowed.
 __device__ __forceinline__ double finalize_node(const GridArgs &g, int k)
 {
@@ -328,7 +329,7 @@ __device__ __forceinline__ double finalize_node(const GridArgs &g, int k)
     rho += g.q0 * n0;
     chi += g.q0 * g.q0 * n0 * g.dt * g.dt / (2.0 * g.m0 * kEps0);
     rho += g.q1 * n1;
-    chi += g.q1 * g.q1 * n1 * g.dt * g.dt / (2.0 * g.m1 * kEps0);
+    if (g.ion_chi) chi += g.q1 * g.q1 * n1 * g.dt1 * g.dt1 / (2.0 * g.m1 * kEps0);
     g.rho[k] = rho;
     g.chi[k] = chi;
     const double eps = 1.0 + chi;
@@ -337,7 +338,7 @@ __device__ __forceinline__ double finalize_node(const GridArgs &g, int k)
     g.f[k] = rho / kEps0;
     if (g.zero_acc) {
         g.acc0w[k] = 0;
-        g.acc1w[k] = 0;
+        if (!g.keep1) g.acc1w[k] = 0;
     }
     return eps;
 }

@@ -77,6 +77,7 @@ struct SpeciesK {
     int s, mc_model;
     double q, m, qm;
     double k1, k2;          // 0.5 q/m dt^2, 0.5 q/m dt
+    double dt;              // time step of the species (K dt for subcycled ions)
     double inv_quantum;     // 2^bits / w_ref
     double p_null, nu_max;
     double ekin;            // 0.5 * (pair mass) / e : eV per (m/s)^2
@@ -90,6 +91,7 @@ struct Phys {
     uint64_t seed;
     double ion_acc_ratio;   // q_i m_e / (q_e m_i) for new ions
     double ion_inv_quantum; // fixed-point scale of the ion deposit
+    double ion_dt;          // time step of the ions (first push of new ions)
 };
 
 struct Counts {      // per species, device resident
@@ -274,6 +276,9 @@ struct GridArgs {
     int zero_acc;
     unsigned long long *acc0w, *acc1w;
     int32_t *status;
+    double dt1;   // ion time step in chi
+    int ion_chi;  // the ions move in the coming step: their chi term is on
+    int keep1;    // keep the ion deposit (subcycled ions that do not move)
 };
 hipError_t launch_finalize(const GridArgs &g, hipStream_t st);
 template <typename T>

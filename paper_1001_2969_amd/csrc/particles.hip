@@ -166,7 +166,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
     const int wpb = blockDim.x >> 6;
     const int64_t wave = ((int64_t)lb * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gb * blockDim.x) >> 6;
-    const T dt = (T)a.phys.dt;
+    const T dt = (T)a.sp.dt;
     const T k1 = (T)a.sp.k1, k2 = (T)a.sp.k2, qm = (T)a.sp.qm;
     constexpr bool kLds = (MODE & M_LDS) != 0;
     constexpr bool kTile = (MODE & M_TILE) != 0;
@@ -403,7 +403,7 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
     const Mesh &m = a.mesh;
     constexpr bool kLds = (MODE & M_LDS) != 0;
     constexpr bool kFirst = (MODE & M_FIRST) != 0;
-    const T dt = (T)a.phys.dt;
+    const T dt = (T)a.sp.dt;
     unsigned long long *dep = a.acc;
     if (threadIdx.x < 1 + kMaxProc) sh_stat[threadIdx.x] = 0;
     if (kLds) {
@@ -481,7 +481,7 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
                     tally_add(a.tally, b, (double)ne.w, a.sp.inv_quantum);
                     ne_live = false;
                 }
-                first_push<T>(ni, dt);
+                first_push<T>(ni, (T)a.phys.ion_dt);
                 b = boundary_of(ni, a.phys);
                 if (b >= 0) {
                     tally_add(a.tally_ion, b, (double)ni.w, a.phys.ion_inv_quantum);
@@ -562,7 +562,7 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_staged(PassArgs<T> a, int cs)
 {
     const Mesh &m = a.mesh;
-    const T dt = (T)a.phys.dt;
+    const T dt = (T)a.sp.dt;
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;

@@ -84,6 +84,11 @@ template <typename T> rzpic_status dalloc(rzpic_ctx *c, T **p, size_t count)
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// Ions subcycled every K >= 2 steps take K dt; everything else dt.
+int ion_K(const rzpic_ctx *c) { return c->c.ion_subcycle > 1 ? c->c.ion_subcycle : 1; }
+
+double dt_of(const rzpic_ctx *c, int s) { return s == 1 ? ion_K(c) * c->c.dt : c->c.dt; }
+
 Mesh mesh_of(const rzpic_ctx *c)
 {
     Mesh m;
@@ -114,6 +119,7 @@ Phys phys_of(const rzpic_ctx *c)
     const rzpic_species_view &e = c->sp[0].v, &i = c->sp[1].v;
     p.ion_acc_ratio = (c->sp[0].bound && c->sp[1].bound) ? (i.q * e.m) / (e.q * i.m) : 0.0;
     p.ion_inv_quantum = 1.0 / c->quantum[1];
+    p.ion_dt = dt_of(c, 1);
     return p;
 }
 
@@ -134,8 +140,9 @@ SpeciesK species_of(const rzpic_ctx *c, int s)
     k.q = v.q;
     k.m = v.m;
     k.qm = v.q / v.m;
-    k.k1 = 0.5 * k.qm * c->c.dt * c->c.dt;
-    k.k2 = 0.5 * k.qm * c->c.dt;
+    k.dt = dt_of(c, s);
+    k.k1 = 0.5 * k.qm * k.dt * k.dt;
+    k.k2 = 0.5 * k.qm * k.dt;
     k.inv_quantum = 1.0 / c->quantum[s];
     k.p_null = ss.p_null;
     k.nu_max = ss.nu_max;
@@ -282,6 +289,7 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
     }
     const bool mc = (mode & M_MC) && a.sp.mc_model != RZPIC_MC_NONE;
     if (mode & M_MC) HIPCHK(launch_fill_u64(a.mcstat, 1 + kMaxProc, c->st));
+    if ((mode & M_FINAL) && (mode & M_LISTS)) a.psteps = c->psteps + s;  // a merged step's pass
     a.nbuckets = blocks;
     a.bucket_waves = threads / 64;
     if (blocks * (threads / 64) > kMaxWaves)
@@ -592,7 +600,9 @@ rzpic_status efield_impl(rzpic_ctx *c)
     return RZPIC_OK;
 }
 
-GridArgs grid_args(rzpic_ctx *c, int zero_acc)
+// ions: the ions move in the coming step (their chi term on, their deposit
+// rebuilt by it); otherwise their deposit is kept and they add charge only.
+GridArgs grid_args(rzpic_ctx *c, int zero_acc, bool ions = true)
 {
     GridArgs g{};
     g.nr = c->c.nr;
@@ -621,6 +631,9 @@ GridArgs grid_args(rzpic_ctx *c, int zero_acc)
     g.acc0w = c->acc[0];
     g.acc1w = c->acc[1];
     g.status = c->status;
+    g.dt1 = dt_of(c, 1);
+    g.ion_chi = ions ? 1 : 0;
+    g.keep1 = ions ? 0 : 1;
     return g;
 }
 
@@ -764,13 +777,15 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
         return fail(RZPIC_ESTATE, "new particles are staged: call rzpic_compact first");
     if (c->timing && c->ev_used >= rzpic_ctx::kPool) TRY(flush_timing(c));
     mark(c, 0);
+    // subcycled ions move only in every K-th step
+    const bool ions = n % ion_K(c) == ion_K(c) - 1;
     {
         // finalize, eps restriction, Dirichlet values of both phi buffers and
         // the Monte Carlo counters cleared, in one launch
         const double t = (double)(n + 1) * c->c.dt;
         const double V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
         const bool circ = c->c.circuit_C > 0.0;  // then phi_P takes the electrode at 0 V
-        HIPCHK(mg_finalize(grid_args(c, 1), c->mg, c->mixed, circ ? c->phiP : c->phi,
+        HIPCHK(mg_finalize(grid_args(c, 1, ions), c->mg, c->mixed, circ ? c->phiP : c->phi,
                            circ ? c->phiP_alt : c->phi_alt, circ ? 0.0 : V, c->mcstat,
                            2 * (1 + kMaxProc), c->st));
     }
@@ -780,7 +795,17 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
     mark(c, 2);
     TRY(efield_impl(c));
     mark(c, 3);
-    TRY(run_pass_both<T>(c, (uint32_t)n));
+    if (ions) {
+        TRY(run_pass_both<T>(c, (uint32_t)n));
+    } else {
+        // electrons alone; the ions keep their state, lists and deposit (new
+        // ions from ionizations are added to it)
+        mark(c, 4);
+        TRY(run_pass<T>(c, 0, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS, (uint32_t)n));
+        mark(c, 5);
+        HIPCHK(launch_fill_u64(c->sp[1].ch.dead, c->sp[1].nchunks_max, c->st));
+        mark(c, 6);
+    }
     c->children_pending[0] = c->children_pending[1] = c->sp[0].v.mc_model == RZPIC_MC_ELECTRON;
     c->children_scanned = false;
     TRY(run_fixup<T>(c, 3));
@@ -895,6 +920,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         return fail(RZPIC_EINVAL, "sort_every, tile_z and tile_r must be >= 0");
     if (!(k.circuit_C >= 0.0) || !std::isfinite(k.circuit_C))
         return fail(RZPIC_EINVAL, "circuit_C must be finite and >= 0");
+    if (k.ion_subcycle < 0) return fail(RZPIC_EINVAL, "ion_subcycle must be >= 0");
 
     rzpic_ctx *c = new rzpic_ctx();
     c->c = k;
@@ -1195,7 +1221,7 @@ rzpic_status rzpic_set_xsec(rzpic_ctx *c, int32_t s, int32_t nproc, const int32_
         if (nu > numax) numax = nu;
     }
     ss.nu_max = numax;
-    ss.p_null = -std::expm1(-numax * c->c.dt);
+    ss.p_null = -std::expm1(-numax * dt_of(c, s));
     ss.has_xsec = true;
     return RZPIC_OK;
 }

@@ -54,6 +54,7 @@ class Config(C.Structure):
         ("n_gas", C.c_double), ("T_gas", C.c_double), ("m_gas", C.c_double),
         ("tile_z", C.c_int32), ("tile_r", C.c_int32),
         ("circuit_C", C.c_double),
+        ("ion_subcycle", C.c_int32), ("reserved1", C.c_int32),
     ]
 
 
@@ -168,7 +169,8 @@ class Context:
                                       else mg_fixed_cycles),
                      resize_every=w.resize_every, sort_every=w.sort_every,
                      resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
-                     tile_z=w.tile_z, tile_r=w.tile_r, circuit_C=w.circuit_C)
+                     tile_z=w.tile_z, tile_r=w.tile_r, circuit_C=w.circuit_C,
+                     ion_subcycle=w.ion_subcycle)
         self._cfg = cfg
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
