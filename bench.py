@@ -370,6 +370,33 @@ def adjoint_run(reps=2):
     return out
 
 
+def circuit_and_subcycle(steps, warmup):
+    """The headline workload (129x65, 2M + 2M, mixed, 3 V-cycles per solve)
+    with a 10 pF blocking capacitor between the rf source and the electrode
+    (two solves per step, the circuit update), with the ions subcycled every
+    4 steps, and with both: ms per step against the plain form measured the
+    same way.  Particle-steps count the particles a step moves (ions only in
+    their steps), so ms per simulated step is the comparison."""
+    from paper_1001_2969_amd import workloads as wl
+
+    base = wl.rf_129x65()
+    forms = {"plain": base, "circuit_10pF": base.replace(circuit_C=1e-11),
+             "ions_every_4": base.replace(ion_subcycle=4),
+             "circuit_and_ions_every_4": base.replace(circuit_C=1e-11, ion_subcycle=4)}
+    out = {"workload": base.name, "precision": "mixed"}
+    for name, w in forms.items():
+        ctx, r = run_gpu(w, "mixed", steps, warmup, timing_steps=20)
+        tm = r["timing"]
+        out[name] = {"ms_per_step": r["ms_per_step"], "value": r["value"],
+                     "solve_ms": tm["solve_ms"], "pass_ms": tm["pass_ms"]}
+        if w.circuit_C > 0:
+            out[name]["circuit"] = ctx.circuit()
+        ctx.close()
+    for name in forms:
+        out[name]["step_time_over_plain"] = out[name]["ms_per_step"] / out["plain"]["ms_per_step"]
+    return out
+
+
 def pmc_run(steps, workload):
     """Short run for hardware-counter passes: a few merged steps of the mixed
     workload, then a plain device copy of known size (the calibration of the
@@ -413,6 +440,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the 257x129 / 4M-per-species gradient window")
+    ap.add_argument("--no-circuit", action="store_true",
+                    help="skip the external-circuit and ion-subcycling forms")
     ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
                     help="only a short mixed run plus a copy calibration (for counter passes)")
     ap.add_argument("--pmc-workload", default="rf_129x65", choices=["rf_129x65", "large_513x129"])
@@ -458,6 +487,10 @@ def main():
     if not args.no_batch:
         batch = batch_run(args.batch_steps, 3)
         print(f"# batch: {json.dumps(batch)}", file=sys.stderr, flush=True)
+    circ = None
+    if not args.no_circuit:
+        circ = circuit_and_subcycle(100, 5)
+        print(f"# circuit/subcycle: {json.dumps(circ)}", file=sys.stderr, flush=True)
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_run()
@@ -518,6 +551,7 @@ def main():
         "vcycle_by_mesh": vmesh,
         "batch_64": batch,
         "adjoint_window": adjoint,
+        "circuit_and_subcycling": circ,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -289,7 +289,6 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
     }
     const bool mc = (mode & M_MC) && a.sp.mc_model != RZPIC_MC_NONE;
     if (mode & M_MC) HIPCHK(launch_fill_u64(a.mcstat, 1 + kMaxProc, c->st));
-    if ((mode & M_FINAL) && (mode & M_LISTS)) a.psteps = c->psteps + s;  // a merged step's pass
     a.nbuckets = blocks;
     a.bucket_waves = threads / 64;
     if (blocks * (threads / 64) > kMaxWaves)
@@ -325,8 +324,10 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
 // The merged step's particle work for both species in two launches: the
 // fused pass of both species side by side (each block privatises the grid of
 // its species in LDS), then the collision kernels of both species with the
-// sum of the LDS slices into the two deposit grids beside them.
-template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
+// sum of the LDS slices into the two deposit grids beside them.  ions =
+// false (subcycled ions in a step where they do not move): no ion blocks in
+// either launch, every LDS slice to the electrons.
+template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bool ions = true)
 {
     PassArgs<T> a[2] = {pass_args<T>(c, 0, step), pass_args<T>(c, 1, step)};
     const int threads = c->pass_threads;
@@ -338,12 +339,17 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
         lds = (size_t)c->nn * sizeof(unsigned long long);
         b[0] = pass_blocks(c, 0, c->slice_blocks / 2);
         b[1] = pass_blocks(c, 1, c->slice_blocks - c->slice_blocks / 2);
+        if (!ions) {  // the electrons take the ions' blocks too
+            b[0] = b[0] + b[1] < c->slice_blocks ? b[0] + b[1] : c->slice_blocks;
+            b[1] = 0;
+        }
     } else {
         // grid larger than LDS: contiguous block ranges with LDS windows of
         // the tiles planned at the last sort (global atomics without a plan)
         mode |= M_TILE;
         lds = (size_t)kWinNodes * sizeof(unsigned long long);
         for (int s = 0; s < 2; ++s) b[s] = tiled_blocks(c, s);
+        if (!ions) b[1] = 0;
     }
     for (int s = 0; s < 2; ++s) {
         a[s].psteps = c->psteps + s;
@@ -368,6 +374,7 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step)
         cb[s] = (want + wpb - 1) / wpb;
         if (a[s].sp.mc_model == RZPIC_MC_NONE) cb[s] = 1;
     }
+    if (!ions) cb[1] = 0;  // no ion candidates were collected
     SliceSum r{};
     if (mode & M_LDS) {
         for (int s = 0; s < 2; ++s) {
@@ -795,17 +802,9 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
     mark(c, 2);
     TRY(efield_impl(c));
     mark(c, 3);
-    if (ions) {
-        TRY(run_pass_both<T>(c, (uint32_t)n));
-    } else {
-        // electrons alone; the ions keep their state, lists and deposit (new
-        // ions from ionizations are added to it)
-        mark(c, 4);
-        TRY(run_pass<T>(c, 0, M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS, (uint32_t)n));
-        mark(c, 5);
+    TRY(run_pass_both<T>(c, (uint32_t)n, ions));
+    if (!ions)  // the ions keep state and deposit; their compaction only appends children
         HIPCHK(launch_fill_u64(c->sp[1].ch.dead, c->sp[1].nchunks_max, c->st));
-        mark(c, 6);
-    }
     c->children_pending[0] = c->children_pending[1] = c->sp[0].v.mc_model == RZPIC_MC_ELECTRON;
     c->children_scanned = false;
     TRY(run_fixup<T>(c, 3));
