@@ -36,6 +36,7 @@ typedef struct {
     int64_t npend;  /* children created this step, stored at [n, n+npend)  */
     int64_t cap;
     double *r, *z, *vr, *vt, *vz, *ar, *az, *w;
+    double *at;     /* a_theta of the global X-Y-Z push (zero otherwise)    */
     uint64_t *id;
     unsigned char *dead;
     uint8_t *ev;
@@ -235,7 +236,7 @@ rzo *rzo_create(const rzo_config *cfg)
 static void free_species(species *sp)
 {
     free(sp->r); free(sp->z); free(sp->vr); free(sp->vt); free(sp->vz);
-    free(sp->ar); free(sp->az); free(sp->w); free(sp->id); free(sp->dead);
+    free(sp->ar); free(sp->az); free(sp->w); free(sp->id); free(sp->dead); free(sp->at);
     free(sp->ev); free(sp->sigma);
 }
 
@@ -268,6 +269,7 @@ static int grow(species *sp, int64_t need)
     } while (0)
     RE(sp->r, double); RE(sp->z, double); RE(sp->vr, double); RE(sp->vt, double);
     RE(sp->vz, double); RE(sp->ar, double); RE(sp->az, double); RE(sp->w, double);
+    RE(sp->at, double);
     RE(sp->id, uint64_t); RE(sp->dead, unsigned char);
 #undef RE
     sp->cap = cap;
@@ -295,11 +297,26 @@ int rzo_set_particles(rzo *o, int s, int64_t n, const double *r, const double *z
     memcpy(sp->r, r, b); memcpy(sp->z, z, b); memcpy(sp->vr, vr, b);
     memcpy(sp->vt, vt, b); memcpy(sp->vz, vz, b); memcpy(sp->ar, ar, b);
     memcpy(sp->az, az, b); memcpy(sp->w, w, b);
+    memset(sp->at, 0, b);
     memcpy(sp->id, id, (size_t)n * sizeof(uint64_t));
     memset(sp->dead, 0, (size_t)n);
     sp->n = n;
     sp->npend = 0;
     sp->next_id = next_id;
+    return 0;
+}
+
+int rzo_set_at(rzo *o, int s, int64_t n, const double *at)
+{
+    if (!o || s < 0 || s > 1 || n < 0 || n > o->sp[s].n) return -1;
+    memcpy(o->sp[s].at, at, (size_t)n * sizeof(double));
+    return 0;
+}
+
+int rzo_get_at(const rzo *o, int s, double *at)
+{
+    if (!o || s < 0 || s > 1) return -1;
+    memcpy(at, o->sp[s].at, (size_t)o->sp[s].n * sizeof(double));
     return 0;
 }
 
@@ -526,8 +543,9 @@ static int absorb(rzo *o, species *sp, int64_t p)
 static int first_push_one(rzo *o, species *sp, int64_t p)
 {
     double dt = dt_of(o, sp);
+    const int xyz = o->c.push_form == RZO_PUSH_XYZ;
     double vx = sp->vr[p] + 0.5 * sp->ar[p] * dt;
-    double vy = sp->vt[p];
+    double vy = xyz ? sp->vt[p] + 0.5 * sp->at[p] * dt : sp->vt[p];
     double x = sp->r[p] + vx * dt;
     double y = vy * dt;
     double vz = sp->vz[p] + 0.5 * sp->az[p] * dt;
@@ -543,7 +561,13 @@ static int first_push_one(rzo *o, species *sp, int64_t p)
     sp->vr[p] = vx * c + vy * s;
     sp->vt[p] = -vx * s + vy * c;
     sp->vz[p] = vz;
-    sp->ar[p] = sp->ar[p] * c;
+    if (xyz) {
+        double ar = sp->ar[p], at = sp->at[p];
+        sp->ar[p] = ar * c + at * s;
+        sp->at[p] = -ar * s + at * c;
+    } else {
+        sp->ar[p] = sp->ar[p] * c;
+    }
     return absorb(o, sp, p);
 }
 
@@ -563,7 +587,22 @@ static int final_push_one(rzo *o, species *sp, int64_t p)
     double vz = sp->vz[p] + 0.5 * aEz * dt;
     double ar = 0.5 * (aEr + sp->ar[p]);
     double az = 0.5 * (aEz + sp->az[p]);
-    if (r < 0.0) {
+    if (o->c.push_form == RZO_PUSH_XYZ) {
+        /* Cartesian final push: E has no theta component at the particle, so
+         * a_theta is damped by the same average; a particle pushed through
+         * the axis continues on the other side (the local frame turns by pi) */
+        double at = 0.5 * sp->at[p];
+        double vt = sp->vt[p];
+        if (r < 0.0) {
+            r = -r;
+            vr = -vr;
+            vt = -vt;
+            ar = -ar;
+            at = -at;
+        }
+        sp->vt[p] = vt;
+        sp->at[p] = at;
+    } else if (r < 0.0) {
         r = -r;
         vr = fabs(vr);
         ar = fabs(ar);
@@ -640,12 +679,12 @@ static double cos_chi_e(double eps, double R)
 }
 
 static int64_t append(species *sp, double r, double z, double vr, double vt, double vz,
-                      double ar, double az, double w)
+                      double ar, double az, double w, double at)
 {
     int64_t k = sp->n + sp->npend;
     if (grow(sp, k + 1) != 0) return -1;
     sp->r[k] = r; sp->z[k] = z; sp->vr[k] = vr; sp->vt[k] = vt; sp->vz[k] = vz;
-    sp->ar[k] = ar; sp->az[k] = az; sp->w[k] = w;
+    sp->ar[k] = ar; sp->az[k] = az; sp->w[k] = w; sp->at[k] = at;
     sp->id[k] = sp->next_id++;
     sp->dead[k] = 0;
     sp->npend++;
@@ -742,7 +781,7 @@ static uint8_t collide_one(rzo *o, int s, int64_t p, uint32_t step)
          * charge-to-mass ratios (Sec. 2.6), the electron's is the parent's. */
         species *ion = &o->sp[1];
         append(sp, sp->r[p], sp->z[p], ve * ue[0], ve * ue[1], ve * ue[2], sp->ar[p],
-               sp->az[p], sp->w[p]);
+               sp->az[p], sp->w[p], sp->at[p]);
         rzo_uniform_pair(seed, s, pid, step, 4, un1);
         rzo_uniform_pair(seed, s, pid, step, 5, un2);
         double g1[2], g2[2];
@@ -751,7 +790,7 @@ static uint8_t collide_one(rzo *o, int s, int64_t p, uint32_t step)
         double vth = sqrt(K_B * o->c.T_gas / o->c.m_gas);
         double ratio = (ion->q * sp->m) / (sp->q * ion->m);
         append(ion, sp->r[p], sp->z[p], vth * g1[0], vth * g1[1], vth * g2[0],
-               sp->ar[p] * ratio, sp->az[p] * ratio, sp->w[p]);
+               sp->ar[p] * ratio, sp->az[p] * ratio, sp->w[p], sp->at[p] * ratio);
         return (uint8_t)(RZO_EV_PROC0 + k);
     }
 
@@ -830,6 +869,7 @@ static void move_particle(species *sp, int64_t dst, int64_t src)
     sp->r[dst] = sp->r[src]; sp->z[dst] = sp->z[src]; sp->vr[dst] = sp->vr[src];
     sp->vt[dst] = sp->vt[src]; sp->vz[dst] = sp->vz[src]; sp->ar[dst] = sp->ar[src];
     sp->az[dst] = sp->az[src]; sp->w[dst] = sp->w[src]; sp->id[dst] = sp->id[src];
+    sp->at[dst] = sp->at[src];
     sp->dead[dst] = sp->dead[src];
 }
 
@@ -884,7 +924,7 @@ int rzo_resize(rzo *o, int s)
         sp->w[p] = w - (double)nc * wr;
         for (int64_t c = 0; c < nc; ++c)
             if (append(sp, sp->r[p], sp->z[p], sp->vr[p], sp->vt[p], sp->vz[p], sp->ar[p],
-                       sp->az[p], wr) < 0)
+                       sp->az[p], wr, sp->at[p]) < 0)
                 return -2;
     }
     sp->n += sp->npend;
@@ -933,8 +973,8 @@ int rzo_sort(rzo *o, int s)
     }
     for (int t = 0; t < nt; ++t) start[t + 1] += start[t];
     for (int64_t p = 0; p < n; ++p) dst[p] = start[key[p]]++;
-    double *f[8] = {sp->r, sp->z, sp->vr, sp->vt, sp->vz, sp->ar, sp->az, sp->w};
-    for (int k = 0; k < 8; ++k) {
+    double *f[9] = {sp->r, sp->z, sp->vr, sp->vt, sp->vz, sp->ar, sp->az, sp->w, sp->at};
+    for (int k = 0; k < 9; ++k) {
         for (int64_t p = 0; p < n; ++p) tmp[dst[p]] = f[k][p];
         memcpy(f[k], tmp, (size_t)n * sizeof(double));
     }
@@ -1353,6 +1393,7 @@ int rzo_init_particles(rzo *o, int s, int64_t n, double n0, double T_eV, uint64_
         sp->vz[p] = vth * g2[0];
         sp->ar[p] = 0.0;
         sp->az[p] = 0.0;
+        sp->at[p] = 0.0;
         sp->w[p] = wcoef * r;
         sp->id[p] = id;
         sp->dead[p] = 0;

@@ -68,8 +68,10 @@ typedef struct {
                               * V_dc+V_rf sin(2 pi f t) and the z=0 electrode  */
     int32_t ion_subcycle;    /* K >= 2: ions (species 1) move every K-th step
                               * with dt_i = K dt; 0 or 1: every step         */
-    int32_t reserved;
+    int32_t push_form;       /* RZO_PUSH_LOCAL (Sec. 2.3 local X-Y push, a_theta
+                              * dropped) or RZO_PUSH_XYZ (the global X-Y-Z push) */
 } rzo_config;
+enum { RZO_PUSH_LOCAL = 0, RZO_PUSH_XYZ = 1 };
 
 rzo *rzo_create(const rzo_config *cfg);
 void rzo_destroy(rzo *o);
@@ -86,6 +88,10 @@ int rzo_set_particles(rzo *o, int s, int64_t n, const double *r, const double *z
                       const uint64_t *id, uint64_t next_id);
 int64_t rzo_count(const rzo *o, int s);
 uint64_t rzo_next_id(const rzo *o, int s);
+/* Azimuthal damped acceleration a_theta (kept by RZO_PUSH_XYZ only; zero after
+ * rzo_set_particles): set / read the first n entries. */
+int rzo_set_at(rzo *o, int s, int64_t n, const double *at);
+int rzo_get_at(const rzo *o, int s, double *at);
 int rzo_get_particles(const rzo *o, int s, double *r, double *z, double *vr,
                       double *vt, double *vz, double *ar, double *az, double *w,
                       uint64_t *id);

@@ -33,7 +33,7 @@ class Config(C.Structure):
         ("n_gas", C.c_double), ("T_gas", C.c_double), ("m_gas", C.c_double),
         ("tile_z", C.c_int32), ("tile_r", C.c_int32),
         ("circuit_C", C.c_double),
-        ("ion_subcycle", C.c_int32), ("reserved", C.c_int32),
+        ("ion_subcycle", C.c_int32), ("push_form", C.c_int32),
     ]
 
 
@@ -79,6 +79,8 @@ def lib():
         L.rzo_set_grid.argtypes = [P, C.c_int, dp]
         L.rzo_absorbed.argtypes = [P, C.c_int, dp]
         L.rzo_set_circuit.argtypes = [P, C.c_double, C.c_double, C.c_double]
+        L.rzo_set_at.argtypes = [P, C.c_int, C.c_int64, dp]
+        L.rzo_get_at.argtypes = [P, C.c_int, dp]
         L.rzo_circuit.argtypes = [P, dp]
         L.rzo_apply_op.argtypes = [P, dp, dp]
         L.rzo_thomas.argtypes = [C.c_int32, dp, dp, dp, dp, dp]
@@ -140,7 +142,7 @@ class Oracle:
                      resize_every=w.resize_every, sort_every=w.sort_every,
                      resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
                      tile_z=w.tile_z, tile_r=w.tile_r, circuit_C=w.circuit_C,
-                     ion_subcycle=w.ion_subcycle)
+                     ion_subcycle=w.ion_subcycle, push_form=w.push_form)
         self._cfg = cfg
         self.h = lib().rzo_create(C.byref(cfg))
         if not self.h:
@@ -251,6 +253,16 @@ class Oracle:
 
     def set_grid(self, which, arr):
         assert lib().rzo_set_grid(self.h, which, _f64(np.asarray(arr).reshape(-1))) == 0
+
+    def set_at(self, s, at):
+        """a_theta of the global X-Y-Z push for the first len(at) particles."""
+        at = _f64(at)
+        assert lib().rzo_set_at(self.h, s, len(at), at) == 0
+
+    def get_at(self, s):
+        out = np.zeros(self.count(s))
+        assert lib().rzo_get_at(self.h, s, out) == 0
+        return out
 
     def set_circuit(self, V, Q, Qc):
         assert lib().rzo_set_circuit(self.h, V, Q, Qc) == 0

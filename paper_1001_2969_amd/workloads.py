@@ -31,6 +31,7 @@ SPECIES_M = (M_ELECTRON, M_ARGON)
 MC_NONE, MC_ELECTRON, MC_ION = 0, 1, 2
 P_ELASTIC, P_EXCITATION, P_IONIZATION = 0, 1, 2
 W_ZR2, W_ZR = 0, 1
+PUSH_LOCAL, PUSH_XYZ = 0, 1
 FACE_AVG, FACE_MAX = 0, 1
 
 # Uniform energy grid of the cross-section tables: 0 .. 200 eV step 0.02 eV.
@@ -71,6 +72,7 @@ class Workload:
     precision: str = "fp64"
     circuit_C: float = 0.0  # > 0: blocking capacitor (F) in series with the rf source
     ion_subcycle: int = 0  # K >= 2: ions move every K-th step with K dt
+    push_form: int = 0  # PUSH_LOCAL (Sec. 2.3 local X-Y push) or PUSH_XYZ (global X-Y-Z)
 
     @property
     def n_gas(self) -> float:
