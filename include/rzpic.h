@@ -50,6 +50,14 @@ enum { RZPIC_FP64 = 0, RZPIC_MIXED = 1 };          /* precision            */
 enum { RZPIC_W_ZR2 = 0, RZPIC_W_ZR = 1 };          /* weighting, Sec. 2.4  */
 enum { RZPIC_FACE_AVG = 0, RZPIC_FACE_MAX = 1 };   /* half-point chi, Sec. 2.5 */
 enum { RZPIC_MC_NONE = 0, RZPIC_MC_ELECTRON = 1, RZPIC_MC_ION = 2 };
+/* Particle push (Sec. 2.3): the local X-Y push with rotation, a_theta dropped
+ * (default), or the global X-Y-Z push (Cartesian particles in the 2-D field),
+ * carried in the particle's local frame: a_theta is kept (species view `at`),
+ * turned with the frame at every first push and damped by the final push
+ * (E has no theta component at the particle), and a particle the final push
+ * carries through the axis goes on at the other side (frame turned by pi)
+ * instead of the axis rule. */
+enum { RZPIC_PUSH_LOCAL = 0, RZPIC_PUSH_XYZ = 1 };
 enum { RZPIC_P_ELASTIC = 0, RZPIC_P_EXCITATION = 1, RZPIC_P_IONIZATION = 2 };
 /* Grid selectors of rzpic_grid_copy.  N0/N1 are the deposited physical
  * particle counts N_ij of Sec. 2.4 (kept internally in fixed point). */
@@ -100,7 +108,7 @@ typedef struct rzpic_config {
                                * K dt.  0 or 1: every step.  rzpic_step only:
                                * the single operations act as in a step where
                                * the ions move. */
-    int32_t reserved1;
+    int32_t push_form;        /* RZPIC_PUSH_LOCAL (0) or RZPIC_PUSH_XYZ        */
 } rzpic_config;
 
 typedef struct rzpic_species_view {
@@ -114,6 +122,9 @@ typedef struct rzpic_species_view {
     double w_ref;             /* reference weight of the fixed-point deposit */
     int32_t mc_model;         /* RZPIC_MC_*                                  */
     int32_t reserved0;
+    void *at;                 /* RZPIC_PUSH_XYZ: device array of `capacity`
+                               * a_theta values (moved with the particles);
+                               * ignored by the local push                   */
 } rzpic_species_view;
 
 typedef struct rzpic_diag {

@@ -645,6 +645,8 @@ rzpic_status check_ctx(const rzpic_ctx *c)
         return rz_fail(RZPIC_EINVAL, "adjoint: the electrode must be driven directly (circuit_C = 0)");
     if (c->c.ion_subcycle > 1)
         return rz_fail(RZPIC_EINVAL, "adjoint: ions must move every step (ion_subcycle <= 1)");
+    if (c->c.push_form != RZPIC_PUSH_LOCAL)
+        return rz_fail(RZPIC_EINVAL, "adjoint: needs the local-frame push (push_form = LOCAL)");
     if (c->children_pending[0] || c->children_pending[1])
         return rz_fail(RZPIC_ESTATE, "adjoint: new particles are staged");
     return RZPIC_OK;

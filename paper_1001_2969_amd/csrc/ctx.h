@@ -51,14 +51,14 @@ struct SpeciesState {
     int64_t nchunks_max = 0;
     // staging of the new particles of ionizations (electron species only):
     // [0] new electrons, [1] new ions, slots indexed like electron particles
-    void *stage[2][8] = {};
+    void *stage[2][9] = {};  // 9th: a_theta (global X-Y-Z push only)
     bool has_xsec = false;
     Xsec xs{};
     double nu_max = 0.0, p_null = 0.0;
     DevBuf sigma;
     // tile sort: sorted-copy staging (8 real arrays + identities), per-segment
     // tile counts/offsets, scan partials, and the window plan of the pass
-    void *sort_buf[9] = {};
+    void *sort_buf[10] = {};  // 10th: a_theta (global X-Y-Z push only)
     int64_t *sort_off = nullptr, *sort_part = nullptr, *tile_pb = nullptr;
     int4 *tile_win = nullptr;
     int64_t sort_seg = 0, sort_nseg = 0;

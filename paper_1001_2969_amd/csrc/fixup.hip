@@ -197,6 +197,7 @@ __device__ __forceinline__ void fill_body(const Blk &kb, const Parts<T> &p, cons
         p.az[dst] = p.az[src];
         p.w[dst] = p.w[src];
         p.id[dst] = p.id[src];
+        if (p.at) p.at[dst] = p.at[src];
     }
 }
 
@@ -311,6 +312,7 @@ template <typename T> __device__ __forceinline__ void append_body(const Blk &kb,
         dst.ar[to] = stage.ar[slot];
         dst.az[to] = stage.az[slot];
         dst.w[to] = stage.w[slot];
+        if (dst.at) dst.at[to] = stage.at[slot];
         dst.id[to] = id0 + (uint64_t)(eoff + __popcll(em & ((1ull << lane) - 1)));
     }
 }
@@ -416,7 +418,7 @@ __global__ __launch_bounds__(256) void k_resize_scatter(Parts<T> p, Counts *cnt,
             double w = (double)p.w[i];
             clones_of(w, (double)p.r[i], wcoef, half_hr, wr);
             const T r = p.r[i], z = p.z[i], vr = p.vr[i], vt = p.vt[i], vz = p.vz[i];
-            const T ar = p.ar[i], az = p.az[i];
+            const T ar = p.ar[i], az = p.az[i], at = p.at ? p.at[i] : (T)0;
             p.w[i] = (T)split_rest(w, nc, wr);
             int64_t base = n + ch.clone_off[c] + ex;
             for (int k = 0; k < nc; ++k) {
@@ -429,6 +431,7 @@ __global__ __launch_bounds__(256) void k_resize_scatter(Parts<T> p, Counts *cnt,
                 p.ar[d] = ar;
                 p.az[d] = az;
                 p.w[d] = (T)wr;
+                if (p.at) p.at[d] = at;
                 p.id[d] = rec->next_id_old + (uint64_t)(ch.clone_off[c] + ex + k);
             }
         }

@@ -57,6 +57,7 @@ template <> struct Vec2<float> { using type = float2; };
 template <typename T> struct Parts {
     T *r, *z, *vr, *vt, *vz, *ar, *az, *w;
     uint64_t *id;
+    T *at;  // a_theta of the global X-Y-Z push; null in the local form
 };
 
 struct Mesh {

@@ -44,6 +44,7 @@ __device__ __forceinline__ void tally_add(unsigned long long *t, int b, double w
 
 template <typename T> struct PState {
     T r, z, vr, vt, vz, ar, az, w;
+    T at;  // a_theta, global X-Y-Z push only
 };
 
 // Absorption at the electrodes (z <= 0, z >= L) and the wall (r >= R).
@@ -55,12 +56,17 @@ template <typename T> __device__ __forceinline__ int boundary_of(const PState<T>
     return -1;
 }
 
-// First push in the local X-Y frame plus rotation (Sec. 2.3); a_theta = 0.
-template <typename T> __device__ __forceinline__ void first_push(PState<T> &s, T dt)
+// First push in the local X-Y frame plus rotation (Sec. 2.3).  Local form:
+// a_theta = 0.  Global X-Y-Z form (xyz): a_theta kicks v_theta and the damped
+// acceleration turns with the frame (the Cartesian push seen from the
+// particle's meridian plane).
+template <typename T> __device__ __forceinline__ void first_push(PState<T> &s, T dt, bool xyz)
 {
+    // no contraction: every kernel instance that inlines the push rounds alike
+#pragma clang fp contract(off)
     const T half = (T)0.5;
     T vx = s.vr + half * s.ar * dt;
-    T vy = s.vt;
+    T vy = xyz ? s.vt + half * s.at * dt : s.vt;
     T x = s.r + vx * dt;
     T y = vy * dt;
     T vz = s.vz + half * s.az * dt;
@@ -76,7 +82,13 @@ template <typename T> __device__ __forceinline__ void first_push(PState<T> &s, T
     s.vr = vx * c + vy * sn;
     s.vt = -vx * sn + vy * c;
     s.vz = vz;
-    s.ar = s.ar * c;
+    if (xyz) {
+        const T ar = s.ar, at = s.at;
+        s.ar = ar * c + at * sn;
+        s.at = -ar * sn + at * c;
+    } else {
+        s.ar = s.ar * c;
+    }
 }
 
 // Gather of E at (r, z) with the deposit weights (any position: the cell is
@@ -94,16 +106,31 @@ __device__ __forceinline__ void gather_E(const Mesh &m, const typename Vec2<T>::
 
 // Final push with the gathered field, the damped-acceleration update and the
 // axis rule (Sec. 2.1, 2.3).
+// Global X-Y-Z form (xyz): E has no theta component at the particle, so a_theta
+// is damped by the same average, and a particle pushed through the axis goes
+// on at the other side (the local frame turns by pi) instead of the axis rule.
 template <typename T>
-__device__ __forceinline__ void final_push(PState<T> &s, T Er, T Ez, T k1, T k2, T qm)
+__device__ __forceinline__ void final_push(PState<T> &s, T Er, T Ez, T k1, T k2, T qm, bool xyz)
 {
+#pragma clang fp contract(off)
     T r = s.r + k1 * Er;
     T z = s.z + k1 * Ez;
     T vr = s.vr + k2 * Er;
     T vz = s.vz + k2 * Ez;
     T ar = (T)0.5 * (qm * Er + s.ar);
     T az = (T)0.5 * (qm * Ez + s.az);
-    if (r < (T)0) {
+    if (xyz) {
+        T at = (T)0.5 * s.at, vt = s.vt;
+        if (r < (T)0) {
+            r = -r;
+            vr = -vr;
+            vt = -vt;
+            ar = -ar;
+            at = -at;
+        }
+        s.vt = vt;
+        s.at = at;
+    } else if (r < (T)0) {
         r = -r;
         vr = fabs(vr);
         ar = fabs(ar);
@@ -118,7 +145,8 @@ __device__ __forceinline__ void final_push(PState<T> &s, T Er, T Ez, T k1, T k2,
 
 template <typename T> __device__ __forceinline__ PState<T> load(const Parts<T> &p, int64_t i)
 {
-    return PState<T>{p.r[i], p.z[i], p.vr[i], p.vt[i], p.vz[i], p.ar[i], p.az[i], p.w[i]};
+    return PState<T>{p.r[i], p.z[i], p.vr[i], p.vt[i], p.vz[i],
+                     p.ar[i], p.az[i], p.w[i], p.at ? p.at[i] : (T)0};
 }
 
 template <typename T>
@@ -131,6 +159,7 @@ __device__ __forceinline__ void store(const Parts<T> &p, int64_t i, const PState
     p.vz[i] = s.vz;
     p.ar[i] = s.ar;
     p.az[i] = s.az;
+    if (p.at) p.at[i] = s.at;
     if (w) p.w[i] = s.w;
 }
 
@@ -168,6 +197,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
     const int64_t nwaves = ((int64_t)gb * blockDim.x) >> 6;
     const T dt = (T)a.sp.dt;
     const T k1 = (T)a.sp.k1, k2 = (T)a.sp.k2, qm = (T)a.sp.qm;
+    const bool xyz = a.p.at != nullptr;  // global X-Y-Z push (a_theta kept)
     constexpr bool kLds = (MODE & M_LDS) != 0;
     constexpr bool kTile = (MODE & M_TILE) != 0;
     constexpr bool kDep = (MODE & M_DEP) != 0;
@@ -215,7 +245,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         if ((MODE & M_MARK) && valid) live = s.w >= (T)0;
         bool died = false, moved = false;
         if ((MODE & M_FINAL) && live) {
-            final_push<T>(s, Er, Ez, k1, k2, qm);
+            final_push<T>(s, Er, Ez, k1, k2, qm, xyz);
             moved = true;
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
@@ -272,7 +302,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
             }
         }
         if ((MODE & M_FIRST) && live && !cand) {
-            first_push<T>(s, dt);
+            first_push<T>(s, dt, xyz);
             moved = true;
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
@@ -404,6 +434,7 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
     constexpr bool kLds = (MODE & M_LDS) != 0;
     constexpr bool kFirst = (MODE & M_FIRST) != 0;
     const T dt = (T)a.sp.dt;
+    const bool xyz = a.p.at != nullptr;  // global X-Y-Z push (a_theta kept)
     unsigned long long *dep = a.acc;
     if (threadIdx.x < 1 + kMaxProc) sh_stat[threadIdx.x] = 0;
     if (kLds) {
@@ -454,7 +485,7 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
         if (iz) {
             // new electron and ion at the parent's position with its weight;
             // the ion's damped acceleration scaled by the charge-to-mass ratios
-            ne = PState<T>{s.r, s.z, (T)che.vr, (T)che.vt, (T)che.vz, s.ar, s.az, s.w};
+            ne = PState<T>{s.r, s.z, (T)che.vr, (T)che.vt, (T)che.vz, s.ar, s.az, s.w, s.at};
             ni = PState<T>{s.r,
                            s.z,
                            (T)chi.vr,
@@ -462,12 +493,13 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
                            (T)chi.vz,
                            (T)((double)s.ar * a.phys.ion_acc_ratio),
                            (T)((double)s.az * a.phys.ion_acc_ratio),
-                           s.w};
+                           s.w,
+                           (T)((double)s.at * a.phys.ion_acc_ratio)};
             ne_live = ni_live = true;
         }
         bool live = true;
         if (kFirst) {
-            first_push<T>(s, dt);
+            first_push<T>(s, dt, xyz);
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
                 tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
@@ -475,13 +507,13 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
                 atomicOr(a.ch.dead + c, bit);
             }
             if (iz) {
-                first_push<T>(ne, dt);
+                first_push<T>(ne, dt, xyz);
                 b = boundary_of(ne, a.phys);
                 if (b >= 0) {
                     tally_add(a.tally, b, (double)ne.w, a.sp.inv_quantum);
                     ne_live = false;
                 }
-                first_push<T>(ni, (T)a.phys.ion_dt);
+                first_push<T>(ni, (T)a.phys.ion_dt, xyz);
                 b = boundary_of(ni, a.phys);
                 if (b >= 0) {
                     tally_add(a.tally_ion, b, (double)ni.w, a.phys.ion_inv_quantum);
@@ -574,7 +606,7 @@ __global__ __launch_bounds__(256) void k_staged(PassArgs<T> a, int cs)
         int64_t slot = c * kChunk + lane;
         PState<T> s = load(a.p, slot);
         if (MODE & M_FIRST) {
-            first_push<T>(s, dt);
+            first_push<T>(s, dt, a.p.at != nullptr);
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
                 tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
@@ -613,6 +645,7 @@ __global__ void k_init(Parts<T> p, int64_t n, double wcoef, double vth, uint64_t
         p.vz[i] = (T)(vth * n3);
         p.ar[i] = (T)0;
         p.az[i] = (T)0;
+        if (p.at) p.at[i] = (T)0;
         p.w[i] = (T)(wcoef * r);
         p.id[i] = id;
     }

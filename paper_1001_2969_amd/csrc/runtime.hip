@@ -164,6 +164,7 @@ template <typename T> Parts<T> parts_of(const rzpic_species_view &v)
     p.az = (T *)v.az;
     p.w = (T *)v.w;
     p.id = v.id;
+    p.at = (T *)v.at;  // null unless the global X-Y-Z push (bind_species)
     return p;
 }
 
@@ -180,6 +181,7 @@ template <typename T> Parts<T> stage_of(const rzpic_ctx *c, int cs)
     p.az = (T *)a[6];
     p.w = (T *)a[7];
     p.id = nullptr;
+    p.at = (T *)a[8];
     return p;
 }
 
@@ -694,6 +696,7 @@ rzpic_status sort_alloc(rzpic_ctx *c, int s)
     };
     for (int f = 0; f < 8; ++f) TRY(get(&ss.sort_buf[f], cap * es));
     TRY(get(&ss.sort_buf[8], cap * sizeof(uint64_t)));
+    if (ss.v.at) TRY(get(&ss.sort_buf[9], cap * es));
     TRY(get((void **)&ss.sort_off, M * sizeof(int64_t)));
     TRY(get((void **)&ss.sort_part, 4096 * sizeof(int64_t)));
     TRY(get((void **)&ss.tile_pb, sizeof(int64_t)));
@@ -716,6 +719,7 @@ template <typename T> rzpic_status sort_impl(rzpic_ctx *c, int s)
     T **tf[8] = {&t.r, &t.z, &t.vr, &t.vt, &t.vz, &t.ar, &t.az, &t.w};
     for (int f = 0; f < 8; ++f) *tf[f] = (T *)ss.sort_buf[f];
     t.id = (uint64_t *)ss.sort_buf[8];
+    t.at = (T *)ss.sort_buf[9];
     a.tmp = t;
     a.cnt = c->cnt + s;
     a.hr = c->hr;
@@ -920,6 +924,8 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     if (!(k.circuit_C >= 0.0) || !std::isfinite(k.circuit_C))
         return fail(RZPIC_EINVAL, "circuit_C must be finite and >= 0");
     if (k.ion_subcycle < 0) return fail(RZPIC_EINVAL, "ion_subcycle must be >= 0");
+    if (k.push_form != RZPIC_PUSH_LOCAL && k.push_form != RZPIC_PUSH_XYZ)
+        return fail(RZPIC_EINVAL, "unknown push_form %d", k.push_form);
 
     rzpic_ctx *c = new rzpic_ctx();
     c->c = k;
@@ -1077,7 +1083,7 @@ rzpic_status rzpic_destroy(rzpic_ctx *c)
     for (void *p : c->allocs) (void)hipFree(p);
     for (int s = 0; s < 2; ++s) {
         for (int a = 0; a < 2; ++a)
-            for (int f = 0; f < 8; ++f)
+            for (int f = 0; f < 9; ++f)
                 if (c->sp[s].stage[a][f]) (void)hipFree(c->sp[s].stage[a][f]);
         if (c->sp[s].sigma.p) (void)hipFree(c->sp[s].sigma.p);
         free_sort(c->sp[s]);
@@ -1108,16 +1114,19 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
         return fail(RZPIC_EINVAL, "species %d: unknown mc_model", s);
     if (v->mc_model == RZPIC_MC_ELECTRON && s != 0)
         return fail(RZPIC_EINVAL, "the electron collision model is species 0");
+    if (c->c.push_form == RZPIC_PUSH_XYZ && !v->at)
+        return fail(RZPIC_EINVAL, "species %d: the global X-Y-Z push needs the a_theta array", s);
     HIPCHK(c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize());
     SpeciesState &ss = c->sp[s];
     for (int a = 0; a < 2; ++a)
-        for (int f = 0; f < 8; ++f)
+        for (int f = 0; f < 9; ++f)
             if (ss.stage[a][f]) {
                 (void)hipFree(ss.stage[a][f]);
                 ss.stage[a][f] = nullptr;
             }
     free_sort(ss);
     ss.v = *v;
+    if (c->c.push_form != RZPIC_PUSH_XYZ) ss.v.at = nullptr;  // the local form keeps no a_theta
     ss.cap = v->capacity;
     ss.bound = true;
     c->quantum[s] = v->w_ref * std::ldexp(1.0, -c->c.fixed_point_bits);
@@ -1136,8 +1145,9 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
 #undef A
     if (s == 0 && v->mc_model == RZPIC_MC_ELECTRON) {
         size_t es = c->mixed ? sizeof(float) : sizeof(double);
+        const int nf = c->c.push_form == RZPIC_PUSH_XYZ ? 9 : 8;
         for (int a = 0; a < 2; ++a)
-            for (int f = 0; f < 8; ++f) HIPCHK(hipMalloc(&ss.stage[a][f], cap * es));
+            for (int f = 0; f < nf; ++f) HIPCHK(hipMalloc(&ss.stage[a][f], cap * es));
     }
     if (c->c.sort_every > 0) TRY(sort_alloc(c, s));
     RZ_LAUNCH(k_set_count, dim3(1), dim3(1), 0, c->st, c->cnt + s, (int64_t)0, (uint64_t)0);

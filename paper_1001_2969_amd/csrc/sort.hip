@@ -185,6 +185,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs<T> a)
             a.tmp.az[d] = a.p.az[p];
             a.tmp.w[d] = a.p.w[p];
             a.tmp.id[d] = a.p.id[p];
+            if (a.p.at) a.tmp.at[d] = a.p.at[p];
         }
     }
 }
@@ -203,6 +204,7 @@ template <typename T> __global__ void k_sort_copy(SortArgs<T> a)
         a.p.az[i] = a.tmp.az[i];
         a.p.w[i] = a.tmp.w[i];
         a.p.id[i] = a.tmp.id[i];
+        if (a.p.at) a.p.at[i] = a.tmp.at[i];
     }
 }
 

@@ -54,7 +54,7 @@ class Config(C.Structure):
         ("n_gas", C.c_double), ("T_gas", C.c_double), ("m_gas", C.c_double),
         ("tile_z", C.c_int32), ("tile_r", C.c_int32),
         ("circuit_C", C.c_double),
-        ("ion_subcycle", C.c_int32), ("reserved1", C.c_int32),
+        ("ion_subcycle", C.c_int32), ("push_form", C.c_int32),
     ]
 
 
@@ -62,7 +62,7 @@ class SpeciesView(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in FIELDS] + [
         ("id", C.c_void_p), ("mc_event", C.c_void_p), ("capacity", C.c_int64),
         ("q", C.c_double), ("m", C.c_double), ("w_ref", C.c_double),
-        ("mc_model", C.c_int32), ("reserved0", C.c_int32),
+        ("mc_model", C.c_int32), ("reserved0", C.c_int32), ("at", C.c_void_p),
     ]
 
 
@@ -170,8 +170,9 @@ class Context:
                      resize_every=w.resize_every, sort_every=w.sort_every,
                      resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
                      tile_z=w.tile_z, tile_r=w.tile_r, circuit_C=w.circuit_C,
-                     ion_subcycle=w.ion_subcycle)
+                     ion_subcycle=w.ion_subcycle, push_form=w.push_form)
         self._cfg = cfg
+        self.xyz = w.push_form == 1
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             h = C.c_void_p()
@@ -200,11 +201,13 @@ class Context:
         t = self.torch
         arr = {f: t.zeros(capacity, dtype=self.dtype, device=self.device) for f in FIELDS}
         arr["id"] = t.zeros(capacity, dtype=t.int64, device=self.device)
+        if self.xyz:  # a_theta of the global X-Y-Z push
+            arr["at"] = t.zeros(capacity, dtype=self.dtype, device=self.device)
         ev = t.zeros(capacity, dtype=t.uint8, device=self.device) if events else None
         v = SpeciesView(**{f: arr[f].data_ptr() for f in FIELDS}, id=arr["id"].data_ptr(),
                         mc_event=ev.data_ptr() if ev is not None else None,
                         capacity=capacity, q=q, m=m, w_ref=w_ref, mc_model=mc_model,
-                        reserved0=0)
+                        reserved0=0, at=arr["at"].data_ptr() if self.xyz else None)
         _check(lib().rzpic_bind_species(self.h, s, C.byref(v)))
         self.arrays[s] = arr
         self.events[s] = ev
@@ -229,6 +232,12 @@ class Context:
         for f in FIELDS:
             arr[f][:n].copy_(t.as_tensor(np.asarray(parts[f]), dtype=self.dtype))
         arr["id"][:n].copy_(t.as_tensor(np.asarray(parts["id"]).astype(np.int64)))
+        if self.xyz:
+            at = parts.get("at")
+            if at is None:
+                arr["at"][:n].zero_()
+            else:
+                arr["at"][:n].copy_(t.as_tensor(np.asarray(at), dtype=self.dtype))
         _check(lib().rzpic_set_count(self.h, s, n, next_id))
 
     def count(self, s):
@@ -241,6 +250,8 @@ class Context:
         arr = self.arrays[s]
         out = {f: arr[f][:n].double().cpu().numpy() for f in FIELDS}
         out["id"] = arr["id"][:n].cpu().numpy().astype(np.uint64)
+        if self.xyz:
+            out["at"] = arr["at"][:n].double().cpu().numpy()
         return out
 
     def event_codes(self, s, n):
