@@ -907,7 +907,7 @@ int rzo_compact(rzo *o, int s)
  * that remainder is not positive (w an exact multiple) one clone fewer is made
  * and the parent keeps w_r.  Clones copy the full phase-space record, take new
  * ids in parent order and are appended after the array. */
-int rzo_resize(rzo *o, int s)
+static int resize_split(rzo *o, int s)
 {
     species *sp = &o->sp[s];
     double half = 0.5 * o->hr;
@@ -931,6 +931,49 @@ int rzo_resize(rzo *o, int s)
     sp->npend = 0;
     return 0;
 }
+
+/* Zero-order particle-based resizing (Sec. 2.2, after Bird): the weight a
+ * particle should have at its present radius is w_r(r); with ratio
+ * q = w / w_r it is kept as N = floor(q) copies plus one more with
+ * probability q - floor(q) (first uniform of draw block 6 of (seed, s, id,
+ * step)), each of weight w_r, so the charge is conserved on average.  N = 0
+ * removes it; the N - 1 duplicates copy its phase space, take new ids in
+ * parent order and are appended; then the array is compacted. */
+static int resize_zero_order(rzo *o, int s, int64_t step)
+{
+    species *sp = &o->sp[s];
+    double half = 0.5 * o->hr;
+    int64_t n = sp->n;
+    for (int64_t p = 0; p < n; ++p) {
+        double rr = sp->r[p] > half ? sp->r[p] : half;
+        double wr = o->c.resize_wcoef * rr;
+        double q = sp->w[p] / wr;
+        double k = floor(q);
+        double u[2];
+        rzo_uniform_pair(o->c.seed, s, sp->id[p], (uint32_t)step, 6, u);
+        int64_t N = (int64_t)k + (u[0] < q - k ? 1 : 0);
+        if (N == 0) {
+            sp->dead[p] = 1;
+            continue;
+        }
+        sp->w[p] = wr;
+        for (int64_t c = 1; c < N; ++c)
+            if (append(sp, sp->r[p], sp->z[p], sp->vr[p], sp->vt[p], sp->vz[p], sp->ar[p],
+                       sp->az[p], wr, sp->at[p]) < 0)
+                return -2;
+    }
+    sp->n += sp->npend;
+    sp->npend = 0;
+    return rzo_compact(o, s);
+}
+
+int rzo_resize_step(rzo *o, int s, int64_t step)
+{
+    if (o->c.resize_mode == RZO_RESIZE_ZERO_ORDER) return resize_zero_order(o, s, step);
+    return resize_split(o, s);
+}
+
+int rzo_resize(rzo *o, int s) { return rzo_resize_step(o, s, 0); }
 
 /* Tile key of a position: the cell (i, j) = (floor(z / hz), floor(r / hr)),
  * clamped to the mesh, and its tile of tile_z x tile_r cells, numbered with
@@ -1463,7 +1506,8 @@ int rzo_step(rzo *o, int64_t n, int merged)
     }
     for (int s = 0; s < 2; ++s) rzo_compact(o, s);
     if (o->c.resize_every > 0 && n % o->c.resize_every == o->c.resize_every - 1) {
-        for (int s = 0; s < 2; ++s) rzo_resize(o, s);
+        for (int s = 0; s < 2; ++s)
+            if (rzo_resize_step(o, s, n) != 0) return -2;
         deposit_all(o);
     }
     if (o->c.sort_every > 0 && n % o->c.sort_every == o->c.sort_every - 1)

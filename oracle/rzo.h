@@ -70,8 +70,12 @@ typedef struct {
                               * with dt_i = K dt; 0 or 1: every step         */
     int32_t push_form;       /* RZO_PUSH_LOCAL (Sec. 2.3 local X-Y push, a_theta
                               * dropped) or RZO_PUSH_XYZ (the global X-Y-Z push) */
+    int32_t resize_mode;     /* RZO_RESIZE_SPLIT (weight-conserving split) or
+                              * RZO_RESIZE_ZERO_ORDER (particle-based, Sec. 2.2) */
+    int32_t reserved;
 } rzo_config;
 enum { RZO_PUSH_LOCAL = 0, RZO_PUSH_XYZ = 1 };
+enum { RZO_RESIZE_SPLIT = 0, RZO_RESIZE_ZERO_ORDER = 1 };
 
 rzo *rzo_create(const rzo_config *cfg);
 void rzo_destroy(rzo *o);
@@ -118,6 +122,9 @@ int rzo_push_final(rzo *o, int s);          /* gather + final push + axis + abso
 int rzo_collide(rzo *o, int s, int64_t step);
 int rzo_compact(rzo *o, int s);
 int rzo_resize(rzo *o, int s);
+/* The resize of step `step` (the zero-order draws are keyed by it;
+ * rzo_resize uses step 0). */
+int rzo_resize_step(rzo *o, int s, int64_t step);
 /* Stable counting sort of species s by the tile (tile_z x tile_r cells) of
  * each particle's cell; returns the number of tiles. */
 int rzo_sort(rzo *o, int s);

@@ -34,6 +34,7 @@ class Config(C.Structure):
         ("tile_z", C.c_int32), ("tile_r", C.c_int32),
         ("circuit_C", C.c_double),
         ("ion_subcycle", C.c_int32), ("push_form", C.c_int32),
+        ("resize_mode", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -67,6 +68,7 @@ def lib():
                                          C.c_uint64]
         for name in ("rzo_push_first", "rzo_push_final", "rzo_compact", "rzo_resize", "rzo_sort"):
             getattr(L, name).argtypes = [P, C.c_int]
+        L.rzo_resize_step.argtypes = [P, C.c_int, C.c_int64]
         L.rzo_tile_key.restype = C.c_int32
         L.rzo_tile_key.argtypes = [P, C.c_double, C.c_double]
         L.rzo_collide.argtypes = [P, C.c_int, C.c_int64]
@@ -142,7 +144,8 @@ class Oracle:
                      resize_every=w.resize_every, sort_every=w.sort_every,
                      resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
                      tile_z=w.tile_z, tile_r=w.tile_r, circuit_C=w.circuit_C,
-                     ion_subcycle=w.ion_subcycle, push_form=w.push_form)
+                     ion_subcycle=w.ion_subcycle, push_form=w.push_form,
+                     resize_mode=w.resize_mode)
         self._cfg = cfg
         self.h = lib().rzo_create(C.byref(cfg))
         if not self.h:
@@ -216,8 +219,11 @@ class Oracle:
     def compact(self, s):
         lib().rzo_compact(self.h, s)
 
-    def resize(self, s):
-        assert lib().rzo_resize(self.h, s) == 0
+    def resize(self, s, step=None):
+        if step is None:
+            assert lib().rzo_resize(self.h, s) == 0
+        else:
+            assert lib().rzo_resize_step(self.h, s, step) == 0
 
     def sort(self, s):
         """Stable counting sort by tile; returns the number of tiles."""

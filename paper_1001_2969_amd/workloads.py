@@ -32,6 +32,7 @@ MC_NONE, MC_ELECTRON, MC_ION = 0, 1, 2
 P_ELASTIC, P_EXCITATION, P_IONIZATION = 0, 1, 2
 W_ZR2, W_ZR = 0, 1
 PUSH_LOCAL, PUSH_XYZ = 0, 1
+RESIZE_SPLIT, RESIZE_ZERO_ORDER = 0, 1
 FACE_AVG, FACE_MAX = 0, 1
 
 # Uniform energy grid of the cross-section tables: 0 .. 200 eV step 0.02 eV.
@@ -73,6 +74,7 @@ class Workload:
     circuit_C: float = 0.0  # > 0: blocking capacitor (F) in series with the rf source
     ion_subcycle: int = 0  # K >= 2: ions move every K-th step with K dt
     push_form: int = 0  # PUSH_LOCAL (Sec. 2.3 local X-Y push) or PUSH_XYZ (global X-Y-Z)
+    resize_mode: int = 0  # RESIZE_SPLIT (weight-conserving) or RESIZE_ZERO_ORDER (particle-based)
 
     @property
     def n_gas(self) -> float:
