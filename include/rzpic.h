@@ -58,6 +58,15 @@ enum { RZPIC_MC_NONE = 0, RZPIC_MC_ELECTRON = 1, RZPIC_MC_ION = 2 };
  * carries through the axis goes on at the other side (frame turned by pi)
  * instead of the axis rule. */
 enum { RZPIC_PUSH_LOCAL = 0, RZPIC_PUSH_XYZ = 1 };
+/* Periodic resize (Sec. 2.2): the weight-conserving split (default), or
+ * zero-order particle-based resizing: a particle of weight w whose weight at
+ * its radius should be w_r = resize_wcoef * max(r, hr/2) is kept as
+ * floor(w/w_r) copies plus one more with probability frac(w/w_r) (first
+ * uniform of draw block 6 of (seed, s, id, step)), each of weight w_r; none
+ * removes it; duplicates copy its record, take new identities in parent
+ * order and are appended, then the array is compacted (rzpic_resize alone
+ * keys its draws by step 0). */
+enum { RZPIC_RESIZE_SPLIT = 0, RZPIC_RESIZE_ZERO_ORDER = 1 };
 enum { RZPIC_P_ELASTIC = 0, RZPIC_P_EXCITATION = 1, RZPIC_P_IONIZATION = 2 };
 /* Grid selectors of rzpic_grid_copy.  N0/N1 are the deposited physical
  * particle counts N_ij of Sec. 2.4 (kept internally in fixed point). */
@@ -109,6 +118,8 @@ typedef struct rzpic_config {
                                * the single operations act as in a step where
                                * the ions move. */
     int32_t push_form;        /* RZPIC_PUSH_LOCAL (0) or RZPIC_PUSH_XYZ        */
+    int32_t resize_mode;      /* RZPIC_RESIZE_SPLIT (0) or RZPIC_RESIZE_ZERO_ORDER */
+    int32_t reserved2;
 } rzpic_config;
 
 typedef struct rzpic_species_view {

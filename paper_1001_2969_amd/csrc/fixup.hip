@@ -356,9 +356,25 @@ __device__ __forceinline__ double split_rest(double w, int nc, double wr)
     return w - (double)nc * wr;
 }
 
+// Zero-order particle-based resizing (Sec. 2.2): copies kept of a particle of
+// weight w at radius r, floor(q) plus one with probability q - floor(q),
+// q = w / w_r (first uniform of draw block 6); each copy weighs w_r.
+__device__ __forceinline__ int copies_of(double w, double r, double wcoef, double half_hr,
+                                         const ResizeKey &k, uint64_t id, double &wr)
+{
+#pragma clang fp contract(off)
+    double rr = r > half_hr ? r : half_hr;
+    wr = wcoef * rr;
+    double q = w / wr;
+    double fl = floor(q);
+    double ua, ub;
+    uniform2(k.seed, k.s, id, k.step, 6, ua, ub);
+    return (int)fl + (ua < q - fl ? 1 : 0);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_resize_count(Parts<T> p, const Counts *cnt, Chunks ch,
-                                                      double wcoef, double half_hr)
+                                                      ResizeKey key, double wcoef, double half_hr)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -370,7 +386,13 @@ __global__ __launch_bounds__(256) void k_resize_count(Parts<T> p, const Counts *
         int nc = 0;
         if (i < n) {
             double wr;
-            nc = clones_of((double)p.w[i], (double)p.r[i], wcoef, half_hr, wr);
+            if (key.zero_order) {
+                const int N = copies_of((double)p.w[i], (double)p.r[i], wcoef, half_hr, key,
+                                        p.id[i], wr);
+                nc = N > 1 ? N - 1 : 0;
+            } else {
+                nc = clones_of((double)p.w[i], (double)p.r[i], wcoef, half_hr, wr);
+            }
             ch.pcount[i] = nc;
         }
         int tot;
@@ -396,8 +418,9 @@ __global__ __launch_bounds__(1024) void k_resize_scan(const Counts *cnt, Chunks 
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_resize_scatter(Parts<T> p, Counts *cnt, Chunks ch,
-                                                        const CloneRec *rec, double wcoef,
-                                                        double half_hr, int32_t *status)
+                                                        const CloneRec *rec, ResizeKey key,
+                                                        double wcoef, double half_hr,
+                                                        int32_t *status)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -413,13 +436,20 @@ __global__ __launch_bounds__(256) void k_resize_scatter(Parts<T> p, Counts *cnt,
         int nc = i < n ? ch.pcount[i] : 0;
         int tot;
         int ex = wave_excl_sum(nc, tot);
-        if (nc > 0) {
+        if (i < n && (nc > 0 || key.zero_order)) {
             double wr;
             double w = (double)p.w[i];
-            clones_of(w, (double)p.r[i], wcoef, half_hr, wr);
+            T wpar;
+            if (key.zero_order) {  // none kept: marked for the compaction that follows
+                const int N = copies_of(w, (double)p.r[i], wcoef, half_hr, key, p.id[i], wr);
+                wpar = N == 0 ? (T)-1 : (T)wr;
+            } else {
+                clones_of(w, (double)p.r[i], wcoef, half_hr, wr);
+                wpar = (T)split_rest(w, nc, wr);
+            }
             const T r = p.r[i], z = p.z[i], vr = p.vr[i], vt = p.vt[i], vz = p.vz[i];
             const T ar = p.ar[i], az = p.az[i], at = p.at ? p.at[i] : (T)0;
-            p.w[i] = (T)split_rest(w, nc, wr);
+            p.w[i] = wpar;
             int64_t base = n + ch.clone_off[c] + ex;
             for (int k = 0; k < nc; ++k) {
                 int64_t d = base + k;
@@ -443,13 +473,14 @@ __global__ __launch_bounds__(256) void k_resize_scatter(Parts<T> p, Counts *cnt,
 }
 
 template <typename T>
-hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, double wcoef,
-                         double half_hr, int64_t cap, int32_t *status, hipStream_t st)
+hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, const ResizeKey &k,
+                         double wcoef, double half_hr, int64_t cap, int32_t *status,
+                         hipStream_t st)
 {
-    RZ_LAUNCH((k_resize_count<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, wcoef,
+    RZ_LAUNCH((k_resize_count<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, k, wcoef,
                        half_hr);
     RZ_LAUNCH(k_resize_scan, dim3(1), dim3(1024), 0, st, cnt, ch, rec, cap);
-    RZ_LAUNCH((k_resize_scatter<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, rec,
+    RZ_LAUNCH((k_resize_scatter<T>), dim3(1024), dim3(256), 0, st, p, cnt, ch, rec, k,
                        wcoef, half_hr, status);
     return hipGetLastError();
 }
@@ -522,9 +553,11 @@ template hipError_t launch_append<double>(const ScanJobs &, Parts<double>, Parts
 template hipError_t launch_append<float>(const ScanJobs &, Parts<float>, Parts<float>,
                                          Parts<float>, Parts<float>, Counts *, Counts *, int64_t,
                                          hipStream_t);
-template hipError_t launch_resize<double>(Parts<double>, Counts *, Chunks, CloneRec *, double,
-                                          double, int64_t, int32_t *, hipStream_t);
-template hipError_t launch_resize<float>(Parts<float>, Counts *, Chunks, CloneRec *, double,
-                                         double, int64_t, int32_t *, hipStream_t);
+template hipError_t launch_resize<double>(Parts<double>, Counts *, Chunks, CloneRec *,
+                                          const ResizeKey &, double, double, int64_t, int32_t *,
+                                          hipStream_t);
+template hipError_t launch_resize<float>(Parts<float>, Counts *, Chunks, CloneRec *,
+                                         const ResizeKey &, double, double, int64_t, int32_t *,
+                                         hipStream_t);
 
 }  // namespace rz

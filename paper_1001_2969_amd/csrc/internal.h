@@ -237,9 +237,17 @@ template <typename T>
 hipError_t launch_append(const ScanJobs &j, Parts<T> dst0, Parts<T> dst1, Parts<T> stage0,
                          Parts<T> stage1, Counts *cnt0, Counts *cnt1, int64_t max_chunks,
                          hipStream_t st);
+// Mode of the periodic resize: the weight-conserving split, or zero-order
+// particle-based resizing with draws keyed by (seed, s, id, step).
+struct ResizeKey {
+    int zero_order, s;
+    uint64_t seed;
+    uint32_t step;
+};
 template <typename T>
-hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, double wcoef,
-                         double half_hr, int64_t cap, int32_t *status, hipStream_t st);
+hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, const ResizeKey &k,
+                         double wcoef, double half_hr, int64_t cap, int32_t *status,
+                         hipStream_t st);
 hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
                                 int nn, hipStream_t st);
 // Both species: slices0[nb0][nn] into acc0 and slices1[nb1][nn] into acc1.

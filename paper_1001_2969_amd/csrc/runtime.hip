@@ -661,11 +661,29 @@ template <typename T> rzpic_status deposit_impl(rzpic_ctx *c)
     return RZPIC_OK;
 }
 
-template <typename T> rzpic_status resize_impl(rzpic_ctx *c, int s)
+// Resize of species s in step `step` (the key of the zero-order draws).  The
+// zero-order form marks the particles it removes (w = -1); the caller
+// compacts (zero_order_compact).
+template <typename T> rzpic_status resize_impl(rzpic_ctx *c, int s, int64_t step)
 {
-    HIPCHK(launch_resize<T>(parts_of<T>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->clrec + s,
+    ResizeKey k{};
+    k.zero_order = c->c.resize_mode == RZPIC_RESIZE_ZERO_ORDER;
+    k.s = s;
+    k.seed = c->c.seed;
+    k.step = (uint32_t)step;
+    HIPCHK(launch_resize<T>(parts_of<T>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->clrec + s, k,
                             c->c.resize_wcoef, 0.5 * c->hr, c->sp[s].cap, c->status, c->st));
     return RZPIC_OK;
+}
+
+// Compaction after a zero-order resize of the species in `which` (bit s).
+template <typename T> rzpic_status zero_order_compact(rzpic_ctx *c, int which)
+{
+    if (c->c.resize_mode != RZPIC_RESIZE_ZERO_ORDER) return RZPIC_OK;
+    for (int s = 0; s < 2; ++s)
+        if ((which >> s) & 1)
+            HIPCHK(launch_dead_scan<T>(parts_of<T>(c->sp[s].v), c->cnt + s, c->sp[s].ch, c->st));
+    return run_fixup<T>(c, which);
 }
 
 // Scratch of the tile sort of species s (sized by its capacity).
@@ -818,8 +836,10 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
     // particle order, and the sorted order gives the deposit its windows).
     const bool resize = c->c.resize_every > 0 && n % c->c.resize_every == c->c.resize_every - 1;
     const bool sort = c->c.sort_every > 0 && n % c->c.sort_every == c->c.sort_every - 1;
-    if (resize)
-        for (int s = 0; s < 2; ++s) TRY(resize_impl<T>(c, s));
+    if (resize) {
+        for (int s = 0; s < 2; ++s) TRY(resize_impl<T>(c, s, n));
+        TRY(zero_order_compact<T>(c, 3));
+    }
     mark(c, 8);
     if (sort)
         for (int s = 0; s < 2; ++s) TRY(sort_impl<T>(c, s));
@@ -926,6 +946,8 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     if (k.ion_subcycle < 0) return fail(RZPIC_EINVAL, "ion_subcycle must be >= 0");
     if (k.push_form != RZPIC_PUSH_LOCAL && k.push_form != RZPIC_PUSH_XYZ)
         return fail(RZPIC_EINVAL, "unknown push_form %d", k.push_form);
+    if (k.resize_mode != RZPIC_RESIZE_SPLIT && k.resize_mode != RZPIC_RESIZE_ZERO_ORDER)
+        return fail(RZPIC_EINVAL, "unknown resize_mode %d", k.resize_mode);
 
     rzpic_ctx *c = new rzpic_ctx();
     c->c = k;
@@ -1384,8 +1406,13 @@ rzpic_status rzpic_resize(rzpic_ctx *c, int32_t s)
     TRY(need_species(c, s));
     if (!(c->c.resize_wcoef > 0)) return fail(RZPIC_EINVAL, "resize_wcoef must be positive");
     if (c->children_pending[s]) return fail(RZPIC_ESTATE, "call rzpic_compact before rzpic_resize");
-    if (c->mixed) TRY(resize_impl<float>(c, s));
-    else TRY(resize_impl<double>(c, s));
+    if (c->mixed) {
+        TRY(resize_impl<float>(c, s, 0));
+        TRY(zero_order_compact<float>(c, 1 << s));
+    } else {
+        TRY(resize_impl<double>(c, s, 0));
+        TRY(zero_order_compact<double>(c, 1 << s));
+    }
     return RZPIC_OK;
 }
 
