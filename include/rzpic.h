@@ -244,6 +244,23 @@ rzpic_status rzpic_prologue(rzpic_ctx *ctx);
  * composition of the single operations above. */
 rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
 
+/* Launch shape of the fused particle pass: threads per block (256, 512 or
+ * 1024) and particles of capacity per block (default 512 threads, 8192).
+ * Results do not depend on it (integer deposit, identities from event
+ * ranks, compaction by index), only the speed.  A tile-sorted context is
+ * sorted again so that its tile plan fits the new block count.  EINVAL for
+ * a shape beyond the pass's wavefront limit. */
+rzpic_status rzpic_set_pass_shape(rzpic_ctx *ctx, int32_t threads, int32_t parts_per_block);
+/* Autotuner of that shape: for each of threads {256, 512, 1024} x
+ * particles per block {2048, 4096, 8192, 16384} that fits, one warm-up and
+ * `steps` timed rzpic_step calls (HIP events on the context's stream),
+ * starting at step `step0`; keeps the fastest.  table (host, may be NULL)
+ * receives 12 rows {threads, parts_per_block, ms per step or -1 if skipped};
+ * best = {threads, parts_per_block}; *next_step the next step index.  The
+ * simulation advances by the steps run.  Synchronises. */
+rzpic_status rzpic_autotune(rzpic_ctx *ctx, int32_t steps, int64_t step0, double *table,
+                            int32_t best[2], int64_t *next_step);
+
 /* Copy grid `which` (RZPIC_G_*) between the context and a caller device
  * buffer of nz*nr doubles: to_ctx = 0 reads from the context, 1 writes into
  * it (PHI, RHO, CHI, ER, EZ, N0, N1 writable).  Asynchronous. */

@@ -75,6 +75,7 @@ struct rzpic_ctx {
     int mixed = 0;
     int pass_threads = 512;
     int tile_per_cu = 1;  // resident blocks per CU of the tiled merged pass
+    int64_t parts_per_block = 8192;  // particles of capacity per pass block
     double hr = 0, hz = 0;
     int L = 0;
     int nn = 0;

@@ -215,14 +215,14 @@ template <typename T> PassArgs<T> pass_args(rzpic_ctx *c, int s, uint32_t step)
     return a;
 }
 
-// Pass blocks of species s, at most `most`: about one per kPartsPerBlock
-// particles of capacity, since every block of a deposit form pays a fixed
-// cost (zeroing and writing out its LDS grid or window) that only pays off
-// over enough particles.
-constexpr int64_t kPartsPerBlock = 8192;
+// Pass blocks of species s, at most `most`: about one per parts_per_block
+// (8192 unless tuned) particles of capacity, since every block of a deposit
+// form pays a fixed cost (zeroing and writing out its LDS grid or window)
+// that only pays off over enough particles.
 int pass_blocks(const rzpic_ctx *c, int s, int most)
 {
-    const int64_t want = (c->sp[s].cap + kPartsPerBlock - 1) / kPartsPerBlock;
+    const int64_t ppb = c->parts_per_block;
+    const int64_t want = (c->sp[s].cap + ppb - 1) / ppb;
     if (most < 1) most = 1;
     return (int)(want < 1 ? 1 : (want < most ? want : most));
 }
@@ -1442,11 +1442,116 @@ rzpic_status rzpic_prologue(rzpic_ctx *c)
     return RZPIC_OK;
 }
 
+// Launch shape of the fused pass: threads per block and particles of
+// capacity per block.  The results do not depend on it (integer deposit,
+// identities from event ranks, compaction by index), only the speed.
+static rzpic_status set_shape(rzpic_ctx *c, int threads, int64_t ppb)
+{
+    c->pass_threads = threads;
+    c->parts_per_block = ppb;
+    if (!c->lds_ok)
+        c->tile_per_cu = c->mixed ? pass2_tiled_blocks_per_cu<float>(threads)
+                                  : pass2_tiled_blocks_per_cu<double>(threads);
+    // the tile plan is made for the tiled pass's block count: plan again
+    for (int s = 0; s < 2; ++s)
+        if (c->sp[s].tile_pb) {
+            if (c->mixed) TRY(sort_impl<float>(c, s));
+            else TRY(sort_impl<double>(c, s));
+        }
+    return RZPIC_OK;
+}
+
+// Whether a shape fits the pass's bucket layout (at most kMaxWaves wavefronts).
+static bool shape_fits(const rzpic_ctx *c, int threads, int64_t ppb)
+{
+    rzpic_ctx t = *c;  // copy of the scalars pass_blocks / tiled_blocks read
+    t.pass_threads = threads;
+    t.parts_per_block = ppb;
+    if (!c->lds_ok)
+        t.tile_per_cu = c->mixed ? pass2_tiled_blocks_per_cu<float>(threads)
+                                 : pass2_tiled_blocks_per_cu<double>(threads);
+    int b0, b1;
+    if (c->lds_ok) {
+        b0 = pass_blocks(&t, 0, c->slice_blocks / 2);
+        b1 = pass_blocks(&t, 1, c->slice_blocks - c->slice_blocks / 2);
+    } else {
+        b0 = tiled_blocks(&t, 0);
+        b1 = tiled_blocks(&t, 1);
+    }
+    return (int64_t)(b0 + b1) * (threads / 64) <= kMaxWaves;
+}
+
 rzpic_status rzpic_step(rzpic_ctx *c, int64_t step)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
     if (step < 0 || step > 0xFFFFFFFELL) return fail(RZPIC_EINVAL, "step out of range");
     return c->mixed ? step_impl<float>(c, step) : step_impl<double>(c, step);
+}
+
+rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *table,
+                            int32_t best[2], int64_t *next_step)
+{
+    if (!c || !best || !next_step) return fail(RZPIC_EINVAL, "null argument");
+    if (steps < 1) return fail(RZPIC_EINVAL, "steps must be >= 1");
+    TRY(need_both(c));
+    if (c->timing) return fail(RZPIC_EINVAL, "autotune needs step timing off");
+    static const int kThreads[3] = {256, 512, 1024};
+    static const int64_t kPpb[4] = {2048, 4096, 8192, 16384};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int64_t n = step0;
+    double best_ms = -1.0;
+    int bt = c->pass_threads;
+    int64_t bp = c->parts_per_block;
+    rzpic_status st = RZPIC_OK;
+    for (int ti = 0; ti < 3 && st == RZPIC_OK; ++ti)
+        for (int pi = 0; pi < 4 && st == RZPIC_OK; ++pi) {
+            double ms = -1.0;
+            if (shape_fits(c, kThreads[ti], kPpb[pi])) {
+                st = set_shape(c, kThreads[ti], kPpb[pi]);
+                if (st == RZPIC_OK) st = rzpic_step(c, n++);  // warm-up
+                if (st == RZPIC_OK && hipEventRecord(e0, c->st) != hipSuccess)
+                    st = fail(RZPIC_EHIP, "hipEventRecord failed");
+                for (int k = 0; k < steps && st == RZPIC_OK; ++k) st = rzpic_step(c, n++);
+                float f = 0.0f;
+                if (st == RZPIC_OK && (hipEventRecord(e1, c->st) != hipSuccess ||
+                                       hipEventSynchronize(e1) != hipSuccess ||
+                                       hipEventElapsedTime(&f, e0, e1) != hipSuccess))
+                    st = fail(RZPIC_EHIP, "event timing failed");
+                if (st == RZPIC_OK) {
+                    ms = f / steps;
+                    if (best_ms < 0.0 || ms < best_ms) {
+                        best_ms = ms;
+                        bt = kThreads[ti];
+                        bp = kPpb[pi];
+                    }
+                }
+            }
+            if (table) {
+                table[3 * (4 * ti + pi) + 0] = kThreads[ti];
+                table[3 * (4 * ti + pi) + 1] = (double)kPpb[pi];
+                table[3 * (4 * ti + pi) + 2] = ms;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RZPIC_OK) return st;
+    TRY(set_shape(c, bt, bp));
+    best[0] = bt;
+    best[1] = (int32_t)bp;
+    *next_step = n;
+    return rzpic_sync(c);
+}
+
+rzpic_status rzpic_set_pass_shape(rzpic_ctx *c, int32_t threads, int32_t parts_per_block)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    if ((threads != 256 && threads != 512 && threads != 1024) || parts_per_block < 64)
+        return fail(RZPIC_EINVAL, "threads must be 256, 512 or 1024 and parts_per_block >= 64");
+    if (c->sp[0].bound && c->sp[1].bound && !shape_fits(c, threads, parts_per_block))
+        return fail(RZPIC_EINVAL, "the shape exceeds the pass's wavefront limit");
+    return set_shape(c, threads, parts_per_block);
 }
 
 rzpic_status rzpic_grid_copy(rzpic_ctx *c, int32_t which, double *dev, int32_t to_ctx)

@@ -30,7 +30,7 @@ EXPORTS = (
     "rzpic_batch_create", "rzpic_batch_step", "rzpic_batch_stats", "rzpic_batch_destroy",
     "rzpic_batch_set_graph", "rzpic_set_voltage", "rzpic_adjoint_create",
     "rzpic_adjoint_forward", "rzpic_adjoint_backward", "rzpic_adjoint_destroy",
-    "rzpic_set_circuit", "rzpic_get_circuit",
+    "rzpic_set_circuit", "rzpic_get_circuit", "rzpic_set_pass_shape", "rzpic_autotune",
 )
 
 
@@ -119,6 +119,8 @@ def lib():
             "rzpic_batch_destroy": [P], "rzpic_batch_set_graph": [P, I],
             "rzpic_set_voltage": [P, D, D, D],
             "rzpic_set_circuit": [P, D, D, D], "rzpic_get_circuit": [P, P],
+            "rzpic_set_pass_shape": [P, I, I],
+            "rzpic_autotune": [P, I, C.c_int64, P, P, C.POINTER(C.c_int64)],
             "rzpic_adjoint_create": [P, C.POINTER(AdjointConfig), C.POINTER(P)],
             "rzpic_adjoint_forward": [P, C.c_int64, C.POINTER(D)],
             "rzpic_adjoint_backward": [P, P, P, P, P], "rzpic_adjoint_destroy": [P],
@@ -310,6 +312,21 @@ class Context:
 
     def set_circuit(self, V, Q, Qc):
         _check(lib().rzpic_set_circuit(self.h, V, Q, Qc))
+
+    def set_pass_shape(self, threads, parts_per_block):
+        _check(lib().rzpic_set_pass_shape(self.h, threads, parts_per_block))
+
+    def autotune(self, steps, step0):
+        """Times the fused pass's launch shapes over real steps from step0 and
+        keeps the fastest; returns (best (threads, parts_per_block), table of
+        (threads, parts_per_block, ms per step), next step index)."""
+        table = (C.c_double * 36)()
+        best = (C.c_int32 * 2)()
+        nxt = C.c_int64()
+        _check(lib().rzpic_autotune(self.h, steps, step0, C.cast(table, C.c_void_p),
+                                    C.cast(best, C.c_void_p), C.byref(nxt)))
+        rows = [(int(table[3 * k]), int(table[3 * k + 1]), table[3 * k + 2]) for k in range(12)]
+        return (best[0], best[1]), rows, nxt.value
 
     def circuit(self):
         """{V, Q, Q_c, Q_conv, Q_P, Q_L} of the last solve (external circuit)."""
