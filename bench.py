@@ -30,10 +30,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE = {"mixed": 8 * 4 + 8 + 7 * 4, "fp64": 8 * 8 + 8 + 7 * 8}
 
 
-def measured_traffic(name):
+def measured_traffic(name, shape=None):
     """HBM bytes per particle of the fused pass from a committed counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
-    the kernel sources have changed since the counters were taken."""
+    the kernel sources have changed since the counters were taken, or when
+    `shape` (threads, particles per block) is not the launch shape they were
+    taken with."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", name)
@@ -45,6 +47,9 @@ def measured_traffic(name):
     hs = re.search(r"^kernel_sources_sha256: ([0-9a-f]{64})$", text, re.M)
     if not t or not hs:
         return None
+    sh = re.search(r"^pass_shape: ([0-9]+) ([0-9]+)$", text, re.M)
+    if shape is not None and (not sh or (int(sh.group(1)), int(sh.group(2))) != tuple(shape)):
+        return None
     h = hashlib.sha256()
     for f in ("particles.hip", "device.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_1001_2969_amd", "csrc", f), "rb") as fh:
@@ -52,11 +57,14 @@ def measured_traffic(name):
     return float(t.group(1)) if h.hexdigest() == hs.group(1) else None
 
 
-def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25):
+def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, tune=False,
+            shape=None):
     """Throughput over `steps` merged steps with nothing else on the stream,
     then `timing_steps` more with the library's HIP events around each phase
     (per-phase device times; every event costs the stream a few microseconds,
-    which is why the throughput run records none)."""
+    which is why the throughput run records none).  tune: the library's
+    autotuner picks the pass's launch shape first (its steps precede the
+    warm-up); shape: (threads, particles per block) set instead."""
     import torch
 
     from paper_1001_2969_amd import rzpic
@@ -70,6 +78,12 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25):
         for s in (0, 1):
             ctx.sort(s)
     n = 0
+    tuning_steps = 0
+    if tune:
+        shape, table, n = ctx.autotune(5, 0)
+        tuning_steps = n
+    elif shape is not None:
+        ctx.set_pass_shape(*shape)
     for _ in range(warmup):
         ctx.step(n)
         n += 1
@@ -96,6 +110,9 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25):
     return ctx, {
         "value": psteps / dt, "ms_per_step": 1e3 * dt / steps, "particle_steps": psteps,
         "timing": tim, "count": d1["count"], "events_last_step": d1["events"],
+        "pass_shape": None if shape is None else {"threads": shape[0],
+                                                  "particles_per_block": shape[1]},
+        "tuning_steps": tuning_steps,
     }
 
 
@@ -397,7 +414,7 @@ def circuit_and_subcycle(steps, warmup):
     return out
 
 
-def pmc_run(steps, workload):
+def pmc_run(steps, workload, shape=None):
     """Short run for hardware-counter passes: a few merged steps of the mixed
     workload, then a plain device copy of known size (the calibration of the
     byte counters: its algorithmic traffic is exactly the bytes read and
@@ -407,7 +424,10 @@ def pmc_run(steps, workload):
     from paper_1001_2969_amd import workloads as wl
 
     w = {"rf_129x65": wl.rf_129x65, "large_513x129": wl.large_513x129}[workload]()
-    ctx, res = run_gpu(w, "mixed", steps, 3, timing_steps=steps, capacity_factor=2.0)
+    # the pass shape the benchmark's autotuner picked (timings under a
+    # counter run are not the benchmark's, so no tuning here)
+    ctx, res = run_gpu(w, "mixed", steps, 3, timing_steps=steps, capacity_factor=2.0,
+                       shape=shape)
     ctx.close()
     nbytes = 256 << 20
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -418,7 +438,8 @@ def pmc_run(steps, workload):
     print(json.dumps({"pmc_run": True, "workload": w.name, "steps": steps, "particles_per_pass":
                       [res["timing"]["n0"], res["timing"]["n1"]],
                       "bytes_per_particle": BYTES_PER_PARTICLE["mixed"],
-                      "copy_bytes_each_way": nbytes}), flush=True)
+                      "copy_bytes_each_way": nbytes,
+                      "pass_shape": list(shape) if shape else [512, 8192]}), flush=True)
 
 
 def main():
@@ -440,11 +461,15 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the 257x129 / 4M-per-species gradient window")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default pass launch shape (no autotuning)")
     ap.add_argument("--no-circuit", action="store_true",
                     help="skip the external-circuit and ion-subcycling forms")
     ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
                     help="only a short mixed run plus a copy calibration (for counter passes)")
     ap.add_argument("--pmc-workload", default="rf_129x65", choices=["rf_129x65", "large_513x129"])
+    ap.add_argument("--pmc-shape", default=None, metavar="THREADS,PARTICLES",
+                    help="pass launch shape of the counter run (default 512,8192)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the "
@@ -458,18 +483,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.pmc_run:
-        pmc_run(args.pmc_run, args.pmc_workload)
+        pmc_run(args.pmc_run, args.pmc_workload,
+                None if args.pmc_shape is None else tuple(int(x) for x in args.pmc_shape.split(",")))
         return
     w = wl.rf_129x65()
     print(f"# workload {w.name}: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr,
           flush=True)
-    ctx_m, mixed = run_gpu(w, "mixed", args.steps, args.warmup)
+    ctx_m, mixed = run_gpu(w, "mixed", args.steps, args.warmup, tune=not args.no_tune)
     print(f"# mixed: {mixed['value']:.4g} particle-steps/s, {mixed['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)
     fp64 = None
     rho = chi = phi = None
     if not args.no_fp64:
-        ctx_d, fp64 = run_gpu(w, "fp64", args.steps, args.warmup)
+        ctx_d, fp64 = run_gpu(w, "fp64", args.steps, args.warmup, tune=not args.no_tune)
         print(f"# fp64: {fp64['value']:.4g} particle-steps/s, {fp64['ms_per_step']:.4f} ms/step",
               file=sys.stderr, flush=True)
         rho, chi, phi = (ctx_d.grid(g) for g in (rzpic.G_RHO, rzpic.G_CHI, rzpic.G_PHI))
@@ -513,7 +539,9 @@ def main():
                 "traffic": None,
                 "bytes_per_particle": bpp, "particles_per_launch": n_launch,
                 "avg_launch_ms": t_launch_ms}
-    tpp = measured_traffic("k_pass2_hbm_traffic_rf129x65.md")
+    ps = mixed["pass_shape"]
+    tpp = measured_traffic("k_pass2_hbm_traffic_rf129x65.md",
+                           None if ps is None else (ps["threads"], ps["particles_per_block"]))
     if tpp is not None:
         # counter bytes per particle (profile run) times this launch's particles
         roofline["traffic"] = tpp * n_launch
@@ -533,7 +561,8 @@ def main():
         "dtype": "f32 particles / f64 residual / int64 deposit", "data": "synthetic",
         "config": {"workload": w.name, "mesh": f"{w.nr}x{w.nz}", "R_m": w.R, "L_m": w.L,
                    "particles_per_species": w.n_per_species, "precision": "mixed",
-                   "v_cycles_per_step": w.mg_fixed_cycles, "V_rf": w.V_rf, "f_rf": w.f_rf},
+                   "v_cycles_per_step": w.mg_fixed_cycles, "V_rf": w.V_rf, "f_rf": w.f_rf,
+                   "pass_shape": mixed["pass_shape"]},
         "breakdown_ms_per_step": {k: tm[k] for k in ("step_ms", "solve_ms", "pass_ms",
                                                      "collide_ms", "grid_ms", "lists_ms",
                                                      "resize_ms", "sort_ms")},

@@ -254,7 +254,8 @@ rzpic_status rzpic_set_pass_shape(rzpic_ctx *ctx, int32_t threads, int32_t parts
 /* Autotuner of that shape: for each of threads {256, 512, 1024} x
  * particles per block {2048, 4096, 8192, 16384} that fits, one warm-up and
  * `steps` timed rzpic_step calls (HIP events on the context's stream),
- * starting at step `step0`; keeps the fastest.  table (host, may be NULL)
+ * starting at step `step0`; keeps the first shape in that order within 2 %
+ * of the fastest (near-ties do not flip between runs).  table (host, may be NULL)
  * receives 12 rows {threads, parts_per_block, ms per step or -1 if skipped};
  * best = {threads, parts_per_block}; *next_step the next step index.  The
  * simulation advances by the steps run.  Synchronises. */

@@ -1502,6 +1502,7 @@ rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *
     HIPCHK(hipEventCreate(&e1));
     int64_t n = step0;
     double best_ms = -1.0;
+    double times[12];
     int bt = c->pass_threads;
     int64_t bp = c->parts_per_block;
     rzpic_status st = RZPIC_OK;
@@ -1521,18 +1522,23 @@ rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *
                     st = fail(RZPIC_EHIP, "event timing failed");
                 if (st == RZPIC_OK) {
                     ms = f / steps;
-                    if (best_ms < 0.0 || ms < best_ms) {
-                        best_ms = ms;
-                        bt = kThreads[ti];
-                        bp = kPpb[pi];
-                    }
+                    if (best_ms < 0.0 || ms < best_ms) best_ms = ms;
                 }
             }
+            times[4 * ti + pi] = ms;
             if (table) {
                 table[3 * (4 * ti + pi) + 0] = kThreads[ti];
                 table[3 * (4 * ti + pi) + 1] = (double)kPpb[pi];
                 table[3 * (4 * ti + pi) + 2] = ms;
             }
+        }
+    // the first shape (table order) within 2 % of the fastest: near-ties do
+    // not flip the choice from run to run
+    for (int k = 0; k < 12 && best_ms > 0.0; ++k)
+        if (times[k] > 0.0 && times[k] <= 1.02 * best_ms) {
+            bt = kThreads[k / 4];
+            bp = kPpb[k % 4];
+            break;
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
