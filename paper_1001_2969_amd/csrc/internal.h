@@ -323,6 +323,8 @@ struct MgLevels {
     int line_off[kMaxLevels + 2];  // first table line of each level; line_off[L+1] = total
     size_t tab_stride;     // elements per line table: (3 + 2 S) (nr - 1)
     void *tab;             // line tables, float (mixed) or double
+    void *coarse_uf;       // levels 1..L-1: u then f of each level in one block
+                           //    (float when mixed), the coarse solve's LDS image
     double *res;           // finest-level residual scratch
     double *cf64;          // FP64 operator of the finest level: a, b, c, d, e arrays [nz][nr]
     size_t solve_lds;      // LDS bytes of the single-block kernel

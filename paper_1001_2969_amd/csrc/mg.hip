@@ -1087,29 +1087,51 @@ template <typename T, int Q, int SMAX> struct LineTab {
     T ta[Q], tc[Q], bf[Q], k1[SMAX][Q], k2[SMAX][Q];
 };
 
+// The loads alone (clamped indices), then the masking of unknowns past the
+// line's end and of reduction steps past S: a prefetched table is masked only
+// when it is used, so nothing waits for its loads before then.
 template <typename T, int Q, int SMAX>
-__device__ __forceinline__ void line_tab_load(const T *tb, int n, int S, int lane,
-                                              LineTab<T, Q, SMAX> &t)
+__device__ __forceinline__ void line_tab_fetch(const T *tb, int n, int S, int lane,
+                                               LineTab<T, Q, SMAX> &t)
 {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int j = q * 64 + lane;
-        const bool ok = j < n;
-        const int jj = ok ? j : n - 1;
+        const int jj = j < n ? j : n - 1;
         t.ta[q] = tb[jj];
         t.tc[q] = tb[n + jj];
-        const T b = tb[2 * n + jj];
-        t.bf[q] = ok ? b : (T)1;
+        t.bf[q] = tb[2 * n + jj];
 #pragma unroll
         for (int st = 0; st < SMAX; ++st) {
             const int sc = st < S ? st : S - 1;
-            const T v1 = tb[(size_t)(3 + 2 * sc) * n + jj];
-            const T v2 = tb[(size_t)(4 + 2 * sc) * n + jj];
-            const bool have = ok && st < S;
-            t.k1[st][q] = have ? v1 : (T)0;
-            t.k2[st][q] = have ? v2 : (T)0;
+            t.k1[st][q] = tb[(size_t)(3 + 2 * sc) * n + jj];
+            t.k2[st][q] = tb[(size_t)(4 + 2 * sc) * n + jj];
         }
     }
+}
+
+template <typename T, int Q, int SMAX>
+__device__ __forceinline__ void line_tab_mask(int n, int S, int lane, LineTab<T, Q, SMAX> &t)
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const bool ok = q * 64 + lane < n;
+        t.bf[q] = ok ? t.bf[q] : (T)1;
+#pragma unroll
+        for (int st = 0; st < SMAX; ++st) {
+            const bool have = ok && st < S;
+            t.k1[st][q] = have ? t.k1[st][q] : (T)0;
+            t.k2[st][q] = have ? t.k2[st][q] : (T)0;
+        }
+    }
+}
+
+template <typename T, int Q, int SMAX>
+__device__ __forceinline__ void line_tab_load(const T *tb, int n, int S, int lane,
+                                              LineTab<T, Q, SMAX> &t)
+{
+    line_tab_fetch<T, Q, SMAX>(tb, n, S, lane, t);
+    line_tab_mask<T, Q, SMAX>(n, S, lane, t);
 }
 
 // The reduction steps on the right-hand sides R (zero for j >= n), then the
@@ -1179,7 +1201,11 @@ __device__ __forceinline__ void k_solve_body(const Blk &kb_, const k_solve_A<T, 
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     const int L = m.L, nr = m.nr, n = nr - 1, nz = m.nzl[L], S = m.S;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    // wave index through readfirstlane: the compiler then knows it is uniform
+    // across the wavefront, and the level tables it indexes (line offsets,
+    // level sizes) come through scalar loads
+    const int lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     auto lev = [&](int l) {  // u of level l; its f follows at + nzl * nr
         size_t o = 0;
         for (int q = 1; q < l; ++q) o += 2 * (size_t)m.nzl[q] * nr;
@@ -1255,11 +1281,29 @@ __device__ __forceinline__ void k_solve_body(const Blk &kb_, const k_solve_A<T, 
         // levels 1..L-1 only: their right-hand sides come from a multi-block
         // residual and restriction launch, the correction u^{L-1} goes back to
         // global memory for the finest level's launch
-        for (int l = 1; l <= L - 1; ++l) {
-            const size_t sz = (size_t)m.nzl[l] * nr;
-            T *fl = lev(l) + sz;
-            const T *gf = mixed ? (const T *)m.f32[l] : (const T *)m.f64[l];
-            for (size_t t = threadIdx.x; t < sz; t += blockDim.x) fl[t] = gf[t];
+        // The levels' global arrays are one block laid out like this LDS
+        // image (u then f of each level), so the copy is one flat loop; each
+        // thread issues a batch of loads (up to 24) before any store, so the
+        // copy costs one global round trip.  The u rows it brings along are
+        // written by the sweeps before they are read.
+        {
+            constexpr int U = 24;
+            size_t total = 0;
+            for (int l = 1; l <= L - 1; ++l) total += 2 * (size_t)m.nzl[l] * nr;
+            const T *src = (const T *)m.coarse_uf;
+            for (size_t t0 = threadIdx.x; t0 < total; t0 += (size_t)U * blockDim.x) {
+                T v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const size_t t = t0 + (size_t)u * blockDim.x;
+                    v[u] = src[t < total ? t : total - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const size_t t = t0 + (size_t)u * blockDim.x;
+                    if (t < total) sm[t] = v[u];
+                }
+            }
         }
         __syncthreads();
         up(L - 1);
@@ -1424,12 +1468,18 @@ __device__ __forceinline__ void k_fine_body(const Blk &kb_, const k_fine_A<T, Q>
     constexpr int SMAX = Q == 1 ? 6 : Q == 2 ? 7 : 8;
     __shared__ T xs[2][Q * 64];
     const int L = m.L, nr = m.nr, n = nr - 1, nz = m.nzl[L], S = m.S;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int i = 2 * kb_.x + 2;
     const bool last = i + 1 == nz - 2;
     const T *uc = mixed ? (const T *)m.u32[L - 1] : (const T *)m.u64[L - 1];
     const T *fr = (const T *)m.f32[L];  // mixed: FP32 residual
     const T *tab0 = (const T *)m.tab + (size_t)(m.line_off[L] - 1) * m.tab_stride;
+    // wavefront 0 also fetches the even line's table, phi and right-hand side
+    // while it reduces its odd line, so that the even line starts right after
+    // the barrier
+    LineTab<T, Q, SMAX> te;
+    double ph2[Q];
+    T g2[Q];
     {
         const int io = i - 1 + 2 * w;
         LineTab<T, Q, SMAX> tb;
@@ -1460,6 +1510,16 @@ __device__ __forceinline__ void k_fine_body(const Blk &kb_, const k_fine_A<T, Q>
             }
             R[q] = ok ? g + tb.ta[q] * lo + tb.tc[q] * hi : (T)0;
         }
+        if (w == 0) {
+            line_tab_fetch<T, Q, SMAX>(tab0 + (size_t)i * m.tab_stride, n, S, lane, te);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int j = q * 64 + lane;
+                const int jj = j < n ? j : n - 1;
+                ph2[q] = phi_in[(size_t)i * nr + jj];
+                g2[q] = mixed ? fr[(size_t)i * nr + jj] : (T)f[(size_t)i * nr + jj];
+            }
+        }
         line_pcr<T, Q, SMAX>(R, tb, S, lane);
         const bool own = w == 0 || last;
 #pragma unroll
@@ -1472,25 +1532,21 @@ __device__ __forceinline__ void k_fine_body(const Blk &kb_, const k_fine_A<T, Q>
     }
     __syncthreads();
     if (w == 0) {
-        LineTab<T, Q, SMAX> tb;
-        line_tab_load<T, Q, SMAX>(tab0 + (size_t)i * m.tab_stride, n, S, lane, tb);
+        line_tab_mask<T, Q, SMAX>(n, S, lane, te);
         T R[Q];
-        double ph[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int j = q * 64 + lane;
             const bool ok = j < n;
             const int jj = ok ? j : n - 1;
-            ph[q] = phi_in[(size_t)i * nr + jj];
-            const T g = mixed ? fr[(size_t)i * nr + jj] : (T)f[(size_t)i * nr + jj];
-            R[q] = ok ? g + tb.ta[q] * xs[0][jj] + tb.tc[q] * xs[1][jj] : (T)0;
+            R[q] = ok ? g2[q] + te.ta[q] * xs[0][jj] + te.tc[q] * xs[1][jj] : (T)0;
         }
-        line_pcr<T, Q, SMAX>(R, tb, S, lane);
+        line_pcr<T, Q, SMAX>(R, te, S, lane);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int j = q * 64 + lane;
             if (j >= n) continue;
-            phi_out[(size_t)i * nr + j] = mixed ? ph[q] + (double)R[q] : (double)R[q];
+            phi_out[(size_t)i * nr + j] = mixed ? ph2[q] + (double)R[q] : (double)R[q];
         }
     }
 }

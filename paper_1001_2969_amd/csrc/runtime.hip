@@ -389,7 +389,20 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         const int nb = b[0] > b[1] ? b[0] : b[1];
         r.by = nb < 32 ? nb : 32;
     }
-    HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, r, c->st));
+    if ((mode & M_LDS) && !g_recorder) {
+        // the collisions, then the slice sum in a kernel of its own: in one
+        // launch the slice-sum blocks would run at the collision blocks'
+        // register allocation, and the two launches measure faster.  A
+        // recorded (batched) step keeps the single launch, whose blocks are
+        // the unit a batch replays for many discharges.
+        SliceSum r0 = r;
+        r0.nb[0] = r0.nb[1] = 0;
+        HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, r0, c->st));
+        HIPCHK(launch_reduce_slices2(r.acc[0], r.slices[0], r.nb[0], r.acc[1], r.slices[1],
+                                     r.nb[1], r.nn, c->st));
+    } else {
+        HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, r, c->st));
+    }
     mark(c, 6);
     return RZPIC_OK;
 }
@@ -1036,6 +1049,17 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     m.nr = k.nr;
     m.chi_face = k.chi_face;
     m.hr = c->hr;
+    // u and f of the coarse levels 1..L-1 in one block, level by level (the
+    // layout the single-workgroup coarse solve holds in LDS)
+    size_t coarse_elems = 0;
+    for (int l = 1; l < L; ++l) coarse_elems += 2 * (((size_t)1 << l) + 1) * (size_t)k.nr;
+    float *cuf32 = nullptr;
+    double *cuf64 = nullptr;
+    if (c->mixed) {
+        A(cuf32, coarse_elems) m.coarse_uf = cuf32;
+    } else {
+        A(cuf64, coarse_elems) m.coarse_uf = cuf64;
+    }
     for (int l = 1; l <= L; ++l) {
         m.nzl[l] = (1 << l) + 1;
         m.hzl[l] = c->hz * (double)(1 << (L - l));
@@ -1046,9 +1070,18 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
             A(m.eps64[l], sz)
         }
         if (c->mixed) {
-            A(m.eps32[l], sz) A(m.u32[l], sz) A(m.f32[l], sz)
+            A(m.eps32[l], sz)
+            if (l == L) {
+                A(m.u32[l], sz) A(m.f32[l], sz)
+            } else {
+                m.u32[l] = cuf32;
+                m.f32[l] = cuf32 + sz;
+                cuf32 += 2 * sz;
+            }
         } else if (l < L) {
-            A(m.u64[l], sz) A(m.f64[l], sz)
+            m.u64[l] = cuf64;
+            m.f64[l] = cuf64 + sz;
+            cuf64 += 2 * sz;
         }
     }
     {
