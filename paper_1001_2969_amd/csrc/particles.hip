@@ -2,6 +2,7 @@
 // Monte Carlo, first push, deposit), initialisation and the pass over staged
 // new particles.
 #include "device.h"
+#include <type_traits>
 
 namespace rz {
 
@@ -149,6 +150,15 @@ template <typename T> __device__ __forceinline__ PState<T> load(const Parts<T> &
                      p.ar[i], p.az[i], p.w[i], p.at ? p.at[i] : (T)0};
 }
 
+// load() with the a_theta array's presence fixed at compile time: no load
+// behind a branch, so the compiler's memory-counter waits stay exact across a
+// loop that keeps loads in flight from one iteration to the next.
+template <typename T, bool X> __device__ __forceinline__ PState<T> load_x(const Parts<T> &p, int64_t i)
+{
+    return PState<T>{p.r[i], p.z[i], p.vr[i], p.vt[i], p.vz[i],
+                     p.ar[i], p.az[i], p.w[i], X ? p.at[i] : (T)0};
+}
+
 template <typename T>
 __device__ __forceinline__ void store(const Parts<T> &p, int64_t i, const PState<T> &s, bool w)
 {
@@ -238,7 +248,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
 
     // The rest of the cycle of chunk c from its loaded state s, identity pid
     // and gathered field (Er, Ez).
-    auto chunk = [&](int64_t c, PState<T> s, uint64_t pid, T Er, T Ez) {
+    auto chunk = [&](int64_t c, PState<T> s, uint64_t pid, T Er, T Ez, auto &&after_mc) {
         const int64_t pi = c * kChunk + lane;
         const bool valid = pi < n;
         bool live = valid;
@@ -301,6 +311,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
                 a.ch.si[c] = 0;
             }
         }
+        after_mc();
         if ((MODE & M_FIRST) && live && !cand) {
             first_push<T>(s, dt, xyz);
             moved = true;
@@ -363,7 +374,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            if (cc[u] >= 0) chunk(cc[u], s[u], pid[u], Er[u], Ez[u]);
+            if (cc[u] >= 0) chunk(cc[u], s[u], pid[u], Er[u], Ez[u], [] {});
     };
     if (kTile) {
         // the planned range, then this block's share of the chunks beyond
@@ -375,6 +386,42 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         const int64_t d0 = (int64_t)gb * q + (int64_t)lb * q2;
         const int64_t d1 = d0 + q2 < nch ? d0 + q2 : nch;
         for (int64_t c = d0 + wib; c < d1; c += kUnroll * wpb) group(c, wpb, d1);
+    } else if (kLds) {
+        // Software pipeline: the next chunk's particle loads are issued after
+        // this chunk's Monte Carlo test (whose cross-section loads would
+        // otherwise wait for them) and fly during its first push, deposit and
+        // stores.  The loads are unconditional (past the end they read
+        // particle 0, unused) and the a_theta choice is a compile-time
+        // branch: a load behind a branch would make the compiler wait for
+        // every load in flight.
+        auto pipeline = [&](auto xyz_c) {
+            constexpr bool X = decltype(xyz_c)::value;
+            auto fetch = [&](int64_t cc, PState<T> &st, uint64_t &id) {
+                const int64_t pi = cc * kChunk + lane;
+                const int64_t pl = cc < nch && pi < n ? pi : 0;
+                st = load_x<T, X>(a.p, pl);
+                id = kMc ? a.p.id[pl] : 0;
+            };
+            PState<T> sn;
+            uint64_t pn;
+            fetch(wave, sn, pn);
+            for (int64_t c = wave; c < nch; c += nwaves) {
+                const PState<T> s = sn;
+                const uint64_t pid = pn;
+                T Er = (T)0, Ez = (T)0;
+                if (MODE & M_FINAL) gather_E<T>(m, a.E2, s.r, s.z, Er, Ez);
+                chunk(c, s, pid, Er, Ez, [&] {
+                    // after this chunk's loads in issue order
+                    __builtin_amdgcn_sched_barrier(0);
+                    fetch(c + nwaves, sn, pn);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            }
+        };
+        if (xyz)
+            pipeline(std::true_type{});
+        else
+            pipeline(std::false_type{});
     } else {
         for (int64_t c = wave; c < nch; c += kUnroll * nwaves) group(c, nwaves, nch);
     }
