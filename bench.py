@@ -562,7 +562,8 @@ def main():
         "config": {"workload": w.name, "mesh": f"{w.nr}x{w.nz}", "R_m": w.R, "L_m": w.L,
                    "particles_per_species": w.n_per_species, "precision": "mixed",
                    "v_cycles_per_step": w.mg_fixed_cycles, "V_rf": w.V_rf, "f_rf": w.f_rf,
-                   "pass_shape": mixed["pass_shape"]},
+                   "pass_shape": mixed["pass_shape"],
+                   "autotune_steps": mixed["tuning_steps"]},
         "breakdown_ms_per_step": {k: tm[k] for k in ("step_ms", "solve_ms", "pass_ms",
                                                      "collide_ms", "grid_ms", "lists_ms",
                                                      "resize_ms", "sort_ms")},
