@@ -248,6 +248,8 @@ template <typename T>
 hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, const ResizeKey &k,
                          double wcoef, double half_hr, int64_t cap, int32_t *status,
                          hipStream_t st);
+// The slice sum of a merged step on its own (blockDim 256; r.bx * 256 >= nn).
+hipError_t launch_slice_sum(const SliceSum &r, hipStream_t st);
 hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
                                 int nn, hipStream_t st);
 // Both species: slices0[nb0][nn] into acc0 and slices1[nb1][nn] into acc1.

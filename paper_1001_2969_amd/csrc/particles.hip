@@ -635,6 +635,27 @@ template <typename T, int MODE> __device__ __forceinline__ void collide2_body(co
     atomicAdd(r.acc[s] + g, sum);
 }
 
+// The sum of the pass's LDS slices alone (blocks as in collide2_body's
+// slice part), as a body of its own: the collision kernel's large register
+// allocation would leave these blocks at one wavefront per SIMD, and a
+// batched step runs this body for many discharges in one launch.
+__device__ __forceinline__ void slice_sum_body(const Blk &k, const SliceSum &r)
+{
+    const int per = r.bx * r.by;
+    const int s = k.x / per, x = k.x % r.bx, y = (k.x % per) / r.bx;
+    const int g = x * blockDim.x + threadIdx.x;
+    if (g >= r.nn) return;
+    const unsigned long long *sl = r.slices[s];
+    unsigned long long sum = 0;
+    for (int q = y; q < r.nb[s]; q += r.by) sum += sl[(size_t)q * r.nn + g];
+    atomicAdd(r.acc[s] + g, sum);
+}
+
+hipError_t launch_slice_sum(const SliceSum &r, hipStream_t st)
+{
+    return launch<SliceSum, slice_sum_body, 256>(dim3(2 * r.bx * r.by), dim3(256), 0, st, r);
+}
+
 // Staged new particles of species cs (unmerged form): first push or deposit
 // of the children recorded in the electron chunk masks (slot = parent index).
 template <typename T, int MODE>

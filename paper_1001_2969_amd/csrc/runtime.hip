@@ -389,17 +389,15 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         const int nb = b[0] > b[1] ? b[0] : b[1];
         r.by = nb < 32 ? nb : 32;
     }
-    if ((mode & M_LDS) && !g_recorder) {
+    if (mode & M_LDS) {
         // the collisions, then the slice sum in a kernel of its own: in one
-        // launch the slice-sum blocks would run at the collision blocks'
-        // register allocation, and the two launches measure faster.  A
-        // recorded (batched) step keeps the single launch, whose blocks are
-        // the unit a batch replays for many discharges.
+        // launch the slice-sum blocks would run at the collision kernel's
+        // register allocation (one wavefront per SIMD).  Both are bodies a
+        // batched step runs for many discharges at once.
         SliceSum r0 = r;
         r0.nb[0] = r0.nb[1] = 0;
         HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, r0, c->st));
-        HIPCHK(launch_reduce_slices2(r.acc[0], r.slices[0], r.nb[0], r.acc[1], r.slices[1],
-                                     r.nb[1], r.nn, c->st));
+        HIPCHK(launch_slice_sum(r, c->st));
     } else {
         HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, r, c->st));
     }
