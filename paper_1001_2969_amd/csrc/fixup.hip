@@ -509,36 +509,6 @@ hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long lon
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_reduce_slices2(unsigned long long *acc0,
-                                                        const unsigned long long *slices0, int nb0,
-                                                        unsigned long long *acc1,
-                                                        const unsigned long long *slices1, int nb1,
-                                                        int nn)
-{
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nn) return;
-    const bool one = blockIdx.z != 0;
-    const unsigned long long *sl = one ? slices1 : slices0;
-    const int nb = one ? nb1 : nb0;
-    unsigned long long s = 0;
-    for (int b = blockIdx.y; b < nb; b += gridDim.y) s += sl[(size_t)b * nn + g];
-    atomicAdd((one ? acc1 : acc0) + g, s);
-}
-
-hipError_t launch_reduce_slices2(unsigned long long *acc0, const unsigned long long *slices0,
-                                 int nb0, unsigned long long *acc1,
-                                 const unsigned long long *slices1, int nb1, int nn,
-                                 hipStream_t st)
-{
-    int threads = 256;
-    int bx = (nn + threads - 1) / threads;
-    int nb = nb0 > nb1 ? nb0 : nb1;
-    int by = nb < 32 ? nb : 32;
-    RZ_LAUNCH(k_reduce_slices2, dim3(bx, by, 2), dim3(threads), 0, st, acc0, slices0, nb0,
-                       acc1, slices1, nb1, nn);
-    return hipGetLastError();
-}
-
 template hipError_t launch_dead_scan<double>(Parts<double>, const Counts *, Chunks, hipStream_t);
 template hipError_t launch_dead_scan<float>(Parts<float>, const Counts *, Chunks, hipStream_t);
 template hipError_t launch_fill<double>(Parts<double>, Chunks, const FixRec *, hipStream_t);

@@ -172,9 +172,9 @@ __host__ __device__ inline int64_t tiled_q2(int64_t nch, int nb, int64_t q)
 }
 
 // Sum of per-block LDS deposit slices into the deposit grids of both
-// species, run by extra blocks of the collision launch: block b of those
-// 2 * bx * by blocks takes species b / (bx by), nodes of column block b % bx
-// (256 per block) and every by-th slice.
+// species (launch_slice_sum): block b of the 2 * bx * by blocks takes
+// species b / (bx by), nodes of column block b % bx (256 per block) and
+// every by-th slice.
 struct SliceSum {
     unsigned long long *acc[2];
     const unsigned long long *slices[2];
@@ -193,7 +193,7 @@ hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, 
 template <typename T> int pass2_tiled_blocks_per_cu(int threads);
 template <typename T>
 hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
-                           int threads, const SliceSum &r, hipStream_t st);
+                           int threads, hipStream_t st);
 template <typename T>
 hipError_t launch_collide(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
                           hipStream_t st);
@@ -252,11 +252,6 @@ hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, cons
 hipError_t launch_slice_sum(const SliceSum &r, hipStream_t st);
 hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
                                 int nn, hipStream_t st);
-// Both species: slices0[nb0][nn] into acc0 and slices1[nb1][nn] into acc1.
-hipError_t launch_reduce_slices2(unsigned long long *acc0, const unsigned long long *slices0,
-                                 int nb0, unsigned long long *acc1,
-                                 const unsigned long long *slices1, int nb1, int nn,
-                                 hipStream_t st);
 
 // sort.hip: stable counting sort of a species by tile of the cell of each
 // particle, and the window plan of the tiled pass.

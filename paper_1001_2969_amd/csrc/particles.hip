@@ -604,41 +604,26 @@ template <typename T, int MODE> __global__ __launch_bounds__(256) void k_collide
     collide_body<T, MODE>(a, blockIdx.x, gridDim.x);
 }
 
-// Collisions of both species (blocks [0, c0) species 0, [c0, c0 + c1)
-// species 1) and, in the remaining blocks, the sum of the pass's LDS slices:
-// both only add into the deposit grids, so they run side by side.
+// Collisions of both species in one launch: blocks [0, c0) species 0,
+// [c0, c0 + c1) species 1.
 template <typename T> struct Collide2Args {
     PassArgs<T> a0, a1;
     int c0, c1;
-    SliceSum r;
 };
 
 template <typename T, int MODE> __device__ __forceinline__ void collide2_body(const Blk &k, const Collide2Args<T> &a)
 {
-    const int b = k.x, c0 = a.c0, c1 = a.c1;
-    if (b < c0) {
-        collide_body<T, MODE>(a.a0, b, c0);
-        return;
-    }
-    if (b < c0 + c1) {
-        collide_body<T, MODE>(a.a1, b - c0, c1);
-        return;
-    }
-    const SliceSum &r = a.r;
-    const int rb = b - c0 - c1, per = r.bx * r.by;
-    const int s = rb / per, x = rb % r.bx, y = (rb % per) / r.bx;
-    const int g = x * blockDim.x + threadIdx.x;
-    if (g >= r.nn) return;
-    const unsigned long long *sl = r.slices[s];
-    unsigned long long sum = 0;
-    for (int k = y; k < r.nb[s]; k += r.by) sum += sl[(size_t)k * r.nn + g];
-    atomicAdd(r.acc[s] + g, sum);
+    const int b = k.x;
+    if (b < a.c0) collide_body<T, MODE>(a.a0, b, a.c0);
+    else collide_body<T, MODE>(a.a1, b - a.c0, a.c1);
 }
 
-// The sum of the pass's LDS slices alone (blocks as in collide2_body's
-// slice part), as a body of its own: the collision kernel's large register
-// allocation would leave these blocks at one wavefront per SIMD, and a
-// batched step runs this body for many discharges in one launch.
+// The sum of the pass's LDS slices into the deposit grids: block
+// (s, y, x) of 2 x by x bx adds slices y, y + by, ... of species s at nodes
+// [256x, 256x + 256) and adds the sum atomically.  A body of its own rather
+// than blocks of the collision kernel, whose large register allocation
+// would leave them at one wavefront per SIMD; a batched step runs it for
+// many discharges in one launch.
 __device__ __forceinline__ void slice_sum_body(const Blk &k, const SliceSum &r)
 {
     const int per = r.bx * r.by;
@@ -821,11 +806,10 @@ template <typename T> int pass2_tiled_blocks_per_cu(int threads)
 
 template <typename T>
 hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
-                           int threads, const SliceSum &r, hipStream_t st)
+                           int threads, hipStream_t st)
 {
-    const int nred = r.nb[0] + r.nb[1] > 0 ? 2 * r.bx * r.by : 0;
     return launch<Collide2Args<T>, collide2_body<T, M_FIRST>, 256>(
-        dim3(c0 + c1 + nred), dim3(threads), 0, st, Collide2Args<T>{a0, a1, c0, c1, r});
+        dim3(c0 + c1), dim3(threads), 0, st, Collide2Args<T>{a0, a1, c0, c1});
 }
 
 template int pass2_tiled_blocks_per_cu<double>(int);
@@ -835,9 +819,9 @@ template hipError_t launch_pass2<double>(int, const PassArgs<double> &, const Pa
 template hipError_t launch_pass2<float>(int, const PassArgs<float> &, const PassArgs<float> &, int,
                                         int, int, size_t, hipStream_t);
 template hipError_t launch_collide2<double>(const PassArgs<double> &, const PassArgs<double> &,
-                                            int, int, int, const SliceSum &, hipStream_t);
+                                            int, int, int, hipStream_t);
 template hipError_t launch_collide2<float>(const PassArgs<float> &, const PassArgs<float> &, int,
-                                           int, int, const SliceSum &, hipStream_t);
+                                           int, int, hipStream_t);
 template hipError_t launch_pass<double>(int, const PassArgs<double> &, int, int, size_t,
                                         hipStream_t);
 template hipError_t launch_pass<float>(int, const PassArgs<float> &, int, int, size_t, hipStream_t);

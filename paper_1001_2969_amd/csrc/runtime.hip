@@ -389,18 +389,12 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         const int nb = b[0] > b[1] ? b[0] : b[1];
         r.by = nb < 32 ? nb : 32;
     }
-    if (mode & M_LDS) {
-        // the collisions, then the slice sum in a kernel of its own: in one
-        // launch the slice-sum blocks would run at the collision kernel's
-        // register allocation (one wavefront per SIMD).  Both are bodies a
-        // batched step runs for many discharges at once.
-        SliceSum r0 = r;
-        r0.nb[0] = r0.nb[1] = 0;
-        HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, r0, c->st));
-        HIPCHK(launch_slice_sum(r, c->st));
-    } else {
-        HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, r, c->st));
-    }
+    // the collisions, then (whole-grid LDS form) the slice sum in a kernel
+    // of its own: in one launch the slice-sum blocks would run at the
+    // collision kernel's register allocation (one wavefront per SIMD).  Both
+    // are bodies a batched step runs for many discharges at once.
+    HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, c->st));
+    if (mode & M_LDS) HIPCHK(launch_slice_sum(r, c->st));
     mark(c, 6);
     return RZPIC_OK;
 }
