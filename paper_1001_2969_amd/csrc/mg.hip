@@ -324,55 +324,103 @@ __device__ __forceinline__ void k_line_body(const Blk &kb_, const k_line_A<T> &A
 template <typename T, int EPT>
 __device__ __forceinline__ void pcr(T *A, T *Bd, T *C, T *Rr, int n, int ne);
 
+// LDS slot of element e of a staged chunk: one pad slot after every Q
+// elements, so that a thread's segment read (stride Q + 1) spreads over the
+// banks while the coalesced staging writes stay contiguous.
+template <int Q> __device__ __forceinline__ int part_slot(int e) { return e + e / Q; }
+
+// Staging passes of k_line_part: a pass stages the rows of NT / P segments
+// (Q NT / P rows of four values) in LDS; P keeps a pass near 72 KB for Q >= 4,
+// so that two blocks can share a compute unit's LDS.
+template <typename T, int Q> constexpr int part_passes()
+{
+    return Q * (int)sizeof(T) / 16 > 1 ? Q * (int)sizeof(T) / 16 : 1;
+}
+
+template <typename T, int Q> constexpr size_t part_lds()
+{
+    constexpr int P = part_passes<T, Q>();
+    constexpr size_t ch = (size_t)Q * kLongThreads / P;
+    constexpr size_t stage = 4 * (ch + ch / Q);
+    constexpr size_t red = 7 * (size_t)kLongThreads;
+    return (stage > red ? stage : red) * sizeof(T);
+}
+
 template <typename T, int Q>
 __global__ __launch_bounds__(kLongThreads) void k_line_part(LineArgs<T> p)
 {
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
-    const int NT = blockDim.x;
-    T *RA = sm, *RB = sm + NT, *RC = sm + 2 * NT, *RR = sm + 3 * NT;
-    T *X0 = sm + 4 * NT, *X1 = sm + 5 * NT, *X2 = sm + 6 * NT;
+    constexpr int NT = kLongThreads;
+    constexpr int P = part_passes<T, Q>();
+    constexpr int TPP = NT / P;          // segments staged per pass
+    constexpr int CH = TPP * Q;          // rows staged per pass
+    constexpr int CHP = CH + CH / Q;     // with the pad slots
+    constexpr int RPT = CH / NT;         // rows each thread stages per pass
+    static_assert(RPT * NT == CH && TPP * P == NT, "staging shape");
+    T *SA = sm, *SB = sm + CHP, *SC = sm + 2 * CHP, *SR = sm + 3 * CHP;
     const int nr = p.nr, n = nr - 1, nzl = p.nzl;
     const int i = p.parity ? 2 * blockIdx.x + 1 : 2 * blockIdx.x + 2;
-    const int t = threadIdx.x, j0 = t * Q;
+    const int t = threadIdx.x, mine = t / TPP, tl = t - mine * TPP;
     auto nb = [&](int row, int j) -> T {
         bool bnd = row == 0 || row == nzl - 1;
         T v = p.zero_old ? (T)0 : p.u[(size_t)row * nr + j];
         if (!bnd && p.uc) v += p.uc[(size_t)(row >> 1) * nr + j];
         return v;
     };
-    // rows of the segment: a x_{j-1} + b x_j + c x_{j+1} = r
+    // rows of the segment: a x_{j-1} + b x_j + c x_{j+1} = r.  Each pass
+    // forms its rows with coalesced loads (thread t: rows k NT + t of the
+    // chunk) into LDS; the threads whose segments lie in the chunk then read
+    // them back and eliminate.
     T ap[Q], bp[Q], c[Q], rp[Q];
+    for (int ps = 0; ps < P; ++ps) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int j = j0 + q;
-        T a = (T)0, b = (T)1, cc = (T)0, r = (T)0;
-        if (j < n) {
-            Coef<T> k = coef<T>(p.eps, nr, i, j, p.inv_hz2, p.inv_hr2, p.rule);
-            T g = p.f[(size_t)i * nr + j] + k.a * nb(i - 1, j) + k.c * nb(i + 1, j);
-            T e = k.e;
-            if (j == n - 1) {
-                g += e * (p.zero_old ? (T)0 : p.u[(size_t)i * nr + nr - 1]);
-                e = (T)0;
+        for (int k = 0; k < RPT; ++k) {
+            const int e = k * NT + t, j = ps * CH + e;
+            T a = (T)0, b = (T)1, cc = (T)0, r = (T)0;
+            if (j < n) {
+                Coef<T> kf = coef<T>(p.eps, nr, i, j, p.inv_hz2, p.inv_hr2, p.rule);
+                T g = p.f[(size_t)i * nr + j] + kf.a * nb(i - 1, j) + kf.c * nb(i + 1, j);
+                T ee = kf.e;
+                if (j == n - 1) {
+                    g += ee * (p.zero_old ? (T)0 : p.u[(size_t)i * nr + nr - 1]);
+                    ee = (T)0;
+                }
+                a = j == 0 ? (T)0 : -kf.d;
+                b = kf.b;
+                cc = -ee;
+                r = g;
             }
-            a = j == 0 ? (T)0 : -k.d;
-            b = k.b;
-            cc = -e;
-            r = g;
+            const int x = part_slot<Q>(e);
+            SA[x] = a;
+            SB[x] = b;
+            SC[x] = cc;
+            SR[x] = r;
         }
-        // forward elimination inside the segment; ap couples to y_{t-1}
-        if (q == 0) {
-            ap[0] = a;
-            bp[0] = b;
-            rp[0] = r;
-        } else {
-            const T mq = a / bp[q - 1];
-            ap[q] = -mq * ap[q - 1];
-            bp[q] = b - mq * c[q - 1];
-            rp[q] = r - mq * rp[q - 1];
+        __syncthreads();
+        if (mine == ps) {
+            // forward elimination inside the segment; ap couples to y_{t-1}
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int x = tl * (Q + 1) + q;
+                const T a = SA[x], b = SB[x], r = SR[x];
+                if (q == 0) {
+                    ap[0] = a;
+                    bp[0] = b;
+                    rp[0] = r;
+                } else {
+                    const T mq = a / bp[q - 1];
+                    ap[q] = -mq * ap[q - 1];
+                    bp[q] = b - mq * c[q - 1];
+                    rp[q] = r - mq * rp[q - 1];
+                }
+                c[q] = SC[x];
+            }
         }
-        c[q] = cc;
+        __syncthreads();
     }
+    T *RA = sm, *RB = sm + NT, *RC = sm + 2 * NT, *RR = sm + 3 * NT;
+    T *X0 = sm + 4 * NT, *X1 = sm + 5 * NT, *X2 = sm + 6 * NT;
     // first unknown of the segment = al y_{t-1} + be y_t + ga
     T al = (T)0, be = (T)1, ga = (T)0;
 #pragma unroll
@@ -404,12 +452,24 @@ __global__ __launch_bounds__(kLongThreads) void k_line_part(LineArgs<T> p)
     pcr<T, 1>(RA, RB, RC, RR, NT, NT);
     const T yt = RR[t] / RB[t];
     const T yp = t > 0 ? RR[t - 1] / RB[t - 1] : (T)0;
-    T x = yt;
-    if (j0 + Q - 1 < n) p.u[(size_t)i * nr + j0 + Q - 1] = x;
+    // back substitution into rp (rp[q] becomes the unknown t Q + q)
+    rp[Q - 1] = yt;
 #pragma unroll
-    for (int q = Q - 2; q >= 0; --q) {
-        x = (rp[q] - ap[q] * yp - c[q] * x) / bp[q];
-        if (j0 + q < n) p.u[(size_t)i * nr + j0 + q] = x;
+    for (int q = Q - 2; q >= 0; --q) rp[q] = (rp[q] - ap[q] * yp - c[q] * rp[q + 1]) / bp[q];
+    __syncthreads();
+    // the solution leaves through LDS, pass by pass, in coalesced stores
+    for (int ps = 0; ps < P; ++ps) {
+        if (mine == ps) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) SA[tl * (Q + 1) + q] = rp[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int e = k * NT + t, j = ps * CH + e;
+            if (j < n) p.u[(size_t)i * nr + j] = SA[part_slot<Q>(e)];
+        }
+        __syncthreads();
     }
 }
 
@@ -434,7 +494,7 @@ static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u,
     if (rows <= 0) return hipSuccess;
     const int n = m.nr - 1;
     size_t lds = 8 * (size_t)n * sizeof(T);
-    if (lds <= m.lds_budget && n <= 1024 * 4) {
+    if (!m.force_part && lds <= m.lds_budget && n <= 1024 * 4) {
         int threads = ((n + 63) / 64) * 64;
         if (threads > 1024) threads = 1024;
         (void)launch<k_line_A<T>, k_line_body<T>, 1024>(dim3(rows), dim3(threads), lds, st, k_line_A<T>{p});
@@ -442,13 +502,12 @@ static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u,
     }
     // long lines: segments of Q unknowns per thread
     const int q = (n + kLongThreads - 1) / kLongThreads;
-    lds = 7 * (size_t)kLongThreads * sizeof(T);
     if (q <= 2)
-        RZ_LAUNCH((k_line_part<T, 2>), dim3(rows), dim3(kLongThreads), lds, st, p);
+        RZ_LAUNCH((k_line_part<T, 2>), dim3(rows), dim3(kLongThreads), (part_lds<T, 2>()), st, p);
     else if (q <= 4)
-        RZ_LAUNCH((k_line_part<T, 4>), dim3(rows), dim3(kLongThreads), lds, st, p);
+        RZ_LAUNCH((k_line_part<T, 4>), dim3(rows), dim3(kLongThreads), (part_lds<T, 4>()), st, p);
     else if (q <= 8)
-        RZ_LAUNCH((k_line_part<T, 8>), dim3(rows), dim3(kLongThreads), lds, st, p);
+        RZ_LAUNCH((k_line_part<T, 8>), dim3(rows), dim3(kLongThreads), (part_lds<T, 8>()), st, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1581,6 +1640,7 @@ void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path)
     // the level kernel holds three lines of four arrays (12 n values) in LDS
     // and reduces 2 n values with at most four per thread
     m.long_lines = path == 3 || 12 * (size_t)n * es > lds_budget || 2 * n > 4 * 1024;
+    m.force_part = path == 3;
     // single-block path
     int S = 0;
     while ((1 << S) < n) ++S;

@@ -138,11 +138,12 @@ def test_solve_cycles_and_convergence(mesh, face, path, monkeypatch):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("mesh", [(4097, 9), (8193, 5), (2049, 17)])
+@pytest.mark.parametrize("mesh", [(4097, 9), (8193, 5), (2049, 17), (5001, 5), (3001, 9)])
 def test_solve_long_lines(mesh, precision):
     """Meshes whose r-lines exceed the level kernel's LDS (4096 and 8192
     unknowns, or 2048 in FP64): the partition-method half-sweeps, selected by
-    the library itself, against the oracle's Thomas solves."""
+    the library itself, against the oracle's Thomas solves.  5000 and 3000
+    unknowns leave a ragged last segment and a partly filled staging pass."""
     nr, nz = mesh
     w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
                     n_per_species=1, steps=1, V_dc=35.0)
