@@ -327,7 +327,6 @@ struct MgLevels {
     size_t solve_lds;      // LDS bytes of the single-block kernel
     size_t lds_budget;     // LDS bytes of one workgroup
     int long_lines;        // r-lines solved by the partition method, two half-sweeps per level
-    int force_part;        // 1: every line by the partition method (the long-line path forced)
 };
 hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st);
 // The merged step's grid preparation in one launch: finalize every node,

@@ -239,6 +239,7 @@ template <typename T> struct LineArgs {
     T *u;
     const T *f;
     const T *uc;  // coarse correction injected into the even neighbours, or null
+    double *add_to;  // if set, each solved value is also added here (phi += correction)
 };
 
 // One zebra half-sweep on a level: block b solves line i (odd rows 2b+1 or
@@ -308,7 +309,11 @@ __device__ __forceinline__ void k_line_body(const Blk &kb_, const k_line_A<T> &A
         t = C; C = C2; C2 = t;
         t = Rr; Rr = R2; R2 = t;
     }
-    for (int j = threadIdx.x; j < n; j += blockDim.x) p.u[(size_t)i * nr + j] = Rr[j] / Bd[j];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const T x = Rr[j] / Bd[j];
+        p.u[(size_t)i * nr + j] = x;
+        if (p.add_to) p.add_to[(size_t)i * nr + j] += (double)x;
+    }
 }
 
 
@@ -467,7 +472,11 @@ __global__ __launch_bounds__(kLongThreads) void k_line_part(LineArgs<T> p)
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
             const int e = k * NT + t, j = ps * CH + e;
-            if (j < n) p.u[(size_t)i * nr + j] = SA[part_slot<Q>(e)];
+            if (j < n) {
+                const T x = SA[part_slot<Q>(e)];
+                p.u[(size_t)i * nr + j] = x;
+                if (p.add_to) p.add_to[(size_t)i * nr + j] += (double)x;
+            }
         }
         __syncthreads();
     }
@@ -475,7 +484,7 @@ __global__ __launch_bounds__(kLongThreads) void k_line_part(LineArgs<T> p)
 
 template <typename T>
 static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u, const T *f,
-                       const T *eps, const T *uc, hipStream_t st)
+                       const T *eps, const T *uc, hipStream_t st, double *add_to = nullptr)
 {
     LineArgs<T> p;
     p.nr = m.nr;
@@ -490,11 +499,12 @@ static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u,
     p.u = u;
     p.f = f;
     p.uc = uc;
+    p.add_to = add_to;
     const int rows = parity ? (p.nzl - 1) / 2 : (p.nzl - 3) / 2;
     if (rows <= 0) return hipSuccess;
     const int n = m.nr - 1;
     size_t lds = 8 * (size_t)n * sizeof(T);
-    if (!m.force_part && lds <= m.lds_budget && n <= 1024 * 4) {
+    if (m.long_lines != 2 && lds <= m.lds_budget && n <= 1024 * 4) {
         int threads = ((n + 63) / 64) * 64;
         if (threads > 1024) threads = 1024;
         (void)launch<k_line_A<T>, k_line_body<T>, 1024>(dim3(rows), dim3(threads), lds, st, k_line_A<T>{p});
@@ -633,39 +643,62 @@ __device__ __forceinline__ void k_down_body(const Blk &kb_, const k_down_A<T> &A
 
 
 // The same down leg row by row, for large meshes (coalesced along r; the
-// column form above reads a z-column per block): the finest residual into
-// m.res (and f32 of the finest level in the mixed form), then one launch per
-// coarser level, f^{l-1} = FW_z(f^l), with the arithmetic of down_body.
-__global__ void k_resid_rows(const double *u, const double *f, MgLevels m, int mixed)
+// column form above reads a z-column per block).  The first launch takes the
+// cells (I, j) of level L-1: it forms the finest residual on rows 2I-1, 2I,
+// 2I+1 and restricts it, f^{L-1}_I = FW_z(r), so the finest residual never
+// goes to memory; the mixed form also stores it in FP32 on rows 2I-1 and 2I
+// (and the last interior row) as the correction's right-hand side.  An odd
+// row between two coarse rows is formed by both of its threads, identically.
+// Then one launch per coarser level, f^{l-1} = FW_z(f^l), with the
+// arithmetic of down_body.
+__device__ __forceinline__ double resid_node(const double *u, const double *f, const double *ep,
+                                             int64_t g, int nr, int j, double iz2, double ir2,
+                                             int rule)
 {
-    const int L = m.L, nr = m.nr, nz = m.nzl[L];
+    auto E = [&](int di, int dj) { return ep[g + (int64_t)di * nr + dj]; };
+    auto U = [&](int di, int dj) { return u[g + (int64_t)di * nr + dj]; };
+    double a = face<double>(E(-1, 0), E(0, 0), rule) * iz2;
+    double c = face<double>(E(0, 0), E(1, 0), rule) * iz2;
+    double d, e;
+    if (j == 0) {
+        d = 0.0;
+        e = 4.0 * face<double>(E(0, 0), E(0, 1), rule) * ir2;
+    } else {
+        double jj = (double)j;
+        d = face<double>(E(0, -1), E(0, 0), rule) * ((jj - 0.5) / jj) * ir2;
+        e = face<double>(E(0, 0), E(0, 1), rule) * ((jj + 0.5) / jj) * ir2;
+    }
+    double b = a + c + d + e;
+    double Au = b * U(0, 0) - a * U(-1, 0) - c * U(1, 0) - e * U(0, 1);
+    if (j > 0) Au -= d * U(0, -1);
+    return f[g] - Au;
+}
+
+template <typename T>
+__global__ void k_resid_restrict_rows(const double *u, const double *f, MgLevels m, T *dst,
+                                      int mixed)
+{
+    const int L = m.L, nr = m.nr, nzc = m.nzl[L - 1];
     const double *ep = m.eps64[L];
     const double hz = m.hzl[L];
     const double iz2 = 1.0 / (hz * hz), ir2 = 1.0 / (m.hr * m.hr);
-    const int64_t nn = (int64_t)nr * nz;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nn;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(g / nr), j = (int)(g - (int64_t)i * nr);
-        if (i == 0 || i == nz - 1 || j == nr - 1) continue;
-        auto E = [&](int di, int dj) { return ep[g + (int64_t)di * nr + dj]; };
-        auto U = [&](int di, int dj) { return u[g + (int64_t)di * nr + dj]; };
-        double a = face<double>(E(-1, 0), E(0, 0), m.chi_face) * iz2;
-        double c = face<double>(E(0, 0), E(1, 0), m.chi_face) * iz2;
-        double d, e;
-        if (j == 0) {
-            d = 0.0;
-            e = 4.0 * face<double>(E(0, 0), E(0, 1), m.chi_face) * ir2;
-        } else {
-            double jj = (double)j;
-            d = face<double>(E(0, -1), E(0, 0), m.chi_face) * ((jj - 0.5) / jj) * ir2;
-            e = face<double>(E(0, 0), E(0, 1), m.chi_face) * ((jj + 0.5) / jj) * ir2;
+    float *f32 = mixed ? (float *)m.f32[L] : nullptr;
+    const int64_t ncell = (int64_t)(nzc - 2) * (nr - 1);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int I = 1 + (int)(t / (nr - 1)), j = (int)(t % (nr - 1));
+        const int64_t g = (int64_t)(2 * I - 1) * nr + j;
+        const double r1 = resid_node(u, f, ep, g, nr, j, iz2, ir2, m.chi_face);
+        const double r2 = resid_node(u, f, ep, g + nr, nr, j, iz2, ir2, m.chi_face);
+        const double r3 = resid_node(u, f, ep, g + 2 * nr, nr, j, iz2, ir2, m.chi_face);
+        double v = 0.25 * r1 + 0.5 * r2 + 0.25 * r3;
+        if (mixed) {
+            v = (double)(float)v;  // coarse right-hand sides in FP32
+            f32[g] = (float)r1;
+            f32[g + nr] = (float)r2;
+            if (I == nzc - 2) f32[g + 2 * nr] = (float)r3;
         }
-        double b = a + c + d + e;
-        double Au = b * U(0, 0) - a * U(-1, 0) - c * U(1, 0) - e * U(0, 1);
-        if (j > 0) Au -= d * U(0, -1);
-        const double r = f[g] - Au;
-        m.res[g] = r;
-        if (mixed) m.f32[L][g] = (float)r;
+        dst[(int64_t)I * nr + j] = (T)v;
     }
 }
 
@@ -696,22 +729,22 @@ static hipError_t down_rows(const MgLevels &m, int mixed, const double *phi, con
 {
     const int L = m.L, nr = m.nr;
     const int threads = 256;
-    RZ_LAUNCH(k_resid_rows, dim3(grid_blocks((int64_t)nr * m.nzl[L], threads)),
-                       dim3(threads), 0, st, phi, f, m, mixed);
     for (int l = L - 1; l >= 1; --l) {
         const int nzc = m.nzl[l];
         const int blocks = grid_blocks((int64_t)(nzc - 2) * (nr - 1), threads);
-        if (mixed) {
-            if (l == L - 1)
-                RZ_LAUNCH((k_restrict_rows<double, float>), dim3(blocks), dim3(threads), 0,
-                                   st, (const double *)m.res, m.f32[l], nr, nzc, mixed);
+        if (l == L - 1) {
+            if (mixed)
+                RZ_LAUNCH((k_resid_restrict_rows<float>), dim3(blocks), dim3(threads), 0, st, phi,
+                          f, m, m.f32[l], mixed);
             else
-                RZ_LAUNCH((k_restrict_rows<float, float>), dim3(blocks), dim3(threads), 0,
-                                   st, (const float *)m.f32[l + 1], m.f32[l], nr, nzc, mixed);
+                RZ_LAUNCH((k_resid_restrict_rows<double>), dim3(blocks), dim3(threads), 0, st,
+                          phi, f, m, m.f64[l], mixed);
+        } else if (mixed) {
+            RZ_LAUNCH((k_restrict_rows<float, float>), dim3(blocks), dim3(threads), 0, st,
+                      (const float *)m.f32[l + 1], m.f32[l], nr, nzc, mixed);
         } else {
-            const double *src = l == L - 1 ? (const double *)m.res : (const double *)m.f64[l + 1];
             RZ_LAUNCH((k_restrict_rows<double, double>), dim3(blocks), dim3(threads), 0, st,
-                               src, m.f64[l], nr, nzc, mixed);
+                      (const double *)m.f64[l + 1], m.f64[l], nr, nzc, mixed);
         }
     }
     return hipGetLastError();
@@ -1639,8 +1672,8 @@ void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path)
     m.lds_budget = lds_budget;
     // the level kernel holds three lines of four arrays (12 n values) in LDS
     // and reduces 2 n values with at most four per thread
-    m.long_lines = path == 3 || 12 * (size_t)n * es > lds_budget || 2 * n > 4 * 1024;
-    m.force_part = path == 3;
+    // 2: the long-line path forced, every line by the partition method
+    m.long_lines = path == 3 ? 2 : 12 * (size_t)n * es > lds_budget || 2 * n > 4 * 1024;
     // single-block path
     int S = 0;
     while ((1 << S) < n) ++S;
@@ -1742,15 +1775,11 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
             if (mixed) {
                 float *u = m.u32[l];
                 const float *uc = l > 1 ? m.u32[l - 1] : nullptr;
-                if ((e = line<float>(m, l, 1, 1, u, m.f32[l], m.eps32[l], uc, st))) return e;
-                if ((e = line<float>(m, l, 0, 0, u, m.f32[l], m.eps32[l], nullptr, st))) return e;
-                if (fine) {
-                    const int nn = nr * nz, threads = 256;
-                    const int blocks = (nn + threads - 1) / threads < 65536 ? (nn + threads - 1) / threads
-                                                                          : 65536;
-                    (void)launch<k_add_corr_A, k_add_corr_body, 256>(dim3(blocks), dim3(threads), 0, st, k_add_corr_A{phi, (const float *)u, nr, nz});
-                    if ((e = hipGetLastError())) return e;
-                }
+                // finest level: phi += correction as each line is solved (the
+                // odd lines are final once their half-sweep is done)
+                double *add = fine ? phi : nullptr;
+                if ((e = line<float>(m, l, 1, 1, u, m.f32[l], m.eps32[l], uc, st, add))) return e;
+                if ((e = line<float>(m, l, 0, 0, u, m.f32[l], m.eps32[l], nullptr, st, add))) return e;
             } else {
                 double *u = fine ? phi : m.u64[l];
                 const double *fl = fine ? f : m.f64[l];

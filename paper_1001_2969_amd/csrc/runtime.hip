@@ -1098,8 +1098,6 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         }
         A(m.res, nn)
         A(m.cf64, 5 * nn)
-    } else if (m.long_lines) {
-        A(m.res, nn)  // finest residual of the row-wise down leg
     }
 #undef A
     // weighting volumes (Sec. 2.4, radial neighbours clamped to the axis and
