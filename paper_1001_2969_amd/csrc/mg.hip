@@ -647,8 +647,8 @@ __device__ __forceinline__ void k_down_body(const Blk &kb_, const k_down_A<T> &A
 // cells (I, j) of level L-1: it forms the finest residual on rows 2I-1, 2I,
 // 2I+1 and restricts it, f^{L-1}_I = FW_z(r), so the finest residual never
 // goes to memory; the mixed form also stores it in FP32 on rows 2I-1 and 2I
-// (and the last interior row) as the correction's right-hand side.  An odd
-// row between two coarse rows is formed by both of its threads, identically.
+// (and the last interior row) as the correction's right-hand side.  The odd
+// row between two blocks' row ranges is formed by both, identically.
 // Then one launch per coarser level, f^{l-1} = FW_z(f^l), with the
 // arithmetic of down_body.
 __device__ __forceinline__ double resid_node(const double *u, const double *f, const double *ep,
@@ -674,6 +674,10 @@ __device__ __forceinline__ double resid_node(const double *u, const double *f, c
     return f[g] - Au;
 }
 
+// Coarse rows of k_resid_restrict_rows per block: a thread walks them in
+// order, carrying the residual of row 2I+1 over as the next row's 2I'-1.
+constexpr int kResidRows = 8;
+
 template <typename T>
 __global__ void k_resid_restrict_rows(const double *u, const double *f, MgLevels m, T *dst,
                                       int mixed)
@@ -683,12 +687,13 @@ __global__ void k_resid_restrict_rows(const double *u, const double *f, MgLevels
     const double hz = m.hzl[L];
     const double iz2 = 1.0 / (hz * hz), ir2 = 1.0 / (m.hr * m.hr);
     float *f32 = mixed ? (float *)m.f32[L] : nullptr;
-    const int64_t ncell = (int64_t)(nzc - 2) * (nr - 1);
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int I = 1 + (int)(t / (nr - 1)), j = (int)(t % (nr - 1));
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int I0 = 1 + blockIdx.y * kResidRows;
+    const int I1 = I0 + kResidRows < nzc - 1 ? I0 + kResidRows : nzc - 1;
+    if (j >= nr - 1) return;  // no barrier follows
+    double r1 = resid_node(u, f, ep, (int64_t)(2 * I0 - 1) * nr + j, nr, j, iz2, ir2, m.chi_face);
+    for (int I = I0; I < I1; ++I) {
         const int64_t g = (int64_t)(2 * I - 1) * nr + j;
-        const double r1 = resid_node(u, f, ep, g, nr, j, iz2, ir2, m.chi_face);
         const double r2 = resid_node(u, f, ep, g + nr, nr, j, iz2, ir2, m.chi_face);
         const double r3 = resid_node(u, f, ep, g + 2 * nr, nr, j, iz2, ir2, m.chi_face);
         double v = 0.25 * r1 + 0.5 * r2 + 0.25 * r3;
@@ -699,6 +704,7 @@ __global__ void k_resid_restrict_rows(const double *u, const double *f, MgLevels
             if (I == nzc - 2) f32[g + 2 * nr] = (float)r3;
         }
         dst[(int64_t)I * nr + j] = (T)v;
+        r1 = r3;
     }
 }
 
@@ -733,12 +739,13 @@ static hipError_t down_rows(const MgLevels &m, int mixed, const double *phi, con
         const int nzc = m.nzl[l];
         const int blocks = grid_blocks((int64_t)(nzc - 2) * (nr - 1), threads);
         if (l == L - 1) {
+            const dim3 g2((nr - 1 + threads - 1) / threads, (nzc - 2 + kResidRows - 1) / kResidRows);
             if (mixed)
-                RZ_LAUNCH((k_resid_restrict_rows<float>), dim3(blocks), dim3(threads), 0, st, phi,
-                          f, m, m.f32[l], mixed);
+                RZ_LAUNCH((k_resid_restrict_rows<float>), g2, dim3(threads), 0, st, phi, f, m,
+                          m.f32[l], mixed);
             else
-                RZ_LAUNCH((k_resid_restrict_rows<double>), dim3(blocks), dim3(threads), 0, st,
-                          phi, f, m, m.f64[l], mixed);
+                RZ_LAUNCH((k_resid_restrict_rows<double>), g2, dim3(threads), 0, st, phi, f, m,
+                          m.f64[l], mixed);
         } else if (mixed) {
             RZ_LAUNCH((k_restrict_rows<float, float>), dim3(blocks), dim3(threads), 0, st,
                       (const float *)m.f32[l + 1], m.f32[l], nr, nzc, mixed);
