@@ -352,7 +352,7 @@ template <typename T, int Q> constexpr size_t part_lds()
 }
 
 template <typename T, int Q>
-__global__ __launch_bounds__(kLongThreads) void k_line_part(LineArgs<T> p)
+__device__ __forceinline__ void line_part_body(const LineArgs<T> &p)
 {
     extern __shared__ unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
@@ -482,6 +482,23 @@ __global__ __launch_bounds__(kLongThreads) void k_line_part(LineArgs<T> p)
     }
 }
 
+// The block holds 16 wavefronts for the whole solve, mostly waiting at its
+// barriers, so a second block on the compute unit hides that latency.  The
+// FP32 form fits two blocks (at most 64 VGPRs, which costs the 8-unknown
+// segments a few spilled registers, and <= 80 KB of LDS); the FP64 form,
+// with 8 doubles per thread in each of four arrays, fits one.
+template <typename T, int Q>
+__global__ __launch_bounds__(kLongThreads) void k_line_part(LineArgs<T> p)
+{
+    line_part_body<T, Q>(p);
+}
+
+template <int Q>
+__global__ __launch_bounds__(kLongThreads, 8) void k_line_part_f32(LineArgs<float> p)
+{
+    line_part_body<float, Q>(p);
+}
+
 template <typename T>
 static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u, const T *f,
                        const T *eps, const T *uc, hipStream_t st, double *add_to = nullptr)
@@ -512,15 +529,27 @@ static hipError_t line(const MgLevels &m, int l, int parity, int zero_old, T *u,
     }
     // long lines: segments of Q unknowns per thread
     const int q = (n + kLongThreads - 1) / kLongThreads;
-    if (q <= 2)
-        RZ_LAUNCH((k_line_part<T, 2>), dim3(rows), dim3(kLongThreads), (part_lds<T, 2>()), st, p);
-    else if (q <= 4)
-        RZ_LAUNCH((k_line_part<T, 4>), dim3(rows), dim3(kLongThreads), (part_lds<T, 4>()), st, p);
-    else if (q <= 8)
-        RZ_LAUNCH((k_line_part<T, 8>), dim3(rows), dim3(kLongThreads), (part_lds<T, 8>()), st, p);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (q <= 2)
+            RZ_LAUNCH((k_line_part_f32<2>), dim3(rows), dim3(kLongThreads), (part_lds<T, 2>()), st, p);
+        else if (q <= 4)
+            RZ_LAUNCH((k_line_part_f32<4>), dim3(rows), dim3(kLongThreads), (part_lds<T, 4>()), st, p);
+        else if (q <= 8)
+            RZ_LAUNCH((k_line_part_f32<8>), dim3(rows), dim3(kLongThreads), (part_lds<T, 8>()), st, p);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    } else {
+        if (q <= 2)
+            RZ_LAUNCH((k_line_part<T, 2>), dim3(rows), dim3(kLongThreads), (part_lds<T, 2>()), st, p);
+        else if (q <= 4)
+            RZ_LAUNCH((k_line_part<T, 4>), dim3(rows), dim3(kLongThreads), (part_lds<T, 4>()), st, p);
+        else if (q <= 8)
+            RZ_LAUNCH((k_line_part<T, 8>), dim3(rows), dim3(kLongThreads), (part_lds<T, 8>()), st, p);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
 }
 
 struct k_add_corr_A {
