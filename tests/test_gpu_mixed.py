@@ -135,6 +135,36 @@ def test_mixed_solve(mesh, path, monkeypatch):
     assert e <= 1e-10
 
 
+# 1001x513 has 1000-unknown r-lines on nine levels whose coarse lines are
+# nearly decoupled in z (h_z up to 0.16 m against h_r = 0.6 mm): the FP32
+# correction's line solves lose more there, and after one cycle from a
+# random start the library's default path (level kernel) is 4.3e-5 from the
+# FP64 oracle, the partition solver 5.0e-5; FP64 agrees to 4e-13 on both.
+@pytest.mark.parametrize("mesh,tol", [((65, 1025), TOL_GRID), ((1001, 513), 1e-4)])
+def test_mixed_long_lines_many_rows(mesh, tol, monkeypatch):
+    """The forced long-line path on meshes with at least 256 lines of a colour
+    on the finest level, where the FP32 line solver runs two blocks per
+    compute unit; the coarse levels (fewer lines) take the other form."""
+    monkeypatch.setenv("RZPIC_MG_PATH", "long")
+    nr, nz = mesh
+    w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
+                    n_per_species=1, steps=1, V_dc=35.0)
+    chi = wl.smooth_chi(w, 1.0)
+    rho = wl.smooth_rho(w, 5, 2e-4)
+    phi0 = np.random.default_rng(9).uniform(-10.0, 10.0, (w.nz, w.nr))
+    for k in (1, 3):
+        o, g = pair(w, precision="mixed", mc=False, mg_fixed_cycles=k)
+        for ctx, G in ((o, rzo), (g, rzpic)):
+            ctx.set_grid(G.G_CHI, chi)
+            ctx.set_grid(G.G_RHO, rho)
+            ctx.set_grid(G.G_PHI, phi0)
+        o.solve(1e-9)
+        g.solve(1e-9)
+        e = rel_err(g.grid(rzpic.G_PHI), o.grid(rzo.G_PHI))
+        print(f"mixed long lines {nr}x{nz}, {k} cycles: phi error {e:.3e}")
+        assert e <= tol
+
+
 def test_mixed_small_workload_ten_steps():
     """33x33 mesh, 20k + 20k particles, 50 V DC, 10 steps from the seeded init."""
     w = wl.small_fp64().replace(precision="mixed")
