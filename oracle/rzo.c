@@ -256,6 +256,18 @@ void rzo_destroy(rzo *o)
     free(o);
 }
 
+/* memcpy/memset of particle arrays that may be empty (and then unallocated):
+ * a zero-length call with a null pointer is undefined in C, so skip it. */
+static void copy_bytes(void *dst, const void *src, size_t n)
+{
+    if (n) memcpy(dst, src, n);
+}
+
+static void zero_bytes(void *dst, size_t n)
+{
+    if (n) memset(dst, 0, n);
+}
+
 static int grow(species *sp, int64_t need)
 {
     if (need <= sp->cap) return 0;
@@ -294,12 +306,12 @@ int rzo_set_particles(rzo *o, int s, int64_t n, const double *r, const double *z
     species *sp = &o->sp[s];
     if (grow(sp, n) != 0) return -2;
     size_t b = (size_t)n * sizeof(double);
-    memcpy(sp->r, r, b); memcpy(sp->z, z, b); memcpy(sp->vr, vr, b);
-    memcpy(sp->vt, vt, b); memcpy(sp->vz, vz, b); memcpy(sp->ar, ar, b);
-    memcpy(sp->az, az, b); memcpy(sp->w, w, b);
-    memset(sp->at, 0, b);
-    memcpy(sp->id, id, (size_t)n * sizeof(uint64_t));
-    memset(sp->dead, 0, (size_t)n);
+    copy_bytes(sp->r, r, b); copy_bytes(sp->z, z, b); copy_bytes(sp->vr, vr, b);
+    copy_bytes(sp->vt, vt, b); copy_bytes(sp->vz, vz, b); copy_bytes(sp->ar, ar, b);
+    copy_bytes(sp->az, az, b); copy_bytes(sp->w, w, b);
+    zero_bytes(sp->at, b);
+    copy_bytes(sp->id, id, (size_t)n * sizeof(uint64_t));
+    zero_bytes(sp->dead, (size_t)n);
     sp->n = n;
     sp->npend = 0;
     sp->next_id = next_id;
@@ -309,14 +321,14 @@ int rzo_set_particles(rzo *o, int s, int64_t n, const double *r, const double *z
 int rzo_set_at(rzo *o, int s, int64_t n, const double *at)
 {
     if (!o || s < 0 || s > 1 || n < 0 || n > o->sp[s].n) return -1;
-    memcpy(o->sp[s].at, at, (size_t)n * sizeof(double));
+    copy_bytes(o->sp[s].at, at, (size_t)n * sizeof(double));
     return 0;
 }
 
 int rzo_get_at(const rzo *o, int s, double *at)
 {
     if (!o || s < 0 || s > 1) return -1;
-    memcpy(at, o->sp[s].at, (size_t)o->sp[s].n * sizeof(double));
+    copy_bytes(at, o->sp[s].at, (size_t)o->sp[s].n * sizeof(double));
     return 0;
 }
 
@@ -330,10 +342,10 @@ int rzo_get_particles(const rzo *o, int s, double *r, double *z, double *vr,
     const species *sp = &o->sp[s];
     size_t n = (size_t)(sp->n + sp->npend);
     size_t b = n * sizeof(double);
-    memcpy(r, sp->r, b); memcpy(z, sp->z, b); memcpy(vr, sp->vr, b);
-    memcpy(vt, sp->vt, b); memcpy(vz, sp->vz, b); memcpy(ar, sp->ar, b);
-    memcpy(az, sp->az, b); memcpy(w, sp->w, b);
-    memcpy(id, sp->id, n * sizeof(uint64_t));
+    copy_bytes(r, sp->r, b); copy_bytes(z, sp->z, b); copy_bytes(vr, sp->vr, b);
+    copy_bytes(vt, sp->vt, b); copy_bytes(vz, sp->vz, b); copy_bytes(ar, sp->ar, b);
+    copy_bytes(az, sp->az, b); copy_bytes(w, sp->w, b);
+    copy_bytes(id, sp->id, n * sizeof(uint64_t));
     return 0;
 }
 
@@ -341,7 +353,7 @@ int rzo_get_events(const rzo *o, int s, uint8_t *ev, int64_t n)
 {
     const species *sp = &o->sp[s];
     if (n > sp->nev) return -1;
-    memcpy(ev, sp->ev, (size_t)n);
+    copy_bytes(ev, sp->ev, (size_t)n);
     return 0;
 }
 
@@ -846,7 +858,7 @@ static int ensure_ev(species *sp)
         if (!sp->ev) return -1;
     }
     sp->nev = sp->n;
-    memset(sp->ev, 0, (size_t)sp->n);
+    zero_bytes(sp->ev, (size_t)sp->n);
     return 0;
 }
 
@@ -898,7 +910,7 @@ int rzo_compact(rzo *o, int s)
     }
     sp->n = dst;
     sp->npend = 0;
-    memset(sp->dead, 0, (size_t)sp->n);
+    zero_bytes(sp->dead, (size_t)sp->n);
     return 0;
 }
 
@@ -1019,10 +1031,10 @@ int rzo_sort(rzo *o, int s)
     double *f[9] = {sp->r, sp->z, sp->vr, sp->vt, sp->vz, sp->ar, sp->az, sp->w, sp->at};
     for (int k = 0; k < 9; ++k) {
         for (int64_t p = 0; p < n; ++p) tmp[dst[p]] = f[k][p];
-        memcpy(f[k], tmp, (size_t)n * sizeof(double));
+        copy_bytes(f[k], tmp, (size_t)n * sizeof(double));
     }
     for (int64_t p = 0; p < n; ++p) tid[dst[p]] = sp->id[p];
-    memcpy(sp->id, tid, (size_t)n * sizeof(uint64_t));
+    copy_bytes(sp->id, tid, (size_t)n * sizeof(uint64_t));
     free(start); free(key); free(tmp); free(tid); free(dst);
     return nt;
 }

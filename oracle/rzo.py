@@ -41,7 +41,9 @@ class Config(C.Structure):
 def lib():
     global _LIB
     if _LIB is None:
-        path = _build.LIB
+        # RZO_LIB selects another build of the same source (the sanitized
+        # one of oracle/sanitize.py)
+        path = os.environ.get("RZO_LIB") or _build.LIB
         if not os.path.exists(path):
             _build.build()
         L = C.CDLL(path)
