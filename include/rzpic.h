@@ -85,11 +85,17 @@ typedef struct rzpic_config {
     int32_t precision;        /* RZPIC_FP64 or RZPIC_MIXED                    */
     int32_t weighting;        /* RZPIC_W_ZR2 (default) or RZPIC_W_ZR          */
     int32_t chi_face;         /* RZPIC_FACE_AVG or RZPIC_FACE_MAX             */
-    int32_t fixed_point_bits; /* deposit quantum = w_ref * 2^-bits (0 -> 46):
-                               * one contribution must stay below 2^51 quanta
-                               * (weights below 2^(51-bits) w_ref) and a node's
-                               * total below 2^63; 46 bits keep the rounding of
-                               * the deposit near 1e-14 of a node's count */
+    int32_t fixed_point_bits; /* deposit quantum = w_ref * 2^-bits (0 -> 46 in
+                               * RZPIC_FP64, 26 in RZPIC_MIXED): one
+                               * contribution must stay below 2^51 quanta in
+                               * FP64 (weights below 2^(51-bits) w_ref) and
+                               * below 1.5 2^30 in MIXED, which forms each
+                               * contribution in FP32 as a 32-bit integer
+                               * (weights below 1.5 2^(30-bits) w_ref; at most
+                               * 30 bits there, else EINVAL); a node's total
+                               * must stay below 2^63.  46 bits keep the
+                               * rounding of the FP64 deposit near 1e-14 of a
+                               * node's count */
     double V_dc, V_rf, f_rf;  /* z=0 electrode: V_dc + V_rf sin(2 pi f_rf t) */
     uint64_t seed;            /* Philox key of every random draw             */
     double mg_tol;            /* relative L-inf residual target (Sec. 2.5)   */
@@ -162,8 +168,8 @@ rzpic_status rzpic_destroy(rzpic_ctx *ctx);
 /* Change the stream later work is enqueued on. */
 rzpic_status rzpic_set_stream(rzpic_ctx *ctx, void *stream);
 
-/* Attach caller-owned particle arrays of species s (0 or 1).  The arrays must
- * outlive the binding.  Allocates per-species scratch sized by `capacity`
+/* Attach caller-owned particle arrays of species s (0 or 1), of capacity
+ * 1 .. 2^29 - 64 (EINVAL beyond).  The arrays must outlive the binding.  Allocates per-species scratch sized by `capacity`
  * (chunk tables, new-particle staging).  The particle count becomes 0. */
 rzpic_status rzpic_bind_species(rzpic_ctx *ctx, int32_t s, const rzpic_species_view *v);
 /* Set the live count n (<= capacity) and the next identity of species s
@@ -244,19 +250,19 @@ rzpic_status rzpic_prologue(rzpic_ctx *ctx);
  * composition of the single operations above. */
 rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
 
-/* Launch shape of the fused particle pass: threads per block (256, 512 or
- * 1024) and particles of capacity per block (default 512 threads, 8192).
+/* Launch shape of the fused particle pass: threads per block (256, 512, 768
+ * or 1024) and particles of capacity per block (default 512 threads, 8192).
  * Results do not depend on it (integer deposit, identities from event
  * ranks, compaction by index), only the speed.  A tile-sorted context is
  * sorted again so that its tile plan fits the new block count.  EINVAL for
  * a shape beyond the pass's wavefront limit. */
 rzpic_status rzpic_set_pass_shape(rzpic_ctx *ctx, int32_t threads, int32_t parts_per_block);
-/* Autotuner of that shape: for each of threads {256, 512, 1024} x
+/* Autotuner of that shape: for each of threads {256, 512, 768, 1024} x
  * particles per block {2048, 4096, 8192, 16384} that fits, one warm-up and
  * `steps` timed rzpic_step calls (HIP events on the context's stream),
  * starting at step `step0`; keeps the first shape in that order within 2 %
  * of the fastest (near-ties do not flip between runs).  table (host, may be NULL)
- * receives 12 rows {threads, parts_per_block, ms per step or -1 if skipped};
+ * receives 16 rows {threads, parts_per_block, ms per step or -1 if skipped};
  * best = {threads, parts_per_block}; *next_step the next step index.  The
  * simulation advances by the steps run.  Synchronises. */
 rzpic_status rzpic_autotune(rzpic_ctx *ctx, int32_t steps, int64_t step0, double *table,

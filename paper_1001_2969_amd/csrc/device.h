@@ -16,13 +16,28 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
+// a ^ b ^ k in one instruction (the three-input bitwise operation of gfx950,
+// truth table 0x96), k a wavefront-uniform key word in a scalar register.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// Each round's two products as full 64-bit products (one multiply-add
+// instruction each).  The key enters opaque, so that its round values are
+// formed by scalar adds at every use instead of being kept (and spilled)
+// across the caller's loop.  The key must be uniform over the wavefront.
 __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
 {
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = U4{xor3_key((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+               xor3_key((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -32,16 +47,32 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
 // Two uniforms in (0,1) from draw block `blk` of (seed, species, id, step):
 // counter (id lo, id hi, step, species<<16 | blk), key = seed; each pair of
 // words gives a 52-bit integer u and U = (u + 1/2) 2^-52, exact in FP64.
-__device__ __forceinline__ void uniform2(uint64_t seed, int s, uint64_t id, uint32_t step,
-                                         uint32_t blk, double &a, double &b)
+// The two 52-bit integers u of that draw, before the conversion.
+__device__ __forceinline__ void draw_u52(uint64_t seed, int s, uint64_t id, uint32_t step,
+                                        uint32_t blk, uint64_t &ua, uint64_t &ub)
 {
     U4 c{(uint32_t)id, (uint32_t)(id >> 32), step, ((uint32_t)s << 16) | (blk & 0xFFFFu)};
     U4 x = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    uint64_t ua = ((uint64_t)x.x << 20) | (uint64_t)(x.y >> 12);
-    uint64_t ub = ((uint64_t)x.z << 20) | (uint64_t)(x.w >> 12);
-    a = ((double)ua + 0.5) * 0x1p-52;
-    b = ((double)ub + 0.5) * 0x1p-52;
+    ua = ((uint64_t)x.x << 20) | (uint64_t)(x.y >> 12);
+    ub = ((uint64_t)x.z << 20) | (uint64_t)(x.w >> 12);
 }
+
+__device__ __forceinline__ double u52_unit(uint64_t u) { return ((double)u + 0.5) * 0x1p-52; }
+
+__device__ __forceinline__ void uniform2(uint64_t seed, int s, uint64_t id, uint32_t step,
+                                         uint32_t blk, double &a, double &b)
+{
+    uint64_t ua, ub;
+    draw_u52(seed, s, id, step, blk, ua, ub);
+    a = u52_unit(ua);
+    b = u52_unit(ub);
+}
+
+// The null-collision candidate test U0 < P_null decided on the integer u of
+// U0 = (u + 1/2) 2^-52: u + 1/2 < P_null 2^52 (both sides exact in FP64)
+// holds exactly for u < ceil(P_null 2^52 - 1/2), the threshold the host
+// computes once (SpeciesK::cand_u52).  Same decision, no conversion.
+__device__ __forceinline__ bool is_candidate(uint64_t ua, uint64_t cand_u52) { return ua < cand_u52; }
 
 __device__ __forceinline__ void normal2(double ua, double ub, double &n1, double &n2)
 {
@@ -67,6 +98,12 @@ template <typename T> struct W4 {
 template <typename T> __device__ __forceinline__ T inv2j1(int j)
 {
     return (T)(1.0 / (double)(2 * j + 1));
+}
+// FP32 particles: the hardware reciprocal (within 1 ulp of FP32), one
+// instruction instead of an FP64 division; every FP32 kernel weights alike.
+template <> __device__ __forceinline__ float inv2j1<float>(int j)
+{
+    return __builtin_amdgcn_rcpf((float)(2 * j + 1));
 }
 
 template <typename T> __device__ __forceinline__ W4<T> weights(const Mesh &m, T r, T z)
@@ -126,6 +163,38 @@ __device__ __forceinline__ int choose_process(const Xsec &x, double n_gas, doubl
         if (thr_nu < cum) return k;
     }
     return -1;
+}
+
+// Whether an electron candidate makes a real collision (some process k with
+// thr_nu < sum_{k' <= k} n_gas sigma_k'(eps) g, i.e. thr_nu below the total,
+// the cumulative sums being non-decreasing): the decision of choose_process,
+// bit for bit.  A cheap estimate of the total decides all but a band around
+// it: eps/de by a multiplication with 1/de (a few ulp of x, so sigma within
+// ~1e-12 of its largest table value) and g by the FP32 square root (within
+// 3e-7); outside a band of 1e-6 of the estimate plus Xsec::band_abs (the
+// bound of the table error) the exact total lies on the same side.  Inside
+// the band the exact evaluation decides.
+__device__ __forceinline__ bool electron_real(const Xsec &x, double n_gas, double thr_nu,
+                                              double eps, double v2)
+{
+#pragma clang fp contract(off)
+    if (eps < x.emax) {
+        const double g = (double)__builtin_amdgcn_sqrtf((float)v2);
+        const double xx = eps * x.inv_de;
+        int j = (int)xx;
+        if (j > x.ne - 2) j = x.ne - 2;
+        const double t = xx - (double)j;
+        double sT = 0.0;
+        for (int k = 0; k < x.nproc; ++k) {
+            const double *sg = x.sigma + (size_t)k * x.ne;
+            sT += sg[j] + t * (sg[j + 1] - sg[j]);
+        }
+        const double est = n_gas * sT * g;
+        const double band = 1e-6 * est + x.band_abs;
+        if (thr_nu < est - band) return true;
+        if (thr_nu > est + band) return false;
+    }
+    return choose_process(x, n_gas, thr_nu, eps, sqrt(v2)) >= 0;
 }
 
 __device__ __forceinline__ double energy_ev(double v0, double v1, double v2, double ekin)

@@ -69,6 +69,8 @@ struct Xsec {
     const double *sigma;   // [nproc][ne]
     int nproc, ne;
     double de, emax;
+    double inv_de;         // 1 / de (the estimate of electron_real)
+    double band_abs;       // absolute part of electron_real's undecided band
     int kind[kMaxProc];
     double thr[kMaxProc];
     double ejB;
@@ -81,6 +83,7 @@ struct SpeciesK {
     double dt;              // time step of the species (K dt for subcycled ions)
     double inv_quantum;     // 2^bits / w_ref
     double p_null, nu_max;
+    uint64_t cand_u52;      // candidate iff the 52-bit u of U0 is below this
     double ekin;            // 0.5 * (pair mass) / e : eV per (m/s)^2
     double mu;              // pair mass
     Xsec xs;

@@ -31,6 +31,33 @@ __device__ __forceinline__ void deposit4_at(unsigned long long *acc, int g, int 
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// FP32 particles: each contribution is formed in FP32 and rounded to a
+// 32-bit integer number of quanta (below 1.5 2^30: with the mixed form's
+// default quantum w_ref 2^-26, weights up to 24 w_ref; a larger one is
+// flagged), then added to the same 64-bit accumulators.  The sum stays
+// exact and order-free; the contribution carries the FP32 rounding of the
+// particle state it comes from.
+template <>
+__device__ __forceinline__ void deposit4_at<float>(unsigned long long *acc, int g, int stride,
+                                                   const W4<float> &q, double w,
+                                                   double inv_quantum, int32_t *status)
+{
+    const float ws = (float)w * (float)inv_quantum;
+    if (!(fabsf(ws) < 0x1.8p30f)) atomicOr(status, kStNumeric);
+    const float a = q.sz0 * q.sr0, b = q.sz0 * q.sr1;
+    const float c = q.sz1 * q.sr0, d = q.sz1 * q.sr1;
+    const long long qa = (int)__builtin_rintf(ws * a), qb = (int)__builtin_rintf(ws * b);
+    const long long qc = (int)__builtin_rintf(ws * c), qd = (int)__builtin_rintf(ws * d);
+    __hip_atomic_fetch_add(acc + g, (unsigned long long)qa, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + 1, (unsigned long long)qb, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + stride, (unsigned long long)qc, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + stride + 1, (unsigned long long)qd, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T>
 __device__ __forceinline__ void deposit4(unsigned long long *acc, const Mesh &m, const W4<T> &q,
                                          double w, double inv_quantum, int32_t *status)
@@ -75,8 +102,17 @@ template <typename T> __device__ __forceinline__ void first_push(PState<T> &s, T
     T rn = sqrt(x * x + y * y);
     T c = (T)1, sn = (T)0;
     if (rn > (T)0) {
-        c = x / rn;
-        sn = y / rn;
+        if constexpr (std::is_same<T, float>::value) {
+            // FP32 particles: one hardware reciprocal for both cosines (the
+            // radius keeps the correctly rounded square root; only the
+            // velocities and a_r see the extra ulp)
+            const float inv = __builtin_amdgcn_rcpf(rn);
+            c = x * inv;
+            sn = y * inv;
+        } else {
+            c = x / rn;
+            sn = y / rn;
+        }
     }
     s.r = rn;
     s.z = z;
@@ -144,10 +180,19 @@ __device__ __forceinline__ void final_push(PState<T> &s, T Er, T Ez, T k1, T k2,
     s.az = az;
 }
 
+// Element i of a particle array through a 32-bit byte offset.  Capacities
+// stay below 2^29 (rzpic_bind_species), so i * sizeof(T) fits in 32 bits:
+// the access takes the array base in scalar registers plus one offset that
+// every array of the record shares, with no 64-bit address arithmetic.
+template <typename T> __device__ __forceinline__ T &el(T *base, int64_t i)
+{
+    return *(T *)((char *)base + (uint32_t)((uint32_t)i * (uint32_t)sizeof(T)));
+}
+
 template <typename T> __device__ __forceinline__ PState<T> load(const Parts<T> &p, int64_t i)
 {
-    return PState<T>{p.r[i], p.z[i], p.vr[i], p.vt[i], p.vz[i],
-                     p.ar[i], p.az[i], p.w[i], p.at ? p.at[i] : (T)0};
+    return PState<T>{el(p.r, i), el(p.z, i), el(p.vr, i), el(p.vt, i), el(p.vz, i),
+                     el(p.ar, i), el(p.az, i), el(p.w, i), p.at ? el(p.at, i) : (T)0};
 }
 
 // load() with the a_theta array's presence fixed at compile time: no load
@@ -155,22 +200,22 @@ template <typename T> __device__ __forceinline__ PState<T> load(const Parts<T> &
 // loop that keeps loads in flight from one iteration to the next.
 template <typename T, bool X> __device__ __forceinline__ PState<T> load_x(const Parts<T> &p, int64_t i)
 {
-    return PState<T>{p.r[i], p.z[i], p.vr[i], p.vt[i], p.vz[i],
-                     p.ar[i], p.az[i], p.w[i], X ? p.at[i] : (T)0};
+    return PState<T>{el(p.r, i), el(p.z, i), el(p.vr, i), el(p.vt, i), el(p.vz, i),
+                     el(p.ar, i), el(p.az, i), el(p.w, i), X ? el(p.at, i) : (T)0};
 }
 
 template <typename T>
 __device__ __forceinline__ void store(const Parts<T> &p, int64_t i, const PState<T> &s, bool w)
 {
-    p.r[i] = s.r;
-    p.z[i] = s.z;
-    p.vr[i] = s.vr;
-    p.vt[i] = s.vt;
-    p.vz[i] = s.vz;
-    p.ar[i] = s.ar;
-    p.az[i] = s.az;
-    if (p.at) p.at[i] = s.at;
-    if (w) p.w[i] = s.w;
+    el(p.r, i) = s.r;
+    el(p.z, i) = s.z;
+    el(p.vr, i) = s.vr;
+    el(p.vt, i) = s.vt;
+    el(p.vz, i) = s.vz;
+    el(p.ar, i) = s.ar;
+    el(p.az, i) = s.az;
+    if (p.at) el(p.at, i) = s.at;
+    if (w) el(p.w, i) = s.w;
 }
 
 // One pass over the particles of a species.  Each wavefront processes chunks
@@ -272,21 +317,20 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
             int code = 0;
             bool tested = false;
             if (live && mc_on) {
-                double ua, ub;
-                uniform2(a.phys.seed, a.sp.s, pid, a.step, 0, ua, ub);
-                if (ua < a.sp.p_null) {
+                uint64_t ua, ub;
+                draw_u52(a.phys.seed, a.sp.s, pid, a.step, 0, ua, ub);
+                if (is_candidate(ua, a.sp.cand_u52)) {
                     tested = true;
                     cand = true;
                     if (a.sp.mc_model == 1) {
-                        double v0 = s.vr, v1 = s.vt, v2 = s.vz;
-                        double thr_nu;
+                        double thr_nu, eps;
+                        const double vv = sumsq3((double)s.vr, (double)s.vt, (double)s.vz);
                         {
 #pragma clang fp contract(off)
-                            thr_nu = ub * a.sp.nu_max;
+                            thr_nu = u52_unit(ub) * a.sp.nu_max;
+                            eps = vv * a.sp.ekin;  // energy_ev, term for term
                         }
-                        double eps = energy_ev(v0, v1, v2, a.sp.ekin);
-                        double vm = sqrt(sumsq3(v0, v1, v2));
-                        if (choose_process(a.sp.xs, a.phys.n_gas, thr_nu, eps, vm) < 0) {
+                        if (!electron_real(a.sp.xs, a.phys.n_gas, thr_nu, eps, vv)) {
                             cand = false;
                             code = 1;
                         }
@@ -336,7 +380,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
             }
         }
         if (valid) {
-            if ((MODE & M_MARK) && died) a.p.w[pi] = (T)-1;
+            if ((MODE & M_MARK) && died) el(a.p.w, pi) = (T)-1;
             else if (live && moved) store(a.p, pi, s, false);
         }
         if (MODE & M_LISTS) {
@@ -364,7 +408,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
             const int64_t pi = cc[u] * kChunk + lane;
             const int64_t pl = cc[u] >= 0 && pi < n ? pi : 0;
             s[u] = load(a.p, pl);
-            pid[u] = kMc ? a.p.id[pl] : 0;
+            pid[u] = kMc ? el(a.p.id, pl) : 0;
             Er[u] = Ez[u] = (T)0;
         }
         if (MODE & M_FINAL) {
@@ -400,7 +444,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
                 const int64_t pi = cc * kChunk + lane;
                 const int64_t pl = cc < nch && pi < n ? pi : 0;
                 st = load_x<T, X>(a.p, pl);
-                id = kMc ? a.p.id[pl] : 0;
+                id = kMc ? el(a.p.id, pl) : 0;
             };
             PState<T> sn;
             uint64_t pn;

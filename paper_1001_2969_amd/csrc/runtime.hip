@@ -146,6 +146,10 @@ SpeciesK species_of(const rzpic_ctx *c, int s)
     k.inv_quantum = 1.0 / c->quantum[s];
     k.p_null = ss.p_null;
     k.nu_max = ss.nu_max;
+    // U0 = (u + 1/2) 2^-52 < P_null exactly when u < ceil(P_null 2^52 - 1/2):
+    // the scaling by 2^52 and the subtraction are exact in FP64
+    const double P = std::ldexp(ss.p_null, 52);
+    k.cand_u52 = P > 0.5 ? (uint64_t)std::ceil(P - 0.5) : 0;
     k.mu = ss.bound ? pair_mass(c, s) : 1.0;
     k.ekin = 0.5 * k.mu / kE;
     k.xs = ss.xs;
@@ -942,6 +946,10 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         return fail(RZPIC_EINVAL, "need mg_fixed_cycles > 0, or mg_max_cycles >= 1 and mg_tol > 0");
     if (k.fixed_point_bits < 0 || k.fixed_point_bits > 52)
         return fail(RZPIC_EINVAL, "fixed_point_bits = %d out of [0, 52]", k.fixed_point_bits);
+    if (k.precision == RZPIC_MIXED && k.fixed_point_bits > 30)
+        return fail(RZPIC_EINVAL,
+                    "fixed_point_bits = %d: the mixed form forms 32-bit contributions (at most 30)",
+                    k.fixed_point_bits);
     if (k.resize_every < 0 || (k.resize_every > 0 && !(k.resize_wcoef > 0)))
         return fail(RZPIC_EINVAL, "resize_every > 0 needs resize_wcoef > 0");
     if (k.sort_every < 0 || k.tile_z < 0 || k.tile_r < 0)
@@ -956,7 +964,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
 
     rzpic_ctx *c = new rzpic_ctx();
     c->c = k;
-    if (c->c.fixed_point_bits == 0) c->c.fixed_point_bits = 46;
+    if (c->c.fixed_point_bits == 0) c->c.fixed_point_bits = k.precision == RZPIC_MIXED ? 26 : 46;
     c->st = (hipStream_t)stream;
     c->mixed = k.precision == RZPIC_MIXED;
     c->hr = k.R / (double)(k.nr - 1);
@@ -1151,7 +1159,8 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
     if (s < 0 || s > 1) return fail(RZPIC_EINVAL, "species %d out of range", s);
     if (!v->r || !v->z || !v->vr || !v->vt || !v->vz || !v->ar || !v->az || !v->w || !v->id)
         return fail(RZPIC_EINVAL, "species %d: null particle array", s);
-    if (v->capacity < 1 || v->capacity > ((int64_t)1 << 31) - kChunk)
+    // particle kernels address the arrays by 32-bit byte offsets (8-byte ids)
+    if (v->capacity < 1 || v->capacity > ((int64_t)1 << 29) - kChunk)
         return fail(RZPIC_EINVAL, "species %d: capacity %lld out of range", s, (long long)v->capacity);
     if (!(v->m > 0) || !(v->w_ref > 0))
         return fail(RZPIC_EINVAL, "species %d: need m > 0 and w_ref > 0", s);
@@ -1252,7 +1261,24 @@ rzpic_status rzpic_set_xsec(rzpic_ctx *c, int32_t s, int32_t nproc, const int32_
     x.ne = ne;
     x.de = de;
     x.emax = (double)(ne - 1) * de;
+    x.inv_de = 1.0 / de;
     x.ejB = ej_B;
+    // electron_real's estimate takes eps/de as eps * (1/de): within 3.3e-16 x
+    // of the quotient, so each interpolated sigma_k moves by at most
+    // 6.6e-12 of its largest table value (its slope per unit x is bounded by
+    // that value, and x < ne); times n_gas and the pair speed at the table's
+    // end, with a factor 3 to spare.
+    {
+        double ssum = 0.0;
+        for (int k = 0; k < nproc; ++k) {
+            double smax = 0.0;
+            for (int j = 0; j < ne; ++j)
+                smax = std::fmax(smax, std::fabs(sigma[(size_t)k * ne + j]));
+            ssum += smax;
+        }
+        const double gmax = std::sqrt(2.0 * x.emax * kE / pair_mass(c, s));
+        x.band_abs = 2e-11 * std::fabs(c->c.n_gas) * gmax * ssum;
+    }
     for (int k = 0; k < nproc; ++k) {
         x.kind[k] = kind[k];
         x.thr[k] = thr_eV[k];
@@ -1518,18 +1544,18 @@ rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *
     if (steps < 1) return fail(RZPIC_EINVAL, "steps must be >= 1");
     TRY(need_both(c));
     if (c->timing) return fail(RZPIC_EINVAL, "autotune needs step timing off");
-    static const int kThreads[3] = {256, 512, 1024};
+    static const int kThreads[4] = {256, 512, 768, 1024};
     static const int64_t kPpb[4] = {2048, 4096, 8192, 16384};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     int64_t n = step0;
     double best_ms = -1.0;
-    double times[12];
+    double times[16];
     int bt = c->pass_threads;
     int64_t bp = c->parts_per_block;
     rzpic_status st = RZPIC_OK;
-    for (int ti = 0; ti < 3 && st == RZPIC_OK; ++ti)
+    for (int ti = 0; ti < 4 && st == RZPIC_OK; ++ti)
         for (int pi = 0; pi < 4 && st == RZPIC_OK; ++pi) {
             double ms = -1.0;
             if (shape_fits(c, kThreads[ti], kPpb[pi])) {
@@ -1557,7 +1583,7 @@ rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *
         }
     // the first shape (table order) within 2 % of the fastest: near-ties do
     // not flip the choice from run to run
-    for (int k = 0; k < 12 && best_ms > 0.0; ++k)
+    for (int k = 0; k < 16 && best_ms > 0.0; ++k)
         if (times[k] > 0.0 && times[k] <= 1.02 * best_ms) {
             bt = kThreads[k / 4];
             bp = kPpb[k % 4];
@@ -1576,8 +1602,10 @@ rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *
 rzpic_status rzpic_set_pass_shape(rzpic_ctx *c, int32_t threads, int32_t parts_per_block)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
-    if ((threads != 256 && threads != 512 && threads != 1024) || parts_per_block < 64)
-        return fail(RZPIC_EINVAL, "threads must be 256, 512 or 1024 and parts_per_block >= 64");
+    if ((threads != 256 && threads != 512 && threads != 768 && threads != 1024) ||
+        parts_per_block < 64)
+        return fail(RZPIC_EINVAL,
+                    "threads must be 256, 512, 768 or 1024 and parts_per_block >= 64");
     if (c->sp[0].bound && c->sp[1].bound && !shape_fits(c, threads, parts_per_block))
         return fail(RZPIC_EINVAL, "the shape exceeds the pass's wavefront limit");
     return set_shape(c, threads, parts_per_block);

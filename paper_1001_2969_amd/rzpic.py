@@ -320,12 +320,12 @@ class Context:
         """Times the fused pass's launch shapes over real steps from step0 and
         keeps the fastest; returns (best (threads, parts_per_block), table of
         (threads, parts_per_block, ms per step), next step index)."""
-        table = (C.c_double * 36)()
+        table = (C.c_double * 48)()
         best = (C.c_int32 * 2)()
         nxt = C.c_int64()
         _check(lib().rzpic_autotune(self.h, steps, step0, C.cast(table, C.c_void_p),
                                     C.cast(best, C.c_void_p), C.byref(nxt)))
-        rows = [(int(table[3 * k]), int(table[3 * k + 1]), table[3 * k + 2]) for k in range(12)]
+        rows = [(int(table[3 * k]), int(table[3 * k + 1]), table[3 * k + 2]) for k in range(16)]
         return (best[0], best[1]), rows, nxt.value
 
     def circuit(self):
