@@ -394,6 +394,40 @@ rzpic_status rzpic_adjoint_backward(rzpic_adjoint *adj, double grad_V[2], double
                                     double *grad_w1, double *grad_density);
 rzpic_status rzpic_adjoint_destroy(rzpic_adjoint *adj);
 
+/* --- deposit without allocation ------------------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * deposit N_ij of Sec. 2.4 of one species' particles into the caller's grid,
+ * with the fixed-point arithmetic of rzpic_deposit: the counts equal, bit for
+ * bit, the N0/N1 grid rzpic_grid_copy returns after rzpic_deposit of the same
+ * particles and quantum.  Nothing is allocated: the accumulators are a fixed
+ * device array of 2^20 nodes inside the library (8 MiB on each device it
+ * runs on, kept until the process ends); nr * nz above 2^20 is EINVAL.  Every
+ * call on a device shares that array, so calls that overlap on one device
+ * (other streams, other host threads) race; calls on one stream are ordered.
+ * Asynchronous on `stream` (a hipStream_t, NULL = default stream); the
+ * current device is the one used. */
+typedef struct rzpic_deposit_args {
+    int32_t nr, nz;           /* mesh nodes, nr >= 3, nz >= 2                 */
+    double R, L;              /* radius and electrode gap (m)                 */
+    int32_t precision;        /* RZPIC_FP64: r, z, w are double; RZPIC_MIXED:
+                               * float, contributions formed in FP32 as the
+                               * mixed form does                              */
+    int32_t weighting;        /* RZPIC_W_ZR2 or RZPIC_W_ZR                    */
+    int32_t fixed_point_bits; /* quantum = w_ref 2^-bits (0 -> 46 in FP64, 26 in
+                               * MIXED; at most 52 / 30)                      */
+    int32_t reserved;
+    double w_ref;             /* reference weight of the quantum (> 0)        */
+    const void *r, *z, *w;    /* device arrays of the n particles, inside the
+                               * mesh (positions in m, weights)               */
+    int64_t n;                /* particle count, 0 .. 2^29 - 64               */
+    double *out;              /* device, nz*nr doubles [nz][nr]: N_ij in
+                               * physical particles                           */
+    int32_t *status;          /* device int32: 2 (the fixed-point overflow bit)
+                               * is ORed in on overflow; the caller clears it */
+} rzpic_deposit_args;
+rzpic_status rzpic_deposit_noalloc(const rzpic_deposit_args *a, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

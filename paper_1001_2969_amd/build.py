@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librzpic.so")
 OBJ = os.path.join(ROOT, "_build")
 SOURCES = ["particles.hip", "fixup.hip", "grid.hip", "mg.hip", "sort.hip", "runtime.hip",
-           "batch.hip", "adjoint.hip", "circuit.hip"]
+           "batch.hip", "adjoint.hip", "circuit.hip", "noalloc.hip"]
 ARCH = os.environ.get("RZPIC_ARCH", "gfx950")
 
 FLAGS = [

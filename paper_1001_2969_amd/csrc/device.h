@@ -471,4 +471,57 @@ __device__ __forceinline__ long long round_fixed(double x)
     return (long long)(__double_as_longlong(y) - __double_as_longlong(magic));
 }
 
+// ---------------------------------------------------------------------------
+// Deposit of one particle (Sec. 2.4): N_ij += w S_z S_r, accumulated in fixed
+// point (quantum = w_ref 2^-bits) so that the sum does not depend on order.
+// Contributions must stay below 2^51 quanta (a weight below 2^(51-bits)
+// w_ref); a larger one is flagged and the step reports RZPIC_ENUMERIC.
+// The four nodes of the cell sit at acc[g], acc[g + 1], acc[g + stride] and
+// acc[g + stride + 1] (stride nr for a whole grid, the row length of a window).
+template <typename T>
+__device__ __forceinline__ void deposit4_at(unsigned long long *acc, int g, int stride,
+                                            const W4<T> &q, double w, double inv_quantum,
+                                            int32_t *status)
+{
+    const double ws = w * inv_quantum;
+    if (!(fabs(ws) < 0x1p51)) atomicOr(status, kStNumeric);
+    const double a = (double)q.sz0 * (double)q.sr0, b = (double)q.sz0 * (double)q.sr1;
+    const double c = (double)q.sz1 * (double)q.sr0, d = (double)q.sz1 * (double)q.sr1;
+    __hip_atomic_fetch_add(acc + g, (unsigned long long)round_fixed(ws * a), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + 1, (unsigned long long)round_fixed(ws * b),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + stride, (unsigned long long)round_fixed(ws * c),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + stride + 1, (unsigned long long)round_fixed(ws * d),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// FP32 particles: each contribution is formed in FP32 and rounded to a
+// 32-bit integer number of quanta (below 1.5 2^30: with the mixed form's
+// default quantum w_ref 2^-26, weights up to 24 w_ref; a larger one is
+// flagged), then added to the same 64-bit accumulators.  The sum stays
+// exact and order-free; the contribution carries the FP32 rounding of the
+// particle state it comes from.
+template <>
+__device__ __forceinline__ void deposit4_at<float>(unsigned long long *acc, int g, int stride,
+                                                   const W4<float> &q, double w,
+                                                   double inv_quantum, int32_t *status)
+{
+    const float ws = (float)w * (float)inv_quantum;
+    if (!(fabsf(ws) < 0x1.8p30f)) atomicOr(status, kStNumeric);
+    const float a = q.sz0 * q.sr0, b = q.sz0 * q.sr1;
+    const float c = q.sz1 * q.sr0, d = q.sz1 * q.sr1;
+    const long long qa = (int)__builtin_rintf(ws * a), qb = (int)__builtin_rintf(ws * b);
+    const long long qc = (int)__builtin_rintf(ws * c), qd = (int)__builtin_rintf(ws * d);
+    __hip_atomic_fetch_add(acc + g, (unsigned long long)qa, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + 1, (unsigned long long)qb, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + stride, (unsigned long long)qc, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + g + stride + 1, (unsigned long long)qd, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace rz

@@ -31,6 +31,7 @@ EXPORTS = (
     "rzpic_batch_set_graph", "rzpic_set_voltage", "rzpic_adjoint_create",
     "rzpic_adjoint_forward", "rzpic_adjoint_backward", "rzpic_adjoint_destroy",
     "rzpic_set_circuit", "rzpic_get_circuit", "rzpic_set_pass_shape", "rzpic_autotune",
+    "rzpic_deposit_noalloc",
 )
 
 
@@ -87,6 +88,16 @@ class AdjointConfig(C.Structure):
 _lib = None
 
 
+class DepositArgs(C.Structure):
+    _fields_ = [
+        ("nr", C.c_int32), ("nz", C.c_int32), ("R", C.c_double), ("L", C.c_double),
+        ("precision", C.c_int32), ("weighting", C.c_int32),
+        ("fixed_point_bits", C.c_int32), ("reserved", C.c_int32),
+        ("w_ref", C.c_double), ("r", C.c_void_p), ("z", C.c_void_p), ("w", C.c_void_p),
+        ("n", C.c_int64), ("out", C.c_void_p), ("status", C.c_void_p),
+    ]
+
+
 def lib():
     """Load the HIP library (raises if it has not been built)."""
     global _lib
@@ -124,6 +135,7 @@ def lib():
             "rzpic_adjoint_create": [P, C.POINTER(AdjointConfig), C.POINTER(P)],
             "rzpic_adjoint_forward": [P, C.c_int64, C.POINTER(D)],
             "rzpic_adjoint_backward": [P, P, P, P, P], "rzpic_adjoint_destroy": [P],
+            "rzpic_deposit_noalloc": [C.POINTER(DepositArgs), P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -146,6 +158,26 @@ def constants():
 def _check(code):
     if code != 0:
         raise RzpicError(code, lib().rzpic_last_error().decode())
+
+
+def deposit_noalloc(nr, nz, R, L, r, z, w, out, status, *, n=None, precision=FP64,
+                    weighting=0, fixed_point_bits=0, w_ref=1.0, stream=None):
+    """rzpic_deposit_noalloc: N_ij of the particles (r, z, w: device tensors of
+    one dtype, float64 for FP64 or float32 for MIXED) into `out` (device
+    float64 tensor of nz*nr), allocating nothing; `status` is a device int32
+    tensor that receives the overflow bit.  Asynchronous on `stream` (a
+    torch.cuda.Stream; the current one if None)."""
+    import torch
+
+    if n is None:
+        n = r.numel()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    a = DepositArgs(nr=nr, nz=nz, R=R, L=L, precision=precision, weighting=weighting,
+                    fixed_point_bits=fixed_point_bits, reserved=0, w_ref=w_ref,
+                    r=r.data_ptr(), z=z.data_ptr(), w=w.data_ptr(), n=n,
+                    out=out.data_ptr(), status=status.data_ptr())
+    _check(lib().rzpic_deposit_noalloc(C.byref(a), C.c_void_p(stream.cuda_stream)))
 
 
 class Context:
