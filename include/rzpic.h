@@ -208,11 +208,21 @@ rzpic_status rzpic_deposit(rzpic_ctx *ctx);
 /* Multigrid solve (Sec. 2.5) of the implicit field equation with phi = V(t)
  * on z = 0, 0 on z = L and r = R, warm-started from the current phi.
  * Fixed-cycle mode runs config.mg_fixed_cycles V(0,1) cycles without a
- * test; otherwise cycles until the relative residual <= mg_tol (this mode
- * synchronises once per cycle).  cycles / relres (host, may be NULL) receive
- * the cycles run and the final relative residual (requesting them
- * synchronises).  ENOTCONV if the tolerance is not met. */
+ * test; otherwise cycles until the relative residual <= mg_tol, tested after
+ * every cycle.  That mode synchronises once per batch of cycles, not once per
+ * cycle: the solution is kept before each cycle of a batch, so the solve
+ * still stops at the first cycle that meets the tolerance (the first batch
+ * takes the cycles the previous solve needed; meshes above 8M nodes test
+ * after every cycle).  cycles / relres (host, may be NULL) receive the
+ * cycles run and the final relative residual (requesting them synchronises).
+ * ENOTCONV if the tolerance is not met. */
 rzpic_status rzpic_solve(rzpic_ctx *ctx, double t, int32_t *cycles, double *relres);
+/* The same solve with its results left on the device: cycles_dev (device
+ * int32) and relres_dev (device double), each may be NULL, are written on
+ * the stream.  Fixed-cycle mode never synchronises (relres_dev costs two
+ * residual kernels; EINVAL with an external circuit, whose two solutions
+ * have a residual each); tolerance mode synchronises as rzpic_solve. */
+rzpic_status rzpic_solve_dev(rzpic_ctx *ctx, double t, int32_t *cycles_dev, double *relres_dev);
 /* Change the multigrid cycling of later solves (same meaning as the config
  * fields mg_tol, mg_max_cycles, mg_fixed_cycles). */
 rzpic_status rzpic_set_mg(rzpic_ctx *ctx, double tol, int32_t max_cycles, int32_t fixed_cycles);
@@ -267,6 +277,31 @@ rzpic_status rzpic_set_pass_shape(rzpic_ctx *ctx, int32_t threads, int32_t parts
  * simulation advances by the steps run.  Synchronises. */
 rzpic_status rzpic_autotune(rzpic_ctx *ctx, int32_t steps, int64_t step0, double *table,
                             int32_t best[2], int64_t *next_step);
+
+/* Device pointers of the context's own grids ([nz][nr] doubles, row-major),
+ * for reading and writing them in place with no copy.  Owned by the context
+ * (valid until rzpic_destroy), except that FP64 solves move phi between two
+ * buffers: phi (and phi_p, phi_l) is valid until the next rzpic_solve,
+ * rzpic_solve_dev or rzpic_step.  rho and chi written here are the sources
+ * of the next rzpic_solve (rzpic_step forms them from the deposit).  er and
+ * ez are the nodal field of the last rzpic_efield (the particle gather reads
+ * its own packed copy: write them through rzpic_grid_copy).  phi_p, phi_l:
+ * the external circuit's charge and unit Laplace solutions, NULL without a
+ * circuit.  dens: the particle densities n_s = N_s / V of the last finalize,
+ * vol the weighting volumes V_ij (Sec. 2.4). */
+typedef struct rzpic_grid {
+    int32_t nr, nz;
+    double *phi, *rho, *chi, *er, *ez;
+    double *dens[2];
+    double *vol;
+    double *phi_p, *phi_l;
+} rzpic_grid;
+rzpic_status rzpic_grid_view(rzpic_ctx *ctx, rzpic_grid *out);
+/* Source of a solver-only use (rzpic_solve without particles): copies
+ * rho (C/m^3) and chi (device arrays of nz*nr doubles, caller-owned, read
+ * before the call returns on the stream) into the context's grids.
+ * Asynchronous. */
+rzpic_status rzpic_set_grid_source(rzpic_ctx *ctx, const double *rho, const double *chi);
 
 /* Copy grid `which` (RZPIC_G_*) between the context and a caller device
  * buffer of nz*nr doubles: to_ctx = 0 reads from the context, 1 writes into

@@ -112,6 +112,19 @@ struct rzpic_ctx {
     bool children_scanned = false;
     int last_cycles = 0;
     double last_relres = 0.0;
+    // Tolerance-mode solves run their cycles in batches with one
+    // synchronisation per batch: the finest-level solution is kept before
+    // each cycle of a batch (ring_slots copies of nn doubles; 0 on meshes
+    // too large for them, which check after every cycle), the residual norm
+    // before the batch and after each of its cycles goes to normk, then to a
+    // pinned host copy.  cyc_hint: cycles of the last solve per solution
+    // buffer (phi, phi_P, phi_L, the adjoint's), the next first batch.
+    static constexpr int kRingMax = 8;
+    double *ring = nullptr;
+    int ring_slots = 0;
+    unsigned long long *normk = nullptr;       // [kRingMax + 1]
+    unsigned long long *normk_host = nullptr;  // pinned, [kRingMax + 2]
+    int cyc_hint[4] = {1, 1, 1, 1};
     unsigned long long *psteps;  // [2]
     // timing: per recorded step 10 events (see mark())
     bool timing = false;

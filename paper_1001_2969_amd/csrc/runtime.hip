@@ -254,6 +254,25 @@ rzpic_status need_both(rzpic_ctx *c)
     return RZPIC_OK;
 }
 
+// Results of rzpic_solve_dev on the device: the cycles run and the relative
+// residual, either given (tolerance mode, known on the host) or formed from
+// the norms the fixed-cycle solve left in norm[0] (residual) and norm[1]
+// (scale), as the host does.
+__global__ void k_solve_out(int32_t *cycles, double *relres, int k, double rr,
+                            const unsigned long long *norm)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (cycles) *cycles = k;
+    if (relres) {
+        if (norm) {
+            const double rn = __longlong_as_double((long long)norm[0]);
+            const double sc = __longlong_as_double((long long)norm[1]);
+            rr = sc > 0 ? rn / sc : rn;
+        }
+        *relres = rr;
+    }
+}
+
 __global__ void k_set_count(Counts *cnt, int64_t n, uint64_t next_id)
 {
     cnt->n = n;
@@ -460,15 +479,22 @@ template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
     return RZPIC_OK;
 }
 
-// Cycles on a prepared system (eps formed and restricted, f set, the
+// V(0,1) cycles on u with right-hand side f (level tables prepared, the
 // Dirichlet values of u and u_alt set): `fixed` > 0 cycles without a test,
-// else cycles until ||f - A u||_inf <= tol ||f_bc||_inf (at most max_cycles;
-// one synchronisation per cycle).  *k receives the cycles run; with want_res
-// (always in tolerance mode) *relres the final relative residual.  The
-// V-cycle may exchange u and u_alt.
+// else cycles until ||f - A u||_inf <= tol ||f_bc||_inf (at most
+// max_cycles).  Tolerance mode runs the cycles in batches with one
+// synchronisation per batch: u is kept before each cycle of the batch and
+// the residual norm before the batch and after each cycle is recorded, so
+// the solve ends exactly at the first cycle that meets the tolerance (u
+// restored from its snapshot), as a test after every cycle would.  The
+// first batch takes the cycles the last solve of the same buffer (hint)
+// needed, later ones 2, 4, 8, ...  Meshes without snapshots test after
+// every cycle.  *k receives the cycles run; with want_res (always in
+// tolerance mode) *relres the final relative residual.  The V-cycle may
+// exchange u and u_alt.
 rzpic_status run_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, const double *f,
                         int fixed, double tol, int max_cycles, bool want_res, int *k_out,
-                        double *relres)
+                        double *relres, int *hint = nullptr)
 {
     const bool ob = c->mg.one_block != 0;
     bool down_done = false;  // the first cycle's restriction came with the tables
@@ -487,15 +513,20 @@ rzpic_status run_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, cons
         }
         return hipSuccess;
     };
+    auto as_double = [](unsigned long long v) {
+        double d;
+        std::memcpy(&d, &v, 8);
+        return d;
+    };
     auto resid = [&](double &rn, double &sc) -> rzpic_status {
-        unsigned long long hv[2];
         HIPCHK(launch_fill_u64(c->norm, 2, c->st));
         HIPCHK(mg_resid_norm(c->mg, u, f, 1, c->norm + 1, c->st));
         HIPCHK(mg_resid_norm(c->mg, u, f, 0, c->norm, c->st));
-        HIPCHK(hipMemcpyAsync(hv, c->norm, sizeof hv, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(c->normk_host, c->norm, 2 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
-        std::memcpy(&rn, &hv[0], 8);
-        std::memcpy(&sc, &hv[1], 8);
+        rn = as_double(c->normk_host[0]);
+        sc = as_double(c->normk_host[1]);
         return RZPIC_OK;
     };
     int k = 0;
@@ -503,34 +534,67 @@ rzpic_status run_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, cons
     if (fixed > 0) {
         HIPCHK(cycles_run(fixed));
         k = fixed;
-    } else {
-        HIPCHK(launch_fill_u64(c->norm, 2, c->st));
-        HIPCHK(mg_resid_norm(c->mg, u, f, 1, c->norm + 1, c->st));
-        for (;;) {
-            HIPCHK(launch_fill_u64(c->norm, 1, c->st));
-            HIPCHK(mg_resid_norm(c->mg, u, f, 0, c->norm, c->st));
-            unsigned long long hv[2];
-            HIPCHK(hipMemcpyAsync(hv, c->norm, sizeof hv, hipMemcpyDeviceToHost, c->st));
-            HIPCHK(hipStreamSynchronize(c->st));
+        *k_out = k;
+        if (want_res) {
             double rn, sc;
-            std::memcpy(&rn, &hv[0], 8);
-            std::memcpy(&sc, &hv[1], 8);
-            if (rn <= tol * sc) break;
-            if (k >= max_cycles) {
-                st = fail(RZPIC_ENOTCONV, "multigrid: relative residual %.3e after %d cycles",
-                          sc > 0 ? rn / sc : rn, k);
-                break;
-            }
+            TRY(resid(rn, sc));
+            *relres = sc > 0 ? rn / sc : rn;
+        }
+        return st;
+    }
+    const size_t nb = (size_t)c->nn * sizeof(double);
+    HIPCHK(launch_fill_u64(c->norm, 2, c->st));
+    HIPCHK(mg_resid_norm(c->mg, u, f, 1, c->norm + 1, c->st));
+    int batch = hint && *hint > 0 ? *hint : 1, next = 2;
+    double rr = 0.0;
+    for (;;) {
+        int B = c->ring_slots > 0 ? batch : 0;
+        if (B > c->ring_slots) B = c->ring_slots;
+        if (B > max_cycles - k) B = max_cycles - k;
+        if (B < 0) B = 0;
+        HIPCHK(launch_fill_u64(c->normk, B + 1, c->st));
+        HIPCHK(mg_resid_norm(c->mg, u, f, 0, c->normk, c->st));
+        for (int q = 0; q < B; ++q) {
+            HIPCHK(hipMemcpyAsync(c->ring + (size_t)q * c->nn, u, nb, hipMemcpyDeviceToDevice,
+                                  c->st));
+            HIPCHK(cycles_run(1));
+            HIPCHK(mg_resid_norm(c->mg, u, f, 0, c->normk + q + 1, c->st));
+        }
+        HIPCHK(hipMemcpyAsync(c->normk_host, c->normk, (B + 1) * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(c->normk_host + B + 1, c->norm + 1, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        const double sc = as_double(c->normk_host[B + 1]);
+        int q = 0;
+        while (q <= B && !(as_double(c->normk_host[q]) <= tol * sc)) ++q;
+        if (q <= B) {
+            // converged after k + q cycles: the later cycles of the batch undone
+            if (q < B)
+                HIPCHK(hipMemcpyAsync(u, c->ring + (size_t)q * c->nn, nb, hipMemcpyDeviceToDevice,
+                                      c->st));
+            k += q;
+            rr = sc > 0 ? as_double(c->normk_host[q]) / sc : as_double(c->normk_host[q]);
+            break;
+        }
+        k += B;
+        if (k >= max_cycles) {
+            const double rn = as_double(c->normk_host[B]);
+            rr = sc > 0 ? rn / sc : rn;
+            st = fail(RZPIC_ENOTCONV, "multigrid: relative residual %.3e after %d cycles", rr, k);
+            break;
+        }
+        if (B == 0) {  // no snapshots: one cycle, then the test again
             HIPCHK(cycles_run(1));
             ++k;
         }
+        // a solve that needs more than its hint: batches of 2, 4, 8, ...
+        batch = next;
+        next = next * 2 < c->ring_slots ? next * 2 : c->ring_slots;
     }
+    if (hint) *hint = k > 0 ? k : 1;
     *k_out = k;
-    if (want_res || fixed <= 0) {
-        double rn, sc;
-        TRY(resid(rn, sc));
-        *relres = sc > 0 ? rn / sc : rn;
-    }
+    *relres = rr;
     return st;
 }
 
@@ -566,11 +630,12 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
         int k2 = 0;
         double rr2 = rr;
         rzpic_status s1 = run_cycles(c, 0.0, c->phiP, c->phiP_alt, c->f, c->c.mg_fixed_cycles,
-                                     c->c.mg_tol, c->c.mg_max_cycles, cycles || relres, &k, &rr);
+                                     c->c.mg_tol, c->c.mg_max_cycles, cycles || relres, &k, &rr,
+                                     &c->cyc_hint[1]);
         if (s1 != RZPIC_OK && s1 != RZPIC_ENOTCONV) return s1;
         rzpic_status s2 = run_cycles(c, 1.0, c->phiL, c->phiL_alt, c->fzero,
                                      c->c.mg_fixed_cycles, c->c.mg_tol, c->c.mg_max_cycles,
-                                     cycles || relres, &k2, &rr2);
+                                     cycles || relres, &k2, &rr2, &c->cyc_hint[2]);
         if (s2 != RZPIC_OK && s2 != RZPIC_ENOTCONV) return s2;
         CircuitArgs a{};
         a.nr = nr;
@@ -599,7 +664,8 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
         return s1 != RZPIC_OK ? s1 : s2;
     }
     rzpic_status st = run_cycles(c, V, c->phi, c->phi_alt, c->f, c->c.mg_fixed_cycles,
-                                 c->c.mg_tol, c->c.mg_max_cycles, cycles || relres, &k, &rr);
+                                 c->c.mg_tol, c->c.mg_max_cycles, cycles || relres, &k, &rr,
+                                 &c->cyc_hint[0]);
     c->last_cycles = k;
     c->last_relres = rr;
     if (cycles) *cycles = k;
@@ -905,7 +971,8 @@ SpeciesK rz_species(const rzpic_ctx *c, int s) { return species_of(c, s); }
 rzpic_status rz_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, double tol,
                        int max_cycles, int *cycles, double *relres)
 {
-    return run_cycles(c, V, u, u_alt, c->f, 0, tol, max_cycles, true, cycles, relres);
+    return run_cycles(c, V, u, u_alt, c->f, 0, tol, max_cycles, true, cycles, relres,
+                      &c->cyc_hint[3]);
 }
 
 // ===========================================================================
@@ -1020,6 +1087,21 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
     A(c->acc[0], nn) A(c->acc[1], nn)
     A(c->cnt, 2) A(c->fix, 2) A(c->crec, 1) A(c->clrec, 2) A(c->tally, 6)
     A(c->mcstat, 2 * (1 + kMaxProc)) A(c->norm, 2) A(c->status, 1) A(c->psteps, 2)
+    A(c->normk, rzpic_ctx::kRingMax + 1)
+    {
+        // snapshots of the finest level for batched tolerance-mode cycles,
+        // within 64 MiB
+        const size_t per = nn * sizeof(double);
+        size_t cap = per > 0 ? ((size_t)64 << 20) / per : 0;
+        const int slots = (int)(cap < (size_t)rzpic_ctx::kRingMax ? cap : rzpic_ctx::kRingMax);
+        if (slots > 0) A(c->ring, (size_t)slots * nn)
+        c->ring_slots = slots;
+        void *h = nullptr;
+        if (hipHostMalloc(&h, (rzpic_ctx::kRingMax + 2) * sizeof(unsigned long long)) !=
+            hipSuccess)
+            return bail(fail(RZPIC_ENOMEM, "hipHostMalloc of the residual buffer failed"));
+        c->normk_host = (unsigned long long *)h;
+    }
     if (k.circuit_C > 0.0) {
         A(c->phiP, nn) A(c->phiP_alt, nn) A(c->phiL, nn) A(c->phiL_alt, nn) A(c->fzero, nn)
         A(c->circ, 1)
@@ -1142,6 +1224,7 @@ rzpic_status rzpic_destroy(rzpic_ctx *c)
         free_sort(c->sp[s]);
     }
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    if (c->normk_host) (void)hipHostFree(c->normk_host);
     delete c;
     return RZPIC_OK;
 }
@@ -1379,6 +1462,60 @@ rzpic_status rzpic_solve(rzpic_ctx *c, double t, int32_t *cycles, double *relres
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
     return solve_impl(c, t, false, cycles, relres);
+}
+
+rzpic_status rzpic_solve_dev(rzpic_ctx *c, double t, int32_t *cycles_dev, double *relres_dev)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    const bool fixed = c->c.mg_fixed_cycles > 0;
+    int32_t k = 0;
+    double rr = 0.0;
+    // fixed cycles: nothing asked on the host, so nothing synchronises
+    TRY(solve_impl(c, t, false, fixed ? nullptr : &k, fixed ? nullptr : &rr));
+    if (!cycles_dev && !relres_dev) return RZPIC_OK;
+    const unsigned long long *norm = nullptr;
+    if (fixed) {
+        k = c->c.mg_fixed_cycles;
+        if (relres_dev) {
+            if (c->c.circuit_C > 0.0)
+                return fail(RZPIC_EINVAL, "solve_dev: the residual of a circuit solve is per "
+                                          "solution; ask rzpic_solve");
+            HIPCHK(launch_fill_u64(c->norm, 2, c->st));
+            HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 1, c->norm + 1, c->st));
+            HIPCHK(mg_resid_norm(c->mg, c->phi, c->f, 0, c->norm, c->st));
+            norm = c->norm;
+        }
+    }
+    RZ_LAUNCH(k_solve_out, dim3(1), dim3(64), 0, c->st, cycles_dev, relres_dev, (int)k, rr, norm);
+    HIPCHK(hipGetLastError());
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_grid_view(rzpic_ctx *c, rzpic_grid *out)
+{
+    if (!c || !out) return fail(RZPIC_EINVAL, "null argument");
+    out->nr = c->c.nr;
+    out->nz = c->c.nz;
+    out->phi = c->phi;
+    out->rho = c->rho;
+    out->chi = c->chi;
+    out->er = c->er;
+    out->ez = c->ez;
+    out->dens[0] = c->dens[0];
+    out->dens[1] = c->dens[1];
+    out->vol = c->vol;
+    out->phi_p = c->phiP;
+    out->phi_l = c->phiL;
+    return RZPIC_OK;
+}
+
+rzpic_status rzpic_set_grid_source(rzpic_ctx *c, const double *rho, const double *chi)
+{
+    if (!c || !rho || !chi) return fail(RZPIC_EINVAL, "null argument");
+    const size_t bytes = (size_t)c->nn * sizeof(double);
+    HIPCHK(hipMemcpyAsync(c->rho, rho, bytes, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->chi, chi, bytes, hipMemcpyDeviceToDevice, c->st));
+    return RZPIC_OK;
 }
 
 rzpic_status rzpic_set_mg(rzpic_ctx *c, double tol, int32_t max_cycles, int32_t fixed_cycles)

@@ -31,7 +31,7 @@ EXPORTS = (
     "rzpic_batch_set_graph", "rzpic_set_voltage", "rzpic_adjoint_create",
     "rzpic_adjoint_forward", "rzpic_adjoint_backward", "rzpic_adjoint_destroy",
     "rzpic_set_circuit", "rzpic_get_circuit", "rzpic_set_pass_shape", "rzpic_autotune",
-    "rzpic_deposit_noalloc",
+    "rzpic_deposit_noalloc", "rzpic_solve_dev", "rzpic_grid_view", "rzpic_set_grid_source",
 )
 
 
@@ -88,6 +88,25 @@ class AdjointConfig(C.Structure):
 _lib = None
 
 
+class GridView(C.Structure):
+    _fields_ = [
+        ("nr", C.c_int32), ("nz", C.c_int32),
+        ("phi", C.c_void_p), ("rho", C.c_void_p), ("chi", C.c_void_p), ("er", C.c_void_p),
+        ("ez", C.c_void_p), ("dens0", C.c_void_p), ("dens1", C.c_void_p), ("vol", C.c_void_p),
+        ("phi_p", C.c_void_p), ("phi_l", C.c_void_p),
+    ]
+
+
+class _DeviceArray:
+    """A device array the library owns, exposed through the CUDA array
+    interface so that torch wraps it without a copy."""
+
+    def __init__(self, ptr, shape):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": "<f8",
+                                         "data": (int(ptr), False), "version": 3,
+                                         "strides": None}
+
+
 class DepositArgs(C.Structure):
     _fields_ = [
         ("nr", C.c_int32), ("nz", C.c_int32), ("R", C.c_double), ("L", C.c_double),
@@ -136,6 +155,9 @@ def lib():
             "rzpic_adjoint_forward": [P, C.c_int64, C.POINTER(D)],
             "rzpic_adjoint_backward": [P, P, P, P, P], "rzpic_adjoint_destroy": [P],
             "rzpic_deposit_noalloc": [C.POINTER(DepositArgs), P],
+            "rzpic_solve_dev": [P, D, P, P],
+            "rzpic_grid_view": [P, C.POINTER(GridView)],
+            "rzpic_set_grid_source": [P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -331,6 +353,32 @@ class Context:
         cyc, rr = C.c_int32(), C.c_double()
         _check(lib().rzpic_solve(self.h, t, C.byref(cyc), C.byref(rr)))
         return cyc.value, rr.value
+
+    def solve_dev(self, t, cycles=None, relres=None):
+        """rzpic_solve_dev: cycles (int32) and relres (float64) device tensors of
+        one element, either may be None; filled on the stream."""
+        _check(lib().rzpic_solve_dev(self.h, t,
+                                     None if cycles is None else C.c_void_p(cycles.data_ptr()),
+                                     None if relres is None else C.c_void_p(relres.data_ptr())))
+
+    def grid_view(self):
+        """The context's grids as torch tensors of shape (nz, nr) sharing its
+        memory (rzpic_grid_view): no copy.  phi is valid until the next solve
+        or step."""
+        v = GridView()
+        _check(lib().rzpic_grid_view(self.h, C.byref(v)))
+        out = {}
+        for f in ("phi", "rho", "chi", "er", "ez", "dens0", "dens1", "vol", "phi_p", "phi_l"):
+            ptr = getattr(v, f)
+            if ptr:
+                out[f] = self.torch.as_tensor(_DeviceArray(ptr, (v.nz, v.nr)),
+                                              device=self.device)
+        return out
+
+    def set_grid_source(self, rho, chi):
+        """rzpic_set_grid_source from device float64 tensors of nz*nr values."""
+        _check(lib().rzpic_set_grid_source(self.h, C.c_void_p(rho.data_ptr()),
+                                           C.c_void_p(chi.data_ptr())))
 
     def set_mg(self, tol=1e-10, max_cycles=100, fixed_cycles=0):
         _check(lib().rzpic_set_mg(self.h, tol, max_cycles, fixed_cycles))
