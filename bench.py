@@ -232,22 +232,105 @@ def vcycle_by_mesh():
     return out
 
 
-def cpu_baseline(w, steps):
-    """The FP64 CPU oracle (single thread, as it stands) on the first `steps`
-    steps of the same workload: particle-steps/s."""
+def host_info():
+    """The host the CPU baseline ran on: CPUs this process may use, the
+    machine's count and the processor model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "model": model}
+
+
+def cpu_threads():
+    """All-core thread count: the CPUs this process may use, at most 16 (the
+    host share of one GPU)."""
+    return max(1, min(len(os.sched_getaffinity(0)), 16))
+
+
+def cpu_leg(o, n0, steps, threads):
+    """`steps` merged steps from step n0 of the OpenMP timing build of the
+    oracle on `threads` threads: particle-steps/s, particle and solve time
+    per step, V-cycle time."""
     from oracle import rzo
 
-    o = rzo.Oracle(w.replace(precision="fp64"))
+    rzo.Oracle.set_threads(threads)
+    ps = 0
+    tp = ts = 0.0
+    cycles = 0
+    t0 = time.perf_counter()
+    for n in range(n0, n0 + steps):
+        ps += o.count(0) + o.count(1)
+        st, a, b, k = o.step_omp(n, with_cycles=True)
+        if st != 0:
+            raise RuntimeError(f"oracle step {n} failed ({st})")
+        tp += a
+        ts += b
+        cycles += k
+    wall = time.perf_counter() - t0
+    return {"threads": threads, "steps": steps, "particle_steps_per_s": ps / wall,
+            "particle_ms_per_step": 1e3 * tp / steps, "solve_ms_per_step": 1e3 * ts / steps,
+            "vcycles_per_step": cycles / steps,
+            "vcycle_ms": 1e3 * ts / cycles if cycles else None, "seconds": wall}
+
+
+def cpu_oracle(w):
+    from oracle import rzo
+
+    o = rzo.Oracle(w.replace(precision="fp64"), omp=True)
     o.init_particles(0, w.n_per_species, w.n0, w.Te_eV, 0)
     o.init_particles(1, w.n_per_species, w.n0, w.Ti_eV, 0)
     o.prologue()
-    ps = 0
-    t0 = time.perf_counter()
-    for n in range(steps):
-        ps += o.count(0) + o.count(1)
-        o.step(n)
-    dt = time.perf_counter() - t0
-    return ps / dt, dt
+    return o
+
+
+def cpu_baseline(study=False):
+    """The FP64 CPU oracle on this host, in its OpenMP timing build (the
+    oracle's own functions, particle loops on threads; tested equal to the
+    serial oracle): one thread and all cores, particle and multigrid time
+    apart.  Default (bounded): the 129x65 workload (10 steps on one thread,
+    then 30 on all cores), the 33x33 workload in full (10 steps, each
+    thread count), and 20 steps of the 513x129 workload on all cores.
+    study: the 129x65 workload's 200 steps on all cores and 20 of them on one
+    thread, and the 513x129 workload's 20 steps on one thread as well."""
+    from paper_1001_2969_amd import workloads as wl
+
+    nt = cpu_threads()
+    legs = {}
+    w1 = wl.rf_129x65()
+    o = cpu_oracle(w1)
+    single = cpu_leg(o, 0, 20 if study else 10, 1)
+    allc = cpu_leg(o, single["steps"], 200 if study else 30, nt)
+    legs[w1.name] = {"single_thread": single, "all_cores": allc}
+    del o
+    w0 = wl.small_fp64()
+    o = cpu_oracle(w0)
+    s0 = cpu_leg(o, 0, w0.steps, 1)
+    o = cpu_oracle(w0)
+    a0 = cpu_leg(o, 0, w0.steps, nt)
+    legs[w0.name] = {"single_thread": s0, "all_cores": a0, "note": "in full (10 steps)"}
+    del o
+    w2 = wl.large_513x129()
+    o = cpu_oracle(w2)
+    big = {"note": "20 of its 1000 steps (steps 0-19)"}
+    big["all_cores"] = cpu_leg(o, 0, 20, nt)
+    if study:
+        o = cpu_oracle(w2)
+        big["single_thread"] = cpu_leg(o, 0, 20, 1)
+    legs[w2.name] = big
+    del o
+    return {"value": allc["particle_steps_per_s"], "unit": "particle-steps/s", "cores": nt,
+            "kind": "oracle",
+            "sample": f"{w1.name}: steps {single['steps']}..{single['steps'] + allc['steps'] - 1} "
+                      f"on {nt} threads (FP64 oracle, OpenMP timing build), "
+                      f"{allc['seconds']:.1f} s",
+            "single_thread": {k: single[k] for k in ("particle_steps_per_s", "steps", "seconds")},
+            "host": host_info(), "legs": legs}
 
 
 def large_mesh(steps, warmup):
@@ -447,8 +530,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-steps", type=int, default=70)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-study", action="store_true",
+                    help="only the CPU oracle study (longer legs), printed as JSON")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-vcycle-study", action="store_true")
     ap.add_argument("--no-large", action="store_true",
@@ -481,6 +565,9 @@ def main():
 
     from paper_1001_2969_amd import rzpic, workloads as wl
 
+    if args.cpu_study:
+        print(json.dumps(cpu_baseline(study=True)), flush=True)
+        return
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.pmc_run:
         pmc_run(args.pmc_run, args.pmc_workload,
@@ -549,10 +636,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        v, secs = cpu_baseline(w, args.cpu_steps)
-        cpu = {"value": v, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {args.cpu_steps} steps of the same workload "
-                         f"(2 x {w.n_per_species} particles, FP64, single thread), {secs:.1f} s"}
+        cpu = cpu_baseline()
+        print(f"# cpu baseline: {json.dumps(cpu)}", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC, "value": mixed["value"], "unit": "particle-steps/s", "n_gpus": 1,

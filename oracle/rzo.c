@@ -544,6 +544,10 @@ static int absorb(rzo *o, species *sp, int64_t p)
     else if (sp->r[p] >= o->c.R) b = 2;
     if (b < 0) return 0;
     sp->dead[p] = 1;
+    /* the OpenMP timing build (rzo_omp.c) pushes particles in parallel */
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
     sp->absorbed[b] += sp->w[p];
     return 1;
 }
