@@ -497,6 +497,23 @@ def circuit_and_subcycle(steps, warmup):
     return out
 
 
+def calibration_copy():
+    """The device copy that calibrates the byte counters: 1 GiB, read from a
+    buffer written before another 1 GiB was written (so that the copy's reads
+    come from HBM, not from the 256 MB last-level cache).  Returns the bytes
+    copied each way."""
+    import torch
+
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    evict = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del evict
+    return nbytes
+
+
 def pmc_run(steps, workload, shape=None):
     """Short run for hardware-counter passes: a few merged steps of the mixed
     workload, then a plain device copy of known size (the calibration of the
@@ -512,17 +529,40 @@ def pmc_run(steps, workload, shape=None):
     ctx, res = run_gpu(w, "mixed", steps, 3, timing_steps=steps, capacity_factor=2.0,
                        shape=shape)
     ctx.close()
-    nbytes = 256 << 20
-    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(2):
-        dst.copy_(src)
-    torch.cuda.synchronize()
+    nbytes = calibration_copy()
     print(json.dumps({"pmc_run": True, "workload": w.name, "steps": steps, "particles_per_pass":
                       [res["timing"]["n0"], res["timing"]["n1"]],
                       "bytes_per_particle": BYTES_PER_PARTICLE["mixed"],
                       "copy_bytes_each_way": nbytes,
                       "pass_shape": list(shape) if shape else [512, 8192]}), flush=True)
+
+
+def pmc_vcycle(mesh, precision, solves=3, cycles=2):
+    """Short run for counter passes on the multigrid: `solves` fixed-cycle
+    solves of `cycles` V(0,1) cycles on the mesh (smooth rho, chi ~ 1), then
+    the device copy that calibrates the byte counters (calibration_copy)."""
+    import numpy as np
+    import torch
+
+    from paper_1001_2969_amd import rzpic, workloads as wl
+
+    if mesh == "129x65":
+        w = wl.rf_129x65()
+    else:
+        w = wl.Workload(name="synthetic_8193x2049_vcycle", nr=8193, nz=2049, R=0.16, L=0.04,
+                        n_per_species=1, steps=1, V_dc=35.0)
+    ctx = rzpic.Context(w, precision=precision, mg_fixed_cycles=cycles)
+    ctx.set_grid(rzpic.G_RHO, wl.smooth_rho(w, 5, 2e-4))
+    ctx.set_grid(rzpic.G_CHI, wl.smooth_chi(w, 1.0))
+    ctx.set_grid(rzpic.G_PHI, np.zeros((w.nz, w.nr)))
+    for _ in range(solves):
+        ctx.solve(1e-9, want=False)
+    ctx.sync()
+    ctx.close()
+    nbytes = calibration_copy()
+    print(json.dumps({"pmc_vcycle": True, "mesh": f"{w.nr}x{w.nz}", "precision": precision,
+                      "solves": solves, "cycles_per_solve": cycles,
+                      "copy_bytes_each_way": nbytes}), flush=True)
 
 
 def main():
@@ -554,6 +594,9 @@ def main():
     ap.add_argument("--pmc-workload", default="rf_129x65", choices=["rf_129x65", "large_513x129"])
     ap.add_argument("--pmc-shape", default=None, metavar="THREADS,PARTICLES",
                     help="pass launch shape of the counter run (default 512,8192)")
+    ap.add_argument("--pmc-vcycle", default=None, metavar="MESH,PRECISION",
+                    help="only fixed-cycle solves on 129x65 or 8193x2049, mixed or fp64, "
+                         "plus the copy calibration (for counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the "
@@ -569,6 +612,10 @@ def main():
         print(json.dumps(cpu_baseline(study=True)), flush=True)
         return
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.pmc_vcycle:
+        mesh, prec = args.pmc_vcycle.split(",")
+        pmc_vcycle(mesh, prec)
+        return
     if args.pmc_run:
         pmc_run(args.pmc_run, args.pmc_workload,
                 None if args.pmc_shape is None else tuple(int(x) for x in args.pmc_shape.split(",")))

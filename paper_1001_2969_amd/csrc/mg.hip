@@ -335,8 +335,9 @@ __device__ __forceinline__ void pcr(T *A, T *Bd, T *C, T *Rr, int n, int ne);
 template <int Q> __device__ __forceinline__ int part_slot(int e) { return e + e / Q; }
 
 // Staging passes of k_line_part: a pass stages the rows of NT / P segments
-// (Q NT / P rows of four values) in LDS; P keeps a pass near 72 KB for Q >= 4,
-// so that two blocks can share a compute unit's LDS.
+// (Q NT / P rows of four values) in LDS; P keeps a pass at 80 KB or less (72
+// KB for Q = 8, 80 KB for Q = 4, in either precision), so that two FP32
+// blocks share a compute unit's 160 KB of LDS.
 template <typename T, int Q> constexpr int part_passes()
 {
     return Q * (int)sizeof(T) / 16 > 1 ? Q * (int)sizeof(T) / 16 : 1;
@@ -350,6 +351,13 @@ template <typename T, int Q> constexpr size_t part_lds()
     constexpr size_t red = 7 * (size_t)kLongThreads;
     return (stage > red ? stage : red) * sizeof(T);
 }
+
+// two FP32 partition-solver blocks per compute unit (k_line_part_f32)
+static_assert(2 * part_lds<float, 2>() <= 160 * 1024, "FP32 Q=2 staging exceeds half the LDS");
+static_assert(2 * part_lds<float, 4>() <= 160 * 1024, "FP32 Q=4 staging exceeds half the LDS");
+static_assert(2 * part_lds<float, 8>() <= 160 * 1024, "FP32 Q=8 staging exceeds half the LDS");
+static_assert(part_lds<double, 8>() <= 160 * 1024 && part_lds<double, 4>() <= 160 * 1024,
+              "FP64 staging exceeds the LDS");
 
 template <typename T, int Q>
 __device__ __forceinline__ void line_part_body(const LineArgs<T> &p)

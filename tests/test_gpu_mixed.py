@@ -103,12 +103,20 @@ def run_mixed(w, nsteps, *, state=None, own_init=False, capacity_factor=2.0, che
 
 
 @pytest.mark.parametrize("path", ["block", "split", "multi", "long"])
-@pytest.mark.parametrize("mesh", [(33, 33), (129, 65), (65, 3)])
+@pytest.mark.parametrize("mesh", [(33, 33), (129, 65), (65, 3), (513, 129)])
 def test_mixed_solve(mesh, path, monkeypatch):
+    """Mixed cycles against the FP64 oracle; 513x129 takes the geometry of the
+    large workload (R = 15 cm, L = 2.5 cm: h_r = 0.29 mm against h_z up to
+    12.5 mm on its coarse levels)."""
     monkeypatch.setenv("RZPIC_MG_PATH", path)
     nr, nz = mesh
-    w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
-                    n_per_species=1, steps=1, V_dc=35.0)
+    if mesh == (513, 129):
+        big = wl.large_513x129()
+        w = wl.Workload(name="t", nr=nr, nz=nz, R=big.R, L=big.L, n_per_species=1, steps=1,
+                        V_dc=35.0)
+    else:
+        w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
+                        n_per_species=1, steps=1, V_dc=35.0)
     chi = wl.smooth_chi(w, 1.0)
     rho = wl.smooth_rho(w, 5, 2e-4)
     phi0 = np.random.default_rng(9).uniform(-10.0, 10.0, (w.nz, w.nr))
@@ -140,11 +148,14 @@ def test_mixed_solve(mesh, path, monkeypatch):
 # correction's line solves lose more there, and after one cycle from a
 # random start the library's default path (level kernel) is 4.3e-5 from the
 # FP64 oracle, the partition solver 5.0e-5; FP64 agrees to 4e-13 on both.
-@pytest.mark.parametrize("mesh,tol", [((65, 1025), TOL_GRID), ((1001, 513), 1e-4)])
+@pytest.mark.parametrize("mesh,tol", [((65, 1025), TOL_GRID), ((1001, 513), 1e-4),
+                                      ((3001, 9), TOL_GRID), ((4097, 9), TOL_GRID)])
 def test_mixed_long_lines_many_rows(mesh, tol, monkeypatch):
     """The forced long-line path on meshes with at least 256 lines of a colour
     on the finest level, where the FP32 line solver runs two blocks per
-    compute unit; the coarse levels (fewer lines) take the other form."""
+    compute unit, and on 3000 and 4096 unknowns per line (four per thread: the
+    FP32 solver's largest staging, 80 KB per block, with a ragged last
+    segment at 3000); every level runs the FP32 partition solver."""
     monkeypatch.setenv("RZPIC_MG_PATH", "long")
     nr, nz = mesh
     w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,

@@ -143,7 +143,9 @@ def test_solve_long_lines(mesh, precision):
     """Meshes whose r-lines exceed the level kernel's LDS (4096 and 8192
     unknowns, or 2048 in FP64): the partition-method half-sweeps, selected by
     the library itself, against the oracle's Thomas solves.  5000 and 3000
-    unknowns leave a ragged last segment and a partly filled staging pass."""
+    unknowns leave a ragged last segment and a partly filled staging pass (in
+    FP64; in the mixed form 3000 and 4096 unknowns fit the level kernel, and
+    the forced long-line path of test_gpu_mixed.py covers them)."""
     nr, nz = mesh
     w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
                     n_per_species=1, steps=1, V_dc=35.0)
