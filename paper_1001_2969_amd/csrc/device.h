@@ -210,45 +210,100 @@ __device__ __forceinline__ double sumsq3(double a, double b, double c)
     return a * a + b * b + c * c;
 }
 
-// Turn unit vector u by polar angle chi (cosine cx) and azimuth phi about
+// ---------------------------------------------------------------------------
+// Collision outcomes (Sec. 2.6) in a precision O of their own.  The decisions
+// (candidate, process, the threshold test, and for ions the Maxwellian target
+// the relative energy is formed with) are always made in FP64, bit for bit as
+// the reference arithmetic; the outcome (scattering angles, the shared energy
+// of an ionization, new-particle velocities) is formed in O: FP64 in the FP64
+// form, FP32 with the hardware transcendental instructions in the mixed form,
+// whose particles hold FP32 velocities anyway.
+template <typename O> struct OMath;
+template <> struct OMath<double> {
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    // (1 + e)^R
+    static __device__ __forceinline__ double pow1p(double e, double R) { return pow(1.0 + e, R); }
+    // sine and cosine of 2 pi u
+    static __device__ __forceinline__ void sincos_turns(double u, double &s, double &c)
+    {
+        sincos(kTwoPi * u, &s, &c);
+    }
+    static __device__ __forceinline__ double log_(double x) { return log(x); }
+    static __device__ __forceinline__ double tan_(double x) { return tan(x); }
+    static __device__ __forceinline__ double atan_(double x) { return atan(x); }
+};
+template <> struct OMath<float> {
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float pow1p(float e, float R)
+    {
+        return __builtin_amdgcn_exp2f(R * __builtin_amdgcn_logf(1.0f + e));
+    }
+    // the hardware sine and cosine take their argument in turns
+    static __device__ __forceinline__ void sincos_turns(float u, float &s, float &c)
+    {
+        s = __builtin_amdgcn_sinf(u);
+        c = __builtin_amdgcn_cosf(u);
+    }
+    static __device__ __forceinline__ float log_(float x)
+    {
+        return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
+    }
+    static __device__ __forceinline__ float tan_(float x) { return tanf(x); }
+    static __device__ __forceinline__ float atan_(float x) { return atanf(x); }
+};
+
+// Turn unit vector u by polar angle chi (cosine cx) and azimuth 2 pi t about
 // itself; azimuth measured from p = (a x u)/|a x u|, a = z (or x if u is within
 // ~8 degrees of z), q = u x p.
-__device__ __forceinline__ void turn(double &u0, double &u1, double &u2, double cx, double phi)
+template <typename O>
+__device__ __forceinline__ void turn(O &u0, O &u1, O &u2, O cx, O t)
 {
-    double px, py, pz;
-    if (fabs(u2) < 0.99) {
+    using M = OMath<O>;
+    O px, py, pz;
+    if (fabs(u2) < (O)0.99) {
         px = -u1;
         py = u0;
-        pz = 0.0;
+        pz = (O)0;
     } else {
-        px = 0.0;
+        px = (O)0;
         py = -u2;
         pz = u1;
     }
-    double pn = sqrt(px * px + py * py + pz * pz);
+    O pn = M::sqrt_(px * px + py * py + pz * pz);
     px /= pn;
     py /= pn;
     pz /= pn;
-    double qx = u1 * pz - u2 * py;
-    double qy = u2 * px - u0 * pz;
-    double qz = u0 * py - u1 * px;
-    double sx = sqrt(fmax(0.0, 1.0 - cx * cx));
-    double sp, cp;
-    sincos(phi, &sp, &cp);
-    double n0 = cx * u0 + sx * (cp * px + sp * qx);
-    double n1 = cx * u1 + sx * (cp * py + sp * qy);
-    double n2 = cx * u2 + sx * (cp * pz + sp * qz);
+    O qx = u1 * pz - u2 * py;
+    O qy = u2 * px - u0 * pz;
+    O qz = u0 * py - u1 * px;
+    O sx = M::sqrt_(fmax((O)0, (O)1 - cx * cx));
+    O sp, cp;
+    M::sincos_turns(t, sp, cp);
+    O n0 = cx * u0 + sx * (cp * px + sp * qx);
+    O n1 = cx * u1 + sx * (cp * py + sp * qy);
+    O n2 = cx * u2 + sx * (cp * pz + sp * qz);
     u0 = n0;
     u1 = n1;
     u2 = n2;
 }
 
 // Vahedi & Surendra (1995) electron scattering angle, eps in eV.
-__device__ __forceinline__ double cos_chi_e(double eps, double R)
+template <typename O> __device__ __forceinline__ O cos_chi_e(O eps, O R)
 {
-    if (!(eps > 0.0)) return 1.0 - 2.0 * R;
-    double c = (2.0 + eps - 2.0 * pow(1.0 + eps, R)) / eps;
-    return fmin(1.0, fmax(-1.0, c));
+    if (!(eps > (O)0)) return (O)1 - (O)2 * R;
+    O c = ((O)2 + eps - (O)2 * OMath<O>::pow1p(eps, R)) / eps;
+    return fmin((O)1, fmax((O)-1, c));
+}
+
+// Two standard normals from a uniform pair (Box-Muller) in precision O.
+template <typename O> __device__ __forceinline__ void normal2o(O ua, O ub, O &n1, O &n2)
+{
+    using M = OMath<O>;
+    O rad = M::sqrt_((O)-2 * M::log_(ua));
+    O sn, cs;
+    M::sincos_turns(ub, sn, cs);
+    n1 = rad * cs;
+    n2 = rad * sn;
 }
 
 struct Child {
@@ -262,10 +317,13 @@ struct Child {
 // *iz.  Draw blocks: 0 = (candidate, process); electrons: 1 = (chi, phi),
 // 2 = (ejected energy, chi_ej), 3 = (phi_ej, -), 4-5 = ion normals;
 // ions: 1-2 = target normals, 3 = (cos chi, phi) in the centre of mass.
+// O: precision of the outcome (see OMath).
+template <typename O>
 __device__ __forceinline__ int collide_candidate(const SpeciesK &sp, const Phys &ph, uint64_t id,
                                               uint32_t step, double ub, double &v0, double &v1,
                                               double &v2, int &iz, Child &ce, Child &ci)
 {
+    using M = OMath<O>;
     iz = 0;
     double thr_nu;
     {
@@ -277,71 +335,76 @@ __device__ __forceinline__ int collide_candidate(const SpeciesK &sp, const Phys 
         double vm = sqrt(sumsq3(v0, v1, v2));
         int k = choose_process(sp.xs, ph.n_gas, thr_nu, eps, vm);
         if (k < 0) return 1;
-        double u0 = 0.0, u1 = 0.0, u2 = 1.0;
-        if (vm > 0.0) {
-            u0 = v0 / vm;
-            u1 = v1 / vm;
-            u2 = v2 / vm;
-        }
-        double ra, rb;
-        uniform2(ph.seed, sp.s, id, step, 1, ra, rb);
-        int kind = sp.xs.kind[k];
-        const double m = sp.m;
-        if (kind == 0) {
-            double cx = cos_chi_e(eps, ra);
-            double eps1 = eps * (1.0 - (2.0 * m / ph.m_gas) * (1.0 - cx));
-            turn(u0, u1, u2, cx, kTwoPi * rb);
-            double s1 = sqrt(2.0 * eps1 * kE / m);
-            v0 = s1 * u0;
-            v1 = s1 * u1;
-            v2 = s1 * u2;
-            return 2 + k;
-        }
         double ex;
         {
 #pragma clang fp contract(off)
             ex = eps - sp.xs.thr[k];
         }
-        if (ex < 0.0) return 1;
+        const int kind = sp.xs.kind[k];
+        if (kind != 0 && ex < 0.0) return 1;
+        O u0 = (O)0, u1 = (O)0, u2 = (O)1;
+        if (vm > 0.0) {
+            u0 = (O)(v0 / vm);
+            u1 = (O)(v1 / vm);
+            u2 = (O)(v2 / vm);
+        }
+        double ra, rb;
+        uniform2(ph.seed, sp.s, id, step, 1, ra, rb);
+        const O m = (O)sp.m, qe = (O)kE;
+        if (kind == 0) {
+            const O e = (O)eps;
+            O cx = cos_chi_e<O>(e, (O)ra);
+            O eps1 = e * ((O)1 - ((O)2 * m / (O)ph.m_gas) * ((O)1 - cx));
+            turn<O>(u0, u1, u2, cx, (O)rb);
+            O s1 = M::sqrt_((O)2 * eps1 * qe / m);
+            v0 = (double)(s1 * u0);
+            v1 = (double)(s1 * u1);
+            v2 = (double)(s1 * u2);
+            return 2 + k;
+        }
+        const O eo = (O)ex;
         if (kind == 1) {
-            double cx = cos_chi_e(ex, ra);
-            turn(u0, u1, u2, cx, kTwoPi * rb);
-            double s1 = sqrt(2.0 * ex * kE / m);
-            v0 = s1 * u0;
-            v1 = s1 * u1;
-            v2 = s1 * u2;
+            O cx = cos_chi_e<O>(eo, (O)ra);
+            turn<O>(u0, u1, u2, cx, (O)rb);
+            O s1 = M::sqrt_((O)2 * eo * qe / m);
+            v0 = (double)(s1 * u0);
+            v1 = (double)(s1 * u1);
+            v2 = (double)(s1 * u2);
             return 2 + k;
         }
         double rc, rd, re, rf;
         uniform2(ph.seed, sp.s, id, step, 2, rc, rd);
         uniform2(ph.seed, sp.s, id, step, 3, re, rf);
-        const double B = sp.xs.ejB;
-        double eej = B * tan(rc * atan(ex / (2.0 * B)));
-        double esc = ex - eej;
-        double s0 = u0, s1_ = u1, s2 = u2;
-        turn(s0, s1_, s2, cos_chi_e(esc, ra), kTwoPi * rb);
-        double e0 = u0, e1 = u1, e2 = u2;
-        turn(e0, e1, e2, cos_chi_e(eej, rd), kTwoPi * re);
-        double vs = sqrt(2.0 * esc * kE / m);
-        double ve = sqrt(2.0 * eej * kE / m);
-        v0 = vs * s0;
-        v1 = vs * s1_;
-        v2 = vs * s2;
-        ce.vr = ve * e0;
-        ce.vt = ve * e1;
-        ce.vz = ve * e2;
-        double g1a, g1b, g2a, g2b, n1, n2, n3, n4;
+        const O B = (O)sp.xs.ejB;
+        O eej = B * M::tan_((O)rc * M::atan_(eo / ((O)2 * B)));
+        O esc = eo - eej;
+        O s0 = u0, s1_ = u1, s2 = u2;
+        turn<O>(s0, s1_, s2, cos_chi_e<O>(esc, (O)ra), (O)rb);
+        O e0 = u0, e1 = u1, e2 = u2;
+        turn<O>(e0, e1, e2, cos_chi_e<O>(eej, (O)rd), (O)re);
+        O vs = M::sqrt_((O)2 * esc * qe / m);
+        O ve = M::sqrt_((O)2 * eej * qe / m);
+        v0 = (double)(vs * s0);
+        v1 = (double)(vs * s1_);
+        v2 = (double)(vs * s2);
+        ce.vr = (double)(ve * e0);
+        ce.vt = (double)(ve * e1);
+        ce.vz = (double)(ve * e2);
+        double g1a, g1b, g2a, g2b;
+        O n1, n2, n3, n4;
         uniform2(ph.seed, sp.s, id, step, 4, g1a, g1b);
         uniform2(ph.seed, sp.s, id, step, 5, g2a, g2b);
-        normal2(g1a, g1b, n1, n2);
-        normal2(g2a, g2b, n3, n4);
-        ci.vr = ph.vth_gas * n1;
-        ci.vt = ph.vth_gas * n2;
-        ci.vz = ph.vth_gas * n3;
+        normal2o<O>((O)g1a, (O)g1b, n1, n2);
+        normal2o<O>((O)g2a, (O)g2b, n3, n4);
+        const O vth = (O)ph.vth_gas;
+        ci.vr = (double)(vth * n1);
+        ci.vt = (double)(vth * n2);
+        ci.vz = (double)(vth * n3);
         iz = 1;
         return 2 + k;
     }
     if (sp.mc_model == 2) {
+        // the target's velocity decides the relative energy: FP64 always
         double g1a, g1b, g2a, g2b, n1, n2, n3, n4;
         uniform2(ph.seed, sp.s, id, step, 1, g1a, g1b);
         uniform2(ph.seed, sp.s, id, step, 2, g2a, g2b);
@@ -366,16 +429,16 @@ __device__ __forceinline__ int collide_candidate(const SpeciesK &sp, const Phys 
         if (k < 0) return 1;
         double ra, rb;
         uniform2(ph.seed, sp.s, id, step, 3, ra, rb);
-        double cx = 1.0 - 2.0 * ra;
-        double sx = sqrt(fmax(0.0, 1.0 - cx * cx));
-        double sp_, cp_;
-        sincos(kTwoPi * rb, &sp_, &cp_);
-        const double M = ph.m_gas, m = sp.m;
-        const double fcm = M / (m + M);
-        double d0 = sx * cp_, d1 = sx * sp_, d2 = cx;
-        v0 = (m * v0 + M * t0) / (m + M) + fcm * gm * d0;
-        v1 = (m * v1 + M * t1) / (m + M) + fcm * gm * d1;
-        v2 = (m * v2 + M * t2) / (m + M) + fcm * gm * d2;
+        const O cx = (O)1 - (O)2 * (O)ra;
+        const O sx = M::sqrt_(fmax((O)0, (O)1 - cx * cx));
+        O sp_, cp_;
+        M::sincos_turns((O)rb, sp_, cp_);
+        const O Mg = (O)ph.m_gas, mi = (O)sp.m;
+        const O fcm = Mg / (mi + Mg), gmo = (O)gm;
+        const O d0 = sx * cp_, d1 = sx * sp_, d2 = cx;
+        v0 = (double)((mi * (O)v0 + Mg * (O)t0) / (mi + Mg) + fcm * gmo * d0);
+        v1 = (double)((mi * (O)v1 + Mg * (O)t1) / (mi + Mg) + fcm * gmo * d1);
+        v2 = (double)((mi * (O)v2 + Mg * (O)t2) / (mi + Mg) + fcm * gmo * d2);
         return 2 + k;
     }
     return 0;

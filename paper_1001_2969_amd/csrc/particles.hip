@@ -511,7 +511,7 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
         double v0 = s.vr, v1 = s.vt, v2 = s.vz;
         int iz = 0;
         Child che{}, chi{};
-        int ev = collide_candidate(a.sp, a.phys, id, a.step, ub, v0, v1, v2, iz, che, chi);
+        int ev = collide_candidate<T>(a.sp, a.phys, id, a.step, ub, v0, v1, v2, iz, che, chi);
         if (ev >= 2) {
             s.vr = (T)v0;
             s.vt = (T)v1;

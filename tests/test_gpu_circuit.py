@@ -66,8 +66,12 @@ def test_circuit_steps_match_oracle(cycles):
     print("circuit after 6 steps", g.circuit())
 
 
-def test_circuit_mixed_form():
-    w = W.replace(mg_fixed_cycles=3)
+@pytest.mark.parametrize("cycles", [3, 0])
+def test_circuit_mixed_form(cycles):
+    """Fixed cycles and converged solves: the electrode potential's error is
+    the same in both (about 2e-4 V here), so it comes from the FP32 particle
+    charge near the electrode, not from the FP32 correction cycles."""
+    w = W.replace(mg_fixed_cycles=cycles)
     o, g = pair(w, precision="mixed", capacity_factor=3.0)
     load_state(o, g, _state(w, 72))
     o.prologue()
@@ -78,8 +82,8 @@ def test_circuit_mixed_form():
     for s in (0, 1):
         compare_mixed(g.particles(s), o.particles(s), w, label=f"s={s}")
     compare_grid(g.grid(rzpic.G_PHI), o.grid(rzo.G_PHI), TOL_GRID, "phi")
-    # The electrode charges are flux differences of phi near the electrode,
-    # solved with FP32 correction cycles (~1e-6 relative here).  V is a
+    # The electrode charges carry the FP32 particle state's error (~1e-6
+    # relative here, with converged solves as with three cycles).  V is a
     # difference of charges over C + Q_L: its error scales with
     # (|Q_P| + |Q_c|) / (C + Q_L), here hundreds of volts against |V| ~ 1.6 V.
     gc, oc = g.circuit(), o.circuit()
