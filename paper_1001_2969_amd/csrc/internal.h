@@ -317,8 +317,11 @@ struct MgLevels {
     // in LDS (FP64: the finest level is phi itself, in global memory), the
     // line matrices factored beforehand into per-line tables.
     int one_block;         // 1: every cycle in one single-workgroup launch
-    int split;             // 1: per cycle a residual/restriction launch, the coarse
-                           //    levels in one workgroup, the finest level's sweep
+    int split;             // 1: per cycle a residual/restriction launch, then the way
+                           //    up: each finest-level block with the coarse lines
+                           //    it depends on (or, split_coarse, the coarse levels
+                           //    in one workgroup and then the finest level's sweep)
+    int split_coarse;      // 1: the split cycle's two-launch way up
     int S;                 // reduction steps of an r-line (ceil(log2(nr - 1)))
     int line_off[kMaxLevels + 2];  // first table line of each level; line_off[L+1] = total
     size_t tab_stride;     // elements per line table: (3 + 2 S) (nr - 1)

@@ -1223,6 +1223,15 @@ template <typename T, int Q, int SMAX> struct LineTab {
     T ta[Q], tc[Q], bf[Q], k1[SMAX][Q], k2[SMAX][Q];
 };
 
+// Row `row` of a line table at a 32-bit byte offset: the row base is the same
+// for the whole wavefront (scalar registers), the offset j * sizeof(T) is
+// one register that every row shares (j < n <= 8192).
+template <typename T>
+__device__ __forceinline__ T tab_at(const T *tb, size_t row, int n, uint32_t off)
+{
+    return *(const T *)((const char *)(tb + row * (size_t)n) + off);
+}
+
 // The loads alone (clamped indices), then the masking of unknowns past the
 // line's end and of reduction steps past S: a prefetched table is masked only
 // when it is used, so nothing waits for its loads before then.
@@ -1234,14 +1243,15 @@ __device__ __forceinline__ void line_tab_fetch(const T *tb, int n, int S, int la
     for (int q = 0; q < Q; ++q) {
         const int j = q * 64 + lane;
         const int jj = j < n ? j : n - 1;
-        t.ta[q] = tb[jj];
-        t.tc[q] = tb[n + jj];
-        t.bf[q] = tb[2 * n + jj];
+        const uint32_t off = (uint32_t)jj * (uint32_t)sizeof(T);
+        t.ta[q] = tab_at(tb, 0, n, off);
+        t.tc[q] = tab_at(tb, 1, n, off);
+        t.bf[q] = tab_at(tb, 2, n, off);
 #pragma unroll
         for (int st = 0; st < SMAX; ++st) {
             const int sc = st < S ? st : S - 1;
-            t.k1[st][q] = tb[(size_t)(3 + 2 * sc) * n + jj];
-            t.k2[st][q] = tb[(size_t)(4 + 2 * sc) * n + jj];
+            t.k1[st][q] = tab_at(tb, (size_t)(3 + 2 * sc), n, off);
+            t.k2[st][q] = tab_at(tb, (size_t)(4 + 2 * sc), n, off);
         }
     }
 }
@@ -1703,6 +1713,260 @@ static hipError_t fine_sweep(const MgLevels &m, int mixed, const double *phi_in,
     return hipGetLastError();
 }
 
+// Up leg of the split cycle in one launch (Algorithm 1's way up: exact
+// coarsest line, then per level the injected correction and one zebra sweep).
+// Block b owns the finest level's even line i = 2b+2 and odd line i-1 (the
+// last block also i+1), as in k_fine.  Before its finest lines it solves,
+// level by level from the coarsest, every coarser line they depend on: an
+// odd line of level l needs rows (r-1)/2 and (r+1)/2 of level l-1, an even
+// line the odd lines beside it.  Those lines form a window of at most five
+// consecutive lines per level (three odd, two even), so each block repeats a
+// few lines of every coarse level that its neighbours also solve, with the
+// same tables and arithmetic and therefore the same values.  The coarse
+// levels then cost 31 compute units a few line tables each, instead of one
+// compute unit all of them, and the cycle needs no separate coarse launch.
+// A line's inputs (table, right-hand side, phi) are fetched two phases before
+// it is solved: data that other compute units wrote takes longer to arrive
+// than one phase lasts.
+constexpr int kUpWin = 5;         // lines of one level's window
+constexpr int kUpThreads = 192;   // three wavefronts: a phase has at most three lines
+
+template <typename T, int Q> struct k_up_A {
+    MgLevels m;
+    int mixed;
+    const double *phi_in;
+    double *phi_out;
+    const double *f;
+};
+
+template <typename T, int Q, int SMAX> struct UpIn {
+    LineTab<T, Q, SMAX> tab;
+    T g[Q];                // right-hand side
+    double pl[Q], ph[Q];   // finest level, FP64: phi_in of rows r-1 and r+1
+    double pc[Q];          // finest level, mixed: phi of row r
+};
+
+static size_t up_lds(const MgLevels &m, int mixed)
+{
+    return (size_t)(m.L + 1) * kUpWin * m.nr * (mixed ? sizeof(float) : sizeof(double));
+}
+
+// A 64-bit address the whole wavefront shares, kept in scalar registers (so
+// that a load adds a 32-bit lane offset to it, with no per-lane address
+// arithmetic).
+template <typename P> __device__ __forceinline__ P *uniform_ptr(P *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P *)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename T> __device__ __forceinline__ T ld_off(const T *base, uint32_t off)
+{
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) T gT;
+    return *(gT *)((gchar *)base + off);
+}
+
+// The levels of a mesh with nz = 2^L + 1 rows have nz_l = 2^l + 1 rows; the
+// line tables of level l start at line 2^l - l - 1 (levels 1..l-1 hold
+// nz_q - 2 interior lines each), and the coarse block (u then f of each level)
+// holds level l's u at row 2 (2^l + l - 3) and its f nz_l rows later.
+__device__ __forceinline__ int up_nzl(int l) { return (1 << l) + 1; }
+__device__ __forceinline__ int up_line_off(int l) { return (1 << l) - l - 1; }
+__device__ __forceinline__ size_t up_f_row(int l) { return 2 * (size_t)((1 << l) + l - 3) + up_nzl(l); }
+
+template <typename T, int Q>
+__device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_)
+{
+    const MgLevels &m = A_.m;
+    const int mixed = A_.mixed;
+    const double *phi_in = A_.phi_in;
+    double *phi_out = A_.phi_out;
+    const double *f = A_.f;
+    constexpr int SMAX = Q == 1 ? 6 : Q == 2 ? 7 : 8;
+    extern __shared__ unsigned char smem_raw[];
+    T *win = (T *)smem_raw;  // [level][kUpWin][nr]: the window's solutions
+    const int L = m.L, nr = m.nr, n = nr - 1, nz = up_nzl(L), S = m.S;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i = 2 * kb_.x + 2;
+    const bool last = i + 1 == nz - 2;
+    // The window of level l, k = L - l levels below the finest: the rows its
+    // level above reads are [p, q] with p = max(floor(i / 2^k) - 1, 0) and
+    // q = floor((i + 2^k - 1) / 2^k) + 1, its lines [p, q] widened to odd ends
+    // and kept inside the interior (the closed form of narrowing [i-1, i+1]
+    // level by level: each odd line reads the rows (r-1)/2, (r+1)/2 below it).
+    auto wlo = [&](int l) {
+        const int k = L - l, p = (i >> k) - 1 > 0 ? (i >> k) - 1 : 0;
+        const int a = (p - 1) | 1;
+        return a > 1 ? a : 1;
+    };
+    auto whi = [&](int l) {
+        const int k = L - l, b = (((i + (1 << k) - 1) >> k) + 1) | 1;
+        return b < (1 << l) - 1 ? b : (1 << l) - 1;
+    };
+    auto W = [&](int l, int r) {  // row r of level l in the window (clamped into it)
+        int k = r - wlo(l);
+        k = k < 0 ? 0 : k >= kUpWin ? kUpWin - 1 : k;
+        return win + ((size_t)l * kUpWin + k) * nr;
+    };
+    auto cnt_of = [&](int l, int par) {
+        const int d = whi(l) - wlo(l);
+        return par ? d / 2 + 1 : d / 2;
+    };
+    // Phase ph = 0 .. 2L-1 is level ph/2 + 1, odd lines (even ph) or even
+    // lines.  A phase has at most three lines and the block three wavefronts,
+    // so wavefront w solves line w of each phase that has one.
+    const int nph = 2 * L;
+    const T *coarse = (const T *)m.coarse_uf;
+    const T *fr = mixed ? (const T *)m.f32[L] : nullptr;  // mixed: FP32 residual
+    const T *tab = (const T *)m.tab;
+    const size_t tstride = m.tab_stride;
+    // The inputs of this wavefront's line of phase ph: its table rows
+    // (a | c | b_final | k1, k2 of each step, see factor_body), right-hand
+    // side and phi.  Every wavefront fetches in every phase (a wavefront
+    // without a line there, or a phase past the last, takes another line of
+    // the block), so that the loads in flight are the same on every path.
+    auto fetch = [&](int ph, UpIn<T, Q, SMAX> &in) {
+        int l = ph / 2 + 1, par = !(ph & 1), t = wave;
+        if (ph >= nph) {
+            l = 1;
+            par = 1;
+            t = 0;
+        } else {
+            const int c = cnt_of(l, par);
+            if (t >= c) {
+                if (c > 0) {
+                    t = c - 1;
+                } else {
+                    par = 1;  // level 1 has no even line
+                    t = 0;
+                }
+            }
+        }
+        const int r = (par ? wlo(l) : wlo(l) + 1) + 2 * t;
+        const bool fine = l == L;
+        const T *tb = tab + (size_t)(up_line_off(l) + r - 1) * tstride;
+        const T *fl = coarse + (up_f_row(l) + r) * nr;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = q * 64 + lane;
+            const int jj = j < n ? j : n - 1;
+            const uint32_t ot = (uint32_t)jj * (uint32_t)sizeof(T);
+            in.tab.ta[q] = ld_off(uniform_ptr(tb), ot);
+            in.tab.tc[q] = ld_off(uniform_ptr(tb + n), ot);
+            in.tab.bf[q] = ld_off(uniform_ptr(tb + 2 * (size_t)n), ot);
+#pragma unroll
+            for (int st = 0; st < SMAX; ++st) {
+                const int sc = st < S ? st : S - 1;
+                in.tab.k1[st][q] = ld_off(uniform_ptr(tb + (size_t)(3 + 2 * sc) * n), ot);
+                in.tab.k2[st][q] = ld_off(uniform_ptr(tb + (size_t)(4 + 2 * sc) * n), ot);
+            }
+            const uint32_t od = (uint32_t)jj * (uint32_t)sizeof(double);
+            in.pl[q] = in.ph[q] = in.pc[q] = 0.0;
+            if (!fine) {
+                in.g[q] = ld_off(uniform_ptr(fl), ot);
+            } else if (mixed) {
+                in.g[q] = ld_off(uniform_ptr(fr + (size_t)r * nr), ot);
+                in.pc[q] = ld_off(uniform_ptr(phi_in + (size_t)r * nr), od);
+            } else {
+                in.g[q] = (T)ld_off(uniform_ptr(f + (size_t)r * nr), od);
+                in.pl[q] = ld_off(uniform_ptr(phi_in + (size_t)(r - 1) * nr), od);
+                in.ph[q] = ld_off(uniform_ptr(phi_in + (size_t)(r + 1) * nr), od);
+            }
+        }
+    };
+    // The line of phase ph, if this wavefront has one, then the barrier.
+    // The table needs no masking: reduction steps past S are not run, and the
+    // lanes past the line's end (their loads clamped to its last unknown)
+    // meet only multipliers that are zero in the table of every unknown.
+    auto run = [&](int ph, const UpIn<T, Q, SMAX> &in) {
+        const int l = ph / 2 + 1, par = !(ph & 1), nzl = up_nzl(l);
+        const bool fine = l == L;
+        if (wave < cnt_of(l, par)) {
+            const int r = (par ? wlo(l) : wlo(l) + 1) + 2 * wave;
+            const int lb = par ? (l > 1 ? l - 1 : 1) : l;
+            const T *ulo = W(lb, par ? (r - 1) >> 1 : r - 1);
+            const T *uhi = W(lb, par ? (r + 1) >> 1 : r + 1);
+            const bool inj = par && l > 1;
+            T R[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int j = q * 64 + lane;
+                const bool ok = j < n;
+                const int jj = ok ? j : n - 1;
+                const T a = ulo[jj], b = uhi[jj];
+                T lo, hi;
+                if (par) {
+                    // odd line: the coarse correction injected into the even
+                    // rows r-1, r+1 (zero on the electrodes)
+                    const T cl = inj && r - 1 > 0 ? a : (T)0;
+                    const T ch = inj && r + 1 < nzl - 1 ? b : (T)0;
+                    if (fine && !mixed) {
+                        lo = (T)(in.pl[q] + (double)cl);
+                        hi = (T)(in.ph[q] + (double)ch);
+                    } else {
+                        lo = cl;
+                        hi = ch;
+                    }
+                } else {
+                    lo = a;
+                    hi = b;
+                }
+                R[q] = ok ? in.g[q] + in.tab.ta[q] * lo + in.tab.tc[q] * hi : (T)0;
+            }
+            line_pcr<T, Q, SMAX>(R, in.tab, S, lane);
+            T *ur = W(l, r);
+            const bool own = fine && (r == i - 1 || r == i || (last && r == i + 1));
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int j = q * 64 + lane;
+                if (j >= n) continue;
+                ur[j] = R[q];
+                if (own)
+                    phi_out[(size_t)r * nr + j] = mixed ? in.pc[q] + (double)R[q] : (double)R[q];
+            }
+        }
+        __syncthreads();
+    };
+    // Three buffers in fixed roles: phase ph reads buffer ph mod 3 while the
+    // inputs of phase ph + 2 are on their way (one phase is shorter than a
+    // load from memory written by other compute units).
+    UpIn<T, Q, SMAX> b0, b1, b2;
+    fetch(0, b0);
+    fetch(1, b1);
+    for (int ph = 0; ph < nph; ph += 3) {
+        fetch(ph + 2, b2);
+        run(ph, b0);
+        if (ph + 1 >= nph) break;
+        fetch(ph + 3, b0);
+        run(ph + 1, b1);
+        if (ph + 2 >= nph) break;
+        fetch(ph + 4, b1);
+        run(ph + 2, b2);
+    }
+}
+
+template <typename T>
+static hipError_t up_sweep(const MgLevels &m, int mixed, const double *phi_in, double *phi_out,
+                           const double *f, hipStream_t st)
+{
+    const int n = m.nr - 1, blocks = (m.nzl[m.L] - 3) / 2;
+    if (blocks <= 0) return hipSuccess;
+    const size_t lds = up_lds(m, mixed);
+    if (n <= 64)
+        (void)launch<k_up_A<T, 1>, k_up_body<T, 1>, kUpThreads>(dim3(blocks), dim3(kUpThreads), lds, st, k_up_A<T, 1>{m, mixed, phi_in, phi_out, f});
+    else if (n <= 128)
+        (void)launch<k_up_A<T, 2>, k_up_body<T, 2>, kUpThreads>(dim3(blocks), dim3(kUpThreads), lds, st, k_up_A<T, 2>{m, mixed, phi_in, phi_out, f});
+    else if constexpr (sizeof(T) == 4)  // the FP64 split cycle takes lines of up to 128 unknowns
+        (void)launch<k_up_A<T, 4>, k_up_body<T, 4>, kUpThreads>(dim3(blocks), dim3(kUpThreads), lds, st, k_up_A<T, 4>{m, mixed, phi_in, phi_out, f});
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t mg_solve_block(const MgLevels &m, int mixed, double *phi, const double *f, double V,
                           int cycles, hipStream_t st)
 {
@@ -1733,7 +1997,12 @@ void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path)
     for (int l = 1; l <= (mixed ? m.L : m.L - 1); ++l) lds += 2 * (size_t)m.nzl[l] * m.nr * es;
     m.solve_lds = lds;
     const bool fits = n <= (mixed ? 256 : 128) && lds <= lds_budget && !m.long_lines;
-    m.split = fits && path == 0 && m.L > 1;
+    // the one-launch way up computes level sizes and table offsets in closed
+    // form (nz_l = 2^l + 1, first line 2^l - l - 1)
+    bool closed = true;
+    for (int l = 1; l <= m.L; ++l)
+        closed = closed && m.nzl[l] == (1 << l) + 1 && m.line_off[l] == (1 << l) - l - 1;
+    m.split = fits && path == 0 && m.L > 1 && up_lds(m, mixed) <= lds_budget && closed;
     m.one_block = fits && (path == 1 || (path == 0 && m.L == 1));
     // multi-launch path: levels of the bottom kernel
     m.K = 0;
@@ -1800,8 +2069,17 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
     // solve's first launch has done it for this cycle)
     if (!skip_down && (e = down(m, mixed, phi, f, st)) != hipSuccess) return e;
     if (m.split) {
-        // coarse levels in one workgroup from the restricted residuals, then
-        // the finest level's zebra sweep with pre-factored lines
+        // the way up in one launch: each block of the finest level's sweep
+        // with the coarse lines it depends on (up_sweep); or (split_coarse)
+        // the coarse levels in one workgroup, then the finest level's sweep
+        if (!m.split_coarse) {
+            if (mixed) return up_sweep<float>(m, mixed, phi, phi, f, st);
+            e = up_sweep<double>(m, mixed, phi, phi_alt, f, st);
+            double *t = phi;
+            phi = phi_alt;
+            phi_alt = t;
+            return e;
+        }
         if ((e = solve_block(m, mixed, phi, f, 0.0, 1, 1, st)) != hipSuccess) return e;
         if (mixed) return fine_sweep<float>(m, mixed, phi, phi, f, st);
         e = fine_sweep<double>(m, mixed, phi, phi_alt, f, st);

@@ -1175,6 +1175,11 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
             else if (!std::strcmp(e, "multi")) path = 2;
             else if (!std::strcmp(e, "long")) path = 3;
         }
+        // the split cycle's way up: one launch (default) or the coarse
+        // levels in one workgroup and then the finest level's sweep
+        // (RZPIC_MG_UP=coarse; the same values, for tests and measurements)
+        const char *ue = std::getenv("RZPIC_MG_UP");
+        m.split_coarse = ue && !std::strcmp(ue, "coarse") ? 1 : 0;
         mg_plan(m, c->mixed, c->lds_block, path);
     }
     if (m.one_block || m.split) {

@@ -143,6 +143,54 @@ def test_mixed_solve(mesh, path, monkeypatch):
     assert e <= 1e-10
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("mesh", [(33, 33), (129, 65), (100, 17), (200, 33), (257, 17), (65, 5),
+                                  (9, 9)])
+def test_split_one_launch_way_up_equals_coarse_workgroup(mesh, precision, monkeypatch):
+    """The split cycle's way up runs in one launch: each block of the finest
+    level's sweep first solves the few lines of every coarser level that its
+    own lines depend on (lines its neighbours solve too).  RZPIC_MG_UP=coarse
+    selects the two-launch form (the coarse levels in one workgroup, then the
+    finest sweep).  Both solve every line with the same table and arithmetic,
+    so phi agrees bitwise after 1 and 3 cycles; the default form also meets
+    the oracle (one, two and four unknowns per lane, ragged lines, two
+    levels)."""
+    nr, nz = mesh
+    if precision == "fp64" and nr - 1 > 128:
+        pytest.skip("the FP64 split cycle takes lines of up to 128 unknowns")
+    w = wl.Workload(name="t", nr=nr, nz=nz, R=0.02 * nr / 33, L=0.02 * (nz - 1) / 32,
+                    n_per_species=1, steps=1, V_dc=35.0)
+    chi = wl.smooth_chi(w, 1.0)
+    rho = wl.smooth_rho(w, 7, 2e-4)
+    phi0 = np.random.default_rng(11).uniform(-10.0, 10.0, (w.nz, w.nr))
+    for k in (1, 3):
+        got = {}
+        for form in ("one", "coarse"):
+            if form == "coarse":
+                monkeypatch.setenv("RZPIC_MG_UP", "coarse")
+            else:
+                monkeypatch.delenv("RZPIC_MG_UP", raising=False)
+            g = rzpic.Context(w, precision=precision, mg_fixed_cycles=k)
+            g.set_grid(rzpic.G_CHI, chi)
+            g.set_grid(rzpic.G_RHO, rho)
+            g.set_grid(rzpic.G_PHI, phi0)
+            g.solve(1e-9, want=False)
+            got[form] = g.grid(rzpic.G_PHI)
+            g.close()
+        np.testing.assert_array_equal(got["one"], got["coarse"])
+    monkeypatch.delenv("RZPIC_MG_UP", raising=False)
+    o, g = pair(w, precision=precision, mc=False, mg_fixed_cycles=3)
+    for ctx, G in ((o, rzo), (g, rzpic)):
+        ctx.set_grid(G.G_CHI, chi)
+        ctx.set_grid(G.G_RHO, rho)
+        ctx.set_grid(G.G_PHI, phi0)
+    o.solve(1e-9)
+    g.solve(1e-9)
+    e = rel_err(g.grid(rzpic.G_PHI), o.grid(rzo.G_PHI))
+    print(f"{precision} {nr}x{nz}, 3 cycles: phi error {e:.3e}")
+    assert e <= (TOL_GRID if precision == "mixed" else 1e-12)
+
+
 # 1001x513 has 1000-unknown r-lines on nine levels whose coarse lines are
 # nearly decoupled in z (h_z up to 0.16 m against h_r = 0.6 mm): the FP32
 # correction's line solves lose more there, and after one cycle from a
