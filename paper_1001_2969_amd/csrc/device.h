@@ -587,4 +587,35 @@ __device__ __forceinline__ void deposit4_at<float>(unsigned long long *acc, int 
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// FP32 particles into a 32-bit copy of the whole grid (a block's LDS copy):
+// the same int32 contributions as above, added to 32-bit accumulators.  Each
+// add returns the value it replaced, so an add that wraps past 2^32 (or, for
+// a negative contribution, below 0) is known exactly, and the 2^32 quanta it
+// carries go to the 64-bit accumulator of the same node in gacc.  The sum,
+// lo + carries 2^32, is the integer the 64-bit accumulators would hold.
+__device__ __forceinline__ void lds32_add(uint32_t *lo, unsigned long long *gacc, int g, int v)
+{
+    const uint32_t old =
+        __hip_atomic_fetch_add(lo + g, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t now = old + (uint32_t)v;
+    if (v >= 0 ? now < old : now > old)
+        atomicAdd(gacc + g, v >= 0 ? 0x100000000ull : 0xFFFFFFFF00000000ull);
+}
+
+__device__ __forceinline__ void deposit4_lds32(uint32_t *lo, unsigned long long *gacc, int g,
+                                               int stride, const W4<float> &q, double w,
+                                               double inv_quantum, int32_t *status)
+{
+    const float ws = (float)w * (float)inv_quantum;
+    if (!(fabsf(ws) < 0x1.8p30f)) atomicOr(status, kStNumeric);
+    const float a = q.sz0 * q.sr0, b = q.sz0 * q.sr1;
+    const float c = q.sz1 * q.sr0, d = q.sz1 * q.sr1;
+    const int qa = (int)__builtin_rintf(ws * a), qb = (int)__builtin_rintf(ws * b);
+    const int qc = (int)__builtin_rintf(ws * c), qd = (int)__builtin_rintf(ws * d);
+    lds32_add(lo, gacc, g, qa);
+    lds32_add(lo, gacc, g + 1, qb);
+    lds32_add(lo, gacc, g + stride, qc);
+    lds32_add(lo, gacc, g + stride + 1, qd);
+}
+
 }  // namespace rz

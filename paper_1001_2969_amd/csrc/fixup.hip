@@ -487,25 +487,30 @@ hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, cons
 
 // acc[g] += sum over blocks of the per-block LDS copies: block (x, y) sums
 // slices y, y + gridDim.y, ... of nodes [256x, 256x + 256) and adds the
-// (integer) partial sum atomically.
-__global__ __launch_bounds__(256) void k_reduce_slices(unsigned long long *acc,
-                                                       const unsigned long long *slices, int nb,
-                                                       int nn)
+// (integer) partial sum atomically.  narrow: 32-bit slice elements.
+__global__ __launch_bounds__(256) void k_reduce_slices(unsigned long long *acc, const void *slices,
+                                                       int narrow, int nb, int nn)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nn) return;
     unsigned long long s = 0;
-    for (int b = blockIdx.y; b < nb; b += gridDim.y) s += slices[(size_t)b * nn + g];
+    if (narrow) {
+        const uint32_t *sl = (const uint32_t *)slices;
+        for (int b = blockIdx.y; b < nb; b += gridDim.y) s += sl[(size_t)b * nn + g];
+    } else {
+        const unsigned long long *sl = (const unsigned long long *)slices;
+        for (int b = blockIdx.y; b < nb; b += gridDim.y) s += sl[(size_t)b * nn + g];
+    }
     atomicAdd(acc + g, s);
 }
 
-hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
+hipError_t launch_reduce_slices(unsigned long long *acc, const void *slices, int narrow, int nb,
                                 int nn, hipStream_t st)
 {
     int threads = 256;
     int bx = (nn + threads - 1) / threads;
     int by = nb < 32 ? nb : 32;
-    RZ_LAUNCH(k_reduce_slices, dim3(bx, by), dim3(threads), 0, st, acc, slices, nb, nn);
+    RZ_LAUNCH(k_reduce_slices, dim3(bx, by), dim3(threads), 0, st, acc, slices, narrow, nb, nn);
     return hipGetLastError();
 }
 

@@ -145,7 +145,8 @@ template <typename T> struct PassArgs {
     const typename Vec2<T>::type *E2;
     unsigned long long *acc;      // deposit of species s (global)
     unsigned long long *acc_ion;  // deposit of new ions (global)
-    unsigned long long *slices;   // per-block LDS flush [gridDim][nn]
+    void *slices;                 // per-block LDS flush [gridDim][nn]: 32-bit elements
+                                  //    for FP32 particles, 64-bit for FP64
     unsigned long long *tally;    // [3] absorbed weight of species s, fixed point
     unsigned long long *tally_ion;
     unsigned long long *mcstat;   // [1 + kMaxProc] candidates, events per process
@@ -180,9 +181,10 @@ __host__ __device__ inline int64_t tiled_q2(int64_t nch, int nb, int64_t q)
 // every by-th slice.
 struct SliceSum {
     unsigned long long *acc[2];
-    const unsigned long long *slices[2];
+    const void *slices[2];
     int nb[2];
     int nn, bx, by;
+    int narrow;  // 32-bit slice elements (FP32 particles)
 };
 
 // Host-side launchers (defined in the .hip files).
@@ -194,6 +196,9 @@ hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, 
                         int threads, size_t lds, hipStream_t st);
 // Resident blocks per CU of the tiled merged pass (register and LDS limits).
 template <typename T> int pass2_tiled_blocks_per_cu(int threads);
+// Resident blocks per CU of the merged pass with a whole-grid LDS copy of
+// `lds` bytes (register and LDS limits).
+template <typename T> int pass2_lds_blocks_per_cu(int threads, size_t lds);
 template <typename T>
 hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0, int c1,
                            int threads, hipStream_t st);
@@ -253,7 +258,7 @@ hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, cons
                          hipStream_t st);
 // The slice sum of a merged step on its own (blockDim 256; r.bx * 256 >= nn).
 hipError_t launch_slice_sum(const SliceSum &r, hipStream_t st);
-hipError_t launch_reduce_slices(unsigned long long *acc, const unsigned long long *slices, int nb,
+hipError_t launch_reduce_slices(unsigned long long *acc, const void *slices, int narrow, int nb,
                                 int nn, hipStream_t st);
 
 // sort.hip: stable counting sort of a species by tile of the cell of each

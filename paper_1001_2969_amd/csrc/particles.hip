@@ -205,6 +205,9 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
     constexpr bool kTile = (MODE & M_TILE) != 0;
     constexpr bool kDep = (MODE & M_DEP) != 0;
     constexpr bool kMc = (MODE & M_MC) != 0;
+    // FP32 particles deposit into a 32-bit LDS grid (deposit4_lds32)
+    constexpr bool kNarrow = kLds && std::is_same<T, float>::value;
+    uint32_t *const lds32 = (uint32_t *)lds_acc;
     const bool mc_on = kMc && a.sp.mc_model != 0;
     unsigned long long *dep = a.acc;
 
@@ -215,7 +218,10 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
     }
     if (a.psteps && lb == 0 && threadIdx.x == 0) atomicAdd(a.psteps, (unsigned long long)n);
     if (kLds) {
-        for (int g = threadIdx.x; g < m.nn; g += blockDim.x) lds_acc[g] = 0;
+        if (kNarrow)
+            for (int g = threadIdx.x; g < m.nn; g += blockDim.x) lds32[g] = 0;
+        else
+            for (int g = threadIdx.x; g < m.nn; g += blockDim.x) lds_acc[g] = 0;
         dep = lds_acc;
     }
     // tiled form: planned chunks per block and this block's window
@@ -323,6 +329,9 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
                                    a.sp.inv_quantum, a.status);
                 else
                     deposit4<T>(a.acc, m, w4, (double)s.w, a.sp.inv_quantum, a.status);
+            } else if constexpr (kNarrow) {
+                deposit4_lds32(lds32, a.acc, w4.g, m.nr, w4, (double)s.w, a.sp.inv_quantum,
+                               a.status);
             } else {
                 deposit4<T>(dep, m, w4, (double)s.w, a.sp.inv_quantum, a.status);
             }
@@ -426,8 +435,13 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
     }
     if (kLds) {
         __syncthreads();
-        unsigned long long *out = a.slices + (size_t)lb * m.nn;
-        for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds_acc[g];
+        if (kNarrow) {
+            uint32_t *out = (uint32_t *)a.slices + (size_t)lb * m.nn;
+            for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds32[g];
+        } else {
+            unsigned long long *out = (unsigned long long *)a.slices + (size_t)lb * m.nn;
+            for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds_acc[g];
+        }
     }
     if (kTile) {
         __syncthreads();
@@ -586,7 +600,7 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
     if (threadIdx.x >= 1 && threadIdx.x < 1 + kMaxProc && sh_stat[threadIdx.x])
         atomicAdd(a.mcstat + threadIdx.x, sh_stat[threadIdx.x]);
     if (kLds) {
-        unsigned long long *out = a.slices + (size_t)lb * m.nn;
+        unsigned long long *out = (unsigned long long *)a.slices + (size_t)lb * m.nn;
         for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds_acc[g];
     }
 }
@@ -622,9 +636,14 @@ __device__ __forceinline__ void slice_sum_body(const Blk &k, const SliceSum &r)
     const int s = k.x / per, x = k.x % r.bx, y = (k.x % per) / r.bx;
     const int g = x * blockDim.x + threadIdx.x;
     if (g >= r.nn) return;
-    const unsigned long long *sl = r.slices[s];
     unsigned long long sum = 0;
-    for (int q = y; q < r.nb[s]; q += r.by) sum += sl[(size_t)q * r.nn + g];
+    if (r.narrow) {
+        const uint32_t *sl = (const uint32_t *)r.slices[s];
+        for (int q = y; q < r.nb[s]; q += r.by) sum += sl[(size_t)q * r.nn + g];
+    } else {
+        const unsigned long long *sl = (const unsigned long long *)r.slices[s];
+        for (int q = y; q < r.nb[s]; q += r.by) sum += sl[(size_t)q * r.nn + g];
+    }
     atomicAdd(r.acc[s] + g, sum);
 }
 
@@ -804,8 +823,19 @@ hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0,
         dim3(c0 + c1), dim3(threads), 0, st, Collide2Args<T>{a0, a1, c0, c1});
 }
 
+template <typename T> int pass2_lds_blocks_per_cu(int threads, size_t lds)
+{
+    constexpr int kMode = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS;
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, k_one<Pass2Args<T>, pass2_body<T, kMode>, 1024>, threads, lds);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
 template int pass2_tiled_blocks_per_cu<double>(int);
 template int pass2_tiled_blocks_per_cu<float>(int);
+template int pass2_lds_blocks_per_cu<double>(int, size_t);
+template int pass2_lds_blocks_per_cu<float>(int, size_t);
 template hipError_t launch_pass2<double>(int, const PassArgs<double> &, const PassArgs<double> &,
                                          int, int, int, size_t, hipStream_t);
 template hipError_t launch_pass2<float>(int, const PassArgs<float> &, const PassArgs<float> &, int,

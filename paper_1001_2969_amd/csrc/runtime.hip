@@ -223,6 +223,10 @@ template <typename T> PassArgs<T> pass_args(rzpic_ctx *c, int s, uint32_t step)
 // (8192 unless tuned) particles of capacity, since every block of a deposit
 // form pays a fixed cost (zeroing and writing out its LDS grid or window)
 // that only pays off over enough particles.
+// Bytes of one node of a block's LDS deposit grid (and of its slice): FP32
+// particles accumulate in 32 bits with carries to the global grid.
+template <typename T> constexpr size_t lds_elem() { return sizeof(T) == 4 ? 4 : 8; }
+
 int pass_blocks(const rzpic_ctx *c, int s, int most)
 {
     const int64_t ppb = c->parts_per_block;
@@ -300,7 +304,7 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
     size_t lds = 0;
     if ((mode & M_DEP) && c->lds_ok) {
         mode |= M_LDS;
-        lds = (size_t)c->nn * sizeof(unsigned long long);
+        lds = (size_t)c->nn * lds_elem<T>();
         blocks = pass_blocks(c, s, c->slice_blocks);
     } else if ((mode & M_DEP) && !(mode & M_MC)) {
         mode |= M_TILE;
@@ -319,7 +323,8 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
     if (blocks * (threads / 64) > kMaxWaves)
         return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", blocks * threads / 64, kMaxWaves);
     HIPCHK(launch_pass<T>(mode, a, blocks, threads, lds, c->st));
-    if (mode & M_LDS) HIPCHK(launch_reduce_slices(c->acc[s], c->slices, blocks, c->nn, c->st));
+    if (mode & M_LDS)
+        HIPCHK(launch_reduce_slices(c->acc[s], c->slices, lds_elem<T>() == 4, blocks, c->nn, c->st));
     if (mc) {
         // candidates: outcome, and in the merged form their first push and deposit
         const bool merged = (mode & M_FIRST) != 0;
@@ -327,7 +332,8 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
         const double expect = c->sp[s].p_null * (double)c->sp[s].cap;
         int cblocks = c->cus * 2, cthreads = 256;
         size_t clds = 0;
-        if (merged && c->lds_ok && expect > 65536.0) {
+        if (merged && c->lds_ok && expect > 65536.0 &&
+            (size_t)c->nn * sizeof(unsigned long long) + 1024 <= c->lds_block) {
             // few blocks: each flushes a whole grid copy
             cmode |= M_LDS;
             clds = (size_t)c->nn * sizeof(unsigned long long);
@@ -341,7 +347,8 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
             cblocks = c->cus / 4 > 0 ? c->cus / 4 : 1;
         }
         HIPCHK(launch_collide<T>(cmode, a, cblocks, cthreads, clds, c->st));
-        if (cmode & M_LDS) HIPCHK(launch_reduce_slices(c->acc[s], c->slices, cblocks, c->nn, c->st));
+        if (cmode & M_LDS)
+            HIPCHK(launch_reduce_slices(c->acc[s], c->slices, 0, cblocks, c->nn, c->st));
     }
     return RZPIC_OK;
 }
@@ -361,7 +368,7 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
     size_t lds = 0;
     if (c->lds_ok) {
         mode |= M_LDS;
-        lds = (size_t)c->nn * sizeof(unsigned long long);
+        lds = (size_t)c->nn * lds_elem<T>();
         b[0] = pass_blocks(c, 0, c->slice_blocks / 2);
         b[1] = pass_blocks(c, 1, c->slice_blocks - c->slice_blocks / 2);
         if (!ions) {  // the electrons take the ions' blocks too
@@ -382,7 +389,7 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         a[s].bucket_waves = threads / 64;
         a[s].tiled = (mode & M_TILE) ? 1 : 0;
     }
-    a[1].slices = c->slices + (size_t)b[0] * c->nn;
+    a[1].slices = (char *)c->slices + (size_t)b[0] * c->nn * lds_elem<T>();
     if ((b[0] + b[1]) * (threads / 64) > kMaxWaves)
         return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", (b[0] + b[1]) * threads / 64,
                     kMaxWaves);
@@ -408,6 +415,7 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
             r.nb[s] = b[s];
         }
         r.nn = c->nn;
+        r.narrow = lds_elem<T>() == 4;
         r.bx = (c->nn + cthreads - 1) / cthreads;
         const int nb = b[0] > b[1] ? b[0] : b[1];
         r.by = nb < 32 ? nb : 32;
@@ -1107,13 +1115,17 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         A(c->circ, 1)
     }
     // LDS privatisation of the whole deposit grid when it fits.
-    const size_t lds_need = nn * sizeof(unsigned long long) + 1024;
+    // (32-bit elements for FP32 particles, see deposit4_lds32)
+    const size_t lds_need = nn * (c->mixed ? sizeof(uint32_t) : sizeof(unsigned long long)) + 1024;
     if (lds_need <= c->lds_block && !std::getenv("RZPIC_NO_LDS")) {
         // blocks per CU: as many as LDS allows up to the 32-wave limit
         int per_cu = (int)(c->lds_cu / lds_need);
         int wave_cap = 2048 / c->pass_threads;
+        const int occ = c->mixed ? pass2_lds_blocks_per_cu<float>(c->pass_threads, lds_need - 1024)
+                                 : pass2_lds_blocks_per_cu<double>(c->pass_threads, lds_need - 1024);
         if (per_cu < 1) per_cu = 1;
         if (per_cu > wave_cap) per_cu = wave_cap;
+        if (per_cu > occ) per_cu = occ;
         c->slice_blocks = c->cus * per_cu;
         if (const char *e = std::getenv("RZPIC_SLICE_BLOCKS")) {
             int b = std::atoi(e);
