@@ -117,14 +117,36 @@ def test_large_mesh_mixed():
 
 def test_adjoint_window_fullsize():
     """The gradient window at full size (257x129, 4M particles per species,
-    50 steps checkpointed every 10, tile sort every 10 steps): dJ/dV_rf against the central difference
-    of the HIP forward window with a relative step of 1e-6 (a smaller one if
-    that step changes which particles are absorbed), and dJ/dV_dc, dJ/dV_rf
-    and the density gradient finite."""
+    50 steps checkpointed every 10, tile sort every 10 steps), each gradient
+    against the central difference of the HIP forward window:
+    - dJ/dV_rf, with a relative step of 1e-6 (a smaller one if that step
+      changes which particles are absorbed);
+    - dJ/dpsi along a smooth psi (cos(2 r / R) sin(3 z / L) + 0.3 on the
+      nodes): the starting weights scaled by 1 + h psi(x_p), psi interpolated
+      with the deposit's node weights, the density deposited again, and the
+      window run; the gradient's projection sum(dJ/dpsi psi) is compared.
+    Both to 1e-5 relative; dJ/dV_dc finite."""
+    import torch
+
     w = wl.adjoint_257x129()
     delta = 2 * w.L / (w.nz - 1)
+    rr = np.linspace(0.0, w.R, w.nr)[None, :]
+    zz = np.linspace(0.0, w.L, w.nz)[:, None]
+    psi = np.cos(2.0 * rr / w.R) * np.sin(3.0 * zz / w.L) + 0.3
+    psi_t = torch.as_tensor(psi.reshape(-1), dtype=torch.float64, device="cuda:0")
+    hr, hz = w.R / (w.nr - 1), w.L / (w.nz - 1)
 
-    def start(V_rf):
+    def psi_at(r, z):
+        # the node weights of the deposit (z linear, r^2 radial)
+        i = torch.clamp(torch.floor(z / hz).long(), 0, w.nz - 2)
+        j = torch.clamp(torch.floor(r / hr).long(), 0, w.nr - 2)
+        tz = (z - i * hz) / hz
+        tr = ((r / hr) ** 2 - (j * j).double()) / (2 * j + 1).double()
+        g = i * w.nr + j
+        return ((1 - tz) * (1 - tr) * psi_t[g] + (1 - tz) * tr * psi_t[g + 1] +
+                tz * (1 - tr) * psi_t[g + w.nr] + tz * tr * psi_t[g + w.nr + 1])
+
+    def start(V_rf, h=0.0):
         g = rzpic.make_context(w.replace(V_rf=V_rf), precision="fp64", with_xsec=False,
                                capacity_factor=1.25)
         for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
@@ -132,7 +154,30 @@ def test_adjoint_window_fullsize():
         g.prologue()
         for s in (0, 1):
             g.sort(s)
+        if h:
+            g.sync()
+            for s in (0, 1):
+                n = g.count(s)[0]
+                a = g.arrays[s]
+                a["w"][:n] *= 1.0 + h * psi_at(a["r"][:n], a["z"][:n])
+            torch.cuda.synchronize()
+            g.deposit()
         return g
+
+    def window(V_rf, h=0.0):
+        gg = start(V_rf, h)
+        a = rzpic.Adjoint(gg, w.steps, checkpoint_every=10, delta=delta)
+        J = a.forward(0)
+        counts = (gg.count(0)[0], gg.count(1)[0])
+        a.close()
+        return J, counts
+
+    def central(f, steps):
+        for h in steps:
+            (jp, cp), (jm, cm) = f(h), f(-h)
+            if cp == cm:
+                return (jp - jm) / (2 * h)
+        raise AssertionError("every step changed the absorbed set")
 
     g = start(w.V_rf)
     adj = rzpic.Adjoint(g, w.steps, checkpoint_every=10, delta=delta)
@@ -140,21 +185,12 @@ def test_adjoint_window_fullsize():
     dvdc, dvrf, gw, gd = adj.backward(density=True)
     adj.close()
     del adj, g
-    assert np.isfinite([J, dvdc, dvrf]).all() and np.isfinite(gd.cpu().numpy()).all()
-    fd = None
-    for rel in (1e-6, 1e-7):
-        h = rel * w.V_rf
-        Js, counts = [], []
-        for v in (w.V_rf + h, w.V_rf - h):
-            gg = start(v)
-            a = rzpic.Adjoint(gg, w.steps, checkpoint_every=10, delta=delta)
-            Js.append(a.forward(0))
-            counts.append((gg.count(0)[0], gg.count(1)[0]))
-            a.close()
-            del a, gg
-        if counts[0] == counts[1]:
-            fd = (Js[0] - Js[1]) / (2 * h)
-            break
-    assert fd is not None, "every step changed the absorbed set"
+    gd = gd.cpu().numpy()
+    assert np.isfinite([J, dvdc, dvrf]).all() and np.isfinite(gd).all()
+    fd = central(lambda h: window(w.V_rf + h), (1e-6 * w.V_rf, 1e-7 * w.V_rf))
     print("257x129 J", J, "dJ/dV_rf", dvrf, "differences", fd, "dJ/dV_dc", dvdc)
     assert abs(dvrf - fd) <= 1e-5 * abs(fd), (dvrf, fd)
+    fd_psi = central(lambda h: window(w.V_rf, h), (1e-6, 1e-7))
+    ad_psi = float(np.sum(gd.reshape(-1) * psi.reshape(-1)))
+    print("257x129 dJ/dpsi along psi", ad_psi, "differences", fd_psi)
+    assert abs(ad_psi - fd_psi) <= 1e-5 * abs(fd_psi), (ad_psi, fd_psi)
