@@ -496,7 +496,8 @@ __global__ __launch_bounds__(256) void k_reduce_slices(unsigned long long *acc, 
     unsigned long long s = 0;
     if (narrow) {
         const uint32_t *sl = (const uint32_t *)slices;
-        for (int b = blockIdx.y; b < nb; b += gridDim.y) s += sl[(size_t)b * nn + g];
+        const size_t stride = slice_stride(nn, 1);
+        for (int b = blockIdx.y; b < nb; b += gridDim.y) s += sl[(size_t)b * stride + g];
     } else {
         const unsigned long long *sl = (const unsigned long long *)slices;
         for (int b = blockIdx.y; b < nb; b += gridDim.y) s += sl[(size_t)b * nn + g];

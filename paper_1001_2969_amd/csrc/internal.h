@@ -175,10 +175,20 @@ __host__ __device__ inline int64_t tiled_q2(int64_t nch, int nb, int64_t q)
     return rem > 0 ? (rem + nb - 1) / nb : 0;
 }
 
+// Elements between consecutive slices: whole groups of four for 32-bit
+// elements (16-byte loads in the slice sum), nn for 64-bit ones.
+__host__ __device__ inline size_t slice_stride(int nn, int narrow)
+{
+    return narrow ? ((size_t)nn + 3) & ~(size_t)3 : (size_t)nn;
+}
+
 // Sum of per-block LDS deposit slices into the deposit grids of both
-// species (launch_slice_sum): block b of the 2 * bx * by blocks takes
-// species b / (bx by), nodes of column block b % bx (256 per block) and
-// every by-th slice.
+// species (launch_slice_sum).  64-bit slices: block b of the 2 * bx * by
+// blocks takes species b / (bx by), nodes of column block b % bx (256 per
+// block) and every by-th slice.  32-bit slices (narrow): block b of the
+// 2 * bx blocks takes species b / bx and 4 kSliceSumGroups nodes, all slices.
+constexpr int kSliceSumGroups = 8;
+
 struct SliceSum {
     unsigned long long *acc[2];
     const void *slices[2];

@@ -436,7 +436,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
     if (kLds) {
         __syncthreads();
         if (kNarrow) {
-            uint32_t *out = (uint32_t *)a.slices + (size_t)lb * m.nn;
+            uint32_t *out = (uint32_t *)a.slices + (size_t)lb * slice_stride(m.nn, 1);
             for (int g = threadIdx.x; g < m.nn; g += blockDim.x) out[g] = lds32[g];
         } else {
             unsigned long long *out = (unsigned long long *)a.slices + (size_t)lb * m.nn;
@@ -632,24 +632,68 @@ template <typename T, int MODE> __device__ __forceinline__ void collide2_body(co
 // many discharges in one launch.
 __device__ __forceinline__ void slice_sum_body(const Blk &k, const SliceSum &r)
 {
+    if (r.narrow) {
+        // 32-bit slices: block x of species s takes nodes [32 x', 32 x' + 32)
+        // (x' = x mod bx) as 8 groups of four; its 256 threads are 8 groups
+        // x 32 parts, part p summing slices p, p + 32, ... of its group with
+        // 16-byte loads (slices padded to whole groups, slice_stride), up to
+        // twelve in flight; the parts are added in LDS and each node gets one
+        // atomic.
+        constexpr int G = kSliceSumGroups, P = 256 / G, U = 12;
+        __shared__ unsigned long long part[P][G][4];
+        const int s = k.x / r.bx, x = k.x % r.bx;
+        const int grp = threadIdx.x % G, p = threadIdx.x / G;
+        const int g4 = x * G + grp, g = 4 * g4;
+        const int nb = r.nb[s];
+        unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        if (g < r.nn) {
+            const size_t stride = slice_stride(r.nn, 1) / 4;
+            const uint4 *sl = (const uint4 *)r.slices[s] + g4;
+            for (int q = p; q < nb; q += U * P) {
+                uint4 v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int qq = q + P * u;
+                    v[u] = sl[(size_t)(qq < nb ? qq : nb - 1) * stride];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (q + P * u >= nb) break;
+                    s0 += v[u].x;
+                    s1 += v[u].y;
+                    s2 += v[u].z;
+                    s3 += v[u].w;
+                }
+            }
+        }
+        part[p][grp][0] = s0;
+        part[p][grp][1] = s1;
+        part[p][grp][2] = s2;
+        part[p][grp][3] = s3;
+        __syncthreads();
+        if (threadIdx.x < 4 * G) {
+            const int gg = threadIdx.x >> 2, c = threadIdx.x & 3, node = 4 * (x * G + gg) + c;
+            unsigned long long t = 0;
+#pragma unroll
+            for (int q = 0; q < P; ++q) t += part[q][gg][c];
+            if (node < r.nn) atomicAdd(r.acc[s] + node, t);
+        }
+        return;
+    }
     const int per = r.bx * r.by;
     const int s = k.x / per, x = k.x % r.bx, y = (k.x % per) / r.bx;
     const int g = x * blockDim.x + threadIdx.x;
     if (g >= r.nn) return;
+    const unsigned long long *sl = (const unsigned long long *)r.slices[s];
     unsigned long long sum = 0;
-    if (r.narrow) {
-        const uint32_t *sl = (const uint32_t *)r.slices[s];
-        for (int q = y; q < r.nb[s]; q += r.by) sum += sl[(size_t)q * r.nn + g];
-    } else {
-        const unsigned long long *sl = (const unsigned long long *)r.slices[s];
-        for (int q = y; q < r.nb[s]; q += r.by) sum += sl[(size_t)q * r.nn + g];
-    }
+    for (int q = y; q < r.nb[s]; q += r.by) sum += sl[(size_t)q * r.nn + g];
     atomicAdd(r.acc[s] + g, sum);
 }
 
 hipError_t launch_slice_sum(const SliceSum &r, hipStream_t st)
 {
-    return launch<SliceSum, slice_sum_body, 256>(dim3(2 * r.bx * r.by), dim3(256), 0, st, r);
+    const int blocks = r.narrow ? 2 * r.bx : 2 * r.bx * r.by;
+    return launch<SliceSum, slice_sum_body, 256>(dim3(blocks), dim3(256), 0, st, r);
 }
 
 // Staged new particles of species cs (unmerged form): first push or deposit

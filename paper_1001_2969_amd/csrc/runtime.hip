@@ -389,7 +389,7 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         a[s].bucket_waves = threads / 64;
         a[s].tiled = (mode & M_TILE) ? 1 : 0;
     }
-    a[1].slices = (char *)c->slices + (size_t)b[0] * c->nn * lds_elem<T>();
+    a[1].slices = (char *)c->slices + (size_t)b[0] * slice_stride(c->nn, lds_elem<T>() == 4) * lds_elem<T>();
     if ((b[0] + b[1]) * (threads / 64) > kMaxWaves)
         return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", (b[0] + b[1]) * threads / 64,
                     kMaxWaves);
@@ -416,9 +416,12 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         }
         r.nn = c->nn;
         r.narrow = lds_elem<T>() == 4;
-        r.bx = (c->nn + cthreads - 1) / cthreads;
+        // 32-bit slices: 4 kSliceSumGroups nodes per block (slice_sum_body);
+        // 64-bit: 256 nodes per block, the slices split over by blocks
+        const int per_block = r.narrow ? 4 * kSliceSumGroups : cthreads;
+        r.bx = (c->nn + per_block - 1) / per_block;
         const int nb = b[0] > b[1] ? b[0] : b[1];
-        r.by = nb < 32 ? nb : 32;
+        r.by = r.narrow ? 1 : nb < 32 ? nb : 32;
     }
     // the collisions, then (whole-grid LDS form) the slice sum in a kernel
     // of its own: in one launch the slice-sum blocks would run at the
