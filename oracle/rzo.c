@@ -167,6 +167,10 @@ rzo *rzo_create(const rzo_config *cfg)
     if (cfg->sort_every < 0 || (cfg->sort_every > 0 && (cfg->tile_z < 1 || cfg->tile_r < 1)))
         return NULL;
     if (!(cfg->circuit_C >= 0.0)) return NULL;
+    if (cfg->damping != RZO_DAMP_D1 && cfg->damping != RZO_DAMP_FRIEDMAN) return NULL;
+    if (cfg->damping == RZO_DAMP_FRIEDMAN &&
+        (cfg->push_form != RZO_PUSH_LOCAL || !(cfg->theta >= 0.0 && cfg->theta <= 1.0)))
+        return NULL;
     rzo *o = (rzo *)calloc(1, sizeof(rzo));
     if (!o) return NULL;
     o->c = *cfg;
@@ -515,7 +519,12 @@ static void finalize_ions(rzo *o, int ions)
             double q = o->sp[s].q, m = o->sp[s].m;
             double dt = dt_of(o, &o->sp[s]);
             rho += q * n;
-            if (s == 0 || ions) chi += q * q * n * dt * dt / (2.0 * m * EPS0);
+            if (s == 0 || ions) {
+                double x = q * q * n * dt * dt / (2.0 * m * EPS0);
+                /* Friedman: implicit coefficient theta/2 instead of 1/2 */
+                if (o->c.damping == RZO_DAMP_FRIEDMAN) x *= o->c.theta;
+                chi += x;
+            }
         }
         o->rho[g] = rho;
         o->chi[g] = chi;
@@ -560,11 +569,13 @@ static int first_push_one(rzo *o, species *sp, int64_t p)
 {
     double dt = dt_of(o, sp);
     const int xyz = o->c.push_form == RZO_PUSH_XYZ;
-    double vx = sp->vr[p] + 0.5 * sp->ar[p] * dt;
+    /* the known part of abar_n: abar_{n-1}/2 (D1), B (Friedman) */
+    const double kn = o->c.damping == RZO_DAMP_FRIEDMAN ? 1.0 : 0.5;
+    double vx = sp->vr[p] + kn * sp->ar[p] * dt;
     double vy = xyz ? sp->vt[p] + 0.5 * sp->at[p] * dt : sp->vt[p];
     double x = sp->r[p] + vx * dt;
     double y = vy * dt;
-    double vz = sp->vz[p] + 0.5 * sp->az[p] * dt;
+    double vz = sp->vz[p] + kn * sp->az[p] * dt;
     double z = sp->z[p] + vz * dt;
     double rn = sqrt(x * x + y * y);
     double c = 1.0, s = 0.0;
@@ -597,6 +608,31 @@ static int final_push_one(rzo *o, species *sp, int64_t p)
     double Er, Ez;
     gather(o, sp->r[p], sp->z[p], &Er, &Ez);
     double aEr = qm * Er, aEz = qm * Ez;
+    if (o->c.damping == RZO_DAMP_FRIEDMAN) {
+        /* x += (theta/2) a dt^2, v += (theta/2) a dt; abar_n = (theta/2) a
+         * + B; the next step's known part
+         * B' = (1 - theta/2) ((1 - theta/2) a + (theta/2) abar_n) */
+        const double c = 0.5 * o->c.theta, c1 = 1.0 - c;
+        double r = sp->r[p] + c * aEr * dt * dt;
+        double z = sp->z[p] + c * aEz * dt * dt;
+        double vr = sp->vr[p] + c * aEr * dt;
+        double vz = sp->vz[p] + c * aEz * dt;
+        const double abr = c * aEr + sp->ar[p], abz = c * aEz + sp->az[p];
+        double br = c1 * (c1 * aEr + c * abr);
+        double bz = c1 * (c1 * aEz + c * abz);
+        if (r < 0.0) { /* the axis rule of the D1 push */
+            r = -r;
+            vr = fabs(vr);
+            br = fabs(br);
+        }
+        sp->r[p] = r;
+        sp->z[p] = z;
+        sp->vr[p] = vr;
+        sp->vz[p] = vz;
+        sp->ar[p] = br;
+        sp->az[p] = bz;
+        return absorb(o, sp, p);
+    }
     double r = sp->r[p] + 0.5 * aEr * dt * dt;
     double z = sp->z[p] + 0.5 * aEz * dt * dt;
     double vr = sp->vr[p] + 0.5 * aEr * dt;

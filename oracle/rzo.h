@@ -72,9 +72,20 @@ typedef struct {
                               * dropped) or RZO_PUSH_XYZ (the global X-Y-Z push) */
     int32_t resize_mode;     /* RZO_RESIZE_SPLIT (weight-conserving split) or
                               * RZO_RESIZE_ZERO_ORDER (particle-based, Sec. 2.2) */
-    int32_t reserved;
+    int32_t damping;         /* RZO_DAMP_D1 (Sec. 2.1) or RZO_DAMP_FRIEDMAN       */
+    double theta;            /* RZO_DAMP_FRIEDMAN: damping parameter in [0, 1]  */
 } rzo_config;
 enum { RZO_PUSH_LOCAL = 0, RZO_PUSH_XYZ = 1 };
+/* Time-averaged acceleration of the implicit push.  D1 (Sec. 2.1):
+ * abar_n = (a_{n+1} + abar_{n-1}) / 2.  FRIEDMAN, the adjustable damping of
+ * A. Friedman, J. Comput. Phys. 90 (1990) 292, as read here:
+ *   abar_n = (theta/2) a_{n+1}
+ *          + (1 - theta/2) [(1 - theta/2) a_n + (theta/2) abar_{n-1}],
+ * leapfrog for theta = 0, the implicit coefficient of a_{n+1} (and with it
+ * chi) theta/2 instead of 1/2.  The particle then carries the known part
+ * B = abar_n - (theta/2) a_{n+1} in place of abar (ar, az), a_n being the
+ * acceleration of the final push that ends step n-1.  Local push only. */
+enum { RZO_DAMP_D1 = 0, RZO_DAMP_FRIEDMAN = 1 };
 enum { RZO_RESIZE_SPLIT = 0, RZO_RESIZE_ZERO_ORDER = 1 };
 
 rzo *rzo_create(const rzo_config *cfg);

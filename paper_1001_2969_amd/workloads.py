@@ -31,6 +31,7 @@ SPECIES_M = (M_ELECTRON, M_ARGON)
 MC_NONE, MC_ELECTRON, MC_ION = 0, 1, 2
 P_ELASTIC, P_EXCITATION, P_IONIZATION = 0, 1, 2
 W_ZR2, W_ZR = 0, 1
+DAMP_D1, DAMP_FRIEDMAN = 0, 1
 PUSH_LOCAL, PUSH_XYZ = 0, 1
 RESIZE_SPLIT, RESIZE_ZERO_ORDER = 0, 1
 FACE_AVG, FACE_MAX = 0, 1
@@ -75,6 +76,8 @@ class Workload:
     ion_subcycle: int = 0  # K >= 2: ions move every K-th step with K dt
     push_form: int = 0  # PUSH_LOCAL (Sec. 2.3 local X-Y push) or PUSH_XYZ (global X-Y-Z)
     resize_mode: int = 0  # RESIZE_SPLIT (weight-conserving) or RESIZE_ZERO_ORDER (particle-based)
+    damping: int = 0  # DAMP_D1 (Sec. 2.1) or DAMP_FRIEDMAN (adjustable damping, parameter theta)
+    theta: float = 1.0  # DAMP_FRIEDMAN: damping parameter in [0, 1] (0: leapfrog)
 
     @property
     def n_gas(self) -> float:
