@@ -67,6 +67,19 @@ enum { RZPIC_PUSH_LOCAL = 0, RZPIC_PUSH_XYZ = 1 };
  * order and are appended, then the array is compacted (rzpic_resize alone
  * keys its draws by step 0). */
 enum { RZPIC_RESIZE_SPLIT = 0, RZPIC_RESIZE_ZERO_ORDER = 1 };
+/* Time-averaged acceleration of the implicit push.  RZPIC_DAMP_D1: the D1
+ * scheme of Sec. 2.1, abar_n = (a_{n+1} + abar_{n-1}) / 2.
+ * RZPIC_DAMP_FRIEDMAN: the adjustable damping of A. Friedman, J. Comput.
+ * Phys. 90 (1990) 292 (cited in the discussion of Sec. 4), read as
+ *   abar_n = (theta/2) a_{n+1}
+ *          + (1 - theta/2) [(1 - theta/2) a_n + (theta/2) abar_{n-1}]
+ * with 0 <= theta <= 1: leapfrog at theta = 0, more damping of the fast
+ * oscillations as theta grows.  The implicit coefficient of a_{n+1} (and so
+ * chi) is theta/2 instead of 1/2, and the species views' ar, az hold the
+ * known part B = abar_n - (theta/2) a_{n+1} of the next step instead of
+ * abar (zero at initialisation, as abar).  Local push only; the gradient
+ * window (rzpic_adjoint_*) takes D1. */
+enum { RZPIC_DAMP_D1 = 0, RZPIC_DAMP_FRIEDMAN = 1 };
 enum { RZPIC_P_ELASTIC = 0, RZPIC_P_EXCITATION = 1, RZPIC_P_IONIZATION = 2 };
 /* Grid selectors of rzpic_grid_copy.  N0/N1 are the deposited physical
  * particle counts N_ij of Sec. 2.4 (kept internally in fixed point). */
@@ -125,7 +138,8 @@ typedef struct rzpic_config {
                                * the ions move. */
     int32_t push_form;        /* RZPIC_PUSH_LOCAL (0) or RZPIC_PUSH_XYZ        */
     int32_t resize_mode;      /* RZPIC_RESIZE_SPLIT (0) or RZPIC_RESIZE_ZERO_ORDER */
-    int32_t reserved2;
+    int32_t damping;          /* RZPIC_DAMP_D1 (0) or RZPIC_DAMP_FRIEDMAN       */
+    double theta;             /* RZPIC_DAMP_FRIEDMAN: damping parameter in [0, 1] */
 } rzpic_config;
 
 typedef struct rzpic_species_view {

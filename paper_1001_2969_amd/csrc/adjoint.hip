@@ -641,6 +641,8 @@ rzpic_status check_ctx(const rzpic_ctx *c)
                        "adjoint: the field solves must be converged (mg_fixed_cycles = 0)");
     if (c->c.chi_face != RZPIC_FACE_AVG)
         return rz_fail(RZPIC_EINVAL, "adjoint: needs the averaged face permittivity");
+    if (c->c.damping != RZPIC_DAMP_D1)
+        return rz_fail(RZPIC_EINVAL, "adjoint: the window differentiates the D1 push");
     if (c->c.circuit_C > 0.0)
         return rz_fail(RZPIC_EINVAL, "adjoint: the electrode must be driven directly (circuit_C = 0)");
     if (c->c.ion_subcycle > 1)

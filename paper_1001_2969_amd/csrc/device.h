@@ -459,9 +459,24 @@ __device__ __forceinline__ double finalize_node(const GridArgs &g, int k)
     g.dens1[k] = n1;
     double rho = 0.0, chi = 0.0;
     rho += g.q0 * n0;
-    chi += g.q0 * g.q0 * n0 * g.dt * g.dt / (2.0 * g.m0 * kEps0);
+    if (g.friedman) {
+        // Friedman damping: the implicit coefficient theta/2 instead of 1/2
+        double x = g.q0 * g.q0 * n0 * g.dt * g.dt / (2.0 * g.m0 * kEps0);
+        x *= g.theta;
+        chi += x;
+    } else {
+        chi += g.q0 * g.q0 * n0 * g.dt * g.dt / (2.0 * g.m0 * kEps0);
+    }
     rho += g.q1 * n1;
-    if (g.ion_chi) chi += g.q1 * g.q1 * n1 * g.dt1 * g.dt1 / (2.0 * g.m1 * kEps0);
+    if (g.ion_chi) {
+        if (g.friedman) {
+            double x = g.q1 * g.q1 * n1 * g.dt1 * g.dt1 / (2.0 * g.m1 * kEps0);
+            x *= g.theta;
+            chi += x;
+        } else {
+            chi += g.q1 * g.q1 * n1 * g.dt1 * g.dt1 / (2.0 * g.m1 * kEps0);
+        }
+    }
     g.rho[k] = rho;
     g.chi[k] = chi;
     const double eps = 1.0 + chi;

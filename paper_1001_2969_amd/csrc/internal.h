@@ -79,7 +79,7 @@ struct Xsec {
 struct SpeciesK {
     int s, mc_model;
     double q, m, qm;
-    double k1, k2;          // 0.5 q/m dt^2, 0.5 q/m dt
+    double k1, k2;          // c q/m dt^2, c q/m dt: c = 1/2 (D1), theta/2 (Friedman)
     double dt;              // time step of the species (K dt for subcycled ions)
     double inv_quantum;     // 2^bits / w_ref
     double p_null, nu_max;
@@ -96,6 +96,8 @@ struct Phys {
     double ion_acc_ratio;   // q_i m_e / (q_e m_i) for new ions
     double ion_inv_quantum; // fixed-point scale of the ion deposit
     double ion_dt;          // time step of the ions (first push of new ions)
+    int friedman;           // Friedman's adjustable damping instead of D1
+    double fc;              // Friedman: theta / 2, the implicit coefficient
 };
 
 struct Counts {      // per species, device resident
@@ -301,6 +303,8 @@ struct GridArgs {
     unsigned long long *acc0w, *acc1w;
     int32_t *status;
     double dt1;   // ion time step in chi
+    int friedman; // Friedman damping: each chi term scaled by theta
+    double theta;
     int ion_chi;  // the ions move in the coming step: their chi term is on
     int keep1;    // keep the ion deposit (subcycled ions that do not move)
 };

@@ -36,16 +36,19 @@ template <typename T> __device__ __forceinline__ int boundary_of(const PState<T>
 // a_theta = 0.  Global X-Y-Z form (xyz): a_theta kicks v_theta and the damped
 // acceleration turns with the frame (the Cartesian push seen from the
 // particle's meridian plane).
-template <typename T> __device__ __forceinline__ void first_push(PState<T> &s, T dt, bool xyz)
+// kn: the factor of the stored acceleration, 1/2 for D1 (abar_{n-1}/2), 1
+// for Friedman damping (the stored known part B of abar_n).
+template <typename T>
+__device__ __forceinline__ void first_push(PState<T> &s, T dt, bool xyz, T kn)
 {
     // no contraction: every kernel instance that inlines the push rounds alike
 #pragma clang fp contract(off)
     const T half = (T)0.5;
-    T vx = s.vr + half * s.ar * dt;
+    T vx = s.vr + kn * s.ar * dt;
     T vy = xyz ? s.vt + half * s.at * dt : s.vt;
     T x = s.r + vx * dt;
     T y = vy * dt;
-    T vz = s.vz + half * s.az * dt;
+    T vz = s.vz + kn * s.az * dt;
     T z = s.z + vz * dt;
     T rn = sqrt(x * x + y * y);
     T c = (T)1, sn = (T)0;
@@ -94,14 +97,36 @@ __device__ __forceinline__ void gather_E(const Mesh &m, const typename Vec2<T>::
 // Global X-Y-Z form (xyz): E has no theta component at the particle, so a_theta
 // is damped by the same average, and a particle pushed through the axis goes
 // on at the other side (the local frame turns by pi) instead of the axis rule.
+// Friedman damping (fr, fc = theta/2, local push): abar_n = fc a + B, and
+// the particle keeps the next step's known part
+// B' = (1 - fc) ((1 - fc) a + fc abar_n) in (ar, az), with the same axis rule.
 template <typename T>
-__device__ __forceinline__ void final_push(PState<T> &s, T Er, T Ez, T k1, T k2, T qm, bool xyz)
+__device__ __forceinline__ void final_push(PState<T> &s, T Er, T Ez, T k1, T k2, T qm, bool xyz,
+                                           bool fr = false, T fc = (T)0)
 {
 #pragma clang fp contract(off)
     T r = s.r + k1 * Er;
     T z = s.z + k1 * Ez;
     T vr = s.vr + k2 * Er;
     T vz = s.vz + k2 * Ez;
+    if (fr) {
+        const T c1 = (T)1 - fc, aEr = qm * Er, aEz = qm * Ez;
+        const T abr = fc * aEr + s.ar, abz = fc * aEz + s.az;
+        T br = c1 * (c1 * aEr + fc * abr);
+        const T bz = c1 * (c1 * aEz + fc * abz);
+        if (r < (T)0) {
+            r = -r;
+            vr = fabs(vr);
+            br = fabs(br);
+        }
+        s.r = r;
+        s.z = z;
+        s.vr = vr;
+        s.vz = vz;
+        s.ar = br;
+        s.az = bz;
+        return;
+    }
     T ar = (T)0.5 * (qm * Er + s.ar);
     T az = (T)0.5 * (qm * Ez + s.az);
     if (xyz) {
@@ -254,7 +279,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         if ((MODE & M_MARK) && valid) live = s.w >= (T)0;
         bool died = false, moved = false;
         if ((MODE & M_FINAL) && live) {
-            final_push<T>(s, Er, Ez, k1, k2, qm, xyz);
+            final_push<T>(s, Er, Ez, k1, k2, qm, xyz, a.phys.friedman != 0, (T)a.phys.fc);
             moved = true;
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
@@ -311,7 +336,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T> &a, int lb, int gb)
         }
         after_mc();
         if ((MODE & M_FIRST) && live && !cand) {
-            first_push<T>(s, dt, xyz);
+            first_push<T>(s, dt, xyz, a.phys.friedman ? (T)1 : (T)0.5);
             moved = true;
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
@@ -552,7 +577,7 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
         }
         bool live = true;
         if (kFirst) {
-            first_push<T>(s, dt, xyz);
+            first_push<T>(s, dt, xyz, a.phys.friedman ? (T)1 : (T)0.5);
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
                 tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);
@@ -560,13 +585,13 @@ __device__ __forceinline__ void collide_body(const PassArgs<T> &a, int lb, int g
                 atomicOr(a.ch.dead + c, bit);
             }
             if (iz) {
-                first_push<T>(ne, dt, xyz);
+                first_push<T>(ne, dt, xyz, a.phys.friedman ? (T)1 : (T)0.5);
                 b = boundary_of(ne, a.phys);
                 if (b >= 0) {
                     tally_add(a.tally, b, (double)ne.w, a.sp.inv_quantum);
                     ne_live = false;
                 }
-                first_push<T>(ni, (T)a.phys.ion_dt, xyz);
+                first_push<T>(ni, (T)a.phys.ion_dt, xyz, a.phys.friedman ? (T)1 : (T)0.5);
                 b = boundary_of(ni, a.phys);
                 if (b >= 0) {
                     tally_add(a.tally_ion, b, (double)ni.w, a.phys.ion_inv_quantum);
@@ -714,7 +739,7 @@ __global__ __launch_bounds__(256) void k_staged(PassArgs<T> a, int cs)
         int64_t slot = c * kChunk + lane;
         PState<T> s = load(a.p, slot);
         if (MODE & M_FIRST) {
-            first_push<T>(s, dt, a.p.at != nullptr);
+            first_push<T>(s, dt, a.p.at != nullptr, a.phys.friedman ? (T)1 : (T)0.5);
             int b = boundary_of(s, a.phys);
             if (b >= 0) {
                 tally_add(a.tally, b, (double)s.w, a.sp.inv_quantum);

@@ -120,6 +120,8 @@ Phys phys_of(const rzpic_ctx *c)
     p.ion_acc_ratio = (c->sp[0].bound && c->sp[1].bound) ? (i.q * e.m) / (e.q * i.m) : 0.0;
     p.ion_inv_quantum = 1.0 / c->quantum[1];
     p.ion_dt = dt_of(c, 1);
+    p.friedman = c->c.damping == RZPIC_DAMP_FRIEDMAN ? 1 : 0;
+    p.fc = 0.5 * c->c.theta;
     return p;
 }
 
@@ -141,8 +143,10 @@ SpeciesK species_of(const rzpic_ctx *c, int s)
     k.m = v.m;
     k.qm = v.q / v.m;
     k.dt = dt_of(c, s);
-    k.k1 = 0.5 * k.qm * k.dt * k.dt;
-    k.k2 = 0.5 * k.qm * k.dt;
+    // implicit coefficient: 1/2 (D1), theta/2 (Friedman damping)
+    const double cf = c->c.damping == RZPIC_DAMP_FRIEDMAN ? 0.5 * c->c.theta : 0.5;
+    k.k1 = cf * k.qm * k.dt * k.dt;
+    k.k2 = cf * k.qm * k.dt;
     k.inv_quantum = 1.0 / c->quantum[s];
     k.p_null = ss.p_null;
     k.nu_max = ss.nu_max;
@@ -727,6 +731,8 @@ GridArgs grid_args(rzpic_ctx *c, int zero_acc, bool ions = true)
     g.acc1w = c->acc[1];
     g.status = c->status;
     g.dt1 = dt_of(c, 1);
+    g.friedman = c->c.damping == RZPIC_DAMP_FRIEDMAN ? 1 : 0;
+    g.theta = c->c.theta;
     g.ion_chi = ions ? 1 : 0;
     g.keep1 = ions ? 0 : 1;
     return g;
@@ -1039,6 +1045,12 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         return fail(RZPIC_EINVAL, "unknown push_form %d", k.push_form);
     if (k.resize_mode != RZPIC_RESIZE_SPLIT && k.resize_mode != RZPIC_RESIZE_ZERO_ORDER)
         return fail(RZPIC_EINVAL, "unknown resize_mode %d", k.resize_mode);
+    if (k.damping != RZPIC_DAMP_D1 && k.damping != RZPIC_DAMP_FRIEDMAN)
+        return fail(RZPIC_EINVAL, "unknown damping %d", k.damping);
+    if (k.damping == RZPIC_DAMP_FRIEDMAN && k.push_form != RZPIC_PUSH_LOCAL)
+        return fail(RZPIC_EINVAL, "Friedman damping takes the local push (push_form 0)");
+    if (k.damping == RZPIC_DAMP_FRIEDMAN && !(k.theta >= 0.0 && k.theta <= 1.0))
+        return fail(RZPIC_EINVAL, "Friedman damping: theta = %g outside [0, 1]", k.theta);
 
     rzpic_ctx *c = new rzpic_ctx();
     c->c = k;

@@ -56,7 +56,7 @@ class Config(C.Structure):
         ("tile_z", C.c_int32), ("tile_r", C.c_int32),
         ("circuit_C", C.c_double),
         ("ion_subcycle", C.c_int32), ("push_form", C.c_int32),
-        ("resize_mode", C.c_int32), ("reserved2", C.c_int32),
+        ("resize_mode", C.c_int32), ("damping", C.c_int32), ("theta", C.c_double),
     ]
 
 
@@ -228,7 +228,7 @@ class Context:
                      resize_wcoef=w.wcoef, n_gas=w.n_gas, T_gas=w.T_gas, m_gas=w.m_gas,
                      tile_z=w.tile_z, tile_r=w.tile_r, circuit_C=w.circuit_C,
                      ion_subcycle=w.ion_subcycle, push_form=w.push_form,
-                     resize_mode=w.resize_mode)
+                     resize_mode=w.resize_mode, damping=w.damping, theta=w.theta)
         self._cfg = cfg
         self.xyz = w.push_form == 1
         with torch.cuda.device(self.device):
