@@ -203,9 +203,11 @@ struct SliceSum {
 template <typename T>
 hipError_t launch_pass(int mode, const PassArgs<T> &a, int blocks, int threads, size_t lds,
                        hipStream_t st);
+// ev0, ev1 (optional): events attached to the kernel's own start and end.
 template <typename T>
 hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, int b0, int b1,
-                        int threads, size_t lds, hipStream_t st);
+                        int threads, size_t lds, hipStream_t st, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 // Resident blocks per CU of the tiled merged pass (register and LDS limits).
 template <typename T> int pass2_tiled_blocks_per_cu(int threads);
 // Resident blocks per CU of the merged pass with a whole-grid LDS copy of

@@ -6,6 +6,7 @@
 // is).  Outside a recorded step both simply launch on the given stream.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -105,6 +106,20 @@ hipError_t launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, const A &a)
     }
     hipLaunchKernelGGL((k_one<A, Body, MT>), grid, block, lds, st, a);
     return hipPeekAtLastError();  // left set for a caller's hipGetLastError
+}
+
+// launch() with HIP events attached to the kernel's own dispatch (ev0 at
+// its start, ev1 at its end; hipExtLaunchKernel), so that the elapsed time
+// between them is the kernel's run time without the dispatch around it.
+// Without events, or while a batched step records, the same as launch().
+template <typename A, void (*Body)(const Blk &, const A &), int MT>
+hipError_t launch_ev(dim3 grid, dim3 block, size_t lds, hipStream_t st, const A &a,
+                     hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (g_recorder || !ev0 || !ev1) return launch<A, Body, MT>(grid, block, lds, st, a);
+    hipExtLaunchKernelGGL((k_one<A, Body, MT>), grid, block, (std::uint32_t)lds, st, ev0, ev1, 0,
+                          a);
+    return hipPeekAtLastError();
 }
 
 template <typename F>

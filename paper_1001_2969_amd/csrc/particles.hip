@@ -861,16 +861,19 @@ hipError_t launch_init(Parts<T> p, int64_t n, double n0, double T_eV, uint64_t i
 // species 1), then their collision kernels in one launch (c0 + c1 blocks).
 template <typename T>
 hipError_t launch_pass2(int mode, const PassArgs<T> &a0, const PassArgs<T> &a1, int b0, int b1,
-                        int threads, size_t lds, hipStream_t st)
+                        int threads, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     constexpr int kBase = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS;
     const Pass2Args<T> a{a0, a1, b0};
     const dim3 grid(b0 + b1), block(threads);
     if (mode == (kBase | M_LDS))
-        return launch<Pass2Args<T>, pass2_body<T, kBase | M_LDS>, 1024>(grid, block, lds, st, a);
+        return launch_ev<Pass2Args<T>, pass2_body<T, kBase | M_LDS>, 1024>(grid, block, lds, st, a,
+                                                                           ev0, ev1);
     if (mode == (kBase | M_TILE))
-        return launch<Pass2Args<T>, pass2_body<T, kBase | M_TILE>, 1024>(grid, block, lds, st, a);
-    if (mode == kBase) return launch<Pass2Args<T>, pass2_body<T, kBase>, 1024>(grid, block, 0, st, a);
+        return launch_ev<Pass2Args<T>, pass2_body<T, kBase | M_TILE>, 1024>(grid, block, lds, st,
+                                                                            a, ev0, ev1);
+    if (mode == kBase)
+        return launch_ev<Pass2Args<T>, pass2_body<T, kBase>, 1024>(grid, block, 0, st, a, ev0, ev1);
     return hipErrorInvalidValue;
 }
 
@@ -906,9 +909,9 @@ template int pass2_tiled_blocks_per_cu<float>(int);
 template int pass2_lds_blocks_per_cu<double>(int, size_t);
 template int pass2_lds_blocks_per_cu<float>(int, size_t);
 template hipError_t launch_pass2<double>(int, const PassArgs<double> &, const PassArgs<double> &,
-                                         int, int, int, size_t, hipStream_t);
+                                         int, int, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_pass2<float>(int, const PassArgs<float> &, const PassArgs<float> &, int,
-                                        int, int, size_t, hipStream_t);
+                                        int, int, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_collide2<double>(const PassArgs<double> &, const PassArgs<double> &,
                                             int, int, int, hipStream_t);
 template hipError_t launch_collide2<float>(const PassArgs<float> &, const PassArgs<float> &, int,

@@ -397,9 +397,13 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
     if ((b[0] + b[1]) * (threads / 64) > kMaxWaves)
         return fail(RZPIC_EINVAL, "pass of %d wavefronts exceeds %d", (b[0] + b[1]) * threads / 64,
                     kMaxWaves);
-    mark(c, 4);
-    HIPCHK(launch_pass2<T>(mode, a[0], a[1], b[0], b[1], threads, lds, c->st));
-    mark(c, 5);
+    // step timing: the pass's events on its own dispatch (its run time alone)
+    hipEvent_t e4 = nullptr, e5 = nullptr;
+    if (c->timing && c->ev_used < rzpic_ctx::kPool) {
+        e4 = c->evpool[(size_t)c->ev_used * rzpic_ctx::kEvPerStep + 4];
+        e5 = c->evpool[(size_t)c->ev_used * rzpic_ctx::kEvPerStep + 5];
+    }
+    HIPCHK(launch_pass2<T>(mode, a[0], a[1], b[0], b[1], threads, lds, c->st, e4, e5));
     // collision kernels: about two wavefronts per electron bucket, one per
     // ion bucket (ion candidates are rare), deposits by global atomics
     const int cthreads = 256, wpb = cthreads / 64;
