@@ -360,12 +360,15 @@ def large_mesh(steps, warmup):
     return out
 
 
-def batch_run(steps, warmup):
+def batch_run(steps, warmup, tune_steps=2):
     """64 independent discharges (meshes 65x33 / 129x65 / 257x129, 1e5-2e6
     particles per species, log-uniform, seeded; 94M particles in all), mixed
-    and FP64: the same contexts stepped one by one on the stream and then as
-    one batch (rzpic_batch_step, graph replay on); particle-steps/s of both.
-    The timed steps include the tile sorts (every 20 steps)."""
+    and FP64, stepped as one batch (rzpic_batch_step, graph replay on):
+    first in the default pass configuration, then the batch autotuner picks
+    each mesh group's launch shape, deposit form and tile shape
+    (rzpic_batch_autotune), and the same contexts are stepped one by one on
+    the stream and as the batch.  Particle-steps/s of each; the timed steps
+    include the tile sorts (every 20 steps)."""
     import torch
 
     from paper_1001_2969_amd import rzpic, workloads as wl
@@ -387,7 +390,27 @@ def batch_run(steps, warmup):
         def psteps():
             return sum(sum(c.diag()["particle_steps"]) for c in ctxs)
 
+        b = rzpic.Batch(ctxs, stream=torch.cuda.Stream())
+        b.set_graph(True)  # steps replayed from captured graphs
         n = 0
+
+        def batched(k):
+            nonlocal n
+            torch.cuda.synchronize()
+            p0, t0 = psteps(), time.perf_counter()
+            for _ in range(k):
+                b.step(n)
+                n += 1
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, psteps() - p0
+
+        batched(warmup)
+        t_u, p_u = batched(steps)  # default configuration
+        rows, n = b.autotune(tune_steps, n)
+        chosen = {}
+        for k, c in enumerate(ctxs):
+            chosen.setdefault(f"{ws[k].nr}x{ws[k].nz}", c.pass_config())
+        torch.cuda.synchronize()
         for _ in range(warmup):
             for c in ctxs:
                 c.step(n)
@@ -400,22 +423,16 @@ def batch_run(steps, warmup):
             n += 1
         torch.cuda.synchronize()
         t_seq, p_seq = time.perf_counter() - t0, psteps() - p0
-        b = rzpic.Batch(ctxs, stream=torch.cuda.Stream())
-        b.set_graph(True)  # steps replayed from captured graphs
-        for _ in range(warmup):
-            b.step(n)
-            n += 1
-        torch.cuda.synchronize()
-        p0, t0 = psteps(), time.perf_counter()
-        for _ in range(steps):
-            b.step(n)
-            n += 1
-        torch.cuda.synchronize()
-        t_b, p_b = time.perf_counter() - t0, psteps() - p0
+        batched(warmup)
+        t_b, p_b = batched(steps)
         out[prec] = {"batched_value": p_b / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
                      "one_by_one_value": p_seq / t_seq,
                      "one_by_one_ms_per_step": 1e3 * t_seq / steps,
-                     "speedup": (p_b / t_b) / (p_seq / t_seq), "launches": b.stats()}
+                     "speedup": (p_b / t_b) / (p_seq / t_seq), "launches": b.stats(),
+                     "untuned_batched_value": p_u / t_u,
+                     "untuned_batched_ms_per_step": 1e3 * t_u / steps,
+                     "tuned_over_untuned": (p_b / t_b) / (p_u / t_u),
+                     "autotune": {"configurations_timed": len(rows), "chosen": chosen}}
         b.close()
         for c in ctxs:
             c.close()

@@ -292,6 +292,27 @@ rzpic_status rzpic_set_pass_shape(rzpic_ctx *ctx, int32_t threads, int32_t parts
 rzpic_status rzpic_autotune(rzpic_ctx *ctx, int32_t steps, int64_t step0, double *table,
                             int32_t best[2], int64_t *next_step);
 
+/* Deposit form of the fused pass (speed only: the deposit of Sec. 2.4 is
+ * the same integer sum in every form).  RZPIC_FORM_AUTO: each block
+ * privatises the whole grid in LDS when it fits (the default);
+ * RZPIC_FORM_LDS: that form, EINVAL when the grid does not fit one
+ * workgroup's LDS; RZPIC_FORM_TILED: each block deposits into an LDS window
+ * of the tiles planned at the last tile sort (rzpic_sort, or the periodic
+ * sort of rzpic_step), by global atomics without a plan.  A context with a
+ * plan is sorted again for the block count of the new form.  EINVAL when
+ * the current pass shape exceeds the wavefront limit in that form. */
+enum { RZPIC_FORM_AUTO = 0, RZPIC_FORM_LDS = 1, RZPIC_FORM_TILED = 2 };
+rzpic_status rzpic_set_pass_form(rzpic_ctx *ctx, int32_t form);
+/* Tile shape of the particle sort: tile_z x tile_r cells (both >= 1, at
+ * most 2048 tiles, EINVAL otherwise).  Speed only; the particle order after
+ * a sort follows the tiles.  Synchronises the stream when sort scratch
+ * exists (it is sized by the tile count and allocated again); a species
+ * that has a plan is sorted again at once by the new tiles. */
+rzpic_status rzpic_set_tiles(rzpic_ctx *ctx, int32_t tile_z, int32_t tile_r);
+/* The pass configuration in use: out = {threads, parts_per_block, form
+ * (RZPIC_FORM_LDS or RZPIC_FORM_TILED), tile_z, tile_r} (host array). */
+rzpic_status rzpic_get_pass_config(rzpic_ctx *ctx, int32_t out[5]);
+
 /* Device pointers of the context's own grids ([nz][nr] doubles, row-major),
  * for reading and writing them in place with no copy.  Owned by the context
  * (valid until rzpic_destroy), except that FP64 solves move phi between two
@@ -374,6 +395,28 @@ rzpic_status rzpic_batch_step(rzpic_batch *batch, int64_t step);
 rzpic_status rzpic_batch_set_graph(rzpic_batch *batch, int32_t on);
 /* out[0] groups, out[1] launches and out[2] of them batched, last step. */
 rzpic_status rzpic_batch_stats(rzpic_batch *batch, int32_t out[3]);
+/* Autotuner of the pass configuration of a batch (Sec. 2.7's regime of
+ * many particles on small grids, where the per-block fixed costs of the
+ * deposit decide the speed): the contexts are grouped by mesh and
+ * precision, and for each group, stepped as a batch of its own, one warm-up
+ * and `steps` timed steps (HIP events on the batch stream) are run for its
+ * current configuration, then for each launch shape (threads {256, 512,
+ * 1024} x particles per block {2048, 4096, 8192, 16384}) in each deposit
+ * form the group can run (RZPIC_FORM_LDS where the grid fits LDS,
+ * RZPIC_FORM_TILED where the contexts sort, sort_every > 0), then, where
+ * they sort, for tile shapes {8x16, 8x32, 16x16, 16x32, 16x64, 32x32,
+ * 32x64} (z x r cells, at most 2048 tiles) with the fastest tiled shape.  Each group
+ * keeps the first configuration, in that order, within 2 % of its fastest.
+ * Groups whose search took fewer steps are stepped on to the same step, so
+ * every context ends at *next_step.  table (host, may be NULL): up to
+ * max_rows rows of 8 doubles {group, threads, parts_per_block, form, tile_z,
+ * tile_r, ms per step, chosen 0/1}; *rows (may be NULL) the rows the search
+ * made.  The simulation advances; results do not depend on the
+ * configuration (particle order after a sort follows the tiles).
+ * Synchronises. */
+rzpic_status rzpic_batch_autotune(rzpic_batch *batch, int32_t steps, int64_t step0,
+                                  double *table, int32_t max_rows, int32_t *rows,
+                                  int64_t *next_step);
 rzpic_status rzpic_batch_destroy(rzpic_batch *batch);
 
 /* Change the z = 0 electrode voltage V_dc + V_rf sin(2 pi f_rf t) of later

@@ -34,6 +34,12 @@ extern "C" rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
 rzpic_status rz_fail(rzpic_status s, const char *msg);
 hipStream_t rz_stream(const rzpic_ctx *c);
 int rz_batchable(const rzpic_ctx *c, std::string &why);
+extern "C" {
+void rz_tune_key(const rzpic_ctx *c, int32_t out[5]);
+int rz_config_fits(const rzpic_ctx *c, int threads, int64_t ppb, int lds);
+rzpic_status rz_set_config(rzpic_ctx *c, int threads, int64_t ppb, int lds, int tz, int tr);
+void rz_get_config(const rzpic_ctx *c, int32_t out[5]);
+}
 
 namespace {
 
@@ -387,6 +393,176 @@ rzpic_status rzpic_batch_set_graph(rzpic_batch *b, int32_t on)
     if (on && !b->st)
         return rz_fail(RZPIC_EINVAL, "batch: graph replay needs a stream other than the null stream");
     b->graph = on != 0;
+    return RZPIC_OK;
+}
+
+// Autotuner of the pass configuration per group of like discharges (same
+// mesh and precision): the launch shape, the deposit form and the tile
+// shape are tried on the group's discharges stepped as a batch of their
+// own, timed with HIP events on the batch stream.
+rzpic_status rzpic_batch_autotune(rzpic_batch *b, int32_t steps, int64_t step0, double *table,
+                                  int32_t max_rows, int32_t *rows, int64_t *next_step)
+{
+    if (!b || !next_step) return rz_fail(RZPIC_EINVAL, "null argument");
+    if (steps < 1) return rz_fail(RZPIC_EINVAL, "steps must be >= 1");
+    if (table && max_rows < 0) return rz_fail(RZPIC_EINVAL, "max_rows must be >= 0");
+    const int n = (int)b->ctx.size();
+    std::map<std::vector<int32_t>, std::vector<int>> by_key;
+    std::vector<std::vector<int32_t>> key_order;
+    for (int i = 0; i < n; ++i) {
+        std::vector<int32_t> k(5);
+        rz_tune_key(b->ctx[i], k.data());
+        auto it = by_key.find(k);
+        if (it == by_key.end()) {
+            by_key.emplace(k, std::vector<int>{i});
+            key_order.push_back(k);
+        } else {
+            it->second.push_back(i);
+        }
+    }
+    struct Cfg {
+        int threads;
+        int64_t ppb;
+        int lds, tz, tr;
+    };
+    static const int kThreads[3] = {256, 512, 1024};
+    static const int64_t kPpb[4] = {2048, 4096, 8192, 16384};
+    static const int kTiles[7][2] = {{8, 16}, {8, 32}, {16, 16}, {16, 32}, {16, 64}, {32, 32}, {32, 64}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BCHK(hipEventCreate(&e0), "autotune: event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return rz_fail(RZPIC_EHIP, "autotune: event");
+    }
+    // earlier batched steps drain before configurations change
+    {
+        const hipError_t se = b->st ? hipStreamSynchronize(b->st) : hipDeviceSynchronize();
+        if (se != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return hipfail(se, "autotune: sync");
+        }
+    }
+    int nrow = 0;
+    std::vector<int64_t> at(key_order.size(), step0);  // next step of each group
+    rzpic_status st = RZPIC_OK;
+    for (size_t g = 0; g < key_order.size() && st == RZPIC_OK; ++g) {
+        const std::vector<int32_t> &key = key_order[g];
+        std::vector<rzpic_ctx *> mem;
+        for (int i : by_key[key]) mem.push_back(b->ctx[i]);
+        rzpic_batch *sb = nullptr;
+        st = rzpic_batch_create(mem.data(), (int32_t)mem.size(), b->st, &sb);
+        if (st != RZPIC_OK) break;
+        sb->graph = b->graph && b->st;
+        sb->nstreams = 1;
+        int32_t cur[5];
+        rz_get_config(mem[0], cur);
+        std::vector<Cfg> tried;
+        std::vector<double> ms;
+        auto fits = [&](const Cfg &c) {
+            for (rzpic_ctx *x : mem)
+                if (!rz_config_fits(x, c.threads, c.ppb, c.lds)) return false;
+            return true;
+        };
+        auto timed = [&](const Cfg &c) -> rzpic_status {
+            for (rzpic_ctx *x : mem) {
+                const rzpic_status s = rz_set_config(x, c.threads, c.ppb, c.lds, c.tz, c.tr);
+                if (s != RZPIC_OK) return s;
+            }
+            rzpic_status s = rzpic_batch_step(sb, at[g]++);  // warm-up (and capture)
+            if (s != RZPIC_OK) return s;
+            BCHK(hipEventRecord(e0, b->st), "autotune: event");
+            for (int k = 0; k < steps; ++k)
+                if ((s = rzpic_batch_step(sb, at[g]++)) != RZPIC_OK) return s;
+            BCHK(hipEventRecord(e1, b->st), "autotune: event");
+            BCHK(hipEventSynchronize(e1), "autotune: sync");
+            float f = 0.0f;
+            BCHK(hipEventElapsedTime(&f, e0, e1), "autotune: timing");
+            tried.push_back(c);
+            ms.push_back((double)f / steps);
+            return RZPIC_OK;
+        };
+        // the configuration in use first: near-ties keep it
+        const Cfg start{cur[0], (int64_t)cur[1], cur[2] == RZPIC_FORM_LDS ? 1 : 0, cur[3], cur[4]};
+        st = timed(start);
+        // launch shapes in each form the group can run (the tiled form only
+        // where the steps sort, so that it has a plan)
+        for (int lds = 1; lds >= 0 && st == RZPIC_OK; --lds) {
+            if (lds ? !key[3] : !key[4]) continue;
+            for (int ti = 0; ti < 3 && st == RZPIC_OK; ++ti)
+                for (int pi = 0; pi < 4 && st == RZPIC_OK; ++pi) {
+                    const Cfg c{kThreads[ti], kPpb[pi], lds, start.tz, start.tr};
+                    const bool same = c.threads == start.threads && c.ppb == start.ppb &&
+                                      c.lds == start.lds;
+                    if (!same && fits(c)) st = timed(c);
+                }
+        }
+        // tile shapes around the best configuration of the tiled form
+        auto best_of = [&](int form) {  // first within 2 % of the fastest
+            double lo = -1.0;
+            for (size_t k = 0; k < ms.size(); ++k)
+                if (form < 0 || tried[k].lds == form) lo = lo < 0.0 || ms[k] < lo ? ms[k] : lo;
+            for (size_t k = 0; k < ms.size(); ++k)
+                if ((form < 0 || tried[k].lds == form) && ms[k] <= 1.02 * lo) return (int)k;
+            return -1;
+        };
+        if (st == RZPIC_OK && key[4]) {
+            const int bt = best_of(0);
+            if (bt >= 0)
+                for (int k = 0; k < 7 && st == RZPIC_OK; ++k) {
+                    Cfg c = tried[bt];
+                    c.tz = kTiles[k][0];
+                    c.tr = kTiles[k][1];
+                    const int ntr = (key[0] - 2) / c.tr + 1;
+                    if (((key[1] - 2) / c.tz + 1) * ntr > 2048) continue;
+                    if (c.tz == tried[bt].tz && c.tr == tried[bt].tr) continue;
+                    st = timed(c);
+                }
+        }
+        const int win = st == RZPIC_OK ? best_of(-1) : -1;
+        if (win >= 0) {
+            const Cfg &c = tried[win];
+            for (rzpic_ctx *x : mem)
+                if (st == RZPIC_OK) st = rz_set_config(x, c.threads, c.ppb, c.lds, c.tz, c.tr);
+        }
+        for (size_t k = 0; k < tried.size() && table; ++k, ++nrow) {
+            if (nrow >= max_rows) continue;
+            double *r = table + (size_t)8 * nrow;
+            r[0] = (double)g;
+            r[1] = tried[k].threads;
+            r[2] = (double)tried[k].ppb;
+            r[3] = tried[k].lds ? RZPIC_FORM_LDS : RZPIC_FORM_TILED;
+            r[4] = tried[k].tz;
+            r[5] = tried[k].tr;
+            r[6] = ms[k];
+            r[7] = (int)k == win ? 1.0 : 0.0;
+        }
+        if (!table) nrow += (int)tried.size();
+        // the group's own streams drain before its batch goes
+        const hipError_t se = b->st ? hipStreamSynchronize(b->st) : hipDeviceSynchronize();
+        rzpic_batch_destroy(sb);
+        if (st == RZPIC_OK && se != hipSuccess) st = hipfail(se, "autotune: sync");
+    }
+    // every discharge at the same next step: the groups behind catch up
+    int64_t last = step0;
+    for (int64_t a : at) last = a > last ? a : last;
+    for (size_t g = 0; g < key_order.size() && st == RZPIC_OK; ++g) {
+        if (at[g] == last) continue;
+        std::vector<rzpic_ctx *> mem;
+        for (int i : by_key[key_order[g]]) mem.push_back(b->ctx[i]);
+        rzpic_batch *sb = nullptr;
+        st = rzpic_batch_create(mem.data(), (int32_t)mem.size(), b->st, &sb);
+        while (st == RZPIC_OK && at[g] < last) st = rzpic_batch_step(sb, at[g]++);
+        if (sb) {
+            if (b->st) (void)hipStreamSynchronize(b->st);
+            rzpic_batch_destroy(sb);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RZPIC_OK) return st;
+    if (rows) *rows = nrow;
+    *next_step = last;
     return RZPIC_OK;
 }
 

@@ -95,7 +95,8 @@ struct rzpic_ctx {
     unsigned long long *acc[2];
     unsigned long long *slices = nullptr;
     int slice_blocks = 0;
-    bool lds_ok = false;
+    bool lds_ok = false;    // the whole deposit grid fits one block's LDS (slices allocated)
+    bool lds_form = false;  // the fused pass uses that form (else the tiled windows)
     rz::MgLevels mg{};
     // device scalars
     rz::Counts *cnt;

@@ -306,7 +306,7 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
     PassArgs<T> a = pass_args<T>(c, s, step);
     int blocks, threads = c->pass_threads;
     size_t lds = 0;
-    if ((mode & M_DEP) && c->lds_ok) {
+    if ((mode & M_DEP) && c->lds_form) {
         mode |= M_LDS;
         lds = (size_t)c->nn * lds_elem<T>();
         blocks = pass_blocks(c, s, c->slice_blocks);
@@ -336,7 +336,7 @@ template <typename T> rzpic_status run_pass(rzpic_ctx *c, int s, int mode, uint3
         const double expect = c->sp[s].p_null * (double)c->sp[s].cap;
         int cblocks = c->cus * 2, cthreads = 256;
         size_t clds = 0;
-        if (merged && c->lds_ok && expect > 65536.0 &&
+        if (merged && c->lds_form && expect > 65536.0 &&
             (size_t)c->nn * sizeof(unsigned long long) + 1024 <= c->lds_block) {
             // few blocks: each flushes a whole grid copy
             cmode |= M_LDS;
@@ -370,7 +370,7 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
     int mode = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS;
     int b[2];
     size_t lds = 0;
-    if (c->lds_ok) {
+    if (c->lds_form) {
         mode |= M_LDS;
         lds = (size_t)c->nn * lds_elem<T>();
         b[0] = pass_blocks(c, 0, c->slice_blocks / 2);
@@ -1151,7 +1151,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
             if (b > 0 && b <= 65536) c->slice_blocks = b;
         }
         A(c->slices, (size_t)c->slice_blocks * nn)
-        c->lds_ok = true;
+        c->lds_ok = c->lds_form = true;
     } else {
         c->tile_per_cu = c->mixed ? pass2_tiled_blocks_per_cu<float>(c->pass_threads)
                                   : pass2_tiled_blocks_per_cu<double>(c->pass_threads);
@@ -1664,14 +1664,17 @@ rzpic_status rzpic_prologue(rzpic_ctx *c)
     return RZPIC_OK;
 }
 
-// Launch shape of the fused pass: threads per block and particles of
-// capacity per block.  The results do not depend on it (integer deposit,
-// identities from event ranks, compaction by index), only the speed.
-static rzpic_status set_shape(rzpic_ctx *c, int threads, int64_t ppb)
+// Launch configuration of the fused pass: threads per block, particles of
+// capacity per block, and the deposit form (the whole grid privatised in
+// each block's LDS, or the LDS windows of the tiles planned at the last
+// sort).  The results do not depend on it (integer deposit, identities from
+// event ranks, compaction by index), only the speed.
+static rzpic_status set_pass_config(rzpic_ctx *c, int threads, int64_t ppb, bool lds)
 {
     c->pass_threads = threads;
     c->parts_per_block = ppb;
-    if (!c->lds_ok)
+    c->lds_form = lds && c->lds_ok;
+    if (!c->lds_form)
         c->tile_per_cu = c->mixed ? pass2_tiled_blocks_per_cu<float>(threads)
                                   : pass2_tiled_blocks_per_cu<double>(threads);
     // the tile plan is made for the tiled pass's block count: plan again
@@ -1683,17 +1686,24 @@ static rzpic_status set_shape(rzpic_ctx *c, int threads, int64_t ppb)
     return RZPIC_OK;
 }
 
-// Whether a shape fits the pass's bucket layout (at most kMaxWaves wavefronts).
-static bool shape_fits(const rzpic_ctx *c, int threads, int64_t ppb)
+static rzpic_status set_shape(rzpic_ctx *c, int threads, int64_t ppb)
 {
+    return set_pass_config(c, threads, ppb, c->lds_form);
+}
+
+// Whether a configuration fits the pass's bucket layout (at most kMaxWaves
+// wavefronts) and, for the whole-grid form, the LDS.
+static bool config_fits(const rzpic_ctx *c, int threads, int64_t ppb, bool lds)
+{
+    if (lds && !c->lds_ok) return false;
     rzpic_ctx t = *c;  // copy of the scalars pass_blocks / tiled_blocks read
     t.pass_threads = threads;
     t.parts_per_block = ppb;
-    if (!c->lds_ok)
+    if (!lds)
         t.tile_per_cu = c->mixed ? pass2_tiled_blocks_per_cu<float>(threads)
                                  : pass2_tiled_blocks_per_cu<double>(threads);
     int b0, b1;
-    if (c->lds_ok) {
+    if (lds) {
         b0 = pass_blocks(&t, 0, c->slice_blocks / 2);
         b1 = pass_blocks(&t, 1, c->slice_blocks - c->slice_blocks / 2);
     } else {
@@ -1701,6 +1711,74 @@ static bool shape_fits(const rzpic_ctx *c, int threads, int64_t ppb)
         b1 = tiled_blocks(&t, 1);
     }
     return (int64_t)(b0 + b1) * (threads / 64) <= kMaxWaves;
+}
+
+static bool shape_fits(const rzpic_ctx *c, int threads, int64_t ppb)
+{
+    return config_fits(c, threads, ppb, c->lds_form);
+}
+
+// Tile shape of the sort (cells in z and r).  The sort's scratch is sized by
+// the tile count: it is freed here (after the stream has drained) and
+// allocated again by the next sort; a species that has a plan is sorted
+// again at once, by the new tiles.
+static rzpic_status set_tiles(rzpic_ctx *c, int tz, int tr)
+{
+    if (tz < 1 || tr < 1) return fail(RZPIC_EINVAL, "tile_z and tile_r must be >= 1");
+    const int ntr = (c->c.nr - 2) / tr + 1;
+    const int nt = ((c->c.nz - 2) / tz + 1) * ntr;
+    if (nt > kMaxTiles)
+        return fail(RZPIC_EINVAL, "%d tiles exceed %d: enlarge tile_z / tile_r", nt, kMaxTiles);
+    if (tz == c->c.tile_z && tr == c->c.tile_r) return RZPIC_OK;
+    const bool planned[2] = {c->sp[0].tile_pb != nullptr, c->sp[1].tile_pb != nullptr};
+    if (c->sp[0].sort_off || c->sp[1].sort_off) HIPCHK(hipStreamSynchronize(c->st));
+    for (int s = 0; s < 2; ++s) free_sort(c->sp[s]);
+    c->c.tile_z = tz;
+    c->c.tile_r = tr;
+    c->ntr = ntr;
+    c->nt = nt;
+    c->kbits = 0;
+    while ((1 << c->kbits) < c->nt) ++c->kbits;
+    for (int s = 0; s < 2; ++s)
+        if (planned[s]) {
+            if (c->mixed) TRY(sort_impl<float>(c, s));
+            else TRY(sort_impl<double>(c, s));
+        }
+    return RZPIC_OK;
+}
+
+// ===========================================================================
+// Helpers of the batch autotuner (batch.hip).
+
+// What the tuner groups contexts by: {nr, nz, FP32 particles, the whole
+// grid fits LDS, tile-sorted steps}.
+void rz_tune_key(const rzpic_ctx *c, int32_t out[5])
+{
+    out[0] = c->c.nr;
+    out[1] = c->c.nz;
+    out[2] = c->mixed;
+    out[3] = c->lds_ok ? 1 : 0;
+    out[4] = c->c.sort_every > 0 ? 1 : 0;
+}
+
+int rz_config_fits(const rzpic_ctx *c, int threads, int64_t ppb, int lds)
+{
+    return config_fits(c, threads, ppb, lds != 0) ? 1 : 0;
+}
+
+rzpic_status rz_set_config(rzpic_ctx *c, int threads, int64_t ppb, int lds, int tz, int tr)
+{
+    TRY(set_tiles(c, tz, tr));
+    return set_pass_config(c, threads, ppb, lds != 0);
+}
+
+void rz_get_config(const rzpic_ctx *c, int32_t out[5])
+{
+    out[0] = c->pass_threads;
+    out[1] = (int32_t)c->parts_per_block;
+    out[2] = c->lds_form ? RZPIC_FORM_LDS : RZPIC_FORM_TILED;
+    out[3] = c->c.tile_z;
+    out[4] = c->c.tile_r;
 }
 
 rzpic_status rzpic_step(rzpic_ctx *c, int64_t step)
@@ -1782,6 +1860,33 @@ rzpic_status rzpic_set_pass_shape(rzpic_ctx *c, int32_t threads, int32_t parts_p
     if (c->sp[0].bound && c->sp[1].bound && !shape_fits(c, threads, parts_per_block))
         return fail(RZPIC_EINVAL, "the shape exceeds the pass's wavefront limit");
     return set_shape(c, threads, parts_per_block);
+}
+
+rzpic_status rzpic_set_pass_form(rzpic_ctx *c, int32_t form)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (form != RZPIC_FORM_AUTO && form != RZPIC_FORM_LDS && form != RZPIC_FORM_TILED)
+        return fail(RZPIC_EINVAL, "form must be RZPIC_FORM_AUTO, RZPIC_FORM_LDS or RZPIC_FORM_TILED");
+    if (form == RZPIC_FORM_LDS && !c->lds_ok)
+        return fail(RZPIC_EINVAL, "the deposit grid does not fit one workgroup's LDS");
+    const bool lds = form != RZPIC_FORM_TILED && c->lds_ok;
+    if (c->sp[0].bound && c->sp[1].bound &&
+        !config_fits(c, c->pass_threads, c->parts_per_block, lds))
+        return fail(RZPIC_EINVAL, "the pass shape exceeds the wavefront limit in that form");
+    return set_pass_config(c, c->pass_threads, c->parts_per_block, lds);
+}
+
+rzpic_status rzpic_set_tiles(rzpic_ctx *c, int32_t tile_z, int32_t tile_r)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    return set_tiles(c, tile_z, tile_r);
+}
+
+rzpic_status rzpic_get_pass_config(rzpic_ctx *c, int32_t out[5])
+{
+    if (!c || !out) return fail(RZPIC_EINVAL, "null argument");
+    rz_get_config(c, out);
+    return RZPIC_OK;
 }
 
 rzpic_status rzpic_grid_copy(rzpic_ctx *c, int32_t which, double *dev, int32_t to_ctx)

@@ -32,7 +32,9 @@ EXPORTS = (
     "rzpic_adjoint_forward", "rzpic_adjoint_backward", "rzpic_adjoint_destroy",
     "rzpic_set_circuit", "rzpic_get_circuit", "rzpic_set_pass_shape", "rzpic_autotune",
     "rzpic_deposit_noalloc", "rzpic_solve_dev", "rzpic_grid_view", "rzpic_set_grid_source",
+    "rzpic_set_pass_form", "rzpic_set_tiles", "rzpic_get_pass_config", "rzpic_batch_autotune",
 )
+FORM_AUTO, FORM_LDS, FORM_TILED = 0, 1, 2
 
 
 class RzpicError(RuntimeError):
@@ -158,6 +160,9 @@ def lib():
             "rzpic_solve_dev": [P, D, P, P],
             "rzpic_grid_view": [P, C.POINTER(GridView)],
             "rzpic_set_grid_source": [P, P, P],
+            "rzpic_set_pass_form": [P, I], "rzpic_set_tiles": [P, I, I],
+            "rzpic_get_pass_config": [P, P],
+            "rzpic_batch_autotune": [P, I, C.c_int64, P, I, C.POINTER(I), C.POINTER(C.c_int64)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -396,6 +401,18 @@ class Context:
     def set_pass_shape(self, threads, parts_per_block):
         _check(lib().rzpic_set_pass_shape(self.h, threads, parts_per_block))
 
+    def set_pass_form(self, form):
+        _check(lib().rzpic_set_pass_form(self.h, form))
+
+    def set_tiles(self, tile_z, tile_r):
+        _check(lib().rzpic_set_tiles(self.h, tile_z, tile_r))
+
+    def pass_config(self):
+        """{threads, parts_per_block, form, tile_z, tile_r} in use."""
+        out = (C.c_int32 * 5)()
+        _check(lib().rzpic_get_pass_config(self.h, C.cast(out, C.c_void_p)))
+        return dict(zip(("threads", "parts_per_block", "form", "tile_z", "tile_r"), list(out)))
+
     def autotune(self, steps, step0):
         """Times the fused pass's launch shapes over real steps from step0 and
         keeps the fastest; returns (best (threads, parts_per_block), table of
@@ -474,6 +491,26 @@ class Batch:
 
     def set_graph(self, on=True):
         _check(lib().rzpic_batch_set_graph(self.h, 1 if on else 0))
+
+    def autotune(self, steps, step0, max_rows=512):
+        """Per group of like discharges, times pass configurations over real
+        batched steps from step0 and keeps the fastest (rzpic_batch_autotune);
+        returns (rows of {group, threads, parts_per_block, form, tile_z,
+        tile_r, ms, chosen}, next step index)."""
+        table = (C.c_double * (8 * max_rows))()
+        rows = C.c_int32()
+        nxt = C.c_int64()
+        _check(lib().rzpic_batch_autotune(self.h, steps, step0, C.cast(table, C.c_void_p),
+                                          max_rows, C.byref(rows), C.byref(nxt)))
+        keys = ("group", "threads", "parts_per_block", "form", "tile_z", "tile_r", "ms", "chosen")
+        out = []
+        for k in range(min(rows.value, max_rows)):
+            r = dict(zip(keys, table[8 * k:8 * k + 8]))
+            for key in keys:
+                if key != "ms":
+                    r[key] = int(r[key])
+            out.append(r)
+        return out, nxt.value
 
     def stats(self):
         out = (C.c_int32 * 3)()
