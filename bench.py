@@ -58,13 +58,16 @@ def measured_traffic(name, shape=None):
 
 
 def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, tune=False,
-            shape=None):
+            shape=None, graph=False):
     """Throughput over `steps` merged steps with nothing else on the stream,
     then `timing_steps` more with the library's HIP events around each phase
     (per-phase device times; every event costs the stream a few microseconds,
-    which is why the throughput run records none).  tune: the library's
-    autotuner picks the pass's launch shape first (its steps precede the
-    warm-up); shape: (threads, particles per block) set instead."""
+    which is why the throughput run records none; those steps run directly).
+    tune: the library's autotuner picks the pass's launch shape first (its
+    steps precede the warm-up); shape: (threads, particles per block) set
+    instead.  graph: after the timed steps, `timing_steps` more captured and
+    replayed as HIP graphs (rzpic_set_step_graph, on a stream of the
+    context's own) are timed too."""
     import torch
 
     from paper_1001_2969_amd import rzpic
@@ -97,6 +100,21 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, 
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     d1 = ctx.diag()
+    graph_ms = None
+    if graph:
+        ctx.use_stream(torch.cuda.Stream())
+        ctx.set_step_graph(True)
+        for _ in range(5):
+            ctx.step(n)
+            n += 1
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(timing_steps):
+            ctx.step(n)
+            n += 1
+        torch.cuda.synchronize()
+        graph_ms = 1e3 * (time.perf_counter() - t2) / timing_steps
+        ctx.set_step_graph(False)
     ctx.set_timing(True)
     ctx.timing()  # reset accumulators
     for _ in range(timing_steps):
@@ -112,7 +130,7 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, 
         "timing": tim, "count": d1["count"], "events_last_step": d1["events"],
         "pass_shape": None if shape is None else {"threads": shape[0],
                                                   "particles_per_block": shape[1]},
-        "tuning_steps": tuning_steps,
+        "tuning_steps": tuning_steps, "graph_ms_per_step": graph_ms,
     }
 
 
@@ -604,6 +622,8 @@ def main():
                     help="skip the 257x129 / 4M-per-species gradient window")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default pass launch shape (no autotuning)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the graph-replayed steps timed after the headline steps")
     ap.add_argument("--no-circuit", action="store_true",
                     help="skip the external-circuit and ion-subcycling forms")
     ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
@@ -640,13 +660,15 @@ def main():
     w = wl.rf_129x65()
     print(f"# workload {w.name}: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr,
           flush=True)
-    ctx_m, mixed = run_gpu(w, "mixed", args.steps, args.warmup, tune=not args.no_tune)
+    ctx_m, mixed = run_gpu(w, "mixed", args.steps, args.warmup, tune=not args.no_tune,
+                           graph=not args.no_graph)
     print(f"# mixed: {mixed['value']:.4g} particle-steps/s, {mixed['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)
     fp64 = None
     rho = chi = phi = None
     if not args.no_fp64:
-        ctx_d, fp64 = run_gpu(w, "fp64", args.steps, args.warmup, tune=not args.no_tune)
+        ctx_d, fp64 = run_gpu(w, "fp64", args.steps, args.warmup, tune=not args.no_tune,
+                              graph=not args.no_graph)
         print(f"# fp64: {fp64['value']:.4g} particle-steps/s, {fp64['ms_per_step']:.4f} ms/step",
               file=sys.stderr, flush=True)
         rho, chi, phi = (ctx_d.grid(g) for g in (rzpic.G_RHO, rzpic.G_CHI, rzpic.G_PHI))
@@ -713,12 +735,14 @@ def main():
                    "v_cycles_per_step": w.mg_fixed_cycles, "V_rf": w.V_rf, "f_rf": w.f_rf,
                    "pass_shape": mixed["pass_shape"],
                    "autotune_steps": mixed["tuning_steps"]},
+        "graph_ms_per_step": mixed["graph_ms_per_step"],
         "breakdown_ms_per_step": {k: tm[k] for k in ("step_ms", "solve_ms", "pass_ms",
                                                      "collide_ms", "grid_ms", "lists_ms",
                                                      "resize_ms", "sort_ms")},
         "vcycle_ms": {"mixed": tm["solve_ms"] / max(tm["vcycles"], 1)},
         "fp64": None if fp64 is None else {
             "value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+            "graph_ms_per_step": fp64["graph_ms_per_step"],
             "breakdown_ms_per_step": {k: fp64["timing"][k] for k in
                                       ("step_ms", "solve_ms", "pass_ms", "collide_ms")},
             "pass_GBps": BYTES_PER_PARTICLE["fp64"] * (fp64["timing"]["n0"] +

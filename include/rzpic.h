@@ -274,6 +274,17 @@ rzpic_status rzpic_prologue(rzpic_ctx *ctx);
  * composition of the single operations above. */
 rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
 
+/* Graph replay of rzpic_step (off by default): each step's launches are
+ * captured from the context's stream and replayed as one HIP graph, the
+ * executable graph of the step's variant (ions moving or not, weight split,
+ * tile sort) updated in place with the step's arguments.  The results are
+ * those of the direct step, bit for bit; the GPU saves about a microsecond
+ * of dispatch per kernel.  Steps run directly while step timing is on,
+ * while a batch records them, or when the solve runs to a tolerance.
+ * EINVAL when enabling on the null stream or with mg_fixed_cycles = 0.
+ * The executable graphs are freed by rzpic_destroy. */
+rzpic_status rzpic_set_step_graph(rzpic_ctx *ctx, int32_t on);
+
 /* Launch shape of the fused particle pass: threads per block (256, 512, 768
  * or 1024) and particles of capacity per block (default 512 threads, 8192).
  * Results do not depend on it (integer deposit, identities from event

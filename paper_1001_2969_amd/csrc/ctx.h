@@ -136,4 +136,10 @@ struct rzpic_ctx {
     double acc_cycles = 0, acc_n[2] = {0, 0};
     int acc_steps = 0;
     std::vector<double> step_n0, step_n1;  // per recorded step, from the pass counts
+    // graph replay of rzpic_step (rzpic_set_step_graph): the step's launches
+    // are captured and replayed; one executable graph per step variant
+    // (ions moving, weight split, tile sort), updated in place with each
+    // step's arguments
+    bool step_graph = false;
+    hipGraphExec_t gexec[8] = {};
 };

@@ -1260,6 +1260,8 @@ rzpic_status rzpic_destroy(rzpic_ctx *c)
         free_sort(c->sp[s]);
     }
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    for (hipGraphExec_t &g : c->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     if (c->normk_host) (void)hipHostFree(c->normk_host);
     delete c;
     return RZPIC_OK;
@@ -1781,11 +1783,71 @@ void rz_get_config(const rzpic_ctx *c, int32_t out[5])
     out[4] = c->c.tile_r;
 }
 
+// One step captured from the stream and replayed as a graph.  The step's
+// launches are recorded by stream capture (their arguments evaluated now, as
+// in a direct step), and the executable graph of the step's variant is
+// updated with them in place (hipGraphExecUpdate: same kernels, new
+// arguments), or instantiated when the variant is new or the update is
+// refused.  Replaying a graph saves the GPU about a microsecond of dispatch
+// per kernel against launching the same kernels one by one.
+static rzpic_status step_graph(rzpic_ctx *c, int64_t n)
+{
+    const bool ions = n % ion_K(c) == ion_K(c) - 1;
+    const bool resize = c->c.resize_every > 0 && n % c->c.resize_every == c->c.resize_every - 1;
+    const bool sort = c->c.sort_every > 0 && n % c->c.sort_every == c->c.sort_every - 1;
+    hipGraphExec_t &ex = c->gexec[(ions ? 1 : 0) | (resize ? 2 : 0) | (sort ? 4 : 0)];
+    HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    const rzpic_status s = c->mixed ? step_impl<float>(c, n) : step_impl<double>(c, n);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(c->st, &g);
+    if (s != RZPIC_OK || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (s != RZPIC_OK) return s;
+        return fail(RZPIC_EHIP, "step capture: %s", hipGetErrorString(ce));
+    }
+    if (ex) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult r = hipGraphExecUpdateSuccess;
+        if (hipGraphExecUpdate(ex, g, &bad, &r) != hipSuccess || r != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(ex);
+            ex = nullptr;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!ex) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ex = nullptr;
+        return fail(RZPIC_EHIP, "step graph instantiation: %s", hipGetErrorString(e));
+    }
+    HIPCHK(hipGraphLaunch(ex, c->st));
+    return RZPIC_OK;
+}
+
 rzpic_status rzpic_step(rzpic_ctx *c, int64_t step)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
     if (step < 0 || step > 0xFFFFFFFELL) return fail(RZPIC_EINVAL, "step out of range");
+    // graph replay unless a batch records this step, timing events are on or
+    // the solve runs to a tolerance (it synchronises)
+    if (c->step_graph && !g_recorder && !c->timing && c->c.mg_fixed_cycles > 0)
+        return step_graph(c, step);
     return c->mixed ? step_impl<float>(c, step) : step_impl<double>(c, step);
+}
+
+rzpic_status rzpic_set_step_graph(rzpic_ctx *c, int32_t on)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (on) {
+        if (!c->st)
+            return fail(RZPIC_EINVAL, "graph replay needs a stream other than the null stream");
+        if (c->c.mg_fixed_cycles <= 0)
+            return fail(RZPIC_EINVAL, "graph replay needs a fixed number of V-cycles "
+                                      "(mg_fixed_cycles > 0): a tolerance-mode solve synchronises");
+    }
+    c->step_graph = on != 0;
+    return RZPIC_OK;
 }
 
 rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *table,

@@ -33,6 +33,7 @@ EXPORTS = (
     "rzpic_set_circuit", "rzpic_get_circuit", "rzpic_set_pass_shape", "rzpic_autotune",
     "rzpic_deposit_noalloc", "rzpic_solve_dev", "rzpic_grid_view", "rzpic_set_grid_source",
     "rzpic_set_pass_form", "rzpic_set_tiles", "rzpic_get_pass_config", "rzpic_batch_autotune",
+    "rzpic_set_step_graph",
 )
 FORM_AUTO, FORM_LDS, FORM_TILED = 0, 1, 2
 
@@ -161,6 +162,7 @@ def lib():
             "rzpic_grid_view": [P, C.POINTER(GridView)],
             "rzpic_set_grid_source": [P, P, P],
             "rzpic_set_pass_form": [P, I], "rzpic_set_tiles": [P, I, I],
+            "rzpic_set_step_graph": [P, I],
             "rzpic_get_pass_config": [P, P],
             "rzpic_batch_autotune": [P, I, C.c_int64, P, I, C.POINTER(I), C.POINTER(C.c_int64)],
         }
@@ -400,6 +402,17 @@ class Context:
 
     def set_pass_shape(self, threads, parts_per_block):
         _check(lib().rzpic_set_pass_shape(self.h, threads, parts_per_block))
+
+    def use_stream(self, stream):
+        """Run the context's work on `stream` (a torch stream) from now on."""
+        self.stream.synchronize()
+        _check(lib().rzpic_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
+    def set_step_graph(self, on=True):
+        """Steps captured and replayed as HIP graphs (rzpic_set_step_graph);
+        needs a stream other than the null stream (use_stream)."""
+        _check(lib().rzpic_set_step_graph(self.h, 1 if on else 0))
 
     def set_pass_form(self, form):
         _check(lib().rzpic_set_pass_form(self.h, form))
