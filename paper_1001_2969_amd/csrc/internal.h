@@ -345,7 +345,9 @@ struct MgLevels {
     int split_coarse;      // 1: the split cycle's two-launch way up
     int S;                 // reduction steps of an r-line (ceil(log2(nr - 1)))
     int line_off[kMaxLevels + 2];  // first table line of each level; line_off[L+1] = total
-    size_t tab_stride;     // elements per line table: (3 + 2 S) (nr - 1)
+    int tab_row;           // elements per row of a line table: nr - 1 rounded up to a
+                           //    multiple of 4 (the padding: zero multipliers, b_final 1)
+    size_t tab_stride;     // elements per line table: (3 + 2 S) tab_row
     void *tab;             // line tables, float (mixed) or double
     void *coarse_uf;       // levels 1..L-1: u then f of each level in one block
                            //    (float when mixed), the coarse solve's LDS image

@@ -1085,7 +1085,7 @@ template <typename T> __device__ __forceinline__ void factor_body(const MgLevels
     int l = 1;
     while (line >= m.line_off[l + 1]) ++l;
     const int i = line - m.line_off[l] + 1;
-    const int nr = m.nr, n = nr - 1;
+    const int nr = m.nr, n = nr - 1, tn = m.tab_row;
     T *tab = (T *)m.tab + (size_t)line * m.tab_stride;
     const T *eps = mixed ? (const T *)m.eps32[l] : (const T *)m.eps64[l];
     const T iz2 = (T)(1.0 / (m.hzl[l] * m.hzl[l])), ir2 = (T)(1.0 / (m.hr * m.hr));
@@ -1094,7 +1094,7 @@ template <typename T> __device__ __forceinline__ void factor_body(const MgLevels
     if (j < n) {
         Coef<T> k = coef<T>(eps, nr, i, j, iz2, ir2, m.chi_face);
         tab[j] = k.a;
-        tab[n + j] = k.c;
+        tab[tn + j] = k.c;
         A[j] = j == 0 ? (T)0 : -k.d;
         Bd[j] = k.b;
         C[j] = j == n - 1 ? (T)0 : -k.e;
@@ -1116,8 +1116,8 @@ template <typename T> __device__ __forceinline__ void factor_body(const MgLevels
                 c2 = -C[j + s] * k2;
                 b -= A[j + s] * k2;
             }
-            tab[(size_t)(3 + 2 * q) * n + j] = k1;
-            tab[(size_t)(4 + 2 * q) * n + j] = k2;
+            tab[(size_t)(3 + 2 * q) * tn + j] = k1;
+            tab[(size_t)(4 + 2 * q) * tn + j] = k2;
         }
         __syncthreads();
         if (j < n) {
@@ -1127,7 +1127,12 @@ template <typename T> __device__ __forceinline__ void factor_body(const MgLevels
         }
         __syncthreads();
     }
-    if (j < n) tab[2 * n + j] = Bd[j];
+    if (j < n) tab[2 * tn + j] = Bd[j];
+    // the padding of every row (read by vector loads of whole lane groups):
+    // zero multipliers and b_final 1, so that it stays finite and inert
+    if (j >= n && j < tn) {
+        for (int r = 0; r < 3 + 2 * m.S; ++r) tab[(size_t)r * tn + j] = r == 2 ? (T)1 : (T)0;
+    }
 }
 
 template <typename T>
@@ -1227,16 +1232,16 @@ template <typename T, int Q, int SMAX> struct LineTab {
 // for the whole wavefront (scalar registers), the offset j * sizeof(T) is
 // one register that every row shares (j < n <= 8192).
 template <typename T>
-__device__ __forceinline__ T tab_at(const T *tb, size_t row, int n, uint32_t off)
+__device__ __forceinline__ T tab_at(const T *tb, size_t row, int tn, uint32_t off)
 {
-    return *(const T *)((const char *)(tb + row * (size_t)n) + off);
+    return *(const T *)((const char *)(tb + row * (size_t)tn) + off);
 }
 
 // The loads alone (clamped indices), then the masking of unknowns past the
 // line's end and of reduction steps past S: a prefetched table is masked only
 // when it is used, so nothing waits for its loads before then.
 template <typename T, int Q, int SMAX>
-__device__ __forceinline__ void line_tab_fetch(const T *tb, int n, int S, int lane,
+__device__ __forceinline__ void line_tab_fetch(const T *tb, int n, int tn, int S, int lane,
                                                LineTab<T, Q, SMAX> &t)
 {
 #pragma unroll
@@ -1244,14 +1249,14 @@ __device__ __forceinline__ void line_tab_fetch(const T *tb, int n, int S, int la
         const int j = q * 64 + lane;
         const int jj = j < n ? j : n - 1;
         const uint32_t off = (uint32_t)jj * (uint32_t)sizeof(T);
-        t.ta[q] = tab_at(tb, 0, n, off);
-        t.tc[q] = tab_at(tb, 1, n, off);
-        t.bf[q] = tab_at(tb, 2, n, off);
+        t.ta[q] = tab_at(tb, 0, tn, off);
+        t.tc[q] = tab_at(tb, 1, tn, off);
+        t.bf[q] = tab_at(tb, 2, tn, off);
 #pragma unroll
         for (int st = 0; st < SMAX; ++st) {
             const int sc = st < S ? st : S - 1;
-            t.k1[st][q] = tab_at(tb, (size_t)(3 + 2 * sc), n, off);
-            t.k2[st][q] = tab_at(tb, (size_t)(4 + 2 * sc), n, off);
+            t.k1[st][q] = tab_at(tb, (size_t)(3 + 2 * sc), tn, off);
+            t.k2[st][q] = tab_at(tb, (size_t)(4 + 2 * sc), tn, off);
         }
     }
 }
@@ -1273,10 +1278,10 @@ __device__ __forceinline__ void line_tab_mask(int n, int S, int lane, LineTab<T,
 }
 
 template <typename T, int Q, int SMAX>
-__device__ __forceinline__ void line_tab_load(const T *tb, int n, int S, int lane,
+__device__ __forceinline__ void line_tab_load(const T *tb, int n, int tn, int S, int lane,
                                               LineTab<T, Q, SMAX> &t)
 {
-    line_tab_fetch<T, Q, SMAX>(tb, n, S, lane, t);
+    line_tab_fetch<T, Q, SMAX>(tb, n, tn, S, lane, t);
     line_tab_mask<T, Q, SMAX>(n, S, lane, t);
 }
 
@@ -1372,7 +1377,7 @@ __device__ __forceinline__ void k_solve_body(const Blk &kb_, const k_solve_A<T, 
                 const int i = parity ? 2 * t + 1 : 2 * t + 2;
                 const T *tb = (const T *)m.tab + (size_t)(m.line_off[l] + i - 1) * m.tab_stride;
                 LineTab<T, Q, SMAX> tab;
-                line_tab_load<T, Q, SMAX>(tb, n, S, lane, tab);
+                line_tab_load<T, Q, SMAX>(tb, n, m.tab_row, S, lane, tab);
                 T R[Q];
                 double ph[Q];  // phi of the line (mixed finest level: phi += x)
 #pragma unroll
@@ -1629,7 +1634,7 @@ __device__ __forceinline__ void k_fine_body(const Blk &kb_, const k_fine_A<T, Q>
     {
         const int io = i - 1 + 2 * w;
         LineTab<T, Q, SMAX> tb;
-        line_tab_load<T, Q, SMAX>(tab0 + (size_t)io * m.tab_stride, n, S, lane, tb);
+        line_tab_load<T, Q, SMAX>(tab0 + (size_t)io * m.tab_stride, n, m.tab_row, S, lane, tb);
         T R[Q];
         double ph[Q];
 #pragma unroll
@@ -1657,7 +1662,7 @@ __device__ __forceinline__ void k_fine_body(const Blk &kb_, const k_fine_A<T, Q>
             R[q] = ok ? g + tb.ta[q] * lo + tb.tc[q] * hi : (T)0;
         }
         if (w == 0) {
-            line_tab_fetch<T, Q, SMAX>(tab0 + (size_t)i * m.tab_stride, n, S, lane, te);
+            line_tab_fetch<T, Q, SMAX>(tab0 + (size_t)i * m.tab_stride, n, m.tab_row, S, lane, te);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int j = q * 64 + lane;
@@ -1769,6 +1774,72 @@ template <typename T> __device__ __forceinline__ T ld_off(const T *base, uint32_
     return *(gT *)((gchar *)base + off);
 }
 
+// Q consecutive elements at a 32-bit byte offset from a wavefront-uniform
+// base, in one load (base + off aligned to Q elements).
+template <typename T, int Q>
+__device__ __forceinline__ void ld_vec(const T *base, uint32_t off, T (&dst)[Q])
+{
+    if constexpr (Q == 1) {
+        dst[0] = ld_off(base, off);
+    } else {
+        typedef T V __attribute__((ext_vector_type(Q)));
+        typedef const __attribute__((address_space(1))) char gchar;
+        typedef const __attribute__((address_space(1))) V gV;
+        const V v = *(gV *)((gchar *)base + off);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) dst[q] = v[q];
+    }
+}
+
+// line_pcr for lanes that hold Q consecutive unknowns (j = Q lane + q): the
+// same reduction steps, term for term, with the neighbours at distance
+// s < Q in the lane itself or the next lane, and those at s >= Q a lane
+// shuffle of s / Q away.
+template <typename T, int Q, int SMAX>
+__device__ __forceinline__ void line_pcr_adj(T (&R)[Q], const LineTab<T, Q, SMAX> &t, int S,
+                                             int lane)
+{
+#pragma unroll
+    for (int st = 0; st < SMAX; ++st) {
+        if (st >= S) break;
+        const int s = 1 << st;
+        T nR[Q];
+        if (s < Q) {
+            T fl[Q], fr[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                // lane - 1 holds unknown j - s for q < s, lane + 1 unknown j + s for q >= Q - s
+                fl[q] = q < s ? __shfl(R[q < s ? q - s + Q : 0], (lane - 1) & 63, 64) : (T)0;
+                fr[q] = q >= Q - s ? __shfl(R[q >= Q - s ? q + s - Q : 0], (lane + 1) & 63, 64) : (T)0;
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const T left = q >= s ? R[q >= s ? q - s : 0] : (lane >= 1 ? fl[q] : (T)0);
+                const T right = q + s < Q ? R[q + s < Q ? q + s : 0] : (lane < 63 ? fr[q] : (T)0);
+                nR[q] = R[q] - left * t.k1[st][q] - right * t.k2[st][q];
+            }
+        } else {
+            const int d = s / Q;
+            T dn[Q], up[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                dn[q] = __shfl(R[q], (lane - d) & 63, 64);
+                up[q] = __shfl(R[q], (lane + d) & 63, 64);
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const T left = lane >= d ? dn[q] : (T)0;
+                const T right = lane + d < 64 ? up[q] : (T)0;
+                nR[q] = R[q] - left * t.k1[st][q] - right * t.k2[st][q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) R[q] = nR[q];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) R[q] = R[q] / t.bf[q];
+}
+
 // The levels of a mesh with nz = 2^L + 1 rows have nz_l = 2^l + 1 rows; the
 // line tables of level l start at line 2^l - l - 1 (levels 1..l-1 hold
 // nz_q - 2 interior lines each), and the coarse block (u then f of each level)
@@ -1826,9 +1897,15 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     const size_t tstride = m.tab_stride;
     // The inputs of this wavefront's line of phase ph: its table rows
     // (a | c | b_final | k1, k2 of each step, see factor_body), right-hand
-    // side and phi.  Every wavefront fetches in every phase (a wavefront
-    // without a line there, or a phase past the last, takes another line of
-    // the block), so that the loads in flight are the same on every path.
+    // side and phi.  A lane holds the Q consecutive unknowns j = Q lane + q,
+    // so that each table row comes in one load of Q elements (the rows are
+    // padded to whole groups; a lane past the row's end takes its last
+    // group): about half the loads of one element per load, and the
+    // wavefront's loads of two phases ahead fit the 63 it can have in
+    // flight.  Every wavefront fetches in every phase (a wavefront without a
+    // line there, or a phase past the last, takes another line of the
+    // block), so that the loads in flight are the same on every path.
+    const int tn = m.tab_row;
     auto fetch = [&](int ph, UpIn<T, Q, SMAX> &in) {
         int l = ph / 2 + 1, par = !(ph & 1), t = wave;
         if (ph >= nph) {
@@ -1850,26 +1927,28 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
         const bool fine = l == L;
         const T *tb = tab + (size_t)(up_line_off(l) + r - 1) * tstride;
         const T *fl = coarse + (up_f_row(l) + r) * nr;
+        const int e0 = Q * lane + Q <= tn ? Q * lane : tn - Q;
+        const uint32_t ot = (uint32_t)e0 * (uint32_t)sizeof(T);
+        ld_vec<T, Q>(uniform_ptr(tb), ot, in.tab.ta);
+        ld_vec<T, Q>(uniform_ptr(tb + tn), ot, in.tab.tc);
+        ld_vec<T, Q>(uniform_ptr(tb + 2 * (size_t)tn), ot, in.tab.bf);
+#pragma unroll
+        for (int st = 0; st < SMAX; ++st) {
+            const int sc = st < S ? st : S - 1;
+            ld_vec<T, Q>(uniform_ptr(tb + (size_t)(3 + 2 * sc) * tn), ot, in.tab.k1[st]);
+            ld_vec<T, Q>(uniform_ptr(tb + (size_t)(4 + 2 * sc) * tn), ot, in.tab.k2[st]);
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int j = q * 64 + lane;
+            const int j = Q * lane + q;
             const int jj = j < n ? j : n - 1;
-            const uint32_t ot = (uint32_t)jj * (uint32_t)sizeof(T);
-            in.tab.ta[q] = ld_off(uniform_ptr(tb), ot);
-            in.tab.tc[q] = ld_off(uniform_ptr(tb + n), ot);
-            in.tab.bf[q] = ld_off(uniform_ptr(tb + 2 * (size_t)n), ot);
-#pragma unroll
-            for (int st = 0; st < SMAX; ++st) {
-                const int sc = st < S ? st : S - 1;
-                in.tab.k1[st][q] = ld_off(uniform_ptr(tb + (size_t)(3 + 2 * sc) * n), ot);
-                in.tab.k2[st][q] = ld_off(uniform_ptr(tb + (size_t)(4 + 2 * sc) * n), ot);
-            }
+            const uint32_t og = (uint32_t)jj * (uint32_t)sizeof(T);
             const uint32_t od = (uint32_t)jj * (uint32_t)sizeof(double);
             in.pl[q] = in.ph[q] = in.pc[q] = 0.0;
             if (!fine) {
-                in.g[q] = ld_off(uniform_ptr(fl), ot);
+                in.g[q] = ld_off(uniform_ptr(fl), og);
             } else if (mixed) {
-                in.g[q] = ld_off(uniform_ptr(fr + (size_t)r * nr), ot);
+                in.g[q] = ld_off(uniform_ptr(fr + (size_t)r * nr), og);
                 in.pc[q] = ld_off(uniform_ptr(phi_in + (size_t)r * nr), od);
             } else {
                 in.g[q] = (T)ld_off(uniform_ptr(f + (size_t)r * nr), od);
@@ -1880,8 +1959,9 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     };
     // The line of phase ph, if this wavefront has one, then the barrier.
     // The table needs no masking: reduction steps past S are not run, and the
-    // lanes past the line's end (their loads clamped to its last unknown)
-    // meet only multipliers that are zero in the table of every unknown.
+    // unknowns past the line's end (holding the padding or the row's last
+    // group, all finite) meet only multipliers that are zero in the table of
+    // every unknown.
     auto run = [&](int ph, const UpIn<T, Q, SMAX> &in) {
         const int l = ph / 2 + 1, par = !(ph & 1), nzl = up_nzl(l);
         const bool fine = l == L;
@@ -1894,7 +1974,7 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
             T R[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const int j = q * 64 + lane;
+                const int j = Q * lane + q;
                 const bool ok = j < n;
                 const int jj = ok ? j : n - 1;
                 const T a = ulo[jj], b = uhi[jj];
@@ -1917,12 +1997,12 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
                 }
                 R[q] = ok ? in.g[q] + in.tab.ta[q] * lo + in.tab.tc[q] * hi : (T)0;
             }
-            line_pcr<T, Q, SMAX>(R, in.tab, S, lane);
+            line_pcr_adj<T, Q, SMAX>(R, in.tab, S, lane);
             T *ur = W(l, r);
             const bool own = fine && (r == i - 1 || r == i || (last && r == i + 1));
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const int j = q * 64 + lane;
+                const int j = Q * lane + q;
                 if (j >= n) continue;
                 ur[j] = R[q];
                 if (own)
@@ -1992,7 +2072,8 @@ void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path)
         off += m.nzl[l] - 2;
     }
     m.line_off[m.L + 1] = off;
-    m.tab_stride = (size_t)(3 + 2 * S) * n;
+    m.tab_row = (n + 3) & ~3;
+    m.tab_stride = (size_t)(3 + 2 * S) * m.tab_row;
     size_t lds = 0;
     for (int l = 1; l <= (mixed ? m.L : m.L - 1); ++l) lds += 2 * (size_t)m.nzl[l] * m.nr * es;
     m.solve_lds = lds;
