@@ -1887,10 +1887,13 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
         const int d = whi(l) - wlo(l);
         return par ? d / 2 + 1 : d / 2;
     };
-    // Phase ph = 0 .. 2L-1 is level ph/2 + 1, odd lines (even ph) or even
-    // lines.  A phase has at most three lines and the block three wavefronts,
-    // so wavefront w solves line w of each phase that has one.
-    const int nph = 2 * L;
+    // Level l's odd lines, then its even lines, level by level from l = 1:
+    // step k = 0 .. 2L-1 is level k/2 + 1, odd lines (even k) or even lines.
+    // Level 1 has no even line, so the phases are the steps but that one
+    // (phase ph is step ph + (ph > 0)).  A phase has at most three lines and
+    // the block three wavefronts, so wavefront w solves line w of each phase
+    // that has one.
+    const int nph = 2 * L - 1;
     const T *coarse = (const T *)m.coarse_uf;
     const T *fr = mixed ? (const T *)m.f32[L] : nullptr;  // mixed: FP32 residual
     const T *tab = (const T *)m.tab;
@@ -1907,7 +1910,8 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     // block), so that the loads in flight are the same on every path.
     const int tn = m.tab_row;
     auto fetch = [&](int ph, UpIn<T, Q, SMAX> &in) {
-        int l = ph / 2 + 1, par = !(ph & 1), t = wave;
+        const int k = ph + (ph > 0);
+        int l = k / 2 + 1, par = !(k & 1), t = wave;
         if (ph >= nph) {
             l = 1;
             par = 1;
@@ -1963,7 +1967,8 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     // group, all finite) meet only multipliers that are zero in the table of
     // every unknown.
     auto run = [&](int ph, const UpIn<T, Q, SMAX> &in) {
-        const int l = ph / 2 + 1, par = !(ph & 1), nzl = up_nzl(l);
+        const int k = ph + (ph > 0);
+        const int l = k / 2 + 1, par = !(k & 1), nzl = up_nzl(l);
         const bool fine = l == L;
         if (wave < cnt_of(l, par)) {
             const int r = (par ? wlo(l) : wlo(l) + 1) + 2 * wave;
