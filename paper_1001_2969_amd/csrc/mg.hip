@@ -103,15 +103,15 @@ __global__ void k_restrict_eps(MgLevels m, int mixed, int cpb)
     double *cur = sbuf, *nxt = sbuf + (size_t)cpb * nz;
     const int j0 = blockIdx.x * cpb;
     for (int t = threadIdx.x; t < cpb * nz; t += blockDim.x) {
-        int cj = t / nz, i = t - cj * nz, j = j0 + cj;
-        cur[t] = j < nr ? m.eps64[L][(size_t)i * nr + j] : 1.0;
+        int i = t / cpb, cj = t - i * cpb, j = j0 + cj;
+        cur[cj * nz + i] = j < nr ? m.eps64[L][(size_t)i * nr + j] : 1.0;
     }
     __syncthreads();
     int nzf = nz;
     for (int l = L - 1; l >= 1; --l) {
         const int nzc = m.nzl[l];
         for (int t = threadIdx.x; t < cpb * nzc; t += blockDim.x) {
-            int cj = t / nzc, I = t - cj * nzc, j = j0 + cj;
+            int I = t / cpb, cj = t - I * cpb, j = j0 + cj;
             const double *col = cur + (size_t)cj * nzf;
             double v;
             if (I == 0) v = col[0];
@@ -180,8 +180,10 @@ __device__ __forceinline__ void k_finalize_mg_body(const Blk &kb_, const k_final
     const int j0 = kb_.x * cpb;
     if (kb_.x == 0)
         for (int t = threadIdx.x; t < nclear; t += blockDim.x) clear[t] = 0;
+    // consecutive threads take consecutive columns of a row (contiguous
+    // loads and stores); LDS holds the block's columns one after another
     for (int t = threadIdx.x; t < cpb * nz; t += blockDim.x) {
-        const int cj = t / nz, i = t - cj * nz, j = j0 + cj;
+        const int i = t / cpb, cj = t - i * cpb, j = j0 + cj;
         double e = 1.0;
         if (j < nr) {
             const int k = i * nr + j;
@@ -192,14 +194,14 @@ __device__ __forceinline__ void k_finalize_mg_body(const Blk &kb_, const k_final
                 if (phi1) phi1[k] = b;
             }
         }
-        cur[t] = e;
+        cur[cj * nz + i] = e;
     }
     __syncthreads();
     int nzf = nz;
     for (int l = L - 1; l >= 1; --l) {
         const int nzc = m.nzl[l];
         for (int t = threadIdx.x; t < cpb * nzc; t += blockDim.x) {
-            int cj = t / nzc, I = t - cj * nzc, j = j0 + cj;
+            int I = t / cpb, cj = t - I * cpb, j = j0 + cj;
             const double *col = cur + (size_t)cj * nzf;
             double v;
             if (I == 0) v = col[0];
@@ -598,17 +600,19 @@ __device__ __forceinline__ void down_body(const double *u, const double *f, cons
     double *us = sbuf, *es = sbuf + (size_t)w * nz;
     double *cur = es + (size_t)w * nz, *nxt = cur + (size_t)cpb * nz;
     const int j0 = blk * cpb;
+    // consecutive threads take consecutive columns of a row (the loads of a
+    // row are contiguous); LDS holds the block's columns one after another
     for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
-        int cj = t / nz, i = t - cj * nz, j = j0 - 1 + cj;
+        int i = t / w, cj = t - i * w, j = j0 - 1 + cj;
         bool in = j >= 0 && j < nr;
-        us[t] = in ? u[(size_t)i * nr + j] : 0.0;
-        es[t] = in ? m.eps64[L][(size_t)i * nr + j] : 1.0;
+        us[cj * nz + i] = in ? u[(size_t)i * nr + j] : 0.0;
+        es[cj * nz + i] = in ? m.eps64[L][(size_t)i * nr + j] : 1.0;
     }
     __syncthreads();
     const double hz = m.hzl[L];
     const double iz2 = 1.0 / (hz * hz), ir2 = 1.0 / (m.hr * m.hr);
     for (int t = threadIdx.x; t < cpb * nz; t += blockDim.x) {
-        int cj = t / nz, i = t - cj * nz, j = j0 + cj;
+        int i = t / cpb, cj = t - i * cpb, j = j0 + cj;
         double r = 0.0;
         if (j < nr - 1 && i > 0 && i < nz - 1) {
             const int k = (cj + 1) * nz + i;  // staged index of (i, j)
@@ -631,7 +635,7 @@ __device__ __forceinline__ void down_body(const double *u, const double *f, cons
             r = f[(size_t)i * nr + j] - Au;
             if (mixed) m.f32[L][(size_t)i * nr + j] = (float)r;
         }
-        cur[t] = r;
+        cur[cj * nz + i] = r;
     }
     __syncthreads();
     int nzf = nz;
@@ -639,7 +643,7 @@ __device__ __forceinline__ void down_body(const double *u, const double *f, cons
         const int nzc = m.nzl[l];
         T *fo = mixed ? (T *)m.f32[l] : (T *)m.f64[l];
         for (int t = threadIdx.x; t < cpb * nzc; t += blockDim.x) {
-            int cj = t / nzc, I = t - cj * nzc, j = j0 + cj;
+            int I = t / cpb, cj = t - I * cpb, j = j0 + cj;
             double v = 0.0;
             if (I > 0 && I < nzc - 1) {
                 const double *col = cur + (size_t)cj * nzf;
