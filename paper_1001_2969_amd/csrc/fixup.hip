@@ -122,9 +122,9 @@ __device__ __forceinline__ void dead_list_body(const Blk &k, const ScanJobs &j)
         }
     }
     if (sc >= nsc) return;
-    const int64_t base = prefix_of(ch.sc_dead, sc, sh64);
     const int64_t c = sc * kSuper + threadIdx.x;
     unsigned long long m = c < nch ? ch.dead[c] : 0ull;
+    const int64_t base = prefix_of(ch.sc_dead, sc, sh64);
     int tot;
     int64_t off = base + block_excl_sum(__popcll(m), tot, sh);
     while (m) {
@@ -271,6 +271,13 @@ template <typename T> __device__ __forceinline__ void append_body(const Blk &kb,
         nch = (j.crec->n_parent + kChunk - 1) / kChunk;
         nsc = (nch + kSuper - 1) / kSuper;
     }
+    // this chunk's masks, loaded before the prefix sums (whose barriers
+    // would otherwise hold them back)
+    const unsigned long long *alive = cs == 0 ? j.ech.se : j.ech.si;
+    const int64_t c = sc * kSuper + threadIdx.x;
+    const bool inc = kids && sc < nsc && c < nch;
+    const unsigned long long am = inc ? alive[c] : 0ull;
+    const unsigned long long em = inc ? j.ech.ev[c] : 0ull;
     if (sc == 0) {
         int64_t surv = kids ? prefix_of(sc_alive, nsc, sh64) : 0;
         int64_t evs = kids ? prefix_of(j.ech.sc_ev, nsc, sh64) : 0;
@@ -285,12 +292,8 @@ template <typename T> __device__ __forceinline__ void append_body(const Blk &kb,
         }
     }
     if (!kids || sc >= nsc) return;
-    const unsigned long long *alive = cs == 0 ? j.ech.se : j.ech.si;
     const int64_t sbase = prefix_of(sc_alive, sc, sh64);
     const int64_t ebase = prefix_of(j.ech.sc_ev, sc, sh64);
-    const int64_t c = sc * kSuper + threadIdx.x;
-    const unsigned long long am = c < nch ? alive[c] : 0ull;
-    const unsigned long long em = c < nch ? j.ech.ev[c] : 0ull;
     int tot;
     const int64_t soff = sbase + block_excl_sum(__popcll(am), tot, sh);
     const int64_t eoff = ebase + block_excl_sum(__popcll(em), tot, sh);

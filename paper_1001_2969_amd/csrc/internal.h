@@ -272,6 +272,9 @@ hipError_t launch_resize(Parts<T> p, Counts *cnt, Chunks ch, CloneRec *rec, cons
                          hipStream_t st);
 // The slice sum of a merged step on its own (blockDim 256; r.bx * 256 >= nn).
 hipError_t launch_slice_sum(const SliceSum &r, hipStream_t st);
+// FP32 particles: the collisions of both species and the slice sum in one launch.
+hipError_t launch_collide_sum(const PassArgs<float> &a0, const PassArgs<float> &a1, int c0,
+                              int c1, const SliceSum &r, hipStream_t st);
 hipError_t launch_reduce_slices(unsigned long long *acc, const void *slices, int narrow, int nb,
                                 int nn, hipStream_t st);
 

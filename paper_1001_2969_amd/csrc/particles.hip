@@ -917,6 +917,34 @@ hipError_t launch_collide2(const PassArgs<T> &a0, const PassArgs<T> &a1, int c0,
         dim3(c0 + c1), dim3(threads), 0, st, Collide2Args<T>{a0, a1, c0, c1});
 }
 
+// The collisions and the slice sum in one launch: blocks [0, c0 + c1) run the
+// collision body, the rest the slice sum (independent work: the collided
+// particles' deposits and the slices' sums are integer atomics on the same
+// grids).  The slice sum's HBM reads then overlap the collisions' chains of
+// dependent loads.  FP32 particles only: there the collision body holds 98
+// VGPRs, so the slice-sum blocks keep five wavefronts per SIMD (in FP64 it
+// holds 245, one wavefront per SIMD, and the two launch apart).
+struct CollideSumArgsF {
+    Collide2Args<float> c;
+    SliceSum r;
+};
+
+__device__ __forceinline__ void collide_sum_body(const Blk &k, const CollideSumArgsF &a)
+{
+    const int nc = a.c.c0 + a.c.c1;
+    if (k.x < nc) collide2_body<float, M_FIRST>(Blk{k.x, 0, nc, 1}, a.c);
+    else slice_sum_body(Blk{k.x - nc, 0, k.nx - nc, 1}, a.r);
+}
+
+hipError_t launch_collide_sum(const PassArgs<float> &a0, const PassArgs<float> &a1, int c0,
+                              int c1, const SliceSum &r, hipStream_t st)
+{
+    const int ns = r.narrow ? 2 * r.bx : 2 * r.bx * r.by;
+    return launch<CollideSumArgsF, collide_sum_body, 256>(
+        dim3(c0 + c1 + ns), dim3(256), 0, st,
+        CollideSumArgsF{Collide2Args<float>{a0, a1, c0, c1}, r});
+}
+
 template <typename T> int pass2_lds_blocks_per_cu(int threads, size_t lds)
 {
     constexpr int kMode = M_FINAL | M_MC | M_FIRST | M_DEP | M_LISTS | M_LDS;

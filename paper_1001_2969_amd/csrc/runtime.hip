@@ -431,12 +431,18 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         const int nb = b[0] > b[1] ? b[0] : b[1];
         r.by = r.narrow ? 1 : nb < 32 ? nb : 32;
     }
-    // the collisions, then (whole-grid LDS form) the slice sum in a kernel
-    // of its own: in one launch the slice-sum blocks would run at the
-    // collision kernel's register allocation (one wavefront per SIMD).  Both
+    // the collisions and (whole-grid LDS form) the slice sum: in one launch
+    // for FP32 particles (launch_collide_sum); in FP64 the slice sum runs in
+    // a kernel of its own, since in one launch its blocks would run at the
+    // collision kernel's register allocation (one wavefront per SIMD).  All
     // are bodies a batched step runs for many discharges at once.
-    HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, c->st));
-    if (mode & M_LDS) HIPCHK(launch_slice_sum(r, c->st));
+    if constexpr (sizeof(T) == 4) {
+        if (mode & M_LDS) HIPCHK(launch_collide_sum(a[0], a[1], cb[0], cb[1], r, c->st));
+        else HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, c->st));
+    } else {
+        HIPCHK(launch_collide2<T>(a[0], a[1], cb[0], cb[1], cthreads, c->st));
+        if (mode & M_LDS) HIPCHK(launch_slice_sum(r, c->st));
+    }
     mark(c, 6);
     return RZPIC_OK;
 }
