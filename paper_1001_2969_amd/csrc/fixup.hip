@@ -58,6 +58,43 @@ __device__ __forceinline__ int64_t prefix_of(const int32_t *sc, int64_t upto, in
     return block_sum64(v, sh);
 }
 
+// Sums of a[0..upto) and b[0..upto) by the whole block in one reduction:
+// the two (non-negative, each total below 2^32) packed in one 64-bit word.
+__device__ __forceinline__ void prefix2_of(const int32_t *a, const int32_t *b, int64_t upto,
+                                           int64_t *sh, int64_t &sa, int64_t &sb)
+{
+    uint64_t v = 0;
+    for (int64_t k = threadIdx.x; k < upto; k += blockDim.x)
+        v += (uint64_t)(uint32_t)a[k] | ((uint64_t)(uint32_t)b[k] << 32);
+    const uint64_t t = (uint64_t)block_sum64((int64_t)v, sh);
+    sa = (int64_t)(t & 0xFFFFFFFFull);
+    sb = (int64_t)(t >> 32);
+}
+
+// Entries of the sorted a[0..D) below x, found by the whole wavefront: each
+// round probes 64 evenly spaced entries of the remaining range at once, so
+// that a range of D entries takes about log64(D) dependent loads instead of
+// log2(D).  Every lane returns the same count.
+__device__ __forceinline__ int64_t wave_lower_bound(const int64_t *a, int64_t D, int64_t x)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = D;  // the count lies in [lo, hi]
+    while (lo < hi) {
+        const int64_t len = hi - lo;
+        if (len <= 64) {
+            const bool t = lane < len && a[lo + lane] < x;
+            return lo + __popcll(__ballot(t));
+        }
+        const int64_t pk = lo + ((int64_t)(lane + 1) * len) / 64 - 1;  // pk(63) = hi - 1
+        const int cnt = __popcll(__ballot(a[pk] < x));
+        const int64_t pl = lo + ((int64_t)cnt * len) / 64 - 1;        // the last probe below x
+        const int64_t ph = lo + ((int64_t)(cnt + 1) * len) / 64 - 1;  // the first at or above
+        if (cnt > 0) lo = pl + 1;
+        if (cnt < 64) hi = ph;
+    }
+    return lo;
+}
+
 // Superchunk totals: block (sc, 0) sums the children masks of its 512
 // electron chunks, blocks (sc, 1 + s) the dead masks of species s.
 __device__ __forceinline__ void scan_body(const Blk &k, const ScanJobs &j)
@@ -172,13 +209,7 @@ __device__ __forceinline__ void fill_body(const Blk &kb, const Parts<T> &p, cons
 {
     const int64_t D = fix->dead, keep = fix->keep;
     if (D == 0) return;
-    int64_t lo = 0, hi = D;  // H = number of dead indices < keep
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (dead[mid] < keep) lo = mid + 1;
-        else hi = mid;
-    }
-    const int64_t H = lo;
+    const int64_t H = wave_lower_bound(dead, D, keep);  // dead indices < keep
     for (int64_t m = kb.x * (int64_t)blockDim.x + threadIdx.x; m < H;
          m += (int64_t)kb.nx * blockDim.x) {
         int64_t a = 0, b = D - H;
@@ -279,8 +310,8 @@ template <typename T> __device__ __forceinline__ void append_body(const Blk &kb,
     const unsigned long long am = inc ? alive[c] : 0ull;
     const unsigned long long em = inc ? j.ech.ev[c] : 0ull;
     if (sc == 0) {
-        int64_t surv = kids ? prefix_of(sc_alive, nsc, sh64) : 0;
-        int64_t evs = kids ? prefix_of(j.ech.sc_ev, nsc, sh64) : 0;
+        int64_t surv = 0, evs = 0;
+        if (kids) prefix2_of(sc_alive, j.ech.sc_ev, nsc, sh64, surv, evs);
         if (threadIdx.x == 0) {
             const int64_t room = cap - keep;
             if (surv > room) {
@@ -292,11 +323,21 @@ template <typename T> __device__ __forceinline__ void append_body(const Blk &kb,
         }
     }
     if (!kids || sc >= nsc) return;
-    const int64_t sbase = prefix_of(sc_alive, sc, sh64);
-    const int64_t ebase = prefix_of(j.ech.sc_ev, sc, sh64);
+    int64_t sbase, ebase;
+    prefix2_of(sc_alive, j.ech.sc_ev, sc, sh64, sbase, ebase);
+    // both in-block scans in one: survivors in the low 16 bits (at most
+    // 512 x 64 in a superchunk), events above (whose superchunk total, from
+    // the scan, must stay below 2^15 for the packed int; else two scans)
     int tot;
-    const int64_t soff = sbase + block_excl_sum(__popcll(am), tot, sh);
-    const int64_t eoff = ebase + block_excl_sum(__popcll(em), tot, sh);
+    int64_t soff, eoff;
+    if (j.ech.sc_ev[sc] < 32768) {
+        const int both = block_excl_sum(__popcll(am) | (__popcll(em) << 16), tot, sh);
+        soff = sbase + (both & 0xFFFF);
+        eoff = ebase + (both >> 16);
+    } else {
+        soff = sbase + block_excl_sum(__popcll(am), tot, sh);
+        eoff = ebase + block_excl_sum(__popcll(em), tot, sh);
+    }
     const uint64_t id0 = j.crec->next_id_old[cs];
     const Parts<T> &dst = g.dst[cs], &stage = g.stage[cs];
     unsigned long long m = am;
