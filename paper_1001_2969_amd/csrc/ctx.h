@@ -97,6 +97,8 @@ struct rzpic_ctx {
     int slice_blocks = 0;
     bool lds_ok = false;    // the whole deposit grid fits one block's LDS (slices allocated)
     bool lds_form = false;  // the fused pass uses that form (else the tiled windows)
+    int lds_resident = 0;   // blocks of that form resident at once for the current thread
+                            //    count (at most slice_blocks): the merged pass's block count
     rz::MgLevels mg{};
     // device scalars
     rz::Counts *cnt;

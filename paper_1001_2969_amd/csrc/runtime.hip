@@ -239,6 +239,23 @@ int pass_blocks(const rzpic_ctx *c, int s, int most)
     return (int)(want < 1 ? 1 : (want < most ? want : most));
 }
 
+// Blocks of the whole-grid LDS pass that fit on the device at once with
+// `threads` per block (LDS, wavefronts and registers), at most the slices
+// allocated: the merged pass runs one round of blocks.
+int lds_resident_of(const rzpic_ctx *c, int threads)
+{
+    const size_t lds = (size_t)c->nn * (c->mixed ? sizeof(uint32_t) : sizeof(unsigned long long));
+    int per_cu = (int)(c->lds_cu / (lds + 1024));
+    const int wave_cap = 2048 / threads;
+    const int occ = c->mixed ? pass2_lds_blocks_per_cu<float>(threads, lds)
+                             : pass2_lds_blocks_per_cu<double>(threads, lds);
+    if (per_cu > wave_cap) per_cu = wave_cap;
+    if (per_cu > occ) per_cu = occ;
+    if (per_cu < 1) per_cu = 1;
+    const int b = c->cus * per_cu;
+    return b < c->slice_blocks ? b : c->slice_blocks;
+}
+
 // Blocks of the tiled pass of species s: at most the blocks the merged pass
 // keeps resident at once, shared by the two species (one round, no tail).
 // The window plan of the sort is made for this count.
@@ -373,10 +390,11 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
     if (c->lds_form) {
         mode |= M_LDS;
         lds = (size_t)c->nn * lds_elem<T>();
-        b[0] = pass_blocks(c, 0, c->slice_blocks / 2);
-        b[1] = pass_blocks(c, 1, c->slice_blocks - c->slice_blocks / 2);
+        const int most = c->lds_resident;
+        b[0] = pass_blocks(c, 0, most / 2);
+        b[1] = pass_blocks(c, 1, most - most / 2);
         if (!ions) {  // the electrons take the ions' blocks too
-            b[0] = b[0] + b[1] < c->slice_blocks ? b[0] + b[1] : c->slice_blocks;
+            b[0] = b[0] + b[1] < most ? b[0] + b[1] : most;
             b[1] = 0;
         }
     } else {
@@ -410,7 +428,11 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
     int cb[2];
     for (int s = 0; s < 2; ++s) {
         const double expect = c->sp[s].p_null * (double)c->sp[s].cap;
-        const int want = expect > 16.0 * b[s] ? 2 * b[s] : b[s];
+        // at least three wavefronts per CU when there are many candidates, so
+        // that fewer, larger pass blocks (more threads each) do not thin
+        // out the collisions' waves
+        const int many = 2 * b[s] > 3 * c->cus ? 2 * b[s] : 3 * c->cus;
+        const int want = expect > 16.0 * b[s] ? many : b[s];
         cb[s] = (want + wpb - 1) / wpb;
         if (a[s].sp.mc_model == RZPIC_MC_NONE) cb[s] = 1;
     }
@@ -1158,6 +1180,7 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
         }
         A(c->slices, (size_t)c->slice_blocks * nn)
         c->lds_ok = c->lds_form = true;
+        c->lds_resident = c->slice_blocks;
     } else {
         c->tile_per_cu = c->mixed ? pass2_tiled_blocks_per_cu<float>(c->pass_threads)
                                   : pass2_tiled_blocks_per_cu<double>(c->pass_threads);
@@ -1682,7 +1705,9 @@ static rzpic_status set_pass_config(rzpic_ctx *c, int threads, int64_t ppb, bool
     c->pass_threads = threads;
     c->parts_per_block = ppb;
     c->lds_form = lds && c->lds_ok;
-    if (!c->lds_form)
+    if (c->lds_form)
+        c->lds_resident = lds_resident_of(c, threads);
+    else
         c->tile_per_cu = c->mixed ? pass2_tiled_blocks_per_cu<float>(threads)
                                   : pass2_tiled_blocks_per_cu<double>(threads);
     // the tile plan is made for the tiled pass's block count: plan again
@@ -1712,8 +1737,9 @@ static bool config_fits(const rzpic_ctx *c, int threads, int64_t ppb, bool lds)
                                  : pass2_tiled_blocks_per_cu<double>(threads);
     int b0, b1;
     if (lds) {
-        b0 = pass_blocks(&t, 0, c->slice_blocks / 2);
-        b1 = pass_blocks(&t, 1, c->slice_blocks - c->slice_blocks / 2);
+        const int most = lds_resident_of(c, threads);
+        b0 = pass_blocks(&t, 0, most / 2);
+        b1 = pass_blocks(&t, 1, most - most / 2);
     } else {
         b0 = tiled_blocks(&t, 0);
         b1 = tiled_blocks(&t, 1);
