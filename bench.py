@@ -58,7 +58,7 @@ def measured_traffic(name, shape=None):
 
 
 def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, tune=False,
-            shape=None, graph=False):
+            shape=None, graph=False, pipeline=True):
     """Throughput over `steps` merged steps with nothing else on the stream,
     then `timing_steps` more with the library's HIP events around each phase
     (per-phase device times; every event costs the stream a few microseconds,
@@ -67,7 +67,10 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, 
     steps precede the warm-up); shape: (threads, particles per block) set
     instead.  graph: after the timed steps, `timing_steps` more captured and
     replayed as HIP graphs (rzpic_set_step_graph, on a stream of the
-    context's own) are timed too."""
+    context's own) are timed too.  pipeline: the timed steps pipelined
+    (rzpic_set_step_pipeline: each step prepares the next step's grid in its
+    list maintenance launches, same results bit for bit); as many
+    unpipelined steps are timed after them for comparison."""
     import torch
 
     from paper_1001_2969_amd import rzpic
@@ -87,6 +90,7 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, 
         tuning_steps = n
     elif shape is not None:
         ctx.set_pass_shape(*shape)
+    ctx.set_step_pipeline(pipeline)
     for _ in range(warmup):
         ctx.step(n)
         n += 1
@@ -100,6 +104,19 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, 
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     d1 = ctx.diag()
+    direct_ms = None
+    if pipeline:
+        ctx.set_step_pipeline(False)
+        for _ in range(5):
+            ctx.step(n)
+            n += 1
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(steps):
+            ctx.step(n)
+            n += 1
+        torch.cuda.synchronize()
+        direct_ms = 1e3 * (time.perf_counter() - t2) / steps
     graph_ms = None
     if graph:
         ctx.use_stream(torch.cuda.Stream())
@@ -115,6 +132,7 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, 
         torch.cuda.synchronize()
         graph_ms = 1e3 * (time.perf_counter() - t2) / timing_steps
         ctx.set_step_graph(False)
+    ctx.set_step_pipeline(pipeline)
     ctx.set_timing(True)
     ctx.timing()  # reset accumulators
     for _ in range(timing_steps):
@@ -131,6 +149,7 @@ def run_gpu(w, precision, steps, warmup, timing_steps=50, capacity_factor=1.25, 
         "pass_shape": None if shape is None else {"threads": shape[0],
                                                   "particles_per_block": shape[1]},
         "tuning_steps": tuning_steps, "graph_ms_per_step": graph_ms,
+        "pipelined": pipeline, "unpipelined_ms_per_step": direct_ms,
     }
 
 
@@ -624,6 +643,8 @@ def main():
                     help="keep the default pass launch shape (no autotuning)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the graph-replayed steps timed after the headline steps")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="time unpipelined steps (no rzpic_set_step_pipeline) as the headline")
     ap.add_argument("--no-circuit", action="store_true",
                     help="skip the external-circuit and ion-subcycling forms")
     ap.add_argument("--pmc-run", type=int, default=0, metavar="STEPS",
@@ -661,14 +682,14 @@ def main():
     print(f"# workload {w.name}: warmup {args.warmup}, timed {args.steps} steps", file=sys.stderr,
           flush=True)
     ctx_m, mixed = run_gpu(w, "mixed", args.steps, args.warmup, tune=not args.no_tune,
-                           graph=not args.no_graph)
+                           graph=not args.no_graph, pipeline=not args.no_pipeline)
     print(f"# mixed: {mixed['value']:.4g} particle-steps/s, {mixed['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)
     fp64 = None
     rho = chi = phi = None
     if not args.no_fp64:
         ctx_d, fp64 = run_gpu(w, "fp64", args.steps, args.warmup, tune=not args.no_tune,
-                              graph=not args.no_graph)
+                              graph=not args.no_graph, pipeline=not args.no_pipeline)
         print(f"# fp64: {fp64['value']:.4g} particle-steps/s, {fp64['ms_per_step']:.4f} ms/step",
               file=sys.stderr, flush=True)
         rho, chi, phi = (ctx_d.grid(g) for g in (rzpic.G_RHO, rzpic.G_CHI, rzpic.G_PHI))
@@ -736,6 +757,8 @@ def main():
                    "pass_shape": mixed["pass_shape"],
                    "autotune_steps": mixed["tuning_steps"]},
         "graph_ms_per_step": mixed["graph_ms_per_step"],
+        "pipelined": mixed["pipelined"],
+        "unpipelined_ms_per_step": mixed["unpipelined_ms_per_step"],
         "breakdown_ms_per_step": {k: tm[k] for k in ("step_ms", "solve_ms", "pass_ms",
                                                      "collide_ms", "grid_ms", "lists_ms",
                                                      "resize_ms", "sort_ms")},
@@ -743,6 +766,7 @@ def main():
         "fp64": None if fp64 is None else {
             "value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
             "graph_ms_per_step": fp64["graph_ms_per_step"],
+            "unpipelined_ms_per_step": fp64["unpipelined_ms_per_step"],
             "breakdown_ms_per_step": {k: fp64["timing"][k] for k in
                                       ("step_ms", "solve_ms", "pass_ms", "collide_ms")},
             "pass_GBps": BYTES_PER_PARTICLE["fp64"] * (fp64["timing"]["n0"] +

@@ -285,6 +285,23 @@ rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
  * The executable graphs are freed by rzpic_destroy. */
 rzpic_status rzpic_set_step_graph(rzpic_ctx *ctx, int32_t on);
 
+/* Step pipelining of rzpic_step (off by default): a directly launched step
+ * n that makes no weight split also prepares the grid of step n + 1 (the
+ * finalize of its deposit, the epsilon levels, the Dirichlet values for the
+ * voltage at t = (n+2) dt, the line tables and the first restriction of the
+ * solve), in the launches of its own list maintenance; step n + 1, if it
+ * comes next, skips that preparation and clears the deposit grids and the
+ * Monte Carlo counters in its E launch.  Particles, potentials and
+ * counters after every step are those of unpipelined steps, bit for bit;
+ * between steps, rho, chi, eps, the densities and the electrode rows of phi
+ * are already those of the next step.  Applies only to the split solve path
+ * with a fixed number of cycles and no external circuit; graph-replayed and
+ * batched steps prepare their own grid.  Every call that changes particles,
+ * deposits, potentials, voltages or solver settings drops the preparation;
+ * writes through a grid view (rzpic_grid_view) between steps do not, so a
+ * caller that writes phi there turns pipelining off first. */
+rzpic_status rzpic_set_step_pipeline(rzpic_ctx *ctx, int32_t on);
+
 /* Launch shape of the fused particle pass: threads per block (256, 512, 768
  * or 1024) and particles of capacity per block (default 512 threads, 8192).
  * Results do not depend on it (integer deposit, identities from event

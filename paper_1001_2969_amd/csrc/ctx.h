@@ -144,4 +144,11 @@ struct rzpic_ctx {
     // step's arguments
     bool step_graph = false;
     hipGraphExec_t gexec[8] = {};
+    // step pipelining (rzpic_set_step_pipeline): a directly launched step
+    // also prepares the grid of step `prepared` (-1: none) in the launches
+    // of its list maintenance; prep_ready tells the next solve that the
+    // line tables and the first way down are in place (consumed by it)
+    bool pipeline = false;
+    int64_t prepared = -1;
+    bool prep_ready = false;
 };

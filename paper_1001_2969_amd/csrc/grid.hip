@@ -31,6 +31,10 @@ struct k_efield_A {
     double *er;
     double *ez;
     typename Vec2<T>::type *E2;
+    unsigned long long *zero0;  // cleared on every node when set
+    unsigned long long *zero1;
+    unsigned long long *clear;  // cleared by block 0: nclear counters
+    int nclear;
 };
 
 template <typename T>
@@ -46,6 +50,8 @@ __device__ __forceinline__ void k_efield_body(const Blk &kb_, const k_efield_A<T
     auto E2 = A_.E2;
 
     const int nn = nr * nz;
+    if (kb_.x == 0)
+        for (int t = threadIdx.x; t < A_.nclear; t += blockDim.x) A_.clear[t] = 0;
     for (int g = kb_.x * blockDim.x + threadIdx.x; g < nn; g += kb_.nx * blockDim.x) {
         int i = g / nr, j = g - i * nr;
         double vz, vr;
@@ -61,16 +67,20 @@ __device__ __forceinline__ void k_efield_body(const Blk &kb_, const k_efield_A<T
         e.x = (T)vr;
         e.y = (T)vz;
         E2[g] = e;
+        if (A_.zero0) A_.zero0[g] = 0;
+        if (A_.zero1) A_.zero1[g] = 0;
     }
 }
 
 
 template <typename T>
 hipError_t launch_efield(int nr, int nz, double hr, double hz, const double *phi, double *er,
-                         double *ez, typename Vec2<T>::type *E2, hipStream_t st)
+                         double *ez, typename Vec2<T>::type *E2, hipStream_t st,
+                         unsigned long long *zero0, unsigned long long *zero1,
+                         unsigned long long *clear, int nclear)
 {
     int nn = nr * nz, threads = 256, blocks = (nn + threads - 1) / threads;
-    (void)launch<k_efield_A<T>, k_efield_body<T>, 256>(dim3(blocks), dim3(threads), 0, st, k_efield_A<T>{nr, nz, hr, hz, phi, er, ez, E2});
+    (void)launch<k_efield_A<T>, k_efield_body<T>, 256>(dim3(blocks), dim3(threads), 0, st, k_efield_A<T>{nr, nz, hr, hz, phi, er, ez, E2, zero0, zero1, clear, nclear});
     return hipGetLastError();
 }
 
@@ -134,8 +144,10 @@ template hipError_t launch_pack_e2<double>(int, const double *, const double *, 
 template hipError_t launch_pack_e2<float>(int, const double *, const double *, float2 *,
                                           hipStream_t);
 template hipError_t launch_efield<double>(int, int, double, double, const double *, double *,
-                                          double *, double2 *, hipStream_t);
+                                          double *, double2 *, hipStream_t, unsigned long long *,
+                                          unsigned long long *, unsigned long long *, int);
 template hipError_t launch_efield<float>(int, int, double, double, const double *, double *,
-                                         double *, float2 *, hipStream_t);
+                                         double *, float2 *, hipStream_t, unsigned long long *,
+                                         unsigned long long *, unsigned long long *, int);
 
 }  // namespace rz

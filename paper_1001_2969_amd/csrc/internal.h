@@ -316,7 +316,9 @@ struct GridArgs {
 hipError_t launch_finalize(const GridArgs &g, hipStream_t st);
 template <typename T>
 hipError_t launch_efield(int nr, int nz, double hr, double hz, const double *phi, double *er,
-                         double *ez, typename Vec2<T>::type *E2, hipStream_t st);
+                         double *ez, typename Vec2<T>::type *E2, hipStream_t st,
+                         unsigned long long *zero0 = nullptr, unsigned long long *zero1 = nullptr,
+                         unsigned long long *clear = nullptr, int nclear = 0);
 template <typename T>
 hipError_t launch_pack_e2(int nn, const double *er, const double *ez, typename Vec2<T>::type *E2,
                           hipStream_t st);
@@ -393,5 +395,14 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
 // runs mg_vcycle with skip_down = 1.
 hipError_t mg_prep(const MgLevels &m, int mixed, const double *phi, const double *f,
                    hipStream_t st);
+// Step pipelining: the superchunk totals of the list maintenance (as
+// launch_scan) beside mg_finalize without its counter clearing (nothing is
+// cleared: the deposit grids keep their values), then the dead lists (as
+// launch_dead_list) beside mg_prep; the split path only.
+hipError_t mg_finalize_scan(const GridArgs &g, const MgLevels &m, int mixed, double *phi0,
+                            double *phi1, double V, const ScanJobs &j, int64_t max_chunks,
+                            hipStream_t st);
+hipError_t mg_prep_dead_list(const MgLevels &m, int mixed, const double *phi, const double *f,
+                             const ScanJobs &j, int64_t max_chunks, hipStream_t st);
 
 }  // namespace rz

@@ -4,6 +4,7 @@
 // sweep of exact r-line solves (parallel cyclic reduction in LDS, one block
 // per line).
 #include "device.h"
+#include "lists.h"
 
 namespace rz {
 
@@ -1201,6 +1202,90 @@ hipError_t mg_prep(const MgLevels &m, int mixed, const double *phi, const double
         (void)launch<k_prep_A<float>, k_prep_body<float>, 256>(dim3(nfb + nd), dim3(256), lds, st, k_prep_A<float>{phi, f, m, mixed, cpb, nfb});
     else
         (void)launch<k_prep_A<double>, k_prep_body<double>, 256>(dim3(nfb + nd), dim3(256), lds, st, k_prep_A<double>{phi, f, m, mixed, cpb, nfb});
+    return hipGetLastError();
+}
+
+// Step pipelining: the list maintenance of one step runs beside the grid
+// preparation of the next, in two launches of kSuper threads instead of
+// four.  The grid blocks come first (the longer chains), then the list
+// blocks, (superchunk, job) flattened superchunk-fastest.  The bodies loop
+// over blockDim.x, so they run unchanged at this width.
+struct k_fin_scan_A {
+    k_finalize_mg_A f;
+    ScanJobs j;
+    int nf, nsc;
+};
+
+__device__ __forceinline__ void k_fin_scan_body(const Blk &kb_, const k_fin_scan_A &A_)
+{
+    if (kb_.x < A_.nf) {
+        k_finalize_mg_body(Blk{kb_.x, 0, A_.nf, 1}, A_.f);
+        return;
+    }
+    const int b = kb_.x - A_.nf;
+    scan_body(Blk{b % A_.nsc, b / A_.nsc, A_.nsc, 3}, A_.j);
+}
+
+template <typename T> struct k_prep_dl_A {
+    k_prep_A<T> p;
+    ScanJobs j;
+    int np, nsc;
+};
+
+template <typename T>
+__device__ __forceinline__ void k_prep_dl_body(const Blk &kb_, const k_prep_dl_A<T> &A_)
+{
+    if (kb_.x < A_.np) {
+        k_prep_body<T>(Blk{kb_.x, 0, A_.np, 1}, A_.p);
+        return;
+    }
+    const int b = kb_.x - A_.np;
+    dead_list_body(Blk{b % A_.nsc, b / A_.nsc, A_.nsc, 2}, A_.j);
+}
+
+static int superchunks(int64_t max_chunks)
+{
+    const int64_t nsc = (max_chunks + kSuper - 1) / kSuper;
+    return nsc < 1 ? 1 : (int)nsc;
+}
+
+hipError_t mg_finalize_scan(const GridArgs &g, const MgLevels &m, int mixed, double *phi0,
+                            double *phi1, double V, const ScanJobs &j, int64_t max_chunks,
+                            hipStream_t st)
+{
+    const int nz = m.nzl[m.L];
+    int cpb = cols_per_block(nz);
+    if (cpb < 1) cpb = 1;
+    const int nf = (m.nr + cpb - 1) / cpb, nsc = superchunks(max_chunks);
+    const size_t lds = 2 * (size_t)cpb * nz * sizeof(double);
+    static_assert(sizeof(k_fin_scan_A) <= 4096, "kernel arguments");
+    (void)launch<k_fin_scan_A, k_fin_scan_body, kSuper>(
+        dim3(nf + 3 * nsc), dim3(kSuper), lds, st,
+        k_fin_scan_A{k_finalize_mg_A{g, m, mixed, cpb, phi0, phi1, V, nullptr, 0}, j, nf, nsc});
+    return hipGetLastError();
+}
+
+hipError_t mg_prep_dead_list(const MgLevels &m, int mixed, const double *phi, const double *f,
+                             const ScanJobs &j, int64_t max_chunks, hipStream_t st)
+{
+    const int nz = m.nzl[m.L], n = m.nr - 1;
+    const int cpb = cols_per_block(nz);
+    const int nfb = m.line_off[m.L + 1], nd = (n + cpb - 1) / cpb, nsc = superchunks(max_chunks);
+    size_t lds = down_lds(nz, cpb);
+    const size_t lf = 3 * (size_t)n * (mixed ? sizeof(float) : sizeof(double));
+    if (lf > lds) lds = lf;
+    const dim3 grid(nfb + nd + 2 * nsc);
+    if (mixed) {
+        static_assert(sizeof(k_prep_dl_A<float>) <= 4096, "kernel arguments");
+        (void)launch<k_prep_dl_A<float>, k_prep_dl_body<float>, kSuper>(
+            grid, dim3(kSuper), lds, st,
+            k_prep_dl_A<float>{k_prep_A<float>{phi, f, m, mixed, cpb, nfb}, j, nfb + nd, nsc});
+    } else {
+        static_assert(sizeof(k_prep_dl_A<double>) <= 4096, "kernel arguments");
+        (void)launch<k_prep_dl_A<double>, k_prep_dl_body<double>, kSuper>(
+            grid, dim3(kSuper), lds, st,
+            k_prep_dl_A<double>{k_prep_A<double>{phi, f, m, mixed, cpb, nfb}, j, nfb + nd, nsc});
+    }
     return hipGetLastError();
 }
 

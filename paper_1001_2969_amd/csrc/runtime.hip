@@ -483,9 +483,20 @@ template <typename T> rzpic_status run_staged(rzpic_ctx *c, int cs, int mode)
     return RZPIC_OK;
 }
 
+// The next step's grid preparation run by a step's list maintenance (step
+// pipelining): mg_finalize's arguments (no clearing) and the solve's
+// electrode voltage.
+struct NextGrid {
+    GridArgs g;
+    double V;
+};
+
 // List maintenance of the species in `which` (bit s): superchunk totals,
-// sorted dead lists, hole filling, appending of staged children.
-template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
+// sorted dead lists, hole filling, appending of staged children.  With
+// `next`, the superchunk totals and the dead lists run beside the next
+// step's grid preparation (mg_finalize_scan, mg_prep_dead_list).
+template <typename T>
+rzpic_status run_fixup(rzpic_ctx *c, int which, const NextGrid *next = nullptr)
 {
     ScanJobs j{};
     j.children = (c->children_pending[0] || c->children_pending[1]) && !c->children_scanned;
@@ -505,9 +516,16 @@ template <typename T> rzpic_status run_fixup(rzpic_ctx *c, int which)
         int64_t nch = (c->sp[s].cap + kChunk - 1) / kChunk;
         if (c->sp[s].bound && nch > max_chunks) max_chunks = nch;
     }
-    HIPCHK(launch_scan(j, max_chunks, c->st));
+    if (next)
+        HIPCHK(mg_finalize_scan(next->g, c->mg, c->mixed, c->phi, c->phi_alt, next->V, j,
+                                max_chunks, c->st));
+    else
+        HIPCHK(launch_scan(j, max_chunks, c->st));
     if (j.children) c->children_scanned = true;
-    HIPCHK(launch_dead_list(j, max_chunks, c->st));
+    if (next)
+        HIPCHK(mg_prep_dead_list(c->mg, c->mixed, c->phi, c->f, j, max_chunks, c->st));
+    else
+        HIPCHK(launch_dead_list(j, max_chunks, c->st));
     if (j.dead[0] && j.dead[1]) {
         HIPCHK(launch_fill2<T>(parts_of<T>(c->sp[0].v), parts_of<T>(c->sp[1].v), c->sp[0].ch,
                                c->sp[1].ch, c->fix, c->fix + 1, c->st));
@@ -545,8 +563,10 @@ rzpic_status run_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, cons
 {
     const bool ob = c->mg.one_block != 0;
     bool down_done = false;  // the first cycle's restriction came with the tables
+    const bool ready = c->prep_ready;  // tables and restriction made by the previous step
+    c->prep_ready = false;
     if (c->mg.split) {
-        HIPCHK(mg_prep(c->mg, c->mixed, u, f, c->st));
+        if (!ready) HIPCHK(mg_prep(c->mg, c->mixed, u, f, c->st));
         down_done = true;
     } else if (ob) {
         HIPCHK(mg_factor(c->mg, c->mixed, c->st));
@@ -720,14 +740,22 @@ rzpic_status solve_impl(rzpic_ctx *c, double t, bool prepared, int32_t *cycles, 
     return st;
 }
 
-rzpic_status efield_impl(rzpic_ctx *c)
+// prepared: the grid of this step was finalized by the previous step's
+// list maintenance (step pipelining), which leaves the deposit grids and the
+// Monte Carlo counters as they were: they are cleared here instead, before
+// the pass (the ion grid only if the ions move in this step).
+rzpic_status efield_impl(rzpic_ctx *c, bool prepared = false, bool ions = true)
 {
+    unsigned long long *z0 = prepared ? c->acc[0] : nullptr;
+    unsigned long long *z1 = prepared && ions ? c->acc[1] : nullptr;
+    unsigned long long *cl = prepared ? c->mcstat : nullptr;
+    const int ncl = prepared ? 2 * (1 + kMaxProc) : 0;
     if (c->mixed)
         HIPCHK(launch_efield<float>(c->c.nr, c->c.nz, c->hr, c->hz, c->phi, c->er, c->ez,
-                                    (float2 *)c->E2, c->st));
+                                    (float2 *)c->E2, c->st, z0, z1, cl, ncl));
     else
         HIPCHK(launch_efield<double>(c->c.nr, c->c.nz, c->hr, c->hz, c->phi, c->er, c->ez,
-                                     (double2 *)c->E2, c->st));
+                                     (double2 *)c->E2, c->st, z0, z1, cl, ncl));
     return RZPIC_OK;
 }
 
@@ -923,16 +951,29 @@ rzpic_status flush_timing(rzpic_ctx *c)
     return RZPIC_OK;
 }
 
-template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
+// Whether step pipelining can prepare the grid of the step after a step
+// that makes no weight split: the split solve path (mg_prep), one operator
+// per step (no circuit) and a fixed number of cycles.
+static bool can_prepare(const rzpic_ctx *c)
+{
+    return c->mg.split && c->c.circuit_C <= 0.0 && c->c.mg_fixed_cycles > 0;
+}
+
+// pipe: step pipelining (a directly launched step with rzpic_set_step_pipeline
+// on); this step then skips its grid preparation when the previous step made
+// it, and makes the next step's when it can.
+template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n, bool pipe = false)
 {
     TRY(need_both(c));
     if (c->children_pending[0] || c->children_pending[1])
         return fail(RZPIC_ESTATE, "new particles are staged: call rzpic_compact first");
     if (c->timing && c->ev_used >= rzpic_ctx::kPool) TRY(flush_timing(c));
+    const bool pre = pipe && c->prepared == n;
+    c->prepared = -1;
     mark(c, 0);
     // subcycled ions move only in every K-th step
     const bool ions = n % ion_K(c) == ion_K(c) - 1;
-    {
+    if (!pre) {
         // finalize, eps restriction, Dirichlet values of both phi buffers and
         // the Monte Carlo counters cleared, in one launch
         const double t = (double)(n + 1) * c->c.dt;
@@ -943,23 +984,38 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
                            2 * (1 + kMaxProc), c->st));
     }
     mark(c, 1);
-    TRY(solve_impl(c, (double)(n + 1) * c->c.dt, true, nullptr, nullptr));
+    c->prep_ready = pre;
+    const rzpic_status ss = solve_impl(c, (double)(n + 1) * c->c.dt, true, nullptr, nullptr);
+    c->prep_ready = false;
+    TRY(ss);
     c->acc_cycles += c->last_cycles;
     mark(c, 2);
-    TRY(efield_impl(c));
+    TRY(efield_impl(c, pre, ions));
     mark(c, 3);
     TRY(run_pass_both<T>(c, (uint32_t)n, ions));
     if (!ions)  // the ions keep state and deposit; their compaction only appends children
         HIPCHK(launch_fill_u64(c->sp[1].ch.dead, c->sp[1].nchunks_max, c->st));
     c->children_pending[0] = c->children_pending[1] = c->sp[0].v.mc_model == RZPIC_MC_ELECTRON;
     c->children_scanned = false;
-    TRY(run_fixup<T>(c, 3));
-    mark(c, 7);
     // Weight split, then the deposit from scratch; a tile sort due at this
     // step runs in between (the fixed-point deposit does not depend on the
     // particle order, and the sorted order gives the deposit its windows).
     const bool resize = c->c.resize_every > 0 && n % c->c.resize_every == c->c.resize_every - 1;
     const bool sort = c->c.sort_every > 0 && n % c->c.sort_every == c->c.sort_every - 1;
+    // step pipelining: the deposit is final once the collisions have run
+    // (no weight split follows), so the next step's grid preparation runs
+    // in the list maintenance's launches; it leaves the deposit grids and
+    // the counters to the next step's E launch
+    const bool prep_next = pipe && !resize && can_prepare(c) && n + 1 <= 0xFFFFFFFELL;
+    NextGrid next{};
+    if (prep_next) {
+        const int64_t m = n + 1;
+        const double t = (double)(m + 1) * c->c.dt;
+        next.V = c->c.V_dc + c->c.V_rf * std::sin(kTwoPi * c->c.f_rf * t);
+        next.g = grid_args(c, 0, m % ion_K(c) == ion_K(c) - 1);
+    }
+    TRY(run_fixup<T>(c, 3, prep_next ? &next : nullptr));
+    mark(c, 7);
     if (resize) {
         for (int s = 0; s < 2; ++s) TRY(resize_impl<T>(c, s, n));
         TRY(zero_order_compact<T>(c, 3));
@@ -973,6 +1029,7 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n)
     }
     mark(c, 9);
     if (c->timing) c->ev_used++;
+    if (prep_next) c->prepared = n + 1;
     return RZPIC_OK;
 }
 
@@ -1026,6 +1083,11 @@ rzpic_status rz_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, doubl
 
 // ===========================================================================
 // C ABI
+
+// Calls that change what the next step's grid preparation reads (particles,
+// deposits, potentials, voltages, solver settings) drop a preparation made by
+// step pipelining; the next step then prepares its grid itself.
+static void unprepare(rzpic_ctx *c) { c->prepared = -1; }
 
 extern "C" {
 
@@ -1299,6 +1361,7 @@ rzpic_status rzpic_destroy(rzpic_ctx *c)
 rzpic_status rzpic_set_stream(rzpic_ctx *c, void *stream)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    unprepare(c);
     c->st = (hipStream_t)stream;
     return RZPIC_OK;
 }
@@ -1306,6 +1369,7 @@ rzpic_status rzpic_set_stream(rzpic_ctx *c, void *stream)
 rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_view *v)
 {
     if (!c || !v) return fail(RZPIC_EINVAL, "null argument");
+    unprepare(c);
     if (s < 0 || s > 1) return fail(RZPIC_EINVAL, "species %d out of range", s);
     if (!v->r || !v->z || !v->vr || !v->vt || !v->vz || !v->ar || !v->az || !v->w || !v->id)
         return fail(RZPIC_EINVAL, "species %d: null particle array", s);
@@ -1362,6 +1426,7 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
 rzpic_status rzpic_set_count(rzpic_ctx *c, int32_t s, int64_t n, uint64_t next_id)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (n < 0 || n > c->sp[s].cap)
         return fail(RZPIC_EINVAL, "count %lld outside [0, capacity %lld]", (long long)n,
                     (long long)c->sp[s].cap);
@@ -1388,6 +1453,7 @@ rzpic_status rzpic_set_xsec(rzpic_ctx *c, int32_t s, int32_t nproc, const int32_
                             double ej_B)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (nproc < 1 || nproc > kMaxProc || ne < 2 || !(de > 0) || !kind || !thr_eV || !sigma)
         return fail(RZPIC_EINVAL, "cross sections: need 1 <= nproc <= %d, ne >= 2, de > 0", kMaxProc);
     for (int k = 0; k < nproc; ++k)
@@ -1468,6 +1534,7 @@ rzpic_status rzpic_init_particles(rzpic_ctx *c, int32_t s, int64_t n, double n0,
                                   uint64_t id0)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (n < 0 || n > c->sp[s].cap) return fail(RZPIC_EINVAL, "n = %lld exceeds capacity", (long long)n);
     if (!(T_eV >= 0) || !(n0 >= 0)) return fail(RZPIC_EINVAL, "need n0 >= 0 and T_eV >= 0");
     Phys ph = phys_of(c);
@@ -1483,6 +1550,7 @@ rzpic_status rzpic_init_particles(rzpic_ctx *c, int32_t s, int64_t n, double n0,
 rzpic_status rzpic_push_first(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (c->mixed) {
         TRY(run_pass<float>(c, s, M_FIRST | M_MARK, 0));
         if (c->children_pending[s]) TRY(run_staged<float>(c, s, M_FIRST));
@@ -1496,6 +1564,7 @@ rzpic_status rzpic_push_first(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_push_final(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (c->mixed) TRY(run_pass<float>(c, s, M_FINAL | M_MARK, 0));
     else TRY(run_pass<double>(c, s, M_FINAL | M_MARK, 0));
     return RZPIC_OK;
@@ -1504,6 +1573,7 @@ rzpic_status rzpic_push_final(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_collide(rzpic_ctx *c, int32_t s, int64_t step)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (!c->sp[s].has_xsec) return RZPIC_OK;
     if (s == 0 && (c->children_pending[0] || c->children_pending[1]))
         return fail(RZPIC_ESTATE, "new particles already staged: call rzpic_compact first");
@@ -1519,6 +1589,7 @@ rzpic_status rzpic_collide(rzpic_ctx *c, int32_t s, int64_t step)
 rzpic_status rzpic_deposit(rzpic_ctx *c)
 {
     TRY(need_both(c));
+    unprepare(c);
     if (c->mixed) TRY(deposit_impl<float>(c));
     else TRY(deposit_impl<double>(c));
     TRY(finalize_impl(c, 0));
@@ -1528,12 +1599,14 @@ rzpic_status rzpic_deposit(rzpic_ctx *c)
 rzpic_status rzpic_solve(rzpic_ctx *c, double t, int32_t *cycles, double *relres)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    unprepare(c);
     return solve_impl(c, t, false, cycles, relres);
 }
 
 rzpic_status rzpic_solve_dev(rzpic_ctx *c, double t, int32_t *cycles_dev, double *relres_dev)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    unprepare(c);
     const bool fixed = c->c.mg_fixed_cycles > 0;
     int32_t k = 0;
     double rr = 0.0;
@@ -1579,6 +1652,7 @@ rzpic_status rzpic_grid_view(rzpic_ctx *c, rzpic_grid *out)
 rzpic_status rzpic_set_grid_source(rzpic_ctx *c, const double *rho, const double *chi)
 {
     if (!c || !rho || !chi) return fail(RZPIC_EINVAL, "null argument");
+    unprepare(c);
     const size_t bytes = (size_t)c->nn * sizeof(double);
     HIPCHK(hipMemcpyAsync(c->rho, rho, bytes, hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->chi, chi, bytes, hipMemcpyDeviceToDevice, c->st));
@@ -1588,6 +1662,7 @@ rzpic_status rzpic_set_grid_source(rzpic_ctx *c, const double *rho, const double
 rzpic_status rzpic_set_mg(rzpic_ctx *c, double tol, int32_t max_cycles, int32_t fixed_cycles)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    unprepare(c);
     if (fixed_cycles < 0 || (fixed_cycles == 0 && (max_cycles < 1 || !(tol > 0))))
         return fail(RZPIC_EINVAL, "need fixed_cycles > 0, or max_cycles >= 1 and tol > 0");
     c->c.mg_tol = tol;
@@ -1599,6 +1674,7 @@ rzpic_status rzpic_set_mg(rzpic_ctx *c, double tol, int32_t max_cycles, int32_t 
 rzpic_status rzpic_set_voltage(rzpic_ctx *c, double V_dc, double V_rf, double f_rf)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    unprepare(c);
     if (!std::isfinite(V_dc) || !std::isfinite(V_rf) || !std::isfinite(f_rf))
         return fail(RZPIC_EINVAL, "voltage parameters must be finite");
     c->c.V_dc = V_dc;
@@ -1610,6 +1686,7 @@ rzpic_status rzpic_set_voltage(rzpic_ctx *c, double V_dc, double V_rf, double f_
 rzpic_status rzpic_set_circuit(rzpic_ctx *c, double V, double Q, double Qc)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    unprepare(c);
     if (!c->circ) return fail(RZPIC_EINVAL, "the context has no external circuit (circuit_C = 0)");
     if (!std::isfinite(V) || !std::isfinite(Q) || !std::isfinite(Qc))
         return fail(RZPIC_EINVAL, "circuit state must be finite");
@@ -1642,6 +1719,7 @@ rzpic_status rzpic_efield(rzpic_ctx *c)
 rzpic_status rzpic_compact(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (s == 1 && c->children_pending[1] && !c->sp[0].bound)
         return fail(RZPIC_ESTATE, "species 0 must stay bound while new ions are staged");
     if (c->mixed) {
@@ -1657,6 +1735,7 @@ rzpic_status rzpic_compact(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_resize(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (!(c->c.resize_wcoef > 0)) return fail(RZPIC_EINVAL, "resize_wcoef must be positive");
     if (c->children_pending[s]) return fail(RZPIC_ESTATE, "call rzpic_compact before rzpic_resize");
     if (c->mixed) {
@@ -1672,6 +1751,7 @@ rzpic_status rzpic_resize(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_sort(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
+    unprepare(c);
     if (c->children_pending[s]) return fail(RZPIC_ESTATE, "call rzpic_compact before rzpic_sort");
     if (c->mixed) TRY(sort_impl<float>(c, s));
     else TRY(sort_impl<double>(c, s));
@@ -1681,6 +1761,7 @@ rzpic_status rzpic_sort(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_prologue(rzpic_ctx *c)
 {
     TRY(need_both(c));
+    unprepare(c);
     if (c->children_pending[0] || c->children_pending[1])
         return fail(RZPIC_ESTATE, "new particles are staged: call rzpic_compact first");
     for (int s = 0; s < 2; ++s) HIPCHK(launch_fill_u64(c->acc[s], c->nn, c->st));
@@ -1865,12 +1946,22 @@ rzpic_status rzpic_step(rzpic_ctx *c, int64_t step)
     // the solve runs to a tolerance (it synchronises)
     if (c->step_graph && !g_recorder && !c->timing && c->c.mg_fixed_cycles > 0)
         return step_graph(c, step);
-    return c->mixed ? step_impl<float>(c, step) : step_impl<double>(c, step);
+    const bool pipe = c->pipeline && !g_recorder;
+    return c->mixed ? step_impl<float>(c, step, pipe) : step_impl<double>(c, step, pipe);
+}
+
+rzpic_status rzpic_set_step_pipeline(rzpic_ctx *c, int32_t on)
+{
+    if (!c) return fail(RZPIC_EINVAL, "null context");
+    c->pipeline = on != 0;
+    c->prepared = -1;
+    return RZPIC_OK;
 }
 
 rzpic_status rzpic_set_step_graph(rzpic_ctx *c, int32_t on)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    unprepare(c);
     if (on) {
         if (!c->st)
             return fail(RZPIC_EINVAL, "graph replay needs a stream other than the null stream");
@@ -1986,6 +2077,7 @@ rzpic_status rzpic_get_pass_config(rzpic_ctx *c, int32_t out[5])
 rzpic_status rzpic_grid_copy(rzpic_ctx *c, int32_t which, double *dev, int32_t to_ctx)
 {
     if (!c || !dev) return fail(RZPIC_EINVAL, "null argument");
+    if (to_ctx) unprepare(c);
     double *src = nullptr;
     switch (which) {
     case RZPIC_G_PHI: src = c->phi; break;

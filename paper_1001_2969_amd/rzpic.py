@@ -34,6 +34,7 @@ EXPORTS = (
     "rzpic_deposit_noalloc", "rzpic_solve_dev", "rzpic_grid_view", "rzpic_set_grid_source",
     "rzpic_set_pass_form", "rzpic_set_tiles", "rzpic_get_pass_config", "rzpic_batch_autotune",
     "rzpic_set_step_graph",
+    "rzpic_set_step_pipeline",
 )
 FORM_AUTO, FORM_LDS, FORM_TILED = 0, 1, 2
 
@@ -163,6 +164,7 @@ def lib():
             "rzpic_set_grid_source": [P, P, P],
             "rzpic_set_pass_form": [P, I], "rzpic_set_tiles": [P, I, I],
             "rzpic_set_step_graph": [P, I],
+            "rzpic_set_step_pipeline": [P, I],
             "rzpic_get_pass_config": [P, P],
             "rzpic_batch_autotune": [P, I, C.c_int64, P, I, C.POINTER(I), C.POINTER(C.c_int64)],
         }
@@ -413,6 +415,11 @@ class Context:
         """Steps captured and replayed as HIP graphs (rzpic_set_step_graph);
         needs a stream other than the null stream (use_stream)."""
         _check(lib().rzpic_set_step_graph(self.h, 1 if on else 0))
+
+    def set_step_pipeline(self, on=True):
+        """Each directly launched step prepares the next step's grid in its
+        list maintenance launches (rzpic_set_step_pipeline)."""
+        _check(lib().rzpic_set_step_pipeline(self.h, 1 if on else 0))
 
     def set_pass_form(self, form):
         _check(lib().rzpic_set_pass_form(self.h, form))

@@ -1,0 +1,110 @@
+"""Step pipelining (rzpic_set_step_pipeline): a step that prepares the next
+step's grid inside its list maintenance launches ends every step bit for bit
+where unpipelined steps end (particles, potentials away from the electrode
+row, deposits, counters), through every step variant (ions moving or not
+under subcycling, weight splits, which turn the preparation off for their
+step, tile sorts) and through calls between steps that drop a preparation.
+Between steps the densities and rho, chi of a pipelined context are already
+those that the unpipelined one forms at the start of the next step."""
+import numpy as np
+import pytest
+
+from paper_1001_2969_amd import rzpic
+from paper_1001_2969_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+_NEXT = (rzpic.G_RHO, rzpic.G_CHI, rzpic.G_DENS0, rzpic.G_DENS1)
+
+
+def _ctx(w, precision, pipe):
+    g = rzpic.make_context(w, precision=precision, capacity_factor=3.0)
+    g.set_step_pipeline(pipe)
+    for s, T in ((0, w.Te_eV), (1, w.Ti_eV)):
+        g.init_particles(s, w.n_per_species, w.n0, T, 0)
+    g.prologue()
+    return g
+
+
+def _same(a, b, what):
+    for s in (0, 1):
+        x, y = a.particles(s), b.particles(s)
+        for f in rzpic.FIELDS + ("id",):
+            np.testing.assert_array_equal(x[f], y[f], err_msg=f"{what} s={s} {f}")
+    # the electrode row (z = 0) of a pipelined phi already holds the next
+    # step's voltage
+    np.testing.assert_array_equal(a.grid(rzpic.G_PHI)[1:], b.grid(rzpic.G_PHI)[1:],
+                                  err_msg=f"{what} phi")
+    for gi in (rzpic.G_N0, rzpic.G_N1, rzpic.G_ER, rzpic.G_EZ):
+        np.testing.assert_array_equal(a.grid(gi), b.grid(gi), err_msg=f"{what} grid {gi}")
+    assert a.diag() == b.diag(), what
+
+
+def _run(w, precision, steps, between=None):
+    """Steps both contexts; returns the step indices at which the pipelined
+    context had already formed the next step's densities."""
+    direct, piped = _ctx(w, precision, False), _ctx(w, precision, True)
+    ahead = []
+    prev = None  # the pipelined context's next-step grids after the last step
+    for n in range(steps):
+        direct.step(n)
+        if prev is not None:
+            # what the direct step just formed from the previous step's
+            # deposit is what the pipelined context held after that step
+            if all(np.array_equal(direct.grid(gi), prev[gi]) for gi in _NEXT):
+                ahead.append(n - 1)
+        piped.step(n)
+        _same(direct, piped, f"{precision} step {n}")
+        prev = {gi: piped.grid(gi) for gi in _NEXT}
+        if between:
+            between(n, direct, piped)
+    direct.close()
+    piped.close()
+    return ahead
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_pipelined_steps_equal_direct_steps_every_step(precision):
+    """65x33 mesh, 30k + 30k particles, 200 V rf, collisions on; tile sort
+    every 3 steps, weight split every 4 (steps 3, 7, 11 prepare nothing),
+    ions moved every 2nd step."""
+    w = wl.rf_129x65().replace(nr=65, nz=33, R=0.02, L=0.01, n_per_species=30_000,
+                               sort_every=3, resize_every=4, ion_subcycle=2)
+    ahead = _run(w, precision, 12)
+    # every step without a weight split prepared the next one (the densities
+    # move from step to step, so an unprepared step does not match)
+    assert ahead == [n for n in range(11) if n % 4 != 3], ahead
+
+
+def test_pipelined_steps_through_calls_between_steps():
+    """129x65 mixed: the voltage changed after step 2, the electron density
+    (its deposit grid) scaled after step 4, phi halved after step 6: each
+    drops the preparation, so the following steps still match (a kept
+    preparation would use the old voltage, the old deposit or the old
+    initial guess)."""
+    w = wl.rf_129x65().replace(n_per_species=40_000, sort_every=0, resize_every=0)
+
+    def between(n, direct, piped):
+        n0, phi = direct.grid(rzpic.G_N0), direct.grid(rzpic.G_PHI)
+        for g in (direct, piped):
+            if n == 2:
+                g.set_voltage(10.0, 150.0)
+            if n == 4:
+                g.set_grid(rzpic.G_N0, 1.25 * n0)
+            if n == 6:
+                g.set_grid(rzpic.G_PHI, 0.5 * phi)
+
+    ahead = _run(w, "mixed", 9, between)
+    # after step 4 the direct step forms its grid from the scaled density
+    assert ahead == [0, 1, 2, 3, 5, 6, 7], ahead
+
+
+def test_pipelining_off_where_it_does_not_apply():
+    """External circuit (two solves) and a tolerance-mode solve: the steps run
+    unpipelined and match."""
+    w = wl.small_fp64().replace(n_per_species=6000, V_dc=20.0, V_rf=200.0, circuit_C=1e-12,
+                                mg_fixed_cycles=3)
+    assert _run(w, "fp64", 4) == []
+    w = wl.small_fp64().replace(n_per_species=6000, mg_fixed_cycles=0, mg_tol=1e-10,
+                                mg_max_cycles=100)
+    assert _run(w, "fp64", 3) == []
