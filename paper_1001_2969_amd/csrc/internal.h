@@ -351,7 +351,8 @@ struct MgLevels {
     int S;                 // reduction steps of an r-line (ceil(log2(nr - 1)))
     int line_off[kMaxLevels + 2];  // first table line of each level; line_off[L+1] = total
     int tab_row;           // elements per row of a line table: nr - 1 rounded up to a
-                           //    multiple of 4 (the padding: zero multipliers, b_final 1)
+                           //    multiple of 8 (the padding: zero coefficients and
+                           //    multipliers, b_final 1)
     size_t tab_stride;     // elements per line table: (3 + 2 S) tab_row
     void *tab;             // line tables, float (mixed) or double
     void *coarse_uf;       // levels 1..L-1: u then f of each level in one block

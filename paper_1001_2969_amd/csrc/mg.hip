@@ -1098,8 +1098,8 @@ template <typename T> __device__ __forceinline__ void factor_body(const MgLevels
     const int j = threadIdx.x;  // blockDim.x >= n
     if (j < n) {
         Coef<T> k = coef<T>(eps, nr, i, j, iz2, ir2, m.chi_face);
-        tab[j] = k.a;
-        tab[tn + j] = k.c;
+        tab[2 * j] = k.a;
+        tab[2 * j + 1] = k.c;
         A[j] = j == 0 ? (T)0 : -k.d;
         Bd[j] = k.b;
         C[j] = j == n - 1 ? (T)0 : -k.e;
@@ -1121,8 +1121,8 @@ template <typename T> __device__ __forceinline__ void factor_body(const MgLevels
                 c2 = -C[j + s] * k2;
                 b -= A[j + s] * k2;
             }
-            tab[(size_t)(3 + 2 * q) * tn + j] = k1;
-            tab[(size_t)(4 + 2 * q) * tn + j] = k2;
+            tab[(size_t)(3 + 2 * q) * tn + 2 * j] = k1;
+            tab[(size_t)(3 + 2 * q) * tn + 2 * j + 1] = k2;
         }
         __syncthreads();
         if (j < n) {
@@ -1134,9 +1134,15 @@ template <typename T> __device__ __forceinline__ void factor_body(const MgLevels
     }
     if (j < n) tab[2 * tn + j] = Bd[j];
     // the padding of every row (read by vector loads of whole lane groups):
-    // zero multipliers and b_final 1, so that it stays finite and inert
+    // zero coefficients and multipliers and b_final 1, so that it stays
+    // finite and inert
     if (j >= n && j < tn) {
-        for (int r = 0; r < 3 + 2 * m.S; ++r) tab[(size_t)r * tn + j] = r == 2 ? (T)1 : (T)0;
+        tab[2 * tn + j] = (T)1;
+        for (int p = 0; p <= m.S; ++p) {
+            const size_t base = p == 0 ? 0 : (size_t)(1 + 2 * p) * tn;
+            tab[base + 2 * j] = (T)0;
+            tab[base + 2 * j + 1] = (T)0;
+        }
     }
 }
 
@@ -1317,13 +1323,26 @@ template <typename T, int Q, int SMAX> struct LineTab {
     T ta[Q], tc[Q], bf[Q], k1[SMAX][Q], k2[SMAX][Q];
 };
 
-// Row `row` of a line table at a 32-bit byte offset: the row base is the same
-// for the whole wavefront (scalar registers), the offset j * sizeof(T) is
-// one register that every row shares (j < n <= 8192).
-template <typename T>
-__device__ __forceinline__ T tab_at(const T *tb, size_t row, int tn, uint32_t off)
+// Layout of a line table (factor_body), tn = tab_row elements per row: the
+// coefficients a, c of unknown j at 2j and 2j + 1 (a pair row of 2 tn
+// elements), b_final at 2 tn + j, then for reduction step st the
+// multipliers k1, k2 at (3 + 2 st) tn + 2j and + 1.  Values used together
+// sit side by side, so that one load brings both.
+__device__ __forceinline__ size_t tab_pair_row(int p)  // p = 0: (a, c); p = 1 + st: (k1, k2)
 {
-    return *(const T *)((const char *)(tb + row * (size_t)tn) + off);
+    return p == 0 ? 0 : (size_t)(1 + 2 * p);
+}
+
+// The pair (x, y) of unknown j of pair row p at the 32-bit byte offset
+// 2 j sizeof(T): the row base is the same for the whole wavefront (scalar
+// registers), the offset one register that every row shares (j < n <= 8192).
+template <typename T>
+__device__ __forceinline__ void tab_pair_at(const T *tb, int p, int tn, uint32_t off2, T &x, T &y)
+{
+    typedef T V __attribute__((ext_vector_type(2)));
+    const V v = *(const V *)((const char *)(tb + tab_pair_row(p) * (size_t)tn) + off2);
+    x = v[0];
+    y = v[1];
 }
 
 // The loads alone (clamped indices), then the masking of unknowns past the
@@ -1338,14 +1357,12 @@ __device__ __forceinline__ void line_tab_fetch(const T *tb, int n, int tn, int S
         const int j = q * 64 + lane;
         const int jj = j < n ? j : n - 1;
         const uint32_t off = (uint32_t)jj * (uint32_t)sizeof(T);
-        t.ta[q] = tab_at(tb, 0, tn, off);
-        t.tc[q] = tab_at(tb, 1, tn, off);
-        t.bf[q] = tab_at(tb, 2, tn, off);
+        tab_pair_at(tb, 0, tn, 2 * off, t.ta[q], t.tc[q]);
+        t.bf[q] = *(const T *)((const char *)(tb + 2 * (size_t)tn) + off);
 #pragma unroll
         for (int st = 0; st < SMAX; ++st) {
             const int sc = st < S ? st : S - 1;
-            t.k1[st][q] = tab_at(tb, (size_t)(3 + 2 * sc), tn, off);
-            t.k2[st][q] = tab_at(tb, (size_t)(4 + 2 * sc), tn, off);
+            tab_pair_at(tb, 1 + sc, tn, 2 * off, t.k1[st][q], t.k2[st][q]);
         }
     }
 }
@@ -1819,9 +1836,9 @@ static hipError_t fine_sweep(const MgLevels &m, int mixed, const double *phi_in,
 // same tables and arithmetic and therefore the same values.  The coarse
 // levels then cost 31 compute units a few line tables each, instead of one
 // compute unit all of them, and the cycle needs no separate coarse launch.
-// A line's inputs (table, right-hand side, phi) are fetched two phases before
-// it is solved: data that other compute units wrote takes longer to arrive
-// than one phase lasts.
+// A line's inputs (table, right-hand side, phi) are fetched three phases
+// before it is solved (FP64 and four unknowns per lane: two): data that other
+// compute units wrote takes longer to arrive than two phases last.
 constexpr int kUpWin = 5;         // lines of one level's window
 constexpr int kUpThreads = 192;   // three wavefronts: a phase has at most three lines
 
@@ -1988,12 +2005,12 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     const T *tab = (const T *)m.tab;
     const size_t tstride = m.tab_stride;
     // The inputs of this wavefront's line of phase ph: its table rows
-    // (a | c | b_final | k1, k2 of each step, see factor_body), right-hand
-    // side and phi.  A lane holds the Q consecutive unknowns j = Q lane + q,
-    // so that each table row comes in one load of Q elements (the rows are
-    // padded to whole groups; a lane past the row's end takes its last
-    // group): about half the loads of one element per load, and the
-    // wavefront's loads of two phases ahead fit the 63 it can have in
+    // (pairs a, c | b_final | pairs k1, k2 of each step, see factor_body),
+    // right-hand side and phi.  A lane holds the Q consecutive unknowns
+    // j = Q lane + q, so that a pair row comes in one load of 2Q elements
+    // and b_final in one of Q (the rows are padded to whole groups; a lane
+    // past the row's end takes its last group): 13 loads per phase, and the
+    // wavefront's loads of three phases ahead fit the 63 it can have in
     // flight.  Every wavefront fetches in every phase (a wavefront without a
     // line there, or a phase past the last, takes another line of the
     // block), so that the loads in flight are the same on every path.
@@ -2022,14 +2039,23 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
         const T *fl = coarse + (up_f_row(l) + r) * nr;
         const int e0 = Q * lane + Q <= tn ? Q * lane : tn - Q;
         const uint32_t ot = (uint32_t)e0 * (uint32_t)sizeof(T);
-        ld_vec<T, Q>(uniform_ptr(tb), ot, in.tab.ta);
-        ld_vec<T, Q>(uniform_ptr(tb + tn), ot, in.tab.tc);
+        T pr[2 * Q];
+        ld_vec<T, 2 * Q>(uniform_ptr(tb), 2 * ot, pr);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            in.tab.ta[q] = pr[2 * q];
+            in.tab.tc[q] = pr[2 * q + 1];
+        }
         ld_vec<T, Q>(uniform_ptr(tb + 2 * (size_t)tn), ot, in.tab.bf);
 #pragma unroll
         for (int st = 0; st < SMAX; ++st) {
             const int sc = st < S ? st : S - 1;
-            ld_vec<T, Q>(uniform_ptr(tb + (size_t)(3 + 2 * sc) * tn), ot, in.tab.k1[st]);
-            ld_vec<T, Q>(uniform_ptr(tb + (size_t)(4 + 2 * sc) * tn), ot, in.tab.k2[st]);
+            ld_vec<T, 2 * Q>(uniform_ptr(tb + tab_pair_row(1 + sc) * tn), 2 * ot, pr);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                in.tab.k1[st][q] = pr[2 * q];
+                in.tab.k2[st][q] = pr[2 * q + 1];
+            }
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -2105,21 +2131,41 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
         }
         __syncthreads();
     };
-    // Three buffers in fixed roles: phase ph reads buffer ph mod 3 while the
-    // inputs of phase ph + 2 are on their way (one phase is shorter than a
-    // load from memory written by other compute units).
+    // Buffers in fixed roles: phase ph reads buffer ph mod 4 while the
+    // inputs of phases ph + 1 .. ph + 3 are on their way (a phase is shorter
+    // than a load from memory written by other compute units); where four
+    // buffers would not fit the registers (FP64, or four unknowns per lane),
+    // three, two phases ahead.
     UpIn<T, Q, SMAX> b0, b1, b2;
     fetch(0, b0);
     fetch(1, b1);
-    for (int ph = 0; ph < nph; ph += 3) {
-        fetch(ph + 2, b2);
-        run(ph, b0);
-        if (ph + 1 >= nph) break;
-        fetch(ph + 3, b0);
-        run(ph + 1, b1);
-        if (ph + 2 >= nph) break;
-        fetch(ph + 4, b1);
-        run(ph + 2, b2);
+    if constexpr (Q * sizeof(T) <= 8) {
+        UpIn<T, Q, SMAX> b3;
+        fetch(2, b2);
+        for (int ph = 0; ph < nph; ph += 4) {
+            fetch(ph + 3, b3);
+            run(ph, b0);
+            if (ph + 1 >= nph) break;
+            fetch(ph + 4, b0);
+            run(ph + 1, b1);
+            if (ph + 2 >= nph) break;
+            fetch(ph + 5, b1);
+            run(ph + 2, b2);
+            if (ph + 3 >= nph) break;
+            fetch(ph + 6, b2);
+            run(ph + 3, b3);
+        }
+    } else {
+        for (int ph = 0; ph < nph; ph += 3) {
+            fetch(ph + 2, b2);
+            run(ph, b0);
+            if (ph + 1 >= nph) break;
+            fetch(ph + 3, b0);
+            run(ph + 1, b1);
+            if (ph + 2 >= nph) break;
+            fetch(ph + 4, b1);
+            run(ph + 2, b2);
+        }
     }
 }
 
@@ -2166,7 +2212,7 @@ void mg_plan(MgLevels &m, int mixed, size_t lds_budget, int path)
         off += m.nzl[l] - 2;
     }
     m.line_off[m.L + 1] = off;
-    m.tab_row = (n + 3) & ~3;
+    m.tab_row = (n + 7) & ~7;  // pair rows of 8-aligned groups: aligned vector loads
     m.tab_stride = (size_t)(3 + 2 * S) * m.tab_row;
     size_t lds = 0;
     for (int l = 1; l <= (mixed ? m.L : m.L - 1); ++l) lds += 2 * (size_t)m.nzl[l] * m.nr * es;

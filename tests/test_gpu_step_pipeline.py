@@ -108,3 +108,33 @@ def test_pipelining_off_where_it_does_not_apply():
     w = wl.small_fp64().replace(n_per_species=6000, mg_fixed_cycles=0, mg_tol=1e-10,
                                 mg_max_cycles=100)
     assert _run(w, "fp64", 3) == []
+
+
+def test_pipelined_steps_back_to_back_then_batched():
+    """129x65 mixed, 100k + 100k: 10 pipelined steps with nothing read
+    between them, compared; then 3 more and 2 steps of the pipelined context
+    in a batch (whose steps prepare their own grid) against 5 direct
+    steps."""
+    import torch
+
+    w = wl.rf_129x65().replace(n_per_species=100_000, sort_every=0, resize_every=0)
+    direct, piped = _ctx(w, "mixed", False), _ctx(w, "mixed", True)
+    for n in range(10):
+        direct.step(n)
+        piped.step(n)
+    _same(direct, piped, "after 10 steps")
+    for n in range(10, 13):
+        direct.step(n)
+        piped.step(n)
+    b = rzpic.Batch([piped], stream=torch.cuda.Stream())
+    for n in range(13, 15):
+        direct.step(n)
+        b.step(n)
+    b.close()
+    for s in (0, 1):
+        x, y = direct.particles(s), piped.particles(s)
+        for f in rzpic.FIELDS + ("id",):
+            np.testing.assert_array_equal(x[f], y[f], err_msg=f"batched s={s} {f}")
+    np.testing.assert_array_equal(direct.grid(rzpic.G_PHI), piped.grid(rzpic.G_PHI))
+    direct.close()
+    piped.close()
