@@ -1897,6 +1897,19 @@ __device__ __forceinline__ void ld_vec(const T *base, uint32_t off, T (&dst)[Q])
     }
 }
 
+// Q consecutive elements at a byte offset from a wavefront-uniform base that
+// is aligned to one element only (rows of nr elements), in one load.
+template <typename T, int Q>
+__device__ __forceinline__ void ld_vec_u(const T *base, uint32_t off, T (&dst)[Q])
+{
+    typedef T V __attribute__((ext_vector_type(Q), aligned(sizeof(T))));
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) V gV;
+    const V v = *(gV *)((gchar *)base + off);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) dst[q] = v[q];
+}
+
 // line_pcr for lanes that hold Q consecutive unknowns (j = Q lane + q): the
 // same reduction steps, term for term, with the neighbours at distance
 // s < Q in the lane itself or the next lane, and those at s >= Q a lane
@@ -1958,7 +1971,7 @@ template <typename T, int Q>
 __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_)
 {
     const MgLevels &m = A_.m;
-    const int mixed = A_.mixed;
+    constexpr bool mixed = sizeof(T) == 4;  // FP32 tables are the mixed form's
     const double *phi_in = A_.phi_in;
     double *phi_out = A_.phi_out;
     const double *f = A_.f;
@@ -2009,9 +2022,11 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     // right-hand side and phi.  A lane holds the Q consecutive unknowns
     // j = Q lane + q, so that a pair row comes in one load of 2Q elements
     // and b_final in one of Q (the rows are padded to whole groups; a lane
-    // past the row's end takes its last group): 13 loads per phase, and the
-    // wavefront's loads of three phases ahead fit the 63 it can have in
-    // flight.  Every wavefront fetches in every phase (a wavefront without a
+    // past the row's end takes its last group), and with Q = 2 the
+    // right-hand side and phi one load per row: 11 loads per phase of the
+    // mixed form, and the wavefront's loads of three phases ahead fit the
+    // 63 it can have in flight (five buffers, four ahead, measured slower:
+    // the extra registers cost more than the deeper overlap gains).  Every wavefront fetches in every phase (a wavefront without a
     // line there, or a phase past the last, takes another line of the
     // block), so that the loads in flight are the same on every path.
     const int tn = m.tab_row;
@@ -2057,22 +2072,45 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
                 in.tab.k2[st][q] = pr[2 * q + 1];
             }
         }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int j = Q * lane + q;
-            const int jj = j < n ? j : n - 1;
-            const uint32_t og = (uint32_t)jj * (uint32_t)sizeof(T);
-            const uint32_t od = (uint32_t)jj * (uint32_t)sizeof(double);
-            in.pl[q] = in.ph[q] = in.pc[q] = 0.0;
+        if constexpr (Q == 2) {
+            // one load of the lane's two unknowns per row: the pair starts at
+            // j = 2 lane and ends at most at column n, the row's last; lanes
+            // past the line's end (masked where used) take the row's last pair
+            const int g0 = 2 * lane + 1 <= n ? 2 * lane : n - 1;
+            const uint32_t og = (uint32_t)g0 * (uint32_t)sizeof(T);
+            const uint32_t od = (uint32_t)g0 * (uint32_t)sizeof(double);
+            double z[2];
+            in.pl[0] = in.pl[1] = in.ph[0] = in.ph[1] = in.pc[0] = in.pc[1] = 0.0;
             if (!fine) {
-                in.g[q] = ld_off(uniform_ptr(fl), og);
+                ld_vec_u<T, 2>(uniform_ptr(fl), og, in.g);
             } else if (mixed) {
-                in.g[q] = ld_off(uniform_ptr(fr + (size_t)r * nr), og);
-                in.pc[q] = ld_off(uniform_ptr(phi_in + (size_t)r * nr), od);
+                ld_vec_u<T, 2>(uniform_ptr(fr + (size_t)r * nr), og, in.g);
+                ld_vec_u<double, 2>(uniform_ptr(phi_in + (size_t)r * nr), od, in.pc);
             } else {
-                in.g[q] = (T)ld_off(uniform_ptr(f + (size_t)r * nr), od);
-                in.pl[q] = ld_off(uniform_ptr(phi_in + (size_t)(r - 1) * nr), od);
-                in.ph[q] = ld_off(uniform_ptr(phi_in + (size_t)(r + 1) * nr), od);
+                ld_vec_u<double, 2>(uniform_ptr(f + (size_t)r * nr), od, z);
+                in.g[0] = (T)z[0];
+                in.g[1] = (T)z[1];
+                ld_vec_u<double, 2>(uniform_ptr(phi_in + (size_t)(r - 1) * nr), od, in.pl);
+                ld_vec_u<double, 2>(uniform_ptr(phi_in + (size_t)(r + 1) * nr), od, in.ph);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int j = Q * lane + q;
+                const int jj = j < n ? j : n - 1;
+                const uint32_t og = (uint32_t)jj * (uint32_t)sizeof(T);
+                const uint32_t od = (uint32_t)jj * (uint32_t)sizeof(double);
+                in.pl[q] = in.ph[q] = in.pc[q] = 0.0;
+                if (!fine) {
+                    in.g[q] = ld_off(uniform_ptr(fl), og);
+                } else if (mixed) {
+                    in.g[q] = ld_off(uniform_ptr(fr + (size_t)r * nr), og);
+                    in.pc[q] = ld_off(uniform_ptr(phi_in + (size_t)r * nr), od);
+                } else {
+                    in.g[q] = (T)ld_off(uniform_ptr(f + (size_t)r * nr), od);
+                    in.pl[q] = ld_off(uniform_ptr(phi_in + (size_t)(r - 1) * nr), od);
+                    in.ph[q] = ld_off(uniform_ptr(phi_in + (size_t)(r + 1) * nr), od);
+                }
             }
         }
     };
@@ -2175,6 +2213,7 @@ static hipError_t up_sweep(const MgLevels &m, int mixed, const double *phi_in, d
 {
     const int n = m.nr - 1, blocks = (m.nzl[m.L] - 3) / 2;
     if (blocks <= 0) return hipSuccess;
+    if ((mixed != 0) != (sizeof(T) == 4)) return hipErrorInvalidValue;  // k_up_body's form
     const size_t lds = up_lds(m, mixed);
     if (n <= 64)
         (void)launch<k_up_A<T, 1>, k_up_body<T, 1>, kUpThreads>(dim3(blocks), dim3(kUpThreads), lds, st, k_up_A<T, 1>{m, mixed, phi_in, phi_out, f});
