@@ -422,8 +422,10 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         e5 = c->evpool[(size_t)c->ev_used * rzpic_ctx::kEvPerStep + 5];
     }
     HIPCHK(launch_pass2<T>(mode, a[0], a[1], b[0], b[1], threads, lds, c->st, e4, e5));
-    // collision kernels: about two wavefronts per electron bucket, one per
-    // ion bucket (ion candidates are rare), deposits by global atomics
+    // collision kernels: four wavefronts per bucket with many candidates
+    // (each lane then takes about one: the chain of dependent loads per
+    // candidate is the kernel's time), one per bucket otherwise (ion
+    // candidates are rare), deposits by global atomics
     const int cthreads = 256, wpb = cthreads / 64;
     int cb[2];
     for (int s = 0; s < 2; ++s) {
@@ -431,7 +433,7 @@ template <typename T> rzpic_status run_pass_both(rzpic_ctx *c, uint32_t step, bo
         // at least three wavefronts per CU when there are many candidates, so
         // that fewer, larger pass blocks (more threads each) do not thin
         // out the collisions' waves
-        const int many = 2 * b[s] > 3 * c->cus ? 2 * b[s] : 3 * c->cus;
+        const int many = 4 * b[s] > 3 * c->cus ? 4 * b[s] : 3 * c->cus;
         const int want = expect > 16.0 * b[s] ? many : b[s];
         cb[s] = (want + wpb - 1) / wpb;
         if (a[s].sp.mc_model == RZPIC_MC_NONE) cb[s] = 1;
