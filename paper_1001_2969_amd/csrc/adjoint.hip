@@ -488,6 +488,7 @@ struct rzpic_adjoint {
 // Defined in runtime.hip.
 rzpic_status rz_fail(rzpic_status s, const char *msg);
 Mesh rz_mesh(const rzpic_ctx *c);
+rzpic_status rz_settle(rzpic_ctx *c);
 SpeciesK rz_species(const rzpic_ctx *c, int s);
 rzpic_status rz_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, double tol,
                        int max_cycles, int *cycles, double *relres);
@@ -666,6 +667,7 @@ rzpic_status rzpic_adjoint_create(rzpic_ctx *c, const rzpic_adjoint_config *cfg,
     if (!c || !cfg || !out) return rz_fail(RZPIC_EINVAL, "adjoint: null argument");
     *out = nullptr;
     ATRY(check_ctx(c));
+    ATRY(rz_settle(c));  // a pipelined step's pending list maintenance
     if (cfg->n_steps < 1) return rz_fail(RZPIC_EINVAL, "adjoint: n_steps must be >= 1");
     if (cfg->checkpoint_every < 0)
         return rz_fail(RZPIC_EINVAL, "adjoint: checkpoint_every must be >= 0");
@@ -736,6 +738,7 @@ rzpic_status rzpic_adjoint_forward(rzpic_adjoint *a, int64_t step0, double *J_ou
     if (!a || !J_out) return rz_fail(RZPIC_EINVAL, "adjoint: null argument");
     rzpic_ctx *c = a->c;
     ATRY(check_ctx(c));
+    ATRY(rz_settle(c));  // a pipelined step's pending list maintenance
     const int N = a->cfg.n_steps;
     if (step0 < 0 || step0 + N > 0xFFFFFFFFLL)
         return rz_fail(RZPIC_EINVAL, "adjoint: step range out of bounds");
@@ -763,6 +766,7 @@ rzpic_status rzpic_adjoint_backward(rzpic_adjoint *a, double grad_V[2], double *
         return rz_fail(RZPIC_ESTATE, "adjoint: backward needs a completed forward window");
     rzpic_ctx *c = a->c;
     ATRY(check_ctx(c));
+    ATRY(rz_settle(c));  // a pipelined step's pending list maintenance
     hipStream_t st = c->st;
     const int N = a->cfg.n_steps, K = a->K, nr = c->c.nr, nz = c->c.nz;
     const size_t nn = (size_t)c->nn;

@@ -33,6 +33,7 @@ using namespace rz;
 extern "C" rzpic_status rzpic_step(rzpic_ctx *ctx, int64_t step);
 rzpic_status rz_fail(rzpic_status s, const char *msg);
 hipStream_t rz_stream(const rzpic_ctx *c);
+rzpic_status rz_settle(rzpic_ctx *c);
 int rz_batchable(const rzpic_ctx *c, std::string &why);
 extern "C" {
 void rz_tune_key(const rzpic_ctx *c, int32_t out[5]);
@@ -168,6 +169,10 @@ rzpic_status rzpic_batch_step(rzpic_batch *b, int64_t step)
             std::snprintf(buf, sizeof buf, "batch: context %d: %s", i, why.c_str());
             return rz_fail(RZPIC_EINVAL, buf);
         }
+        // a pipelined step's pending list maintenance precedes the batch
+        // (which orders itself after the contexts' streams)
+        rzpic_status ss = rz_settle(b->ctx[i]);
+        if (ss != RZPIC_OK) return ss;
     }
     // record every discharge's step (host bookkeeping only)
     for (int i = 0; i < n; ++i) {

@@ -151,4 +151,8 @@ struct rzpic_ctx {
     bool pipeline = false;
     int64_t prepared = -1;
     bool prep_ready = false;
+    // a pipelined step's hole filling and appending, launched beside the
+    // next step's way-down launches (or on their own before anything else
+    // reads the particles: flush_tail)
+    rz::ListTail tail;
 };

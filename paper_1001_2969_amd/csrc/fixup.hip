@@ -3,6 +3,8 @@
 // increasing order by the live particles of the tail, and new particles are
 // appended in parent order with consecutive identities.  The resulting array
 // does not depend on the launch shape or on the order atomics land in.
+#include <cstring>
+
 #include "device.h"
 #include "lists.h"
 
@@ -73,38 +75,6 @@ hipError_t launch_dead_scan(Parts<T> p, const Counts *cnt, Chunks ch, hipStream_
     return hipGetLastError();
 }
 
-// Hole m (the m-th dead index below keep) receives the m-th live particle of
-// [keep, n).  With T_k the dead indices >= keep (sorted), that particle is
-// keep + m + k for the smallest k whose T_k lies beyond it.
-template <typename T>
-__device__ __forceinline__ void fill_body(const Blk &kb, const Parts<T> &p, const int64_t *dead,
-                                          const FixRec *fix)
-{
-    const int64_t D = fix->dead, keep = fix->keep;
-    if (D == 0) return;
-    const int64_t H = wave_lower_bound(dead, D, keep);  // dead indices < keep
-    for (int64_t m = kb.x * (int64_t)blockDim.x + threadIdx.x; m < H;
-         m += (int64_t)kb.nx * blockDim.x) {
-        int64_t a = 0, b = D - H;
-        while (a < b) {
-            int64_t k = (a + b) >> 1;
-            if (dead[H + k] - keep - k > m) b = k;
-            else a = k + 1;
-        }
-        const int64_t src = keep + m + a, dst = dead[m];
-        p.r[dst] = p.r[src];
-        p.z[dst] = p.z[src];
-        p.vr[dst] = p.vr[src];
-        p.vt[dst] = p.vt[src];
-        p.vz[dst] = p.vz[src];
-        p.ar[dst] = p.ar[src];
-        p.az[dst] = p.az[src];
-        p.w[dst] = p.w[src];
-        p.id[dst] = p.id[src];
-        if (p.at) p.at[dst] = p.at[src];
-    }
-}
-
 template <typename T> __global__ void k_fill(Parts<T> p, const int64_t *dead, const FixRec *fix)
 {
     fill_body<T>(Blk{(int)blockIdx.x, 0, (int)gridDim.x, 1}, p, dead, fix);
@@ -115,18 +85,6 @@ hipError_t launch_fill(Parts<T> p, Chunks ch, const FixRec *fix, hipStream_t st)
 {
     RZ_LAUNCH((k_fill<T>), dim3(256), dim3(256), 0, st, p, ch.dead_glob, fix);
     return hipGetLastError();
-}
-
-// Both species in one launch (the block row selects the species).
-template <typename T> struct Fill2Args {
-    Parts<T> p[2];
-    const int64_t *dead[2];
-    const FixRec *fix[2];
-};
-
-template <typename T> __device__ __forceinline__ void fill2_body(const Blk &k, const Fill2Args<T> &a)
-{
-    fill_body<T>(k, a.p[k.y], a.dead[k.y], a.fix[k.y]);
 }
 
 template <typename T>
@@ -141,97 +99,6 @@ hipError_t launch_fill2(Parts<T> p0, Parts<T> p1, Chunks ch0, Chunks ch1, const 
     a.fix[0] = fix0;
     a.fix[1] = fix1;
     return launch<Fill2Args<T>, fill2_body<T>, 256>(dim3(256, 2), dim3(256), 0, st, a);
-}
-
-// Append of the staged children of species blockIdx.y after its kept
-// particles: the survivor and event offsets of each electron chunk come from
-// the superchunk prefix and an in-block scan; slot = parent index, identity =
-// next identity + event rank.  Block (0, cs) commits the count and identity.
-template <typename T> struct AppendArgs {
-    Parts<T> dst[2], stage[2];
-    Counts *cnt[2];
-};
-
-template <typename T> struct AppendJob {
-    ScanJobs j;
-    AppendArgs<T> g;
-};
-
-template <typename T> __device__ __forceinline__ void append_body(const Blk &kb, const AppendJob<T> &aj)
-{
-    __shared__ int sh[64];
-    __shared__ int64_t sh64[16];
-    const ScanJobs &j = aj.j;
-    const AppendArgs<T> &g = aj.g;
-    const int cs = kb.y;
-    if (!j.dead[cs]) return;
-    const int64_t sc = kb.x;
-    const int64_t keep = j.fix[cs]->keep;
-    const int64_t cap = j.cap[cs];
-    const bool kids = j.kids[cs] != 0;
-    int64_t nch = 0, nsc = 0;
-    const int32_t *sc_alive = cs == 0 ? j.ech.sc_se : j.ech.sc_si;
-    if (kids) {
-        nch = (j.crec->n_parent + kChunk - 1) / kChunk;
-        nsc = (nch + kSuper - 1) / kSuper;
-    }
-    // this chunk's masks, loaded before the prefix sums (whose barriers
-    // would otherwise hold them back)
-    const unsigned long long *alive = cs == 0 ? j.ech.se : j.ech.si;
-    const int64_t c = sc * kSuper + threadIdx.x;
-    const bool inc = kids && sc < nsc && c < nch;
-    const unsigned long long am = inc ? alive[c] : 0ull;
-    const unsigned long long em = inc ? j.ech.ev[c] : 0ull;
-    if (sc == 0) {
-        int64_t surv = 0, evs = 0;
-        if (kids) prefix2_of(sc_alive, j.ech.sc_ev, nsc, sh64, surv, evs);
-        if (threadIdx.x == 0) {
-            const int64_t room = cap - keep;
-            if (surv > room) {
-                atomicOr(j.status, kStCapacity);
-                surv = room;
-            }
-            g.cnt[cs]->n = keep + surv;
-            if (kids) g.cnt[cs]->next_id = j.crec->next_id_old[cs] + (uint64_t)evs;
-        }
-    }
-    if (!kids || sc >= nsc) return;
-    int64_t sbase, ebase;
-    prefix2_of(sc_alive, j.ech.sc_ev, sc, sh64, sbase, ebase);
-    // both in-block scans in one: survivors in the low 16 bits (at most
-    // 512 x 64 in a superchunk), events above (whose superchunk total, from
-    // the scan, must stay below 2^15 for the packed int; else two scans)
-    int tot;
-    int64_t soff, eoff;
-    if (j.ech.sc_ev[sc] < 32768) {
-        const int both = block_excl_sum(__popcll(am) | (__popcll(em) << 16), tot, sh);
-        soff = sbase + (both & 0xFFFF);
-        eoff = ebase + (both >> 16);
-    } else {
-        soff = sbase + block_excl_sum(__popcll(am), tot, sh);
-        eoff = ebase + block_excl_sum(__popcll(em), tot, sh);
-    }
-    const uint64_t id0 = j.crec->next_id_old[cs];
-    const Parts<T> &dst = g.dst[cs], &stage = g.stage[cs];
-    unsigned long long m = am;
-    int64_t k = 0;
-    while (m) {
-        const int lane = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        const int64_t slot = c * kChunk + lane;
-        const int64_t to = keep + soff + k++;
-        if (to >= cap) continue;
-        dst.r[to] = stage.r[slot];
-        dst.z[to] = stage.z[slot];
-        dst.vr[to] = stage.vr[slot];
-        dst.vt[to] = stage.vt[slot];
-        dst.vz[to] = stage.vz[slot];
-        dst.ar[to] = stage.ar[slot];
-        dst.az[to] = stage.az[slot];
-        dst.w[to] = stage.w[slot];
-        if (dst.at) dst.at[to] = stage.at[slot];
-        dst.id[to] = id0 + (uint64_t)(eoff + __popcll(em & ((1ull << lane) - 1)));
-    }
 }
 
 template <typename T>
@@ -250,6 +117,61 @@ hipError_t launch_append(const ScanJobs &j, Parts<T> dst0, Parts<T> dst1, Parts<
     if (nsc < 1) nsc = 1;
     return launch<AppendJob<T>, append_body<T>, kSuper>(dim3((unsigned)nsc, 2), dim3(kSuper), 0, st,
                                                         AppendJob<T>{j, g});
+}
+
+template <typename T>
+void list_tail_keep(ListTail &t, Parts<T> p0, Parts<T> p1, Chunks ch0, Chunks ch1,
+                    const FixRec *fix0, const FixRec *fix1, const ScanJobs &j, Parts<T> dst0,
+                    Parts<T> dst1, Parts<T> stage0, Parts<T> stage1, Counts *cnt0, Counts *cnt1,
+                    int64_t max_chunks)
+{
+    static_assert(sizeof(Fill2Args<T>) <= kTailFillBytes, "fill arguments");
+    static_assert(sizeof(AppendJob<T>) <= kTailAppBytes, "append arguments");
+    Fill2Args<T> f;
+    f.p[0] = p0;
+    f.p[1] = p1;
+    f.dead[0] = ch0.dead_glob;
+    f.dead[1] = ch1.dead_glob;
+    f.fix[0] = fix0;
+    f.fix[1] = fix1;
+    AppendJob<T> a{};
+    a.j = j;
+    a.g.dst[0] = dst0;
+    a.g.dst[1] = dst1;
+    a.g.stage[0] = stage0;
+    a.g.stage[1] = stage1;
+    a.g.cnt[0] = cnt0;
+    a.g.cnt[1] = cnt1;
+    std::memcpy(t.fill, &f, sizeof f);
+    std::memcpy(t.app, &a, sizeof a);
+    const int64_t nsc = (max_chunks + kSuper - 1) / kSuper;
+    t.nsc = nsc < 1 ? 1 : (int)nsc;
+    t.fp32 = sizeof(T) == 4;
+    t.stage = 2;
+}
+
+template <typename T> static hipError_t tail_flush(ListTail &t, hipStream_t st)
+{
+    if (t.stage == 2) {
+        Fill2Args<T> f;
+        std::memcpy(&f, t.fill, sizeof f);
+        (void)launch<Fill2Args<T>, fill2_body<T>, 256>(dim3(256, 2), dim3(256), 0, st, f);
+        t.stage = 1;
+    }
+    if (t.stage == 1) {
+        AppendJob<T> a;
+        std::memcpy(&a, t.app, sizeof a);
+        (void)launch<AppendJob<T>, append_body<T>, kSuper>(dim3((unsigned)t.nsc, 2), dim3(kSuper),
+                                                            0, st, a);
+        t.stage = 0;
+    }
+    return hipGetLastError();
+}
+
+hipError_t list_tail_flush(ListTail &t, hipStream_t st)
+{
+    if (t.stage == 0) return hipSuccess;
+    return t.fp32 ? tail_flush<float>(t, st) : tail_flush<double>(t, st);
 }
 
 // Weight split (Sec. 2.2): clone count of each particle.  Contraction is off
@@ -434,6 +356,14 @@ hipError_t launch_reduce_slices(unsigned long long *acc, const void *slices, int
 
 template hipError_t launch_dead_scan<double>(Parts<double>, const Counts *, Chunks, hipStream_t);
 template hipError_t launch_dead_scan<float>(Parts<float>, const Counts *, Chunks, hipStream_t);
+template void list_tail_keep<double>(ListTail &, Parts<double>, Parts<double>, Chunks, Chunks,
+                                    const FixRec *, const FixRec *, const ScanJobs &,
+                                    Parts<double>, Parts<double>, Parts<double>, Parts<double>,
+                                    Counts *, Counts *, int64_t);
+template void list_tail_keep<float>(ListTail &, Parts<float>, Parts<float>, Chunks, Chunks,
+                                   const FixRec *, const FixRec *, const ScanJobs &, Parts<float>,
+                                   Parts<float>, Parts<float>, Parts<float>, Counts *, Counts *,
+                                   int64_t);
 template hipError_t launch_fill<double>(Parts<double>, Chunks, const FixRec *, hipStream_t);
 template hipError_t launch_fill<float>(Parts<float>, Chunks, const FixRec *, hipStream_t);
 template hipError_t launch_fill2<double>(Parts<double>, Parts<double>, Chunks, Chunks,

@@ -259,6 +259,26 @@ template <typename T>
 hipError_t launch_append(const ScanJobs &j, Parts<T> dst0, Parts<T> dst1, Parts<T> stage0,
                          Parts<T> stage1, Counts *cnt0, Counts *cnt1, int64_t max_chunks,
                          hipStream_t st);
+// The hole filling and appending of a step's list maintenance kept for
+// later launches (step pipelining): they run beside the next step's way-down
+// launches (mg_vcycle), or on their own (list_tail_flush).  stage: 2 both
+// pending, 1 the appending, 0 nothing.  The launch arguments are kept as
+// bytes (Fill2Args<T>, AppendJob<T> of the particles' type).
+constexpr int kTailFillBytes = 512, kTailAppBytes = 1536;
+struct ListTail {
+    int stage = 0;
+    int fp32 = 0;
+    int nsc = 1;  // superchunks of the appending
+    alignas(16) unsigned char fill[kTailFillBytes];
+    alignas(16) unsigned char app[kTailAppBytes];
+};
+template <typename T>
+void list_tail_keep(ListTail &t, Parts<T> p0, Parts<T> p1, Chunks ch0, Chunks ch1,
+                    const FixRec *fix0, const FixRec *fix1, const ScanJobs &j, Parts<T> dst0,
+                    Parts<T> dst1, Parts<T> stage0, Parts<T> stage1, Counts *cnt0, Counts *cnt1,
+                    int64_t max_chunks);
+// Launches what is pending, on its own (stage becomes 0).
+hipError_t list_tail_flush(ListTail &t, hipStream_t st);
 // Mode of the periodic resize: the weight-conserving split, or zero-order
 // particle-based resizing with draws keyed by (seed, s, id, step).
 struct ResizeKey {
@@ -388,9 +408,10 @@ hipError_t mg_solve_block(const MgLevels &m, int mixed, double *phi, const doubl
                           int cycles, hipStream_t st);
 // One V(0,1) cycle of the multi-launch path.  FP64: the finest level
 // alternates between phi and phi_alt (both carry the boundary values); the
-// pointers are swapped.
+// pointers are swapped.  With a pending list tail (step pipelining), its
+// next stage runs in the way-down launch of the split path, beside it.
 hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_alt,
-                     const double *f, int skip_down, hipStream_t st);
+                     const double *f, int skip_down, hipStream_t st, ListTail *tail = nullptr);
 // Split path, first launch of a solve (after the Dirichlet values are set):
 // the line tables and the first cycle's residual restriction; that cycle then
 // runs mg_vcycle with skip_down = 1.

@@ -1,6 +1,7 @@
 // Device bodies of the list maintenance shared by its own launches
-// (fixup.hip) and by the launches that run them beside the next step's grid
-// preparation (mg.hip): block sums, the superchunk scan and the dead lists.
+// (fixup.hip) and by the launches that run them beside the multigrid's
+// (mg.hip, step pipelining): block sums, the superchunk scan, the dead
+// lists, the hole filling and the appending of new particles.
 #pragma once
 
 #include "device.h"
@@ -134,5 +135,141 @@ __device__ __forceinline__ void dead_list_body(const Blk &k, const ScanJobs &j)
         m &= m - 1;
     }
 }
+
+// Hole m (the m-th dead index below keep) receives the m-th live particle of
+// [keep, n).  With T_k the dead indices >= keep (sorted), that particle is
+// keep + m + k for the smallest k whose T_k lies beyond it.
+template <typename T>
+__device__ __forceinline__ void fill_body(const Blk &kb, const Parts<T> &p, const int64_t *dead,
+                                          const FixRec *fix)
+{
+    const int64_t D = fix->dead, keep = fix->keep;
+    if (D == 0) return;
+    const int64_t H = wave_lower_bound(dead, D, keep);  // dead indices < keep
+    for (int64_t m = kb.x * (int64_t)blockDim.x + threadIdx.x; m < H;
+         m += (int64_t)kb.nx * blockDim.x) {
+        int64_t a = 0, b = D - H;
+        while (a < b) {
+            int64_t k = (a + b) >> 1;
+            if (dead[H + k] - keep - k > m) b = k;
+            else a = k + 1;
+        }
+        const int64_t src = keep + m + a, dst = dead[m];
+        p.r[dst] = p.r[src];
+        p.z[dst] = p.z[src];
+        p.vr[dst] = p.vr[src];
+        p.vt[dst] = p.vt[src];
+        p.vz[dst] = p.vz[src];
+        p.ar[dst] = p.ar[src];
+        p.az[dst] = p.az[src];
+        p.w[dst] = p.w[src];
+        p.id[dst] = p.id[src];
+        if (p.at) p.at[dst] = p.at[src];
+    }
+}
+
+// Both species in one launch (the block row selects the species).
+template <typename T> struct Fill2Args {
+    Parts<T> p[2];
+    const int64_t *dead[2];
+    const FixRec *fix[2];
+};
+
+template <typename T> __device__ __forceinline__ void fill2_body(const Blk &k, const Fill2Args<T> &a)
+{
+    fill_body<T>(k, a.p[k.y], a.dead[k.y], a.fix[k.y]);
+}
+
+// Append of the staged children of species blockIdx.y after its kept
+// particles: the survivor and event offsets of each electron chunk come from
+// the superchunk prefix and an in-block scan; slot = parent index, identity =
+// next identity + event rank.  Block (0, cs) commits the count and identity.
+template <typename T> struct AppendArgs {
+    Parts<T> dst[2], stage[2];
+    Counts *cnt[2];
+};
+
+template <typename T> struct AppendJob {
+    ScanJobs j;
+    AppendArgs<T> g;
+};
+
+template <typename T> __device__ __forceinline__ void append_body(const Blk &kb, const AppendJob<T> &aj)
+{
+    __shared__ int sh[64];
+    __shared__ int64_t sh64[16];
+    const ScanJobs &j = aj.j;
+    const AppendArgs<T> &g = aj.g;
+    const int cs = kb.y;
+    if (!j.dead[cs]) return;
+    const int64_t sc = kb.x;
+    const int64_t keep = j.fix[cs]->keep;
+    const int64_t cap = j.cap[cs];
+    const bool kids = j.kids[cs] != 0;
+    int64_t nch = 0, nsc = 0;
+    const int32_t *sc_alive = cs == 0 ? j.ech.sc_se : j.ech.sc_si;
+    if (kids) {
+        nch = (j.crec->n_parent + kChunk - 1) / kChunk;
+        nsc = (nch + kSuper - 1) / kSuper;
+    }
+    // this chunk's masks, loaded before the prefix sums (whose barriers
+    // would otherwise hold them back)
+    const unsigned long long *alive = cs == 0 ? j.ech.se : j.ech.si;
+    const int64_t c = sc * kSuper + threadIdx.x;
+    const bool inc = kids && sc < nsc && c < nch;
+    const unsigned long long am = inc ? alive[c] : 0ull;
+    const unsigned long long em = inc ? j.ech.ev[c] : 0ull;
+    if (sc == 0) {
+        int64_t surv = 0, evs = 0;
+        if (kids) prefix2_of(sc_alive, j.ech.sc_ev, nsc, sh64, surv, evs);
+        if (threadIdx.x == 0) {
+            const int64_t room = cap - keep;
+            if (surv > room) {
+                atomicOr(j.status, kStCapacity);
+                surv = room;
+            }
+            g.cnt[cs]->n = keep + surv;
+            if (kids) g.cnt[cs]->next_id = j.crec->next_id_old[cs] + (uint64_t)evs;
+        }
+    }
+    if (!kids || sc >= nsc) return;
+    int64_t sbase, ebase;
+    prefix2_of(sc_alive, j.ech.sc_ev, sc, sh64, sbase, ebase);
+    // both in-block scans in one: survivors in the low 16 bits (at most
+    // 512 x 64 in a superchunk), events above (whose superchunk total, from
+    // the scan, must stay below 2^15 for the packed int; else two scans)
+    int tot;
+    int64_t soff, eoff;
+    if (j.ech.sc_ev[sc] < 32768) {
+        const int both = block_excl_sum(__popcll(am) | (__popcll(em) << 16), tot, sh);
+        soff = sbase + (both & 0xFFFF);
+        eoff = ebase + (both >> 16);
+    } else {
+        soff = sbase + block_excl_sum(__popcll(am), tot, sh);
+        eoff = ebase + block_excl_sum(__popcll(em), tot, sh);
+    }
+    const uint64_t id0 = j.crec->next_id_old[cs];
+    const Parts<T> &dst = g.dst[cs], &stage = g.stage[cs];
+    unsigned long long m = am;
+    int64_t k = 0;
+    while (m) {
+        const int lane = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const int64_t slot = c * kChunk + lane;
+        const int64_t to = keep + soff + k++;
+        if (to >= cap) continue;
+        dst.r[to] = stage.r[slot];
+        dst.z[to] = stage.z[slot];
+        dst.vr[to] = stage.vr[slot];
+        dst.vt[to] = stage.vt[slot];
+        dst.vz[to] = stage.vz[slot];
+        dst.ar[to] = stage.ar[slot];
+        dst.az[to] = stage.az[slot];
+        dst.w[to] = stage.w[slot];
+        if (dst.at) dst.at[to] = stage.at[slot];
+        dst.id[to] = id0 + (uint64_t)(eoff + __popcll(em & ((1ull << lane) - 1)));
+    }
+}
+
 
 }  // namespace rz

@@ -3,6 +3,8 @@
 // solve, and on the way up the prolonged correction followed by one zebra
 // sweep of exact r-line solves (parallel cyclic reduction in LDS, one block
 // per line).
+#include <cstring>
+
 #include "device.h"
 #include "lists.h"
 
@@ -2299,12 +2301,80 @@ static hipError_t bottom(const MgLevels &m, int mixed, hipStream_t st)
 // One V(0,1) cycle on phi.  FP64: every level in double, the finest level on
 // phi itself.  Mixed: the finest residual in double, the correction cycle in
 // float on every level, phi += correction in double.
+// The way down beside the next stage of a pending list tail (step
+// pipelining), at kSuper threads: the way-down blocks first, then the hole
+// filling's (fill_blocks per species) or the appending's blocks.  down_body
+// and the list bodies loop over the block's threads.
+constexpr int kTailFillBlocks = 128;
+
+template <typename T> struct k_down_fill_A {
+    k_down_A<T> d;
+    Fill2Args<T> f;
+    int nd;
+};
+
+template <typename T>
+__device__ __forceinline__ void k_down_fill_body(const Blk &kb_, const k_down_fill_A<T> &A_)
+{
+    if (kb_.x < A_.nd) {
+        k_down_body<T>(Blk{kb_.x, 0, A_.nd, 1}, A_.d);
+        return;
+    }
+    const int b = kb_.x - A_.nd;
+    fill2_body<T>(Blk{b % kTailFillBlocks, b / kTailFillBlocks, kTailFillBlocks, 2}, A_.f);
+}
+
+template <typename T> struct k_down_app_A {
+    k_down_A<T> d;
+    AppendJob<T> a;
+    int nd, nsc;
+};
+
+template <typename T>
+__device__ __forceinline__ void k_down_app_body(const Blk &kb_, const k_down_app_A<T> &A_)
+{
+    if (kb_.x < A_.nd) {
+        k_down_body<T>(Blk{kb_.x, 0, A_.nd, 1}, A_.d);
+        return;
+    }
+    const int b = kb_.x - A_.nd;
+    append_body<T>(Blk{b % A_.nsc, b / A_.nsc, A_.nsc, 2}, A_.a);
+}
+
+template <typename T>
+static hipError_t down_tail(const MgLevels &m, int mixed, const double *phi, const double *f,
+                            int cpb, ListTail &t, hipStream_t st)
+{
+    const int nr = m.nr, nz = m.nzl[m.L], nd = (nr - 1 + cpb - 1) / cpb;
+    const k_down_A<T> d{phi, f, m, mixed, cpb};
+    if (t.stage == 2) {
+        static_assert(sizeof(k_down_fill_A<T>) <= 4096, "kernel arguments");
+        k_down_fill_A<T> a{d, {}, nd};
+        std::memcpy(&a.f, t.fill, sizeof a.f);
+        (void)launch<k_down_fill_A<T>, k_down_fill_body<T>, kSuper>(
+            dim3(nd + 2 * kTailFillBlocks), dim3(kSuper), down_lds(nz, cpb), st, a);
+        t.stage = 1;
+    } else {
+        static_assert(sizeof(k_down_app_A<T>) <= 4096, "kernel arguments");
+        k_down_app_A<T> a{d, {}, nd, t.nsc};
+        std::memcpy(&a.a, t.app, sizeof a.a);
+        (void)launch<k_down_app_A<T>, k_down_app_body<T>, kSuper>(
+            dim3(nd + 2 * t.nsc), dim3(kSuper), down_lds(nz, cpb), st, a);
+        t.stage = 0;
+    }
+    return hipGetLastError();
+}
+
 static hipError_t down(const MgLevels &m, int mixed, const double *phi, const double *f,
-                       hipStream_t st)
+                       hipStream_t st, ListTail *tail = nullptr)
 {
     if (m.long_lines) return down_rows(m, mixed, phi, f, st);
     const int nr = m.nr, nz = m.nzl[m.L];
     const int cpb = cols_per_block(nz);
+    if (tail && tail->stage > 0 && (tail->fp32 != 0) == (mixed != 0)) {
+        if (mixed) return down_tail<float>(m, mixed, phi, f, cpb, *tail, st);
+        return down_tail<double>(m, mixed, phi, f, cpb, *tail, st);
+    }
     if (mixed)
         (void)launch<k_down_A<float>, k_down_body<float>, 256>(dim3((nr - 1 + cpb - 1) / cpb), dim3(256), down_lds(nz, cpb), st, k_down_A<float>{phi, f, m, mixed, cpb});
     else
@@ -2313,7 +2383,7 @@ static hipError_t down(const MgLevels &m, int mixed, const double *phi, const do
 }
 
 hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_alt,
-                     const double *f, int skip_down, hipStream_t st)
+                     const double *f, int skip_down, hipStream_t st, ListTail *tail)
 {
     const int L = m.L, nr = m.nr, nz = m.nzl[L];
     hipError_t e;
@@ -2330,7 +2400,9 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
     }
     // the residual of the finest level restricted to every level (unless the
     // solve's first launch has done it for this cycle)
-    if (!skip_down && (e = down(m, mixed, phi, f, st)) != hipSuccess) return e;
+    if (!skip_down &&
+        (e = down(m, mixed, phi, f, st, m.split ? tail : nullptr)) != hipSuccess)
+        return e;
     if (m.split) {
         // the way up in one launch: each block of the finest level's sweep
         // with the coarse lines it depends on (up_sweep); or (split_coarse)

@@ -491,6 +491,7 @@ template <typename T> rzpic_status run_staged(rzpic_ctx *c, int cs, int mode)
 struct NextGrid {
     GridArgs g;
     double V;
+    bool defer;  // keep the hole filling and appending for the next step's way down
 };
 
 // List maintenance of the species in `which` (bit s): superchunk totals,
@@ -528,18 +529,29 @@ rzpic_status run_fixup(rzpic_ctx *c, int which, const NextGrid *next = nullptr)
         HIPCHK(mg_prep_dead_list(c->mg, c->mixed, c->phi, c->f, j, max_chunks, c->st));
     else
         HIPCHK(launch_dead_list(j, max_chunks, c->st));
-    if (j.dead[0] && j.dead[1]) {
-        HIPCHK(launch_fill2<T>(parts_of<T>(c->sp[0].v), parts_of<T>(c->sp[1].v), c->sp[0].ch,
-                               c->sp[1].ch, c->fix, c->fix + 1, c->st));
-    } else {
-        for (int s = 0; s < 2; ++s)
-            if (j.dead[s])
-                HIPCHK(launch_fill<T>(parts_of<T>(c->sp[s].v), c->sp[s].ch, c->fix + s, c->st));
-    }
     Parts<T> none{};
-    HIPCHK(launch_append<T>(j, c->sp[0].bound ? parts_of<T>(c->sp[0].v) : none,
-                            c->sp[1].bound ? parts_of<T>(c->sp[1].v) : none, stage_of<T>(c, 0),
-                            stage_of<T>(c, 1), c->cnt, c->cnt + 1, max_chunks, c->st));
+    if (next && next->defer && j.dead[0] && j.dead[1]) {
+        // step pipelining: kept for the next step's way-down launches
+        list_tail_keep<T>(c->tail, parts_of<T>(c->sp[0].v), parts_of<T>(c->sp[1].v),
+                          c->sp[0].ch, c->sp[1].ch, c->fix, c->fix + 1, j,
+                          c->sp[0].bound ? parts_of<T>(c->sp[0].v) : none,
+                          c->sp[1].bound ? parts_of<T>(c->sp[1].v) : none, stage_of<T>(c, 0),
+                          stage_of<T>(c, 1), c->cnt, c->cnt + 1, max_chunks);
+    } else {
+        if (j.dead[0] && j.dead[1]) {
+            HIPCHK(launch_fill2<T>(parts_of<T>(c->sp[0].v), parts_of<T>(c->sp[1].v),
+                                   c->sp[0].ch, c->sp[1].ch, c->fix, c->fix + 1, c->st));
+        } else {
+            for (int s = 0; s < 2; ++s)
+                if (j.dead[s])
+                    HIPCHK(launch_fill<T>(parts_of<T>(c->sp[s].v), c->sp[s].ch, c->fix + s,
+                                          c->st));
+        }
+        HIPCHK(launch_append<T>(j, c->sp[0].bound ? parts_of<T>(c->sp[0].v) : none,
+                                c->sp[1].bound ? parts_of<T>(c->sp[1].v) : none,
+                                stage_of<T>(c, 0), stage_of<T>(c, 1), c->cnt, c->cnt + 1,
+                                max_chunks, c->st));
+    }
     for (int s = 0; s < 2; ++s)
         if (j.kids[s]) c->children_pending[s] = false;
     if (!c->children_pending[0] && !c->children_pending[1]) c->children_scanned = false;
@@ -576,7 +588,8 @@ rzpic_status run_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, cons
     auto cycles_run = [&](int kk) -> hipError_t {
         if (ob) return mg_solve_block(c->mg, c->mixed, u, f, V, kk, c->st);
         for (int q = 0; q < kk; ++q) {
-            hipError_t e = mg_vcycle(c->mg, c->mixed, u, u_alt, f, down_done ? 1 : 0, c->st);
+            hipError_t e = mg_vcycle(c->mg, c->mixed, u, u_alt, f, down_done ? 1 : 0, c->st,
+                                     &c->tail);
             down_done = false;
             if (e != hipSuccess) return e;
         }
@@ -972,6 +985,7 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n, bool pipe 
     if (c->timing && c->ev_used >= rzpic_ctx::kPool) TRY(flush_timing(c));
     const bool pre = pipe && c->prepared == n;
     c->prepared = -1;
+    if (!pre) HIPCHK(list_tail_flush(c->tail, c->st));
     mark(c, 0);
     // subcycled ions move only in every K-th step
     const bool ions = n % ion_K(c) == ion_K(c) - 1;
@@ -990,6 +1004,9 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n, bool pipe 
     const rzpic_status ss = solve_impl(c, (double)(n + 1) * c->c.dt, true, nullptr, nullptr);
     c->prep_ready = false;
     TRY(ss);
+    // what of the previous step's list maintenance the way-down launches did
+    // not take (fewer than three cycles) runs before the pass reads the lists
+    HIPCHK(list_tail_flush(c->tail, c->st));
     c->acc_cycles += c->last_cycles;
     mark(c, 2);
     TRY(efield_impl(c, pre, ions));
@@ -1010,6 +1027,9 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n, bool pipe 
     // the counters to the next step's E launch
     const bool prep_next = pipe && !resize && can_prepare(c) && n + 1 <= 0xFFFFFFFELL;
     NextGrid next{};
+    // the hole filling and appending go with the next step's way down,
+    // unless a tile sort of this step reads the compacted particles
+    next.defer = !sort;
     if (prep_next) {
         const int64_t m = n + 1;
         const double t = (double)(m + 1) * c->c.dt;
@@ -1043,6 +1063,14 @@ template <typename T> rzpic_status step_impl(rzpic_ctx *c, int64_t n, bool pipe 
 rzpic_status rz_fail(rzpic_status s, const char *msg) { return fail(s, "%s", msg); }
 
 hipStream_t rz_stream(const rzpic_ctx *c) { return c->st; }
+
+// What a pipelined step left of its list maintenance, launched on the
+// context's stream (batches and gradient windows read the particles).
+rzpic_status rz_settle(rzpic_ctx *c)
+{
+    HIPCHK(list_tail_flush(c->tail, c->st));
+    return RZPIC_OK;
+}
 
 // Whether a context can join a batch: its step must launch kernels only (no
 // synchronisation, no timing events) and both species must be bound.
@@ -1089,7 +1117,19 @@ rzpic_status rz_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, doubl
 // Calls that change what the next step's grid preparation reads (particles,
 // deposits, potentials, voltages, solver settings) drop a preparation made by
 // step pipelining; the next step then prepares its grid itself.
-static void unprepare(rzpic_ctx *c) { c->prepared = -1; }
+static void unprepare(rzpic_ctx *c)
+{
+    c->prepared = -1;
+    (void)list_tail_flush(c->tail, c->st);
+}
+
+// Calls that read the particles or their counts first launch what a
+// pipelined step left of its list maintenance.
+static rzpic_status settle(rzpic_ctx *c)
+{
+    HIPCHK(list_tail_flush(c->tail, c->st));
+    return RZPIC_OK;
+}
 
 extern "C" {
 
@@ -1363,6 +1403,12 @@ rzpic_status rzpic_destroy(rzpic_ctx *c)
 rzpic_status rzpic_set_stream(rzpic_ctx *c, void *stream)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    if (c->tail.stage) {
+        // the new stream does not wait for the old one: what a pipelined
+        // step left runs and ends before the switch
+        HIPCHK(list_tail_flush(c->tail, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+    }
     unprepare(c);
     c->st = (hipStream_t)stream;
     return RZPIC_OK;
@@ -1440,6 +1486,7 @@ rzpic_status rzpic_set_count(rzpic_ctx *c, int32_t s, int64_t n, uint64_t next_i
 rzpic_status rzpic_get_count(rzpic_ctx *c, int32_t s, int64_t *n, uint64_t *next_id)
 {
     TRY(need_species(c, s));
+    TRY(settle(c));
     Counts h;
     HIPCHK(hipMemcpyAsync(&h, c->cnt + s, sizeof h, hipMemcpyDeviceToHost, c->st));
     // synchronises, then returns (and clears) a pending device-side failure;
@@ -1946,8 +1993,10 @@ rzpic_status rzpic_step(rzpic_ctx *c, int64_t step)
     if (step < 0 || step > 0xFFFFFFFELL) return fail(RZPIC_EINVAL, "step out of range");
     // graph replay unless a batch records this step, timing events are on or
     // the solve runs to a tolerance (it synchronises)
-    if (c->step_graph && !g_recorder && !c->timing && c->c.mg_fixed_cycles > 0)
+    if (c->step_graph && !g_recorder && !c->timing && c->c.mg_fixed_cycles > 0) {
+        TRY(settle(c));  // outside the capture
         return step_graph(c, step);
+    }
     const bool pipe = c->pipeline && !g_recorder;
     return c->mixed ? step_impl<float>(c, step, pipe) : step_impl<double>(c, step, pipe);
 }
@@ -1979,6 +2028,7 @@ rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *
                             int32_t best[2], int64_t *next_step)
 {
     if (!c || !best || !next_step) return fail(RZPIC_EINVAL, "null argument");
+    TRY(settle(c));
     if (steps < 1) return fail(RZPIC_EINVAL, "steps must be >= 1");
     TRY(need_both(c));
     if (c->timing) return fail(RZPIC_EINVAL, "autotune needs step timing off");
@@ -2080,6 +2130,7 @@ rzpic_status rzpic_grid_copy(rzpic_ctx *c, int32_t which, double *dev, int32_t t
 {
     if (!c || !dev) return fail(RZPIC_EINVAL, "null argument");
     if (to_ctx) unprepare(c);
+    else TRY(settle(c));
     double *src = nullptr;
     switch (which) {
     case RZPIC_G_PHI: src = c->phi; break;
@@ -2125,6 +2176,7 @@ rzpic_status rzpic_grid_copy(rzpic_ctx *c, int32_t which, double *dev, int32_t t
 rzpic_status rzpic_sync(rzpic_ctx *c)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    TRY(settle(c));
     int32_t h = 0;
     HIPCHK(hipMemcpyAsync(&h, c->status, sizeof h, hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
@@ -2140,6 +2192,7 @@ rzpic_status rzpic_sync(rzpic_ctx *c)
 rzpic_status rzpic_get_diag(rzpic_ctx *c, rzpic_diag *out)
 {
     if (!c || !out) return fail(RZPIC_EINVAL, "null argument");
+    TRY(settle(c));
     std::memset(out, 0, sizeof *out);
     Counts cn[2];
     unsigned long long tal[6], ms[2 * (1 + kMaxProc)];

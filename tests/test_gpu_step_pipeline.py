@@ -138,3 +138,24 @@ def test_pipelined_steps_back_to_back_then_batched():
     np.testing.assert_array_equal(direct.grid(rzpic.G_PHI), piped.grid(rzpic.G_PHI))
     direct.close()
     piped.close()
+
+
+@pytest.mark.parametrize("precision,cycles", [("mixed", 3), ("fp64", 3), ("mixed", 2),
+                                              ("mixed", 1)])
+def test_pipelined_steps_back_to_back_every_variant(precision, cycles):
+    """The 65x33 variant workload (tile sort every 3 steps, weight split
+    every 4, ions every 2nd step) stepped 12 times with nothing read in
+    between: each step's hole filling and appending then run beside the next
+    step's way-down launches (with fewer than three cycles, what those do
+    not take runs before the pass).  Compared after steps 5 and 11."""
+    w = wl.rf_129x65().replace(nr=65, nz=33, R=0.02, L=0.01, n_per_species=30_000,
+                               sort_every=3, resize_every=4, ion_subcycle=2,
+                               mg_fixed_cycles=cycles)
+    direct, piped = _ctx(w, precision, False), _ctx(w, precision, True)
+    for n in range(12):
+        direct.step(n)
+        piped.step(n)
+        if n in (5, 11):
+            _same(direct, piped, f"{precision} {cycles} cycles, step {n}")
+    direct.close()
+    piped.close()
