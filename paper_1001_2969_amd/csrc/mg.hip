@@ -1986,6 +1986,13 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     const int L = m.L, nr = m.nr, n = nr - 1, nz = up_nzl(L), S = m.S;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nph = 2 * L - 1;
+    if (wave >= kUpThreads / 64) {
+        // the spare wavefronts of a wider launch (k_up_app_body): the phases'
+        // barriers only
+        for (int ph = 0; ph < nph; ++ph) __syncthreads();
+        return;
+    }
     const int i = 2 * kb_.x + 2;
     const bool last = i + 1 == nz - 2;
     // The window of level l, k = L - l levels below the finest: the rows its
@@ -2017,7 +2024,6 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     // (phase ph is step ph + (ph > 0)).  A phase has at most three lines and
     // the block three wavefronts, so wavefront w solves line w of each phase
     // that has one.
-    const int nph = 2 * L - 1;
     const T *coarse = (const T *)m.coarse_uf;
     const T *fr = mixed ? (const T *)m.f32[L] : nullptr;  // mixed: FP32 residual
     const T *tab = (const T *)m.tab;
@@ -2212,14 +2218,56 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     }
 }
 
+// The way up beside the appending of a pending list tail (step
+// pipelining), at kSuper threads: the way-up blocks first (their spare
+// wavefronts take the barriers only), then the appending's.  Only where the
+// way up's registers fit two wavefronts of the block per SIMD.
+template <typename T, int Q> struct k_up_app_A {
+    k_up_A<T, Q> u;
+    AppendJob<T> a;
+    int nu, nsc;
+};
+
+template <typename T, int Q>
+__device__ __forceinline__ void k_up_app_body(const Blk &kb_, const k_up_app_A<T, Q> &A_)
+{
+    if (kb_.x < A_.nu) {
+        k_up_body<T, Q>(Blk{kb_.x, 0, A_.nu, 1}, A_.u);
+        return;
+    }
+    const int b = kb_.x - A_.nu;
+    append_body<T>(Blk{b % A_.nsc, b / A_.nsc, A_.nsc, 2}, A_.a);
+}
+
+template <typename T, int Q>
+static hipError_t up_app(const k_up_A<T, Q> &u, int blocks, size_t lds, ListTail &t,
+                         hipStream_t st)
+{
+    static_assert(sizeof(k_up_app_A<T, Q>) <= 4096, "kernel arguments");
+    k_up_app_A<T, Q> a{u, {}, blocks, t.nsc};
+    std::memcpy(&a.a, t.app, sizeof a.a);
+    (void)launch<k_up_app_A<T, Q>, k_up_app_body<T, Q>, kSuper>(
+        dim3(blocks + 2 * t.nsc), dim3(kSuper), lds, st, a);
+    t.stage = 0;
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t up_sweep(const MgLevels &m, int mixed, const double *phi_in, double *phi_out,
-                           const double *f, hipStream_t st)
+                           const double *f, hipStream_t st, ListTail *tail = nullptr)
 {
     const int n = m.nr - 1, blocks = (m.nzl[m.L] - 3) / 2;
     if (blocks <= 0) return hipSuccess;
     if ((mixed != 0) != (sizeof(T) == 4)) return hipErrorInvalidValue;  // k_up_body's form
     const size_t lds = up_lds(m, mixed);
+    if (tail && tail->stage == 1 && (tail->fp32 != 0) == (mixed != 0)) {
+        if (n <= 64) return up_app<T, 1>(k_up_A<T, 1>{m, mixed, phi_in, phi_out, f}, blocks, lds,
+                                         *tail, st);
+        if constexpr (sizeof(T) == 4)
+            if (n <= 128)
+                return up_app<T, 2>(k_up_A<T, 2>{m, mixed, phi_in, phi_out, f}, blocks, lds,
+                                    *tail, st);
+    }
     if (n <= 64)
         (void)launch<k_up_A<T, 1>, k_up_body<T, 1>, kUpThreads>(dim3(blocks), dim3(kUpThreads), lds, st, k_up_A<T, 1>{m, mixed, phi_in, phi_out, f});
     else if (n <= 128)
@@ -2408,8 +2456,8 @@ hipError_t mg_vcycle(const MgLevels &m, int mixed, double *&phi, double *&phi_al
         // with the coarse lines it depends on (up_sweep); or (split_coarse)
         // the coarse levels in one workgroup, then the finest level's sweep
         if (!m.split_coarse) {
-            if (mixed) return up_sweep<float>(m, mixed, phi, phi, f, st);
-            e = up_sweep<double>(m, mixed, phi, phi_alt, f, st);
+            if (mixed) return up_sweep<float>(m, mixed, phi, phi, f, st, tail);
+            e = up_sweep<double>(m, mixed, phi, phi_alt, f, st, tail);
             double *t = phi;
             phi = phi_alt;
             phi_alt = t;
