@@ -291,11 +291,18 @@ rzpic_status rzpic_set_step_graph(rzpic_ctx *ctx, int32_t on);
  * voltage at t = (n+2) dt, the line tables and the first restriction of the
  * solve), in the launches of its own list maintenance; step n + 1, if it
  * comes next, skips that preparation and clears the deposit grids and the
- * Monte Carlo counters in its E launch.  Particles, potentials and
- * counters after every step are those of unpipelined steps, bit for bit;
- * between steps, rho, chi, eps, the densities and the electrode rows of phi
- * are already those of the next step.  Applies only to the split solve path
- * with a fixed number of cycles and no external circuit; graph-replayed and
+ * Monte Carlo counters in its E launch.  Unless a tile sort follows in step
+ * n, its hole filling and appending are kept and run in step n + 1's
+ * way-down and way-up launches.  Particles, potentials and counters after
+ * every step are those of unpipelined steps, bit for bit; between steps,
+ * rho, chi, eps, the densities and the electrode rows of phi are already
+ * those of the next step.  Every call that reads or changes particles,
+ * counts or grids (rzpic_get_count, rzpic_sync, rzpic_get_diag,
+ * rzpic_grid_copy, and every operation) first launches the kept filling and
+ * appending on the context's stream, so the particle arrays are final once
+ * such a call has been made: a caller reading the bound arrays directly
+ * calls rzpic_sync first.  Applies only to the split solve path with a
+ * fixed number of cycles and no external circuit; graph-replayed and
  * batched steps prepare their own grid.  Every call that changes particles,
  * deposits, potentials, voltages or solver settings drops the preparation;
  * writes through a grid view (rzpic_grid_view) between steps do not, so a
