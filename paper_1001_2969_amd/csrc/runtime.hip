@@ -1382,6 +1382,9 @@ rzpic_status rzpic_create(const rzpic_config *cfg, void *stream, rzpic_ctx **out
 rzpic_status rzpic_destroy(rzpic_ctx *c)
 {
     if (!c) return RZPIC_OK;
+    // the caller's particle arrays end compacted: what a pipelined step kept
+    // of its list maintenance runs first
+    (void)list_tail_flush(c->tail, c->st);
     if (c->st) (void)hipStreamSynchronize(c->st);
     else (void)hipDeviceSynchronize();
     for (void *p : c->allocs) (void)hipFree(p);
