@@ -606,6 +606,14 @@ __device__ __forceinline__ void down_body(const double *u, const double *f, cons
     double *us = sbuf, *es = sbuf + (size_t)w * nz;
     double *cur = es + (size_t)w * nz, *nxt = cur + (size_t)cpb * nz;
     const int j0 = blk * cpb;
+    // the right-hand side of this thread's first residual node, loaded with
+    // the staged columns rather than after their barrier (one round trip to
+    // memory less)
+    double f_first = 0.0;
+    if ((int)threadIdx.x < cpb * nz) {
+        const int i = threadIdx.x / cpb, j = j0 + (int)threadIdx.x - i * cpb;
+        if (j < nr - 1 && i > 0 && i < nz - 1) f_first = f[(size_t)i * nr + j];
+    }
     // consecutive threads take consecutive columns of a row (the loads of a
     // row are contiguous); LDS holds the block's columns one after another
     for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
@@ -638,7 +646,7 @@ __device__ __forceinline__ void down_body(const double *u, const double *f, cons
             double b = a + c + d + e;
             double Au = b * U(0, 0) - a * U(-1, 0) - c * U(1, 0) - e * U(0, 1);
             if (j > 0) Au -= d * U(0, -1);
-            r = f[(size_t)i * nr + j] - Au;
+            r = (t == (int)threadIdx.x ? f_first : f[(size_t)i * nr + j]) - Au;
             if (mixed) m.f32[L][(size_t)i * nr + j] = (float)r;
         }
         cur[cj * nz + i] = r;
