@@ -1935,6 +1935,7 @@ int rz_config_fits(const rzpic_ctx *c, int threads, int64_t ppb, int lds)
 
 rzpic_status rz_set_config(rzpic_ctx *c, int threads, int64_t ppb, int lds, int tz, int tr)
 {
+    HIPCHK(list_tail_flush(c->tail, c->st));  // the tiles may re-sort the particles
     TRY(set_tiles(c, tz, tr));
     return set_pass_config(c, threads, ppb, lds != 0);
 }
@@ -2093,6 +2094,7 @@ rzpic_status rzpic_autotune(rzpic_ctx *c, int32_t steps, int64_t step0, double *
 rzpic_status rzpic_set_pass_shape(rzpic_ctx *c, int32_t threads, int32_t parts_per_block)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    TRY(settle(c));  // a new shape may re-sort the particles
     if ((threads != 256 && threads != 512 && threads != 768 && threads != 1024) ||
         parts_per_block < 64)
         return fail(RZPIC_EINVAL,
@@ -2105,6 +2107,7 @@ rzpic_status rzpic_set_pass_shape(rzpic_ctx *c, int32_t threads, int32_t parts_p
 rzpic_status rzpic_set_pass_form(rzpic_ctx *c, int32_t form)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    TRY(settle(c));  // a new form may re-sort the particles
     if (form != RZPIC_FORM_AUTO && form != RZPIC_FORM_LDS && form != RZPIC_FORM_TILED)
         return fail(RZPIC_EINVAL, "form must be RZPIC_FORM_AUTO, RZPIC_FORM_LDS or RZPIC_FORM_TILED");
     if (form == RZPIC_FORM_LDS && !c->lds_ok)
@@ -2119,6 +2122,7 @@ rzpic_status rzpic_set_pass_form(rzpic_ctx *c, int32_t form)
 rzpic_status rzpic_set_tiles(rzpic_ctx *c, int32_t tile_z, int32_t tile_r)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
+    TRY(settle(c));  // new tiles re-sort the particles
     return set_tiles(c, tile_z, tile_r);
 }
 

@@ -159,3 +159,26 @@ def test_pipelined_steps_back_to_back_every_variant(precision, cycles):
             _same(direct, piped, f"{precision} {cycles} cycles, step {n}")
     direct.close()
     piped.close()
+
+
+def test_pipelined_steps_through_pass_configuration_changes():
+    """65x33 mixed with tile sorts every 3 steps: new tiles, the tiled form
+    and a new pass shape set between steps (each may re-sort the particles,
+    so the kept filling and appending run first); both contexts get the same
+    calls and agree bit for bit."""
+    w = wl.rf_129x65().replace(nr=65, nz=33, R=0.02, L=0.01, n_per_species=30_000,
+                               sort_every=3, resize_every=0)
+    direct, piped = _ctx(w, "mixed", False), _ctx(w, "mixed", True)
+    for n in range(10):
+        direct.step(n)
+        piped.step(n)
+        for g in (direct, piped):
+            if n == 1:
+                g.set_tiles(8, 16)
+            if n == 4:
+                g.set_pass_form(rzpic.FORM_TILED)
+            if n == 6:
+                g.set_pass_shape(256, 4096)
+    _same(direct, piped, "after 10 steps")
+    direct.close()
+    piped.close()
