@@ -2045,10 +2045,25 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     // right-hand side and phi one load per row: 11 loads per phase of the
     // mixed form, and the wavefront's loads of three phases ahead fit the
     // 63 it can have in flight (five buffers, four ahead, measured slower:
-    // the extra registers cost more than the deeper overlap gains).  Every wavefront fetches in every phase (a wavefront without a
-    // line there, or a phase past the last, takes another line of the
-    // block), so that the loads in flight are the same on every path.
+    // the extra registers cost more than the deeper overlap gains).  Every
+    // wavefront fetches in every phase (a wavefront without a line there,
+    // or a phase past the last, takes another line of the block), so that
+    // the loads in flight are the same on every path.  The byte offsets of
+    // the lane's group in each row, from the start of a line's table, are
+    // the same for every line: computed once, they leave a load one scalar
+    // base per line and no address arithmetic per row.
     const int tn = m.tab_row;
+    const int e0 = Q * lane + Q <= tn ? Q * lane : tn - Q;
+    const uint32_t ot = (uint32_t)e0 * (uint32_t)sizeof(T);
+    const uint32_t rowb = (uint32_t)tn * (uint32_t)sizeof(T);
+    const uint32_t o_bf = 2 * rowb + ot;
+    uint32_t o_pair[SMAX + 1];
+    o_pair[0] = 2 * ot;
+#pragma unroll
+    for (int st = 0; st < SMAX; ++st) {
+        const int sc = st < S ? st : S - 1;
+        o_pair[1 + st] = (uint32_t)tab_pair_row(1 + sc) * rowb + 2 * ot;
+    }
     auto fetch = [&](int ph, UpIn<T, Q, SMAX> &in) {
         const int k = ph + (ph > 0);
         int l = k / 2 + 1, par = !(k & 1), t = wave;
@@ -2069,22 +2084,19 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
         }
         const int r = (par ? wlo(l) : wlo(l) + 1) + 2 * t;
         const bool fine = l == L;
-        const T *tb = tab + (size_t)(up_line_off(l) + r - 1) * tstride;
+        const T *tb = uniform_ptr(tab + (size_t)(up_line_off(l) + r - 1) * tstride);
         const T *fl = coarse + (up_f_row(l) + r) * nr;
-        const int e0 = Q * lane + Q <= tn ? Q * lane : tn - Q;
-        const uint32_t ot = (uint32_t)e0 * (uint32_t)sizeof(T);
         T pr[2 * Q];
-        ld_vec<T, 2 * Q>(uniform_ptr(tb), 2 * ot, pr);
+        ld_vec<T, 2 * Q>(tb, o_pair[0], pr);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             in.tab.ta[q] = pr[2 * q];
             in.tab.tc[q] = pr[2 * q + 1];
         }
-        ld_vec<T, Q>(uniform_ptr(tb + 2 * (size_t)tn), ot, in.tab.bf);
+        ld_vec<T, Q>(tb, o_bf, in.tab.bf);
 #pragma unroll
         for (int st = 0; st < SMAX; ++st) {
-            const int sc = st < S ? st : S - 1;
-            ld_vec<T, 2 * Q>(uniform_ptr(tb + tab_pair_row(1 + sc) * tn), 2 * ot, pr);
+            ld_vec<T, 2 * Q>(tb, o_pair[1 + st], pr);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 in.tab.k1[st][q] = pr[2 * q];
