@@ -1117,10 +1117,11 @@ rzpic_status rz_cycles(rzpic_ctx *c, double V, double *&u, double *&u_alt, doubl
 // Calls that change what the next step's grid preparation reads (particles,
 // deposits, potentials, voltages, solver settings) drop a preparation made by
 // step pipelining; the next step then prepares its grid itself.
-static void unprepare(rzpic_ctx *c)
+static rzpic_status unprepare(rzpic_ctx *c)
 {
     c->prepared = -1;
-    (void)list_tail_flush(c->tail, c->st);
+    HIPCHK(list_tail_flush(c->tail, c->st));
+    return RZPIC_OK;
 }
 
 // Calls that read the particles or their counts first launch what a
@@ -1412,7 +1413,7 @@ rzpic_status rzpic_set_stream(rzpic_ctx *c, void *stream)
         HIPCHK(list_tail_flush(c->tail, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
     }
-    unprepare(c);
+    TRY(unprepare(c));
     c->st = (hipStream_t)stream;
     return RZPIC_OK;
 }
@@ -1420,7 +1421,7 @@ rzpic_status rzpic_set_stream(rzpic_ctx *c, void *stream)
 rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_view *v)
 {
     if (!c || !v) return fail(RZPIC_EINVAL, "null argument");
-    unprepare(c);
+    TRY(unprepare(c));
     if (s < 0 || s > 1) return fail(RZPIC_EINVAL, "species %d out of range", s);
     if (!v->r || !v->z || !v->vr || !v->vt || !v->vz || !v->ar || !v->az || !v->w || !v->id)
         return fail(RZPIC_EINVAL, "species %d: null particle array", s);
@@ -1477,7 +1478,7 @@ rzpic_status rzpic_bind_species(rzpic_ctx *c, int32_t s, const rzpic_species_vie
 rzpic_status rzpic_set_count(rzpic_ctx *c, int32_t s, int64_t n, uint64_t next_id)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (n < 0 || n > c->sp[s].cap)
         return fail(RZPIC_EINVAL, "count %lld outside [0, capacity %lld]", (long long)n,
                     (long long)c->sp[s].cap);
@@ -1505,7 +1506,7 @@ rzpic_status rzpic_set_xsec(rzpic_ctx *c, int32_t s, int32_t nproc, const int32_
                             double ej_B)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (nproc < 1 || nproc > kMaxProc || ne < 2 || !(de > 0) || !kind || !thr_eV || !sigma)
         return fail(RZPIC_EINVAL, "cross sections: need 1 <= nproc <= %d, ne >= 2, de > 0", kMaxProc);
     for (int k = 0; k < nproc; ++k)
@@ -1586,7 +1587,7 @@ rzpic_status rzpic_init_particles(rzpic_ctx *c, int32_t s, int64_t n, double n0,
                                   uint64_t id0)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (n < 0 || n > c->sp[s].cap) return fail(RZPIC_EINVAL, "n = %lld exceeds capacity", (long long)n);
     if (!(T_eV >= 0) || !(n0 >= 0)) return fail(RZPIC_EINVAL, "need n0 >= 0 and T_eV >= 0");
     Phys ph = phys_of(c);
@@ -1602,7 +1603,7 @@ rzpic_status rzpic_init_particles(rzpic_ctx *c, int32_t s, int64_t n, double n0,
 rzpic_status rzpic_push_first(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (c->mixed) {
         TRY(run_pass<float>(c, s, M_FIRST | M_MARK, 0));
         if (c->children_pending[s]) TRY(run_staged<float>(c, s, M_FIRST));
@@ -1616,7 +1617,7 @@ rzpic_status rzpic_push_first(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_push_final(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (c->mixed) TRY(run_pass<float>(c, s, M_FINAL | M_MARK, 0));
     else TRY(run_pass<double>(c, s, M_FINAL | M_MARK, 0));
     return RZPIC_OK;
@@ -1625,7 +1626,7 @@ rzpic_status rzpic_push_final(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_collide(rzpic_ctx *c, int32_t s, int64_t step)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (!c->sp[s].has_xsec) return RZPIC_OK;
     if (s == 0 && (c->children_pending[0] || c->children_pending[1]))
         return fail(RZPIC_ESTATE, "new particles already staged: call rzpic_compact first");
@@ -1641,7 +1642,7 @@ rzpic_status rzpic_collide(rzpic_ctx *c, int32_t s, int64_t step)
 rzpic_status rzpic_deposit(rzpic_ctx *c)
 {
     TRY(need_both(c));
-    unprepare(c);
+    TRY(unprepare(c));
     if (c->mixed) TRY(deposit_impl<float>(c));
     else TRY(deposit_impl<double>(c));
     TRY(finalize_impl(c, 0));
@@ -1651,14 +1652,14 @@ rzpic_status rzpic_deposit(rzpic_ctx *c)
 rzpic_status rzpic_solve(rzpic_ctx *c, double t, int32_t *cycles, double *relres)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
-    unprepare(c);
+    TRY(unprepare(c));
     return solve_impl(c, t, false, cycles, relres);
 }
 
 rzpic_status rzpic_solve_dev(rzpic_ctx *c, double t, int32_t *cycles_dev, double *relres_dev)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
-    unprepare(c);
+    TRY(unprepare(c));
     const bool fixed = c->c.mg_fixed_cycles > 0;
     int32_t k = 0;
     double rr = 0.0;
@@ -1704,7 +1705,7 @@ rzpic_status rzpic_grid_view(rzpic_ctx *c, rzpic_grid *out)
 rzpic_status rzpic_set_grid_source(rzpic_ctx *c, const double *rho, const double *chi)
 {
     if (!c || !rho || !chi) return fail(RZPIC_EINVAL, "null argument");
-    unprepare(c);
+    TRY(unprepare(c));
     const size_t bytes = (size_t)c->nn * sizeof(double);
     HIPCHK(hipMemcpyAsync(c->rho, rho, bytes, hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->chi, chi, bytes, hipMemcpyDeviceToDevice, c->st));
@@ -1714,7 +1715,7 @@ rzpic_status rzpic_set_grid_source(rzpic_ctx *c, const double *rho, const double
 rzpic_status rzpic_set_mg(rzpic_ctx *c, double tol, int32_t max_cycles, int32_t fixed_cycles)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
-    unprepare(c);
+    TRY(unprepare(c));
     if (fixed_cycles < 0 || (fixed_cycles == 0 && (max_cycles < 1 || !(tol > 0))))
         return fail(RZPIC_EINVAL, "need fixed_cycles > 0, or max_cycles >= 1 and tol > 0");
     c->c.mg_tol = tol;
@@ -1726,7 +1727,7 @@ rzpic_status rzpic_set_mg(rzpic_ctx *c, double tol, int32_t max_cycles, int32_t 
 rzpic_status rzpic_set_voltage(rzpic_ctx *c, double V_dc, double V_rf, double f_rf)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
-    unprepare(c);
+    TRY(unprepare(c));
     if (!std::isfinite(V_dc) || !std::isfinite(V_rf) || !std::isfinite(f_rf))
         return fail(RZPIC_EINVAL, "voltage parameters must be finite");
     c->c.V_dc = V_dc;
@@ -1738,7 +1739,7 @@ rzpic_status rzpic_set_voltage(rzpic_ctx *c, double V_dc, double V_rf, double f_
 rzpic_status rzpic_set_circuit(rzpic_ctx *c, double V, double Q, double Qc)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
-    unprepare(c);
+    TRY(unprepare(c));
     if (!c->circ) return fail(RZPIC_EINVAL, "the context has no external circuit (circuit_C = 0)");
     if (!std::isfinite(V) || !std::isfinite(Q) || !std::isfinite(Qc))
         return fail(RZPIC_EINVAL, "circuit state must be finite");
@@ -1771,7 +1772,7 @@ rzpic_status rzpic_efield(rzpic_ctx *c)
 rzpic_status rzpic_compact(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (s == 1 && c->children_pending[1] && !c->sp[0].bound)
         return fail(RZPIC_ESTATE, "species 0 must stay bound while new ions are staged");
     if (c->mixed) {
@@ -1787,7 +1788,7 @@ rzpic_status rzpic_compact(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_resize(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (!(c->c.resize_wcoef > 0)) return fail(RZPIC_EINVAL, "resize_wcoef must be positive");
     if (c->children_pending[s]) return fail(RZPIC_ESTATE, "call rzpic_compact before rzpic_resize");
     if (c->mixed) {
@@ -1803,7 +1804,7 @@ rzpic_status rzpic_resize(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_sort(rzpic_ctx *c, int32_t s)
 {
     TRY(need_species(c, s));
-    unprepare(c);
+    TRY(unprepare(c));
     if (c->children_pending[s]) return fail(RZPIC_ESTATE, "call rzpic_compact before rzpic_sort");
     if (c->mixed) TRY(sort_impl<float>(c, s));
     else TRY(sort_impl<double>(c, s));
@@ -1813,7 +1814,7 @@ rzpic_status rzpic_sort(rzpic_ctx *c, int32_t s)
 rzpic_status rzpic_prologue(rzpic_ctx *c)
 {
     TRY(need_both(c));
-    unprepare(c);
+    TRY(unprepare(c));
     if (c->children_pending[0] || c->children_pending[1])
         return fail(RZPIC_ESTATE, "new particles are staged: call rzpic_compact first");
     for (int s = 0; s < 2; ++s) HIPCHK(launch_fill_u64(c->acc[s], c->nn, c->st));
@@ -2016,7 +2017,7 @@ rzpic_status rzpic_set_step_pipeline(rzpic_ctx *c, int32_t on)
 rzpic_status rzpic_set_step_graph(rzpic_ctx *c, int32_t on)
 {
     if (!c) return fail(RZPIC_EINVAL, "null context");
-    unprepare(c);
+    TRY(unprepare(c));
     if (on) {
         if (!c->st)
             return fail(RZPIC_EINVAL, "graph replay needs a stream other than the null stream");
@@ -2136,7 +2137,7 @@ rzpic_status rzpic_get_pass_config(rzpic_ctx *c, int32_t out[5])
 rzpic_status rzpic_grid_copy(rzpic_ctx *c, int32_t which, double *dev, int32_t to_ctx)
 {
     if (!c || !dev) return fail(RZPIC_EINVAL, "null argument");
-    if (to_ctx) unprepare(c);
+    if (to_ctx) TRY(unprepare(c));
     else TRY(settle(c));
     double *src = nullptr;
     switch (which) {
