@@ -135,9 +135,9 @@ __global__ void k_restrict_eps(MgLevels m, int mixed, int cpb)
 }
 
 // Columns per block of the column-parallel grid launches (finalize, way
-// down, table preparation): about 128 nodes a block, so that a small mesh
-// still spreads over many compute units (64 blocks at 129x65).
-static int cols_per_block(int nz) { return nz >= 128 ? 1 : 128 / (nz - 1 > 0 ? nz - 1 : 1); }
+// down, table preparation): about 64 nodes a block, so that a small mesh
+// still spreads over many compute units (128 blocks at 129x65).
+static int cols_per_block(int nz) { return nz >= 64 ? 1 : 64 / (nz - 1 > 0 ? nz - 1 : 1); }
 
 hipError_t mg_restrict_eps(const MgLevels &m, int mixed, hipStream_t st)
 {
