@@ -51,9 +51,21 @@ def field_scales(w, parts):
     return sc
 
 
-def compare_particles(gp, op, w, tol, *, ordered=True, label=""):
+def elem_rel_err(a, b, floor):
+    """max_i |a_i - b_i| / max(|b_i|, floor): the error of each element
+    against its own size (elements below `floor` against the floor)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    if a.size == 0:
+        return 0.0
+    return float((np.abs(a - b) / np.maximum(np.abs(b), floor)).max())
+
+
+def compare_particles(gp, op, w, tol, *, ordered=True, label="", elem=None):
     """Particle arrays of the two sides: same ids (in order when `ordered`),
-    fields within tol of each field's max-norm."""
+    fields within tol of each field's max-norm.  elem = (etol, frac): also
+    every element within etol of its own size, sizes below frac of the
+    field's scale (R, L, or the max-norm) taken as that floor."""
     assert len(gp["id"]) == len(op["id"]), (label, len(gp["id"]), len(op["id"]))
     if ordered:
         np.testing.assert_array_equal(gp["id"], op["id"], err_msg=label)
@@ -68,6 +80,13 @@ def compare_particles(gp, op, w, tol, *, ordered=True, label=""):
         e = rel_err(gp[f][gi], op[f][oi], sc)
         worst[f] = e
         assert e <= tol, (label, f, e)
+        if elem is not None:
+            etol, frac = elem
+            o = np.asarray(op[f][oi], np.float64)
+            scale = sc if sc is not None else (float(np.abs(o).max()) if o.size else 1.0)
+            ee = elem_rel_err(gp[f][gi], o, frac * (scale if scale > 0 else 1.0))
+            print(f"{label} {f}: normwise {e:.3g}, per element {ee:.3g}")
+            assert ee <= etol, (label, f, "per element", ee)
     return worst
 
 

@@ -16,6 +16,14 @@ from paper_1001_2969_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
+# Per element as well as per field: every element within etol of its own
+# size (sizes below 1e-9 of the field's scale taken as that floor, so an
+# exact zero does not divide).  Single operations: 1e-10 (measured at most
+# 6.5e-12, on accelerations near field zeros); after steps: 1e-7 (measured
+# at most 6.5e-9: an element's error grows with its trajectory's
+# sensitivity, the field-wide bound stays 1e-10).
+_ELEM = (1e-10, 1e-9)
+_ELEM_STEPS = (1e-7, 1e-9)
 
 
 def _small(**kw):
@@ -48,7 +56,8 @@ def test_first_push_and_compaction(weighting):
         g.push_first(s)
         o.compact(s)
         g.compact(s)
-        compare_particles(g.particles(s), o.particles(s), w, 1e-13, label=f"first s={s}")
+        compare_particles(g.particles(s), o.particles(s), w, 1e-13, label=f"first s={s}",
+                          elem=_ELEM)
     d = g.diag()
     for s in (0, 1):
         np.testing.assert_allclose(d["absorbed"][s], o.absorbed(s), rtol=1e-10, atol=1e-30)
@@ -79,7 +88,8 @@ def test_efield_and_final_push_gather():
         g.push_final(s)
         o.compact(s)
         g.compact(s)
-        compare_particles(g.particles(s), o.particles(s), w, 1e-13, label=f"final s={s}")
+        compare_particles(g.particles(s), o.particles(s), w, 1e-13, label=f"final s={s}",
+                          elem=_ELEM)
 
 
 @pytest.mark.parametrize("weighting", [wl.W_ZR2, wl.W_ZR])
@@ -189,7 +199,7 @@ def test_collisions_bit_exact_decisions(eps_eV):
         g.compact(s)
     for s in (0, 1):
         gp, op = g.particles(s), o.particles(s)
-        compare_particles(gp, op, w, 1e-12, label=f"collide s={s}")
+        compare_particles(gp, op, w, 1e-12, label=f"collide s={s}", elem=_ELEM)
         assert g.count(s) == (o.count(s), o.next_id(s))
     d = g.diag()
     evs = o.events(0, n)
@@ -211,7 +221,8 @@ def test_weight_split():
     for s in (0, 1):
         o.resize(s)
         g.resize(s)
-        compare_particles(g.particles(s), o.particles(s), w, 1e-15, label=f"resize s={s}")
+        compare_particles(g.particles(s), o.particles(s), w, 1e-15, label=f"resize s={s}",
+                          elem=_ELEM)
         assert g.count(s) == (o.count(s), o.next_id(s))
 
 
@@ -235,7 +246,7 @@ def _run_steps(w, nsteps, *, state=None, own_init=False, precision="fp64", check
         e = {}
         for s in (0, 1):
             e[s] = compare_particles(g.particles(s), o.particles(s), w, tol, ordered=ordered,
-                                     label=f"step {n} s={s}")
+                                     label=f"step {n} s={s}", elem=_ELEM_STEPS)
         e["phi"] = compare_grid(g.grid(rzpic.G_PHI), o.grid(rzo.G_PHI), tol, f"phi step {n}")
         for go, oo in ((rzpic.G_N0, rzo.G_N0), (rzpic.G_N1, rzo.G_N1)):
             compare_grid(g.grid(go), o.grid(oo), tol, f"N step {n}")
