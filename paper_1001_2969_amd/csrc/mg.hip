@@ -2059,6 +2059,10 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     const uint32_t o_bf = 2 * rowb + ot;
     uint32_t o_pair[SMAX + 1];
     o_pair[0] = 2 * ot;
+    // scalar bases of the right-hand side and phi rows: a row is a 32-bit
+    // byte offset added to the lane's
+    const T *coarse_b = uniform_ptr(coarse), *fr_b = uniform_ptr(fr);
+    const double *phi_b = uniform_ptr(phi_in), *f_b = uniform_ptr(f);
 #pragma unroll
     for (int st = 0; st < SMAX; ++st) {
         const int sc = st < S ? st : S - 1;
@@ -2112,17 +2116,19 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
             const uint32_t od = (uint32_t)g0 * (uint32_t)sizeof(double);
             double z[2];
             in.pl[0] = in.pl[1] = in.ph[0] = in.ph[1] = in.pc[0] = in.pc[1] = 0.0;
+            const uint32_t row = (uint32_t)r * (uint32_t)nr;
             if (!fine) {
-                ld_vec_u<T, 2>(uniform_ptr(fl), og, in.g);
+                const uint32_t cr = (uint32_t)(up_f_row(l) + r) * (uint32_t)nr;
+                ld_vec_u<T, 2>(coarse_b, og + cr * (uint32_t)sizeof(T), in.g);
             } else if (mixed) {
-                ld_vec_u<T, 2>(uniform_ptr(fr + (size_t)r * nr), og, in.g);
-                ld_vec_u<double, 2>(uniform_ptr(phi_in + (size_t)r * nr), od, in.pc);
+                ld_vec_u<T, 2>(fr_b, og + row * (uint32_t)sizeof(T), in.g);
+                ld_vec_u<double, 2>(phi_b, od + row * 8u, in.pc);
             } else {
-                ld_vec_u<double, 2>(uniform_ptr(f + (size_t)r * nr), od, z);
+                ld_vec_u<double, 2>(f_b, od + row * 8u, z);
                 in.g[0] = (T)z[0];
                 in.g[1] = (T)z[1];
-                ld_vec_u<double, 2>(uniform_ptr(phi_in + (size_t)(r - 1) * nr), od, in.pl);
-                ld_vec_u<double, 2>(uniform_ptr(phi_in + (size_t)(r + 1) * nr), od, in.ph);
+                ld_vec_u<double, 2>(phi_b, od + (row - (uint32_t)nr) * 8u, in.pl);
+                ld_vec_u<double, 2>(phi_b, od + (row + (uint32_t)nr) * 8u, in.ph);
             }
         } else {
 #pragma unroll
