@@ -216,7 +216,8 @@ VCYCLE_BYTES_PER_NODE = {"fp64": 32 + 2 * 44, "mixed": 32 + 2 * 22 + 20}
 
 def vcycle_time(w, precision):
     """Device time of one V(0,1) cycle on w's mesh: (T(6) - T(1)) / 5 for
-    fixed-cycle solves of a smooth rho, chi ~ 1 (best of 3), and the path."""
+    fixed-cycle solves of a smooth rho, chi ~ 1 (best of 7 each: the
+    difference of two short event-timed solves is noisy), and the path."""
     import numpy as np
     import torch
 
@@ -233,7 +234,7 @@ def vcycle_time(w, precision):
         ctx.set_mg(fixed_cycles=k)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         best = math.inf
-        for _ in range(3):
+        for _ in range(7):
             ctx.stream.synchronize()
             ev0.record(ctx.stream)
             ctx.solve(1e-9, want=False)
