@@ -2061,7 +2061,8 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
     o_pair[0] = 2 * ot;
     // scalar bases of the right-hand side and phi rows: a row is a 32-bit
     // byte offset added to the lane's
-    const T *coarse_b = uniform_ptr(coarse), *fr_b = uniform_ptr(fr);
+    const T *coarse_b = uniform_ptr(coarse), *fr_b = uniform_ptr(fr), *tab_b = uniform_ptr(tab);
+    const uint32_t tstride_b = (uint32_t)(tstride * sizeof(T));
     const double *phi_b = uniform_ptr(phi_in), *f_b = uniform_ptr(f);
 #pragma unroll
     for (int st = 0; st < SMAX; ++st) {
@@ -2088,7 +2089,9 @@ __device__ __forceinline__ void k_up_body(const Blk &kb_, const k_up_A<T, Q> &A_
         }
         const int r = (par ? wlo(l) : wlo(l) + 1) + 2 * t;
         const bool fine = l == L;
-        const T *tb = uniform_ptr(tab + (size_t)(up_line_off(l) + r - 1) * tstride);
+        // the line's table: a 32-bit byte offset from the tables' scalar base
+        const T *tb = (const T *)((const char *)tab_b +
+                                  (uint32_t)(up_line_off(l) + r - 1) * tstride_b);
         const T *fl = coarse + (up_f_row(l) + r) * nr;
         T pr[2 * Q];
         ld_vec<T, 2 * Q>(tb, o_pair[0], pr);
